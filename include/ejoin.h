@@ -1,0 +1,165 @@
+/*
+ * ejoin.h -- C ABI of the MI355X (gfx950) context-enhanced similarity join.
+ *
+ * The operator is the E-theta-join of the paper (Section III.C): two relations
+ * of embedding vectors R and S are joined on the cosine similarity of their
+ * rows (Section III.A, the "Cosine Similarity" equation).  It is evaluated in
+ * the tensor-join form of Section IV.C: the |R| x |S| similarity matrix
+ * D = R_hat S_hat^T of the L2-normalised rows (cosine = dot of normalised
+ * vectors) is computed block by block (the block-matrix decomposition
+ * equation) and the predicate is applied to each block as it is produced; D
+ * is never materialised, which is the bounded-buffer scheme of Section V.B
+ * taken to the size of one MFMA tile.  The result is a list of tuple-offset
+ * pairs (Section IV.C, "late materialisation").
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Pointers are DEVICE pointers unless a comment says "(host)".  The caller
+ *    owns every buffer: inputs, outputs and the workspace.  The library never
+ *    allocates device memory inside a join call.
+ *  - Inputs are row-major float32, ejoin_rel.ld elements between rows
+ *    (ld >= dim); only the first dim columns are read.  They must stay valid
+ *    until the stream work is complete.
+ *  - Canonical similarity.  The exact result is defined with the FP64 rule
+ *        sim64(r,s) = dot(r,s) / sqrt(dot(r,r) * dot(s,s))   (0 for a zero row)
+ *    with every dot summed sequentially over k = 0..dim-1 in FP64 from the
+ *    float32 inputs, one rounding per product and per sum, correctly rounded
+ *    sqrt and divide.  A pair matches iff sim64 >= theta.
+ *  - Exactness.  The bulk contraction runs in FP32, BF16 or FP8 e4m3 on the
+ *    matrix cores; every pair whose approximate score lies within a rigorous
+ *    error band of theta is rescored on the GPU with the rule above, so the
+ *    returned set is exactly { (i,j) : sim64(r_i,s_j) >= theta } in every
+ *    precision.
+ *  - Errors are returned, never printed or aborted on.  No global mutable
+ *    state: calls with distinct workspaces may run concurrently.
+ *  - Rows with a non-finite element give EJOIN_E_NONFINITE; rows whose L2 norm
+ *    is non-zero but outside [2^-100, 2^100] give EJOIN_E_RANGE (rescale such
+ *    input; zero rows are fine and have similarity 0 with everything).
+ *  - Offsets in results are int32, so |R| and |S| must be < 2^31.
+ */
+#ifndef EJOIN_H
+#define EJOIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EJOIN_OK = 0,
+    EJOIN_E_INVAL = 1,       /* bad argument (null pointer, dim mismatch, theta not finite, ...) */
+    EJOIN_E_OVERFLOW = 2,    /* output capacity too small: *n_out holds the true count */
+    EJOIN_E_WORKSPACE = 3,   /* workspace too small: see ejoin_stats.ws_needed / band_needed */
+    EJOIN_E_NONFINITE = 4,   /* an input row holds NaN or Inf */
+    EJOIN_E_HIP = 5,         /* a HIP runtime call failed */
+    EJOIN_E_UNSUPPORTED = 6, /* combination not supported (e.g. dimension too large) */
+    EJOIN_E_RANGE = 7        /* a row norm outside [2^-100, 2^100] (and not zero) */
+} ejoin_status;
+
+/* Precision of the bulk contraction (the FP64 rescore is always FP64). */
+typedef enum {
+    EJOIN_FP32 = 0,     /* float32 operands, FP32 MFMA */
+    EJOIN_BF16 = 1,     /* bfloat16 operands (RNE), FP32 accumulate */
+    EJOIN_FP8_E4M3 = 2  /* OCP e4m3 operands, per-row power-of-two scale, FP32 accumulate */
+} ejoin_prec;
+
+/* One relation: rows x dim embedding matrix, row-major, ld elements per row. */
+typedef struct {
+    const float *data;  /* device */
+    int64_t rows;
+    int32_t dim;
+    int64_t ld;
+} ejoin_rel;
+
+/* One result pair: offsets into R and S, and the score (float32 of the FP64
+ * rescored value for pairs inside the band, the accumulator otherwise). */
+typedef struct {
+    int32_t r;
+    int32_t s;
+    float score;
+} ejoin_pair;
+
+/* flags */
+#define EJOIN_NO_SYNC   0x1u  /* do not synchronise; n_out is a DEVICE int64 and the status
+                                 only covers argument and launch errors */
+#define EJOIN_TIMING    0x2u  /* record per-phase times in ejoin_stats (adds event syncs) */
+
+typedef struct {
+    int32_t prec;           /* ejoin_prec */
+    int32_t tile;           /* 0: planner's choice; otherwise a tile id from ejoin_tile_name */
+    double band;            /* < 0: the rigorous default for prec and dim; otherwise the band
+                               half-width (must be >= the rigorous bound, else EJOIN_E_INVAL) */
+    int64_t band_capacity;  /* <= 0: default; number of band pairs the workspace can hold */
+    uint32_t flags;         /* EJOIN_* flags */
+    int32_t topk_cand;      /* top-k: per-row candidate capacity (<= 0: default) */
+} ejoin_opts;
+
+/* Optional per-call report (host struct, may be NULL). */
+typedef struct {
+    int64_t n_pairs;        /* total matches (may exceed capacity) */
+    int64_t n_certain;      /* pairs accepted straight from the approximate score */
+    int64_t n_band;         /* pairs rescored in FP64 */
+    int64_t n_band_accepted;
+    int64_t band_needed;    /* band capacity that would have been enough */
+    size_t ws_needed;       /* workspace bytes this call needs */
+    double band;            /* band half-width used */
+    int32_t tile;           /* tile id used */
+    int32_t n_fallback;     /* top-k: rows recomputed by the exact row scan */
+    float ms_prep, ms_main, ms_rescore, ms_total;  /* with EJOIN_TIMING */
+} ejoin_stats;
+
+/* Library version string (static storage). */
+const char *ejoin_version(void);
+
+/* Human-readable text for a status code (static storage). */
+const char *ejoin_strerror(ejoin_status s);
+
+/* Default options: FP32, planner tile, rigorous band, default capacities. */
+void ejoin_opts_default(ejoin_opts *opts /* host */);
+
+/* Rigorous band half-width for a precision and dimension: the bound on
+ * |approximate score - sim64| derived in the design notes (FP32 and BF16:
+ * a global bound; FP8: the worst case of the per-pair bound). */
+double ejoin_band_default(int32_t prec, int32_t dim);
+
+/*
+ * Workspace bytes needed by ejoin_threshold for these relations and options
+ * (the band list size follows opts->band_capacity).  R, S, opts are host
+ * pointers; only rows/dim are read from R and S.  Returns 0 on bad arguments.
+ */
+size_t ejoin_threshold_workspace(const ejoin_rel *R, const ejoin_rel *S,
+                                 const ejoin_opts *opts);
+
+/*
+ * Threshold E-join (Sections III.C, IV.C): every (i, j) with
+ * sim64(R_i, S_j) >= theta.
+ *   R, S      (host structs) relations; R->dim == S->dim.  R and S may alias.
+ *   theta     finite threshold.
+ *   opts      (host, may be NULL = defaults).
+ *   out       device array of `capacity` pairs; order of pairs is unspecified.
+ *   n_out     (host) receives the number of matching pairs, or, with
+ *             EJOIN_NO_SYNC, a DEVICE int64 that will hold it.
+ *   ws        device workspace of ws_bytes >= ejoin_threshold_workspace(...).
+ *   stream    HIP stream for all work.
+ *   stats     (host, may be NULL) per-call report; filled only in sync mode.
+ * Returns EJOIN_E_OVERFLOW when more pairs matched than `capacity`: out then
+ * holds an arbitrary `capacity`-sized subset and *n_out the true count.
+ */
+ejoin_status ejoin_threshold(const ejoin_rel *R, const ejoin_rel *S, double theta,
+                             const ejoin_opts *opts, ejoin_pair *out, int64_t capacity,
+                             int64_t *n_out, void *ws, size_t ws_bytes,
+                             hipStream_t stream, ejoin_stats *stats);
+
+/* Number of tile shapes the library was built with, and the name of one
+ * ("prec:BMxBNxBK"); id 0 is "planner's choice".  Static storage. */
+int32_t ejoin_tile_count(void);
+const char *ejoin_tile_name(int32_t tile);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EJOIN_H */

@@ -1,0 +1,290 @@
+// api.cpp -- the C ABI (include/ejoin.h): argument checks, the plan (padded
+// sizes, band, tile), workspace carve-up and the launch sequence.
+#include "../../include/ejoin.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "common.hpp"
+#include "launch.hpp"
+
+using namespace ej;
+
+namespace {
+
+const double kU32 = 5.9604644775390625e-08;  // 2^-24, FP32 unit roundoff
+
+int elem_bytes(int prec) { return prec == P_FP32 ? 4 : prec == P_BF16 ? 2 : 1; }
+
+// contraction depth: dim rounded up to a whole 128-byte slice
+int padded_k(int prec, int dim) {
+    const int per = 128 / elem_bytes(prec);
+    return ((dim + per - 1) / per) * per;
+}
+
+int64_t padded_rows(int64_t rows) { return ((rows + 255) / 256) * 256; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Rigorous bound on |approximate score - sim64| for unit-norm operands.
+//  * normalisation in FP32 (norm, sqrt, divide, scale): relative error per
+//    operand below gamma_d + 4u;
+//  * FP32 accumulation over Kp terms: gamma_Kp times sum |r_k s_k| <= 1;
+//  * BF16 rounding of both operands: 2 u_b + u_b^2 with u_b = 2^-8;
+//  * FP8 e4m3: |e_r| + |e_s| + |e_r||e_s| from the quantisation error norms,
+//    worst case |e| <= 2^-4 + sqrt(d) 2^-10 / 224 (power-of-two scale puts
+//    the largest element in [224, 448]);
+//  * 1e-5 of slack absorbs the FP64 rounding of sim64 itself (~1e-15) and
+//    second-order terms.
+// The FP32 terms are counted four times over to stay valid if the matrix
+// cores round each step toward zero rather than to nearest.
+double band_fp32_terms(int Kp) { return 1e-5 + 4.04 * (double)(Kp + 8) * kU32; }
+
+double band_rigorous(int prec, int dim) {
+    if (dim < 1) return -1.0;
+    const int Kp = padded_k(prec, dim);
+    const double f = band_fp32_terms(Kp);
+    if (prec == P_FP32) return f;
+    if (prec == P_BF16) return 0.0078125 + 1.52587890625e-05 + f;
+    const double E = 0.0625 * 1.001 + sqrt((double)dim) * (1.0 / 1024.0) / 224.0 + 1e-7;
+    return 2.0 * E + E * E + f * (1.0 + E) * (1.0 + E);
+}
+
+float round_down_f(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = nextafterf(f, -INFINITY);
+    return f;
+}
+float round_up_f(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+struct Plan {
+    int prec = 0, tile = 0, Kp = 0, dim = 0;
+    bool alias = false;
+    int64_t nR = 0, nS = 0, padR = 0, padS = 0;
+    double band = 0.0;
+    int64_t band_cap = 0;
+    size_t off_info_r = 0, off_info_s = 0, off_xr = 0, off_xs = 0, off_band = 0, total = 0;
+};
+
+bool rel_ok(const ejoin_rel* X) {
+    if (!X) return false;
+    if (X->rows < 0 || X->rows >= 0x7fffffffLL) return false;
+    if (X->dim < 1 || X->ld < X->dim) return false;
+    if (X->rows > 0 && X->data == nullptr) return false;
+    return true;
+}
+
+int default_tile(int prec) { return prec == P_FP32 ? 1 : prec == P_BF16 ? 3 : 5; }
+
+ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts* o, Plan& p) {
+    if (!rel_ok(R) || !rel_ok(S) || R->dim != S->dim) return EJOIN_E_INVAL;
+    if (o->prec < EJOIN_FP32 || o->prec > EJOIN_FP8_E4M3) return EJOIN_E_INVAL;
+    p.prec = o->prec;
+    p.dim = R->dim;
+    if (p.dim > 65536) return EJOIN_E_UNSUPPORTED;
+    p.Kp = padded_k(p.prec, p.dim);
+    p.nR = R->rows;
+    p.nS = S->rows;
+    p.alias = R->data == S->data && R->rows == S->rows && R->ld == S->ld;
+    p.padR = padded_rows(p.nR);
+    p.padS = p.alias ? p.padR : padded_rows(p.nS);
+    const double rig = band_rigorous(p.prec, p.dim);
+    if (o->band < 0) {
+        p.band = rig;  // FP8: refined on the device from the measured error norms
+    } else {
+        if (!(o->band >= rig) || !isfinite(o->band)) return EJOIN_E_INVAL;
+        p.band = o->band;
+    }
+    p.tile = o->tile > 0 ? o->tile : default_tile(p.prec);
+    const TileDesc* td = tile_get(p.tile);
+    if (!td || td->prec != p.prec) return EJOIN_E_INVAL;
+    p.band_cap = o->band_capacity > 0 ? o->band_capacity
+                                      : std::max<int64_t>(1 << 16, p.nR + p.nS);
+    const size_t eb = (size_t)elem_bytes(p.prec);
+    size_t off = align256(H_COUNT * sizeof(unsigned long long));
+    p.off_info_r = off;
+    off = align256(off + (size_t)p.padR * sizeof(RowInfo));
+    p.off_info_s = p.alias ? p.off_info_r : off;
+    if (!p.alias) off = align256(off + (size_t)p.padS * sizeof(RowInfo));
+    p.off_xr = off;
+    off = align256(off + (size_t)p.padR * p.Kp * eb);
+    p.off_xs = p.alias ? p.off_xr : off;
+    if (!p.alias) off = align256(off + (size_t)p.padS * p.Kp * eb);
+    p.off_band = off;
+    off = align256(off + (size_t)p.band_cap * sizeof(int2));
+    p.total = off;
+    return EJOIN_OK;
+}
+
+ejoin_opts opts_or_default(const ejoin_opts* o) {
+    ejoin_opts d;
+    ejoin_opts_default(&d);
+    return o ? *o : d;
+}
+
+}  // namespace
+
+#define HIP_TRY(x)                                  \
+    do {                                            \
+        if ((x) != hipSuccess) return EJOIN_E_HIP;  \
+    } while (0)
+
+extern "C" {
+
+const char* ejoin_version(void) { return "ejoin-gfx950 0.1.0"; }
+
+const char* ejoin_strerror(ejoin_status s) {
+    switch (s) {
+        case EJOIN_OK: return "ok";
+        case EJOIN_E_INVAL: return "invalid argument";
+        case EJOIN_E_OVERFLOW: return "output capacity too small (n_out holds the true count)";
+        case EJOIN_E_WORKSPACE: return "workspace too small";
+        case EJOIN_E_NONFINITE: return "input row holds NaN or Inf";
+        case EJOIN_E_HIP: return "HIP runtime error";
+        case EJOIN_E_UNSUPPORTED: return "unsupported configuration";
+        case EJOIN_E_RANGE: return "row norm outside [2^-100, 2^100]";
+    }
+    return "unknown status";
+}
+
+void ejoin_opts_default(ejoin_opts* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->prec = EJOIN_FP32;
+    o->tile = 0;
+    o->band = -1.0;
+    o->band_capacity = 0;
+    o->flags = 0;
+    o->topk_cand = 0;
+}
+
+double ejoin_band_default(int32_t prec, int32_t dim) {
+    if (prec < EJOIN_FP32 || prec > EJOIN_FP8_E4M3) return -1.0;
+    return band_rigorous(prec, dim);
+}
+
+int32_t ejoin_tile_count(void) { return tile_count(); }
+
+const char* ejoin_tile_name(int32_t tile) {
+    if (tile == 0) return "auto";
+    const TileDesc* t = tile_get(tile);
+    return t ? t->name : nullptr;
+}
+
+size_t ejoin_threshold_workspace(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts* opts) {
+    ejoin_opts o = opts_or_default(opts);
+    Plan p;
+    if (make_plan(R, S, &o, p) != EJOIN_OK) return 0;
+    return p.total;
+}
+
+ejoin_status ejoin_threshold(const ejoin_rel* R, const ejoin_rel* S, double theta,
+                             const ejoin_opts* opts, ejoin_pair* out, int64_t capacity,
+                             int64_t* n_out, void* ws, size_t ws_bytes, hipStream_t stream,
+                             ejoin_stats* stats) {
+    if (!isfinite(theta) || capacity < 0 || !n_out) return EJOIN_E_INVAL;
+    if (capacity > 0 && !out) return EJOIN_E_INVAL;
+    ejoin_opts o = opts_or_default(opts);
+    Plan p;
+    ejoin_status s = make_plan(R, S, &o, p);
+    if (s != EJOIN_OK) return s;
+    const bool sync = !(o.flags & EJOIN_NO_SYNC);
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->ws_needed = p.total;
+        stats->band = p.band;
+        stats->tile = p.tile;
+    }
+    if (!ws || ws_bytes < p.total) return EJOIN_E_WORKSPACE;
+    if (p.nR == 0 || p.nS == 0) {
+        if (sync) {
+            *n_out = 0;
+        } else {
+            // still need a defined device count
+            unsigned long long* hdr = (unsigned long long*)ws;
+            HIP_TRY(launch_zero_header(hdr, stream));
+            HIP_TRY(launch_copy_count(hdr, n_out, stream));
+        }
+        return EJOIN_OK;
+    }
+
+    char* w = (char*)ws;
+    unsigned long long* hdr = (unsigned long long*)w;
+    RowInfo* info_r = (RowInfo*)(w + p.off_info_r);
+    RowInfo* info_s = (RowInfo*)(w + p.off_info_s);
+    void* xr = w + p.off_xr;
+    void* xs = w + p.off_xs;
+    int2* band = (int2*)(w + p.off_band);
+
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    const bool timing = sync && (o.flags & EJOIN_TIMING) && stats;
+    if (timing)
+        for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    auto rec = [&](int i) { return timing ? hipEventRecord(ev[i], stream) : hipSuccess; };
+
+    HIP_TRY(rec(0));
+    HIP_TRY(launch_zero_header(hdr, stream));
+    HIP_TRY(launch_prep(p.prec, R->data, p.nR, p.dim, R->ld, xr, p.Kp, p.padR, info_r, hdr,
+                        H_ENORM_R, stream));
+    if (!p.alias)
+        HIP_TRY(launch_prep(p.prec, S->data, p.nS, p.dim, S->ld, xs, p.Kp, p.padS, info_s, hdr,
+                            H_ENORM_S, stream));
+    HIP_TRY(rec(1));
+
+    ThresholdArgs a;
+    a.A = xr;
+    a.B = xs;
+    a.info_r = info_r;
+    a.info_s = info_s;
+    a.Kp = p.Kp;
+    a.nR = p.nR;
+    a.nS = p.nS;
+    a.lo = round_down_f(theta - p.band);
+    a.hi = round_up_f(theta + p.band);
+    a.out = (Pair*)out;
+    a.capacity = capacity;
+    a.band = band;
+    a.band_cap = p.band_cap;
+    a.hdr = hdr;
+    HIP_TRY(launch_threshold(p.tile, a, stream));
+    HIP_TRY(rec(2));
+    HIP_TRY(launch_rescore_band(R->data, R->ld, S->data, S->ld, p.dim, band, p.band_cap, theta,
+                                (Pair*)out, capacity, hdr, stream));
+    HIP_TRY(rec(3));
+
+    if (!sync) {
+        HIP_TRY(launch_copy_count(hdr, n_out, stream));
+        return EJOIN_OK;
+    }
+    unsigned long long h[H_COUNT];
+    HIP_TRY(hipMemcpyAsync(h, hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (timing) {
+        hipEventElapsedTime(&stats->ms_prep, ev[0], ev[1]);
+        hipEventElapsedTime(&stats->ms_main, ev[1], ev[2]);
+        hipEventElapsedTime(&stats->ms_rescore, ev[2], ev[3]);
+        hipEventElapsedTime(&stats->ms_total, ev[0], ev[3]);
+        for (auto& e : ev) hipEventDestroy(e);
+    }
+    if (h[H_FLAGS] & F_NONFINITE) return EJOIN_E_NONFINITE;
+    if (h[H_FLAGS] & F_RANGE) return EJOIN_E_RANGE;
+    *n_out = (int64_t)h[H_OUT];
+    if (stats) {
+        stats->n_pairs = (int64_t)h[H_OUT];
+        stats->n_band = (int64_t)h[H_BAND];
+        stats->n_band_accepted = (int64_t)h[H_BAND_ACC];
+        stats->n_certain = stats->n_pairs - stats->n_band_accepted;
+        stats->band_needed = (int64_t)h[H_BAND];
+    }
+    if ((int64_t)h[H_BAND] > p.band_cap) return EJOIN_E_WORKSPACE;
+    if ((int64_t)h[H_OUT] > capacity) return EJOIN_E_OVERFLOW;
+    return EJOIN_OK;
+}
+
+}  // extern "C"

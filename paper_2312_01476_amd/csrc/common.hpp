@@ -1,0 +1,113 @@
+// common.hpp -- shared device-side definitions of the gfx950 E-join kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ej {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+enum Prec : int { P_FP32 = 0, P_BF16 = 1, P_FP8 = 2 };
+
+// Workspace header: int64 counters at the start of every workspace.
+enum : int {
+    H_OUT = 0,        // matching pairs emitted so far (certain + accepted band)
+    H_BAND = 1,       // band pairs found (may exceed the band capacity)
+    H_FLAGS = 2,      // OR of row flags (non-finite / range)
+    H_CERT = 3,       // certain pairs (for the report)
+    H_BAND_ACC = 4,   // band pairs accepted by the FP64 rescore
+    H_ENORM_R = 5,    // max quantisation error norm over R rows (float bits)
+    H_ENORM_S = 6,    // same for S
+    H_MISC = 7,
+    H_COUNT = 32      // header size in int64 (256 bytes)
+};
+
+enum : uint32_t { F_NONFINITE = 1u, F_RANGE = 2u };
+
+// Per-row information written by the prep kernel.
+struct RowInfo {
+    float inv;      // 1 / ||x|| in FP32 (0 for a zero row)
+    float qscale;   // power-of-two multiplier applied before FP8 rounding (1 otherwise)
+    float enorm;    // || dequantised row - fp32 normalised row ||_2 (0 for FP32)
+    uint32_t flags; // F_* bits
+};
+
+// Result pair as laid out in the public header.
+struct Pair {
+    int32_t r;
+    int32_t s;
+    float score;
+};
+
+// ---------------------------------------------------------------------------
+// wave-level helpers (wave64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` strictly below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// ---------------------------------------------------------------------------
+// rounding to the narrow operand formats (software, round-to-nearest-even)
+// ---------------------------------------------------------------------------
+
+// float -> bfloat16 bits, RNE.  Inputs are finite here.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// OCP e4m3 (bias 7, 3 mantissa bits, max 448, no infinities): value of the
+// nearest representable number (ties to even) for |x| <= 448.
+__device__ __forceinline__ float e4m3_round(float x) {
+    float a = fabsf(x);
+    if (a == 0.0f) return x;
+    // spacing of representable numbers around a: 2^(e-3) for normals
+    // (e >= -6), 2^-9 in the subnormal range
+    int e = ilogbf(a);
+    if (e < -6) e = -6;
+    float step = ldexpf(1.0f, e - 3);
+    float q = rintf(a / step) * step;  // a/step exact (power-of-two divide)
+    return copysignf(q, x);
+}
+// Encode a value already representable in e4m3 (|q| <= 448).
+__device__ __forceinline__ uint8_t e4m3_bits(float q) {
+    uint32_t sign = (__float_as_uint(q) >> 31) & 1u;
+    float a = fabsf(q);
+    uint32_t bits;
+    if (a == 0.0f) {
+        bits = 0;
+    } else if (a < 0.015625f) {          // subnormal: a = m * 2^-9, m in 1..7
+        bits = (uint32_t)(a * 512.0f);
+    } else {
+        int e = ilogbf(a);               // -6 .. 8
+        uint32_t m = (uint32_t)(ldexpf(a, -e) * 8.0f) - 8u;   // 0..7
+        bits = ((uint32_t)(e + 7) << 3) | m;
+    }
+    return (uint8_t)((sign << 7) | bits);
+}
+
+}  // namespace ej

@@ -1,0 +1,52 @@
+// launch.hpp -- host-side launch wrappers shared between the kernel files and
+// the C ABI implementation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ej {
+
+struct RowInfo;
+struct Pair;
+
+// Tile shapes of the threshold kernel (ids are part of the ABI's tile names).
+struct TileDesc {
+    int id;
+    int prec;   // Prec
+    int bm, bn; // output tile
+    int bk;     // elements per K step (128 bytes)
+    const char* name;
+};
+int tile_count();                 // number of real tiles (ids 1..count)
+const TileDesc* tile_get(int id); // nullptr if unknown
+
+hipError_t launch_zero_header(unsigned long long* hdr, hipStream_t st);
+
+hipError_t launch_prep(int prec, const float* X, int64_t rows, int dim, int64_t ld, void* Xq,
+                       int Kp, int64_t rows_pad, RowInfo* info, unsigned long long* hdr,
+                       int enorm_slot, hipStream_t st);
+
+struct ThresholdArgs {
+    const void* A;   // normalised R copy, rows_pad_r x Kp
+    const void* B;   // normalised S copy, rows_pad_s x Kp
+    const RowInfo* info_r;
+    const RowInfo* info_s;
+    int Kp;
+    int64_t nR, nS;
+    float lo, hi;    // approximate-score band edges (rounded outward)
+    Pair* out;
+    int64_t capacity;
+    int2* band;
+    int64_t band_cap;
+    unsigned long long* hdr;
+};
+hipError_t launch_threshold(int tile_id, const ThresholdArgs& a, hipStream_t st);
+
+hipError_t launch_rescore_band(const float* R, int64_t ldR, const float* S, int64_t ldS, int dim,
+                               const int2* band, int64_t band_cap, double theta, Pair* out,
+                               int64_t capacity, unsigned long long* hdr, hipStream_t st);
+
+hipError_t launch_copy_count(const unsigned long long* hdr, int64_t* dst, hipStream_t st);
+
+}  // namespace ej

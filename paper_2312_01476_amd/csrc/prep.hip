@@ -1,0 +1,162 @@
+// prep.hip -- row preparation: L2 normalisation fused with the narrow-format
+// rounding and K padding of the operand copies.
+//
+// The tensor join computes cosine similarity as the dot product of
+// L2-normalised rows (Section IV.C).  This pass reads each input row once,
+// finds its norm, and writes the normalised row in the contraction format
+// (float32, bfloat16 or OCP e4m3 with a per-row power-of-two scale), zero
+// padded to the contraction depth Kp and to a whole number of row tiles, so
+// that the matrix-core kernel runs without bounds checks or per-element
+// scaling.  It also records per-row data used by the error bounds.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace ej {
+
+// One wave per row.  Rows >= rows (tile padding) are written as zeros.
+template <int PREC>
+__global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, int64_t rows,
+                                                 int dim, int64_t ld, void* __restrict__ Xq,
+                                                 int Kp, int64_t rows_pad,
+                                                 RowInfo* __restrict__ info,
+                                                 unsigned long long* __restrict__ hdr,
+                                                 int enorm_slot) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= rows_pad) return;
+
+    float inv = 0.0f, qscale = 1.0f, enorm = 0.0f;
+    uint32_t flags = 0;
+    const float* x = X + row * ld;
+    const bool real = row < rows;
+
+    if (real) {
+        // pass 1: finiteness and max |x|
+        float amax = 0.0f;
+        bool bad = false;
+        for (int k = lane; k < dim; k += 64) {
+            float v = x[k];
+            bad |= !isfinite(v);
+            amax = fmaxf(amax, fabsf(v));
+        }
+        bad = __any(bad);
+        amax = wave_max(amax);
+        if (bad) {
+            flags = F_NONFINITE;
+        } else if (amax > 0.0f) {
+            // pass 2: sum of squares of the row scaled by a power of two so
+            // that max |x| lands in [1, 2): no overflow or underflow
+            int e = ilogbf(amax);
+            float sc = ldexpf(1.0f, -e);
+            float ss = 0.0f;
+            for (int k = lane; k < dim; k += 64) {
+                float v = x[k] * sc;
+                ss = fmaf(v, v, ss);
+            }
+            ss = wave_sum(ss);
+            // ||x|| = sqrt(ss) * 2^e with sqrt(ss) in [1, 2 sqrt(dim))
+            if (e < -100 || e > 99) {
+                flags = F_RANGE;
+            } else {
+                inv = ldexpf(1.0f / sqrtf(ss), -e);
+            }
+        }
+    }
+    if (flags != 0 && lane == 0) atomicOr(hdr + H_FLAGS, (unsigned long long)flags);
+
+    // FP8: choose the largest power of two p with max|x_hat| * 2^p <= 448
+    if (PREC == P_FP8 && inv != 0.0f) {
+        float amax = 0.0f;
+        for (int k = lane; k < dim; k += 64) amax = fmaxf(amax, fabsf(x[k] * inv));
+        amax = wave_max(amax);
+        int p = ilogbf(448.0f / amax);
+        while (ldexpf(amax, p + 1) <= 448.0f) ++p;
+        while (ldexpf(amax, p) > 448.0f) --p;
+        qscale = ldexpf(1.0f, p);
+    }
+
+    // pass 3: write the normalised, rounded, zero-padded row
+    float esq = 0.0f;
+    if (PREC == P_FP32) {
+        float* out = (float*)Xq + row * (int64_t)Kp;
+        for (int k = lane; k < Kp; k += 64) {
+            float v = (k < dim && inv != 0.0f) ? x[k] * inv : 0.0f;
+            out[k] = v;
+        }
+    } else if (PREC == P_BF16) {
+        uint16_t* out = (uint16_t*)Xq + row * (int64_t)Kp;
+        for (int k = lane; k < Kp; k += 64) {
+            uint16_t b = 0;
+            if (k < dim && inv != 0.0f) {
+                float v = x[k] * inv;
+                b = f32_to_bf16_rne(v);
+                float e = bf16_to_f32(b) - v;
+                esq = fmaf(e, e, esq);
+            }
+            out[k] = b;
+        }
+    } else {
+        uint8_t* out = (uint8_t*)Xq + row * (int64_t)Kp;
+        const float rq = 1.0f / qscale;  // exact: power of two
+        for (int k = lane; k < Kp; k += 64) {
+            uint8_t b = 0;
+            if (k < dim && inv != 0.0f) {
+                float v = x[k] * inv;
+                float q = e4m3_round(v * qscale);
+                b = e4m3_bits(q);
+                float e = q * rq - v;
+                esq = fmaf(e, e, esq);
+            }
+            out[k] = b;
+        }
+    }
+    if (PREC != P_FP32) {
+        esq = wave_sum(esq);
+        enorm = sqrtf(esq);
+        if (enorm > 0.0f && lane == 0)
+            atomicMax((unsigned int*)(hdr + enorm_slot), __float_as_uint(enorm));
+    }
+    if (lane == 0) {
+        RowInfo ri;
+        ri.inv = inv;
+        ri.qscale = qscale;
+        ri.enorm = enorm;
+        ri.flags = flags;
+        info[row] = ri;
+    }
+}
+
+// Zero the workspace header (a kernel rather than a memset so that the call
+// sequence stays safe to capture in a graph).
+__global__ void zero_header(unsigned long long* hdr) {
+    if (threadIdx.x < H_COUNT) hdr[threadIdx.x] = 0ull;
+}
+
+hipError_t launch_zero_header(unsigned long long* hdr, hipStream_t st) {
+    hipLaunchKernelGGL(zero_header, dim3(1), dim3(64), 0, st, hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(int prec, const float* X, int64_t rows, int dim, int64_t ld, void* Xq,
+                       int Kp, int64_t rows_pad, RowInfo* info, unsigned long long* hdr,
+                       int enorm_slot, hipStream_t st) {
+    if (rows_pad <= 0) return hipSuccess;
+    dim3 grid((unsigned)((rows_pad + 3) / 4)), block(256);
+    switch (prec) {
+        case P_FP32:
+            hipLaunchKernelGGL(prep_rows<P_FP32>, grid, block, 0, st, X, rows, dim, ld, Xq, Kp,
+                               rows_pad, info, hdr, enorm_slot);
+            break;
+        case P_BF16:
+            hipLaunchKernelGGL(prep_rows<P_BF16>, grid, block, 0, st, X, rows, dim, ld, Xq, Kp,
+                               rows_pad, info, hdr, enorm_slot);
+            break;
+        default:
+            hipLaunchKernelGGL(prep_rows<P_FP8>, grid, block, 0, st, X, rows, dim, ld, Xq, Kp,
+                               rows_pad, info, hdr, enorm_slot);
+            break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ej

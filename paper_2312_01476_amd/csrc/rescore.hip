@@ -1,0 +1,102 @@
+// rescore.hip -- FP64 rescoring of the pairs whose approximate score falls in
+// the uncertainty band around theta.
+//
+// The similarity is the cosine of Section III.A.  The band pairs are decided
+// with the canonical FP64 rule, evaluated from the caller's original float32
+// rows:
+//     dot(a,b) = (((0 + a0 b0) + a1 b1) + ...)  sequential, one rounding per
+//                product and per sum (this file is compiled without FP
+//                contraction, so no fused multiply-add appears);
+//     sim64    = dot(r,s) / sqrt(dot(r,r) dot(s,s)),  0 for a zero row;
+//     accept   iff sim64 >= theta.
+// The same rule defines the exact result set, so a pair accepted here is a
+// pair of that set and the score written is sim64 rounded to float.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace ej {
+
+__device__ __forceinline__ double sim64_canonical(const float* __restrict__ r,
+                                                  const float* __restrict__ s, int dim) {
+    double dot = 0.0, nr = 0.0, ns = 0.0;
+    for (int k = 0; k < dim; ++k) {
+        const double a = (double)r[k];
+        const double b = (double)s[k];
+        dot = dot + a * b;
+        nr = nr + a * a;
+        ns = ns + b * b;
+    }
+    if (nr == 0.0 || ns == 0.0) return 0.0;
+    return dot / __builtin_sqrt(nr * ns);
+}
+
+// One lane per band pair; accepted pairs are appended to the output with one
+// atomicAdd per wave.
+__global__ __launch_bounds__(256) void rescore_band(const float* __restrict__ R, int64_t ldR,
+                                                    const float* __restrict__ S, int64_t ldS,
+                                                    int dim, const int2* __restrict__ band,
+                                                    int64_t band_cap, double theta,
+                                                    Pair* __restrict__ out, int64_t capacity,
+                                                    unsigned long long* __restrict__ hdr) {
+    if (hdr[H_FLAGS] != 0) return;
+    const int64_t n = min((int64_t)hdr[H_BAND], band_cap);
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n;
+         base += stride) {
+        const int64_t p = base + lane;
+        bool acc = false;
+        double sim = 0.0;
+        int2 e = make_int2(0, 0);
+        if (p < n) {
+            e = band[p];
+            sim = sim64_canonical(R + (int64_t)e.x * ldR, S + (int64_t)e.y * ldS, dim);
+            acc = sim >= theta;
+        }
+        const uint64_t m = __ballot(acc);
+        if (m) {
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            unsigned long long b = 0;
+            if (lane == leader) {
+                b = atomicAdd(hdr + H_OUT, (unsigned long long)__popcll(m));
+                atomicAdd(hdr + H_BAND_ACC, (unsigned long long)__popcll(m));
+            }
+            const uint32_t blo = __shfl((uint32_t)b, leader, 64);
+            const uint32_t bhi = __shfl((uint32_t)(b >> 32), leader, 64);
+            const unsigned long long bb = ((unsigned long long)bhi << 32) | blo;
+            if (acc) {
+                const unsigned long long q = bb + lanes_below(m);
+                if ((int64_t)q < capacity) {
+                    Pair pr;
+                    pr.r = e.x;
+                    pr.s = e.y;
+                    pr.score = (float)sim;
+                    out[q] = pr;
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_rescore_band(const float* R, int64_t ldR, const float* S, int64_t ldS, int dim,
+                               const int2* band, int64_t band_cap, double theta, Pair* out,
+                               int64_t capacity, unsigned long long* hdr, hipStream_t st) {
+    if (band_cap <= 0) return hipSuccess;
+    int64_t blocks = (band_cap + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(rescore_band, dim3((unsigned)blocks), dim3(256), 0, st, R, ldR, S, ldS, dim,
+                       band, band_cap, theta, out, capacity, hdr);
+    return hipGetLastError();
+}
+
+// Device-side copy of the output count (asynchronous mode).
+__global__ void copy_count(const unsigned long long* hdr, int64_t* dst) {
+    if (threadIdx.x == 0) dst[0] = (int64_t)hdr[H_OUT];
+}
+
+hipError_t launch_copy_count(const unsigned long long* hdr, int64_t* dst, hipStream_t st) {
+    hipLaunchKernelGGL(copy_count, dim3(1), dim3(64), 0, st, hdr, dst);
+    return hipGetLastError();
+}
+
+}  // namespace ej

@@ -1,0 +1,200 @@
+"""Python binding of ``libejoin.so`` (argument marshalling only).
+
+Every step of the join runs in the library's HIP kernels; this module only
+allocates device buffers through PyTorch, passes raw pointers and the current
+HIP stream across the C ABI (``include/ejoin.h``) and turns status codes into
+exceptions.  There is no CPU fallback: if the library is missing or fails to
+load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libejoin.so")
+
+OK, E_INVAL, E_OVERFLOW, E_WORKSPACE, E_NONFINITE, E_HIP, E_UNSUPPORTED, E_RANGE = range(8)
+PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "fp8_e4m3": 2}
+NO_SYNC = 0x1
+TIMING = 0x2
+
+
+class Rel(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("rows", C.c_int64), ("dim", C.c_int32), ("ld", C.c_int64)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("tile", C.c_int32), ("band", C.c_double),
+                ("band_capacity", C.c_int64), ("flags", C.c_uint32), ("topk_cand", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_pairs", C.c_int64), ("n_certain", C.c_int64), ("n_band", C.c_int64),
+                ("n_band_accepted", C.c_int64), ("band_needed", C.c_int64),
+                ("ws_needed", C.c_size_t), ("band", C.c_double), ("tile", C.c_int32),
+                ("n_fallback", C.c_int32), ("ms_prep", C.c_float), ("ms_main", C.c_float),
+                ("ms_rescore", C.c_float), ("ms_total", C.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class EjoinError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib().ejoin_strerror(status).decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libejoin.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2312_01476_amd.build` (no fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.ejoin_version.restype = C.c_char_p
+        L.ejoin_strerror.restype = C.c_char_p
+        L.ejoin_strerror.argtypes = [C.c_int]
+        L.ejoin_opts_default.argtypes = [P(Opts)]
+        L.ejoin_opts_default.restype = None
+        L.ejoin_band_default.restype = C.c_double
+        L.ejoin_band_default.argtypes = [C.c_int32, C.c_int32]
+        L.ejoin_tile_count.restype = C.c_int32
+        L.ejoin_tile_name.restype = C.c_char_p
+        L.ejoin_tile_name.argtypes = [C.c_int32]
+        L.ejoin_threshold_workspace.restype = C.c_size_t
+        L.ejoin_threshold_workspace.argtypes = [P(Rel), P(Rel), P(Opts)]
+        L.ejoin_threshold.restype = C.c_int
+        L.ejoin_threshold.argtypes = [P(Rel), P(Rel), C.c_double, P(Opts), C.c_void_p,
+                                      C.c_int64, P(C.c_int64), C.c_void_p, C.c_size_t,
+                                      C.c_void_p, P(Stats)]
+        _lib = L
+    return _lib
+
+
+def version() -> str:
+    return lib().ejoin_version().decode()
+
+
+def band_default(prec: str, dim: int) -> float:
+    return float(lib().ejoin_band_default(PREC[prec], int(dim)))
+
+
+def tiles():
+    L = lib()
+    return {i: L.ejoin_tile_name(i).decode() for i in range(1, L.ejoin_tile_count() + 1)}
+
+
+def _rel(X, d):
+    import torch
+    if not isinstance(X, torch.Tensor) or X.device.type != "cuda":
+        raise TypeError("relations must be CUDA (HIP) tensors")
+    if X.dtype != torch.float32 or X.dim() != 2:
+        raise TypeError("relations must be float32 2-D tensors")
+    n, ld = X.shape
+    if n > 0 and ld > 1 and X.stride(1) != 1:
+        raise TypeError("relations must have unit column stride")
+    dim = ld if d is None else int(d)
+    return Rel(X.data_ptr() if n > 0 else 0, n, dim, X.stride(0) if n > 1 else max(ld, dim))
+
+
+def _opts(prec, band, tile, band_capacity, flags, topk_cand=0):
+    o = Opts()
+    lib().ejoin_opts_default(C.byref(o))
+    o.prec = PREC[prec]
+    o.tile = int(tile)
+    o.band = -1.0 if band is None else float(band)
+    o.band_capacity = int(band_capacity)
+    o.flags = int(flags)
+    o.topk_cand = int(topk_cand)
+    return o
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class Pairs:
+    """Result of a threshold join: int32 offsets and float32 scores (device)."""
+    r: "object"
+    s: "object"
+    score: "object"
+    stats: dict
+
+    def __len__(self):
+        return int(self.r.shape[0])
+
+
+def threshold_workspace(R, S, *, d=None, prec="fp32", band=None, tile=0, band_capacity=0):
+    r, s = _rel(R, d), _rel(S, d)
+    o = _opts(prec, band, tile, band_capacity, 0)
+    n = lib().ejoin_threshold_workspace(C.byref(r), C.byref(s), C.byref(o))
+    if n == 0:
+        raise EjoinError(E_INVAL, "ejoin_threshold_workspace")
+    return int(n)
+
+
+def threshold_raw(R, S, theta, out, capacity, ws, *, d=None, prec="fp32", band=None, tile=0,
+                  band_capacity=0, flags=0, stream=None, n_out_dev=None):
+    """One ejoin_threshold call on caller-provided buffers (``out``: int32
+    tensor (capacity, 3); ``ws``: uint8 tensor).  Returns (status, n_out,
+    stats dict).  With NO_SYNC, ``n_out_dev`` (int64 device tensor) receives
+    the count."""
+    r, s = _rel(R, d), _rel(S, d)
+    o = _opts(prec, band, tile, band_capacity, flags)
+    st = Stats()
+    n = C.c_int64(0)
+    if flags & NO_SYNC:
+        nptr = C.cast(C.c_void_p(n_out_dev.data_ptr()), C.POINTER(C.c_int64))
+    else:
+        nptr = C.byref(n)
+    rc = lib().ejoin_threshold(C.byref(r), C.byref(s), float(theta), C.byref(o),
+                               C.c_void_p(out.data_ptr() if capacity > 0 else 0),
+                               int(capacity), nptr, C.c_void_p(ws.data_ptr()),
+                               int(ws.numel()), _stream(stream), C.byref(st))
+    return rc, int(n.value), st.as_dict()
+
+
+def threshold(R, S, theta: float, *, d=None, prec="fp32", band=None, tile=0, capacity=None,
+              band_capacity=0, timing=False, stream=None) -> Pairs:
+    """Threshold E-join on the GPU: all (i, j) with sim64(R_i, S_j) >= theta.
+
+    R, S: float32 CUDA tensors (n, ld) with unit column stride; ``d`` is the
+    embedding dimension (default: all columns).  Grows the output and band
+    buffers and retries when the library reports they were too small."""
+    import torch
+    dev = R.device
+    nR, nS = R.shape[0], S.shape[0]
+    if capacity is None:
+        capacity = max(1 << 16, min(nR * nS, (nR + nS) * 64))
+    flags = TIMING if timing else 0
+    for _ in range(4):
+        ws_bytes = threshold_workspace(R, S, d=d, prec=prec, band=band, tile=tile,
+                                       band_capacity=band_capacity)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        out = torch.empty((max(capacity, 1), 3), dtype=torch.int32, device=dev)
+        rc, n, st = threshold_raw(R, S, theta, out, capacity, ws, d=d, prec=prec, band=band,
+                                  tile=tile, band_capacity=band_capacity, flags=flags,
+                                  stream=stream)
+        if rc == OK:
+            o = out[:n]
+            return Pairs(o[:, 0], o[:, 1], o[:, 2].view(torch.float32), st)
+        if rc == E_OVERFLOW:
+            capacity = n
+            continue
+        if rc == E_WORKSPACE and st["band_needed"] > 0:
+            band_capacity = int(st["band_needed"] * 1.25) + 1024
+            continue
+        raise EjoinError(rc, "ejoin_threshold")
+    raise EjoinError(rc, "ejoin_threshold (retries exhausted)")

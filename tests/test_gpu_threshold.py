@@ -1,0 +1,222 @@
+"""Parity of the GPU threshold join (through the C ABI) with the FP64 oracle.
+
+The bar: the GPU result set equals the oracle's set exactly; every score is
+within 1e-3 of sim64 in FP32 mode and for every FP64-rescored pair, and within
+the rigorous band for the BF16/FP8 certain pairs.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2312_01476_amd import datagen as G
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+E = None
+
+
+def setup_module(module):
+    global E
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_01476_amd import ejoin
+    E = ejoin
+
+
+def _dev(X):
+    return torch.from_numpy(np.ascontiguousarray(X)).to("cuda")
+
+
+def _run(R, S, theta, d=None, **kw):
+    Rd = _dev(R)
+    Sd = Rd if S is R else _dev(S)
+    res = E.threshold(Rd, Sd, theta, d=d, **kw)
+    r = res.r.cpu().numpy().astype(np.int64)
+    s = res.s.cpu().numpy().astype(np.int64)
+    sc = res.score.cpu().numpy().astype(np.float64)
+    return r, s, sc, res.stats
+
+
+def _check(R, S, theta, d=None, prec="fp32", score_tol=None, **kw):
+    d_ = R.shape[1] if d is None else d
+    r, s, sc, st = _run(R, S, theta, d=d, prec=prec, **kw)
+    ori, osi, osc, _ = O.threshold(R, S, theta, d=d_)
+    got = set(zip(r.tolist(), s.tolist()))
+    want = set(zip(ori.tolist(), osi.tolist()))
+    assert len(got) == len(r), "duplicate pairs in GPU output"
+    missing = want - got
+    extra = got - want
+    assert not missing and not extra, (f"{prec}: {len(missing)} missing, {len(extra)} extra; "
+                                       f"e.g. {sorted(missing)[:3]} {sorted(extra)[:3]}")
+    assert st["n_pairs"] == len(r)
+    if len(r):
+        ref = O.sim64_pairs(R, S, r, s, d=d_)
+        err = np.abs(sc - ref)
+        tol = score_tol if score_tol is not None else (1e-3 if prec == "fp32" else st["band"])
+        assert err.max() <= tol, (prec, err.max())
+    return st
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_words_1k_full(prec):
+    w = G.WORKLOADS["words_1k"]
+    R, S, lr, ls = G.make_host(w)
+    st = _check(R, S, w.theta, d=w.d, prec=prec)
+    assert st["n_pairs"] == int((lr[:, None] == ls[None, :]).sum())
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (5, 7, 3), (130, 257, 33), (300, 129, 300),
+                                   (257, 513, 768)])
+def test_ragged_random(prec, shape):
+    nr, ns, d = shape
+    R = G.gaussian_raw(nr, d, seed=nr * 7 + d)
+    S = G.gaussian_raw(ns, d, seed=ns * 11 + d)
+    sims = O.sim_matrix(R, S)
+    for q in (0.5, 0.99):
+        theta = float(np.quantile(sims, q))
+        _check(R, S, theta, prec=prec)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_planted_pairs_around_theta(prec):
+    """Pairs planted at theta +- tiny offsets land in the band and must be
+    decided exactly by the FP64 rescore."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    d = 300
+    R = G.uniform_sphere(200, d, seed=1)
+    S = G.uniform_sphere(300, d, seed=2)
+    theta = 0.8
+    # make S[j] = cos(phi) R[i] + sin(phi) u for u orthogonal to R[i]
+    planted = []
+    offs = [-1e-3, -1e-5, -1e-7, 0.0, 1e-7, 1e-5, 1e-3]
+    for t, off in enumerate(offs * 4):
+        i, j = 3 * t, 5 * t + 1
+        r = R[i].astype(np.float64)
+        u = rng.standard_normal(d)
+        u -= (u @ r) / (r @ r) * r
+        u /= np.linalg.norm(u)
+        c = theta + off
+        S[j] = (c * r / np.linalg.norm(r) + np.sqrt(1 - c * c) * u).astype(np.float32)
+        planted.append((i, j))
+    st = _check(R, S, theta, prec=prec)
+    assert st["n_band"] >= len(planted) // 2
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_self_join_alias_symmetric(prec):
+    X = G.gaussian_raw(333, 64, seed=3)
+    X[10] = X[4]
+    res = E.threshold(_dev(X), _dev(X), 0.3, prec=prec)          # distinct buffers
+    Xd = _dev(X)
+    res2 = E.threshold(Xd, Xd, 0.3, prec=prec)                  # aliased
+    a = set(zip(res.r.cpu().tolist(), res.s.cpu().tolist()))
+    b = set(zip(res2.r.cpu().tolist(), res2.s.cpu().tolist()))
+    assert a == b
+    assert all((j, i) in b for (i, j) in b)
+    assert all((i, i) in b for i in range(X.shape[0]))
+    _check(X, X, 0.3, prec=prec)
+
+
+def test_zero_rows_and_theta_extremes():
+    R = G.gaussian_raw(70, 20, seed=8)
+    S = G.gaussian_raw(90, 20, seed=9)
+    R[5] = 0.0
+    S[7] = 0.0
+    for theta in (-2.0, -1.0, -1e-6, 0.0, 1e-6, 0.5, 1.0, 1.0 + 1e-6, 3.0):
+        _check(R, S, theta)
+        _check(R, S, theta, prec="bf16")
+
+
+def test_padding_columns_never_read():
+    w = G.WORKLOADS["words_1k"]
+    R, S, _, _ = G.make_host(w, n_r=300, n_s=200, pad_value=np.nan)
+    _check(R, S, w.theta, d=w.d)
+
+
+def test_nonfinite_and_range_errors():
+    R = G.gaussian_raw(40, 16, seed=1)
+    S = G.gaussian_raw(50, 16, seed=2)
+    R2 = R.copy()
+    R2[3, 2] = np.inf
+    with pytest.raises(E.EjoinError) as ei:
+        E.threshold(_dev(R2), _dev(S), 0.5)
+    assert ei.value.status == E.E_NONFINITE
+    S2 = S.copy()
+    S2[4] *= np.float32(2.0 ** -110)
+    with pytest.raises(E.EjoinError) as ei:
+        E.threshold(_dev(R), _dev(S2), 0.5)
+    assert ei.value.status == E.E_RANGE
+
+
+def test_empty_inputs():
+    R = G.gaussian_raw(0, 16, seed=1)
+    S = G.gaussian_raw(50, 16, seed=2)
+    res = E.threshold(_dev(R).reshape(0, 16), _dev(S), 0.1)
+    assert len(res) == 0
+    res = E.threshold(_dev(S), _dev(R).reshape(0, 16), 0.1)
+    assert len(res) == 0
+
+
+def test_overflow_reports_true_count_then_retry():
+    R = G.gaussian_raw(100, 8, seed=4)
+    S = G.gaussian_raw(100, 8, seed=5)
+    Rd, Sd = _dev(R), _dev(S)
+    ws = torch.empty(E.threshold_workspace(Rd, Sd), dtype=torch.uint8, device="cuda")
+    out = torch.empty((10, 3), dtype=torch.int32, device="cuda")
+    rc, n, st = E.threshold_raw(Rd, Sd, 0.0, out, 10, ws)
+    assert rc == E.E_OVERFLOW
+    ori, _, _, _ = O.threshold(R, S, 0.0)
+    assert n == len(ori)
+    out = torch.empty((n, 3), dtype=torch.int32, device="cuda")
+    rc, n2, st = E.threshold_raw(Rd, Sd, 0.0, out, n, ws)
+    assert rc == E.OK and n2 == n
+
+
+def test_band_capacity_too_small_reports_workspace():
+    """Everything in the band (theta at the common similarity of identical
+    rows): a tiny band list must be reported, then the retry is exact."""
+    X = np.tile(G.gaussian_raw(1, 32, seed=6), (50, 1))
+    Xd = _dev(X)
+    ws_small = E.threshold_workspace(Xd, Xd, band_capacity=16)
+    ws = torch.empty(ws_small, dtype=torch.uint8, device="cuda")
+    out = torch.empty((4000, 3), dtype=torch.int32, device="cuda")
+    rc, n, st = E.threshold_raw(Xd, Xd, 1.0, out, 4000, ws, band_capacity=16)
+    assert rc == E.E_WORKSPACE and st["band_needed"] == 2500
+    res = E.threshold(Xd, Xd, 1.0, band_capacity=16)
+    assert len(res) == 2500
+
+
+def test_invalid_arguments():
+    R = _dev(G.gaussian_raw(10, 8, seed=1))
+    S = _dev(G.gaussian_raw(10, 9, seed=2))
+    with pytest.raises(E.EjoinError) as ei:
+        E.threshold(R, S, 0.5)
+    assert ei.value.status == E.E_INVAL
+    with pytest.raises(E.EjoinError):
+        E.threshold(R, R, float("nan"))
+    with pytest.raises(E.EjoinError):
+        E.threshold(R, R, 0.5, band=1e-9)  # narrower than the rigorous bound
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+def test_tile_shapes_give_identical_sets_fp32(tile):
+    w = G.WORKLOADS["fp32_100k"]
+    R, S, lr, ls = G.make_host(w, n_r=3000, n_s=2500)
+    _check(R, S, w.theta, d=w.d, tile=tile)
+
+
+@pytest.mark.parametrize("tile", [3, 4])
+def test_tile_shapes_bf16(tile):
+    w = G.WORKLOADS["bf16_1m"]
+    R, S, lr, ls = G.make_host(w, n_r=2000, n_s=3000)
+    st = _check(R, S, w.theta, d=w.d, prec="bf16", band=w.band, tile=tile)
+    assert st["n_pairs"] == int((lr[:, None] == ls[None, :]).sum())
+
+
+@pytest.mark.parametrize("tile", [5, 6])
+def test_tile_shapes_fp8(tile):
+    w = G.WORKLOADS["fp8_topk_2m"]
+    R, S, lr, ls = G.make_host(w, n_r=1000, n_s=1500)
+    _check(R, S, 0.8, d=w.d, prec="fp8", tile=tile)
