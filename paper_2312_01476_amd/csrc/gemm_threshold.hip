@@ -91,7 +91,8 @@ template <int PREC, int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(WM* WN * 64) void threshold_tile(
     const char* __restrict__ A, const char* __restrict__ B, const RowInfo* __restrict__ info_r,
     const RowInfo* __restrict__ info_s, int Kp_bytes, int64_t nR, int64_t nS,
-    int tiles_m, int tiles_n, float lo, float hi, Pair* __restrict__ out, int64_t capacity,
+    int tiles_m, int tiles_n, int ntiles, float lo, float hi, Pair* __restrict__ out,
+    int64_t capacity,
     int2* __restrict__ band, int64_t band_cap, unsigned long long* __restrict__ hdr) {
     constexpr int NT = WM * WN * 64;
     constexpr int NW = WM * WN;
@@ -109,12 +110,17 @@ __global__ __launch_bounds__(WM* WN * 64) void threshold_tile(
     __shared__ uint32_t s_cnt[2 * NW];
     __shared__ unsigned long long s_base[2];
 
+    // 2-D grid (a 1-D grid of this many workgroups would overflow the 32-bit
+    // dispatch size); workgroups past the last tile leave at once
+    int bid = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if (bid >= ntiles) return;
     if (hdr[H_FLAGS] != 0) return;  // bad input rows: nothing to compute
 
     // ---- tile index: XCD-aware remap, then grouped rasterisation ----
-    const int nb = gridDim.x;
-    int bid = blockIdx.x;
-    const int full = nb & ~7;
+    // Workgroups are dispatched to the 8 XCDs round-robin; remapping gives
+    // each XCD a contiguous range of tiles, so the tiles that run together
+    // on one XCD share operand panels in that XCD's L2.
+    const int full = ntiles & ~7;
     if (bid < full) bid = (bid & 7) * (full >> 3) + (bid >> 3);
     constexpr int GROUP_M = 8;
     const int per_group = GROUP_M * tiles_n;
@@ -315,6 +321,11 @@ static const TileDesc kTiles[] = {
     {4, P_BF16, 256, 128, 64, "bf16:256x128x64"},
     {5, P_FP8, 128, 128, 128, "fp8:128x128x128"},
     {6, P_FP8, 256, 128, 128, "fp8:256x128x128"},
+    {7, P_BF16, 256, 256, 64, "bf16:256x256x64/4w"},
+    {8, P_BF16, 256, 256, 64, "bf16:256x256x64/8w"},
+    {9, P_FP8, 256, 256, 128, "fp8:256x256x128/4w"},
+    {10, P_FP8, 256, 256, 128, "fp8:256x256x128/8w"},
+    {11, P_FP32, 256, 128, 32, "fp32:256x128x32"},
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -330,11 +341,14 @@ static hipError_t run(const ThresholdArgs& a, hipStream_t st) {
     const int64_t nblocks = tm * tn;
     if (nblocks == 0) return hipSuccess;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int64_t gx = nblocks < 65536 ? nblocks : 65536;
+    const int64_t gy = (nblocks + gx - 1) / gx;
+    if (gy > 65535) return hipErrorInvalidValue;
     const int kpb = a.Kp * (PREC == P_FP32 ? 4 : PREC == P_BF16 ? 2 : 1);
-    hipLaunchKernelGGL((threshold_tile<PREC, BM, BN, WM, WN>), dim3((unsigned)nblocks),
+    hipLaunchKernelGGL((threshold_tile<PREC, BM, BN, WM, WN>), dim3((unsigned)gx, (unsigned)gy),
                        dim3(WM * WN * 64), 0, st, (const char*)a.A, (const char*)a.B, a.info_r,
                        a.info_s, kpb, a.nR,
-                       a.nS, (int)tm, (int)tn, a.lo, a.hi, a.out, a.capacity, a.band, a.band_cap,
+                       a.nS, (int)tm, (int)tn, (int)nblocks, a.lo, a.hi, a.out, a.capacity, a.band, a.band_cap,
                        a.hdr);
     return hipGetLastError();
 }
@@ -347,6 +361,11 @@ hipError_t launch_threshold(int tile_id, const ThresholdArgs& a, hipStream_t st)
         case 4: return run<P_BF16, 256, 128, 2, 2>(a, st);
         case 5: return run<P_FP8, 128, 128, 2, 2>(a, st);
         case 6: return run<P_FP8, 256, 128, 2, 2>(a, st);
+        case 7: return run<P_BF16, 256, 256, 2, 2>(a, st);
+        case 8: return run<P_BF16, 256, 256, 2, 4>(a, st);
+        case 9: return run<P_FP8, 256, 256, 2, 2>(a, st);
+        case 10: return run<P_FP8, 256, 256, 2, 4>(a, st);
+        case 11: return run<P_FP32, 256, 128, 2, 2>(a, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -22,8 +22,9 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
                                                  unsigned long long* __restrict__ hdr,
                                                  int enorm_slot) {
     const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= rows_pad) return;
+    // grid-stride over rows, one wave per row
+    for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < rows_pad;
+         row += (int64_t)gridDim.x * 4) {
 
     float inv = 0.0f, qscale = 1.0f, enorm = 0.0f;
     uint32_t flags = 0;
@@ -124,6 +125,7 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
         ri.flags = flags;
         info[row] = ri;
     }
+    }
 }
 
 // Zero the workspace header (a kernel rather than a memset so that the call
@@ -141,7 +143,9 @@ hipError_t launch_prep(int prec, const float* X, int64_t rows, int dim, int64_t 
                        int Kp, int64_t rows_pad, RowInfo* info, unsigned long long* hdr,
                        int enorm_slot, hipStream_t st) {
     if (rows_pad <= 0) return hipSuccess;
-    dim3 grid((unsigned)((rows_pad + 3) / 4)), block(256);
+    int64_t nb = (rows_pad + 3) / 4;
+    if (nb > 65536) nb = 65536;
+    dim3 grid((unsigned)nb), block(256);
     switch (prec) {
         case P_FP32:
             hipLaunchKernelGGL(prep_rows<P_FP32>, grid, block, 0, st, X, rows, dim, ld, Xq, Kp,
