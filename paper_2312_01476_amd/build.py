@@ -26,7 +26,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
 PER_FILE = {
     "rescore.hip": ["-ffp-contract=off"],
 }
-SOURCES = ["prep.hip", "gemm_threshold.hip", "rescore.hip", "api.cpp"]
+SOURCES = ["prep.hip", "gemm_threshold.hip", "panel.hip", "rescore.hip", "api.cpp"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -80,7 +80,13 @@ bool rel_ok(const ejoin_rel* X) {
     return true;
 }
 
-int default_tile(int prec) { return prec == P_FP32 ? 1 : prec == P_BF16 ? 3 : 5; }
+// planner default: the register-resident panel kernel for narrow formats
+// whose rows fit it (up to 768 bytes of K), else the LDS tile kernel
+int default_tile(int prec, int Kp) {
+    if (prec == P_FP32) return 1;
+    if (Kp * elem_bytes(prec) <= 768) return prec == P_BF16 ? 14 : 13;
+    return prec == P_BF16 ? 3 : 5;
+}
 
 ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts* o, Plan& p) {
     if (!rel_ok(R) || !rel_ok(S) || R->dim != S->dim) return EJOIN_E_INVAL;
@@ -101,9 +107,10 @@ ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts*
         if (!(o->band >= rig) || !isfinite(o->band)) return EJOIN_E_INVAL;
         p.band = o->band;
     }
-    p.tile = o->tile > 0 ? o->tile : default_tile(p.prec);
+    p.tile = o->tile > 0 ? o->tile : default_tile(p.prec, p.Kp);
     const TileDesc* td = tile_get(p.tile);
     if (!td || td->prec != p.prec) return EJOIN_E_INVAL;
+    if (td->bm == 0 && p.Kp * elem_bytes(p.prec) > 768) return EJOIN_E_INVAL;
     p.band_cap = o->band_capacity > 0 ? o->band_capacity
                                       : std::max<int64_t>(1 << 16, p.nR + p.nS);
     const size_t eb = (size_t)elem_bytes(p.prec);

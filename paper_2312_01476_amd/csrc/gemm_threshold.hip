@@ -21,71 +21,9 @@
 // (hits of lower lanes, mbcnt).
 #include "common.hpp"
 #include "launch.hpp"
+#include "mma.hpp"
 
 namespace ej {
-
-// ---------------------------------------------------------------------------
-// matrix-core step per precision
-//
-// Every operand row is stored in LDS as 128-byte K slices made of eight
-// 16-byte chunks.  For one MFMA a lane reads the chunk(s) of its row given by
-// its lane half; the A and B operands are read with the same chunk schedule,
-// so the pairing of k indices inside the instruction is consistent whatever
-// order the hardware sums them in.
-// ---------------------------------------------------------------------------
-template <int PREC>
-struct Mma;
-
-template <>
-struct Mma<P_FP32> {
-    // v_mfma_f32_32x32x2_f32: per lane one float of A and of B.
-    // A k-group is two chunks (half h reads chunk 2g+h) = 4 MFMAs.
-    static constexpr int GROUPS = 4;     // k-groups per 128-byte slice
-    static constexpr int CPL = 1;        // chunks per lane per group
-    typedef v4i Frag;
-    static __device__ __forceinline__ int chunk(int g, int h, int c) { return 2 * g + h; }
-    static __device__ __forceinline__ void mma(const Frag& a, const Frag& b, v16f& acc, int, int) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(a[j]), __int_as_float(b[j]),
-                                                       acc, 0, 0, 0);
-    }
-};
-
-template <>
-struct Mma<P_BF16> {
-    // v_mfma_f32_32x32x16_bf16: per lane 8 bf16 (one chunk) of A and of B.
-    static constexpr int GROUPS = 4;
-    static constexpr int CPL = 1;
-    typedef v4i Frag;
-    static __device__ __forceinline__ int chunk(int g, int h, int c) { return 2 * g + h; }
-    static __device__ __forceinline__ void mma(const Frag& a, const Frag& b, v16f& acc, int, int) {
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a),
-                                                      __builtin_bit_cast(v8bf, b), acc, 0, 0, 0);
-    }
-};
-
-template <>
-struct Mma<P_FP8> {
-    // v_mfma_scale_f32_32x32x64_f8f6f4 with e4m3 operands: per lane 32
-    // bytes (two chunks) of A and of B, and one E8M0 scale per lane that
-    // covers the lane's 32 k values.  The scale of a row is 2^-p, the
-    // inverse of the power of two the prep kernel applied before rounding,
-    // so the accumulator is the dot of the normalised rows directly.
-    static constexpr int GROUPS = 2;
-    static constexpr int CPL = 2;
-    typedef v8i Frag;
-    static __device__ __forceinline__ int chunk(int g, int h, int c) { return 4 * g + 2 * h + c; }
-    static __device__ __forceinline__ void mma(const Frag& a, const Frag& b, v16f& acc, int sa,
-                                               int sb) {
-        acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, sa, 0, sb);
-    }
-};
-
-// byte offset of 16-byte chunk c of LDS row `row` (XOR swizzle on the chunk
-// index so that 8 consecutive rows read at the same chunk hit 8 different
-// bank groups)
-__device__ __forceinline__ int lds_off(int row, int c) { return row * 128 + ((c ^ (row & 7)) << 4); }
 
 template <int PREC, int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__(WM* WN * 64) void threshold_tile(
@@ -326,6 +264,11 @@ static const TileDesc kTiles[] = {
     {9, P_FP8, 256, 256, 128, "fp8:256x256x128/4w"},
     {10, P_FP8, 256, 256, 128, "fp8:256x256x128/8w"},
     {11, P_FP32, 256, 128, 32, "fp32:256x128x32"},
+    // register-resident R panels (K up to 768 bytes per row)
+    {12, P_BF16, 0, 0, 64, "bf16:panel"},
+    {13, P_FP8, 0, 0, 128, "fp8:panel"},
+    {14, P_BF16, 0, 0, 64, "bf16:panel/2wg"},
+    {15, P_FP8, 0, 0, 128, "fp8:panel/2wg"},
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -366,6 +309,10 @@ hipError_t launch_threshold(int tile_id, const ThresholdArgs& a, hipStream_t st)
         case 9: return run<P_FP8, 256, 256, 2, 2>(a, st);
         case 10: return run<P_FP8, 256, 256, 2, 4>(a, st);
         case 11: return run<P_FP32, 256, 128, 2, 2>(a, st);
+        case 12: return launch_threshold_panel(P_BF16, false, a, st);
+        case 13: return launch_threshold_panel(P_FP8, false, a, st);
+        case 14: return launch_threshold_panel(P_BF16, true, a, st);
+        case 15: return launch_threshold_panel(P_FP8, true, a, st);
         default: return hipErrorInvalidValue;
     }
 }

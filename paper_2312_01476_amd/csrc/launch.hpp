@@ -42,6 +42,8 @@ struct ThresholdArgs {
     unsigned long long* hdr;
 };
 hipError_t launch_threshold(int tile_id, const ThresholdArgs& a, hipStream_t st);
+hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs& a,
+                                  hipStream_t st);
 
 hipError_t launch_rescore_band(const float* R, int64_t ldR, const float* S, int64_t ldS, int dim,
                                const int2* band, int64_t band_cap, double theta, Pair* out,

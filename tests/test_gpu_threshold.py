@@ -200,14 +200,14 @@ def test_invalid_arguments():
         E.threshold(R, R, 0.5, band=1e-9)  # narrower than the rigorous bound
 
 
-@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("tile", [1, 2, 11])
 def test_tile_shapes_give_identical_sets_fp32(tile):
     w = G.WORKLOADS["fp32_100k"]
     R, S, lr, ls = G.make_host(w, n_r=3000, n_s=2500)
     _check(R, S, w.theta, d=w.d, tile=tile)
 
 
-@pytest.mark.parametrize("tile", [3, 4])
+@pytest.mark.parametrize("tile", [3, 4, 8, 12, 14])
 def test_tile_shapes_bf16(tile):
     w = G.WORKLOADS["bf16_1m"]
     R, S, lr, ls = G.make_host(w, n_r=2000, n_s=3000)
@@ -215,8 +215,21 @@ def test_tile_shapes_bf16(tile):
     assert st["n_pairs"] == int((lr[:, None] == ls[None, :]).sum())
 
 
-@pytest.mark.parametrize("tile", [5, 6])
+@pytest.mark.parametrize("tile", [5, 6, 10, 13])
 def test_tile_shapes_fp8(tile):
     w = G.WORKLOADS["fp8_topk_2m"]
     R, S, lr, ls = G.make_host(w, n_r=1000, n_s=1500)
     _check(R, S, 0.8, d=w.d, prec="fp8", tile=tile)
+
+
+@pytest.mark.parametrize("prec,d", [("bf16", 64), ("bf16", 200), ("bf16", 384), ("fp8", 128),
+                                    ("fp8", 300), ("fp8", 700)])
+def test_panel_kernel_depths(prec, d):
+    """Every resident-fragment depth of the panel kernel, ragged |R| and |S|
+    (several panels, S chunks and a partial last tile)."""
+    cent = G.centres(d, 40, seed=d)
+    R, lr = G.clustered_points(cent, 1100, 0.3, seed=d + 1)
+    S, ls = G.clustered_points(cent, 1900, 0.3, seed=d + 2)
+    tile = 12 if prec == "bf16" else 13
+    st = _check(R, S, 0.7, prec=prec, tile=tile)
+    assert st["tile"] == tile
