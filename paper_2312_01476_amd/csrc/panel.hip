@@ -169,40 +169,57 @@ __global__ __launch_bounds__(256, OCC) void threshold_panel(
         }
 
         // ---- epilogue of S tile t ----
-        // Interior tiles skip the bounds test.  Four accumulators (four rows
-        // of one column per lane) are screened with one compare of their
-        // maximum; only a group with a possible hit is split per register.
+        // Phase 1 (no branches): one wave mask per group of four
+        // accumulators (four rows of one column per lane), from a compare of
+        // their maximum.  Phase 2: only groups with a possible hit are split
+        // per register; interior tiles skip the bounds test.
         const bool edge = redge || (int64_t)(t + 1) * PN_BN > nS;
         const int gi0 = r0 + 4 * h;               // + rb*32 + 8*(e/4) + e%4
         const int gj0 = t * PN_BN + r32;          // + cb*32
+        uint64_t gmask[RB][CB][4];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-                for (int e4 = 0; e4 < 16; e4 += 4) {
-                    const float m4 = fmaxf(fmaxf(acc[rb][cb][e4], acc[rb][cb][e4 + 1]),
-                                           fmaxf(acc[rb][cb][e4 + 2], acc[rb][cb][e4 + 3]));
-                    if (__ballot(m4 >= lo)) {
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const int e4 = 4 * q4;
+                    const float m4 =
+                        __builtin_fmaxf(__builtin_fmaxf(acc[rb][cb][e4], acc[rb][cb][e4 + 1]),
+                                        __builtin_fmaxf(acc[rb][cb][e4 + 2], acc[rb][cb][e4 + 3]));
+                    gmask[rb][cb][q4] = __ballot(m4 >= lo);
+                }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const int e4 = 4 * q4;
+                    if (gmask[rb][cb][q4]) {
                         // room for the at most 4 x 64 hits of this group
                         if (n_out > PN_OUTCAP - 256)
                             flush_stage(sOut[wave], n_out, out, capacity, hdr + H_OUT, lane);
                         if (n_band > PN_BANDCAP - 256)
                             flush_stage(sBand[wave], n_band, band, band_cap, hdr + H_BAND, lane);
                         const int gj = gj0 + cb * 32;
+                        const bool vj = !edge || gj < nS;
+                        uint64_t ml[4];
 #pragma unroll
-                        for (int e = e4; e < e4 + 4; ++e) {
-                            const float a = acc[rb][cb][e];
-                            const int gi = gi0 + rb * 32 + 8 * (e >> 2) + (e & 3);
-                            bool in_lo = a >= lo, in_hi = a >= hi;
-                            if (edge) {
-                                const bool v = gi < nR && gj < nS;
-                                in_lo = in_lo && v;
-                                in_hi = in_hi && v;
-                            }
-                            const uint64_t mlo = __ballot(in_lo);
+                        for (int k = 0; k < 4; ++k) {
+                            const int gi = gi0 + rb * 32 + 8 * q4 + k;
+                            const bool v = vj && (!edge || gi < nR);
+                            ml[k] = __ballot(v && acc[rb][cb][e4 + k] >= lo);
+                        }
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            if (!ml[k]) continue;
+                            const float a = acc[rb][cb][e4 + k];
+                            const int gi = gi0 + rb * 32 + 8 * q4 + k;
+                            const bool in_lo = (ml[k] >> lane) & 1ull;
+                            const bool in_hi = in_lo && a >= hi;
                             const uint64_t mhi = __ballot(in_hi);
-                            const uint64_t mb = mlo & ~mhi;
+                            const uint64_t mb = ml[k] & ~mhi;
                             if (in_hi) {
                                 Pair pr;
                                 pr.r = gi;
