@@ -22,6 +22,7 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
                                                  unsigned long long* __restrict__ hdr,
                                                  int enorm_slot) {
     const int lane = threadIdx.x & 63;
+    float wave_emax = 0.0f;  // largest error norm seen by this wave
     // grid-stride over rows, one wave per row
     for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < rows_pad;
          row += (int64_t)gridDim.x * 4) {
@@ -114,8 +115,7 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
     if (PREC != P_FP32) {
         esq = wave_sum(esq);
         enorm = sqrtf(esq);
-        if (enorm > 0.0f && lane == 0)
-            atomicMax((unsigned int*)(hdr + enorm_slot), __float_as_uint(enorm));
+        wave_emax = fmaxf(wave_emax, enorm);
     }
     if (lane == 0) {
         RowInfo ri;
@@ -125,6 +125,14 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
         ri.flags = flags;
         info[row] = ri;
     }
+    }
+    // one atomic per workgroup for the maximum error norm
+    __shared__ float s_emax[4];
+    if (lane == 0) s_emax[threadIdx.x >> 6] = wave_emax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float m = fmaxf(fmaxf(s_emax[0], s_emax[1]), fmaxf(s_emax[2], s_emax[3]));
+        if (m > 0.0f) atomicMax((unsigned int*)(hdr + enorm_slot), __float_as_uint(m));
     }
 }
 
@@ -144,7 +152,7 @@ hipError_t launch_prep(int prec, const float* X, int64_t rows, int dim, int64_t 
                        int enorm_slot, hipStream_t st) {
     if (rows_pad <= 0) return hipSuccess;
     int64_t nb = (rows_pad + 3) / 4;
-    if (nb > 65536) nb = 65536;
+    if (nb > 4096) nb = 4096;  // 16 workgroups per CU, a few rows per wave
     dim3 grid((unsigned)nb), block(256);
     switch (prec) {
         case P_FP32:
