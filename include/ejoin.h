@@ -109,6 +109,8 @@ typedef struct {
     int32_t tile;           /* tile id used */
     int32_t n_fallback;     /* top-k: rows recomputed by the exact row scan */
     float ms_prep, ms_main, ms_rescore, ms_total;  /* with EJOIN_TIMING */
+    double topk_floor;      /* top-k: candidate floor used by the sweep */
+    int32_t topk_slots;     /* top-k: candidate slots per row */
 } ejoin_stats;
 
 /* Library version string (static storage). */
@@ -152,6 +154,33 @@ ejoin_status ejoin_threshold(const ejoin_rel *R, const ejoin_rel *S, double thet
                              const ejoin_opts *opts, ejoin_pair *out, int64_t capacity,
                              int64_t *n_out, void *ws, size_t ws_bytes,
                              hipStream_t stream, ejoin_stats *stats);
+
+/*
+ * Workspace bytes needed by ejoin_topk (host arguments; 0 on bad arguments or
+ * an unsupported combination).
+ */
+size_t ejoin_topk_workspace(const ejoin_rel *R, const ejoin_rel *S, int32_t k,
+                            const ejoin_opts *opts);
+
+/*
+ * Top-k E-join (the top-k join condition of Section VI.E): for every R row i,
+ * the first min(k, |S|) S indices in the order (sim64 desc, index asc).
+ *   out_idx    device int32 [|R| * k], row-major; slots past |S| hold -1.
+ *   out_score  device float [|R| * k]: float(sim64); -inf in empty slots.
+ *   opts->prec EJOIN_BF16 (dim <= 384) or EJOIN_FP8_E4M3 (dim <= 768) for the
+ *              contraction sweep; the result is exact in both (EJOIN_FP32 and
+ *              larger dims return EJOIN_E_UNSUPPORTED).
+ *   opts->topk_cand  candidate slots per row (k..256; <= 0: 256).
+ * 1 <= k <= 256.  The call runs a pilot (exact FP64 top-k of up to 256 sample
+ * rows) to set a candidate floor, one contraction sweep that keeps every
+ * column above the floor, and a per-row finalize that certifies the candidate
+ * set (no slot overflow, k-th score minus twice the row's error bound at or
+ * above the floor), rescores it in FP64 and sorts it; rows that fail the
+ * certificate take an exact FP64 scan (reported in stats->n_fallback).
+ */
+ejoin_status ejoin_topk(const ejoin_rel *R, const ejoin_rel *S, int32_t k, const ejoin_opts *opts,
+                        int32_t *out_idx, float *out_score, void *ws, size_t ws_bytes,
+                        hipStream_t stream, ejoin_stats *stats);
 
 /* Number of tile shapes the library was built with, and the name of one
  * ("prec:BMxBNxBK"); id 0 is "planner's choice".  Static storage. */

@@ -25,11 +25,12 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 PER_FILE = {
     "rescore.hip": ["-ffp-contract=off"],
+    "topk.hip": ["-ffp-contract=off"],
     # accumulators of the panel kernel are always finite: IEEE mode off lets
     # min/max skip NaN canonicalisation in the threshold screening
     "panel.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"],
 }
-SOURCES = ["prep.hip", "gemm_threshold.hip", "panel.hip", "rescore.hip", "api.cpp"]
+SOURCES = ["prep.hip", "gemm_threshold.hip", "panel.hip", "rescore.hip", "topk.hip", "api.cpp"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -129,6 +129,54 @@ ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts*
     return EJOIN_OK;
 }
 
+// ---- top-k plan ----
+struct TopkPlan {
+    Plan base;      // prep part (no band list)
+    int Kc = 0, n_pilot = 0;
+    bool all_columns = false;
+    size_t off_nr = 0, off_ns = 0, off_cnt = 0, off_cand = 0, off_fb = 0, off_prow = 0,
+           off_pkth = 0, total = 0;
+};
+
+ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const ejoin_opts* o,
+                            TopkPlan& tp) {
+    if (k < 1) return EJOIN_E_INVAL;
+    if (k > 256) return EJOIN_E_UNSUPPORTED;
+    if (!rel_ok(R) || !rel_ok(S) || R->dim != S->dim) return EJOIN_E_INVAL;
+    if (o->prec != EJOIN_BF16 && o->prec != EJOIN_FP8_E4M3)
+        return o->prec == EJOIN_FP32 ? EJOIN_E_UNSUPPORTED : EJOIN_E_INVAL;
+    if (padded_k(o->prec, R->dim) * elem_bytes(o->prec) > 768) return EJOIN_E_UNSUPPORTED;
+    ejoin_opts ob = *o;
+    ob.tile = 0;
+    ob.band = -1.0;
+    ob.band_capacity = 1;
+    ejoin_status s = make_plan(R, S, &ob, tp.base);
+    if (s != EJOIN_OK) return s;
+    Plan& p = tp.base;
+    tp.Kc = o->topk_cand > 0 ? o->topk_cand : 256;
+    if (tp.Kc < k) tp.Kc = k;
+    if (tp.Kc > 256) return EJOIN_E_INVAL;
+    tp.all_columns = p.nS <= tp.Kc;
+    tp.n_pilot = (int)std::min<int64_t>(256, p.nR);
+    size_t off = p.off_band;  // the band list is not used by top-k
+    tp.off_nr = off;
+    off = align256(off + (size_t)p.padR * sizeof(double));
+    tp.off_ns = p.alias ? tp.off_nr : off;
+    if (!p.alias) off = align256(off + (size_t)p.padS * sizeof(double));
+    tp.off_cnt = off;
+    off = align256(off + (size_t)p.padR * sizeof(int));
+    tp.off_cand = off;
+    off = align256(off + (size_t)p.padR * tp.Kc * sizeof(int2));
+    tp.off_fb = off;
+    off = align256(off + (size_t)p.padR * sizeof(int));
+    tp.off_prow = off;
+    off = align256(off + 256 * sizeof(int));
+    tp.off_pkth = off;
+    off = align256(off + 256 * sizeof(double));
+    tp.total = off;
+    return EJOIN_OK;
+}
+
 ejoin_opts opts_or_default(const ejoin_opts* o) {
     ejoin_opts d;
     ejoin_opts_default(&d);
@@ -189,6 +237,124 @@ size_t ejoin_threshold_workspace(const ejoin_rel* R, const ejoin_rel* S, const e
     Plan p;
     if (make_plan(R, S, &o, p) != EJOIN_OK) return 0;
     return p.total;
+}
+
+size_t ejoin_topk_workspace(const ejoin_rel* R, const ejoin_rel* S, int32_t k,
+                            const ejoin_opts* opts) {
+    ejoin_opts o = opts_or_default(opts);
+    TopkPlan tp;
+    if (make_topk_plan(R, S, k, &o, tp) != EJOIN_OK) return 0;
+    return tp.total;
+}
+
+ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const ejoin_opts* opts,
+                        int32_t* out_idx, float* out_score, void* ws, size_t ws_bytes,
+                        hipStream_t stream, ejoin_stats* stats) {
+    ejoin_opts o = opts_or_default(opts);
+    TopkPlan tp;
+    ejoin_status s = make_topk_plan(R, S, k, &o, tp);
+    if (s != EJOIN_OK) return s;
+    const Plan& p = tp.base;
+    const bool sync = !(o.flags & EJOIN_NO_SYNC);
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->ws_needed = tp.total;
+        stats->topk_slots = tp.Kc;
+        stats->tile = p.prec == P_BF16 ? 14 : 13;
+    }
+    if (p.nR == 0) return EJOIN_OK;
+    if (!out_idx || !out_score) return EJOIN_E_INVAL;
+    if (!ws || ws_bytes < tp.total) return EJOIN_E_WORKSPACE;
+
+    char* w = (char*)ws;
+    unsigned long long* hdr = (unsigned long long*)w;
+    RowInfo* info_r = (RowInfo*)(w + p.off_info_r);
+    RowInfo* info_s = (RowInfo*)(w + p.off_info_s);
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    const bool timing = sync && (o.flags & EJOIN_TIMING) && stats;
+    if (timing)
+        for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    auto rec = [&](int i) { return timing ? hipEventRecord(ev[i], stream) : hipSuccess; };
+
+    HIP_TRY(rec(0));
+    HIP_TRY(launch_zero_header(hdr, stream));
+    HIP_TRY(launch_prep(p.prec, R->data, p.nR, p.dim, R->ld, w + p.off_xr, p.Kp, p.padR, info_r,
+                        hdr, H_ENORM_R, stream));
+    if (!p.alias)
+        HIP_TRY(launch_prep(p.prec, S->data, p.nS, p.dim, S->ld, w + p.off_xs, p.Kp, p.padS,
+                            info_s, hdr, H_ENORM_S, stream));
+    else
+        HIP_TRY(hipMemcpyAsync(hdr + H_ENORM_S, hdr + H_ENORM_R, 8, hipMemcpyDeviceToDevice,
+                               stream));
+    double* nr64 = (double*)(w + tp.off_nr);
+    double* ns64 = (double*)(w + tp.off_ns);
+    HIP_TRY(launch_norms64(R->data, p.nR, p.dim, R->ld, nr64, stream));
+    if (!p.alias) HIP_TRY(launch_norms64(S->data, p.nS, p.dim, S->ld, ns64, stream));
+
+    TopkArgs ta;
+    ta.R = R->data;
+    ta.ldR = R->ld;
+    ta.S = S->data;
+    ta.ldS = S->ld;
+    ta.dim = p.dim;
+    ta.nR = p.nR;
+    ta.nS = p.nS;
+    ta.nr64 = nr64;
+    ta.ns64 = ns64;
+    ta.info_r = info_r;
+    ta.cnt = (const int*)(w + tp.off_cnt);
+    ta.cand = (const int2*)(w + tp.off_cand);
+    ta.Kc = tp.Kc;
+    ta.k = k;
+    ta.fp32_terms = band_fp32_terms(p.Kp);
+    ta.hdr = hdr;
+    ta.fb_rows = (int*)(w + tp.off_fb);
+    ta.pilot_rows = (int*)(w + tp.off_prow);
+    ta.pilot_kth = (double*)(w + tp.off_pkth);
+    ta.n_pilot = tp.n_pilot;
+    ta.all_columns = tp.all_columns;
+    ta.out_idx = out_idx;
+    ta.out_score = out_score;
+    if (p.nS > 0) HIP_TRY(launch_topk_pilot(ta, stream));
+    HIP_TRY(rec(1));
+
+    if (p.nS > 0) {
+        CandArgs ca;
+        ca.A = w + p.off_xr;
+        ca.B = w + p.off_xs;
+        ca.info_r = info_r;
+        ca.info_s = info_s;
+        ca.Kp = p.Kp;
+        ca.nR = p.nR;
+        ca.nS = p.nS;
+        ca.hdr = hdr;
+        ca.cnt = (int*)(w + tp.off_cnt);
+        ca.cand = (int2*)(w + tp.off_cand);
+        ca.Kc = tp.Kc;
+        HIP_TRY(launch_topk_candidates(p.prec, ca, stream));
+    }
+    HIP_TRY(rec(2));
+    HIP_TRY(launch_topk_finalize(ta, stream));
+    HIP_TRY(rec(3));
+    if (!sync) return EJOIN_OK;
+    unsigned long long h[H_COUNT];
+    HIP_TRY(hipMemcpyAsync(h, hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (timing) {
+        hipEventElapsedTime(&stats->ms_prep, ev[0], ev[1]);
+        hipEventElapsedTime(&stats->ms_main, ev[1], ev[2]);
+        hipEventElapsedTime(&stats->ms_rescore, ev[2], ev[3]);
+        hipEventElapsedTime(&stats->ms_total, ev[0], ev[3]);
+        for (auto& e : ev) hipEventDestroy(e);
+    }
+    if (h[H_FLAGS] & F_NONFINITE) return EJOIN_E_NONFINITE;
+    if (h[H_FLAGS] & F_RANGE) return EJOIN_E_RANGE;
+    if (stats) {
+        stats->n_fallback = (int32_t)h[H_TOPK_FB];
+        stats->topk_floor = (double)__builtin_bit_cast(float, (uint32_t)h[H_TOPK_F]);
+        stats->band = (double)__builtin_bit_cast(float, (uint32_t)h[H_TOPK_EMAX]);
+    }
+    return EJOIN_OK;
 }
 
 ejoin_status ejoin_threshold(const ejoin_rel* R, const ejoin_rel* S, double theta,

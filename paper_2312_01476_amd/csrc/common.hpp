@@ -24,6 +24,9 @@ enum : int {
     H_ENORM_R = 5,    // max quantisation error norm over R rows (float bits)
     H_ENORM_S = 6,    // same for S
     H_MISC = 7,
+    H_TOPK_F = 8,     // top-k candidate floor (float bits)
+    H_TOPK_FB = 9,    // top-k rows sent to the exact fallback
+    H_TOPK_EMAX = 10, // top-k: largest per-row error bound (float bits)
     H_COUNT = 32      // header size in int64 (256 bytes)
 };
 

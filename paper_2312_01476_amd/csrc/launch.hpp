@@ -45,6 +45,51 @@ hipError_t launch_threshold(int tile_id, const ThresholdArgs& a, hipStream_t st)
 hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs& a,
                                   hipStream_t st);
 
+// top-k candidate sweep (panel kernel with the candidate epilogue)
+struct CandArgs {
+    const void* A;
+    const void* B;
+    const RowInfo* info_r;
+    const RowInfo* info_s;
+    int Kp;
+    int64_t nR, nS;
+    unsigned long long* hdr;  // floor read from H_TOPK_F
+    int* cnt;                 // per padded R row
+    int2* cand;               // per padded R row, Kc slots
+    int Kc;
+};
+hipError_t launch_topk_candidates(int prec, const CandArgs& a, hipStream_t st);
+
+// exact top-k: pilot + floor, per-row finalize and fallback
+struct TopkArgs {
+    const float* R;
+    int64_t ldR;
+    const float* S;
+    int64_t ldS;
+    int dim;
+    int64_t nR, nS;
+    const double* nr64;       // canonical FP64 squared norms
+    const double* ns64;
+    const RowInfo* info_r;
+    const int* cnt;
+    const int2* cand;
+    int Kc;
+    int k;
+    double fp32_terms;        // FP32 part of the error bound
+    unsigned long long* hdr;
+    int* fb_rows;             // rows sent to the exact fallback
+    int* pilot_rows;
+    double* pilot_kth;
+    int n_pilot;
+    bool all_columns;         // |S| <= Kc: every column is a candidate
+    int32_t* out_idx;
+    float* out_score;
+};
+hipError_t launch_norms64(const float* X, int64_t rows, int dim, int64_t ld, double* out,
+                          hipStream_t st);
+hipError_t launch_topk_pilot(const TopkArgs& a, hipStream_t st);
+hipError_t launch_topk_finalize(const TopkArgs& a, hipStream_t st);
+
 hipError_t launch_rescore_band(const float* R, int64_t ldR, const float* S, int64_t ldS, int dim,
                                const int2* band, int64_t band_cap, double theta, Pair* out,
                                int64_t capacity, unsigned long long* hdr, hipStream_t st);

@@ -2,27 +2,30 @@
 //
 // The tensor join's cache argument (Section IV.C: a block of vectors stays in
 // cache and is reused across many products) is taken here to the register
-// file.  A workgroup owns a panel of 256 R rows (64 per wave); each wave loads
-// its rows' BF16 or FP8 MFMA operand fragments into VGPRs once and keeps them
-// while the workgroup sweeps a range of S tiles (128 columns each).  S slices
-// (128 bytes of K per row) stream through a double-buffered LDS ring shared by
-// the four waves, so per MFMA only the S operand is read from LDS and only S
-// traffic reaches L2.  With K short (a few hundred), this removes the
-// per-output-tile prologue that a classic tile kernel pays for every block of
-// D (Section V.B's mini-batch slowdown, at tile scale).
+// file.  A workgroup owns a panel of 128 * RB R rows (32 * RB per wave); each
+// wave loads its rows' BF16 or FP8 MFMA operand fragments into VGPRs once and
+// keeps them while the workgroup sweeps a range of S tiles (32 * CB columns
+// each).  S slices (128 bytes of K per row) stream through a double-buffered
+// LDS ring shared by the four waves, so per MFMA only the S operand is read
+// from LDS and only S traffic reaches L2.  With K short (a few hundred), this
+// removes the per-output-tile prologue that a classic tile kernel pays for
+// every block of D (Section V.B's mini-batch slowdown, at tile scale).
 //
-// Epilogue (single pass): each accumulator is compared with the band edges;
-// the rare hits are appended to a per-wave staging list in LDS (ballot +
-// mbcnt, no atomics) and the list is flushed to the global output with one
-// atomicAdd per flush, i.e. per few hundred pairs.
+// The accumulators of each S tile go to an epilogue policy:
+//  * ThresholdEpi -- the threshold predicate of the E-theta-join, with hits
+//    staged per wave in LDS and flushed with one atomicAdd per few hundred
+//    pairs;
+//  * CandEpi -- top-k candidates: every column with score >= a floor goes to
+//    its row's candidate slots (the workgroup sweeps all of S, so each row is
+//    owned by one wave and its counter lives in LDS).
 #include "common.hpp"
 #include "launch.hpp"
 #include "mma.hpp"
 
 namespace ej {
 
-constexpr int PN_OUTCAP = 512;  // staged certain pairs per wave
-constexpr int PN_BANDCAP = 512; // staged band pairs per wave
+constexpr int PN_OUTCAP = 512;   // staged certain pairs per wave
+constexpr int PN_BANDCAP = 512;  // staged band pairs per wave
 
 // Append the staged entries of one wave to a global list: one atomicAdd on
 // the list counter, then a coalesced copy.  Entries past `cap` are dropped
@@ -42,15 +45,212 @@ __device__ __forceinline__ void flush_stage(T* stage, int& n, T* __restrict__ ds
     n = 0;
 }
 
+// Position of the accumulators: element e of 32x32 block (rb, cb) of a lane
+// is row 8*(e/4) + 4*h + e%4 of the block and column r32 (h = lane / 32).
+struct TileCtx {
+    int lane, wave, h, r32;
+    int r0;       // first R row of the wave
+    int rows;     // R rows per wave (32 * RB)
+    int t;        // S tile index
+    int bn;       // columns per S tile
+    bool edge;    // tile touches the end of R or S
+    int64_t nR, nS;
+};
+
+// ---------------------------------------------------------------------------
+// threshold epilogue
+// ---------------------------------------------------------------------------
+struct ThresholdEpi {
+    struct Params {
+        float lo, hi;
+        Pair* out;
+        int64_t capacity;
+        int2* band;
+        int64_t band_cap;
+        unsigned long long* hdr;
+    };
+    struct Smem {
+        Pair out[4][PN_OUTCAP];
+        int2 band[4][PN_BANDCAP];
+    };
+    struct State {
+        int n_out, n_band;  // staged entries of this wave (wave-uniform)
+    };
+
+    __device__ static void init(const Params&, Smem&, State& s, const TileCtx&) {
+        s.n_out = 0;
+        s.n_band = 0;
+    }
+
+    // Phase 1 (no branches): one wave mask per group of four accumulators
+    // from a compare of their maximum.  Phase 2: only groups with a possible
+    // hit are split per register; interior tiles skip the bounds test.
+    template <int RB, int CB>
+    __device__ static __forceinline__ void tile(const Params& p, Smem& sm, State& s,
+                                                v16f (&acc)[RB][CB], const TileCtx& c) {
+        const int gi0 = c.r0 + 4 * c.h;
+        const int gj0 = c.t * c.bn + c.r32;
+        uint64_t gmask[RB][CB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const int e4 = 4 * q4;
+                    const float m4 =
+                        __builtin_fmaxf(__builtin_fmaxf(acc[rb][cb][e4], acc[rb][cb][e4 + 1]),
+                                        __builtin_fmaxf(acc[rb][cb][e4 + 2], acc[rb][cb][e4 + 3]));
+                    gmask[rb][cb][q4] = __ballot(m4 >= p.lo);
+                }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    if (!gmask[rb][cb][q4]) continue;
+                    const int e4 = 4 * q4;
+                    // room for the at most 4 x 64 hits of this group
+                    if (s.n_out > PN_OUTCAP - 256)
+                        flush_stage(sm.out[c.wave], s.n_out, p.out, p.capacity, p.hdr + H_OUT,
+                                    c.lane);
+                    if (s.n_band > PN_BANDCAP - 256)
+                        flush_stage(sm.band[c.wave], s.n_band, p.band, p.band_cap,
+                                    p.hdr + H_BAND, c.lane);
+                    const int gj = gj0 + cb * 32;
+                    const bool vj = !c.edge || gj < c.nS;
+                    uint64_t ml[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int gi = gi0 + rb * 32 + 8 * q4 + k;
+                        const bool v = vj && (!c.edge || gi < c.nR);
+                        ml[k] = __ballot(v && acc[rb][cb][e4 + k] >= p.lo);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if (!ml[k]) continue;
+                        const float a = acc[rb][cb][e4 + k];
+                        const int gi = gi0 + rb * 32 + 8 * q4 + k;
+                        const bool in_lo = (ml[k] >> c.lane) & 1ull;
+                        const bool in_hi = in_lo && a >= p.hi;
+                        const uint64_t mhi = __ballot(in_hi);
+                        const uint64_t mb = ml[k] & ~mhi;
+                        if (in_hi) {
+                            Pair pr;
+                            pr.r = gi;
+                            pr.s = gj;
+                            pr.score = a;
+                            sm.out[c.wave][s.n_out + lanes_below(mhi)] = pr;
+                        } else if (in_lo) {
+                            sm.band[c.wave][s.n_band + lanes_below(mb)] = make_int2(gi, gj);
+                        }
+                        s.n_out += __popcll(mhi);
+                        s.n_band += __popcll(mb);
+                    }
+                }
+    }
+
+    __device__ static void finish(const Params& p, Smem& sm, State& s, const TileCtx& c) {
+        if (s.n_out)
+            flush_stage(sm.out[c.wave], s.n_out, p.out, p.capacity, p.hdr + H_OUT, c.lane);
+        if (s.n_band)
+            flush_stage(sm.band[c.wave], s.n_band, p.band, p.band_cap, p.hdr + H_BAND, c.lane);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// top-k candidate epilogue: every (i, j) with approximate score >= floor goes
+// to slot cnt[i]++ of row i (slots past Kc are counted, not written)
+// ---------------------------------------------------------------------------
+struct CandEpi {
+    struct Params {
+        const unsigned long long* hdr;  // floor as float bits in H_TOPK_F
+        int* cnt;                       // per R row, number of candidates seen
+        int2* cand;                     // per R row, Kc slots of (j, score bits)
+        int Kc;
+    };
+    struct Smem {
+        int cnt[4][64];  // per wave, its (up to 64) rows
+    };
+    struct State {
+        float floor;
+    };
+
+    __device__ static void init(const Params& p, Smem& sm, State& s, const TileCtx& c) {
+        s.floor = __uint_as_float((uint32_t)p.hdr[H_TOPK_F]);
+        sm.cnt[c.wave][c.lane] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+
+    template <int RB, int CB>
+    __device__ static __forceinline__ void tile(const Params& p, Smem& sm, State& s,
+                                                v16f (&acc)[RB][CB], const TileCtx& c) {
+        const float F = s.floor;
+        uint64_t gmask[RB][CB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const int e4 = 4 * q4;
+                    const float m4 =
+                        __builtin_fmaxf(__builtin_fmaxf(acc[rb][cb][e4], acc[rb][cb][e4 + 1]),
+                                        __builtin_fmaxf(acc[rb][cb][e4 + 2], acc[rb][cb][e4 + 3]));
+                    gmask[rb][cb][q4] = __ballot(m4 >= F);
+                }
+        const uint32_t below_half = (1u << c.r32) - 1u;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    if (!gmask[rb][cb][q4]) continue;
+                    const int e4 = 4 * q4;
+                    const int gj = c.t * c.bn + cb * 32 + c.r32;
+                    const bool vj = !c.edge || gj < c.nS;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int lr = rb * 32 + 8 * q4 + 4 * c.h + k;  // row within the wave
+                        const int gi = c.r0 + lr;
+                        const float a = acc[rb][cb][e4 + k];
+                        const bool hit = vj && (!c.edge || gi < c.nR) && a >= F;
+                        const uint64_t m = __ballot(hit);
+                        if (!m) continue;
+                        // lanes of one half share a row: count within the half
+                        const uint32_t mh = c.h ? (uint32_t)(m >> 32) : (uint32_t)m;
+                        const int base = sm.cnt[c.wave][lr];
+                        if (hit) {
+                            const int pos = base + __popc(mh & below_half);
+                            if (pos < p.Kc)
+                                p.cand[(int64_t)gi * p.Kc + pos] = make_int2(gj, __float_as_int(a));
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        if (c.r32 == 0) sm.cnt[c.wave][lr] = base + __popc(mh);
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    }
+                }
+    }
+
+    __device__ static void finish(const Params& p, Smem& sm, State&, const TileCtx& c) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (c.lane < c.rows) p.cnt[c.r0 + c.lane] = sm.cnt[c.wave][c.lane];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// the panel kernel
+// ---------------------------------------------------------------------------
 // RB 32-row blocks per wave (4 waves), CB 32-column blocks per S tile, KS
-// 128-byte K slices per row.
-template <int PREC, int KS, int RB, int CB, int OCC>
-__global__ __launch_bounds__(256, OCC) void threshold_panel(
+// 128-byte K slices per row, OCC workgroups per CU.
+template <int PREC, int KS, int RB, int CB, int OCC, class EPI>
+__global__ __launch_bounds__(256, OCC) void panel_kernel(
     const char* __restrict__ A, const char* __restrict__ B, const RowInfo* __restrict__ info_r,
     const RowInfo* __restrict__ info_s, int64_t nR, int64_t nS, int n_panels, int n_items,
-    int tiles_per_chunk, int n_stiles, float lo, float hi, Pair* __restrict__ out,
-    int64_t capacity, int2* __restrict__ band, int64_t band_cap,
-    unsigned long long* __restrict__ hdr) {
+    int tiles_per_chunk, int n_stiles, const unsigned long long* __restrict__ flags,
+    typename EPI::Params ep) {
     typedef Mma<PREC> M;
     constexpr int G = M::GROUPS;
     constexpr int NF = KS * G;       // A fragments per 32-row block
@@ -60,23 +260,31 @@ __global__ __launch_bounds__(256, OCC) void threshold_panel(
     constexpr int NCH = PN_BN * 8 / 256;  // 16-byte chunks per thread per S slice
 
     __shared__ __attribute__((aligned(16))) char sB[2][PN_BN * 128];
-    __shared__ Pair sOut[4][PN_OUTCAP];
-    __shared__ int2 sBand[4][PN_BANDCAP];
+    __shared__ typename EPI::Smem esm;
 
     const int item = (int)(blockIdx.y * gridDim.x + blockIdx.x);
     if (item >= n_items) return;
-    if (hdr[H_FLAGS] != 0) return;
+    if (flags[H_FLAGS] != 0) return;
     const int chunk = item / n_panels;
     const int panel = item - chunk * n_panels;
     const int t0 = chunk * tiles_per_chunk;
     const int t1 = min(t0 + tiles_per_chunk, n_stiles);
     if (t0 >= t1) return;
 
+    TileCtx ctx;
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int h = lane >> 5, r32 = lane & 31;
-    const int r0 = panel * PN_ROWS + wave * 32 * RB;  // first R row of this wave
+    ctx.lane = tid & 63;
+    ctx.wave = tid >> 6;
+    ctx.h = ctx.lane >> 5;
+    ctx.r32 = ctx.lane & 31;
+    ctx.r0 = panel * PN_ROWS + ctx.wave * 32 * RB;
+    ctx.rows = 32 * RB;
+    ctx.bn = PN_BN;
+    ctx.nR = nR;
+    ctx.nS = nS;
+    ctx.t = t0;
+    ctx.edge = false;
+    const int h = ctx.h, r32 = ctx.r32, r0 = ctx.r0;
 
     // ---- R fragments, resident for the whole sweep ----
     typename M::Frag af[RB][NF];
@@ -126,7 +334,8 @@ __global__ __launch_bounds__(256, OCC) void threshold_panel(
         }
     };
 
-    int n_out = 0, n_band = 0;  // staged entries of this wave (wave-uniform)
+    typename EPI::State est;
+    EPI::init(ep, esm, est, ctx);
     const bool redge = (int64_t)panel * PN_ROWS + PN_ROWS > nR;
 
     gload(0);
@@ -168,72 +377,9 @@ __global__ __launch_bounds__(256, OCC) void threshold_panel(
             __syncthreads();
         }
 
-        // ---- epilogue of S tile t ----
-        // Phase 1 (no branches): one wave mask per group of four
-        // accumulators (four rows of one column per lane), from a compare of
-        // their maximum.  Phase 2: only groups with a possible hit are split
-        // per register; interior tiles skip the bounds test.
-        const bool edge = redge || (int64_t)(t + 1) * PN_BN > nS;
-        const int gi0 = r0 + 4 * h;               // + rb*32 + 8*(e/4) + e%4
-        const int gj0 = t * PN_BN + r32;          // + cb*32
-        uint64_t gmask[RB][CB][4];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    const int e4 = 4 * q4;
-                    const float m4 =
-                        __builtin_fmaxf(__builtin_fmaxf(acc[rb][cb][e4], acc[rb][cb][e4 + 1]),
-                                        __builtin_fmaxf(acc[rb][cb][e4 + 2], acc[rb][cb][e4 + 3]));
-                    gmask[rb][cb][q4] = __ballot(m4 >= lo);
-                }
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    const int e4 = 4 * q4;
-                    if (gmask[rb][cb][q4]) {
-                        // room for the at most 4 x 64 hits of this group
-                        if (n_out > PN_OUTCAP - 256)
-                            flush_stage(sOut[wave], n_out, out, capacity, hdr + H_OUT, lane);
-                        if (n_band > PN_BANDCAP - 256)
-                            flush_stage(sBand[wave], n_band, band, band_cap, hdr + H_BAND, lane);
-                        const int gj = gj0 + cb * 32;
-                        const bool vj = !edge || gj < nS;
-                        uint64_t ml[4];
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const int gi = gi0 + rb * 32 + 8 * q4 + k;
-                            const bool v = vj && (!edge || gi < nR);
-                            ml[k] = __ballot(v && acc[rb][cb][e4 + k] >= lo);
-                        }
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            if (!ml[k]) continue;
-                            const float a = acc[rb][cb][e4 + k];
-                            const int gi = gi0 + rb * 32 + 8 * q4 + k;
-                            const bool in_lo = (ml[k] >> lane) & 1ull;
-                            const bool in_hi = in_lo && a >= hi;
-                            const uint64_t mhi = __ballot(in_hi);
-                            const uint64_t mb = ml[k] & ~mhi;
-                            if (in_hi) {
-                                Pair pr;
-                                pr.r = gi;
-                                pr.s = gj;
-                                pr.score = a;
-                                sOut[wave][n_out + lanes_below(mhi)] = pr;
-                            } else if (in_lo) {
-                                sBand[wave][n_band + lanes_below(mb)] = make_int2(gi, gj);
-                            }
-                            n_out += __popcll(mhi);
-                            n_band += __popcll(mb);
-                        }
-                    }
-                }
+        ctx.t = t;
+        ctx.edge = redge || (int64_t)(t + 1) * PN_BN > nS;
+        EPI::template tile<RB, CB>(ep, esm, est, acc, ctx);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -241,80 +387,127 @@ __global__ __launch_bounds__(256, OCC) void threshold_panel(
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[rb][cb][e] = 0.0f;
     }
-    if (n_out) flush_stage(sOut[wave], n_out, out, capacity, hdr + H_OUT, lane);
-    if (n_band) flush_stage(sBand[wave], n_band, band, band_cap, hdr + H_BAND, lane);
+    EPI::finish(ep, esm, est, ctx);
 }
 
-template <int PREC, int KS, int RB, int CB, int OCC = 1>
-static hipError_t run_panel(const ThresholdArgs& a, hipStream_t st) {
+// S chunks per panel: the threshold sweep is split so that there are enough
+// workgroups to balance the 256 CUs (about 32 per CU); the top-k sweep must
+// see all of S in one workgroup (one chunk).
+template <int PREC, int KS, int RB, int CB, int OCC, class EPI>
+static hipError_t run_panel(const void* A, const void* B, const RowInfo* info_r,
+                            const RowInfo* info_s, int64_t nR, int64_t nS, bool split_s,
+                            const unsigned long long* hdr, const typename EPI::Params& ep,
+                            hipStream_t st) {
     constexpr int PN_BN = 32 * CB;
     constexpr int PN_ROWS = 128 * RB;
-    const int64_t n_panels = (a.nR + PN_ROWS - 1) / PN_ROWS;
-    const int64_t n_stiles = (a.nS + PN_BN - 1) / PN_BN;
+    const int64_t n_panels = (nR + PN_ROWS - 1) / PN_ROWS;
+    const int64_t n_stiles = (nS + PN_BN - 1) / PN_BN;
     if (n_panels == 0 || n_stiles == 0) return hipSuccess;
-    // split the S sweep so that there are enough workgroups to balance the
-    // 256 CUs (about 32 per CU), keeping whole S tiles per chunk
-    int64_t n_chunks = (8192 + n_panels - 1) / n_panels;
-    if (n_chunks > n_stiles) n_chunks = n_stiles;
+    int64_t n_chunks = 1;
+    if (split_s) {
+        n_chunks = (8192 + n_panels - 1) / n_panels;
+        if (n_chunks > n_stiles) n_chunks = n_stiles;
+    }
     const int64_t tpc = (n_stiles + n_chunks - 1) / n_chunks;
     n_chunks = (n_stiles + tpc - 1) / tpc;
     const int64_t items = n_panels * n_chunks;
     if (items > 0x7fffffffLL) return hipErrorInvalidValue;
     const int64_t gx = items < 65536 ? items : 65536;
     const int64_t gy = (items + gx - 1) / gx;
-    hipLaunchKernelGGL((threshold_panel<PREC, KS, RB, CB, OCC>), dim3((unsigned)gx, (unsigned)gy), dim3(256),
-                       0, st, (const char*)a.A, (const char*)a.B, a.info_r, a.info_s, a.nR, a.nS,
-                       (int)n_panels, (int)items, (int)tpc, (int)n_stiles, a.lo, a.hi, a.out,
-                       a.capacity, a.band, a.band_cap, a.hdr);
+    hipLaunchKernelGGL((panel_kernel<PREC, KS, RB, CB, OCC, EPI>), dim3((unsigned)gx, (unsigned)gy),
+                       dim3(256), 0, st, (const char*)A, (const char*)B, info_r, info_s, nR, nS,
+                       (int)n_panels, (int)items, (int)tpc, (int)n_stiles, hdr, ep);
     return hipGetLastError();
 }
 
-// Kp * element size must be KS * 128 bytes with KS in 1..6.  Two 32-row
-// blocks per wave while the resident fragments fit the register file (up to
-// 512 bytes of K per row), one beyond.
-template <int PREC>
-static hipError_t dispatch_panel(int ks, bool two_waves, const ThresholdArgs& a, hipStream_t st) {
+// Kp * element size must be KS * 128 bytes with KS in 1..6.
+//  * two_waves: one 32-row block per wave, 128-column S tiles, two
+//    workgroups per CU (the epilogue of one overlaps the MFMAs of the other);
+//  * otherwise one workgroup per CU, two row blocks per wave while the
+//    resident fragments fit the register file.
+template <int PREC, class EPI>
+static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const void* B,
+                                 const RowInfo* ir, const RowInfo* is, int64_t nR, int64_t nS,
+                                 bool split_s, const unsigned long long* hdr,
+                                 const typename EPI::Params& ep, hipStream_t st) {
+#define EJ_RUN(KS_, RB_, CB_, OCC_) \
+    return run_panel<PREC, KS_, RB_, CB_, OCC_, EPI>(A, B, ir, is, nR, nS, split_s, hdr, ep, st)
     if (two_waves) {
-        // one 32-row block per wave, 128-column S tiles, two workgroups per CU
         switch (ks) {
-            case 1: return run_panel<PREC, 1, 1, 4, 2>(a, st);
-            case 2: return run_panel<PREC, 2, 1, 4, 2>(a, st);
-            case 3: return run_panel<PREC, 3, 1, 4, 2>(a, st);
-            case 4: return run_panel<PREC, 4, 1, 4, 2>(a, st);
-            case 5: return run_panel<PREC, 5, 1, 4, 2>(a, st);
-            case 6: return run_panel<PREC, 6, 1, 4, 2>(a, st);
+            case 1: EJ_RUN(1, 1, 4, 2);
+            case 2: EJ_RUN(2, 1, 4, 2);
+            case 3: EJ_RUN(3, 1, 4, 2);
+            case 4: EJ_RUN(4, 1, 4, 2);
+            case 5: EJ_RUN(5, 1, 4, 2);
+            case 6: EJ_RUN(6, 1, 4, 2);
         }
         return hipErrorInvalidValue;
     }
     if constexpr (PREC == P_BF16) {
         switch (ks) {
-            case 1: return run_panel<PREC, 1, 2, 4>(a, st);
-            case 2: return run_panel<PREC, 2, 2, 4>(a, st);
-            case 3: return run_panel<PREC, 3, 2, 4>(a, st);
-            case 4: return run_panel<PREC, 4, 2, 4>(a, st);
-            case 5: return run_panel<PREC, 5, 1, 8>(a, st);
-            case 6: return run_panel<PREC, 6, 1, 8>(a, st);
+            case 1: EJ_RUN(1, 2, 4, 1);
+            case 2: EJ_RUN(2, 2, 4, 1);
+            case 3: EJ_RUN(3, 2, 4, 1);
+            case 4: EJ_RUN(4, 2, 4, 1);
+            case 5: EJ_RUN(5, 1, 8, 1);
+            case 6: EJ_RUN(6, 1, 8, 1);
         }
     } else {
-        // FP8 fragments are twice as wide per MFMA: one row block beyond 256 B
+        // FP8 fragments are twice as wide per MFMA
         switch (ks) {
-            case 1: return run_panel<PREC, 1, 2, 4>(a, st);
-            case 2: return run_panel<PREC, 2, 2, 4>(a, st);
-            case 3: return run_panel<PREC, 3, 1, 4>(a, st);
-            case 4: return run_panel<PREC, 4, 1, 4>(a, st);
-            case 5: return run_panel<PREC, 5, 1, 2>(a, st);
-            case 6: return run_panel<PREC, 6, 1, 2>(a, st);
+            case 1: EJ_RUN(1, 2, 4, 1);
+            case 2: EJ_RUN(2, 2, 4, 1);
+            case 3: EJ_RUN(3, 1, 4, 1);
+            case 4: EJ_RUN(4, 1, 4, 1);
+            case 5: EJ_RUN(5, 1, 2, 1);
+            case 6: EJ_RUN(6, 1, 2, 1);
         }
     }
+#undef EJ_RUN
     return hipErrorInvalidValue;
 }
+
+static int slices(int prec, int Kp) { return Kp * (prec == P_BF16 ? 2 : 1) / 128; }
 
 hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs& a,
                                   hipStream_t st) {
     const int kpb = a.Kp * (prec == P_BF16 ? 2 : 1);
     if (kpb % 128 != 0) return hipErrorInvalidValue;
-    if (prec == P_BF16) return dispatch_panel<P_BF16>(kpb / 128, two_waves, a, st);
-    if (prec == P_FP8) return dispatch_panel<P_FP8>(kpb / 128, two_waves, a, st);
+    ThresholdEpi::Params ep;
+    ep.lo = a.lo;
+    ep.hi = a.hi;
+    ep.out = a.out;
+    ep.capacity = a.capacity;
+    ep.band = a.band;
+    ep.band_cap = a.band_cap;
+    ep.hdr = a.hdr;
+    const int ks = slices(prec, a.Kp);
+    if (prec == P_BF16)
+        return dispatch_panel<P_BF16, ThresholdEpi>(ks, two_waves, a.A, a.B, a.info_r, a.info_s,
+                                                    a.nR, a.nS, true, a.hdr, ep, st);
+    if (prec == P_FP8)
+        return dispatch_panel<P_FP8, ThresholdEpi>(ks, two_waves, a.A, a.B, a.info_r, a.info_s,
+                                                   a.nR, a.nS, true, a.hdr, ep, st);
+    return hipErrorInvalidValue;
+}
+
+// Top-k candidate sweep.  Every workgroup sweeps all of S for its rows.  The
+// counter table holds 64 rows per wave, which covers both layouts.
+hipError_t launch_topk_candidates(int prec, const CandArgs& a, hipStream_t st) {
+    const int kpb = a.Kp * (prec == P_BF16 ? 2 : 1);
+    if (kpb % 128 != 0 || kpb > 768) return hipErrorInvalidValue;
+    CandEpi::Params ep;
+    ep.hdr = a.hdr;
+    ep.cnt = a.cnt;
+    ep.cand = a.cand;
+    ep.Kc = a.Kc;
+    const int ks = slices(prec, a.Kp);
+    if (prec == P_BF16)
+        return dispatch_panel<P_BF16, CandEpi>(ks, true, a.A, a.B, a.info_r, a.info_s, a.nR,
+                                               a.nS, false, a.hdr, ep, st);
+    if (prec == P_FP8)
+        return dispatch_panel<P_FP8, CandEpi>(ks, false, a.A, a.B, a.info_r, a.info_s, a.nR,
+                                              a.nS, false, a.hdr, ep, st);
     return hipErrorInvalidValue;
 }
 

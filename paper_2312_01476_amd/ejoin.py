@@ -35,7 +35,8 @@ class Stats(C.Structure):
                 ("n_band_accepted", C.c_int64), ("band_needed", C.c_int64),
                 ("ws_needed", C.c_size_t), ("band", C.c_double), ("tile", C.c_int32),
                 ("n_fallback", C.c_int32), ("ms_prep", C.c_float), ("ms_main", C.c_float),
-                ("ms_rescore", C.c_float), ("ms_total", C.c_float)]
+                ("ms_rescore", C.c_float), ("ms_total", C.c_float),
+                ("topk_floor", C.c_double), ("topk_slots", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -76,6 +77,11 @@ def lib():
         L.ejoin_threshold.argtypes = [P(Rel), P(Rel), C.c_double, P(Opts), C.c_void_p,
                                       C.c_int64, P(C.c_int64), C.c_void_p, C.c_size_t,
                                       C.c_void_p, P(Stats)]
+        L.ejoin_topk_workspace.restype = C.c_size_t
+        L.ejoin_topk_workspace.argtypes = [P(Rel), P(Rel), C.c_int32, P(Opts)]
+        L.ejoin_topk.restype = C.c_int
+        L.ejoin_topk.argtypes = [P(Rel), P(Rel), C.c_int32, P(Opts), C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_size_t, C.c_void_p, P(Stats)]
         _lib = L
     return _lib
 
@@ -198,3 +204,44 @@ def threshold(R, S, theta: float, *, d=None, prec="fp32", band=None, tile=0, cap
             continue
         raise EjoinError(rc, "ejoin_threshold")
     raise EjoinError(rc, "ejoin_threshold (retries exhausted)")
+
+
+def topk_workspace(R, S, k, *, d=None, prec="bf16", topk_cand=0):
+    r, s = _rel(R, d), _rel(S, d)
+    o = _opts(prec, None, 0, 0, 0, topk_cand)
+    n = lib().ejoin_topk_workspace(C.byref(r), C.byref(s), int(k), C.byref(o))
+    if n == 0:
+        raise EjoinError(E_INVAL if prec != "fp32" else E_UNSUPPORTED, "ejoin_topk_workspace")
+    return int(n)
+
+
+def topk_raw(R, S, k, out_idx, out_score, ws, *, d=None, prec="bf16", topk_cand=0, flags=0,
+             stream=None):
+    """One ejoin_topk call on caller buffers.  Returns (status, stats dict)."""
+    r, s = _rel(R, d), _rel(S, d)
+    o = _opts(prec, None, 0, 0, flags, topk_cand)
+    st = Stats()
+    rc = lib().ejoin_topk(C.byref(r), C.byref(s), int(k), C.byref(o),
+                          C.c_void_p(out_idx.data_ptr() if out_idx.numel() else 0),
+                          C.c_void_p(out_score.data_ptr() if out_score.numel() else 0),
+                          C.c_void_p(ws.data_ptr()), int(ws.numel()), _stream(stream),
+                          C.byref(st))
+    return rc, st.as_dict()
+
+
+def topk(R, S, k: int, *, d=None, prec="bf16", topk_cand=0, timing=False, stream=None):
+    """Top-k E-join on the GPU: per R row the k most similar S rows, ordered by
+    (sim64 desc, index asc).  Returns (idx int32 (|R|, k), score float32
+    (|R|, k), stats); empty slots hold (-1, -inf)."""
+    import torch
+    dev = R.device
+    nR = R.shape[0]
+    ws = torch.empty(topk_workspace(R, S, k, d=d, prec=prec, topk_cand=topk_cand),
+                     dtype=torch.uint8, device=dev)
+    idx = torch.empty((nR, k), dtype=torch.int32, device=dev)
+    sc = torch.empty((nR, k), dtype=torch.float32, device=dev)
+    rc, st = topk_raw(R, S, k, idx, sc, ws, d=d, prec=prec, topk_cand=topk_cand,
+                      flags=TIMING if timing else 0, stream=stream)
+    if rc != OK:
+        raise EjoinError(rc, "ejoin_topk")
+    return idx, sc, st

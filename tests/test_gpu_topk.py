@@ -1,0 +1,106 @@
+"""Parity of the GPU top-k join (through the C ABI) with the FP64 oracle.
+
+Indices must equal the oracle's exactly (including the order of ties, which
+the canonical rule breaks by the smaller S index) and every score must equal
+the oracle's sim64 rounded to float32.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2312_01476_amd import datagen as G
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+E = None
+
+
+def setup_module(module):
+    global E
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_01476_amd import ejoin
+    E = ejoin
+
+
+def _dev(X):
+    return torch.from_numpy(np.ascontiguousarray(X)).to("cuda")
+
+
+def _check(R, S, k, prec, d=None, **kw):
+    idx, sc, st = E.topk(_dev(R), _dev(S), k, d=d, prec=prec, **kw)
+    oi, osc = O.topk(R, S, k, d=d)
+    gi = idx.cpu().numpy().astype(np.int64)
+    gs = sc.cpu().numpy()
+    bad = np.nonzero(np.any(gi != oi, axis=1))[0]
+    assert bad.size == 0, (prec, k, bad[:5], gi[bad[:2]], oi[bad[:2]], st)
+    np.testing.assert_array_equal(gs, osc.astype(np.float32))
+    return st
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("k", [1, 3, 10, 37])
+def test_clustered(prec, k):
+    cent = G.centres(128, 30, seed=1)
+    R, _ = G.clustered_points(cent, 700, 0.3, seed=2)
+    S, _ = G.clustered_points(cent, 3000, 0.3, seed=3)
+    st = _check(R, S, k, prec)
+    assert st["n_fallback"] < R.shape[0] // 10
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_ties_and_duplicates(prec):
+    cent = G.centres(64, 10, seed=4)
+    R, _ = G.clustered_points(cent, 300, 0.3, seed=5)
+    S, _ = G.clustered_points(cent, 1500, 0.3, seed=6)
+    S[100:110] = S[5]                         # exact ties: order by index
+    S[200] = S[5] * np.float32(4.0)           # scaled copy: same similarity
+    R[7] = S[5]
+    R[8] = 0.0                                # zero row: all similarities 0
+    _check(R, S, 16, prec)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_k_larger_than_s_and_small_s(prec):
+    R = G.gaussian_raw(50, 40, seed=7)
+    S = G.gaussian_raw(9, 40, seed=8)
+    _check(R, S, 12, prec)    # k > |S|: padding
+    _check(R, S, 9, prec)
+    S2 = G.gaussian_raw(200, 40, seed=9)
+    _check(R, S2, 5, prec)    # |S| <= slots: every column a candidate
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_forced_fallback_is_exact(prec):
+    """Few slots per row: most rows overflow and take the exact scan."""
+    cent = G.centres(96, 5, seed=10)
+    R, _ = G.clustered_points(cent, 400, 0.3, seed=11)
+    S, _ = G.clustered_points(cent, 2500, 0.3, seed=12)
+    st = _check(R, S, 8, prec, topk_cand=8)
+    assert st["n_fallback"] > 0
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_unstructured_data(prec):
+    R = G.uniform_sphere(333, 200, seed=13)
+    S = G.uniform_sphere(4100, 200, seed=14)
+    _check(R, S, 10, prec)
+
+
+@pytest.mark.parametrize("prec,d", [("bf16", 384), ("fp8", 768), ("fp8", 300), ("bf16", 33)])
+def test_depths_and_ragged(prec, d):
+    cent = G.centres(d, 50, seed=d)
+    R, _ = G.clustered_points(cent, 517, 0.3, seed=d + 1)
+    S, _ = G.clustered_points(cent, 2711, 0.3, seed=d + 2)
+    _check(R, S, 10, prec)
+
+
+def test_unsupported_and_invalid():
+    R = _dev(G.gaussian_raw(10, 8, seed=1))
+    with pytest.raises(E.EjoinError):
+        E.topk(R, R, 4, prec="fp32")
+    with pytest.raises(E.EjoinError):
+        E.topk(R, R, 0, prec="bf16")
+    with pytest.raises(E.EjoinError):
+        E.topk(R, R, 300, prec="bf16")
