@@ -135,7 +135,9 @@ struct TopkPlan {
     int Kc = 0, n_pilot = 0;
     bool all_columns = false;
     size_t off_nr = 0, off_ns = 0, off_cnt = 0, off_cand = 0, off_fb = 0, off_prow = 0,
-           off_pkth = 0, total = 0;
+           off_pkth = 0, off_keys = 0, off_counts = 0, off_order = 0, off_partv = 0,
+           off_partj = 0, total = 0;
+    int part_rows = 256;
 };
 
 ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const ejoin_opts* o,
@@ -173,6 +175,17 @@ ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, c
     off = align256(off + 256 * sizeof(int));
     tp.off_pkth = off;
     off = align256(off + 256 * sizeof(double));
+    tp.off_keys = off;
+    off = align256(off + (size_t)p.padR * sizeof(int));
+    tp.off_counts = off;
+    off = align256(off + (size_t)(p.nS + 1) * sizeof(int));
+    tp.off_order = off;
+    off = align256(off + (size_t)p.padR * sizeof(int));
+    // partial lists of the exact scans: 256 rows x up to 64 S ranges x k
+    tp.off_partv = off;
+    off = align256(off + (size_t)tp.part_rows * 64 * k * sizeof(double));
+    tp.off_partj = off;
+    off = align256(off + (size_t)tp.part_rows * 64 * k * sizeof(int));
     tp.total = off;
     return EJOIN_OK;
 }
@@ -312,6 +325,12 @@ ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const
     ta.pilot_rows = (int*)(w + tp.off_prow);
     ta.pilot_kth = (double*)(w + tp.off_pkth);
     ta.n_pilot = tp.n_pilot;
+    ta.keys = (int*)(w + tp.off_keys);
+    ta.counts = (int*)(w + tp.off_counts);
+    ta.order = (int*)(w + tp.off_order);
+    ta.part_v = (double*)(w + tp.off_partv);
+    ta.part_j = (int*)(w + tp.off_partj);
+    ta.part_rows = tp.part_rows;
     ta.all_columns = tp.all_columns;
     ta.out_idx = out_idx;
     ta.out_score = out_score;
@@ -335,10 +354,15 @@ ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const
     }
     HIP_TRY(rec(2));
     HIP_TRY(launch_topk_finalize(ta, stream));
-    HIP_TRY(rec(3));
-    if (!sync) return EJOIN_OK;
+    if (!sync) {
+        HIP_TRY(launch_topk_fallback(ta, -1, stream));
+        return EJOIN_OK;
+    }
     unsigned long long h[H_COUNT];
     HIP_TRY(hipMemcpyAsync(h, hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (h[H_FLAGS] == 0) HIP_TRY(launch_topk_fallback(ta, (int64_t)h[H_TOPK_FB], stream));
+    HIP_TRY(rec(3));
     HIP_TRY(hipStreamSynchronize(stream));
     if (timing) {
         hipEventElapsedTime(&stats->ms_prep, ev[0], ev[1]);

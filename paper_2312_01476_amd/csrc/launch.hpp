@@ -80,6 +80,12 @@ struct TopkArgs {
     int* fb_rows;             // rows sent to the exact fallback
     int* pilot_rows;
     double* pilot_kth;
+    int* keys;                // finalize order: best candidate per row
+    int* counts;              // nS + 1 bucket counts / offsets
+    int* order;               // rows grouped by best candidate
+    double* part_v;           // per-range partial lists of the exact scans
+    int* part_j;
+    int part_rows;            // list entries one exact-scan batch holds
     int n_pilot;
     bool all_columns;         // |S| <= Kc: every column is a candidate
     int32_t* out_idx;
@@ -89,6 +95,7 @@ hipError_t launch_norms64(const float* X, int64_t rows, int dim, int64_t ld, dou
                           hipStream_t st);
 hipError_t launch_topk_pilot(const TopkArgs& a, hipStream_t st);
 hipError_t launch_topk_finalize(const TopkArgs& a, hipStream_t st);
+hipError_t launch_topk_fallback(const TopkArgs& a, int64_t n_fb, hipStream_t st);
 
 hipError_t launch_rescore_band(const float* R, int64_t ldR, const float* S, int64_t ldS, int dim,
                                const int2* band, int64_t band_cap, double theta, Pair* out,

@@ -17,6 +17,11 @@
 //     overflowed and A_k - 2 D_i >= F, every such column is a candidate: they
 //     are rescored in FP64 and sorted, which gives the exact answer;
 //  4. rows that fail the certificate take an exact FP64 scan of all S.
+//
+// All FP64 dot products keep the canonical sequential order.  Each thread
+// owns one (row, column) dot; the column rows are staged through LDS in
+// 32-float chunks loaded with coalesced reads, and every thread sums its own
+// row chunk by chunk, so the order of the sum stays k = 0, 1, ..., d-1.
 #include <math.h>
 
 #include "common.hpp"
@@ -24,14 +29,6 @@
 
 namespace ej {
 
-// canonical FP64 pieces: sums in order k = 0..d-1, one rounding per product
-// and per sum (this file is compiled without FP contraction)
-__device__ __forceinline__ double dot64_seq(const float* __restrict__ a,
-                                            const float* __restrict__ b, int d) {
-    double acc = 0.0;
-    for (int k = 0; k < d; ++k) acc = acc + (double)a[k] * (double)b[k];
-    return acc;
-}
 __device__ __forceinline__ double sim64_from(double dot, double nr, double ns) {
     if (nr == 0.0 || ns == 0.0) return 0.0;
     return dot / __builtin_sqrt(nr * ns);
@@ -47,22 +44,47 @@ __device__ __forceinline__ bool better(double va, int ja, double vb, int jb) {
     return va > vb || (va == vb && ja < jb);
 }
 
-// Squared FP64 norms of all rows (one lane per row).
-__global__ __launch_bounds__(256) void norms64(const float* __restrict__ X, int64_t rows, int dim,
-                                               int64_t ld, double* __restrict__ out) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
-         i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = dot64_seq(X + i * ld, X + i * ld, dim);
+// ---------------------------------------------------------------------------
+// block-wide canonical FP64 dots (256 threads)
+// ---------------------------------------------------------------------------
+constexpr int SD_CH = 32;
+struct StageSmem {
+    float tile[256][SD_CH + 1];  // +1: conflict-free column reads
+    float rch[SD_CH];
+    int64_t row_of[256];
+};
+
+// Thread t returns the sequential FP64 dot of X[row_of[t]] with r (with
+// itself when r is null).  row_of[t] < 0: no row (returns 0).  Must be
+// called by all 256 threads.
+__device__ double block_dots(const float* __restrict__ X, int64_t ldX,
+                             const float* __restrict__ r, int dim, StageSmem& sm) {
+    const int tid = threadIdx.x;
+    const int64_t mine = sm.row_of[tid];
+    double acc = 0.0;
+    for (int k0 = 0; k0 < dim; k0 += SD_CH) {
+        const int kn = min(SD_CH, dim - k0);
+        for (int q = tid; q < 256 * SD_CH; q += 256) {
+            const int ri = q / SD_CH, kk = q - ri * SD_CH;
+            const int64_t row = sm.row_of[ri];
+            sm.tile[ri][kk] = (row >= 0 && kk < kn) ? X[row * ldX + k0 + kk] : 0.0f;
+        }
+        if (r && tid < kn) sm.rch[tid] = r[k0 + tid];
+        __syncthreads();
+        if (mine >= 0) {
+            for (int kk = 0; kk < kn; ++kk) {
+                const double a = (double)sm.tile[tid][kk];
+                const double b = r ? (double)sm.rch[kk] : a;
+                acc = acc + a * b;
+            }
+        }
+        __syncthreads();
+    }
+    return acc;
 }
 
-// Exact FP64 top-k of the rows in `rows_list` (one workgroup per row).  A
-// block-wide buffer of 512 (score, index) entries collects every column that
-// beats the current k-th best; when it fills it is sorted (bitonic) and cut to
-// k.  k <= 256.
-constexpr int XK_BUF = 512;
-
+// bitonic sort of n_pow2 (v desc, j asc) entries in LDS by 256 threads
 __device__ void bitonic_sort_desc(double* v, int* j, int n_pow2) {
-    // sorts (v desc, j asc) over n_pow2 entries with 256 threads
     for (int size = 2; size <= n_pow2; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             for (int t = threadIdx.x; t < n_pow2 / 2; t += blockDim.x) {
@@ -84,12 +106,38 @@ __device__ void bitonic_sort_desc(double* v, int* j, int n_pow2) {
     }
 }
 
+// Squared FP64 norms of all rows, 256 rows per workgroup.
+__global__ __launch_bounds__(256) void norms64(const float* __restrict__ X, int64_t rows, int dim,
+                                               int64_t ld, double* __restrict__ out) {
+    __shared__ StageSmem sm;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < rows; base += (int64_t)gridDim.x * 256) {
+        const int64_t i = base + threadIdx.x;
+        sm.row_of[threadIdx.x] = i < rows ? i : -1;
+        __syncthreads();
+        const double n = block_dots(X, ld, nullptr, dim, sm);
+        if (i < rows) out[i] = n;
+        __syncthreads();
+    }
+}
+
+// Exact FP64 top-k of the rows in `rows_list` (one workgroup per row).  A
+// 512-entry buffer collects every column that beats the current k-th best;
+// when it fills it is sorted and cut to k.  k <= 256.
+constexpr int XK_BUF = 512;
+
+//
+// The S columns may be split into n_rg ranges (blockIdx.y): each workgroup
+// then writes its range's top-k of list entry rr to part_v/part_j at
+// [(rr - row_base) * n_rg + range] * k, and exact_topk_merge combines them.
+// With n_rg == 1 the list's rows are written to the outputs directly.
 __global__ __launch_bounds__(256) void exact_topk_rows(
     const float* __restrict__ R, int64_t ldR, const float* __restrict__ S, int64_t ldS, int dim,
     int64_t nS, const double* __restrict__ nr64, const double* __restrict__ ns64, int k,
     const int* __restrict__ rows_list, const unsigned long long* __restrict__ n_rows_ptr,
-    int n_rows_fixed, int32_t* __restrict__ out_idx, float* __restrict__ out_score,
-    double* __restrict__ kth_out) {
+    int n_rows_fixed, int row_base, int row_limit, int32_t* __restrict__ out_idx,
+    float* __restrict__ out_score, double* __restrict__ kth_out, double* __restrict__ part_v,
+    int* __restrict__ part_j) {
+    __shared__ StageSmem sm;
     __shared__ double bv[XK_BUF];
     __shared__ int bj[XK_BUF];
     __shared__ int s_n;
@@ -97,9 +145,13 @@ __global__ __launch_bounds__(256) void exact_topk_rows(
     __shared__ int s_thr_j;
     __shared__ int s_wcnt[4];
 
-    const int n_rows = n_rows_ptr ? (int)*n_rows_ptr : n_rows_fixed;
+    const int n_rows_all = n_rows_ptr ? (int)*n_rows_ptr : n_rows_fixed;
+    const int n_rows = min(n_rows_all, row_limit);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int rr = blockIdx.x; rr < n_rows; rr += gridDim.x) {
+    const int n_rg = gridDim.y, rg = blockIdx.y;
+    const int64_t per = (nS + n_rg - 1) / n_rg;
+    const int64_t s_lo = rg * per, s_hi = min(nS, s_lo + per);
+    for (int rr = row_base + blockIdx.x; rr < n_rows; rr += gridDim.x) {
         const int64_t i = rows_list[rr];
         const float* r = R + i * ldR;
         const double nr = nr64[i];
@@ -109,12 +161,15 @@ __global__ __launch_bounds__(256) void exact_topk_rows(
             s_thr_j = 0x7fffffff;
         }
         __syncthreads();
-        for (int64_t j0 = 0; j0 < nS; j0 += 256) {
+        for (int64_t j0 = s_lo; j0 < s_hi; j0 += 256) {
             const int64_t jj = j0 + threadIdx.x;
+            sm.row_of[threadIdx.x] = jj < s_hi ? jj : -1;
+            __syncthreads();
+            const double dot = block_dots(S, ldS, r, dim, sm);
             double v = -INFINITY;
             bool cand = false;
-            if (jj < nS) {
-                v = sim64_from(dot64_seq(r, S + jj * ldS, dim), nr, ns64[jj]);
+            if (jj < s_hi) {
+                v = sim64_from(dot, nr, ns64[jj]);
                 cand = better(v, (int)jj, s_thr_v, s_thr_j);
             }
             // block compaction into the buffer
@@ -157,6 +212,58 @@ __global__ __launch_bounds__(256) void exact_topk_rows(
         __syncthreads();
         bitonic_sort_desc(bv, bj, XK_BUF);
         const int have = min(s_n, k);
+        if (part_v) {
+            const int64_t o = ((int64_t)(rr - row_base) * n_rg + rg) * k;
+            for (int t = threadIdx.x; t < k; t += blockDim.x) {
+                part_v[o + t] = t < have ? bv[t] : -INFINITY;
+                part_j[o + t] = t < have ? bj[t] : 0x7fffffff;
+            }
+        } else {
+            for (int t = threadIdx.x; t < k; t += blockDim.x) {
+                if (out_idx) {
+                    out_idx[i * k + t] = t < have ? bj[t] : -1;
+                    out_score[i * k + t] = t < have ? (float)bv[t] : -INFINITY;
+                }
+            }
+            if (kth_out && threadIdx.x == 0) kth_out[rr] = have == k ? bv[k - 1] : -INFINITY;
+        }
+        __syncthreads();
+    }
+}
+
+// Combine the per-range lists of exact_topk_rows (one workgroup per list
+// entry): the exact top-k of the row is the top-k of the union.
+__global__ __launch_bounds__(256) void exact_topk_merge(
+    const int* __restrict__ rows_list, const unsigned long long* __restrict__ n_rows_ptr,
+    int n_rows_fixed, int row_base, int row_limit, int n_rg, int k, int64_t nS,
+    const double* __restrict__ part_v, const int* __restrict__ part_j,
+    int32_t* __restrict__ out_idx, float* __restrict__ out_score, double* __restrict__ kth_out) {
+    __shared__ double bv[XK_BUF];
+    __shared__ int bj[XK_BUF];
+    const int n_rows_all = n_rows_ptr ? (int)*n_rows_ptr : n_rows_fixed;
+    const int n_rows = min(n_rows_all, row_limit);
+    for (int rr = row_base + blockIdx.x; rr < n_rows; rr += gridDim.x) {
+        const int64_t i = rows_list[rr];
+        const int64_t o = (int64_t)(rr - row_base) * n_rg * k;
+        int n = 0;  // entries held (block-uniform)
+        for (int g = 0; g < n_rg; ++g) {
+            for (int t = threadIdx.x; t < k; t += blockDim.x) {
+                bv[n + t] = part_v[o + (int64_t)g * k + t];
+                bj[n + t] = part_j[o + (int64_t)g * k + t];
+            }
+            n += k;
+            __syncthreads();
+            if (n > XK_BUF - k || g == n_rg - 1) {
+                for (int t = n + threadIdx.x; t < XK_BUF; t += blockDim.x) {
+                    bv[t] = -INFINITY;
+                    bj[t] = 0x7fffffff;
+                }
+                __syncthreads();
+                bitonic_sort_desc(bv, bj, XK_BUF);
+                n = k;
+            }
+        }
+        const int have = (int)min((int64_t)k, nS);
         for (int t = threadIdx.x; t < k; t += blockDim.x) {
             if (out_idx) {
                 out_idx[i * k + t] = t < have ? bj[t] : -1;
@@ -187,54 +294,91 @@ __global__ void topk_floor(unsigned long long* hdr, const double* __restrict__ k
     hdr[H_TOPK_EMAX] = (unsigned long long)__float_as_uint((float)dmax);
 }
 
-// Per-row finalize (one wave per row, Kc <= 256 candidate slots).
-constexpr int FZ_SLOTS = 256;
+// ---------------------------------------------------------------------------
+// finalize order: rows grouped by their best candidate, so that rows with the
+// same neighbourhood rescore the same S rows one after the other (L2 reuse)
+// ---------------------------------------------------------------------------
+__global__ void fill_int(int* p, int64_t n, int v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
 
-// wave-level bitonic sort of 256 (key desc, j asc) entries in LDS
-__device__ void wave_sort256(double* v, int* j) {
-    const int lane = threadIdx.x & 63;
-    for (int size = 2; size <= FZ_SLOTS; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = lane; t < FZ_SLOTS / 2; t += 64) {
-                const int lo = 2 * t - (t & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = ((lo & size) == 0);
-                const bool hi_better = better(v[hi], j[hi], v[lo], j[lo]);
-                if (hi_better == up) {
-                    const double tv = v[lo];
-                    v[lo] = v[hi];
-                    v[hi] = tv;
-                    const int tj = j[lo];
-                    j[lo] = j[hi];
-                    j[hi] = tj;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+// key[i] = smallest candidate index of row i (nS if none); counts[key]++.
+// Rows whose candidate sets coincide (one neighbourhood) get the same key.
+__global__ __launch_bounds__(256) void topk_keys(const int* __restrict__ cnt,
+                                                 const int2* __restrict__ cand, int Kc,
+                                                 int64_t nR, int64_t nS, int* __restrict__ key,
+                                                 int* __restrict__ counts) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < nR; i += (int64_t)gridDim.x * 4) {
+        const int n = min(cnt[i], Kc);
+        int bj = (int)nS;
+        for (int t = lane; t < n; t += 64) bj = min(bj, cand[i * (int64_t)Kc + t].x);
+        for (int o = 32; o > 0; o >>= 1) bj = min(bj, __shfl_xor(bj, o, 64));
+        if (lane == 0) {
+            key[i] = bj;
+            atomicAdd(counts + bj, 1);
         }
     }
 }
 
+// exclusive scan of counts[0..n) in place (one workgroup)
+__global__ __launch_bounds__(256) void scan_counts(int* counts, int64_t n) {
+    __shared__ int part[256];
+    const int64_t per = (n + 255) / 256;
+    const int64_t b = threadIdx.x * per, e = min(n, b + per);
+    int s = 0;
+    for (int64_t q = b; q < e; ++q) s += counts[q];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int t = 0; t < 256; ++t) {
+            const int v = part[t];
+            part[t] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    int acc = part[threadIdx.x];
+    for (int64_t q = b; q < e; ++q) {
+        const int v = counts[q];
+        counts[q] = acc;
+        acc += v;
+    }
+}
+
+__global__ void scatter_order(const int* __restrict__ key, int64_t nR, int* __restrict__ offs,
+                              int* __restrict__ order) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nR;
+         i += (int64_t)gridDim.x * blockDim.x)
+        order[atomicAdd(offs + key[i], 1)] = (int)i;
+}
+
+// ---------------------------------------------------------------------------
+// per-row finalize: one workgroup per row, Kc <= 256 candidate slots
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void topk_finalize(
     const float* __restrict__ R, int64_t ldR, const float* __restrict__ S, int64_t ldS, int dim,
     int64_t nR, int64_t nS, const double* __restrict__ nr64, const double* __restrict__ ns64,
     const RowInfo* __restrict__ info_r, const int* __restrict__ cnt,
     const int2* __restrict__ cand, int Kc, int k, double fp32_terms,
-    unsigned long long* __restrict__ hdr, int* __restrict__ fb_rows,
-    int32_t* __restrict__ out_idx, float* __restrict__ out_score) {
-    __shared__ double sv[4][FZ_SLOTS];
-    __shared__ int sj[4][FZ_SLOTS];
+    const int* __restrict__ order, unsigned long long* __restrict__ hdr,
+    int* __restrict__ fb_rows, int32_t* __restrict__ out_idx, float* __restrict__ out_score) {
+    __shared__ StageSmem sm;
+    __shared__ double v[256];
+    __shared__ int jv[256];
     if (hdr[H_FLAGS] != 0) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double* v = sv[wave];
-    int* jv = sj[wave];
+    const int tid = threadIdx.x;
     const float F = __uint_as_float((uint32_t)hdr[H_TOPK_F]);
     const double es = (double)__uint_as_float((uint32_t)hdr[H_ENORM_S]) * 1.001 + 1e-7;
     const int kk = (int)min((int64_t)k, nS);
 
-    for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < nR; i += (int64_t)gridDim.x * 4) {
+    for (int64_t rr = blockIdx.x; rr < nR; rr += gridDim.x) {
+        const int64_t i = order ? order[rr] : rr;
         if (nS == 0) {  // nothing to join: every slot is padding
-            for (int t = lane; t < k; t += 64) {
+            for (int t = tid; t < k; t += 256) {
                 out_idx[i * k + t] = -1;
                 out_score[i * k + t] = -INFINITY;
             }
@@ -244,19 +388,15 @@ __global__ __launch_bounds__(256) void topk_finalize(
         const int n = min(c, Kc);
         const double er = (double)info_r[i].enorm * 1.001 + 1e-7;
         const double di = er * (1.0 + es) + es + fp32_terms * (1.0 + er) * (1.0 + es);
-        // load the candidates (approximate score, index)
-        for (int t = lane; t < FZ_SLOTS; t += 64) {
-            if (t < n) {
-                const int2 e = cand[i * (int64_t)Kc + t];
-                v[t] = (double)__int_as_float(e.y);
-                jv[t] = e.x;
-            } else {
-                v[t] = -INFINITY;
-                jv[t] = 0x7fffffff;
-            }
+        if (tid < n) {
+            const int2 e = cand[i * (int64_t)Kc + tid];
+            v[tid] = (double)__int_as_float(e.y);
+            jv[tid] = e.x;
+        } else {
+            v[tid] = -INFINITY;
+            jv[tid] = 0x7fffffff;
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        __syncthreads();
         bool ok = c <= Kc;
         double lim = -INFINITY;
         if (ok) {
@@ -265,42 +405,37 @@ __global__ __launch_bounds__(256) void topk_finalize(
             } else {
                 ok = n >= kk;
                 if (ok) {
-                    wave_sort256(v, jv);
-                    const double ak = v[kk - 1];
-                    lim = ak - 2.0 * di;
+                    bitonic_sort_desc(v, jv, 256);
+                    lim = v[kk - 1] - 2.0 * di;
                     ok = lim >= (double)F;
                 }
             }
         }
-        if (!ok) {
-            if (lane == 0) {
+        if (!ok) {  // uniform: every value above is block-uniform
+            if (tid == 0) {
                 const unsigned long long p = atomicAdd(hdr + H_TOPK_FB, 1ull);
                 fb_rows[p] = (int)i;
             }
+            __syncthreads();
             continue;
         }
         // rescore every candidate that can still be in the top k
-        const float* r = R + i * ldR;
-        const double nr = nr64[i];
-        for (int t = lane; t < FZ_SLOTS; t += 64) {
-            if (t < n && v[t] >= lim) {
-                const int j = jv[t];
-                v[t] = sim64_from(dot64_seq(r, S + (int64_t)j * ldS, dim), nr, ns64[j]);
-            } else {
-                v[t] = -INFINITY;
-                jv[t] = 0x7fffffff;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        wave_sort256(v, jv);
-        for (int t = lane; t < k; t += 64) {
+        const bool live = tid < n && v[tid] >= lim;
+        sm.row_of[tid] = live ? (int64_t)jv[tid] : -1;
+        __syncthreads();
+        const double dot = block_dots(S, ldS, R + i * ldR, dim, sm);
+        const double sim = live ? sim64_from(dot, nr64[i], ns64[jv[tid]]) : -INFINITY;
+        __syncthreads();
+        v[tid] = sim;
+        if (!live) jv[tid] = 0x7fffffff;
+        __syncthreads();
+        bitonic_sort_desc(v, jv, 256);
+        for (int t = tid; t < k; t += 256) {
             const bool have = t < kk;
             out_idx[i * k + t] = have ? jv[t] : -1;
             out_score[i * k + t] = have ? (float)v[t] : -INFINITY;
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        __syncthreads();
     }
 }
 
@@ -319,32 +454,84 @@ hipError_t launch_norms64(const float* X, int64_t rows, int dim, int64_t ld, dou
     return hipGetLastError();
 }
 
+// number of S ranges per exact row scan (enough workgroups per row to use
+// the GPU, with the merged lists fitting the merge buffer in a few rounds)
+static int exact_ranges(int64_t nS) {
+    int64_t g = (nS + 4095) / 4096;
+    if (g > 64) g = 64;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// exact top-k of list entries [row_base, row_base + n) (n <= part rows)
+static hipError_t exact_topk_batch(const TopkArgs& a, const int* rows,
+                                   const unsigned long long* n_ptr, int n_fixed, int row_base,
+                                   int n_rows_max, int32_t* oi, float* os, double* kth,
+                                   hipStream_t st) {
+    const int n_rg = exact_ranges(a.nS);
+    hipLaunchKernelGGL(exact_topk_rows, dim3(n_rows_max, n_rg), dim3(256), 0, st, a.R, a.ldR,
+                       a.S, a.ldS, a.dim, a.nS, a.nr64, a.ns64, a.k, rows, n_ptr, n_fixed,
+                       row_base, row_base + n_rows_max, (int32_t*)nullptr, (float*)nullptr,
+                       (double*)nullptr, a.part_v, a.part_j);
+    hipLaunchKernelGGL(exact_topk_merge, dim3(n_rows_max), dim3(256), 0, st, rows, n_ptr,
+                       n_fixed, row_base, row_base + n_rows_max, n_rg, a.k, a.nS,
+                       (const double*)a.part_v, (const int*)a.part_j, oi, os, kth);
+    return hipGetLastError();
+}
+
 hipError_t launch_topk_pilot(const TopkArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(pilot_rows, dim3((a.n_pilot + 255) / 256), dim3(256), 0, st, a.pilot_rows,
                        a.n_pilot, a.nR);
-    hipLaunchKernelGGL(exact_topk_rows, dim3(a.n_pilot), dim3(256), 0, st, a.R, a.ldR, a.S, a.ldS,
-                       a.dim, a.nS, a.nr64, a.ns64, a.k, (const int*)a.pilot_rows,
-                       (const unsigned long long*)nullptr, a.n_pilot, (int32_t*)nullptr,
-                       (float*)nullptr, a.pilot_kth);
+    hipError_t e = exact_topk_batch(a, a.pilot_rows, nullptr, a.n_pilot, 0, a.n_pilot, nullptr,
+                                    nullptr, a.pilot_kth, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(topk_floor, dim3(1), dim3(64), 0, st, a.hdr, a.pilot_kth, a.n_pilot,
                        a.fp32_terms, a.all_columns ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_topk_finalize(const TopkArgs& a, hipStream_t st) {
-    int64_t nb = (a.nR + 3) / 4;
-    if (nb > 16384) nb = 16384;
-    if (nb > 0)
-        hipLaunchKernelGGL(topk_finalize, dim3((unsigned)nb), dim3(256), 0, st, a.R, a.ldR, a.S,
-                           a.ldS, a.dim, a.nR, a.nS, a.nr64, a.ns64, a.info_r, a.cnt, a.cand,
-                           a.Kc, a.k, a.fp32_terms, a.hdr, a.fb_rows, a.out_idx, a.out_score);
-    // exact scan of the rows that failed the certificate (count read on the
-    // device; a fixed grid loops over them)
-    hipLaunchKernelGGL(exact_topk_rows, dim3(1024), dim3(256), 0, st, a.R, a.ldR, a.S, a.ldS,
-                       a.dim, a.nS, a.nr64, a.ns64, a.k, (const int*)a.fb_rows,
-                       (const unsigned long long*)(a.hdr + H_TOPK_FB), 0, a.out_idx,
-                       a.out_score, (double*)nullptr);
+    if (a.nR <= 0) return hipSuccess;
+    const int* order = nullptr;
+    if (a.nS > 0) {
+        // rows grouped by their best candidate
+        hipLaunchKernelGGL(fill_int, dim3(256), dim3(256), 0, st, a.counts, a.nS + 1, 0);
+        int64_t nb = (a.nR + 3) / 4;
+        if (nb > 16384) nb = 16384;
+        hipLaunchKernelGGL(topk_keys, dim3((unsigned)nb), dim3(256), 0, st, a.cnt, a.cand, a.Kc,
+                           a.nR, a.nS, a.keys, a.counts);
+        hipLaunchKernelGGL(scan_counts, dim3(1), dim3(256), 0, st, a.counts, a.nS + 1);
+        hipLaunchKernelGGL(scatter_order, dim3(1024), dim3(256), 0, st, a.keys, a.nR, a.counts,
+                           a.order);
+        order = a.order;
+    }
+    int64_t nb = a.nR < 65536 ? a.nR : 65536;
+    hipLaunchKernelGGL(topk_finalize, dim3((unsigned)nb), dim3(256), 0, st, a.R, a.ldR, a.S,
+                       a.ldS, a.dim, a.nR, a.nS, a.nr64, a.ns64, a.info_r, a.cnt, a.cand, a.Kc,
+                       a.k, a.fp32_terms, order, a.hdr, a.fb_rows, a.out_idx, a.out_score);
     return hipGetLastError();
+}
+
+// Exact scan of the rows that failed the certificate.  n_fb is the count read
+// back by the host (-1: unknown, asynchronous call): with a known count the
+// rows go in batches through the split scan; otherwise one workgroup per row
+// loops over the device-side list.
+hipError_t launch_topk_fallback(const TopkArgs& a, int64_t n_fb, hipStream_t st) {
+    if (a.nR <= 0 || a.nS <= 0) return hipSuccess;
+    const unsigned long long* cnt = a.hdr + H_TOPK_FB;
+    if (n_fb < 0) {
+        hipLaunchKernelGGL(exact_topk_rows, dim3(1024, 1), dim3(256), 0, st, a.R, a.ldR, a.S,
+                           a.ldS, a.dim, a.nS, a.nr64, a.ns64, a.k, (const int*)a.fb_rows, cnt,
+                           0, 0, 0x7fffffff, a.out_idx, a.out_score, (double*)nullptr,
+                           (double*)nullptr, (int*)nullptr);
+        return hipGetLastError();
+    }
+    for (int64_t b = 0; b < n_fb; b += a.part_rows) {
+        hipError_t e = exact_topk_batch(a, a.fb_rows, cnt, 0, (int)b, a.part_rows, a.out_idx,
+                                        a.out_score, nullptr, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace ej
