@@ -84,8 +84,14 @@ typedef struct {
 
 /* flags */
 #define EJOIN_NO_SYNC   0x1u  /* do not synchronise; n_out is a DEVICE int64 and the status
-                                 only covers argument and launch errors */
+                                 only covers argument and launch errors.  The device count
+                                 is the match count, or minus a status code when the call
+                                 failed on the device: -EJOIN_E_WORKSPACE (band list too
+                                 small), -EJOIN_E_NONFINITE, -EJOIN_E_RANGE */
 #define EJOIN_TIMING    0x2u  /* record per-phase times in ejoin_stats (adds event syncs) */
+
+/* Autotuned tile choices (opaque; see ejoin_tuner_create). */
+typedef struct ejoin_tuner ejoin_tuner;
 
 typedef struct {
     int32_t prec;           /* ejoin_prec */
@@ -95,6 +101,7 @@ typedef struct {
     int64_t band_capacity;  /* <= 0: default; number of band pairs the workspace can hold */
     uint32_t flags;         /* EJOIN_* flags */
     int32_t topk_cand;      /* top-k: per-row candidate capacity (<= 0: default) */
+    const ejoin_tuner *tuner; /* (host, may be NULL) consulted when tile == 0 */
 } ejoin_opts;
 
 /* Optional per-call report (host struct, may be NULL). */
@@ -181,6 +188,93 @@ size_t ejoin_topk_workspace(const ejoin_rel *R, const ejoin_rel *S, int32_t k,
 ejoin_status ejoin_topk(const ejoin_rel *R, const ejoin_rel *S, int32_t k, const ejoin_opts *opts,
                         int32_t *out_idx, float *out_score, void *ws, size_t ws_bytes,
                         hipStream_t stream, ejoin_stats *stats);
+
+/* ------------------------------------------------------------------------
+ * Batched threshold joins
+ * ------------------------------------------------------------------------
+ * Many independent threshold joins (each its own R, S, theta, output) run
+ * as ONE pass: a batched prep launch, one persistent contraction launch in
+ * which workgroups pull (job, tile) work items from an atomic counter (jobs
+ * ordered largest first), a batched FP64 rescore of the band pairs of all
+ * jobs, and a count copy.  "Many queries as one join": the result of every
+ * job is exactly its own threshold join (Section III.C); the partition of
+ * the work into jobs and tiles does not change any result (the block
+ * decomposition of Section IV.C). */
+typedef struct {
+    ejoin_rel R, S;       /* (host structs; data pointers on the device) */
+    double theta;         /* finite */
+    ejoin_pair *out;      /* device array of `capacity` pairs */
+    int64_t capacity;
+} ejoin_job;
+
+/* Workspace bytes for ejoin_batch (host arguments; 0 on bad arguments).
+ * opts->band_capacity is the size of the band list SHARED by all jobs
+ * (<= 0: sum over jobs of max(65536, |R| + |S|)). */
+size_t ejoin_batch_workspace(const ejoin_job *jobs, int32_t n_jobs, const ejoin_opts *opts);
+
+/*
+ * Run a batch of threshold joins.
+ *   jobs, n_jobs  (host) 0 <= n_jobs <= 65536; all jobs use opts->prec.
+ *   opts->tile    a tile of the LDS tile kernel for opts->prec (the
+ *                 register-panel tiles have no batch form: EJOIN_E_INVAL),
+ *                 or 0: the tuner's choice, else the planner's default.
+ *   n_out         (host) int64[n_jobs] receives each job's true match count;
+ *                 with EJOIN_NO_SYNC a DEVICE int64[n_jobs] (negative status
+ *                 codes as for EJOIN_NO_SYNC above).
+ * Returns EJOIN_E_OVERFLOW if any job matched more pairs than its capacity
+ * (that job's `out` holds an arbitrary capacity-sized subset; re-run it with
+ * more room), EJOIN_E_WORKSPACE if the shared band list was too small
+ * (stats->band_needed), EJOIN_E_NONFINITE / EJOIN_E_RANGE if any job's
+ * input is bad (that job's count is 0).  stats (may be NULL) sums over jobs.
+ */
+ejoin_status ejoin_batch(const ejoin_job *jobs, int32_t n_jobs, const ejoin_opts *opts,
+                         int64_t *n_out, void *ws, size_t ws_bytes, hipStream_t stream,
+                         ejoin_stats *stats);
+
+/*
+ * A captured HIP graph of the batch pass, replayable for new batches.
+ *   create   captures the pass once on `stream` for up to max_jobs jobs and
+ *            the workspace ws (ws_bytes); opts fixes prec, tile, band and the
+ *            band-list capacity.  A pinned host staging table of
+ *            max_jobs entries is allocated here (the only allocation).
+ *   launch   plans `jobs` into the same workspace, writes the job table into
+ *            the staging buffer (waiting for the previous replay to finish
+ *            with it) and replays the graph on `stream`.  n_out is a DEVICE
+ *            int64[n_jobs] as in asynchronous ejoin_batch, and must stay the
+ *            same array between replays only if the caller wants that.
+ *            EJOIN_E_WORKSPACE if the jobs do not fit the workspace.
+ *   destroy  waits for outstanding replays and frees the graph.
+ */
+typedef struct ejoin_batch_graph ejoin_batch_graph;
+ejoin_status ejoin_batch_graph_create(int32_t max_jobs, const ejoin_opts *opts, void *ws,
+                                      size_t ws_bytes, hipStream_t stream,
+                                      ejoin_batch_graph **graph /* host */);
+ejoin_status ejoin_batch_graph_launch(ejoin_batch_graph *graph, const ejoin_job *jobs,
+                                      int32_t n_jobs, int64_t *n_out, hipStream_t stream);
+ejoin_status ejoin_batch_graph_destroy(ejoin_batch_graph *graph);
+
+/* ------------------------------------------------------------------------
+ * Autotuner: tile shapes measured on the caller's own data
+ * ------------------------------------------------------------------------
+ * A tuner maps (operation, precision, padded dimension, size bucket) to a
+ * tile id; the size bucket is floor(log4(total |R| x |S|)).  It is a plain
+ * host object owned by the caller (no global state); it can be saved to and
+ * loaded from a small text file.  ejoin_autotune times every tile of
+ * opts->prec that can run the given jobs (the batch pass for n_jobs > 1,
+ * the single join for n_jobs == 1, panels included there), `reps` timed runs
+ * each after one warm-up, records the fastest in the tuner and returns it in
+ * *best_tile.  ms (host, may be NULL) receives ejoin_tile_count() + 1 values
+ * indexed by tile id: median milliseconds, or -1 for tiles not timed. */
+ejoin_tuner *ejoin_tuner_create(void);
+void ejoin_tuner_destroy(ejoin_tuner *t);
+int32_t ejoin_tuner_lookup(const ejoin_tuner *t, int32_t batch, int32_t prec, int32_t dim,
+                           double pairs);
+ejoin_status ejoin_tuner_save(const ejoin_tuner *t, const char *path /* host */);
+ejoin_status ejoin_tuner_load(ejoin_tuner *t, const char *path /* host */);
+ejoin_status ejoin_autotune(ejoin_tuner *t, const ejoin_job *jobs, int32_t n_jobs,
+                            const ejoin_opts *opts, void *ws, size_t ws_bytes,
+                            hipStream_t stream, int32_t reps, int32_t *best_tile /* host */,
+                            float *ms /* host, may be NULL */);
 
 /* Number of tile shapes the library was built with, and the name of one
  * ("prec:BMxBNxBK"); id 0 is "planner's choice".  Static storage. */

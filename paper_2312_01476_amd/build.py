@@ -30,7 +30,8 @@ PER_FILE = {
     # min/max skip NaN canonicalisation in the threshold screening
     "panel.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"],
 }
-SOURCES = ["prep.hip", "gemm_threshold.hip", "panel.hip", "rescore.hip", "topk.hip", "api.cpp"]
+SOURCES = ["prep.hip", "gemm_threshold.hip", "panel.hip", "rescore.hip", "topk.hip", "batch.hip",
+           "api.cpp", "api_batch.cpp", "tune.cpp"]
 
 
 def _compile(src: str, verbose: bool) -> str:

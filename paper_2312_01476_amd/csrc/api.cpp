@@ -1,67 +1,12 @@
 // api.cpp -- the C ABI (include/ejoin.h): argument checks, the plan (padded
 // sizes, band, tile), workspace carve-up and the launch sequence.
-#include "../../include/ejoin.h"
-
-#include <math.h>
-#include <string.h>
-
-#include <algorithm>
-
-#include "common.hpp"
-#include "launch.hpp"
+#include "plan.hpp"
 
 using namespace ej;
 
 namespace {
 
-const double kU32 = 5.9604644775390625e-08;  // 2^-24, FP32 unit roundoff
-
-int elem_bytes(int prec) { return prec == P_FP32 ? 4 : prec == P_BF16 ? 2 : 1; }
-
-// contraction depth: dim rounded up to a whole 128-byte slice
-int padded_k(int prec, int dim) {
-    const int per = 128 / elem_bytes(prec);
-    return ((dim + per - 1) / per) * per;
-}
-
-int64_t padded_rows(int64_t rows) { return ((rows + 255) / 256) * 256; }
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// Rigorous bound on |approximate score - sim64| for unit-norm operands.
-//  * normalisation in FP32 (norm, sqrt, divide, scale): relative error per
-//    operand below gamma_d + 4u;
-//  * FP32 accumulation over Kp terms: gamma_Kp times sum |r_k s_k| <= 1;
-//  * BF16 rounding of both operands: 2 u_b + u_b^2 with u_b = 2^-8;
-//  * FP8 e4m3: |e_r| + |e_s| + |e_r||e_s| from the quantisation error norms,
-//    worst case |e| <= 2^-4 + sqrt(d) 2^-10 / 224 (power-of-two scale puts
-//    the largest element in [224, 448]);
-//  * 1e-5 of slack absorbs the FP64 rounding of sim64 itself (~1e-15) and
-//    second-order terms.
-// The FP32 terms are counted four times over to stay valid if the matrix
-// cores round each step toward zero rather than to nearest.
-double band_fp32_terms(int Kp) { return 1e-5 + 4.04 * (double)(Kp + 8) * kU32; }
-
-double band_rigorous(int prec, int dim) {
-    if (dim < 1) return -1.0;
-    const int Kp = padded_k(prec, dim);
-    const double f = band_fp32_terms(Kp);
-    if (prec == P_FP32) return f;
-    if (prec == P_BF16) return 0.0078125 + 1.52587890625e-05 + f;
-    const double E = 0.0625 * 1.001 + sqrt((double)dim) * (1.0 / 1024.0) / 224.0 + 1e-7;
-    return 2.0 * E + E * E + f * (1.0 + E) * (1.0 + E);
-}
-
-float round_down_f(double x) {
-    float f = (float)x;
-    if ((double)f > x) f = nextafterf(f, -INFINITY);
-    return f;
-}
-float round_up_f(double x) {
-    float f = (float)x;
-    if ((double)f < x) f = nextafterf(f, INFINITY);
-    return f;
-}
+using namespace ej::plan;
 
 struct Plan {
     int prec = 0, tile = 0, Kp = 0, dim = 0;
@@ -71,22 +16,6 @@ struct Plan {
     int64_t band_cap = 0;
     size_t off_info_r = 0, off_info_s = 0, off_xr = 0, off_xs = 0, off_band = 0, total = 0;
 };
-
-bool rel_ok(const ejoin_rel* X) {
-    if (!X) return false;
-    if (X->rows < 0 || X->rows >= 0x7fffffffLL) return false;
-    if (X->dim < 1 || X->ld < X->dim) return false;
-    if (X->rows > 0 && X->data == nullptr) return false;
-    return true;
-}
-
-// planner default: the register-resident panel kernel for narrow formats
-// whose rows fit it (up to 768 bytes of K), else the LDS tile kernel
-int default_tile(int prec, int Kp) {
-    if (prec == P_FP32) return 1;
-    if (Kp * elem_bytes(prec) <= 768) return prec == P_BF16 ? 14 : 13;
-    return prec == P_BF16 ? 3 : 5;
-}
 
 ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts* o, Plan& p) {
     if (!rel_ok(R) || !rel_ok(S) || R->dim != S->dim) return EJOIN_E_INVAL;
@@ -107,7 +36,15 @@ ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts*
         if (!(o->band >= rig) || !isfinite(o->band)) return EJOIN_E_INVAL;
         p.band = o->band;
     }
-    p.tile = o->tile > 0 ? o->tile : default_tile(p.prec, p.Kp);
+    p.tile = o->tile;
+    if (p.tile <= 0) {
+        // the tuner's measured choice for this shape when it has one that fits
+        const int t = o->tuner ? tuner_pick(o->tuner, 0, p.prec, p.dim, (double)p.nR * p.nS) : 0;
+        const TileDesc* td = t > 0 ? tile_get(t) : nullptr;
+        const bool fits = td && td->prec == p.prec &&
+                          !(td->bm == 0 && p.Kp * elem_bytes(p.prec) > 768);
+        p.tile = fits ? t : default_tile(p.prec, p.Kp);
+    }
     const TileDesc* td = tile_get(p.tile);
     if (!td || td->prec != p.prec) return EJOIN_E_INVAL;
     if (td->bm == 0 && p.Kp * elem_bytes(p.prec) > 768) return EJOIN_E_INVAL;
@@ -190,18 +127,7 @@ ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, c
     return EJOIN_OK;
 }
 
-ejoin_opts opts_or_default(const ejoin_opts* o) {
-    ejoin_opts d;
-    ejoin_opts_default(&d);
-    return o ? *o : d;
-}
-
 }  // namespace
-
-#define HIP_TRY(x)                                  \
-    do {                                            \
-        if ((x) != hipSuccess) return EJOIN_E_HIP;  \
-    } while (0)
 
 extern "C" {
 
@@ -222,14 +148,7 @@ const char* ejoin_strerror(ejoin_status s) {
 }
 
 void ejoin_opts_default(ejoin_opts* o) {
-    if (!o) return;
-    memset(o, 0, sizeof(*o));
-    o->prec = EJOIN_FP32;
-    o->tile = 0;
-    o->band = -1.0;
-    o->band_capacity = 0;
-    o->flags = 0;
-    o->topk_cand = 0;
+    if (o) opts_init(o);
 }
 
 double ejoin_band_default(int32_t prec, int32_t dim) {
@@ -406,7 +325,7 @@ ejoin_status ejoin_threshold(const ejoin_rel* R, const ejoin_rel* S, double thet
             // still need a defined device count
             unsigned long long* hdr = (unsigned long long*)ws;
             HIP_TRY(launch_zero_header(hdr, stream));
-            HIP_TRY(launch_copy_count(hdr, n_out, stream));
+            HIP_TRY(launch_copy_count(hdr, p.band_cap, n_out, stream));
         }
         return EJOIN_OK;
     }
@@ -456,7 +375,7 @@ ejoin_status ejoin_threshold(const ejoin_rel* R, const ejoin_rel* S, double thet
     HIP_TRY(rec(3));
 
     if (!sync) {
-        HIP_TRY(launch_copy_count(hdr, n_out, stream));
+        HIP_TRY(launch_copy_count(hdr, p.band_cap, n_out, stream));
         return EJOIN_OK;
     }
     unsigned long long h[H_COUNT];

@@ -1,0 +1,160 @@
+// batch.hip -- the persistent contraction kernel of the batched threshold
+// join, and the small bookkeeping kernels around it.
+//
+// Many joins of uneven |R|, |S| and theta are served by ONE launch: the
+// output tiles of all jobs form a flat work list (job j owns items
+// [tile_base_j, tile_base_j + tiles_m_j * tiles_n_j)), and a grid sized to
+// fill the GPU once pulls items from an atomic counter until the list is
+// exhausted.  Jobs are stored largest first, so the last items handed out
+// are small and the tail of the launch stays short.  Each item runs the same
+// tile body as the single-join kernel with its job's operands, band edges,
+// output buffer and counters; band pairs of all jobs go to one shared list
+// tagged with the job index.
+#include "batch.hpp"
+#include "common.hpp"
+#include "launch.hpp"
+#include "mma.hpp"
+#include "tile_body.hpp"
+
+namespace ej {
+
+template <int PREC, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void batch_tile(const BatchHead* __restrict__ head,
+                                                          const BatchJob* __restrict__ jobs,
+                                                          unsigned long long* __restrict__ bctr) {
+    __shared__ TileSmem<BM, BN, WM * WN> sm;
+    __shared__ int64_t s_item;
+    __shared__ int s_job;
+    const int64_t total = head->n_tiles;
+    const int n_jobs = head->n_jobs;
+    int4* band = head->band;
+    const int64_t band_cap = head->band_cap;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int64_t item = (int64_t)atomicAdd(bctr + B_ITEM, 1ull);
+            int job = 0;
+            if (item < total) {
+                // last job whose first item is <= item
+                int lo = 0, hi = n_jobs - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (jobs[mid].tile_base <= item) lo = mid;
+                    else hi = mid - 1;
+                }
+                job = lo;
+            }
+            s_item = item;
+            s_job = job;
+        }
+        __syncthreads();
+        const int64_t item = s_item;
+        const int job = __builtin_amdgcn_readfirstlane(s_job);
+        __syncthreads();  // s_item / s_job are rewritten by the next iteration
+        if (item >= total) break;
+        const BatchJob& J = jobs[job];
+        if (J.hdr[H_FLAGS] != 0) continue;  // bad input rows in this job
+        int tm, tn;
+        raster_tile((int)(item - J.tile_base), J.tiles_m, J.tiles_n, tm, tn);
+        tile_body<PREC, BM, BN, WM, WN, true>(sm, J.A, J.B, J.info_r, J.info_s, J.Kp_bytes, J.nR,
+                                              J.nS, tm, tn, J.lo, J.hi, J.out, J.capacity,
+                                              J.hdr + H_OUT, band, band_cap, bctr + B_BAND, job);
+    }
+}
+
+// Zero the pass counters and every job's counters (a kernel, not a memset,
+// so that a captured graph of the pass replays correctly).
+__global__ void batch_zero(const BatchHead* __restrict__ head, unsigned long long* bctr) {
+    const int64_t n = (int64_t)head->n_jobs * H_COUNT;
+    unsigned long long* hdrs = head->hdrs;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 < B_COUNT) bctr[i0] = 0ull;
+    for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * blockDim.x) hdrs[i] = 0ull;
+}
+
+// Per-job match counts to the caller's device array (asynchronous mode):
+// the count, or minus the status code of a failure found on the device
+// (the band list is shared, so its overflow fails every job).
+__global__ void batch_counts(const BatchHead* __restrict__ head, const BatchJob* __restrict__ jobs,
+                             const unsigned long long* __restrict__ bctr) {
+    int64_t* n_out = head->n_out;
+    if (n_out == nullptr) return;
+    const bool band_over = (int64_t)bctr[B_BAND] > head->band_cap;
+    for (int j = threadIdx.x; j < head->n_jobs; j += blockDim.x) {
+        const unsigned long long* h = jobs[j].hdr;
+        int64_t v = (int64_t)h[H_OUT];
+        if (h[H_FLAGS] & F_NONFINITE) v = -4;      // EJOIN_E_NONFINITE
+        else if (h[H_FLAGS] & F_RANGE) v = -7;     // EJOIN_E_RANGE
+        else if (band_over) v = -3;                // EJOIN_E_WORKSPACE
+        n_out[jobs[j].user] = v;
+    }
+}
+
+template <int PREC, int BM, int BN, int WM, int WN>
+static hipError_t run_batch(const BatchHead* head, const BatchJob* jobs, unsigned long long* bctr,
+                            int grid, hipStream_t st) {
+    hipLaunchKernelGGL((batch_tile<PREC, BM, BN, WM, WN>), dim3((unsigned)grid),
+                       dim3(WM * WN * 64), 0, st, head, jobs, bctr);
+    return hipGetLastError();
+}
+
+template <int PREC, int BM, int BN, int WM, int WN>
+static int occ_of() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_tile<PREC, BM, BN, WM, WN>,
+                                                     WM * WN * 64, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+
+bool batch_has_tile(int tile_id) {
+    switch (tile_id) {
+        case 1: case 2: case 3: case 4: case 5: case 6: case 8: case 10: case 11: return true;
+        default: return false;
+    }
+}
+
+// Workgroups per CU the persistent kernel of a tile keeps resident (0: the
+// tile has no batch form).
+int batch_occupancy(int tile_id) {
+    switch (tile_id) {
+        case 1: return occ_of<P_FP32, 128, 128, 2, 2>();
+        case 2: return occ_of<P_FP32, 64, 64, 2, 2>();
+        case 3: return occ_of<P_BF16, 128, 128, 2, 2>();
+        case 4: return occ_of<P_BF16, 256, 128, 2, 2>();
+        case 5: return occ_of<P_FP8, 128, 128, 2, 2>();
+        case 6: return occ_of<P_FP8, 256, 128, 2, 2>();
+        case 8: return occ_of<P_BF16, 256, 256, 2, 4>();
+        case 10: return occ_of<P_FP8, 256, 256, 2, 4>();
+        case 11: return occ_of<P_FP32, 256, 128, 2, 2>();
+        default: return 0;
+    }
+}
+
+hipError_t launch_batch_tile(int tile_id, const BatchHead* head, const BatchJob* jobs,
+                             unsigned long long* bctr, int grid, hipStream_t st) {
+    switch (tile_id) {
+        case 1: return run_batch<P_FP32, 128, 128, 2, 2>(head, jobs, bctr, grid, st);
+        case 2: return run_batch<P_FP32, 64, 64, 2, 2>(head, jobs, bctr, grid, st);
+        case 3: return run_batch<P_BF16, 128, 128, 2, 2>(head, jobs, bctr, grid, st);
+        case 4: return run_batch<P_BF16, 256, 128, 2, 2>(head, jobs, bctr, grid, st);
+        case 5: return run_batch<P_FP8, 128, 128, 2, 2>(head, jobs, bctr, grid, st);
+        case 6: return run_batch<P_FP8, 256, 128, 2, 2>(head, jobs, bctr, grid, st);
+        case 8: return run_batch<P_BF16, 256, 256, 2, 4>(head, jobs, bctr, grid, st);
+        case 10: return run_batch<P_FP8, 256, 256, 2, 4>(head, jobs, bctr, grid, st);
+        case 11: return run_batch<P_FP32, 256, 128, 2, 2>(head, jobs, bctr, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_zero(const BatchHead* head, unsigned long long* bctr, hipStream_t st) {
+    hipLaunchKernelGGL(batch_zero, dim3(64), dim3(256), 0, st, head, bctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_counts(const BatchHead* head, const BatchJob* jobs,
+                               const unsigned long long* bctr, hipStream_t st) {
+    hipLaunchKernelGGL(batch_counts, dim3(1), dim3(256), 0, st, head, jobs, bctr);
+    return hipGetLastError();
+}
+
+}  // namespace ej

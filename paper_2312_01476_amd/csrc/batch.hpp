@@ -1,0 +1,76 @@
+// batch.hpp -- device-side job table of the batched threshold join.
+//
+// A batch is a list of independent threshold joins (each its own R, S,
+// theta, output buffer and capacity), run as one pass of four launches:
+// batched prep, one persistent contraction kernel whose workgroups pull
+// (job, tile) work items from an atomic counter, a batched FP64 rescore of
+// the band pairs of every job, and a count copy.  Every launch reads its
+// work from this table in device memory and uses a grid size that does not
+// depend on the jobs, so a captured graph of the pass can be replayed for
+// another batch after only the table has been rewritten.
+#pragma once
+
+#include "common.hpp"
+
+namespace ej {
+
+// One join of the batch.  Jobs are stored largest first (by tile count), so
+// the work items handed out last are the small tiles of small jobs.
+struct BatchJob {
+    const char* A;             // prepared R rows (padded K)
+    const char* B;             // prepared S rows
+    const RowInfo* info_r;
+    const RowInfo* info_s;
+    const float* R;            // caller's float32 rows (FP64 rescore)
+    const float* S;
+    Pair* out;
+    unsigned long long* hdr;   // per-job counters (H_OUT, H_FLAGS, H_BAND_ACC)
+    int64_t ldR, ldS;
+    int64_t nR, nS;
+    int64_t capacity;
+    int64_t tile_base;         // first flat work item of this job
+    double theta;
+    float lo, hi;              // approximate-score band edges
+    int32_t tiles_m, tiles_n;
+    int32_t Kp_bytes, dim;
+    int32_t user;              // index of the job in the caller's array
+    int32_t pad_;
+};
+
+// One relation to prepare (R or S of a job; an aliased self-join has one).
+struct PrepSeg {
+    const float* X;
+    void* Xq;
+    RowInfo* info;
+    unsigned long long* hdr;   // flags go to the owning job's counters
+    int64_t rows, rows_pad, ld;
+    int64_t row_base;          // first flat prep row of this segment
+    int32_t dim, Kp;
+};
+
+struct BatchHead {
+    int64_t n_tiles;           // flat work items over all jobs
+    int64_t n_rows;            // flat prep rows over all segments
+    int64_t band_cap;          // entries of the shared band list
+    int4* band;                // {r, s, job, 0}
+    int64_t* n_out;            // per caller job (device), or null
+    unsigned long long* hdrs;  // n_jobs x H_COUNT counters, contiguous
+    int32_t n_jobs, n_segs;
+    int32_t pad_[2];
+};
+
+// Global counters of a batch pass.
+enum : int {
+    B_ITEM = 0,     // next work item of the persistent kernel
+    B_BAND = 1,     // band entries found (may exceed band_cap)
+    B_COUNT = 32
+};
+
+// Table image: head, then jobs[max_jobs], then segs[2 * max_jobs].
+struct BatchTable {
+    const BatchHead* head;
+    const BatchJob* jobs;
+    const PrepSeg* segs;
+};
+
+}  // namespace ej

@@ -101,6 +101,25 @@ hipError_t launch_rescore_band(const float* R, int64_t ldR, const float* S, int6
                                const int2* band, int64_t band_cap, double theta, Pair* out,
                                int64_t capacity, unsigned long long* hdr, hipStream_t st);
 
-hipError_t launch_copy_count(const unsigned long long* hdr, int64_t* dst, hipStream_t st);
+hipError_t launch_copy_count(const unsigned long long* hdr, int64_t band_cap, int64_t* dst,
+                             hipStream_t st);
 
+}  // namespace ej
+
+// ---- batched threshold join (batch.hpp holds the table layout) ----
+namespace ej {
+struct BatchHead;
+struct BatchJob;
+struct PrepSeg;
+bool batch_has_tile(int tile_id);  // the tile has a persistent batch form
+int batch_occupancy(int tile_id);  // resident workgroups per CU, 0: no batch form
+hipError_t launch_batch_zero(const BatchHead* head, unsigned long long* bctr, hipStream_t st);
+hipError_t launch_batch_prep(int prec, const BatchHead* head, const PrepSeg* segs, int grid,
+                             hipStream_t st);
+hipError_t launch_batch_tile(int tile_id, const BatchHead* head, const BatchJob* jobs,
+                             unsigned long long* bctr, int grid, hipStream_t st);
+hipError_t launch_batch_rescore(const BatchHead* head, const BatchJob* jobs,
+                                const unsigned long long* bctr, int grid, hipStream_t st);
+hipError_t launch_batch_counts(const BatchHead* head, const BatchJob* jobs,
+                               const unsigned long long* bctr, hipStream_t st);
 }  // namespace ej

@@ -9,24 +9,19 @@
 // that the matrix-core kernel runs without bounds checks or per-element
 // scaling.  It also records per-row data used by the error bounds.
 #include "common.hpp"
+#include "batch.hpp"
 #include "launch.hpp"
 
 namespace ej {
 
-// One wave per row.  Rows >= rows (tile padding) are written as zeros.
+// Prepare row `row` (one wave; rows >= rows are tile padding, written as
+// zeros).  Returns the row's quantisation error norm (0 for FP32).
 template <int PREC>
-__global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, int64_t rows,
-                                                 int dim, int64_t ld, void* __restrict__ Xq,
-                                                 int Kp, int64_t rows_pad,
-                                                 RowInfo* __restrict__ info,
-                                                 unsigned long long* __restrict__ hdr,
-                                                 int enorm_slot) {
-    const int lane = threadIdx.x & 63;
-    float wave_emax = 0.0f;  // largest error norm seen by this wave
-    // grid-stride over rows, one wave per row
-    for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < rows_pad;
-         row += (int64_t)gridDim.x * 4) {
-
+__device__ __forceinline__ float prep_one_row(const float* __restrict__ X, int64_t rows, int dim,
+                                              int64_t ld, void* __restrict__ Xq, int Kp,
+                                              RowInfo* __restrict__ info,
+                                              unsigned long long* __restrict__ hdr, int64_t row,
+                                              int lane) {
     float inv = 0.0f, qscale = 1.0f, enorm = 0.0f;
     uint32_t flags = 0;
     const float* x = X + row * ld;
@@ -115,7 +110,6 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
     if (PREC != P_FP32) {
         esq = wave_sum(esq);
         enorm = sqrtf(esq);
-        wave_emax = fmaxf(wave_emax, enorm);
     }
     if (lane == 0) {
         RowInfo ri;
@@ -125,7 +119,23 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
         ri.flags = flags;
         info[row] = ri;
     }
-    }
+    return enorm;
+}
+
+// One wave per row, grid-stride.
+template <int PREC>
+__global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, int64_t rows,
+                                                 int dim, int64_t ld, void* __restrict__ Xq,
+                                                 int Kp, int64_t rows_pad,
+                                                 RowInfo* __restrict__ info,
+                                                 unsigned long long* __restrict__ hdr,
+                                                 int enorm_slot) {
+    const int lane = threadIdx.x & 63;
+    float wave_emax = 0.0f;  // largest error norm seen by this wave
+    for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < rows_pad;
+         row += (int64_t)gridDim.x * 4)
+        wave_emax = fmaxf(wave_emax,
+                          prep_one_row<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr, row, lane));
     // one atomic per workgroup for the maximum error norm
     __shared__ float s_emax[4];
     if (lane == 0) s_emax[threadIdx.x >> 6] = wave_emax;
@@ -134,6 +144,41 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
         const float m = fmaxf(fmaxf(s_emax[0], s_emax[1]), fmaxf(s_emax[2], s_emax[3]));
         if (m > 0.0f) atomicMax((unsigned int*)(hdr + enorm_slot), __float_as_uint(m));
     }
+}
+
+// Batched prep: the rows of every relation of a batch form one flat range;
+// each wave finds its row's relation by binary search over the segment
+// starts.  The error-norm maximum is not needed by the threshold join and is
+// not collected here.
+template <int PREC>
+__global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ head,
+                                                  const PrepSeg* __restrict__ segs) {
+    const int lane = threadIdx.x & 63;
+    const int64_t n = head->n_rows;
+    const int nseg = head->n_segs;
+    for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n;
+         row += (int64_t)gridDim.x * 4) {
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (segs[mid].row_base <= row) lo = mid;
+            else hi = mid - 1;
+        }
+        const PrepSeg& g = segs[lo];
+        prep_one_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, row - g.row_base,
+                           lane);
+    }
+}
+
+hipError_t launch_batch_prep(int prec, const BatchHead* head, const PrepSeg* segs, int grid,
+                             hipStream_t st) {
+    dim3 g((unsigned)grid), b(256);
+    switch (prec) {
+        case P_FP32: hipLaunchKernelGGL(batch_prep<P_FP32>, g, b, 0, st, head, segs); break;
+        case P_BF16: hipLaunchKernelGGL(batch_prep<P_BF16>, g, b, 0, st, head, segs); break;
+        default: hipLaunchKernelGGL(batch_prep<P_FP8>, g, b, 0, st, head, segs); break;
+    }
+    return hipGetLastError();
 }
 
 // Zero the workspace header (a kernel rather than a memset so that the call

@@ -12,6 +12,7 @@
 // The same rule defines the exact result set, so a pair accepted here is a
 // pair of that set and the score written is sim64 rounded to float.
 #include "common.hpp"
+#include "batch.hpp"
 #include "launch.hpp"
 
 namespace ej {
@@ -89,13 +90,79 @@ hipError_t launch_rescore_band(const float* R, int64_t ldR, const float* S, int6
     return hipGetLastError();
 }
 
-// Device-side copy of the output count (asynchronous mode).
-__global__ void copy_count(const unsigned long long* hdr, int64_t* dst) {
-    if (threadIdx.x == 0) dst[0] = (int64_t)hdr[H_OUT];
+// Batched rescore: one lane per entry of the band list shared by the jobs
+// of a batch ({r, s, job}); each entry is decided with its own job's rows and
+// theta.  Accepted pairs are appended to their job's output with one
+// atomicAdd per (wave, job): lanes are grouped by job with ballots (entries
+// of one tile are contiguous, so a wave nearly always holds one job).
+__global__ __launch_bounds__(256) void batch_rescore(const BatchHead* __restrict__ head,
+                                                     const BatchJob* __restrict__ jobs,
+                                                     const unsigned long long* __restrict__ bctr) {
+    const int64_t n = min((int64_t)bctr[B_BAND], head->band_cap);
+    const int4* __restrict__ band = head->band;
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n;
+         base += stride) {
+        const int64_t p = base + lane;
+        bool acc = false;
+        double sim = 0.0;
+        int4 e = make_int4(0, 0, -1, 0);
+        if (p < n) {
+            e = band[p];
+            const BatchJob& J = jobs[e.z];
+            sim = sim64_canonical(J.R + (int64_t)e.x * J.ldR, J.S + (int64_t)e.y * J.ldS, J.dim);
+            acc = sim >= J.theta;
+        }
+        uint64_t todo = __ballot(acc);
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const int job = __shfl(e.z, leader, 64);
+            const uint64_t m = __ballot(acc && e.z == job);
+            todo &= ~m;
+            unsigned long long* hdr = jobs[job].hdr;
+            unsigned long long b = 0;
+            if (lane == leader) {
+                b = atomicAdd(hdr + H_OUT, (unsigned long long)__popcll(m));
+                atomicAdd(hdr + H_BAND_ACC, (unsigned long long)__popcll(m));
+            }
+            const uint32_t blo = __shfl((uint32_t)b, leader, 64);
+            const uint32_t bhi = __shfl((uint32_t)(b >> 32), leader, 64);
+            const unsigned long long bb = ((unsigned long long)bhi << 32) | blo;
+            if ((m >> lane) & 1ull) {
+                const unsigned long long q = bb + lanes_below(m);
+                if ((int64_t)q < jobs[job].capacity) {
+                    Pair pr;
+                    pr.r = e.x;
+                    pr.s = e.y;
+                    pr.score = (float)sim;
+                    jobs[job].out[q] = pr;
+                }
+            }
+        }
+    }
 }
 
-hipError_t launch_copy_count(const unsigned long long* hdr, int64_t* dst, hipStream_t st) {
-    hipLaunchKernelGGL(copy_count, dim3(1), dim3(64), 0, st, hdr, dst);
+hipError_t launch_batch_rescore(const BatchHead* head, const BatchJob* jobs,
+                                const unsigned long long* bctr, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(batch_rescore, dim3((unsigned)grid), dim3(256), 0, st, head, jobs, bctr);
+    return hipGetLastError();
+}
+
+// Device-side copy of the output count (asynchronous mode): the count, or
+// minus the status code of a failure found on the device.
+__global__ void copy_count(const unsigned long long* hdr, int64_t band_cap, int64_t* dst) {
+    if (threadIdx.x != 0) return;
+    int64_t v = (int64_t)hdr[H_OUT];
+    if (hdr[H_FLAGS] & F_NONFINITE) v = -4;             // EJOIN_E_NONFINITE
+    else if (hdr[H_FLAGS] & F_RANGE) v = -7;            // EJOIN_E_RANGE
+    else if ((int64_t)hdr[H_BAND] > band_cap) v = -3;   // EJOIN_E_WORKSPACE
+    dst[0] = v;
+}
+
+hipError_t launch_copy_count(const unsigned long long* hdr, int64_t band_cap, int64_t* dst,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(copy_count, dim3(1), dim3(64), 0, st, hdr, band_cap, dst);
     return hipGetLastError();
 }
 

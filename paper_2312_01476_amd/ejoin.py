@@ -27,7 +27,13 @@ class Rel(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("tile", C.c_int32), ("band", C.c_double),
-                ("band_capacity", C.c_int64), ("flags", C.c_uint32), ("topk_cand", C.c_int32)]
+                ("band_capacity", C.c_int64), ("flags", C.c_uint32), ("topk_cand", C.c_int32),
+                ("tuner", C.c_void_p)]
+
+
+class Job(C.Structure):
+    _fields_ = [("R", Rel), ("S", Rel), ("theta", C.c_double), ("out", C.c_void_p),
+                ("capacity", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -82,6 +88,33 @@ def lib():
         L.ejoin_topk.restype = C.c_int
         L.ejoin_topk.argtypes = [P(Rel), P(Rel), C.c_int32, P(Opts), C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_size_t, C.c_void_p, P(Stats)]
+        L.ejoin_batch_workspace.restype = C.c_size_t
+        L.ejoin_batch_workspace.argtypes = [P(Job), C.c_int32, P(Opts)]
+        L.ejoin_batch.restype = C.c_int
+        L.ejoin_batch.argtypes = [P(Job), C.c_int32, P(Opts), C.c_void_p, C.c_void_p,
+                                  C.c_size_t, C.c_void_p, P(Stats)]
+        L.ejoin_batch_graph_create.restype = C.c_int
+        L.ejoin_batch_graph_create.argtypes = [C.c_int32, P(Opts), C.c_void_p, C.c_size_t,
+                                               C.c_void_p, P(C.c_void_p)]
+        L.ejoin_batch_graph_launch.restype = C.c_int
+        L.ejoin_batch_graph_launch.argtypes = [C.c_void_p, P(Job), C.c_int32, C.c_void_p,
+                                               C.c_void_p]
+        L.ejoin_batch_graph_destroy.restype = C.c_int
+        L.ejoin_batch_graph_destroy.argtypes = [C.c_void_p]
+        L.ejoin_tuner_create.restype = C.c_void_p
+        L.ejoin_tuner_create.argtypes = []
+        L.ejoin_tuner_destroy.restype = None
+        L.ejoin_tuner_destroy.argtypes = [C.c_void_p]
+        L.ejoin_tuner_lookup.restype = C.c_int32
+        L.ejoin_tuner_lookup.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double]
+        L.ejoin_tuner_save.restype = C.c_int
+        L.ejoin_tuner_save.argtypes = [C.c_void_p, C.c_char_p]
+        L.ejoin_tuner_load.restype = C.c_int
+        L.ejoin_tuner_load.argtypes = [C.c_void_p, C.c_char_p]
+        L.ejoin_autotune.restype = C.c_int
+        L.ejoin_autotune.argtypes = [C.c_void_p, P(Job), C.c_int32, P(Opts), C.c_void_p,
+                                     C.c_size_t, C.c_void_p, C.c_int32, P(C.c_int32),
+                                     P(C.c_float)]
         _lib = L
     return _lib
 
@@ -112,7 +145,7 @@ def _rel(X, d):
     return Rel(X.data_ptr() if n > 0 else 0, n, dim, X.stride(0) if n > 1 else max(ld, dim))
 
 
-def _opts(prec, band, tile, band_capacity, flags, topk_cand=0):
+def _opts(prec, band, tile, band_capacity, flags, topk_cand=0, tuner=None):
     o = Opts()
     lib().ejoin_opts_default(C.byref(o))
     o.prec = PREC[prec]
@@ -121,6 +154,7 @@ def _opts(prec, band, tile, band_capacity, flags, topk_cand=0):
     o.band_capacity = int(band_capacity)
     o.flags = int(flags)
     o.topk_cand = int(topk_cand)
+    o.tuner = tuner.handle if tuner is not None else None
     return o
 
 
@@ -142,9 +176,10 @@ class Pairs:
         return int(self.r.shape[0])
 
 
-def threshold_workspace(R, S, *, d=None, prec="fp32", band=None, tile=0, band_capacity=0):
+def threshold_workspace(R, S, *, d=None, prec="fp32", band=None, tile=0, band_capacity=0,
+                        tuner=None):
     r, s = _rel(R, d), _rel(S, d)
-    o = _opts(prec, band, tile, band_capacity, 0)
+    o = _opts(prec, band, tile, band_capacity, 0, tuner=tuner)
     n = lib().ejoin_threshold_workspace(C.byref(r), C.byref(s), C.byref(o))
     if n == 0:
         raise EjoinError(E_INVAL, "ejoin_threshold_workspace")
@@ -152,13 +187,13 @@ def threshold_workspace(R, S, *, d=None, prec="fp32", band=None, tile=0, band_ca
 
 
 def threshold_raw(R, S, theta, out, capacity, ws, *, d=None, prec="fp32", band=None, tile=0,
-                  band_capacity=0, flags=0, stream=None, n_out_dev=None):
+                  band_capacity=0, flags=0, stream=None, n_out_dev=None, tuner=None):
     """One ejoin_threshold call on caller-provided buffers (``out``: int32
     tensor (capacity, 3); ``ws``: uint8 tensor).  Returns (status, n_out,
     stats dict).  With NO_SYNC, ``n_out_dev`` (int64 device tensor) receives
     the count."""
     r, s = _rel(R, d), _rel(S, d)
-    o = _opts(prec, band, tile, band_capacity, flags)
+    o = _opts(prec, band, tile, band_capacity, flags, tuner=tuner)
     st = Stats()
     n = C.c_int64(0)
     if flags & NO_SYNC:
@@ -173,7 +208,7 @@ def threshold_raw(R, S, theta, out, capacity, ws, *, d=None, prec="fp32", band=N
 
 
 def threshold(R, S, theta: float, *, d=None, prec="fp32", band=None, tile=0, capacity=None,
-              band_capacity=0, timing=False, stream=None) -> Pairs:
+              band_capacity=0, timing=False, stream=None, tuner=None) -> Pairs:
     """Threshold E-join on the GPU: all (i, j) with sim64(R_i, S_j) >= theta.
 
     R, S: float32 CUDA tensors (n, ld) with unit column stride; ``d`` is the
@@ -187,12 +222,12 @@ def threshold(R, S, theta: float, *, d=None, prec="fp32", band=None, tile=0, cap
     flags = TIMING if timing else 0
     for _ in range(4):
         ws_bytes = threshold_workspace(R, S, d=d, prec=prec, band=band, tile=tile,
-                                       band_capacity=band_capacity)
+                                       band_capacity=band_capacity, tuner=tuner)
         ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
         out = torch.empty((max(capacity, 1), 3), dtype=torch.int32, device=dev)
         rc, n, st = threshold_raw(R, S, theta, out, capacity, ws, d=d, prec=prec, band=band,
                                   tile=tile, band_capacity=band_capacity, flags=flags,
-                                  stream=stream)
+                                  stream=stream, tuner=tuner)
         if rc == OK:
             o = out[:n]
             return Pairs(o[:, 0], o[:, 1], o[:, 2].view(torch.float32), st)
@@ -245,3 +280,176 @@ def topk(R, S, k: int, *, d=None, prec="bf16", topk_cand=0, timing=False, stream
     if rc != OK:
         raise EjoinError(rc, "ejoin_topk")
     return idx, sc, st
+
+
+# ---------------------------------------------------------------------------
+# batched threshold joins
+# ---------------------------------------------------------------------------
+
+def _jobs(jobs, outs, caps, d):
+    arr = (Job * max(1, len(jobs)))()
+    for i, (R, S, theta) in enumerate(jobs):
+        arr[i].R = _rel(R, d)
+        arr[i].S = _rel(S, d)
+        arr[i].theta = float(theta)
+        arr[i].out = outs[i].data_ptr() if (outs is not None and caps[i] > 0) else None
+        arr[i].capacity = int(caps[i]) if caps is not None else 0
+    return arr
+
+
+def batch_workspace(jobs, *, d=None, prec="fp32", band=None, tile=0, band_capacity=0,
+                    tuner=None):
+    """Workspace bytes for ejoin_batch; ``jobs`` is a list of (R, S, theta)."""
+    arr = _jobs(jobs, None, [0] * len(jobs), d)
+    o = _opts(prec, band, tile, band_capacity, 0, tuner=tuner)
+    n = lib().ejoin_batch_workspace(arr, len(jobs), C.byref(o))
+    if n == 0:
+        raise EjoinError(E_INVAL, "ejoin_batch_workspace")
+    return int(n)
+
+
+def batch_raw(jobs, outs, caps, ws, n_out, *, d=None, prec="fp32", band=None, tile=0,
+              band_capacity=0, flags=0, stream=None, tuner=None):
+    """One ejoin_batch call on caller buffers.  ``outs[i]``: int32 (cap_i, 3)
+    tensors; ``n_out``: int64 CPU tensor (sync) or CUDA tensor (NO_SYNC).
+    Returns (status, stats dict)."""
+    arr = _jobs(jobs, outs, caps, d)
+    o = _opts(prec, band, tile, band_capacity, flags, tuner=tuner)
+    st = Stats()
+    rc = lib().ejoin_batch(arr, len(jobs), C.byref(o), C.c_void_p(n_out.data_ptr()),
+                           C.c_void_p(ws.data_ptr()), int(ws.numel()), _stream(stream),
+                           C.byref(st))
+    return rc, st.as_dict()
+
+
+def batch(jobs, *, d=None, prec="fp32", band=None, tile=0, capacities=None, band_capacity=0,
+          timing=False, stream=None, tuner=None):
+    """Run many threshold joins as one batch pass.  ``jobs``: list of
+    (R, S, theta).  Returns (list of Pairs, stats dict).  Jobs whose output
+    overflowed are run again (as a smaller batch) with exactly enough room."""
+    import torch
+    n = len(jobs)
+    if n == 0:
+        return [], {}
+    dev = jobs[0][0].device
+    caps = list(capacities) if capacities is not None else [
+        max(1 << 16, min(R.shape[0] * S.shape[0], (R.shape[0] + S.shape[0]) * 64))
+        for R, S, _ in jobs]
+    results = [None] * n
+    todo = list(range(n))
+    stats = {}
+    flags = TIMING if timing else 0
+    for _ in range(6):
+        sub = [jobs[i] for i in todo]
+        sub_caps = [caps[i] for i in todo]
+        ws = torch.empty(batch_workspace(sub, d=d, prec=prec, band=band, tile=tile,
+                                         band_capacity=band_capacity, tuner=tuner),
+                         dtype=torch.uint8, device=dev)
+        outs = [torch.empty((max(c, 1), 3), dtype=torch.int32, device=dev) for c in sub_caps]
+        n_out = torch.zeros(len(sub), dtype=torch.int64)
+        rc, st = batch_raw(sub, outs, sub_caps, ws, n_out, d=d, prec=prec, band=band, tile=tile,
+                           band_capacity=band_capacity, flags=flags, stream=stream, tuner=tuner)
+        if not stats:
+            stats = st
+        if rc == E_WORKSPACE and st["band_needed"] > 0:
+            band_capacity = int(st["band_needed"] * 1.25) + 1024
+            continue
+        if rc not in (OK, E_OVERFLOW):
+            raise EjoinError(rc, "ejoin_batch")
+        again = []
+        for q, i in enumerate(todo):
+            c = int(n_out[q])
+            if c > sub_caps[q]:
+                caps[i] = c
+                again.append(i)
+            else:
+                o = outs[q][:c]
+                results[i] = Pairs(o[:, 0], o[:, 1], o[:, 2].view(torch.float32), {})
+        todo = again
+        if not todo:
+            return results, stats
+    raise EjoinError(E_OVERFLOW, "ejoin_batch (retries exhausted)")
+
+
+class BatchGraph:
+    """A captured graph of the batch pass (ejoin_batch_graph_*), replayable
+    for new batches of at most ``max_jobs`` jobs within the workspace ``ws``."""
+
+    def __init__(self, max_jobs, ws, *, prec="fp32", band=None, tile=0, band_capacity=0,
+                 stream=None):
+        self.ws = ws
+        self.handle = C.c_void_p()
+        o = _opts(prec, band, tile, band_capacity, NO_SYNC)
+        rc = lib().ejoin_batch_graph_create(int(max_jobs), C.byref(o), C.c_void_p(ws.data_ptr()),
+                                            int(ws.numel()), _stream(stream),
+                                            C.byref(self.handle))
+        if rc != OK:
+            raise EjoinError(rc, "ejoin_batch_graph_create")
+        self.d = None
+
+    def launch(self, jobs, outs, caps, n_out_dev, *, d=None, stream=None):
+        arr = _jobs(jobs, outs, caps, d)
+        rc = lib().ejoin_batch_graph_launch(self.handle, arr, len(jobs),
+                                            C.c_void_p(n_out_dev.data_ptr()), _stream(stream))
+        if rc != OK:
+            raise EjoinError(rc, "ejoin_batch_graph_launch")
+
+    def close(self):
+        if self.handle:
+            rc = lib().ejoin_batch_graph_destroy(self.handle)
+            self.handle = C.c_void_p()
+            if rc != OK:
+                raise EjoinError(rc, "ejoin_batch_graph_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tuner:
+    """Caller-owned table of measured tile choices (ejoin_tuner_*)."""
+
+    def __init__(self):
+        self.handle = lib().ejoin_tuner_create()
+        if not self.handle:
+            raise EjoinError(E_INVAL, "ejoin_tuner_create")
+
+    def lookup(self, batch, prec, dim, pairs):
+        return int(lib().ejoin_tuner_lookup(self.handle, int(bool(batch)), PREC[prec],
+                                            int(dim), float(pairs)))
+
+    def save(self, path):
+        rc = lib().ejoin_tuner_save(self.handle, str(path).encode())
+        if rc != OK:
+            raise EjoinError(rc, "ejoin_tuner_save")
+
+    def load(self, path):
+        rc = lib().ejoin_tuner_load(self.handle, str(path).encode())
+        if rc != OK:
+            raise EjoinError(rc, "ejoin_tuner_load")
+
+    def autotune(self, jobs, outs, caps, ws, *, d=None, prec="fp32", band=None,
+                 band_capacity=0, reps=3, stream=None):
+        """Time every tile that can run ``jobs`` and record the fastest.
+        Returns (best tile id, {tile id: median ms})."""
+        arr = _jobs(jobs, outs, caps, d)
+        o = _opts(prec, band, 0, band_capacity, 0)
+        best = C.c_int32(0)
+        nt = lib().ejoin_tile_count()
+        ms = (C.c_float * (nt + 1))()
+        rc = lib().ejoin_autotune(self.handle, arr, len(jobs), C.byref(o),
+                                  C.c_void_p(ws.data_ptr()), int(ws.numel()), _stream(stream),
+                                  int(reps), C.byref(best), ms)
+        if rc != OK:
+            raise EjoinError(rc, "ejoin_autotune")
+        return int(best.value), {i: float(ms[i]) for i in range(1, nt + 1) if ms[i] >= 0}
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().ejoin_tuner_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

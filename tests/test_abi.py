@@ -58,3 +58,74 @@ def test_workspace_query_is_bounded_not_dense():
     assert 0 < ws < 0.01 * 100_000 * 100_000 * 4
     bad = E.Rel(0x1000, 10, 300, 200)     # ld < dim
     assert L.ejoin_threshold_workspace(C.byref(bad), C.byref(R), C.byref(o)) == 0
+
+
+def _job(E, nr, ns, d=768, theta=0.8, cap=0, alias=False):
+    j = E.Job()
+    j.R = E.Rel(0x1000, nr, d, d)
+    j.S = E.Rel(0x1000 if alias else 0x2000, ns, d, d)
+    j.theta = theta
+    j.out = 0x3000 if cap else None
+    j.capacity = cap
+    return j
+
+
+def test_batch_workspace_query():
+    """The batch workspace holds the prepared operands of every job, one
+    counter block per job and the shared band list; never a dense block of
+    similarities.  A self-join prepares its relation once."""
+    from paper_2312_01476_amd import ejoin as E
+    L = E.lib()
+    arr = (E.Job * 3)(_job(E, 500_000, 100_000), _job(E, 1000, 1000), _job(E, 0, 50))
+    o = E._opts("bf16", None, 0, 0, 0)
+    ws = L.ejoin_batch_workspace(arr, 3, C.byref(o))
+    ops = (500_096 + 100_096 + 1024 * 2) * 768 * 2
+    assert ops < ws < ops * 1.2
+    # aliasing: one copy of the relation
+    a1 = (E.Job * 1)(_job(E, 10_000, 10_000, alias=True))
+    a2 = (E.Job * 1)(_job(E, 10_000, 10_000))
+    o.band_capacity = 1
+    assert L.ejoin_batch_workspace(a1, 1, C.byref(o)) < L.ejoin_batch_workspace(a2, 1, C.byref(o))
+    # invalid: theta not finite, capacity without buffer, panel tile, wrong-precision tile
+    bad = (E.Job * 1)(_job(E, 10, 10, theta=float("nan")))
+    assert L.ejoin_batch_workspace(bad, 1, C.byref(o)) == 0
+    bad = (E.Job * 1)(_job(E, 10, 10))
+    bad[0].capacity = 5
+    assert L.ejoin_batch_workspace(bad, 1, C.byref(o)) == 0
+    ok = (E.Job * 1)(_job(E, 10, 10))
+    for tile in (14, 12, 1):
+        ot = E._opts("bf16", None, tile, 0, 0)
+        assert L.ejoin_batch_workspace(ok, 1, C.byref(ot)) == 0
+    assert L.ejoin_batch_workspace(ok, 1, C.byref(E._opts("bf16", None, 8, 0, 0))) > 0
+    # empty batch is valid
+    assert L.ejoin_batch_workspace(ok, 0, C.byref(o)) > 0
+
+
+def test_tuner_file_roundtrip_and_nearest_bucket(tmp_path):
+    from paper_2312_01476_amd import ejoin as E
+    p = tmp_path / "t.txt"
+    # batch prec Kp bucket tile
+    p.write_text("# hand-written\n1 1 768 17 4 bf16:256x128x64\n1 1 768 12 3 x\n"
+                 "0 1 384 15 14 bf16:panel/2wg\n0 0 320 16 11 fp32:256x128x32\n")
+    t = E.Tuner()
+    t.load(p)
+    assert t.lookup(True, "bf16", 768, 4.0 ** 17) == 4
+    assert t.lookup(True, "bf16", 768, 4.0 ** 18 + 5) == 4      # nearest bucket
+    assert t.lookup(True, "bf16", 768, 4.0 ** 12) == 3
+    assert t.lookup(True, "bf16", 720, 4.0 ** 12) == 3          # same padded depth (768)
+    assert t.lookup(True, "bf16", 700, 4.0 ** 12) == 0          # padded depth 704
+    assert t.lookup(False, "bf16", 384, 1e9) == 14
+    assert t.lookup(False, "fp32", 300, 1e10) == 11
+    assert t.lookup(True, "fp8", 768, 1e10) == 0                 # nothing recorded
+    q = tmp_path / "u.txt"
+    t.save(q)
+    t2 = E.Tuner()
+    t2.load(q)
+    for args in ((True, "bf16", 768, 4.0 ** 17), (False, "fp32", 300, 1e10)):
+        assert t2.lookup(*args) == t.lookup(*args)
+    # a panel tile has no batch form; a tile of another precision is rejected
+    for line in ("1 1 384 15 14 x\n", "0 0 320 16 3 x\n", "garbage\n"):
+        r = tmp_path / "bad.txt"
+        r.write_text(line)
+        with pytest.raises(E.EjoinError):
+            E.Tuner().load(r)
