@@ -186,6 +186,15 @@ WORKLOADS = {
     "fp8_topk_2m": Workload("fp8_topk_2m", 2_000_000, 200_000, 768, 768, 2000,
                             0.3, k=10, prec="fp8", seeds=(401, 402, 403),
                             notes="2M x 200k, 768-d, top-10, fp8 e4m3"),
+    # 64 joins in one batch: |R| log-uniform 1k-500k, |S| log-uniform 1k-100k,
+    # theta uniform in [0.75, 0.95], 768-d, 1000 shared clusters sigma 0.3
+    # (job shapes from batch_jobs, seed 501; per-job R/S seeds from there).
+    "batch64_fp32": Workload("batch64_fp32", 0, 0, 768, 768, 1000, 0.3, prec="fp32",
+                             seeds=(500, 0, 0), extra={"batch": 64, "job_seed": 501},
+                             notes="64 uneven joins, 768-d, fp32 + fp64 band, one batch pass"),
+    "batch64_bf16": Workload("batch64_bf16", 0, 0, 768, 768, 1000, 0.3, prec="bf16",
+                             seeds=(500, 0, 0), extra={"batch": 64, "job_seed": 501},
+                             notes="64 uneven joins, 768-d, bf16 + fp64 band, one batch pass"),
 }
 
 
