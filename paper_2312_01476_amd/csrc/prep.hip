@@ -122,6 +122,125 @@ __device__ __forceinline__ float prep_one_row(const float* __restrict__ X, int64
     return enorm;
 }
 
+// Register-resident form of prep_one_row for rows of at most 1024 elements:
+// the row is read from memory once (lane l holds elements l + 64 j) and every
+// pass works on the registers.  Same arithmetic in the same order as
+// prep_one_row, so both give identical bits.
+constexpr int kRegMax = 1024;
+
+template <int PREC>
+__device__ __forceinline__ float prep_row_reg(const float* __restrict__ X, int64_t rows, int dim,
+                                              int64_t ld, void* __restrict__ Xq, int Kp,
+                                              RowInfo* __restrict__ info,
+                                              unsigned long long* __restrict__ hdr, int64_t row,
+                                              int lane) {
+    constexpr int NV = kRegMax / 64;
+    float inv = 0.0f, qscale = 1.0f, enorm = 0.0f;
+    uint32_t flags = 0;
+    const float* x = X + row * ld;
+    const bool real = row < rows;
+    float xv[NV];
+    float amax = 0.0f;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int k = lane + 64 * j;
+        float v = 0.0f;
+        if (real && k < dim) v = x[k];
+        xv[j] = v;
+        bad |= !isfinite(v);
+        amax = fmaxf(amax, fabsf(v));
+    }
+    if (real) {
+        bad = __any(bad);
+        amax = wave_max(amax);
+        if (bad) {
+            flags = F_NONFINITE;
+        } else if (amax > 0.0f) {
+            int e = ilogbf(amax);
+            float sc = ldexpf(1.0f, -e);
+            float ss = 0.0f;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                if (lane + 64 * j < dim) {
+                    float v = xv[j] * sc;
+                    ss = fmaf(v, v, ss);
+                }
+            }
+            ss = wave_sum(ss);
+            if (e < -100 || e > 99) flags = F_RANGE;
+            else inv = ldexpf(1.0f / sqrtf(ss), -e);
+        }
+    }
+    if (flags != 0 && lane == 0) atomicOr(hdr + H_FLAGS, (unsigned long long)flags);
+
+    if (PREC == P_FP8 && inv != 0.0f) {
+        float am = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NV; ++j)
+            if (lane + 64 * j < dim) am = fmaxf(am, fabsf(xv[j] * inv));
+        am = wave_max(am);
+        int p = ilogbf(448.0f / am);
+        while (ldexpf(am, p + 1) <= 448.0f) ++p;
+        while (ldexpf(am, p) > 448.0f) --p;
+        qscale = ldexpf(1.0f, p);
+    }
+
+    float esq = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int k = lane + 64 * j;
+        if (k >= Kp) break;
+        const bool live = k < dim && inv != 0.0f;
+        if (PREC == P_FP32) {
+            ((float*)Xq)[row * (int64_t)Kp + k] = live ? xv[j] * inv : 0.0f;
+        } else if (PREC == P_BF16) {
+            uint16_t b = 0;
+            if (live) {
+                float v = xv[j] * inv;
+                b = f32_to_bf16_rne(v);
+                float e = bf16_to_f32(b) - v;
+                esq = fmaf(e, e, esq);
+            }
+            ((uint16_t*)Xq)[row * (int64_t)Kp + k] = b;
+        } else {
+            uint8_t b = 0;
+            if (live) {
+                float v = xv[j] * inv;
+                float q = e4m3_round(v * qscale);
+                b = e4m3_bits(q);
+                float e = q * (1.0f / qscale) - v;
+                esq = fmaf(e, e, esq);
+            }
+            ((uint8_t*)Xq)[row * (int64_t)Kp + k] = b;
+        }
+    }
+    if (PREC != P_FP32) {
+        esq = wave_sum(esq);
+        enorm = sqrtf(esq);
+    }
+    if (lane == 0) {
+        RowInfo ri;
+        ri.inv = inv;
+        ri.qscale = qscale;
+        ri.enorm = enorm;
+        ri.flags = flags;
+        info[row] = ri;
+    }
+    return enorm;
+}
+
+template <int PREC>
+__device__ __forceinline__ float prep_row(const float* __restrict__ X, int64_t rows, int dim,
+                                          int64_t ld, void* __restrict__ Xq, int Kp,
+                                          RowInfo* __restrict__ info,
+                                          unsigned long long* __restrict__ hdr, int64_t row,
+                                          int lane) {
+    if (Kp <= kRegMax)
+        return prep_row_reg<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr, row, lane);
+    return prep_one_row<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr, row, lane);
+}
+
 // One wave per row, grid-stride.
 template <int PREC>
 __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, int64_t rows,
@@ -135,7 +254,7 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
     for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < rows_pad;
          row += (int64_t)gridDim.x * 4)
         wave_emax = fmaxf(wave_emax,
-                          prep_one_row<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr, row, lane));
+                          prep_row<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr, row, lane));
     // one atomic per workgroup for the maximum error norm
     __shared__ float s_emax[4];
     if (lane == 0) s_emax[threadIdx.x >> 6] = wave_emax;
@@ -165,8 +284,8 @@ __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ 
             else hi = mid - 1;
         }
         const PrepSeg& g = segs[lo];
-        prep_one_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, row - g.row_base,
-                           lane);
+        prep_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, row - g.row_base,
+                       lane);
     }
 }
 

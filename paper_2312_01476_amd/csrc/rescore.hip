@@ -17,15 +17,69 @@
 
 namespace ej {
 
-__device__ __forceinline__ double sim64_canonical(const float* __restrict__ r,
-                                                  const float* __restrict__ s, int dim) {
+// Each lane of a wave holds one pair (rp, sp, dim; valid=false for none) and
+// gets sim64 of it.  The rule is sequential in k, so one lane sums one pair;
+// the rows are brought in through LDS in chunks of 32 elements so that every
+// global load instruction reads whole row segments (lanes 0-31 one R chunk,
+// lanes 32-63 the matching S chunk of one pair) instead of 64 scattered
+// words.  Per pair the chunk is stored at stride 65 floats, so the lanes'
+// sequential reads fall in 64 distinct banks.
+constexpr int kChunk = 32;
+
+// 32-bit word `w` of lane i (uniform i), zero-extended.
+__device__ __forceinline__ uint32_t lane_word(uint64_t w, int i) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)w, i);
+}
+constexpr int kPairStride = 2 * kChunk + 1;
+
+__device__ __forceinline__ double wave_sim64(const float* rp, const float* sp, int dim, bool valid,
+                                             float* __restrict__ lds) {
+    const int lane = threadIdx.x & 63;
+    const int kmax = valid ? dim : 0;
+    int dmax = kmax;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, 64));
+    const uint64_t ru = (uint64_t)rp, su = (uint64_t)sp;
+    const int half = lane >> 5, kk = lane & 31;
     double dot = 0.0, nr = 0.0, ns = 0.0;
-    for (int k = 0; k < dim; ++k) {
-        const double a = (double)r[k];
-        const double b = (double)s[k];
-        dot = dot + a * b;
-        nr = nr + a * a;
-        ns = ns + b * b;
+    for (int k0 = 0; k0 < dmax; k0 += kChunk) {
+        // 16 pairs at a time: their loads are independent and in flight
+        // together, then the values go to LDS
+        for (int i0 = 0; i0 < 64; i0 += 16) {
+            float vals[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = i0 + q;
+                const int di = __builtin_amdgcn_readlane(kmax, i);
+                // pair i's row pointers (scalar), then each half takes its
+                // row; readlane returns int, so each half goes through
+                // uint32_t before widening (a sign-extended low half would be
+                // a wild address)
+                const uint64_t r_i = ((uint64_t)lane_word(ru >> 32, i) << 32) | lane_word(ru, i);
+                const uint64_t s_i = ((uint64_t)lane_word(su >> 32, i) << 32) | lane_word(su, i);
+                const float* base = (const float*)(half ? s_i : r_i);
+                float v = 0.0f;
+                if (k0 + kk < di) v = base[k0 + kk];
+                vals[q] = v;
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) lds[(i0 + q) * kPairStride + half * kChunk + kk] = vals[q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int n = min(kChunk, kmax - k0);
+        const float* mine = lds + lane * kPairStride;
+        for (int k = 0; k < n; ++k) {
+            const double a = (double)mine[k];
+            const double b = (double)mine[kChunk + k];
+            dot = dot + a * b;
+            nr = nr + a * a;
+            ns = ns + b * b;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (nr == 0.0 || ns == 0.0) return 0.0;
     return dot / __builtin_sqrt(nr * ns);
@@ -40,6 +94,8 @@ __global__ __launch_bounds__(256) void rescore_band(const float* __restrict__ R,
                                                     Pair* __restrict__ out, int64_t capacity,
                                                     unsigned long long* __restrict__ hdr) {
     if (hdr[H_FLAGS] != 0) return;
+    __shared__ float s_rows[4][64 * kPairStride];
+    float* lds = s_rows[threadIdx.x >> 6];
     const int64_t n = min((int64_t)hdr[H_BAND], band_cap);
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -49,11 +105,9 @@ __global__ __launch_bounds__(256) void rescore_band(const float* __restrict__ R,
         bool acc = false;
         double sim = 0.0;
         int2 e = make_int2(0, 0);
-        if (p < n) {
-            e = band[p];
-            sim = sim64_canonical(R + (int64_t)e.x * ldR, S + (int64_t)e.y * ldS, dim);
-            acc = sim >= theta;
-        }
+        if (p < n) e = band[p];
+        sim = wave_sim64(R + (int64_t)e.x * ldR, S + (int64_t)e.y * ldS, dim, p < n, lds);
+        acc = p < n && sim >= theta;
         const uint64_t m = __ballot(acc);
         if (m) {
             const int leader = __ffsll((unsigned long long)m) - 1;
@@ -100,6 +154,8 @@ __global__ __launch_bounds__(256) void batch_rescore(const BatchHead* __restrict
                                                      const unsigned long long* __restrict__ bctr) {
     const int64_t n = min((int64_t)bctr[B_BAND], head->band_cap);
     const int4* __restrict__ band = head->band;
+    __shared__ float s_rows[4][64 * kPairStride];
+    float* lds = s_rows[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n;
@@ -108,12 +164,20 @@ __global__ __launch_bounds__(256) void batch_rescore(const BatchHead* __restrict
         bool acc = false;
         double sim = 0.0;
         int4 e = make_int4(0, 0, -1, 0);
+        const float* rp = nullptr;
+        const float* sp = nullptr;
+        int dim = 0;
+        double theta = 0.0;
         if (p < n) {
             e = band[p];
             const BatchJob& J = jobs[e.z];
-            sim = sim64_canonical(J.R + (int64_t)e.x * J.ldR, J.S + (int64_t)e.y * J.ldS, J.dim);
-            acc = sim >= J.theta;
+            rp = J.R + (int64_t)e.x * J.ldR;
+            sp = J.S + (int64_t)e.y * J.ldS;
+            dim = J.dim;
+            theta = J.theta;
         }
+        sim = wave_sim64(rp, sp, dim, p < n, lds);
+        acc = p < n && sim >= theta;
         uint64_t todo = __ballot(acc);
         while (todo) {
             const int leader = __ffsll((unsigned long long)todo) - 1;
