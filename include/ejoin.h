@@ -276,6 +276,81 @@ ejoin_status ejoin_autotune(ejoin_tuner *t, const ejoin_job *jobs, int32_t n_job
                             hipStream_t stream, int32_t reps, int32_t *best_tile /* host */,
                             float *ms /* host, may be NULL */);
 
+/* ------------------------------------------------------------------------
+ * Learned prefilter network (approximate mode; not part of the paper)
+ * ------------------------------------------------------------------------
+ * A two-layer MLP codes a normalised embedding row x (dim values) as a unit
+ * vector: h = ReLU(x W1 + b1) (256), z = h W2 + b2 (64), u = z / ||z||; the
+ * predicted similarity of a pair is u_r . u_s.  Weights are FP32 masters
+ * with BF16 copies; products use the BF16 values and accumulate in FP32.
+ * Training minimises, over a batch of pairs with targets t (their sim64),
+ *     mean[(p - t)^2] + lambda * mean[max(0, t - p)^2 * 1{t >= theta_lo}]
+ * with Adam.  All network state lives in ONE caller-owned device block whose
+ * layout ejoin_mlp_layout_get describes. */
+#define EJOIN_MLP_HIDDEN 256
+#define EJOIN_MLP_OUT    64
+#define EJOIN_MLP_PLANES 16
+#define EJOIN_MLP_GRAD_ONLY 0x1u  /* train step: compute gradients, do not update */
+
+typedef struct {
+    int32_t dim, dim_pad;   /* input width; its padding to a multiple of 64 */
+    int64_t n_params;       /* dim*256 + 256 + 256*64 + 64 */
+    /* byte offsets in the state block.  FP32 vectors of n_params values,
+     * flat: W1 (dim x 256, row-major), b1 (256), W2 (256 x 64), b2 (64) */
+    size_t off_params, off_grads, off_m, off_v;
+    size_t off_w1t;         /* BF16 W1^T, 256 x dim_pad (zero beyond dim) */
+    size_t off_w2t;         /* BF16 W2^T, 64 x 256 */
+    size_t off_planes;      /* FP32 16 x 64 hyperplanes of the row-ordering key */
+    size_t off_step;        /* int64 number of Adam steps taken */
+    size_t total;           /* bytes of the state block */
+} ejoin_mlp_layout;
+
+typedef struct {
+    float lr, beta1, beta2, eps;  /* Adam (defaults 1e-3, 0.9, 0.999, 1e-8) */
+    float lambda, theta_lo;       /* recall term (defaults 4, 0.7) */
+    uint32_t flags;               /* EJOIN_MLP_GRAD_ONLY */
+} ejoin_mlp_hparams;
+
+/* Layout of the state block for inputs of width dim (1..1024). */
+ejoin_status ejoin_mlp_layout_get(int32_t dim, ejoin_mlp_layout *layout /* host */);
+void ejoin_mlp_hparams_default(ejoin_mlp_hparams *hp /* host */);
+
+/* Set the masters to `params` (device, n_params FP32 in the flat order; the
+ * seeded initial weights are the caller's), the hyperplanes to `planes`
+ * (device, 16 x 64), zero gradients, moments and step count, and build the
+ * BF16 copies. */
+ejoin_status ejoin_mlp_init(void *state, int32_t dim, const float *params, const float *planes,
+                            hipStream_t stream);
+
+/* Workspace bytes of a training step of `batch` pairs. */
+size_t ejoin_mlp_train_workspace(int32_t dim, int32_t batch);
+
+/*
+ * One training step on `batch` pairs: rows pr[i] and ps[i] (device int32,
+ * 0 <= index < rows; an index outside that range reads as a zero row) of X
+ * (device BF16 rows, ldx elements apart, the first dim used), targets
+ * target[i] (device FP32).  Writes the batch loss to *loss (device FP32) and
+ * the gradients into the state; unless hp->flags has EJOIN_MLP_GRAD_ONLY,
+ * applies Adam and refreshes the BF16 copies.  hp: host, NULL = defaults.
+ */
+ejoin_status ejoin_mlp_train_step(void *state, int32_t dim, const uint16_t *X, int64_t ldx,
+                                  int64_t rows, const int32_t *pr, const int32_t *ps,
+                                  const float *target, int32_t batch,
+                                  const ejoin_mlp_hparams *hp, void *ws, size_t ws_bytes,
+                                  float *loss, hipStream_t stream);
+
+/* Workspace bytes of ejoin_mlp_forward over n rows. */
+size_t ejoin_mlp_forward_workspace(int32_t dim, int64_t n);
+
+/*
+ * Codes of n rows on the matrix cores: U (device FP32, n x 64) = u(X_i).
+ * X: device BF16 rows of exactly dim_pad values each (zero beyond dim), and
+ * round_up(n, 128) rows must be readable (the layout of the join's prepared
+ * BF16 operands).  The hidden layer is kept in BF16.
+ */
+ejoin_status ejoin_mlp_forward(const void *state, int32_t dim, const uint16_t *X, int64_t n,
+                               float *U, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Number of tile shapes the library was built with, and the name of one
  * ("prec:BMxBNxBK"); id 0 is "planner's choice".  Static storage. */
 int32_t ejoin_tile_count(void);

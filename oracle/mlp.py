@@ -65,13 +65,16 @@ def forward_weights(params: dict, round_bf16: bool = True) -> dict:
     return {k: bf16_round(v) for k, v in params.items()}
 
 
-def forward(W: dict, X) -> dict:
+def forward(W: dict, X, round_h: bool = False) -> dict:
     """Codes of the rows of X (n x d, float64 values).  Returns the
     intermediates a1 = x W1 + b1, h = ReLU(a1), z = h W2 + b2, the norm of z
-    and u = z / ||z||."""
+    and u = z / ||z||.  round_h stores h in BF16 before the second layer
+    (the inference form, whose hidden layer is kept in BF16)."""
     X = np.asarray(X, np.float64)
     a1 = X @ W["W1"] + W["b1"]
     h = np.maximum(a1, 0.0)
+    if round_h:
+        h = bf16_round(h)
     z = h @ W["W2"] + W["b2"]
     nz = np.sqrt(np.sum(z * z, axis=1))
     u = z / nz[:, None]

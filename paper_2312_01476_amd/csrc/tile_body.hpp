@@ -46,31 +46,37 @@ __device__ __forceinline__ void raster_tile(int bid, int tiles_m, int tiles_n, i
     tn = in_grp / gsize;
 }
 
-// All threads of the workgroup call this for tile (tm, tn).  out_ctr and
-// band_ctr count the pairs appended to `out` and to the band list.  Band
-// entries are int2 {r, s}, or, with TAG, int4 {r, s, job, 0} (one band list
-// shared by the jobs of a batch).
-template <int PREC, int BM, int BN, int WM, int WN, bool TAG = false>
-__device__ __forceinline__ void tile_body(
-    TileSmem<BM, BN, WM * WN>& sm, const char* __restrict__ A, const char* __restrict__ B,
-    const RowInfo* __restrict__ info_r, const RowInfo* __restrict__ info_s, int Kp_bytes,
-    int64_t nR, int64_t nS, int tm, int tn, float lo, float hi, Pair* __restrict__ out,
-    int64_t capacity, unsigned long long* __restrict__ out_ctr, void* __restrict__ band,
-    int64_t band_cap, unsigned long long* __restrict__ band_ctr, int job = 0) {
-    constexpr int NT = WM * WN * 64;
-    constexpr int NW = WM * WN;
-    constexpr int WTM = BM / WM;  // rows per wave
-    constexpr int WTN = BN / WN;  // cols per wave
-    constexpr int FM = WTM / 32;  // 32x32 blocks per wave
-    constexpr int FN = WTN / 32;
-    constexpr int CA = BM * 8 / NT;  // 16-byte chunks per thread per slice
-    constexpr int CB = BN * 8 / NT;
+// Shape constants of a BM x BN tile computed by WM x WN waves.
+template <int BM, int BN, int WM, int WN>
+struct TileGeom {
+    static constexpr int NT = WM * WN * 64;
+    static constexpr int NW = WM * WN;
+    static constexpr int WTM = BM / WM;  // rows per wave
+    static constexpr int WTN = BN / WN;  // cols per wave
+    static constexpr int FM = WTM / 32;  // 32x32 blocks per wave
+    static constexpr int FN = WTN / 32;
+    static constexpr int CA = BM * 8 / NT;  // 16-byte chunks per thread per slice
+    static constexpr int CB = BN * 8 / NT;
     static_assert(CA * NT == BM * 8 && CB * NT == BN * 8, "tile/thread mismatch");
+};
+
+// Contraction of tile (tm, tn): acc[i][j] receives the 32x32 block (i, j)
+// of this wave's WTM x WTN part of A_tile B_tile^T.  Both operands are
+// K-contiguous rows of Kp_bytes bytes (a multiple of 128); rows up to the
+// end of the tile must be readable.  info_r / info_s give the FP8 row scales
+// (unused otherwise).  All threads of the workgroup call this.
+template <int PREC, int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void tile_mainloop(
+    TileSmem<BM, BN, WM * WN>& sm, const char* __restrict__ A, const char* __restrict__ B,
+    const RowInfo* __restrict__ info_r, const RowInfo* __restrict__ info_s, int Kp_bytes, int tm,
+    int tn, v16f (&acc)[TileGeom<BM, BN, WM, WN>::FM][TileGeom<BM, BN, WM, WN>::FN]) {
+    typedef TileGeom<BM, BN, WM, WN> TG;
+    constexpr int NT = TG::NT;
+    constexpr int WTM = TG::WTM, WTN = TG::WTN, FM = TG::FM, FN = TG::FN;
+    constexpr int CA = TG::CA, CB = TG::CB;
     typedef Mma<PREC> M;
     auto& sA = sm.sA;
     auto& sB = sm.sB;
-    auto& s_cnt = sm.s_cnt;
-    auto& s_base = sm.s_base;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -82,7 +88,6 @@ __device__ __forceinline__ void tile_body(
     const char* Bg = B + (int64_t)tn * BN * Kp_bytes;
     const int nk = Kp_bytes >> 7;
 
-    v16f acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -168,6 +173,33 @@ __device__ __forceinline__ void tile_body(
         if (kb + 1 < nk) lstore(st ^ 1);
         __syncthreads();
     }
+
+}
+
+// All threads of the workgroup call this for tile (tm, tn).  out_ctr and
+// band_ctr count the pairs appended to `out` and to the band list.  Band
+// entries are int2 {r, s}, or, with TAG, int4 {r, s, job, 0} (one band list
+// shared by the jobs of a batch).
+template <int PREC, int BM, int BN, int WM, int WN, bool TAG = false>
+__device__ __forceinline__ void tile_body(
+    TileSmem<BM, BN, WM * WN>& sm, const char* __restrict__ A, const char* __restrict__ B,
+    const RowInfo* __restrict__ info_r, const RowInfo* __restrict__ info_s, int Kp_bytes,
+    int64_t nR, int64_t nS, int tm, int tn, float lo, float hi, Pair* __restrict__ out,
+    int64_t capacity, unsigned long long* __restrict__ out_ctr, void* __restrict__ band,
+    int64_t band_cap, unsigned long long* __restrict__ band_ctr, int job = 0) {
+    typedef TileGeom<BM, BN, WM, WN> TG;
+    constexpr int NW = TG::NW;
+    constexpr int WTM = TG::WTM, WTN = TG::WTN, FM = TG::FM, FN = TG::FN;
+    auto& s_cnt = sm.s_cnt;
+    auto& s_base = sm.s_base;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    const int h = lane >> 5, r32 = lane & 31;
+
+    v16f acc[FM][FN];
+    tile_mainloop<PREC, BM, BN, WM, WN>(sm, A, B, info_r, info_s, Kp_bytes, tm, tn, acc);
 
     // ---- epilogue ----
     // accumulator element e of block (i, j) of this lane sits at

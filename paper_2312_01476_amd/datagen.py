@@ -238,3 +238,22 @@ def make_host(w: Workload, n_r: int | None = None, n_s: int | None = None,
     R, lr = clustered_points(cent, n_r, w.sigma, rs, ld=w.ld, pad_value=pad_value)
     S, ls = clustered_points(cent, n_s, w.sigma, ss, ld=w.ld, pad_value=pad_value)
     return R, S, lr, ls
+
+
+# --------------------------------------------------------------------------
+# seeded initial state of the prefilter network (random draws only)
+# --------------------------------------------------------------------------
+
+def mlp_init(dim: int, seed: int, hidden: int = 256, out: int = 64, planes: int = 16,
+             bias_scale: float = 0.0):
+    """He-initialised flat parameters (W1 dim x hidden, b1, W2 hidden x out,
+    b2; biases N(0, bias_scale^2)) and Gaussian ordering-key hyperplanes
+    (planes x out), float32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W1 = rng.standard_normal((dim, hidden)) * math.sqrt(2.0 / dim)
+    b1 = rng.standard_normal(hidden) * bias_scale
+    W2 = rng.standard_normal((hidden, out)) * math.sqrt(2.0 / hidden)
+    b2 = rng.standard_normal(out) * bias_scale
+    flat = np.concatenate([W1.ravel(), b1, W2.ravel(), b2]).astype(np.float32)
+    P = rng.standard_normal((planes, out)).astype(np.float32)
+    return flat, P

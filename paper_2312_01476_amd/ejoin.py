@@ -453,3 +453,136 @@ class Tuner:
                 self.handle = None
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# prefilter network
+# ---------------------------------------------------------------------------
+
+MLP_HIDDEN, MLP_OUT, MLP_PLANES = 256, 64, 16
+MLP_GRAD_ONLY = 0x1
+
+
+class MlpLayout(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("dim_pad", C.c_int32), ("n_params", C.c_int64),
+                ("off_params", C.c_size_t), ("off_grads", C.c_size_t), ("off_m", C.c_size_t),
+                ("off_v", C.c_size_t), ("off_w1t", C.c_size_t), ("off_w2t", C.c_size_t),
+                ("off_planes", C.c_size_t), ("off_step", C.c_size_t), ("total", C.c_size_t)]
+
+
+class MlpHparams(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("lambda_", C.c_float), ("theta_lo", C.c_float),
+                ("flags", C.c_uint32)]
+
+
+def _mlp_sigs(L):
+    P = C.POINTER
+    L.ejoin_mlp_layout_get.restype = C.c_int
+    L.ejoin_mlp_layout_get.argtypes = [C.c_int32, P(MlpLayout)]
+    L.ejoin_mlp_hparams_default.restype = None
+    L.ejoin_mlp_hparams_default.argtypes = [P(MlpHparams)]
+    L.ejoin_mlp_init.restype = C.c_int
+    L.ejoin_mlp_init.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.ejoin_mlp_train_workspace.restype = C.c_size_t
+    L.ejoin_mlp_train_workspace.argtypes = [C.c_int32, C.c_int32]
+    L.ejoin_mlp_train_step.restype = C.c_int
+    L.ejoin_mlp_train_step.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_int64,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                       P(MlpHparams), C.c_void_p, C.c_size_t, C.c_void_p,
+                                       C.c_void_p]
+    L.ejoin_mlp_forward_workspace.restype = C.c_size_t
+    L.ejoin_mlp_forward_workspace.argtypes = [C.c_int32, C.c_int64]
+    L.ejoin_mlp_forward.restype = C.c_int
+    L.ejoin_mlp_forward.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                                    C.c_void_p, C.c_size_t, C.c_void_p]
+
+
+def mlp_layout(dim):
+    L = lib()
+    if not hasattr(L, "_mlp_sigs"):
+        _mlp_sigs(L)
+        L._mlp_sigs = True
+    lay = MlpLayout()
+    rc = L.ejoin_mlp_layout_get(int(dim), C.byref(lay))
+    if rc != OK:
+        raise EjoinError(rc, "ejoin_mlp_layout_get")
+    return lay
+
+
+class Mlp:
+    """The prefilter network's state block (one device tensor) and views of
+    its regions.  ``params``: flat FP32 initial weights (W1 dim x 256, b1,
+    W2 256 x 64, b2); ``planes``: 16 x 64 ordering-key hyperplanes."""
+
+    def __init__(self, dim, params, planes, stream=None):
+        import torch
+        self.dim = int(dim)
+        self.lay = mlp_layout(dim)
+        self.state = torch.zeros(self.lay.total, dtype=torch.uint8, device="cuda")
+        p = params.to(device="cuda", dtype=torch.float32).contiguous()
+        q = planes.to(device="cuda", dtype=torch.float32).contiguous()
+        if p.numel() != self.lay.n_params or q.numel() != MLP_PLANES * MLP_OUT:
+            raise ValueError("params / planes have the wrong size")
+        rc = lib().ejoin_mlp_init(C.c_void_p(self.state.data_ptr()), self.dim,
+                                  C.c_void_p(p.data_ptr()), C.c_void_p(q.data_ptr()),
+                                  _stream(stream))
+        if rc != OK:
+            raise EjoinError(rc, "ejoin_mlp_init")
+        self._ws = None
+
+    def _f32(self, off, n):
+        return self.state[off:off + 4 * n].view(__import__("torch").float32)
+
+    def params(self):
+        return self._f32(self.lay.off_params, self.lay.n_params)
+
+    def grads(self):
+        return self._f32(self.lay.off_grads, self.lay.n_params)
+
+    def moments(self):
+        return (self._f32(self.lay.off_m, self.lay.n_params),
+                self._f32(self.lay.off_v, self.lay.n_params))
+
+    def split(self, flat):
+        """Views W1, b1, W2, b2 of a flat parameter-shaped vector."""
+        d, H, O = self.dim, MLP_HIDDEN, MLP_OUT
+        a = d * H
+        return {"W1": flat[:a].view(d, H), "b1": flat[a:a + H],
+                "W2": flat[a + H:a + H + H * O].view(H, O), "b2": flat[a + H + H * O:]}
+
+    def train_step(self, X, pr, ps, target, loss, *, hp=None, grad_only=False, stream=None):
+        """One step on pairs (pr, ps) of the BF16 rows X with targets."""
+        import torch
+        L = lib()
+        h = MlpHparams()
+        L.ejoin_mlp_hparams_default(C.byref(h))
+        for k, v in (hp or {}).items():
+            setattr(h, "lambda_" if k == "lambda" else k, v)
+        if grad_only:
+            h.flags |= MLP_GRAD_ONLY
+        B = int(pr.numel())
+        need = L.ejoin_mlp_train_workspace(self.dim, B)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        rc = L.ejoin_mlp_train_step(C.c_void_p(self.state.data_ptr()), self.dim,
+                                    C.c_void_p(X.data_ptr()), X.stride(0), X.shape[0],
+                                    C.c_void_p(pr.data_ptr()), C.c_void_p(ps.data_ptr()),
+                                    C.c_void_p(target.data_ptr()), B, C.byref(h),
+                                    C.c_void_p(self._ws.data_ptr()), self._ws.numel(),
+                                    C.c_void_p(loss.data_ptr()), _stream(stream))
+        if rc != OK:
+            raise EjoinError(rc, "ejoin_mlp_train_step")
+
+    def forward(self, X, n, U, stream=None):
+        """Codes of the first n rows of X (dim_pad BF16 values per row,
+        round_up(n, 128) rows) into U (n x 64 FP32)."""
+        import torch
+        L = lib()
+        need = L.ejoin_mlp_forward_workspace(self.dim, int(n))
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+        rc = L.ejoin_mlp_forward(C.c_void_p(self.state.data_ptr()), self.dim,
+                                 C.c_void_p(X.data_ptr()), int(n), C.c_void_p(U.data_ptr()),
+                                 C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+        if rc != OK:
+            raise EjoinError(rc, "ejoin_mlp_forward")

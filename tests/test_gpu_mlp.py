@@ -1,0 +1,151 @@
+"""Prefilter network on the GPU (through the C ABI) against the FP64
+reference: gradients, loss, the Adam update, training progress and the
+matrix-core inference codes."""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from paper_2312_01476_amd import datagen as G
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+E = None
+
+
+def setup_module(module):
+    global E
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_01476_amd import ejoin
+    E = ejoin
+
+
+def _split(flat, d):
+    H, O = 256, 64
+    a = d * H
+    return {"W1": flat[:a].reshape(d, H), "b1": flat[a:a + H],
+            "W2": flat[a + H:a + H + H * O].reshape(H, O), "b2": flat[a + H + H * O:]}
+
+
+def _rows_bf16(n, d, seed, pad_to=None):
+    """Normalised rows rounded to BF16: (float64 values, device BF16 tensor)."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, d))
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    xb = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16)
+    vals = xb.to(torch.float64).numpy()
+    if pad_to is not None:
+        n_pad, d_pad = pad_to
+        full = torch.zeros((n_pad, d_pad), dtype=torch.bfloat16)
+        full[:n, :d] = xb
+        xb = full
+    return vals, xb.cuda()
+
+
+def _setup(d, n_rows, B, seed):
+    flat, planes = G.mlp_init(d, seed, bias_scale=0.05)
+    net = E.Mlp(d, torch.from_numpy(flat), torch.from_numpy(planes))
+    X, Xd = _rows_bf16(n_rows, d, seed + 1)
+    rng = np.random.default_rng(seed + 2)
+    pr = rng.integers(0, n_rows, B).astype(np.int32)
+    ps = rng.integers(0, n_rows, B).astype(np.int32)
+    t = rng.uniform(-0.2, 1.0, B).astype(np.float32)
+    dev = [torch.from_numpy(a).cuda() for a in (pr, ps, t)]
+    return flat, net, X, Xd, pr, ps, t, dev
+
+
+@pytest.mark.parametrize("d,B", [(96, 256), (300, 700), (768, 1024)])
+def test_gradients_and_loss_match_reference(d, B):
+    flat, net, X, Xd, pr, ps, t, (prd, psd, td) = _setup(d, 500, B, 10 + d)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    net.train_step(Xd, prd, psd, td, loss, grad_only=True)
+    torch.cuda.synchronize()
+    p0 = _split(flat.astype(np.float64), d)
+    want_loss, want, _ = M.loss_and_grads(p0, X, pr, ps, t.astype(np.float64), 4.0, 0.7)
+    got = _split(net.grads().cpu().numpy().astype(np.float64), d)
+    assert abs(loss.item() - want_loss) <= 1e-4 * max(1.0, want_loss)
+    for k in ("W1", "b1", "W2", "b2"):
+        scale = np.abs(want[k]).max()
+        err = np.abs(got[k] - want[k]).max()
+        assert err <= 2e-3 * scale + 1e-8, (k, err, scale)
+    # grad-only leaves the weights and the moments untouched
+    assert np.array_equal(net.params().cpu().numpy(), flat)
+    m, v = net.moments()
+    assert float(m.abs().max()) == 0.0 and float(v.abs().max()) == 0.0
+
+
+def test_adam_first_step_matches_reference():
+    d, B = 128, 512
+    flat, net, X, Xd, pr, ps, t, (prd, psd, td) = _setup(d, 400, B, 77)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    lr = 1e-3
+    net.train_step(Xd, prd, psd, td, loss, hp={"lr": lr})
+    torch.cuda.synchronize()
+    p0 = _split(flat.astype(np.float64), d)
+    _, g, _ = M.loss_and_grads(p0, X, pr, ps, t.astype(np.float64), 4.0, 0.7)
+    zero = {k: np.zeros_like(v) for k, v in p0.items()}
+    want, _, _ = M.adam_step(p0, g, zero, zero, 1, lr=lr)
+    got = _split(net.params().cpu().numpy().astype(np.float64), d)
+    for k in p0:
+        dg = got[k] - p0[k]
+        dw = want[k] - p0[k]
+        firm = np.abs(g[k]) > 1e-3 * np.abs(g[k]).max()
+        # where the gradient's sign is well determined the step is +-lr
+        assert np.abs(dg[firm] - dw[firm]).max() <= 1e-2 * lr, k
+        assert np.abs(dg).max() <= lr * 1.001 + 1e-6, k
+    # the BF16 copies follow the masters
+    w1t = net.state[net.lay.off_w1t:net.lay.off_w1t + 2 * 256 * net.lay.dim_pad]
+    w1t = w1t.view(torch.bfloat16).view(256, net.lay.dim_pad).cpu().double().numpy()
+    assert np.array_equal(w1t[:, :d], M.bf16_round(got["W1"].T.astype(np.float32)))
+    assert np.all(w1t[:, d:] == 0)
+
+
+def test_training_reduces_loss_on_clustered_pairs():
+    d = 128
+    cent = G.centres(d, 20, 5)
+    Xf, lab = G.clustered_points(cent, 2000, 0.4, 6)
+    Xb = torch.from_numpy(Xf).to(torch.bfloat16)
+    X = Xb.double().numpy()
+    Xd = Xb.cuda()
+    flat, planes = G.mlp_init(d, 7)
+    net = E.Mlp(d, torch.from_numpy(flat), torch.from_numpy(planes))
+    rng = np.random.default_rng(8)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    losses = []
+    for step in range(150):
+        # half same-cluster pairs, half uniform pairs; sim64 targets
+        B = 1024
+        pr = rng.integers(0, 2000, B)
+        ps = rng.integers(0, 2000, B)
+        same = np.flatnonzero(lab == lab[pr[0]])
+        for i in range(B // 2):
+            c = np.flatnonzero(lab == lab[pr[i]])
+            ps[i] = c[rng.integers(0, c.size)]
+        Xn = X / np.linalg.norm(X, axis=1, keepdims=True)
+        t = np.sum(Xn[pr] * Xn[ps], axis=1).astype(np.float32)
+        net.train_step(Xd, torch.from_numpy(pr.astype(np.int32)).cuda(),
+                       torch.from_numpy(ps.astype(np.int32)).cuda(),
+                       torch.from_numpy(t).cuda(), loss, hp={"lr": 3e-3})
+        losses.append(loss.item())
+    assert np.mean(losses[-10:]) < 0.2 * np.mean(losses[:5]), (losses[:5], losses[-10:])
+
+
+@pytest.mark.parametrize("d,n", [(96, 300), (768, 1000), (384, 128)])
+def test_forward_codes_match_reference(d, n):
+    flat, planes = G.mlp_init(d, 31 + d, bias_scale=0.05)
+    net = E.Mlp(d, torch.from_numpy(flat), torch.from_numpy(planes))
+    dp = net.lay.dim_pad
+    n_pad = (n + 127) // 128 * 128
+    X, Xd = _rows_bf16(n, d, 41 + n, pad_to=(n_pad, dp))
+    U = torch.empty((n, 64), dtype=torch.float32, device="cuda")
+    net.forward(Xd, n, U)
+    torch.cuda.synchronize()
+    W = M.forward_weights(_split(flat.astype(np.float64), d))
+    want = M.forward(W, X, round_h=True)["u"]
+    got = U.cpu().numpy().astype(np.float64)
+    assert np.allclose(np.linalg.norm(got, axis=1), 1.0, atol=1e-5)
+    # BF16 hidden values may round the other way where FP32 and FP64 sums
+    # straddle a rounding boundary: a few units of 2^-9 relative on some h
+    assert np.abs(got - want).max() <= 5e-3
+    assert np.mean(np.abs(got - want)) <= 2e-4
