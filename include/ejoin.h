@@ -89,6 +89,11 @@ typedef struct {
                                  failed on the device: -EJOIN_E_WORKSPACE (band list too
                                  small), -EJOIN_E_NONFINITE, -EJOIN_E_RANGE */
 #define EJOIN_TIMING    0x2u  /* record per-phase times in ejoin_stats (adds event syncs) */
+#define EJOIN_APPROX_PREFILTER 0x4u  /* ejoin_batch: skip the 128 x 128 tile pairs that the
+                                        learned prefilter (opts->prefilter) bounds below
+                                        theta - opts->prefilter_eps.  Approximate: the result
+                                        of each job is a SUBSET of its exact join (every pair
+                                        returned is exact); see ejoin_batch. */
 
 /* Autotuned tile choices (opaque; see ejoin_tuner_create). */
 typedef struct ejoin_tuner ejoin_tuner;
@@ -102,6 +107,9 @@ typedef struct {
     uint32_t flags;         /* EJOIN_* flags */
     int32_t topk_cand;      /* top-k: per-row candidate capacity (<= 0: default) */
     const ejoin_tuner *tuner; /* (host, may be NULL) consulted when tile == 0 */
+    const void *prefilter;  /* EJOIN_APPROX_PREFILTER: device state block of a prefilter
+                               network (ejoin_mlp_*) for the jobs' dim */
+    float prefilter_eps;    /* EJOIN_APPROX_PREFILTER: margin below theta */
 } ejoin_opts;
 
 /* Optional per-call report (host struct, may be NULL). */
@@ -118,6 +126,8 @@ typedef struct {
     float ms_prep, ms_main, ms_rescore, ms_total;  /* with EJOIN_TIMING */
     double topk_floor;      /* top-k: candidate floor used by the sweep */
     int32_t topk_slots;     /* top-k: candidate slots per row */
+    int64_t tiles_total;    /* batch: tile pairs of all jobs */
+    int64_t tiles_kept;     /* batch: tile pairs contracted (all of them unless prefiltered) */
 } ejoin_stats;
 
 /* Library version string (static storage). */
@@ -221,6 +231,13 @@ size_t ejoin_batch_workspace(const ejoin_job *jobs, int32_t n_jobs, const ejoin_
  *   n_out         (host) int64[n_jobs] receives each job's true match count;
  *                 with EJOIN_NO_SYNC a DEVICE int64[n_jobs] (negative status
  *                 codes as for EJOIN_NO_SYNC above).
+ * With EJOIN_APPROX_PREFILTER (BF16, tile 3 or 0, every job of the same dim
+ * as the network, eager calls only): the prepared rows are coded by the
+ * network, each relation is reordered by the codes' sign pattern against the
+ * network's 16 hyperplanes, and only the 128 x 128 tile pairs whose bound
+ *     c_T . c_U + rho_T |c_U| + rho_U |c_T| + rho_T rho_U >= theta - eps
+ * (c: mean code of a tile, rho: largest distance of a code from c) are
+ * contracted; pairs are mapped back to the caller's row numbers.
  * Returns EJOIN_E_OVERFLOW if any job matched more pairs than its capacity
  * (that job's `out` holds an arbitrary capacity-sized subset; re-run it with
  * more room), EJOIN_E_WORKSPACE if the shared band list was too small
@@ -350,6 +367,33 @@ size_t ejoin_mlp_forward_workspace(int32_t dim, int64_t n);
  */
 ejoin_status ejoin_mlp_forward(const void *state, int32_t dim, const uint16_t *X, int64_t n,
                                float *U, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Training of the prefilter on the caller's batch: pairs are drawn from the
+ * exact join's outputs (share pos_frac) and uniformly from R x S of the
+ * jobs (job chosen in proportion to |R| |S|), their targets are their sim64
+ * (the canonical FP64 rule, on the GPU), their rows are prepared exactly as
+ * the BF16 join prepares operands, and `steps` training steps of `batch`
+ * pairs are taken.  Draws use SplitMix64 seeded with `seed`. */
+typedef struct {
+    int32_t steps;          /* default 300 */
+    int32_t batch;          /* pairs per step, default 4096 */
+    uint64_t seed;          /* default 1 */
+    float pos_frac;         /* default 0.5 */
+    ejoin_mlp_hparams hp;   /* defaults of ejoin_mlp_hparams_default */
+} ejoin_prefilter_train_opts;
+
+void ejoin_prefilter_train_opts_default(ejoin_prefilter_train_opts *to /* host */);
+size_t ejoin_prefilter_train_workspace(int32_t n_jobs, int32_t dim, int32_t batch);
+
+/*
+ * jobs: the batch whose exact join was run (jobs[i].out holds n_out[i]
+ * pairs, n_out host int64[n_jobs]; only min(n_out[i], capacity) are drawn
+ * from); all jobs of the network's dim.  losses (host, may be NULL)
+ * receives the loss of every step (this synchronises once per step).
+ */
+ejoin_status ejoin_prefilter_train(void *state, const ejoin_job *jobs, int32_t n_jobs,
+                                   const int64_t *n_out, const ejoin_prefilter_train_opts *to,
+                                   void *ws, size_t ws_bytes, float *losses, hipStream_t stream);
 
 /* Number of tile shapes the library was built with, and the name of one
  * ("prec:BMxBNxBK"); id 0 is "planner's choice".  Static storage. */

@@ -31,7 +31,7 @@ PER_FILE = {
     "panel.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"],
 }
 SOURCES = ["prep.hip", "gemm_threshold.hip", "panel.hip", "rescore.hip", "topk.hip", "batch.hip",
-           "mlp.hip", "api.cpp", "api_batch.cpp", "api_mlp.cpp", "tune.cpp"]
+           "mlp.hip", "prefilter.hip", "api.cpp", "api_batch.cpp", "api_mlp.cpp", "tune.cpp"]
 
 
 def _compile(src: str, verbose: bool) -> str:

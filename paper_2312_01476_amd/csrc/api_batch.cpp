@@ -6,7 +6,9 @@
 #include <vector>
 
 #include "batch.hpp"
+#include "mlp.hpp"
 #include "plan.hpp"
+#include "prefilter.hpp"
 
 using namespace ej;
 using namespace ej::plan;
@@ -31,6 +33,10 @@ struct BatchPlan {
     double band_max = 0.0;
     int64_t band_cap = 0, n_tiles = 0, n_rows = 0, pairs_total = 0;
     size_t off_table = 0, table_bytes = 0, off_hdrs = 0, off_band = 0, total = 0;
+    // prefilter mode
+    bool approx = false;
+    size_t off_hb = 0, off_z = 0, off_u = 0, off_key = 0, off_pa = 0, off_pb = 0, off_hist = 0,
+           off_offs = 0, off_c = 0, off_rho = 0, off_cn = 0, off_work = 0;
     std::vector<char> image;  // head, jobs[table_jobs], segs[2 * table_jobs]
     BatchHead* head() { return (BatchHead*)image.data(); }
     BatchJob* jobs() { return (BatchJob*)(image.data() + sizeof(BatchHead)); }
@@ -45,6 +51,7 @@ size_t table_size(int table_jobs) {
 
 int pick_batch_tile(const ejoin_opts& o, const ejoin_job* jobs, int n) {
     if (o.tile > 0) return o.tile;
+    if (o.flags & EJOIN_APPROX_PREFILTER) return 3;  // 128 x 128 tiles: the statistics' grain
     if (o.tuner && n > 0) {
         double pairs = 0.0;
         int dim = jobs[0].R.dim;
@@ -62,6 +69,15 @@ int pick_batch_tile(const ejoin_opts& o, const ejoin_job* jobs, int n) {
 ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, int tile,
                              int table_jobs, char* ws, int64_t* n_out_dev, BatchPlan& bp) {
     if (n < 0 || n > 65536 || (n > 0 && !jobs) || table_jobs < n) return EJOIN_E_INVAL;
+    bp.approx = (o.flags & EJOIN_APPROX_PREFILTER) != 0;
+    if (bp.approx) {
+        // the network reads BF16 prepared rows; tile statistics are per 128 rows
+        if (o.prec != EJOIN_BF16 || !o.prefilter || !(o.prefilter_eps >= 0.0f)) return EJOIN_E_INVAL;
+        if (tile != 3) return EJOIN_E_INVAL;
+        for (int i = 1; i < n; ++i)
+            if (jobs && jobs[i].R.dim != jobs[0].R.dim) return EJOIN_E_INVAL;
+        if (n > 0 && jobs && (jobs[0].R.dim < 1 || jobs[0].R.dim > 1024)) return EJOIN_E_UNSUPPORTED;
+    }
     if (o.prec < EJOIN_FP32 || o.prec > EJOIN_FP8_E4M3) return EJOIN_E_INVAL;
     const TileDesc* td = tile_get(tile);
     if (!td || td->prec != o.prec || !batch_has_tile(tile)) return EJOIN_E_INVAL;
@@ -101,6 +117,7 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
     PrepSeg* G = bp.segs();
     int nseg = 0;
     int64_t tile_base = 0, row_base = 0, band_default = 0;
+    std::vector<int64_t> rb_r(n, 0), rb_s(n, 0);
     auto at = [&](size_t o_) -> char* { return ws ? ws + o_ : nullptr; };
     for (int q = 0; q < n; ++q) {
         const ejoin_job& u = jobs[order[q]];
@@ -172,11 +189,40 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
             g.Kp = Kp;
             row_base += pad;
         };
+        rb_r[q] = row_base;
         seg(u.R, o_xr, o_ir, padR);
+        rb_s[q] = alias ? rb_r[q] : row_base;
         if (!alias) seg(u.S, o_xs, o_is, padS);
     }
     bp.n_tiles = tile_base;
     bp.n_rows = row_base;
+    if (bp.approx) {
+        const size_t nr = (size_t)bp.n_rows;
+        auto take = [&](size_t bytes) {
+            const size_t at_ = off;
+            off = align256(off + bytes);
+            return at_;
+        };
+        bp.off_hb = take(nr * MLP_HIDDEN * 2);
+        bp.off_z = take(nr * MLP_OUT * 4);
+        bp.off_u = take(nr * MLP_OUT * 4);
+        bp.off_key = take(nr * 4);
+        bp.off_pa = take(nr * 4);
+        bp.off_pb = take(nr * 4);
+        bp.off_hist = take(nr / 256 * 64 * 4);
+        bp.off_offs = take(nr / 256 * 64 * 4);
+        bp.off_c = take(nr / 128 * MLP_OUT * 4);
+        bp.off_rho = take(nr / 128 * 4);
+        bp.off_cn = take(nr / 128 * 4);
+        bp.off_work = take((size_t)bp.n_tiles * 8);
+        for (int q = 0; q < n; ++q) {
+            J[q].perm_r = (const int32_t*)at(bp.off_pa + (size_t)rb_r[q] * 4);
+            J[q].perm_s = (const int32_t*)at(bp.off_pa + (size_t)rb_s[q] * 4);
+            J[q].rtile0 = rb_r[q] / 128;
+            J[q].stile0 = rb_s[q] / 128;
+        }
+        for (int i = 0; i < nseg; ++i) G[i].perm = (const int32_t*)at(bp.off_pa + (size_t)G[i].row_base * 4);
+    }
     bp.band_cap = o.band_capacity > 0 ? o.band_capacity : std::max<int64_t>(65536, band_default);
     bp.off_band = off;
     off = align256(off + (size_t)bp.band_cap * sizeof(int4));
@@ -191,6 +237,10 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
     h->hdrs = (unsigned long long*)at(bp.off_hdrs);
     h->n_jobs = n;
     h->n_segs = nseg;
+    if (bp.approx) {
+        h->work = (const int64_t*)at(bp.off_work);
+        h->n_work = (const unsigned long long*)at(B_WORK * sizeof(unsigned long long));
+    }
     return EJOIN_OK;
 }
 
@@ -217,7 +267,7 @@ hipError_t launch_pass(const BatchPlan& bp, char* ws, int tile_grid, bool fixed,
     if ((e = launch_batch_zero(head, bctr, st)) != hipSuccess) return e;
     int pg = kPrepGrid;
     if (!fixed) pg = (int)std::max<int64_t>(1, std::min<int64_t>(kPrepGrid, (bp.n_rows + 3) / 4));
-    if ((e = launch_batch_prep(bp.prec, head, segs, pg, st)) != hipSuccess) return e;
+    if ((e = launch_batch_prep(bp.prec, head, segs, pg, false, st)) != hipSuccess) return e;
     if ((e = rec(1)) != hipSuccess) return e;
     int tg = tile_grid;
     if (!fixed) tg = (int)std::max<int64_t>(1, std::min<int64_t>(tile_grid, bp.n_tiles));
@@ -225,6 +275,65 @@ hipError_t launch_pass(const BatchPlan& bp, char* ws, int tile_grid, bool fixed,
     if ((e = rec(2)) != hipSuccess) return e;
     int rg = kRescoreGrid;
     if (!fixed) rg = (int)std::max<int64_t>(1, std::min<int64_t>(kRescoreGrid, (bp.band_cap + 255) / 256));
+    if ((e = launch_batch_rescore(head, jobs, bctr, rg, st)) != hipSuccess) return e;
+    if ((e = rec(3)) != hipSuccess) return e;
+    return launch_batch_counts(head, jobs, bctr, st);
+}
+
+// The prefiltered pass: prep in input order, codes and keys, per-relation
+// order, prep again in that order, tile statistics and bounds (work list),
+// persistent tiles over the work list, rescore, counts.
+hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, const ejoin_opts& o,
+                              hipStream_t st, hipEvent_t* ev) {
+    const BatchHead* head = (const BatchHead*)(ws + bp.off_table);
+    const BatchJob* jobs = (const BatchJob*)(ws + bp.off_table + sizeof(BatchHead));
+    const PrepSeg* segs = (const PrepSeg*)(ws + bp.off_table + sizeof(BatchHead) +
+                                           (size_t)bp.table_jobs * sizeof(BatchJob));
+    unsigned long long* bctr = (unsigned long long*)ws;
+    const int n_segs = ((const BatchHead*)bp.image.data())->n_segs;
+    hipError_t e;
+    auto rec = [&](int i) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
+    ejoin_mlp_layout L;
+    if (ejoin_mlp_layout_get(bp.n_jobs ? ((const BatchJob*)(bp.image.data() + sizeof(BatchHead)))[0].dim : 1,
+                             &L) != EJOIN_OK)
+        return hipErrorInvalidValue;
+    MlpDev m;
+    {
+        char* b = (char*)o.prefilter;
+        m.dim = L.dim;
+        m.Dp = L.dim_pad;
+        m.np = L.n_params;
+        m.P = (float*)(b + L.off_params);
+        m.W1t = (uint16_t*)(b + L.off_w1t);
+        m.W2t = (uint16_t*)(b + L.off_w2t);
+        m.planes = (float*)(b + L.off_planes);
+    }
+    const int pg = (int)std::max<int64_t>(1, std::min<int64_t>(kPrepGrid, (bp.n_rows + 3) / 4));
+    if ((e = rec(0)) != hipSuccess) return e;
+    if ((e = launch_batch_zero(head, bctr, st)) != hipSuccess) return e;
+    if ((e = launch_batch_prep(bp.prec, head, segs, pg, false, st)) != hipSuccess) return e;
+    int32_t* perm_a = (int32_t*)(ws + bp.off_pa);
+    if ((e = launch_pf_codes(head, segs, bp.n_rows, m, (uint16_t*)(ws + bp.off_hb),
+                             (float*)(ws + bp.off_z), (float*)(ws + bp.off_u),
+                             (int32_t*)(ws + bp.off_key), st)) != hipSuccess)
+        return e;
+    if ((e = launch_pf_sort(head, segs, n_segs, bp.n_rows, (const int32_t*)(ws + bp.off_key),
+                            perm_a, (int32_t*)(ws + bp.off_pb), (int32_t*)(ws + bp.off_hist),
+                            (int32_t*)(ws + bp.off_offs), st)) != hipSuccess)
+        return e;
+    if ((e = launch_batch_prep(bp.prec, head, segs, pg, true, st)) != hipSuccess) return e;
+    if ((e = launch_pf_tiles(head, segs, jobs, bp.n_rows, (const float*)(ws + bp.off_u), perm_a,
+                             (float*)(ws + bp.off_c), (float*)(ws + bp.off_rho),
+                             (float*)(ws + bp.off_cn), o.prefilter_eps,
+                             (int64_t*)(ws + bp.off_work), bctr + B_WORK, bp.n_tiles, st)) !=
+        hipSuccess)
+        return e;
+    if ((e = rec(1)) != hipSuccess) return e;
+    const int tg = (int)std::max<int64_t>(1, std::min<int64_t>(tile_grid, bp.n_tiles));
+    if ((e = launch_batch_tile(bp.tile, head, jobs, bctr, tg, st)) != hipSuccess) return e;
+    if ((e = rec(2)) != hipSuccess) return e;
+    const int rg =
+        (int)std::max<int64_t>(1, std::min<int64_t>(kRescoreGrid, (bp.band_cap + 255) / 256));
     if ((e = launch_batch_rescore(head, jobs, bctr, rg, st)) != hipSuccess) return e;
     if ((e = rec(3)) != hipSuccess) return e;
     return launch_batch_counts(head, jobs, bctr, st);
@@ -288,7 +397,10 @@ ejoin_status ejoin_batch(const ejoin_job* jobs, int32_t n_jobs, const ejoin_opts
         for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
     const int grid = cu_count() * occ;
     if (grid <= 0) return EJOIN_E_HIP;
-    HIP_TRY(launch_pass(bp, w, grid, false, stream, timing ? ev : nullptr));
+    if (bp.approx)
+        HIP_TRY(launch_pass_approx(bp, w, grid, o, stream, timing ? ev : nullptr));
+    else
+        HIP_TRY(launch_pass(bp, w, grid, false, stream, timing ? ev : nullptr));
     if (!sync) return EJOIN_OK;
 
     std::vector<unsigned long long> h((size_t)(n_jobs + 1) * H_COUNT);
@@ -320,6 +432,8 @@ ejoin_status ejoin_batch(const ejoin_job* jobs, int32_t n_jobs, const ejoin_opts
         acc += (int64_t)hj[H_BAND_ACC];
     }
     if (stats) {
+        stats->tiles_total = bp.n_tiles;
+        stats->tiles_kept = bp.approx ? (int64_t)h[B_WORK] : bp.n_tiles;
         stats->n_pairs = total;
         stats->n_band = (int64_t)band_found;
         stats->n_band_accepted = acc;
@@ -341,6 +455,7 @@ ejoin_status ejoin_batch_graph_create(int32_t max_jobs, const ejoin_opts* opts, 
     ejoin_opts o = opts_or_default(opts);
     o.flags |= EJOIN_NO_SYNC;
     if (o.prec < EJOIN_FP32 || o.prec > EJOIN_FP8_E4M3) return EJOIN_E_INVAL;
+    if (o.flags & EJOIN_APPROX_PREFILTER) return EJOIN_E_UNSUPPORTED;
     const int tile = o.tile > 0 ? o.tile : batch_default_tile(o.prec);
     const TileDesc* td = tile_get(tile);
     if (!td || td->prec != o.prec || !batch_has_tile(tile)) return EJOIN_E_INVAL;

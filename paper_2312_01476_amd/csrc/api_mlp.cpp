@@ -2,6 +2,9 @@
 // training step and inference.
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
+#include "batch.hpp"
 #include "mlp.hpp"
 #include "plan.hpp"
 
@@ -66,9 +69,172 @@ size_t fwd_ws(int64_t n) {
     return align256(rows * MLP_HIDDEN * 2) + align256(rows * MLP_OUT * 4);
 }
 
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", 2014): a 64-bit counter advanced by the golden-ratio
+// increment, then a variant of the MurmurHash3 finaliser.
+struct SplitMix64 {
+    uint64_t x;
+    uint64_t next() {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    // uniform in [0, n) (n >= 1), by the high product (bias < n / 2^64)
+    uint64_t below(uint64_t n) { return (uint64_t)(((unsigned __int128)next() * n) >> 64); }
+    double unit() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }
+};
+
+struct TrainWs {
+    size_t jobs, samples, pool, info, hdr, idx, targets, loss, mlp, total;
+};
+
+TrainWs train_layout(int n_jobs, int dim_pad, int batch) {
+    TrainWs t;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        const size_t a = off;
+        off = align256(off + b);
+        return a;
+    };
+    t.jobs = take((size_t)n_jobs * sizeof(TrainJob));
+    t.samples = take((size_t)batch * 16);
+    t.pool = take(2 * (size_t)batch * dim_pad * 2);
+    t.info = take(2 * (size_t)batch * sizeof(RowInfo));
+    t.hdr = take(H_COUNT * 8);
+    t.idx = take(2 * (size_t)batch * 4);
+    t.targets = take((size_t)batch * 4);
+    t.loss = take(4);
+    t.mlp = take(train_ws(dim_pad, batch));
+    t.total = off;
+    return t;
+}
+
 }  // namespace
 
 extern "C" {
+
+void ejoin_prefilter_train_opts_default(ejoin_prefilter_train_opts* to) {
+    if (!to) return;
+    to->steps = 300;
+    to->batch = 4096;
+    to->seed = 1;
+    to->pos_frac = 0.5f;
+    ejoin_mlp_hparams_default(&to->hp);
+}
+
+size_t ejoin_prefilter_train_workspace(int32_t n_jobs, int32_t dim, int32_t batch) {
+    ejoin_mlp_layout L;
+    if (n_jobs < 1 || !layout_of(dim, L) || batch < 1 || batch > (1 << 20)) return 0;
+    return train_layout(n_jobs, L.dim_pad, batch).total;
+}
+
+ejoin_status ejoin_prefilter_train(void* state, const ejoin_job* jobs, int32_t n_jobs,
+                                   const int64_t* n_out, const ejoin_prefilter_train_opts* to_,
+                                   void* ws, size_t ws_bytes, float* losses, hipStream_t stream) {
+    ejoin_prefilter_train_opts to;
+    ejoin_prefilter_train_opts_default(&to);
+    if (to_) to = *to_;
+    if (!state || !jobs || n_jobs < 1 || !n_out || to.steps < 0 || to.batch < 1 ||
+        to.batch > (1 << 20) || !(to.pos_frac >= 0.0f && to.pos_frac <= 1.0f))
+        return EJOIN_E_INVAL;
+    const int dim = jobs[0].R.dim;
+    ejoin_mlp_layout L;
+    if (!layout_of(dim, L)) return EJOIN_E_UNSUPPORTED;
+    std::vector<TrainJob> tj(n_jobs);
+    std::vector<double> cum_pos(n_jobs), cum_all(n_jobs);
+    double tp = 0.0, ta = 0.0;
+    for (int i = 0; i < n_jobs; ++i) {
+        const ejoin_job& j = jobs[i];
+        if (!rel_ok(&j.R) || !rel_ok(&j.S) || j.R.dim != dim || j.S.dim != dim || n_out[i] < 0)
+            return EJOIN_E_INVAL;
+        const int64_t np = std::min(n_out[i], j.capacity);
+        if (np > 0 && !j.out) return EJOIN_E_INVAL;
+        tj[i] = TrainJob{j.R.data, j.S.data, (const Pair*)j.out, j.R.ld, j.S.ld, j.R.rows,
+                         j.S.rows, dim, 0};
+        tp += (double)np;
+        ta += (double)j.R.rows * (double)j.S.rows;
+        cum_pos[i] = tp;
+        cum_all[i] = ta;
+    }
+    if (ta <= 0.0) return EJOIN_E_INVAL;
+    const int B = to.batch;
+    const TrainWs lay = train_layout(n_jobs, L.dim_pad, B);
+    if (!ws || ws_bytes < lay.total) return EJOIN_E_WORKSPACE;
+    char* w = (char*)ws;
+    HIP_TRY(hipMemcpyAsync(w + lay.jobs, tj.data(), tj.size() * sizeof(TrainJob),
+                           hipMemcpyHostToDevice, stream));
+    {
+        std::vector<int32_t> idx(2 * (size_t)B);
+        for (int i = 0; i < 2 * B; ++i) idx[i] = i;
+        HIP_TRY(hipMemcpyAsync(w + lay.idx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice,
+                               stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+    }
+    MlpDev m = dev_of(state, L);
+    ejoin_mlp_hparams& h = to.hp;
+    MlpHyper hy{h.lr, h.beta1, h.beta2, h.eps, h.lambda, h.theta_lo,
+                (h.flags & EJOIN_MLP_GRAD_ONLY) != 0};
+    const size_t r2 = 2 * (size_t)B;
+    MlpTrainWs t;
+    {
+        char* b = w + lay.mlp;
+        t.Xb = (float*)b;
+        b += align256(r2 * L.dim_pad * 4);
+        t.A1 = (float*)b;
+        b += align256(r2 * MLP_HIDDEN * 4);
+        t.dA1 = (float*)b;
+        b += align256(r2 * MLP_HIDDEN * 4);
+        t.Z = (float*)b;
+        b += align256(r2 * MLP_OUT * 4);
+        t.dZ = (float*)b;
+    }
+    SplitMix64 rng{to.seed};
+    std::vector<int32_t> smp(4 * (size_t)B);
+    auto pick = [&](const std::vector<double>& cum, double tot) {
+        const double u = rng.unit() * tot;
+        return (int)(std::upper_bound(cum.begin(), cum.end(), u) - cum.begin());
+    };
+    for (int step = 0; step < to.steps; ++step) {
+        for (int i = 0; i < B; ++i) {
+            int32_t* e = &smp[4 * (size_t)i];
+            if (tp > 0.0 && rng.unit() < to.pos_frac) {
+                const int j = std::min(pick(cum_pos, tp), n_jobs - 1);
+                const int64_t np = std::min(n_out[j], jobs[j].capacity);
+                e[0] = j;
+                e[1] = 1;
+                e[2] = (int32_t)rng.below((uint64_t)np);
+                e[3] = 0;
+            } else {
+                const int j = std::min(pick(cum_all, ta), n_jobs - 1);
+                e[0] = j;
+                e[1] = 0;
+                e[2] = (int32_t)rng.below((uint64_t)jobs[j].R.rows);
+                e[3] = (int32_t)rng.below((uint64_t)jobs[j].S.rows);
+            }
+        }
+        // the previous step has consumed the sample buffer once the stream
+        // is idle; a synchronous copy keeps the host array reusable at once
+        HIP_TRY(hipStreamSynchronize(stream));
+        HIP_TRY(hipMemcpy(w + lay.samples, smp.data(), smp.size() * 4, hipMemcpyHostToDevice));
+        const TrainJob* dj = (const TrainJob*)(w + lay.jobs);
+        const int4* ds = (const int4*)(w + lay.samples);
+        HIP_TRY(launch_train_rows(dj, ds, B, L.dim_pad, (uint16_t*)(w + lay.pool),
+                                  (RowInfo*)(w + lay.info), (unsigned long long*)(w + lay.hdr),
+                                  stream));
+        HIP_TRY(launch_train_targets(dj, ds, B, (float*)(w + lay.targets), stream));
+        const int32_t* idx = (const int32_t*)(w + lay.idx);
+        HIP_TRY(launch_mlp_train_step(m, (const uint16_t*)(w + lay.pool), L.dim_pad, 2 * B, idx,
+                                      idx + B, (const float*)(w + lay.targets), B, hy, t,
+                                      (float*)(w + lay.loss), stream));
+        if (losses) {
+            HIP_TRY(hipMemcpyAsync(&losses[step], w + lay.loss, 4, hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    return EJOIN_OK;
+}
 
 ejoin_status ejoin_mlp_layout_get(int32_t dim, ejoin_mlp_layout* layout) {
     if (!layout) return EJOIN_E_INVAL;

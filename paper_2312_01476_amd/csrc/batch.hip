@@ -25,39 +25,54 @@ __global__ __launch_bounds__(WM* WN * 64) void batch_tile(const BatchHead* __res
     __shared__ TileSmem<BM, BN, WM * WN> sm;
     __shared__ int64_t s_item;
     __shared__ int s_job;
-    const int64_t total = head->n_tiles;
+    // dense mode: every tile of every job; prefilter mode: the work list
+    const int64_t* work = head->work;
+    const int64_t total = work ? (int64_t)*head->n_work : head->n_tiles;
     const int n_jobs = head->n_jobs;
     int4* band = head->band;
     const int64_t band_cap = head->band_cap;
+    __shared__ int s_tm, s_tn;
     for (;;) {
         if (threadIdx.x == 0) {
             const int64_t item = (int64_t)atomicAdd(bctr + B_ITEM, 1ull);
-            int job = 0;
+            int job = 0, tm = 0, tn = 0;
             if (item < total) {
-                // last job whose first item is <= item
-                int lo = 0, hi = n_jobs - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (jobs[mid].tile_base <= item) lo = mid;
-                    else hi = mid - 1;
+                if (work) {
+                    const int64_t w = work[item];
+                    job = (int)(w >> 48);
+                    tm = (int)((w >> 24) & 0xFFFFFF);
+                    tn = (int)(w & 0xFFFFFF);
+                } else {
+                    // last job whose first item is <= item
+                    int lo = 0, hi = n_jobs - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (jobs[mid].tile_base <= item) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    job = lo;
+                    raster_tile((int)(item - jobs[lo].tile_base), jobs[lo].tiles_m,
+                                jobs[lo].tiles_n, tm, tn);
                 }
-                job = lo;
             }
             s_item = item;
             s_job = job;
+            s_tm = tm;
+            s_tn = tn;
         }
         __syncthreads();
         const int64_t item = s_item;
         const int job = __builtin_amdgcn_readfirstlane(s_job);
-        __syncthreads();  // s_item / s_job are rewritten by the next iteration
+        const int tm = __builtin_amdgcn_readfirstlane(s_tm);
+        const int tn = __builtin_amdgcn_readfirstlane(s_tn);
+        __syncthreads();  // the shared slots are rewritten by the next iteration
         if (item >= total) break;
         const BatchJob& J = jobs[job];
         if (J.hdr[H_FLAGS] != 0) continue;  // bad input rows in this job
-        int tm, tn;
-        raster_tile((int)(item - J.tile_base), J.tiles_m, J.tiles_n, tm, tn);
         tile_body<PREC, BM, BN, WM, WN, true>(sm, J.A, J.B, J.info_r, J.info_s, J.Kp_bytes, J.nR,
                                               J.nS, tm, tn, J.lo, J.hi, J.out, J.capacity,
-                                              J.hdr + H_OUT, band, band_cap, bctr + B_BAND, job);
+                                              J.hdr + H_OUT, band, band_cap, bctr + B_BAND, job,
+                                              J.perm_r, J.perm_s);
     }
 }
 

@@ -35,6 +35,12 @@ struct BatchJob {
     int32_t Kp_bytes, dim;
     int32_t user;              // index of the job in the caller's array
     int32_t pad_;
+    // prefilter mode: the prepared rows are in code order; perm maps a
+    // prepared row back to the caller's row, rtile0 / stile0 are the flat
+    // indices of the first 128-row tiles of R and S
+    const int32_t* perm_r;
+    const int32_t* perm_s;
+    int64_t rtile0, stile0;
 };
 
 // One relation to prepare (R or S of a job; an aliased self-join has one).
@@ -43,6 +49,7 @@ struct PrepSeg {
     void* Xq;
     RowInfo* info;
     unsigned long long* hdr;   // flags go to the owning job's counters
+    const int32_t* perm;       // prefilter ordering: prepared row r is input row perm[r] (or null)
     int64_t rows, rows_pad, ld;
     int64_t row_base;          // first flat prep row of this segment
     int32_t dim, Kp;
@@ -57,13 +64,29 @@ struct BatchHead {
     unsigned long long* hdrs;  // n_jobs x H_COUNT counters, contiguous
     int32_t n_jobs, n_segs;
     int32_t pad_[2];
+    // prefilter mode: the surviving (job, tm, tn) work items, packed as
+    // job << 48 | tm << 24 | tn, and their count (null in the plain mode)
+    const int64_t* work;
+    const unsigned long long* n_work;
 };
 
 // Global counters of a batch pass.
 enum : int {
     B_ITEM = 0,     // next work item of the persistent kernel
     B_BAND = 1,     // band entries found (may exceed band_cap)
+    B_WORK = 2,     // prefilter: surviving tile pairs
     B_COUNT = 32
+};
+
+// Prefilter training: the relations and exact outputs of one job, and one
+// drawn pair {job, kind, a, b}: kind 1 is output pair a of the job, kind 0
+// the pair (row a of R, row b of S).
+struct TrainJob {
+    const float* R;
+    const float* S;
+    const Pair* out;
+    int64_t ldR, ldS, nR, nS;
+    int32_t dim, pad_;
 };
 
 // Table image: head, then jobs[max_jobs], then segs[2 * max_jobs].

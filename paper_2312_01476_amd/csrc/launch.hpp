@@ -115,11 +115,19 @@ bool batch_has_tile(int tile_id);  // the tile has a persistent batch form
 int batch_occupancy(int tile_id);  // resident workgroups per CU, 0: no batch form
 hipError_t launch_batch_zero(const BatchHead* head, unsigned long long* bctr, hipStream_t st);
 hipError_t launch_batch_prep(int prec, const BatchHead* head, const PrepSeg* segs, int grid,
-                             hipStream_t st);
+                             bool ordered, hipStream_t st);
 hipError_t launch_batch_tile(int tile_id, const BatchHead* head, const BatchJob* jobs,
                              unsigned long long* bctr, int grid, hipStream_t st);
 hipError_t launch_batch_rescore(const BatchHead* head, const BatchJob* jobs,
                                 const unsigned long long* bctr, int grid, hipStream_t st);
 hipError_t launch_batch_counts(const BatchHead* head, const BatchJob* jobs,
                                const unsigned long long* bctr, hipStream_t st);
+
+// prefilter training data
+struct TrainJob;
+hipError_t launch_train_rows(const TrainJob* jobs, const int4* samples, int B, int Dp,
+                             uint16_t* pool, RowInfo* info, unsigned long long* hdr,
+                             hipStream_t st);
+hipError_t launch_train_targets(const TrainJob* jobs, const int4* samples, int B, float* t,
+                                hipStream_t st);
 }  // namespace ej

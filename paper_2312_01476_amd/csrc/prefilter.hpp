@@ -1,0 +1,33 @@
+// prefilter.hpp -- launch wrappers of the approximate (prefiltered) batch
+// mode (prefilter.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mlp.hpp"
+
+namespace ej {
+
+struct BatchHead;
+struct BatchJob;
+struct PrepSeg;
+
+constexpr int32_t PF_PAD_KEY = 1 << 16;  // ordering key of padding rows (sorts last)
+
+// codes U (flat rows x 64) and ordering keys of every prepared row
+hipError_t launch_pf_codes(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
+                           const MlpDev& m, uint16_t* Hb, float* Z, float* U, int32_t* key,
+                           hipStream_t st);
+// stable order of every relation's rows by key: perm_a[row_base + i] is the
+// local row at ordered position i
+hipError_t launch_pf_sort(const BatchHead* head, const PrepSeg* segs, int n_segs, int64_t n_rows,
+                          const int32_t* key, int32_t* perm_a, int32_t* perm_b, int32_t* hist,
+                          int32_t* offs, hipStream_t st);
+// 128-row tile statistics of the ordered rows and the surviving tile pairs
+hipError_t launch_pf_tiles(const BatchHead* head, const PrepSeg* segs, const BatchJob* jobs,
+                           int64_t n_rows, const float* U, const int32_t* perm, float* C,
+                           float* rho, float* cnorm, float eps, int64_t* work,
+                           unsigned long long* n_work, int64_t n_tiles, hipStream_t st);
+
+}  // namespace ej

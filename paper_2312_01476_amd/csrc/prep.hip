@@ -14,18 +14,19 @@
 
 namespace ej {
 
-// Prepare row `row` (one wave; rows >= rows are tile padding, written as
-// zeros).  Returns the row's quantisation error norm (0 for FP32).
+// Prepare input row `src` into output row `row` (one wave; src >= rows is
+// tile padding, written as zeros).  Returns the row's quantisation error
+// norm (0 for FP32).
 template <int PREC>
 __device__ __forceinline__ float prep_one_row(const float* __restrict__ X, int64_t rows, int dim,
                                               int64_t ld, void* __restrict__ Xq, int Kp,
                                               RowInfo* __restrict__ info,
                                               unsigned long long* __restrict__ hdr, int64_t row,
-                                              int lane) {
+                                              int64_t src, int lane) {
     float inv = 0.0f, qscale = 1.0f, enorm = 0.0f;
     uint32_t flags = 0;
-    const float* x = X + row * ld;
-    const bool real = row < rows;
+    const float* x = X + src * ld;
+    const bool real = src < rows;
 
     if (real) {
         // pass 1: finiteness and max |x|
@@ -133,12 +134,12 @@ __device__ __forceinline__ float prep_row_reg(const float* __restrict__ X, int64
                                               int64_t ld, void* __restrict__ Xq, int Kp,
                                               RowInfo* __restrict__ info,
                                               unsigned long long* __restrict__ hdr, int64_t row,
-                                              int lane) {
+                                              int64_t src, int lane) {
     constexpr int NV = kRegMax / 64;
     float inv = 0.0f, qscale = 1.0f, enorm = 0.0f;
     uint32_t flags = 0;
-    const float* x = X + row * ld;
-    const bool real = row < rows;
+    const float* x = X + src * ld;
+    const bool real = src < rows;
     float xv[NV];
     float amax = 0.0f;
     bool bad = false;
@@ -235,10 +236,10 @@ __device__ __forceinline__ float prep_row(const float* __restrict__ X, int64_t r
                                           int64_t ld, void* __restrict__ Xq, int Kp,
                                           RowInfo* __restrict__ info,
                                           unsigned long long* __restrict__ hdr, int64_t row,
-                                          int lane) {
+                                          int64_t src, int lane) {
     if (Kp <= kRegMax)
-        return prep_row_reg<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr, row, lane);
-    return prep_one_row<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr, row, lane);
+        return prep_row_reg<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr, row, src, lane);
+    return prep_one_row<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr, row, src, lane);
 }
 
 // One wave per row, grid-stride.
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
     for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < rows_pad;
          row += (int64_t)gridDim.x * 4)
         wave_emax = fmaxf(wave_emax,
-                          prep_row<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr, row, lane));
+                          prep_row<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr, row, row, lane));
     // one atomic per workgroup for the maximum error norm
     __shared__ float s_emax[4];
     if (lane == 0) s_emax[threadIdx.x >> 6] = wave_emax;
@@ -271,7 +272,8 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
 // not collected here.
 template <int PREC>
 __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ head,
-                                                  const PrepSeg* __restrict__ segs) {
+                                                  const PrepSeg* __restrict__ segs,
+                                                  bool ordered) {
     const int lane = threadIdx.x & 63;
     const int64_t n = head->n_rows;
     const int nseg = head->n_segs;
@@ -284,19 +286,54 @@ __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ 
             else hi = mid - 1;
         }
         const PrepSeg& g = segs[lo];
-        prep_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, row - g.row_base,
-                       lane);
+        const int64_t r = row - g.row_base;
+        // with an ordering, output row r holds input row perm[r]
+        const int64_t src = (ordered && g.perm) ? (int64_t)g.perm[r] : r;
+        prep_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, r, src, lane);
     }
 }
 
 hipError_t launch_batch_prep(int prec, const BatchHead* head, const PrepSeg* segs, int grid,
-                             hipStream_t st) {
+                             bool ordered, hipStream_t st) {
     dim3 g((unsigned)grid), b(256);
     switch (prec) {
-        case P_FP32: hipLaunchKernelGGL(batch_prep<P_FP32>, g, b, 0, st, head, segs); break;
-        case P_BF16: hipLaunchKernelGGL(batch_prep<P_BF16>, g, b, 0, st, head, segs); break;
-        default: hipLaunchKernelGGL(batch_prep<P_FP8>, g, b, 0, st, head, segs); break;
+        case P_FP32: hipLaunchKernelGGL(batch_prep<P_FP32>, g, b, 0, st, head, segs, ordered); break;
+        case P_BF16: hipLaunchKernelGGL(batch_prep<P_BF16>, g, b, 0, st, head, segs, ordered); break;
+        default: hipLaunchKernelGGL(batch_prep<P_FP8>, g, b, 0, st, head, segs, ordered); break;
     }
+    return hipGetLastError();
+}
+
+// Prefilter training rows: slot i < B is the R row of drawn pair i, slot
+// B + i its S row, prepared exactly as the join prepares BF16 operands (one
+// wave per slot).
+__global__ __launch_bounds__(256) void train_rows(const TrainJob* __restrict__ jobs,
+                                                  const int4* __restrict__ samples, int B, int Dp,
+                                                  uint16_t* __restrict__ pool,
+                                                  RowInfo* __restrict__ info,
+                                                  unsigned long long* __restrict__ hdr) {
+    const int lane = threadIdx.x & 63;
+    const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (slot >= 2 * B) return;
+    const int4 smp = samples[slot < B ? slot : slot - B];
+    const TrainJob& J = jobs[smp.x];
+    int64_t r = smp.z, c = smp.w;
+    if (smp.y == 1) {
+        const Pair p = J.out[smp.z];
+        r = p.r;
+        c = p.s;
+    }
+    if (slot < B)
+        prep_row<P_BF16>(J.R, J.nR, J.dim, J.ldR, pool, Dp, info, hdr, slot, r, lane);
+    else
+        prep_row<P_BF16>(J.S, J.nS, J.dim, J.ldS, pool, Dp, info, hdr, slot, c, lane);
+}
+
+hipError_t launch_train_rows(const TrainJob* jobs, const int4* samples, int B, int Dp,
+                             uint16_t* pool, RowInfo* info, unsigned long long* hdr,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(train_rows, dim3((unsigned)((2 * B + 3) / 4)), dim3(256), 0, st, jobs,
+                       samples, B, Dp, pool, info, hdr);
     return hipGetLastError();
 }
 

@@ -11,6 +11,8 @@
 //     accept   iff sim64 >= theta.
 // The same rule defines the exact result set, so a pair accepted here is a
 // pair of that set and the score written is sim64 rounded to float.
+#include <algorithm>
+
 #include "common.hpp"
 #include "batch.hpp"
 #include "launch.hpp"
@@ -210,6 +212,44 @@ __global__ __launch_bounds__(256) void batch_rescore(const BatchHead* __restrict
 hipError_t launch_batch_rescore(const BatchHead* head, const BatchJob* jobs,
                                 const unsigned long long* bctr, int grid, hipStream_t st) {
     hipLaunchKernelGGL(batch_rescore, dim3((unsigned)grid), dim3(256), 0, st, head, jobs, bctr);
+    return hipGetLastError();
+}
+
+// Prefilter training targets: sim64 of every drawn pair (one lane each).
+__global__ __launch_bounds__(256) void train_targets(const TrainJob* __restrict__ jobs,
+                                                     const int4* __restrict__ samples, int B,
+                                                     float* __restrict__ t) {
+    __shared__ float s_rows[4][64 * kPairStride];
+    float* lds = s_rows[threadIdx.x >> 6];
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < B;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + (threadIdx.x & 63);
+        const float* rp = nullptr;
+        const float* sp = nullptr;
+        int dim = 0;
+        if (i < B) {
+            const int4 smp = samples[i];
+            const TrainJob& J = jobs[smp.x];
+            int64_t r = smp.z, c = smp.w;
+            if (smp.y == 1) {
+                const Pair p = J.out[smp.z];
+                r = p.r;
+                c = p.s;
+            }
+            rp = J.R + r * J.ldR;
+            sp = J.S + c * J.ldS;
+            dim = J.dim;
+        }
+        const double sim = wave_sim64(rp, sp, dim, i < B, lds);
+        if (i < B) t[i] = (float)sim;
+    }
+}
+
+hipError_t launch_train_targets(const TrainJob* jobs, const int4* samples, int B, float* t,
+                                hipStream_t st) {
+    const int blocks = std::max(1, std::min(1024, (B + 255) / 256));
+    hipLaunchKernelGGL(train_targets, dim3((unsigned)blocks), dim3(256), 0, st, jobs, samples, B,
+                       t);
     return hipGetLastError();
 }
 

@@ -179,14 +179,16 @@ __device__ __forceinline__ void tile_mainloop(
 // All threads of the workgroup call this for tile (tm, tn).  out_ctr and
 // band_ctr count the pairs appended to `out` and to the band list.  Band
 // entries are int2 {r, s}, or, with TAG, int4 {r, s, job, 0} (one band list
-// shared by the jobs of a batch).
+// shared by the jobs of a batch).  perm_r / perm_s (may be null) map the
+// operand rows back to the caller's rows when the operands were reordered.
 template <int PREC, int BM, int BN, int WM, int WN, bool TAG = false>
 __device__ __forceinline__ void tile_body(
     TileSmem<BM, BN, WM * WN>& sm, const char* __restrict__ A, const char* __restrict__ B,
     const RowInfo* __restrict__ info_r, const RowInfo* __restrict__ info_s, int Kp_bytes,
     int64_t nR, int64_t nS, int tm, int tn, float lo, float hi, Pair* __restrict__ out,
     int64_t capacity, unsigned long long* __restrict__ out_ctr, void* __restrict__ band,
-    int64_t band_cap, unsigned long long* __restrict__ band_ctr, int job = 0) {
+    int64_t band_cap, unsigned long long* __restrict__ band_ctr, int job = 0,
+    const int32_t* __restrict__ perm_r = nullptr, const int32_t* __restrict__ perm_s = nullptr) {
     typedef TileGeom<BM, BN, WM, WN> TG;
     constexpr int NW = TG::NW;
     constexpr int WTM = TG::WTM, WTN = TG::WTN, FM = TG::FM, FN = TG::FN;
@@ -264,12 +266,18 @@ __device__ __forceinline__ void tile_body(
                 if (mlo) {
                     const uint64_t mhi = __ballot(v && a >= hi);
                     const uint64_t mb = mlo & ~mhi;
+                    const bool hit = (mlo >> lane) & 1ull;
+                    int32_t ri = (int32_t)gi, si = (int32_t)gj;
+                    if (hit && perm_r) {
+                        ri = perm_r[gi];
+                        si = perm_s[gj];
+                    }
                     if ((mhi >> lane) & 1ull) {
                         const unsigned long long p = oc + lanes_below(mhi);
                         if ((int64_t)p < capacity) {
                             Pair pr;
-                            pr.r = (int32_t)gi;
-                            pr.s = (int32_t)gj;
+                            pr.r = ri;
+                            pr.s = si;
                             pr.score = a;
                             out[p] = pr;
                         }
@@ -278,9 +286,9 @@ __device__ __forceinline__ void tile_body(
                         const unsigned long long p = ob + lanes_below(mb);
                         if ((int64_t)p < band_cap) {
                             if (TAG)
-                                ((int4*)band)[p] = make_int4((int)gi, (int)gj, job, 0);
+                                ((int4*)band)[p] = make_int4(ri, si, job, 0);
                             else
-                                ((int2*)band)[p] = make_int2((int)gi, (int)gj);
+                                ((int2*)band)[p] = make_int2(ri, si);
                         }
                     }
                     oc += __popcll(mhi);

@@ -19,6 +19,7 @@ OK, E_INVAL, E_OVERFLOW, E_WORKSPACE, E_NONFINITE, E_HIP, E_UNSUPPORTED, E_RANGE
 PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "fp8_e4m3": 2}
 NO_SYNC = 0x1
 TIMING = 0x2
+APPROX_PREFILTER = 0x4
 
 
 class Rel(C.Structure):
@@ -28,7 +29,7 @@ class Rel(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("tile", C.c_int32), ("band", C.c_double),
                 ("band_capacity", C.c_int64), ("flags", C.c_uint32), ("topk_cand", C.c_int32),
-                ("tuner", C.c_void_p)]
+                ("tuner", C.c_void_p), ("prefilter", C.c_void_p), ("prefilter_eps", C.c_float)]
 
 
 class Job(C.Structure):
@@ -42,7 +43,8 @@ class Stats(C.Structure):
                 ("ws_needed", C.c_size_t), ("band", C.c_double), ("tile", C.c_int32),
                 ("n_fallback", C.c_int32), ("ms_prep", C.c_float), ("ms_main", C.c_float),
                 ("ms_rescore", C.c_float), ("ms_total", C.c_float),
-                ("topk_floor", C.c_double), ("topk_slots", C.c_int32)]
+                ("topk_floor", C.c_double), ("topk_slots", C.c_int32),
+                ("tiles_total", C.c_int64), ("tiles_kept", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -145,7 +147,8 @@ def _rel(X, d):
     return Rel(X.data_ptr() if n > 0 else 0, n, dim, X.stride(0) if n > 1 else max(ld, dim))
 
 
-def _opts(prec, band, tile, band_capacity, flags, topk_cand=0, tuner=None):
+def _opts(prec, band, tile, band_capacity, flags, topk_cand=0, tuner=None, prefilter=None,
+          eps=0.0):
     o = Opts()
     lib().ejoin_opts_default(C.byref(o))
     o.prec = PREC[prec]
@@ -155,6 +158,10 @@ def _opts(prec, band, tile, band_capacity, flags, topk_cand=0, tuner=None):
     o.flags = int(flags)
     o.topk_cand = int(topk_cand)
     o.tuner = tuner.handle if tuner is not None else None
+    if prefilter is not None:
+        o.flags |= APPROX_PREFILTER
+        o.prefilter = prefilter.state.data_ptr()
+        o.prefilter_eps = float(eps)
     return o
 
 
@@ -298,10 +305,10 @@ def _jobs(jobs, outs, caps, d):
 
 
 def batch_workspace(jobs, *, d=None, prec="fp32", band=None, tile=0, band_capacity=0,
-                    tuner=None):
+                    tuner=None, prefilter=None, eps=0.0):
     """Workspace bytes for ejoin_batch; ``jobs`` is a list of (R, S, theta)."""
     arr = _jobs(jobs, None, [0] * len(jobs), d)
-    o = _opts(prec, band, tile, band_capacity, 0, tuner=tuner)
+    o = _opts(prec, band, tile, band_capacity, 0, tuner=tuner, prefilter=prefilter, eps=eps)
     n = lib().ejoin_batch_workspace(arr, len(jobs), C.byref(o))
     if n == 0:
         raise EjoinError(E_INVAL, "ejoin_batch_workspace")
@@ -309,12 +316,12 @@ def batch_workspace(jobs, *, d=None, prec="fp32", band=None, tile=0, band_capaci
 
 
 def batch_raw(jobs, outs, caps, ws, n_out, *, d=None, prec="fp32", band=None, tile=0,
-              band_capacity=0, flags=0, stream=None, tuner=None):
+              band_capacity=0, flags=0, stream=None, tuner=None, prefilter=None, eps=0.0):
     """One ejoin_batch call on caller buffers.  ``outs[i]``: int32 (cap_i, 3)
     tensors; ``n_out``: int64 CPU tensor (sync) or CUDA tensor (NO_SYNC).
     Returns (status, stats dict)."""
     arr = _jobs(jobs, outs, caps, d)
-    o = _opts(prec, band, tile, band_capacity, flags, tuner=tuner)
+    o = _opts(prec, band, tile, band_capacity, flags, tuner=tuner, prefilter=prefilter, eps=eps)
     st = Stats()
     rc = lib().ejoin_batch(arr, len(jobs), C.byref(o), C.c_void_p(n_out.data_ptr()),
                            C.c_void_p(ws.data_ptr()), int(ws.numel()), _stream(stream),
@@ -323,7 +330,7 @@ def batch_raw(jobs, outs, caps, ws, n_out, *, d=None, prec="fp32", band=None, ti
 
 
 def batch(jobs, *, d=None, prec="fp32", band=None, tile=0, capacities=None, band_capacity=0,
-          timing=False, stream=None, tuner=None):
+          timing=False, stream=None, tuner=None, prefilter=None, eps=0.0):
     """Run many threshold joins as one batch pass.  ``jobs``: list of
     (R, S, theta).  Returns (list of Pairs, stats dict).  Jobs whose output
     overflowed are run again (as a smaller batch) with exactly enough room."""
@@ -343,12 +350,14 @@ def batch(jobs, *, d=None, prec="fp32", band=None, tile=0, capacities=None, band
         sub = [jobs[i] for i in todo]
         sub_caps = [caps[i] for i in todo]
         ws = torch.empty(batch_workspace(sub, d=d, prec=prec, band=band, tile=tile,
-                                         band_capacity=band_capacity, tuner=tuner),
+                                         band_capacity=band_capacity, tuner=tuner,
+                                         prefilter=prefilter, eps=eps),
                          dtype=torch.uint8, device=dev)
         outs = [torch.empty((max(c, 1), 3), dtype=torch.int32, device=dev) for c in sub_caps]
         n_out = torch.zeros(len(sub), dtype=torch.int64)
         rc, st = batch_raw(sub, outs, sub_caps, ws, n_out, d=d, prec=prec, band=band, tile=tile,
-                           band_capacity=band_capacity, flags=flags, stream=stream, tuner=tuner)
+                           band_capacity=band_capacity, flags=flags, stream=stream, tuner=tuner,
+                           prefilter=prefilter, eps=eps)
         if not stats:
             stats = st
         if rc == E_WORKSPACE and st["band_needed"] > 0:
@@ -586,3 +595,45 @@ class Mlp:
                                  C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
         if rc != OK:
             raise EjoinError(rc, "ejoin_mlp_forward")
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("seed", C.c_uint64),
+                ("pos_frac", C.c_float), ("hp", MlpHparams)]
+
+
+def prefilter_train(net, jobs, outs, caps, n_out, *, d=None, steps=300, batch=4096, seed=1,
+                    pos_frac=0.5, hp=None, losses=True, stream=None):
+    """Train ``net`` (an Mlp) on the batch ``jobs`` whose exact outputs are
+    in ``outs`` (``n_out``: per-job counts).  Returns the per-step losses."""
+    import torch
+    L = lib()
+    if not hasattr(L, "_pf_sigs"):
+        P = C.POINTER
+        L.ejoin_prefilter_train_opts_default.restype = None
+        L.ejoin_prefilter_train_opts_default.argtypes = [P(TrainOpts)]
+        L.ejoin_prefilter_train_workspace.restype = C.c_size_t
+        L.ejoin_prefilter_train_workspace.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+        L.ejoin_prefilter_train.restype = C.c_int
+        L.ejoin_prefilter_train.argtypes = [C.c_void_p, P(Job), C.c_int32, P(C.c_int64),
+                                            P(TrainOpts), C.c_void_p, C.c_size_t,
+                                            P(C.c_float), C.c_void_p]
+        L._pf_sigs = True
+    arr = _jobs(jobs, outs, caps, d)
+    to = TrainOpts()
+    L.ejoin_prefilter_train_opts_default(C.byref(to))
+    to.steps, to.batch, to.seed, to.pos_frac = int(steps), int(batch), int(seed), float(pos_frac)
+    for k, v in (hp or {}).items():
+        setattr(to.hp, "lambda_" if k == "lambda" else k, v)
+    need = L.ejoin_prefilter_train_workspace(len(jobs), net.dim, int(batch))
+    if need == 0:
+        raise EjoinError(E_INVAL, "ejoin_prefilter_train_workspace")
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    cnt = (C.c_int64 * len(jobs))(*[int(x) for x in n_out])
+    ls = (C.c_float * max(1, int(steps)))() if losses else None
+    rc = L.ejoin_prefilter_train(C.c_void_p(net.state.data_ptr()), arr, len(jobs), cnt,
+                                 C.byref(to), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                 ls, _stream(stream))
+    if rc != OK:
+        raise EjoinError(rc, "ejoin_prefilter_train")
+    return [float(x) for x in ls[:int(steps)]] if losses else None

@@ -1,0 +1,143 @@
+"""The prefiltered (approximate) batch join on the GPU.
+
+Exactness where it is promised: with a margin that keeps every tile pair the
+prefiltered pass (codes, per-relation reordering, work list, back-mapping of
+row numbers) must return exactly the plain batched result; with a working
+margin every returned pair must be a pair of the exact join (precision 1).
+Recall is measured against the exact join; it is not pinned to a reference
+(the mode is approximate by design).  A trained network is compared with the
+untrained one it started from."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2312_01476_amd import datagen as G
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+E = None
+
+
+def setup_module(module):
+    global E
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_01476_amd import ejoin
+    E = ejoin
+
+
+D = 96
+
+
+def _jobs(seed=3):
+    """Clustered jobs of uneven size, thresholds across and above the
+    within-cluster similarity, a self-join and an empty job."""
+    cent = G.centres(D, 24, seed)
+    shapes = [(3000, 1500), (900, 2500), (1200, 1200), (257, 700), (0, 300), (2000, 129)]
+    thetas = [0.80, 0.85, 0.75, 0.90, 0.8, 0.70]
+    host = []
+    for i, ((nr, ns), th) in enumerate(zip(shapes, thetas)):
+        R = G.clustered_points(cent, nr, 0.5, seed * 100 + 2 * i)[0] if nr else \
+            np.zeros((0, D), np.float32)
+        S = G.clustered_points(cent, ns, 0.5, seed * 100 + 2 * i + 1)[0]
+        host.append((R, S, th))
+    X = G.clustered_points(cent, 1500, 0.5, seed * 100 + 77)[0]
+    host.append((X, X, 0.82))
+    jobs = []
+    for R, S, th in host:
+        Rd = torch.from_numpy(R).cuda()
+        Sd = Rd if S is R else torch.from_numpy(S).cuda()
+        jobs.append((Rd, Sd, th))
+    return host, jobs
+
+
+def _sets(res):
+    return [set(zip(r.r.cpu().tolist(), r.s.cpu().tolist())) for r in res]
+
+
+def _net(seed):
+    flat, planes = G.mlp_init(D, seed)
+    return E.Mlp(D, torch.from_numpy(flat), torch.from_numpy(planes))
+
+
+@pytest.fixture(scope="module")
+def setup():
+    host, jobs = _jobs()
+    plain, _ = E.batch(jobs, prec="bf16")
+    return host, jobs, plain
+
+
+def test_plain_batch_matches_oracle_on_samples(setup):
+    host, jobs, plain = setup
+    sets = _sets(plain)
+    for (R, S, th), got in zip(host, sets):
+        if R.shape[0] == 0:
+            assert not got
+            continue
+        sub_r, sub_s = min(400, R.shape[0]), min(400, S.shape[0])
+        ori, osi, _, _ = O.threshold(R[:sub_r], S[:sub_s], th)
+        want = set(zip(ori.tolist(), osi.tolist()))
+        assert {p for p in got if p[0] < sub_r and p[1] < sub_s} == want
+
+
+def test_prefilter_keeping_every_tile_is_exact(setup):
+    """eps = 4 keeps every tile pair: the reordered pass must give exactly
+    the plain result (ordering, work list and back-mapping are lossless)."""
+    host, jobs, plain = setup
+    net = _net(5)
+    res, st = E.batch(jobs, prec="bf16", prefilter=net, eps=4.0)
+    assert _sets(res) == _sets(plain)
+
+
+def _train(net, jobs, plain, steps=200):
+    caps = [max(1, len(r)) for r in plain]
+    outs = []
+    for r in plain:
+        o = torch.empty((max(1, len(r)), 3), dtype=torch.int32, device="cuda")
+        if len(r):
+            o[:, 0] = r.r
+            o[:, 1] = r.s
+            o[:, 2] = r.score.view(torch.int32)
+        outs.append(o)
+    return E.prefilter_train(net, jobs, outs, caps, [len(r) for r in plain], steps=steps,
+                             batch=2048, seed=11, hp={"lr": 3e-3})
+
+
+def test_trained_prefilter_is_a_subset_with_high_recall(setup):
+    host, jobs, plain = setup
+    want = _sets(plain)
+    total = sum(len(w) for w in want)
+    net = _net(5)
+    losses = _train(net, jobs, plain)
+    assert np.mean(losses[-20:]) < 0.5 * np.mean(losses[:5])
+    res, st = E.batch(jobs, prec="bf16", prefilter=net, eps=0.1)
+    got = _sets(res)
+    for g, w in zip(got, want):
+        assert g <= w, "a prefiltered pair is not in the exact join"
+    recall = sum(len(g) for g in got) / total
+    kept = st["tiles_kept"] / st["tiles_total"]
+    print(f"trained: recall {recall:.4f}, tile pairs kept {kept:.4f}")
+    assert recall >= 0.95
+    assert kept < 1.0
+
+    # the untrained network (same initial weights) at the same margin
+    raw = _net(5)
+    res0, st0 = E.batch(jobs, prec="bf16", prefilter=raw, eps=0.1)
+    got0 = _sets(res0)
+    for g, w in zip(got0, want):
+        assert g <= w
+    recall0 = sum(len(g) for g in got0) / total
+    kept0 = st0["tiles_kept"] / st0["tiles_total"]
+    print(f"untrained: recall {recall0:.4f}, tile pairs kept {kept0:.4f}")
+    # training must buy recall, or the same recall for less work
+    assert recall > recall0 + 0.01 or (recall >= recall0 - 1e-3 and kept < kept0)
+
+
+def test_prefilter_rejects_bad_options(setup):
+    host, jobs, plain = setup
+    net = _net(5)
+    with pytest.raises(E.EjoinError):
+        E.batch(jobs, prec="fp32", prefilter=net, eps=0.1)
+    with pytest.raises(E.EjoinError):
+        E.batch(jobs, prec="bf16", tile=4, prefilter=net, eps=0.1)
