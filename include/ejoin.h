@@ -233,11 +233,16 @@ size_t ejoin_batch_workspace(const ejoin_job *jobs, int32_t n_jobs, const ejoin_
  *                 codes as for EJOIN_NO_SYNC above).
  * With EJOIN_APPROX_PREFILTER (BF16, tile 3 or 0, every job of the same dim
  * as the network, eager calls only): the prepared rows are coded by the
- * network, each relation is reordered by the codes' sign pattern against the
- * network's 16 hyperplanes, and only the 128 x 128 tile pairs whose bound
- *     c_T . c_U + rho_T |c_U| + rho_U |c_T| + rho_T rho_U >= theta - eps
- * (c: mean code of a tile, rho: largest distance of a code from c) are
- * contracted; pairs are mapped back to the caller's row numbers.
+ * network; 2048 anchor codes drawn from the rows (SplitMix64, seed
+ * 0x5EED) are grouped by leader clustering at cosine 0.6 and every relation
+ * is reordered by the group of each row's nearest anchor; only the
+ * 128 x 128 tile pairs whose bound reaches theta - eps are contracted, the
+ * bound being the smaller of
+ *     c_T . c_U + rho_T |c_U| + rho_U |c_T| + rho_T rho_U   and
+ *     cos(max(0, angle(c_T, c_U) - a_T - a_U))
+ * (c: mean code of a tile, rho: largest distance of a code from c, a:
+ * largest angle of a code from c's direction); pairs are mapped back to the
+ * caller's row numbers.
  * Returns EJOIN_E_OVERFLOW if any job matched more pairs than its capacity
  * (that job's `out` holds an arbitrary capacity-sized subset; re-run it with
  * more room), EJOIN_E_WORKSPACE if the shared band list was too small
@@ -306,7 +311,6 @@ ejoin_status ejoin_autotune(ejoin_tuner *t, const ejoin_job *jobs, int32_t n_job
  * layout ejoin_mlp_layout_get describes. */
 #define EJOIN_MLP_HIDDEN 256
 #define EJOIN_MLP_OUT    64
-#define EJOIN_MLP_PLANES 16
 #define EJOIN_MLP_GRAD_ONLY 0x1u  /* train step: compute gradients, do not update */
 
 typedef struct {
@@ -317,7 +321,6 @@ typedef struct {
     size_t off_params, off_grads, off_m, off_v;
     size_t off_w1t;         /* BF16 W1^T, 256 x dim_pad (zero beyond dim) */
     size_t off_w2t;         /* BF16 W2^T, 64 x 256 */
-    size_t off_planes;      /* FP32 16 x 64 hyperplanes of the row-ordering key */
     size_t off_step;        /* int64 number of Adam steps taken */
     size_t total;           /* bytes of the state block */
 } ejoin_mlp_layout;
@@ -333,11 +336,9 @@ ejoin_status ejoin_mlp_layout_get(int32_t dim, ejoin_mlp_layout *layout /* host 
 void ejoin_mlp_hparams_default(ejoin_mlp_hparams *hp /* host */);
 
 /* Set the masters to `params` (device, n_params FP32 in the flat order; the
- * seeded initial weights are the caller's), the hyperplanes to `planes`
- * (device, 16 x 64), zero gradients, moments and step count, and build the
- * BF16 copies. */
-ejoin_status ejoin_mlp_init(void *state, int32_t dim, const float *params, const float *planes,
-                            hipStream_t stream);
+ * seeded initial weights are the caller's), zero gradients, moments and step
+ * count, and build the BF16 copies. */
+ejoin_status ejoin_mlp_init(void *state, int32_t dim, const float *params, hipStream_t stream);
 
 /* Workspace bytes of a training step of `batch` pairs. */
 size_t ejoin_mlp_train_workspace(int32_t dim, int32_t batch);

@@ -150,12 +150,29 @@ def adam_step(params: dict, grads: dict, m: dict, v: dict, step: int, lr: float 
 # inference side: ordering key and tile bounds
 # ---------------------------------------------------------------------------
 
-def lsh_code(U, planes) -> np.ndarray:
-    """Sign pattern of the codes against hyperplanes (planes: nbits x 64):
-    bit b of row i is 1 iff U[i] . planes[b] >= 0 (bit 0 least significant)."""
-    s = (np.asarray(U, np.float64) @ np.asarray(planes, np.float64).T) >= 0.0
-    w = (1 << np.arange(s.shape[1], dtype=np.int64))
-    return (s.astype(np.int64) * w).sum(axis=1)
+def leader_labels(A, tau: float) -> np.ndarray:
+    """Leader clustering of anchor codes A (K x 64) in order: an anchor joins
+    the first earlier leader whose code has cosine >= tau with it, else it
+    becomes a leader; returns each anchor's leader rank."""
+    A = np.asarray(A, np.float64)
+    leaders = []
+    lab = np.zeros(A.shape[0], np.int64)
+    for k in range(A.shape[0]):
+        for rank, j in enumerate(leaders):
+            if A[k] @ A[j] >= tau:
+                lab[k] = rank
+                break
+        else:
+            lab[k] = len(leaders)
+            leaders.append(k)
+    return lab
+
+
+def anchor_key(U, A, labels) -> np.ndarray:
+    """Ordering key of every code: the label of its nearest anchor (largest
+    dot product, ties to the lower anchor index)."""
+    d = np.asarray(U, np.float64) @ np.asarray(A, np.float64).T
+    return np.asarray(labels)[np.argmax(d, axis=1)]
 
 
 def order_by_key(keys) -> np.ndarray:
@@ -182,3 +199,32 @@ def tile_pair_bound(cT, rT, cU, rU) -> float:
     cT = np.asarray(cT, np.float64)
     cU = np.asarray(cU, np.float64)
     return float(cT @ cU + rT * np.linalg.norm(cU) + rU * np.linalg.norm(cT) + rT * rU)
+
+
+def tile_angles(U, tile: int):
+    """Angular radius of every block of `tile` consecutive unit codes: the
+    largest angle between a code of the block and the direction of the
+    block's centroid (nan for a zero centroid)."""
+    C, _ = tile_stats(U, tile)
+    U = np.asarray(U, np.float64)
+    out = np.zeros(C.shape[0])
+    for i in range(C.shape[0]):
+        n = np.linalg.norm(C[i])
+        if n == 0.0:
+            out[i] = np.nan
+            continue
+        cos = U[i * tile:(i + 1) * tile] @ (C[i] / n)
+        out[i] = np.arccos(np.clip(cos.min(), -1.0, 1.0))
+    return out
+
+
+def tile_pair_bound_angular(cT, aT, cU, aU) -> float:
+    """Upper bound of u . v for unit u within angle aT of the direction of cT
+    and unit v within angle aU of the direction of cU: the angle between u
+    and v is at least (angle between the directions) - aT - aU."""
+    cT = np.asarray(cT, np.float64)
+    cU = np.asarray(cU, np.float64)
+    cphi = cT @ cU / (np.linalg.norm(cT) * np.linalg.norm(cU))
+    gap = np.arccos(np.clip(cphi, -1.0, 1.0)) - aT - aU
+    return float(np.cos(gap)) if gap > 0.0 else 1.0
+

@@ -16,6 +16,22 @@ using namespace ej::plan;
 namespace {
 
 constexpr int kPrepGrid = 4096;     // batched prep: grid-stride over all rows
+constexpr int kAnchors = 2048;      // prefilter: anchor codes of the ordering key
+constexpr float kAnchorTau = 0.6f;  // prefilter: leader-clustering cosine of the anchors
+constexpr uint64_t kAnchorSeed = 0x5EED;
+
+// SplitMix64 (Steele, Lea and Flood, 2014): golden-ratio counter and a
+// MurmurHash3-style finaliser
+struct SplitMix64 {
+    uint64_t x;
+    uint64_t next() {
+        uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    uint64_t below(uint64_t n) { return (uint64_t)(((unsigned __int128)next() * n) >> 64); }
+};
 constexpr int kRescoreGrid = 2048;  // batched rescore: grid-stride over the band list
 
 int batch_default_tile(int prec) { return prec == P_FP32 ? 1 : prec == P_BF16 ? 3 : 5; }
@@ -36,7 +52,12 @@ struct BatchPlan {
     // prefilter mode
     bool approx = false;
     size_t off_hb = 0, off_z = 0, off_u = 0, off_key = 0, off_pa = 0, off_pb = 0, off_hist = 0,
-           off_offs = 0, off_c = 0, off_rho = 0, off_cn = 0, off_work = 0;
+           off_offs = 0, off_c = 0, off_rho = 0, off_cn = 0, off_alpha = 0, off_work = 0,
+           off_ub = 0, off_aidx = 0, off_af = 0, off_ab = 0, off_lab = 0, off_up = 0,
+           off_dir = 0, off_m1 = 0, off_m2 = 0;
+    int64_t n_side = 0;
+    int n_anchor = 0;
+    std::vector<int64_t> anchor_idx;  // flat rows whose codes are the anchors
     std::vector<char> image;  // head, jobs[table_jobs], segs[2 * table_jobs]
     BatchHead* head() { return (BatchHead*)image.data(); }
     BatchJob* jobs() { return (BatchJob*)(image.data() + sizeof(BatchHead)); }
@@ -214,7 +235,36 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         bp.off_c = take(nr / 128 * MLP_OUT * 4);
         bp.off_rho = take(nr / 128 * 4);
         bp.off_cn = take(nr / 128 * 4);
+        bp.off_alpha = take(nr / 128 * 4);
         bp.off_work = take((size_t)bp.n_tiles * 8);
+        bp.off_ub = take(nr * MLP_OUT * 2);
+        bp.off_up = take(nr * MLP_OUT * 2);
+        bp.off_dir = take((nr / 128 + 128) * MLP_OUT * 2);
+        bp.off_m1 = take((size_t)bp.n_tiles * 4);
+        bp.off_m2 = take((size_t)bp.n_tiles * 4);
+        for (int q = 0; q < n; ++q) {
+            J[q].side_base = bp.n_side;
+            bp.n_side += (int64_t)((J[q].tiles_m + 127) / 128) * J[q].tiles_n +
+                         (int64_t)((J[q].tiles_n + 127) / 128) * J[q].tiles_m;
+        }
+        // anchors: rows drawn uniformly over the real rows of all relations
+        int64_t real = 0;
+        for (int i = 0; i < nseg; ++i) real += G[i].rows;
+        bp.n_anchor = (int)std::min<int64_t>(kAnchors, real);
+        bp.off_aidx = take((size_t)std::max(1, bp.n_anchor) * 8);
+        bp.off_af = take((size_t)std::max(1, bp.n_anchor) * MLP_OUT * 4);
+        bp.off_ab = take((size_t)((bp.n_anchor + 127) / 128 * 128 + 128) * MLP_OUT * 2);
+        bp.off_lab = take((size_t)std::max(1, bp.n_anchor) * 4);
+        if (ws) {
+            SplitMix64 rng{kAnchorSeed};
+            bp.anchor_idx.resize(bp.n_anchor);
+            for (int k = 0; k < bp.n_anchor; ++k) {
+                int64_t r = (int64_t)rng.below((uint64_t)real);
+                int i = 0;
+                while (r >= G[i].rows) r -= G[i++].rows;
+                bp.anchor_idx[k] = G[i].row_base + r;
+            }
+        }
         for (int q = 0; q < n; ++q) {
             J[q].perm_r = (const int32_t*)at(bp.off_pa + (size_t)rb_r[q] * 4);
             J[q].perm_s = (const int32_t*)at(bp.off_pa + (size_t)rb_s[q] * 4);
@@ -239,6 +289,7 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
     h->n_segs = nseg;
     if (bp.approx) {
         h->work = (const int64_t*)at(bp.off_work);
+        h->n_side = bp.n_side;
         h->n_work = (const unsigned long long*)at(B_WORK * sizeof(unsigned long long));
     }
     return EJOIN_OK;
@@ -306,7 +357,6 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
         m.P = (float*)(b + L.off_params);
         m.W1t = (uint16_t*)(b + L.off_w1t);
         m.W2t = (uint16_t*)(b + L.off_w2t);
-        m.planes = (float*)(b + L.off_planes);
     }
     const int pg = (int)std::max<int64_t>(1, std::min<int64_t>(kPrepGrid, (bp.n_rows + 3) / 4));
     if ((e = rec(0)) != hipSuccess) return e;
@@ -315,8 +365,20 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
     int32_t* perm_a = (int32_t*)(ws + bp.off_pa);
     if ((e = launch_pf_codes(head, segs, bp.n_rows, m, (uint16_t*)(ws + bp.off_hb),
                              (float*)(ws + bp.off_z), (float*)(ws + bp.off_u),
-                             (int32_t*)(ws + bp.off_key), st)) != hipSuccess)
+                             (uint16_t*)(ws + bp.off_ub), st)) != hipSuccess)
         return e;
+    if (bp.n_anchor > 0) {
+        if ((e = hipMemcpyAsync(ws + bp.off_aidx, bp.anchor_idx.data(), bp.n_anchor * 8,
+                                hipMemcpyHostToDevice, st)) != hipSuccess)
+            return e;
+        if ((e = launch_pf_keys(head, segs, bp.n_rows, (const float*)(ws + bp.off_u),
+                                (const uint16_t*)(ws + bp.off_ub),
+                                (const int64_t*)(ws + bp.off_aidx), bp.n_anchor, kAnchorTau,
+                                (float*)(ws + bp.off_af), (uint16_t*)(ws + bp.off_ab),
+                                (int32_t*)(ws + bp.off_lab), (int32_t*)(ws + bp.off_key), st)) !=
+            hipSuccess)
+            return e;
+    }
     if ((e = launch_pf_sort(head, segs, n_segs, bp.n_rows, (const int32_t*)(ws + bp.off_key),
                             perm_a, (int32_t*)(ws + bp.off_pb), (int32_t*)(ws + bp.off_hist),
                             (int32_t*)(ws + bp.off_offs), st)) != hipSuccess)
@@ -324,7 +386,10 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
     if ((e = launch_batch_prep(bp.prec, head, segs, pg, true, st)) != hipSuccess) return e;
     if ((e = launch_pf_tiles(head, segs, jobs, bp.n_rows, (const float*)(ws + bp.off_u), perm_a,
                              (float*)(ws + bp.off_c), (float*)(ws + bp.off_rho),
-                             (float*)(ws + bp.off_cn), o.prefilter_eps,
+                             (float*)(ws + bp.off_cn), (float*)(ws + bp.off_alpha),
+                             (uint16_t*)(ws + bp.off_up), (uint16_t*)(ws + bp.off_dir),
+                             (float*)(ws + bp.off_m1), (float*)(ws + bp.off_m2), bp.n_side,
+                             o.prefilter_eps,
                              (int64_t*)(ws + bp.off_work), bctr + B_WORK, bp.n_tiles, st)) !=
         hipSuccess)
         return e;

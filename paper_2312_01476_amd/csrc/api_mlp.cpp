@@ -33,8 +33,6 @@ bool layout_of(int32_t dim, ejoin_mlp_layout& L) {
     off = align256(off + (size_t)MLP_HIDDEN * L.dim_pad * 2);
     L.off_w2t = off;
     off = align256(off + (size_t)MLP_OUT * MLP_HIDDEN * 2);
-    L.off_planes = off;
-    off = align256(off + (size_t)MLP_PLANES * MLP_OUT * 4);
     L.off_step = off;
     off = align256(off + 8);
     L.total = off;
@@ -53,7 +51,6 @@ MlpDev dev_of(void* state, const ejoin_mlp_layout& L) {
     m.V = (float*)(b + L.off_v);
     m.W1t = (uint16_t*)(b + L.off_w1t);
     m.W2t = (uint16_t*)(b + L.off_w2t);
-    m.planes = (float*)(b + L.off_planes);
     m.step = (int64_t*)(b + L.off_step);
     return m;
 }
@@ -72,7 +69,7 @@ size_t fwd_ws(int64_t n) {
 // SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
 // generators", 2014): a 64-bit counter advanced by the golden-ratio
 // increment, then a variant of the MurmurHash3 finaliser.
-struct SplitMix64 {
+struct SplitMix64T {
     uint64_t x;
     uint64_t next() {
         uint64_t z = (x += 0x9E3779B97F4A7C15ull);
@@ -189,7 +186,7 @@ ejoin_status ejoin_prefilter_train(void* state, const ejoin_job* jobs, int32_t n
         b += align256(r2 * MLP_OUT * 4);
         t.dZ = (float*)b;
     }
-    SplitMix64 rng{to.seed};
+    SplitMix64T rng{to.seed};
     std::vector<int32_t> smp(4 * (size_t)B);
     auto pick = [&](const std::vector<double>& cum, double tot) {
         const double u = rng.unit() * tot;
@@ -252,11 +249,10 @@ void ejoin_mlp_hparams_default(ejoin_mlp_hparams* hp) {
     hp->flags = 0;
 }
 
-ejoin_status ejoin_mlp_init(void* state, int32_t dim, const float* params, const float* planes,
-                            hipStream_t stream) {
+ejoin_status ejoin_mlp_init(void* state, int32_t dim, const float* params, hipStream_t stream) {
     ejoin_mlp_layout L;
-    if (!state || !params || !planes || !layout_of(dim, L)) return EJOIN_E_INVAL;
-    HIP_TRY(launch_mlp_init(dev_of(state, L), params, planes, stream));
+    if (!state || !params || !layout_of(dim, L)) return EJOIN_E_INVAL;
+    HIP_TRY(launch_mlp_init(dev_of(state, L), params, stream));
     return EJOIN_OK;
 }
 

@@ -41,6 +41,7 @@ struct BatchJob {
     const int32_t* perm_r;
     const int32_t* perm_s;
     int64_t rtile0, stile0;
+    int64_t side_base;         // first item of this job's tile-to-rows bound pass
 };
 
 // One relation to prepare (R or S of a job; an aliased self-join has one).
@@ -68,6 +69,7 @@ struct BatchHead {
     // job << 48 | tm << 24 | tn, and their count (null in the plain mode)
     const int64_t* work;
     const unsigned long long* n_work;
+    int64_t n_side;            // items of the tile-to-rows bound pass
 };
 
 // Global counters of a batch pass.

@@ -211,14 +211,11 @@ __global__ void mlp_zero_i64(int64_t* p) {
     if (threadIdx.x == 0) *p = 0;
 }
 
-hipError_t launch_mlp_init(const MlpDev& m, const float* params, const float* planes,
-                           hipStream_t st) {
+hipError_t launch_mlp_init(const MlpDev& m, const float* params, hipStream_t st) {
     hipLaunchKernelGGL(mlp_copy, dim3(256), dim3(256), 0, st, m.P, params, m.np);
     hipLaunchKernelGGL(mlp_copy, dim3(256), dim3(256), 0, st, m.G, (const float*)nullptr, m.np);
     hipLaunchKernelGGL(mlp_copy, dim3(256), dim3(256), 0, st, m.M, (const float*)nullptr, m.np);
     hipLaunchKernelGGL(mlp_copy, dim3(256), dim3(256), 0, st, m.V, (const float*)nullptr, m.np);
-    hipLaunchKernelGGL(mlp_copy, dim3(4), dim3(256), 0, st, m.planes, planes,
-                       (int64_t)MLP_PLANES * MLP_OUT);
     hipLaunchKernelGGL(mlp_zero_i64, dim3(1), dim3(64), 0, st, m.step);
     hipLaunchKernelGGL(mlp_refresh, dim3(256), dim3(256), 0, st, m.P, m.dim, m.Dp, m.W1t, m.W2t);
     return hipGetLastError();

@@ -11,7 +11,6 @@ namespace ej {
 
 constexpr int MLP_HIDDEN = 256;
 constexpr int MLP_OUT = 64;
-constexpr int MLP_PLANES = 16;  // hyperplanes of the ordering key
 
 // Pointers into a state block (layout fixed by the C ABI).
 struct MlpDev {
@@ -23,7 +22,6 @@ struct MlpDev {
     float* V = nullptr;        // Adam second moments
     uint16_t* W1t = nullptr;   // BF16 W1^T, 256 x Dp (zero beyond dim)
     uint16_t* W2t = nullptr;   // BF16 W2^T, 64 x 256
-    float* planes = nullptr;   // ordering-key hyperplanes, 16 x 64
     int64_t* step = nullptr;   // Adam steps taken
 };
 
@@ -41,8 +39,7 @@ struct MlpTrainWs {
     float* dA1;  // 2B x 256
 };
 
-hipError_t launch_mlp_init(const MlpDev& m, const float* params, const float* planes,
-                           hipStream_t st);
+hipError_t launch_mlp_init(const MlpDev& m, const float* params, hipStream_t st);
 hipError_t launch_mlp_train_step(const MlpDev& m, const uint16_t* X, int64_t ldx, int64_t rows,
                                  const int32_t* pr, const int32_t* ps, const float* t, int B,
                                  const MlpHyper& hp, const MlpTrainWs& w, float* loss,

@@ -7,6 +7,11 @@
 // from the same contraction and FP64 band rescore); only tile pairs are
 // skipped, so the result is a subset of the exact join.
 //
+// Ordering key: K anchor codes are sampled from the batch's rows, grouped by
+// leader clustering (an anchor joins the first earlier leader within cosine
+// tau), and every row takes the group of its nearest anchor; rows of one
+// tight cluster of codes then share a key and become contiguous.
+//
 // Flat row space: the relations of a batch are concatenated, each padded to
 // a multiple of 256 rows (PrepSeg.row_base), so every 128-row tile and every
 // 256-row block lies inside one relation.
@@ -103,13 +108,12 @@ __global__ __launch_bounds__(256) void pf_l2(int64_t n_rows, const uint16_t* __r
     }
 }
 
-// u = z / ||z|| and the ordering key: bit b set iff u . plane_b >= 0;
-// padding rows get the key PF_PAD_KEY so that they sort last
+// u = z / ||z|| (FP32, and a BF16 copy for the anchor assignment); codes
+// of padding rows are zero
 __global__ __launch_bounds__(256) void pf_code(const BatchHead* __restrict__ head,
                                                const PrepSeg* __restrict__ segs,
-                                               const float* __restrict__ Z,
-                                               const float* __restrict__ planes,
-                                               float* __restrict__ U, int32_t* __restrict__ key) {
+                                               const float* __restrict__ Z, float* __restrict__ U,
+                                               uint16_t* __restrict__ Ub) {
     const int lane = threadIdx.x & 63;
     const int64_t n = head->n_rows;
     for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n;
@@ -120,16 +124,135 @@ __global__ __launch_bounds__(256) void pf_code(const BatchHead* __restrict__ hea
         const float nz = sqrtf(wave_sum(z * z));
         const float u = real && nz > 0.0f ? z / nz : 0.0f;
         U[row * MLP_OUT + lane] = u;
-        int code = 0;
+        Ub[row * MLP_OUT + lane] = f32_to_bf16_rne(u);
+    }
+}
+
+// anchors: the codes of sampled rows (FP32, and BF16 zero-padded to a
+// multiple of 128 anchors)
+__global__ void pf_anchor_gather(const float* __restrict__ U, const int64_t* __restrict__ idx,
+                                 int K, int Kpad, float* __restrict__ Af,
+                                 uint16_t* __restrict__ Ab) {
+    const int k = blockIdx.x, o = threadIdx.x;  // 64 threads
+    if (k >= Kpad) return;
+    const float v = k < K ? U[idx[k] * MLP_OUT + o] : 0.0f;
+    if (k < K) Af[(int64_t)k * MLP_OUT + o] = v;
+    Ab[(int64_t)k * MLP_OUT + o] = f32_to_bf16_rne(v);
+}
+
+// leader labels of the anchors, in anchor order: an anchor joins the first
+// leader whose code has cosine >= tau with it, else becomes a leader; the
+// label is the leader's rank.  One workgroup.
+__global__ __launch_bounds__(256) void pf_leaders(const float* __restrict__ Af, int K, float tau,
+                                                  int32_t* __restrict__ label) {
+    __shared__ int s_lead[PF_MAX_ANCHORS];
+    __shared__ int s_n, s_hit;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    for (int k = 0; k < K; ++k) {
+        if (threadIdx.x == 0) s_hit = 0x7fffffff;
+        __syncthreads();
+        const int nl = s_n;
+        const float* a = Af + (int64_t)k * MLP_OUT;
+        for (int t = threadIdx.x; t < nl; t += blockDim.x) {
+            const float* b = Af + (int64_t)s_lead[t] * MLP_OUT;
+            float d = 0.0f;
+            for (int o = 0; o < MLP_OUT; ++o) d = fmaf(a[o], b[o], d);
+            if (d >= tau) atomicMin(&s_hit, t);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (s_hit == 0x7fffffff) {
+                s_lead[s_n] = k;
+                label[k] = s_n;
+                s_n = s_n + 1;
+            } else {
+                label[k] = s_hit;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ordering key of every row: the label of its nearest anchor (largest code
+// dot product, ties to the lower anchor), on the matrix cores: 128 rows per
+// workgroup against all anchors, 128 at a time; padding rows get PF_PAD_KEY
+__global__ __launch_bounds__(256) void pf_assign(const BatchHead* __restrict__ head,
+                                                 const PrepSeg* __restrict__ segs,
+                                                 const uint16_t* __restrict__ Ub,
+                                                 const uint16_t* __restrict__ Ab, int K, int Kpad,
+                                                 const int32_t* __restrict__ label,
+                                                 int32_t* __restrict__ key) {
+    constexpr int BM = 128, BN = 128, WM = 2, WN = 2;
+    typedef TileGeom<BM, BN, WM, WN> TG;
+    __shared__ TileSmem<BM, BN, WM * WN> sm;
+    __shared__ float s_v[WN][BM];
+    __shared__ int s_i[WN][BM];
+    const int64_t tm = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (tm * BM >= head->n_rows) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WN, wn = wave % WN, h = lane >> 5, r32 = lane & 31;
+    float bv[TG::FM][16];
+    int bi[TG::FM][16];
 #pragma unroll
-        for (int b = 0; b < MLP_PLANES; ++b)
-            code |= (wave_sum(u * planes[b * MLP_OUT + lane]) >= 0.0f ? 1 : 0) << b;
-        if (lane == 0) key[row] = real ? code : PF_PAD_KEY;
+    for (int i = 0; i < TG::FM; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            bv[i][e] = -3.0f;
+            bi[i][e] = 0x7fffffff;
+        }
+    for (int at = 0; at < Kpad / BN; ++at) {
+        v16f acc[TG::FM][TG::FN];
+        tile_mainloop<P_BF16, BM, BN, WM, WN>(sm, (const char*)(Ub + tm * BM * MLP_OUT),
+                                              (const char*)Ab, nullptr, nullptr, MLP_OUT * 2, 0,
+                                              at, acc);
+#pragma unroll
+        for (int j = 0; j < TG::FN; ++j) {
+            const int col = at * BN + wn * TG::WTN + j * 32 + r32;
+#pragma unroll
+            for (int i = 0; i < TG::FM; ++i)
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    if (col < K && acc[i][j][e] > bv[i][e]) {  // columns ascend: ties keep the lower
+                        bv[i][e] = acc[i][j][e];
+                        bi[i][e] = col;
+                    }
+        }
+    }
+    // best over the 32 lanes of a half (same rows, different anchors)
+#pragma unroll
+    for (int i = 0; i < TG::FM; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1) {
+                const float ov = __shfl_xor(bv[i][e], o, 64);
+                const int oi = __shfl_xor(bi[i][e], o, 64);
+                if (ov > bv[i][e] || (ov == bv[i][e] && oi < bi[i][e])) {
+                    bv[i][e] = ov;
+                    bi[i][e] = oi;
+                }
+            }
+            if (r32 == 0) {
+                const int rl = wm * TG::WTM + i * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                s_v[wn][rl] = bv[i][e];
+                s_i[wn][rl] = bi[i][e];
+            }
+        }
+    __syncthreads();
+    if (threadIdx.x < BM) {
+        const int t = threadIdx.x;
+        int best = s_i[0][t];
+        if (s_v[1][t] > s_v[0][t] || (s_v[1][t] == s_v[0][t] && s_i[1][t] < best)) best = s_i[1][t];
+        const int64_t row = tm * BM + t;
+        const PrepSeg& g = segs[seg_of(segs, head->n_segs, row)];
+        const bool real = row - g.row_base < g.rows;
+        key[row] = (real && best < K) ? label[best] : PF_PAD_KEY;
     }
 }
 
 // ---------------------------------------------------------------------------
-// stable radix sort of every relation's rows by key: 3 passes of 6 bits,
+// stable radix sort of every relation's rows by key: 2 passes of 6 bits,
 // blocks of 256 rows (one workgroup each) inside one relation
 // ---------------------------------------------------------------------------
 
@@ -228,7 +351,10 @@ __global__ __launch_bounds__(256) void pf_tile_stats(const BatchHead* __restrict
                                                      const int32_t* __restrict__ perm,
                                                      float* __restrict__ C,
                                                      float* __restrict__ rho,
-                                                     float* __restrict__ cnorm) {
+                                                     float* __restrict__ cnorm,
+                                                     float* __restrict__ alpha,
+                                                     uint16_t* __restrict__ Up,
+                                                     uint16_t* __restrict__ Dir) {
     const int lane = threadIdx.x & 63;
     const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t row0 = tile * 128;
@@ -239,27 +365,116 @@ __global__ __launch_bounds__(256) void pf_tile_stats(const BatchHead* __restrict
     float c = 0.0f;
     for (int i = 0; i < cnt; ++i) c += U[(g.row_base + perm[row0 + i]) * MLP_OUT + lane];
     c = cnt ? c / (float)cnt : 0.0f;
-    float r2 = 0.0f;
-    for (int i = 0; i < cnt; ++i) {
-        const float dlt = U[(g.row_base + perm[row0 + i]) * MLP_OUT + lane] - c;
-        r2 = fmaxf(r2, wave_sum(dlt * dlt));
-    }
-    C[tile * MLP_OUT + lane] = c;
     const float cn = sqrtf(wave_sum(c * c));
+    const float ch = cn > 0.0f ? c / cn : 0.0f;  // centroid direction
+    float r2 = 0.0f, cmin = 1.0f;
+    for (int i = 0; i < cnt; ++i) {
+        const float u = U[(g.row_base + perm[row0 + i]) * MLP_OUT + lane];
+        const float dlt = u - c;
+        r2 = fmaxf(r2, wave_sum(dlt * dlt));
+        cmin = fminf(cmin, wave_sum(u * ch));
+        Up[(row0 + i) * MLP_OUT + lane] = f32_to_bf16_rne(u);  // codes in tile order
+    }
+    for (int i = cnt; i < 128; ++i) Up[(row0 + i) * MLP_OUT + lane] = 0;
+    Dir[tile * MLP_OUT + lane] = f32_to_bf16_rne(cn > 1e-3f ? ch : 0.0f);
+    C[tile * MLP_OUT + lane] = c;
     if (lane == 0) {
-        // one FP32 ulp of slack per quantity for the rounding of the sums
+        // slack for the FP32 rounding of the sums
         rho[tile] = cnt ? sqrtf(r2) * (1.0f + 1e-6f) + 1e-6f : -1.0f;
         cnorm[tile] = cn * (1.0f + 1e-6f);
+        // angular radius: largest angle between a code and the centroid
+        // direction (pi: no direction, the angular bound is void)
+        alpha[tile] = cn > 1e-3f ? acosf(fmaxf(-1.0f, fminf(1.0f, cmin))) + 1e-4f : 3.2f;
     }
 }
 
-// every tile pair of every job: keep it when
-//   c_T . c_U + rho_T ||c_U|| + rho_U ||c_T|| + rho_T rho_U >= theta - eps
+// Tile-to-rows maxima, on the matrix cores: for every tile pair (T, U) of a
+// job, M1 = max over the rows s of U of dir(T) . u_s and M2 = max over the
+// rows r of T of dir(U) . u_r, with dir the unit centroid direction.  One
+// item multiplies the directions of 128 tiles of one side by the 128 codes
+// of one tile of the other side and keeps the row maxima.
+__global__ __launch_bounds__(256) void pf_sidemax(const BatchHead* __restrict__ head,
+                                                  const BatchJob* __restrict__ jobs,
+                                                  const uint16_t* __restrict__ Up,
+                                                  const uint16_t* __restrict__ Dir,
+                                                  float* __restrict__ M1,
+                                                  float* __restrict__ M2) {
+    constexpr int BM = 128, BN = 128, WM = 2, WN = 2;
+    typedef TileGeom<BM, BN, WM, WN> TG;
+    __shared__ TileSmem<BM, BN, WM * WN> sm;
+    __shared__ float s_v[WN][BM];
+    const int64_t item = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (item >= head->n_side) return;
+    const int n_jobs = head->n_jobs;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].side_base <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchJob& J = jobs[lo];
+    int64_t local = item - J.side_base;
+    const int64_t n0 = (int64_t)((J.tiles_m + 127) / 128) * J.tiles_n;
+    int64_t a_first, b_tile, n_a;  // direction tiles [a_first, +128), code tile b_tile
+    bool side0 = local < n0;
+    int ag, b;
+    if (side0) {
+        ag = (int)(local / J.tiles_n);
+        b = (int)(local % J.tiles_n);
+        a_first = J.rtile0 + (int64_t)ag * 128;
+        b_tile = J.stile0 + b;
+        n_a = J.tiles_m;
+    } else {
+        local -= n0;
+        ag = (int)(local / J.tiles_m);
+        b = (int)(local % J.tiles_m);
+        a_first = J.stile0 + (int64_t)ag * 128;
+        b_tile = J.rtile0 + b;
+        n_a = J.tiles_n;
+    }
+    v16f acc[TG::FM][TG::FN];
+    tile_mainloop<P_BF16, BM, BN, WM, WN>(sm, (const char*)(Dir + a_first * MLP_OUT),
+                                          (const char*)(Up + b_tile * 128 * MLP_OUT), nullptr,
+                                          nullptr, MLP_OUT * 2, 0, 0, acc);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WN, wn = wave % WN, h = lane >> 5, r32 = lane & 31;
+#pragma unroll
+    for (int i = 0; i < TG::FM; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            float v = acc[i][0][e];
+#pragma unroll
+            for (int j = 1; j < TG::FN; ++j) v = fmaxf(v, acc[i][j][e]);
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+            if (r32 == 0) s_v[wn][wm * TG::WTM + i * 32 + 8 * (e >> 2) + 4 * h + (e & 3)] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < BM) {
+        const int t = threadIdx.x;
+        const int64_t a = (int64_t)ag * 128 + t;
+        if (a < n_a) {
+            const float v = fmaxf(s_v[0][t], s_v[1][t]);
+            if (side0) M1[J.tile_base + a * J.tiles_n + b] = v;
+            else M2[J.tile_base + (int64_t)b * J.tiles_n + a] = v;
+        }
+    }
+}
+
+// every tile pair of every job: keep it when the smallest of these upper
+// bounds of the predicted similarity reaches theta - eps:
+//   c_T . c_U + rho_T ||c_U|| + rho_U ||c_T|| + rho_T rho_U   (any codes),
+//   cos(max(0, angle(c_T, c_U) - a_T - a_U))                  (unit codes),
+//   cos(max(0, acos(M1) - a_T)) and cos(max(0, acos(M2) - a_U))
+// (M1, M2: tile-to-rows maxima of pf_sidemax)
 __global__ __launch_bounds__(256) void pf_bounds(const BatchHead* __restrict__ head,
                                                  const BatchJob* __restrict__ jobs,
                                                  const float* __restrict__ C,
                                                  const float* __restrict__ rho,
-                                                 const float* __restrict__ cnorm, float eps,
+                                                 const float* __restrict__ cnorm,
+                                                 const float* __restrict__ alpha,
+                                                 const float* __restrict__ M1,
+                                                 const float* __restrict__ M2, float eps,
                                                  int64_t* __restrict__ work,
                                                  unsigned long long* __restrict__ n_work) {
     const int lane = threadIdx.x & 63;
@@ -289,7 +504,29 @@ __global__ __launch_bounds__(256) void pf_bounds(const BatchHead* __restrict__ h
                 for (int k = 0; k < MLP_OUT; ++k) dot = fmaf(ca[k], cb[k], dot);
                 // 1e-5 covers the FP32 rounding of the 64-term dot of
                 // vectors of norm <= 1
-                const float bound = dot + 1e-5f + ra * cnorm[b] + rb * cnorm[a] + ra * rb;
+                float bound = dot + 1e-5f + ra * cnorm[b] + rb * cnorm[a] + ra * rb;
+                // codes are unit vectors: the angle between two of them is at
+                // least the angle between the tile directions minus both
+                // angular radii (1e-4 rad of slack for the FP32 acos/cos)
+                const float na = cnorm[a], nb = cnorm[b];
+                if (na > 1e-3f && nb > 1e-3f) {
+                    const float cphi = fmaxf(-1.0f, fminf(1.0f, dot / (na * nb)));
+                    const float gap = acosf(cphi) - alpha[a] - alpha[b] - 1e-4f;
+                    if (gap > 0.0f) bound = fminf(bound, cosf(gap) + 1e-5f);
+                }
+                // one tile's rows against the other tile's direction: the
+                // angle of u_r to u_s is at least the angle of dir(T) to u_s
+                // minus a_T; 0.02 covers the BF16 codes of the product
+                if (na > 1e-3f) {
+                    const float m = fminf(1.0f, M1[item] + 0.02f);
+                    const float gap = acosf(fmaxf(-1.0f, m)) - alpha[a] - 1e-4f;
+                    bound = fminf(bound, gap > 0.0f ? cosf(gap) + 1e-5f : 1.0f + 1e-5f);
+                }
+                if (nb > 1e-3f) {
+                    const float m = fminf(1.0f, M2[item] + 0.02f);
+                    const float gap = acosf(fmaxf(-1.0f, m)) - alpha[b] - 1e-4f;
+                    bound = fminf(bound, gap > 0.0f ? cosf(gap) + 1e-5f : 1.0f + 1e-5f);
+                }
                 keep = (double)bound >= J.theta - (double)eps;
                 packed = ((int64_t)lo << 48) | ((int64_t)tm << 24) | (int64_t)tn;
             }
@@ -312,7 +549,7 @@ __global__ __launch_bounds__(256) void pf_bounds(const BatchHead* __restrict__ h
 // ---------------------------------------------------------------------------
 
 hipError_t launch_pf_codes(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
-                           const MlpDev& m, uint16_t* Hb, float* Z, float* U, int32_t* key,
+                           const MlpDev& m, uint16_t* Hb, float* Z, float* U, uint16_t* Ub,
                            hipStream_t st) {
     if (n_rows <= 0) return hipSuccess;
     const int64_t tiles = n_rows / 128;  // n_rows is a multiple of 256
@@ -327,8 +564,24 @@ hipError_t launch_pf_codes(const BatchHead* head, const PrepSeg* segs, int64_t n
     hipLaunchKernelGGL(pf_l2, dim3((unsigned)gx2, (unsigned)gy2), dim3(256), 0, st, n_rows, Hb,
                        m.W2t, b2, Z);
     const int64_t blocks = std::min<int64_t>((n_rows + 3) / 4, 16384);
-    hipLaunchKernelGGL(pf_code, dim3((unsigned)blocks), dim3(256), 0, st, head, segs, Z,
-                       m.planes, U, key);
+    hipLaunchKernelGGL(pf_code, dim3((unsigned)blocks), dim3(256), 0, st, head, segs, Z, U, Ub);
+    return hipGetLastError();
+}
+
+hipError_t launch_pf_keys(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
+                          const float* U, const uint16_t* Ub, const int64_t* anchor_idx, int K,
+                          float tau, float* Af, uint16_t* Ab, int32_t* label, int32_t* key,
+                          hipStream_t st) {
+    if (n_rows <= 0 || K <= 0) return hipSuccess;
+    if (K > PF_MAX_ANCHORS) return hipErrorInvalidValue;
+    const int Kpad = (K + 127) / 128 * 128;
+    hipLaunchKernelGGL(pf_anchor_gather, dim3((unsigned)Kpad), dim3(64), 0, st, U, anchor_idx, K,
+                       Kpad, Af, Ab);
+    hipLaunchKernelGGL(pf_leaders, dim3(1), dim3(256), 0, st, Af, K, tau, label);
+    const int64_t tiles = n_rows / 128;
+    const int64_t gx = std::min<int64_t>(tiles, 65536), gy = (tiles + gx - 1) / gx;
+    hipLaunchKernelGGL(pf_assign, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, head, segs,
+                       Ub, Ab, K, Kpad, label, key);
     return hipGetLastError();
 }
 
@@ -338,11 +591,9 @@ hipError_t launch_pf_sort(const BatchHead* head, const PrepSeg* segs, int n_segs
     if (n_rows <= 0) return hipSuccess;
     const int64_t blocks = n_rows / 256;
     const int32_t* in = nullptr;
-    int32_t* bufs[2] = {perm_a, perm_b};
-    // three passes end in perm_a: a, b, a
-    for (int pass = 0; pass < 3; ++pass) {
-        int32_t* out = bufs[pass & 1 ? 1 : 0];
-        if (pass == 2) out = perm_a;
+    // two passes of 6 bits cover keys below 4096 and end in perm_a: b, a
+    for (int pass = 0; pass < 2; ++pass) {
+        int32_t* out = pass == 0 ? perm_b : perm_a;
         hipLaunchKernelGGL(pf_hist, dim3((unsigned)blocks), dim3(256), 0, st, head, segs, pass,
                            key, in, hist);
         hipLaunchKernelGGL(pf_scan, dim3((unsigned)n_segs), dim3(64), 0, st, head, segs, hist,
@@ -356,15 +607,21 @@ hipError_t launch_pf_sort(const BatchHead* head, const PrepSeg* segs, int n_segs
 
 hipError_t launch_pf_tiles(const BatchHead* head, const PrepSeg* segs, const BatchJob* jobs,
                            int64_t n_rows, const float* U, const int32_t* perm, float* C,
-                           float* rho, float* cnorm, float eps, int64_t* work,
+                           float* rho, float* cnorm, float* alpha, uint16_t* Up, uint16_t* Dir,
+                           float* M1, float* M2, int64_t n_side, float eps, int64_t* work,
                            unsigned long long* n_work, int64_t n_tiles, hipStream_t st) {
     if (n_rows <= 0) return hipSuccess;
     const int64_t tiles = n_rows / 128;
     hipLaunchKernelGGL(pf_tile_stats, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, head,
-                       segs, U, perm, C, rho, cnorm);
+                       segs, U, perm, C, rho, cnorm, alpha, Up, Dir);
+    if (n_side > 0) {
+        const int64_t gx = std::min<int64_t>(n_side, 65536), gy = (n_side + gx - 1) / gx;
+        hipLaunchKernelGGL(pf_sidemax, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, head,
+                           jobs, Up, Dir, M1, M2);
+    }
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n_tiles + 255) / 256, 8192));
     hipLaunchKernelGGL(pf_bounds, dim3((unsigned)blocks), dim3(256), 0, st, head, jobs, C, rho,
-                       cnorm, eps, work, n_work);
+                       cnorm, alpha, M1, M2, eps, work, n_work);
     return hipGetLastError();
 }
 

@@ -13,12 +13,19 @@ struct BatchHead;
 struct BatchJob;
 struct PrepSeg;
 
-constexpr int32_t PF_PAD_KEY = 1 << 16;  // ordering key of padding rows (sorts last)
+constexpr int32_t PF_PAD_KEY = 4095;        // ordering key of padding rows (sorts last)
+constexpr int PF_MAX_ANCHORS = 4094;        // anchors of the ordering key (labels < 4095)
 
-// codes U (flat rows x 64) and ordering keys of every prepared row
+// codes U (flat rows x 64, and a BF16 copy Ub) of every prepared row
 hipError_t launch_pf_codes(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
-                           const MlpDev& m, uint16_t* Hb, float* Z, float* U, int32_t* key,
+                           const MlpDev& m, uint16_t* Hb, float* Z, float* U, uint16_t* Ub,
                            hipStream_t st);
+// ordering keys: K anchors = codes of the flat rows anchor_idx, leader
+// labels at cosine tau, key = label of the nearest anchor
+hipError_t launch_pf_keys(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
+                          const float* U, const uint16_t* Ub, const int64_t* anchor_idx, int K,
+                          float tau, float* Af, uint16_t* Ab, int32_t* label, int32_t* key,
+                          hipStream_t st);
 // stable order of every relation's rows by key: perm_a[row_base + i] is the
 // local row at ordered position i
 hipError_t launch_pf_sort(const BatchHead* head, const PrepSeg* segs, int n_segs, int64_t n_rows,
@@ -27,7 +34,8 @@ hipError_t launch_pf_sort(const BatchHead* head, const PrepSeg* segs, int n_segs
 // 128-row tile statistics of the ordered rows and the surviving tile pairs
 hipError_t launch_pf_tiles(const BatchHead* head, const PrepSeg* segs, const BatchJob* jobs,
                            int64_t n_rows, const float* U, const int32_t* perm, float* C,
-                           float* rho, float* cnorm, float eps, int64_t* work,
+                           float* rho, float* cnorm, float* alpha, uint16_t* Up, uint16_t* Dir,
+                           float* M1, float* M2, int64_t n_side, float eps, int64_t* work,
                            unsigned long long* n_work, int64_t n_tiles, hipStream_t st);
 
 }  // namespace ej

@@ -195,6 +195,14 @@ WORKLOADS = {
     "batch64_bf16": Workload("batch64_bf16", 0, 0, 768, 768, 1000, 0.3, prec="bf16",
                              seeds=(500, 0, 0), extra={"batch": 64, "job_seed": 501},
                              notes="64 uneven joins, 768-d, bf16 + fp64 band, one batch pass"),
+    # the same 64 joins through the learned prefilter (approximate mode):
+    # network 768-256-64 trained on pairs drawn from the exact batch output
+    "batch64_learned": Workload("batch64_learned", 0, 0, 768, 768, 1000, 0.3, prec="bf16",
+                                seeds=(500, 0, 0),
+                                extra={"batch": 64, "job_seed": 501, "prefilter": True,
+                                       "mlp_seed": 601, "train_steps": 300,
+                                       "train_batch": 4096, "eps": 0.05},
+                                notes="64 uneven joins, 768-d, learned prefilter (approximate)"),
 }
 
 
@@ -244,16 +252,12 @@ def make_host(w: Workload, n_r: int | None = None, n_s: int | None = None,
 # seeded initial state of the prefilter network (random draws only)
 # --------------------------------------------------------------------------
 
-def mlp_init(dim: int, seed: int, hidden: int = 256, out: int = 64, planes: int = 16,
-             bias_scale: float = 0.0):
+def mlp_init(dim: int, seed: int, hidden: int = 256, out: int = 64, bias_scale: float = 0.0):
     """He-initialised flat parameters (W1 dim x hidden, b1, W2 hidden x out,
-    b2; biases N(0, bias_scale^2)) and Gaussian ordering-key hyperplanes
-    (planes x out), float32."""
+    b2; biases N(0, bias_scale^2)), float32."""
     rng = np.random.Generator(np.random.PCG64(seed))
     W1 = rng.standard_normal((dim, hidden)) * math.sqrt(2.0 / dim)
     b1 = rng.standard_normal(hidden) * bias_scale
     W2 = rng.standard_normal((hidden, out)) * math.sqrt(2.0 / hidden)
     b2 = rng.standard_normal(out) * bias_scale
-    flat = np.concatenate([W1.ravel(), b1, W2.ravel(), b2]).astype(np.float32)
-    P = rng.standard_normal((planes, out)).astype(np.float32)
-    return flat, P
+    return np.concatenate([W1.ravel(), b1, W2.ravel(), b2]).astype(np.float32)

@@ -468,7 +468,7 @@ class Tuner:
 # prefilter network
 # ---------------------------------------------------------------------------
 
-MLP_HIDDEN, MLP_OUT, MLP_PLANES = 256, 64, 16
+MLP_HIDDEN, MLP_OUT = 256, 64
 MLP_GRAD_ONLY = 0x1
 
 
@@ -476,7 +476,7 @@ class MlpLayout(C.Structure):
     _fields_ = [("dim", C.c_int32), ("dim_pad", C.c_int32), ("n_params", C.c_int64),
                 ("off_params", C.c_size_t), ("off_grads", C.c_size_t), ("off_m", C.c_size_t),
                 ("off_v", C.c_size_t), ("off_w1t", C.c_size_t), ("off_w2t", C.c_size_t),
-                ("off_planes", C.c_size_t), ("off_step", C.c_size_t), ("total", C.c_size_t)]
+                ("off_step", C.c_size_t), ("total", C.c_size_t)]
 
 
 class MlpHparams(C.Structure):
@@ -492,7 +492,7 @@ def _mlp_sigs(L):
     L.ejoin_mlp_hparams_default.restype = None
     L.ejoin_mlp_hparams_default.argtypes = [P(MlpHparams)]
     L.ejoin_mlp_init.restype = C.c_int
-    L.ejoin_mlp_init.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.ejoin_mlp_init.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
     L.ejoin_mlp_train_workspace.restype = C.c_size_t
     L.ejoin_mlp_train_workspace.argtypes = [C.c_int32, C.c_int32]
     L.ejoin_mlp_train_step.restype = C.c_int
@@ -522,20 +522,18 @@ def mlp_layout(dim):
 class Mlp:
     """The prefilter network's state block (one device tensor) and views of
     its regions.  ``params``: flat FP32 initial weights (W1 dim x 256, b1,
-    W2 256 x 64, b2); ``planes``: 16 x 64 ordering-key hyperplanes."""
+    W2 256 x 64, b2)."""
 
-    def __init__(self, dim, params, planes, stream=None):
+    def __init__(self, dim, params, stream=None):
         import torch
         self.dim = int(dim)
         self.lay = mlp_layout(dim)
         self.state = torch.zeros(self.lay.total, dtype=torch.uint8, device="cuda")
         p = params.to(device="cuda", dtype=torch.float32).contiguous()
-        q = planes.to(device="cuda", dtype=torch.float32).contiguous()
-        if p.numel() != self.lay.n_params or q.numel() != MLP_PLANES * MLP_OUT:
-            raise ValueError("params / planes have the wrong size")
+        if p.numel() != self.lay.n_params:
+            raise ValueError("params have the wrong size")
         rc = lib().ejoin_mlp_init(C.c_void_p(self.state.data_ptr()), self.dim,
-                                  C.c_void_p(p.data_ptr()), C.c_void_p(q.data_ptr()),
-                                  _stream(stream))
+                                  C.c_void_p(p.data_ptr()), _stream(stream))
         if rc != OK:
             raise EjoinError(rc, "ejoin_mlp_init")
         self._ws = None

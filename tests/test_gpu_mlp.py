@@ -44,8 +44,8 @@ def _rows_bf16(n, d, seed, pad_to=None):
 
 
 def _setup(d, n_rows, B, seed):
-    flat, planes = G.mlp_init(d, seed, bias_scale=0.05)
-    net = E.Mlp(d, torch.from_numpy(flat), torch.from_numpy(planes))
+    flat = G.mlp_init(d, seed, bias_scale=0.05)
+    net = E.Mlp(d, torch.from_numpy(flat))
     X, Xd = _rows_bf16(n_rows, d, seed + 1)
     rng = np.random.default_rng(seed + 2)
     pr = rng.integers(0, n_rows, B).astype(np.int32)
@@ -108,8 +108,8 @@ def test_training_reduces_loss_on_clustered_pairs():
     Xb = torch.from_numpy(Xf).to(torch.bfloat16)
     X = Xb.double().numpy()
     Xd = Xb.cuda()
-    flat, planes = G.mlp_init(d, 7)
-    net = E.Mlp(d, torch.from_numpy(flat), torch.from_numpy(planes))
+    flat = G.mlp_init(d, 7)
+    net = E.Mlp(d, torch.from_numpy(flat))
     rng = np.random.default_rng(8)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     losses = []
@@ -133,8 +133,8 @@ def test_training_reduces_loss_on_clustered_pairs():
 
 @pytest.mark.parametrize("d,n", [(96, 300), (768, 1000), (384, 128)])
 def test_forward_codes_match_reference(d, n):
-    flat, planes = G.mlp_init(d, 31 + d, bias_scale=0.05)
-    net = E.Mlp(d, torch.from_numpy(flat), torch.from_numpy(planes))
+    flat = G.mlp_init(d, 31 + d, bias_scale=0.05)
+    net = E.Mlp(d, torch.from_numpy(flat))
     dp = net.lay.dim_pad
     n_pad = (n + 127) // 128 * 128
     X, Xd = _rows_bf16(n, d, 41 + n, pad_to=(n_pad, dp))

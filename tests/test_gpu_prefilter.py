@@ -38,11 +38,11 @@ def _jobs(seed=3):
     thetas = [0.80, 0.85, 0.75, 0.90, 0.8, 0.70]
     host = []
     for i, ((nr, ns), th) in enumerate(zip(shapes, thetas)):
-        R = G.clustered_points(cent, nr, 0.5, seed * 100 + 2 * i)[0] if nr else \
+        R = G.clustered_points(cent, nr, 0.3, seed * 100 + 2 * i)[0] if nr else \
             np.zeros((0, D), np.float32)
-        S = G.clustered_points(cent, ns, 0.5, seed * 100 + 2 * i + 1)[0]
+        S = G.clustered_points(cent, ns, 0.3, seed * 100 + 2 * i + 1)[0]
         host.append((R, S, th))
-    X = G.clustered_points(cent, 1500, 0.5, seed * 100 + 77)[0]
+    X = G.clustered_points(cent, 1500, 0.3, seed * 100 + 77)[0]
     host.append((X, X, 0.82))
     jobs = []
     for R, S, th in host:
@@ -57,8 +57,8 @@ def _sets(res):
 
 
 def _net(seed):
-    flat, planes = G.mlp_init(D, seed)
-    return E.Mlp(D, torch.from_numpy(flat), torch.from_numpy(planes))
+    flat = G.mlp_init(D, seed)
+    return E.Mlp(D, torch.from_numpy(flat))
 
 
 @pytest.fixture(scope="module")

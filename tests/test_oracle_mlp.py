@@ -165,14 +165,46 @@ def test_tile_bound_dominates_brute_force():
     assert np.isclose(M.tile_pair_bound(C[2], 0.0, C[7], 0.0), U[2] @ U[7])
 
 
-def test_lsh_code_and_stable_order():
-    planes = np.eye(3, 64)
-    U = np.zeros((5, 64))
-    U[0, :3] = [1, 1, 1]
-    U[1, :3] = [-1, 1, -1]
-    U[2, :3] = [1, -1, -1]
-    U[3, :3] = [1, 1, 1]
-    U[4, :3] = [-1, -1, -1]
-    code = M.lsh_code(U, planes)
-    assert code.tolist() == [7, 2, 1, 7, 0]
-    assert M.order_by_key(code).tolist() == [4, 2, 1, 0, 3]
+def test_angular_tile_bound_dominates_brute_force_and_can_be_tighter():
+    rng = np.random.default_rng(17)
+    base = rng.standard_normal((6, 64))
+    V = np.repeat(base, 32, axis=0) + 0.08 * rng.standard_normal((192, 64))
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    C, rho = M.tile_stats(V, 32)
+    A = M.tile_angles(V, 32)
+    tighter = 0
+    for i in range(6):
+        for j in range(6):
+            bi, bj = V[i * 32:(i + 1) * 32], V[j * 32:(j + 1) * 32]
+            true_max = (bi @ bj.T).max()
+            ang = M.tile_pair_bound_angular(C[i], A[i], C[j], A[j])
+            lin = M.tile_pair_bound(C[i], rho[i], C[j], rho[j])
+            assert ang >= true_max - 1e-12
+            tighter += ang < lin
+    assert tighter > 0
+    # one-point tiles: zero angle, the bound is the dot product itself
+    A1 = M.tile_angles(V[:4], 1)
+    assert np.allclose(A1, 0.0, atol=1e-7)
+    assert np.isclose(M.tile_pair_bound_angular(V[0], 0.0, V[3], 0.0), V[0] @ V[3])
+
+
+def test_anchor_key_groups_tight_clusters_and_orders_stably():
+    rng = np.random.default_rng(19)
+    cent = rng.standard_normal((7, 64))
+    cent /= np.linalg.norm(cent, axis=1, keepdims=True)
+    lab = rng.integers(0, 7, 500)
+    U = cent[lab] + 0.02 * rng.standard_normal((500, 64))
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    A = U[rng.choice(500, 60, replace=False)]
+    L = M.leader_labels(A, 0.6)
+    key = M.anchor_key(U, A, L)
+    # one key per cluster, and different clusters never share a key
+    for c in range(7):
+        assert len(set(key[lab == c].tolist())) <= 1
+    seen = {}
+    for c, k in zip(lab, key):
+        assert seen.setdefault(k, c) == c
+    # leaders come in anchor order: the first anchor leads group 0
+    assert L[0] == 0 and L.max() == len(set(L.tolist())) - 1
+    keys = np.array([3, 1, 3, 0, 1])
+    assert M.order_by_key(keys).tolist() == [3, 1, 4, 0, 2]
