@@ -18,7 +18,7 @@
 
 namespace ej {
 
-template <int PREC, int BM, int BN, int WM, int WN>
+template <int PREC, int BM, int BN, int WM, int WN, bool BIG = false>
 __global__ __launch_bounds__(WM* WN * 64) void batch_tile(const BatchHead* __restrict__ head,
                                                           const BatchJob* __restrict__ jobs,
                                                           unsigned long long* __restrict__ bctr) {
@@ -69,10 +69,15 @@ __global__ __launch_bounds__(WM* WN * 64) void batch_tile(const BatchHead* __res
         if (item >= total) break;
         const BatchJob& J = jobs[job];
         if (J.hdr[H_FLAGS] != 0) continue;  // bad input rows in this job
-        tile_body<PREC, BM, BN, WM, WN, true>(sm, J.A, J.B, J.info_r, J.info_s, J.Kp_bytes, J.nR,
-                                              J.nS, tm, tn, J.lo, J.hi, J.out, J.capacity,
-                                              J.hdr + H_OUT, band, band_cap, bctr + B_BAND, job,
-                                              J.perm_r, J.perm_s);
+        if constexpr (BIG)
+            big_tile_body<PREC, true>(sm, J.A, J.B, J.info_r, J.info_s, J.Kp_bytes, J.nR, J.nS, tm,
+                                      tn, J.lo, J.hi, J.out, J.capacity, J.hdr + H_OUT, band,
+                                      band_cap, bctr + B_BAND, job, J.perm_r, J.perm_s);
+        else
+            tile_body<PREC, BM, BN, WM, WN, true>(sm, J.A, J.B, J.info_r, J.info_s, J.Kp_bytes,
+                                                  J.nR, J.nS, tm, tn, J.lo, J.hi, J.out,
+                                                  J.capacity, J.hdr + H_OUT, band, band_cap,
+                                                  bctr + B_BAND, job, J.perm_r, J.perm_s);
     }
 }
 
@@ -104,18 +109,18 @@ __global__ void batch_counts(const BatchHead* __restrict__ head, const BatchJob*
     }
 }
 
-template <int PREC, int BM, int BN, int WM, int WN>
+template <int PREC, int BM, int BN, int WM, int WN, bool BIG = false>
 static hipError_t run_batch(const BatchHead* head, const BatchJob* jobs, unsigned long long* bctr,
                             int grid, hipStream_t st) {
-    hipLaunchKernelGGL((batch_tile<PREC, BM, BN, WM, WN>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((batch_tile<PREC, BM, BN, WM, WN, BIG>), dim3((unsigned)grid),
                        dim3(WM * WN * 64), 0, st, head, jobs, bctr);
     return hipGetLastError();
 }
 
-template <int PREC, int BM, int BN, int WM, int WN>
+template <int PREC, int BM, int BN, int WM, int WN, bool BIG = false>
 static int occ_of() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_tile<PREC, BM, BN, WM, WN>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_tile<PREC, BM, BN, WM, WN, BIG>,
                                                      WM * WN * 64, 0) != hipSuccess)
         return 0;
     return n;
@@ -123,7 +128,9 @@ static int occ_of() {
 
 bool batch_has_tile(int tile_id) {
     switch (tile_id) {
-        case 1: case 2: case 3: case 4: case 5: case 6: case 8: case 10: case 11: return true;
+        case 1: case 2: case 3: case 4: case 5: case 6: case 8: case 10: case 11: case 16:
+        case 17: case 18:
+            return true;
         default: return false;
     }
 }
@@ -141,6 +148,9 @@ int batch_occupancy(int tile_id) {
         case 8: return occ_of<P_BF16, 256, 256, 2, 4>();
         case 10: return occ_of<P_FP8, 256, 256, 2, 4>();
         case 11: return occ_of<P_FP32, 256, 128, 2, 2>();
+        case 16: return occ_of<P_BF16, 256, 256, 2, 2, true>();
+        case 17: return occ_of<P_FP8, 256, 256, 2, 2, true>();
+        case 18: return occ_of<P_FP32, 256, 256, 2, 2, true>();
         default: return 0;
     }
 }
@@ -157,6 +167,9 @@ hipError_t launch_batch_tile(int tile_id, const BatchHead* head, const BatchJob*
         case 8: return run_batch<P_BF16, 256, 256, 2, 4>(head, jobs, bctr, grid, st);
         case 10: return run_batch<P_FP8, 256, 256, 2, 4>(head, jobs, bctr, grid, st);
         case 11: return run_batch<P_FP32, 256, 128, 2, 2>(head, jobs, bctr, grid, st);
+        case 16: return run_batch<P_BF16, 256, 256, 2, 2, true>(head, jobs, bctr, grid, st);
+        case 17: return run_batch<P_FP8, 256, 256, 2, 2, true>(head, jobs, bctr, grid, st);
+        case 18: return run_batch<P_FP32, 256, 256, 2, 2, true>(head, jobs, bctr, grid, st);
         default: return hipErrorInvalidValue;
     }
 }

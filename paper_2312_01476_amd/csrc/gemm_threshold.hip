@@ -7,7 +7,7 @@
 
 namespace ej {
 
-template <int PREC, int BM, int BN, int WM, int WN>
+template <int PREC, int BM, int BN, int WM, int WN, bool BIG = false>
 __global__ __launch_bounds__(WM* WN * 64) void threshold_tile(
     const char* __restrict__ A, const char* __restrict__ B, const RowInfo* __restrict__ info_r,
     const RowInfo* __restrict__ info_s, int Kp_bytes, int64_t nR, int64_t nS,
@@ -27,8 +27,13 @@ __global__ __launch_bounds__(WM* WN * 64) void threshold_tile(
     if (bid < full) bid = (bid & 7) * (full >> 3) + (bid >> 3);
     int tm, tn;
     raster_tile(bid, tiles_m, tiles_n, tm, tn);
-    tile_body<PREC, BM, BN, WM, WN>(sm, A, B, info_r, info_s, Kp_bytes, nR, nS, tm, tn, lo, hi,
-                                    out, capacity, hdr + H_OUT, band, band_cap, hdr + H_BAND);
+    if constexpr (BIG)
+        big_tile_body<PREC>(sm, A, B, info_r, info_s, Kp_bytes, nR, nS, tm, tn, lo, hi, out,
+                            capacity, hdr + H_OUT, band, band_cap, hdr + H_BAND);
+    else
+        tile_body<PREC, BM, BN, WM, WN>(sm, A, B, info_r, info_s, Kp_bytes, nR, nS, tm, tn, lo,
+                                        hi, out, capacity, hdr + H_OUT, band, band_cap,
+                                        hdr + H_BAND);
 }
 
 // ---------------------------------------------------------------------------
@@ -51,6 +56,10 @@ static const TileDesc kTiles[] = {
     {13, P_FP8, 0, 0, 128, "fp8:panel"},
     {14, P_BF16, 0, 0, 64, "bf16:panel/2wg"},
     {15, P_FP8, 0, 0, 128, "fp8:panel/2wg"},
+    // 256 x 256 tiles, 128 x 128 per wave, staged single-pass epilogue
+    {16, P_BF16, 256, 256, 64, "bf16:256x256x64/4w/staged"},
+    {17, P_FP8, 256, 256, 128, "fp8:256x256x128/4w/staged"},
+    {18, P_FP32, 256, 256, 32, "fp32:256x256x32/4w/staged"},
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -60,7 +69,7 @@ const TileDesc* tile_get(int id) {
     return nullptr;
 }
 
-template <int PREC, int BM, int BN, int WM, int WN>
+template <int PREC, int BM, int BN, int WM, int WN, bool BIG = false>
 static hipError_t run(const ThresholdArgs& a, hipStream_t st) {
     const int64_t tm = (a.nR + BM - 1) / BM, tn = (a.nS + BN - 1) / BN;
     const int64_t nblocks = tm * tn;
@@ -70,7 +79,7 @@ static hipError_t run(const ThresholdArgs& a, hipStream_t st) {
     const int64_t gy = (nblocks + gx - 1) / gx;
     if (gy > 65535) return hipErrorInvalidValue;
     const int kpb = a.Kp * (PREC == P_FP32 ? 4 : PREC == P_BF16 ? 2 : 1);
-    hipLaunchKernelGGL((threshold_tile<PREC, BM, BN, WM, WN>), dim3((unsigned)gx, (unsigned)gy),
+    hipLaunchKernelGGL((threshold_tile<PREC, BM, BN, WM, WN, BIG>), dim3((unsigned)gx, (unsigned)gy),
                        dim3(WM * WN * 64), 0, st, (const char*)a.A, (const char*)a.B, a.info_r,
                        a.info_s, kpb, a.nR,
                        a.nS, (int)tm, (int)tn, (int)nblocks, a.lo, a.hi, a.out, a.capacity, a.band, a.band_cap,
@@ -95,6 +104,9 @@ hipError_t launch_threshold(int tile_id, const ThresholdArgs& a, hipStream_t st)
         case 13: return launch_threshold_panel(P_FP8, false, a, st);
         case 14: return launch_threshold_panel(P_BF16, true, a, st);
         case 15: return launch_threshold_panel(P_FP8, true, a, st);
+        case 16: return run<P_BF16, 256, 256, 2, 2, true>(a, st);
+        case 17: return run<P_FP8, 256, 256, 2, 2, true>(a, st);
+        case 18: return run<P_FP32, 256, 256, 2, 2, true>(a, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -22,6 +22,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "epi_stage.hpp"
 #include "mma.hpp"
 
 namespace ej {
@@ -297,4 +298,37 @@ __device__ __forceinline__ void tile_body(
             }
 }
 
+// 256 x 256 tiles computed by 4 waves of 128 x 128 each: per K slice a wave
+// reads 32 KB of fragments from LDS for 64 matrix-core steps, which keeps
+// the LDS below the matrix cores' pace; the 256 accumulators per lane fill
+// the accumulation registers, so the epilogue works in one pass and stages
+// its hits in the operand LDS, which is idle once the contraction is done.
+template <int PREC, bool TAG = false>
+__device__ __forceinline__ void big_tile_body(
+    TileSmem<256, 256, 4>& sm, const char* __restrict__ A, const char* __restrict__ B,
+    const RowInfo* __restrict__ info_r, const RowInfo* __restrict__ info_s, int Kp_bytes,
+    int64_t nR, int64_t nS, int tm, int tn, float lo, float hi, Pair* __restrict__ out,
+    int64_t capacity, unsigned long long* __restrict__ out_ctr, void* __restrict__ band,
+    int64_t band_cap, unsigned long long* __restrict__ band_ctr, int job = 0,
+    const int32_t* __restrict__ perm_r = nullptr, const int32_t* __restrict__ perm_s = nullptr) {
+    typedef TileGeom<256, 256, 2, 2> TG;
+    typedef typename BandEntryT<TAG>::type BE;
+    v16f acc[TG::FM][TG::FN];
+    tile_mainloop<PREC, 256, 256, 2, 2>(sm, A, B, info_r, info_s, Kp_bytes, tm, tn, acc);
+    // the mainloop ends on a barrier: the operand LDS is free for staging
+    constexpr int PER_WAVE = ST_OUT * (int)sizeof(Pair) + ST_BAND * (int)sizeof(BE);
+    static_assert(4 * PER_WAVE <= (int)sizeof(sm.sA), "staging does not fit");
+    const int wave = threadIdx.x >> 6;
+    const int wm = wave / 2, wn = wave % 2;
+    char* base = &sm.sA[0][0] + wave * PER_WAVE;
+    const bool edge = ((int64_t)(tm + 1) * 256 > nR) || ((int64_t)(tn + 1) * 256 > nS);
+    stage_epilogue<TG::FM, TG::FN, TAG>(acc, (int64_t)tm * 256 + wm * TG::WTM,
+                                        (int64_t)tn * 256 + wn * TG::WTN, edge, nR, nS, lo, hi,
+                                        out, capacity, out_ctr, band, band_cap, band_ctr, job,
+                                        perm_r, perm_s, (Pair*)base,
+                                        (BE*)(base + ST_OUT * sizeof(Pair)));
+    __syncthreads();  // staging area is the next tile's operand buffer
+}
+
 }  // namespace ej
+

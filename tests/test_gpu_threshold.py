@@ -200,14 +200,14 @@ def test_invalid_arguments():
         E.threshold(R, R, 0.5, band=1e-9)  # narrower than the rigorous bound
 
 
-@pytest.mark.parametrize("tile", [1, 2, 11])
+@pytest.mark.parametrize("tile", [1, 2, 11, 18])
 def test_tile_shapes_give_identical_sets_fp32(tile):
     w = G.WORKLOADS["fp32_100k"]
     R, S, lr, ls = G.make_host(w, n_r=3000, n_s=2500)
     _check(R, S, w.theta, d=w.d, tile=tile)
 
 
-@pytest.mark.parametrize("tile", [3, 4, 8, 12, 14])
+@pytest.mark.parametrize("tile", [3, 4, 8, 12, 14, 16])
 def test_tile_shapes_bf16(tile):
     w = G.WORKLOADS["bf16_1m"]
     R, S, lr, ls = G.make_host(w, n_r=2000, n_s=3000)
@@ -215,7 +215,7 @@ def test_tile_shapes_bf16(tile):
     assert st["n_pairs"] == int((lr[:, None] == ls[None, :]).sum())
 
 
-@pytest.mark.parametrize("tile", [5, 6, 10, 13])
+@pytest.mark.parametrize("tile", [5, 6, 10, 13, 17])
 def test_tile_shapes_fp8(tile):
     w = G.WORKLOADS["fp8_topk_2m"]
     R, S, lr, ls = G.make_host(w, n_r=1000, n_s=1500)
