@@ -19,7 +19,7 @@
 namespace ej {
 
 template <int PREC, int BM, int BN, int WM, int WN, bool BIG = false>
-__global__ __launch_bounds__(WM* WN * 64) void batch_tile(const BatchHead* __restrict__ head,
+__global__ __launch_bounds__(WM* WN * 64, (BM * BN <= 128 * 128) ? 2 : 1) void batch_tile(const BatchHead* __restrict__ head,
                                                           const BatchJob* __restrict__ jobs,
                                                           unsigned long long* __restrict__ bctr) {
     __shared__ TileSmem<BM, BN, WM * WN> sm;

@@ -7,8 +7,10 @@
 
 namespace ej {
 
+// Tiles of up to 128 x 128 are held to two resident workgroups per CU
+// (256 registers per lane), which their accumulators allow.
 template <int PREC, int BM, int BN, int WM, int WN, bool BIG = false>
-__global__ __launch_bounds__(WM* WN * 64) void threshold_tile(
+__global__ __launch_bounds__(WM* WN * 64, (BM * BN <= 128 * 128) ? 2 : 1) void threshold_tile(
     const char* __restrict__ A, const char* __restrict__ B, const RowInfo* __restrict__ info_r,
     const RowInfo* __restrict__ info_s, int Kp_bytes, int64_t nR, int64_t nS,
     int tiles_m, int tiles_n, int ntiles, float lo, float hi, Pair* __restrict__ out,
