@@ -34,6 +34,12 @@ PEAK = {  # MI355X published dense peaks
 }
 DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}
 
+# HBM bytes per launch of the dominant kernel from FETCH_SIZE / WRITE_SIZE
+# counter runs scaled by a plain copy of known size (the commands and the raw
+# figures are in profiles/threshold_fp32_100k_traffic.md); valid for the
+# kernel as it was when the counters were taken, keyed by workload and tile
+TRAFFIC = {("fp32_100k", "fp32:128x128x32"): 6198814.7 * 1024 * 2.0 + 618113.3 * 1024 * 1.0}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -80,6 +86,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="fp32_100k")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only copy a BYTES-sized device buffer 3 times (reference kernel "
+                         "for scaling the HBM traffic counters) and exit")
     ap.add_argument("--autotune", action="store_true",
                     help="batched workloads: time every tile first and use the fastest")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -94,6 +103,16 @@ def main():
     import torch
     from paper_2312_01476_amd import datagen as G
     from paper_2312_01476_amd import ejoin as E
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {n * 4} bytes 3 times")
+        return
 
     w = G.WORKLOADS[args.workload]
     if w.k is not None:
@@ -145,9 +164,13 @@ def main():
     flops = 2.0 * w.d * pairs
     achieved = flops / (ms_main * 1e-3) / 1e12
     unit, peak = PEAK[prec]
+    tile_name = E.lib().ejoin_tile_name(st["tile"]).decode()
+    kname = "panel_kernel<ThresholdEpi>" if "panel" in tile_name else "threshold_tile"
+    traffic = TRAFFIC.get((w.name, tile_name))
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": unit,
-            "frac": round(achieved / peak, 4), "traffic": None,
-            "kernel": "threshold_tile", "kernel_ms": round(ms_main, 4),
+            "frac": round(achieved / peak, 4),
+            "traffic": round(traffic) if traffic else None,
+            "kernel": kname, "kernel_ms": round(ms_main, 4),
             "algorithmic_flops_per_launch": flops}
 
     verify = None
