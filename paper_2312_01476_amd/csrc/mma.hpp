@@ -24,6 +24,7 @@ struct Mma<P_FP32> {
     // A k-group is two chunks (half h reads chunk 2g+h) = 4 MFMAs.
     static constexpr int GROUPS = 4;     // k-groups per 128-byte slice
     static constexpr int CPL = 1;        // chunks per lane per group
+    static constexpr int SUB = 4;        // matrix-core steps per fragment pair
     typedef v4i Frag;
     static __device__ __forceinline__ int chunk(int g, int h, int c) { return 2 * g + h; }
     static __device__ __forceinline__ void mma(const Frag& a, const Frag& b, v16f& acc, int, int) {
@@ -32,6 +33,12 @@ struct Mma<P_FP32> {
             acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(a[j]), __int_as_float(b[j]),
                                                        acc, 0, 0, 0);
     }
+    // step j only: callers interleave the steps of independent accumulators
+    static __device__ __forceinline__ void mma_sub(const Frag& a, const Frag& b, v16f& acc, int,
+                                                   int, int j) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(a[j]), __int_as_float(b[j]), acc,
+                                                   0, 0, 0);
+    }
 };
 
 template <>
@@ -39,11 +46,16 @@ struct Mma<P_BF16> {
     // v_mfma_f32_32x32x16_bf16: per lane 8 bf16 (one chunk) of A and of B.
     static constexpr int GROUPS = 4;
     static constexpr int CPL = 1;
+    static constexpr int SUB = 1;
     typedef v4i Frag;
     static __device__ __forceinline__ int chunk(int g, int h, int c) { return 2 * g + h; }
     static __device__ __forceinline__ void mma(const Frag& a, const Frag& b, v16f& acc, int, int) {
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a),
                                                       __builtin_bit_cast(v8bf, b), acc, 0, 0, 0);
+    }
+    static __device__ __forceinline__ void mma_sub(const Frag& a, const Frag& b, v16f& acc, int sa,
+                                                   int sb, int) {
+        mma(a, b, acc, sa, sb);
     }
 };
 
@@ -56,11 +68,16 @@ struct Mma<P_FP8> {
     // so the accumulator is the dot of the normalised rows directly.
     static constexpr int GROUPS = 2;
     static constexpr int CPL = 2;
+    static constexpr int SUB = 1;
     typedef v8i Frag;
     static __device__ __forceinline__ int chunk(int g, int h, int c) { return 4 * g + 2 * h + c; }
     static __device__ __forceinline__ void mma(const Frag& a, const Frag& b, v16f& acc, int sa,
                                                int sb) {
         acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, sa, 0, sb);
+    }
+    static __device__ __forceinline__ void mma_sub(const Frag& a, const Frag& b, v16f& acc, int sa,
+                                                   int sb, int) {
+        mma(a, b, acc, sa, sb);
     }
 };
 

@@ -166,10 +166,15 @@ __device__ __forceinline__ void tile_mainloop(
                     for (int e = 0; e < 4; ++e) fb[j][c * 4 + e] = v[e];
                 }
             }
+            // sub-steps outermost: consecutive matrix-core steps go to
+            // different accumulators, none waits on the previous one
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+            for (int u = 0; u < M::SUB; ++u)
 #pragma unroll
-                for (int j = 0; j < FN; ++j) M::mma(fa[i], fb[j], acc[i][j], sa[i], sb[j]);
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        M::mma_sub(fa[i], fb[j], acc[i][j], sa[i], sb[j], u);
         }
         if (kb + 1 < nk) lstore(st ^ 1);
         __syncthreads();
