@@ -368,6 +368,7 @@ ejoin_status ejoin_threshold(const ejoin_rel* R, const ejoin_rel* S, double thet
     a.band = band;
     a.band_cap = p.band_cap;
     a.hdr = hdr;
+    a.kg_last = last_slice_groups(p.prec, p.dim);
     HIP_TRY(launch_threshold(p.tile, a, stream));
     HIP_TRY(rec(2));
     HIP_TRY(launch_rescore_band(R->data, R->ld, S->data, S->ld, p.dim, band, p.band_cap, theta,

@@ -173,6 +173,7 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         b.tiles_n = empty ? 0 : (int32_t)((u.S.rows + bp.bn - 1) / bp.bn);
         b.Kp_bytes = Kp * (int)eb;
         b.dim = dim;
+        b.kg_last = last_slice_groups(o.prec, dim);
         b.user = order[q];
         b.tile_base = tile_base;
         tile_base += (int64_t)b.tiles_m * b.tiles_n;

@@ -72,12 +72,14 @@ __global__ __launch_bounds__(WM* WN * 64, (BM * BN <= 128 * 128) ? 2 : 1) void b
         if constexpr (BIG)
             big_tile_body<PREC, true>(sm, J.A, J.B, J.info_r, J.info_s, J.Kp_bytes, J.nR, J.nS, tm,
                                       tn, J.lo, J.hi, J.out, J.capacity, J.hdr + H_OUT, band,
-                                      band_cap, bctr + B_BAND, job, J.perm_r, J.perm_s);
+                                      band_cap, bctr + B_BAND, job, J.perm_r, J.perm_s,
+                                      J.kg_last);
         else
             tile_body<PREC, BM, BN, WM, WN, true>(sm, J.A, J.B, J.info_r, J.info_s, J.Kp_bytes,
                                                   J.nR, J.nS, tm, tn, J.lo, J.hi, J.out,
                                                   J.capacity, J.hdr + H_OUT, band, band_cap,
-                                                  bctr + B_BAND, job, J.perm_r, J.perm_s);
+                                                  bctr + B_BAND, job, J.perm_r, J.perm_s,
+                                                  J.kg_last);
     }
 }
 

@@ -15,7 +15,7 @@ __global__ __launch_bounds__(WM* WN * 64, (BM * BN <= 128 * 128) ? 2 : 1) void t
     const RowInfo* __restrict__ info_s, int Kp_bytes, int64_t nR, int64_t nS,
     int tiles_m, int tiles_n, int ntiles, float lo, float hi, Pair* __restrict__ out,
     int64_t capacity, int2* __restrict__ band, int64_t band_cap,
-    unsigned long long* __restrict__ hdr) {
+    unsigned long long* __restrict__ hdr, int kg_last) {
     __shared__ TileSmem<BM, BN, WM * WN> sm;
     // 2-D grid (a 1-D grid of this many workgroups would overflow the 32-bit
     // dispatch size); workgroups past the last tile leave at once
@@ -31,11 +31,12 @@ __global__ __launch_bounds__(WM* WN * 64, (BM * BN <= 128 * 128) ? 2 : 1) void t
     raster_tile(bid, tiles_m, tiles_n, tm, tn);
     if constexpr (BIG)
         big_tile_body<PREC>(sm, A, B, info_r, info_s, Kp_bytes, nR, nS, tm, tn, lo, hi, out,
-                            capacity, hdr + H_OUT, band, band_cap, hdr + H_BAND);
+                            capacity, hdr + H_OUT, band, band_cap, hdr + H_BAND, 0, nullptr,
+                            nullptr, kg_last);
     else
         tile_body<PREC, BM, BN, WM, WN>(sm, A, B, info_r, info_s, Kp_bytes, nR, nS, tm, tn, lo,
                                         hi, out, capacity, hdr + H_OUT, band, band_cap,
-                                        hdr + H_BAND);
+                                        hdr + H_BAND, 0, nullptr, nullptr, kg_last);
 }
 
 // ---------------------------------------------------------------------------
@@ -85,7 +86,7 @@ static hipError_t run(const ThresholdArgs& a, hipStream_t st) {
                        dim3(WM * WN * 64), 0, st, (const char*)a.A, (const char*)a.B, a.info_r,
                        a.info_s, kpb, a.nR,
                        a.nS, (int)tm, (int)tn, (int)nblocks, a.lo, a.hi, a.out, a.capacity, a.band, a.band_cap,
-                       a.hdr);
+                       a.hdr, a.kg_last);
     return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ struct ThresholdArgs {
     int2* band;
     int64_t band_cap;
     unsigned long long* hdr;
+    int kg_last;     // k-groups of the last K slice that hold data
 };
 hipError_t launch_threshold(int tile_id, const ThresholdArgs& a, hipStream_t st);
 hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs& a,

@@ -27,6 +27,16 @@ inline int padded_k(int prec, int dim) {
     return ((dim + per - 1) / per) * per;
 }
 
+// k-groups (elements per matrix-core step group: FP32 8, BF16 16, FP8 64)
+// of the last 128-byte K slice that hold data
+inline int last_slice_groups(int prec, int dim) {
+    const int per = 128 / elem_bytes(prec);
+    const int gsz = prec == P_FP32 ? 8 : prec == P_BF16 ? 16 : 64;
+    const int Kp = padded_k(prec, dim);
+    const int rem = dim - (Kp - per);  // elements of the last slice, 1..per
+    return (rem + gsz - 1) / gsz;
+}
+
 inline int64_t padded_rows(int64_t rows) { return ((rows + 255) / 256) * 256; }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }

@@ -21,6 +21,8 @@
 // (hits of lower lanes, mbcnt).
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "epi_stage.hpp"
 #include "mma.hpp"
@@ -65,12 +67,15 @@ struct TileGeom {
 // of this wave's WTM x WTN part of A_tile B_tile^T.  Both operands are
 // K-contiguous rows of Kp_bytes bytes (a multiple of 128); rows up to the
 // end of the tile must be readable.  info_r / info_s give the FP8 row scales
-// (unused otherwise).  All threads of the workgroup call this.
+// (unused otherwise).  Only the first kg_last k-groups of the last slice are
+// contracted (the rest of it is zero padding).  All threads of the workgroup
+// call this.
 template <int PREC, int BM, int BN, int WM, int WN>
 __device__ __forceinline__ void tile_mainloop(
     TileSmem<BM, BN, WM * WN>& sm, const char* __restrict__ A, const char* __restrict__ B,
     const RowInfo* __restrict__ info_r, const RowInfo* __restrict__ info_s, int Kp_bytes, int tm,
-    int tn, v16f (&acc)[TileGeom<BM, BN, WM, WN>::FM][TileGeom<BM, BN, WM, WN>::FN]) {
+    int tn, v16f (&acc)[TileGeom<BM, BN, WM, WN>::FM][TileGeom<BM, BN, WM, WN>::FN],
+    int kg_last = Mma<PREC>::GROUPS) {
     typedef TileGeom<BM, BN, WM, WN> TG;
     constexpr int NT = TG::NT;
     constexpr int WTM = TG::WTM, WTN = TG::WTN, FM = TG::FM, FN = TG::FN;
@@ -137,14 +142,11 @@ __device__ __forceinline__ void tile_mainloop(
         }
     };
 
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int kb = 0; kb < nk; ++kb) {
-        const int st = kb & 1;
-        if (kb + 1 < nk) gload(kb + 1);
+    // the matrix-core steps of the first NG k-groups of the slice in stage st
+    auto compute = [&](int st, auto ng_c) {
+        constexpr int NG = decltype(ng_c)::value;
 #pragma unroll
-        for (int g = 0; g < M::GROUPS; ++g) {
+        for (int g = 0; g < NG; ++g) {
             typename M::Frag fa[FM], fb[FN];
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
@@ -176,10 +178,38 @@ __device__ __forceinline__ void tile_mainloop(
                     for (int j = 0; j < FN; ++j)
                         M::mma_sub(fa[i], fb[j], acc[i][j], sa[i], sb[j], u);
         }
-        if (kb + 1 < nk) lstore(st ^ 1);
+    };
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int kb = 0; kb + 1 < nk; ++kb) {
+        const int st = kb & 1;
+        gload(kb + 1);
+        compute(st, std::integral_constant<int, M::GROUPS>{});
+        lstore(st ^ 1);
         __syncthreads();
     }
-
+    const int st_last = (nk - 1) & 1;
+    if constexpr (BM * BN > 128 * 128) {
+        // the largest tiles have no registers to spare for more copies of
+        // the slice code: they contract the last slice whole
+        compute(st_last, std::integral_constant<int, M::GROUPS>{});
+    } else {
+        // last slice: only its k-groups that hold data (a uniform switch, so
+        // the steady-state loop above keeps its fully unrolled schedule)
+        switch (kg_last) {
+            case 1: compute(st_last, std::integral_constant<int, 1>{}); break;
+            case 2:
+                if constexpr (M::GROUPS >= 2) compute(st_last, std::integral_constant<int, 2>{});
+                break;
+            case 3:
+                if constexpr (M::GROUPS >= 3) compute(st_last, std::integral_constant<int, 3>{});
+                break;
+            default: compute(st_last, std::integral_constant<int, M::GROUPS>{}); break;
+        }
+    }
+    __syncthreads();
 }
 
 // All threads of the workgroup call this for tile (tm, tn).  out_ctr and
@@ -194,7 +224,8 @@ __device__ __forceinline__ void tile_body(
     int64_t nR, int64_t nS, int tm, int tn, float lo, float hi, Pair* __restrict__ out,
     int64_t capacity, unsigned long long* __restrict__ out_ctr, void* __restrict__ band,
     int64_t band_cap, unsigned long long* __restrict__ band_ctr, int job = 0,
-    const int32_t* __restrict__ perm_r = nullptr, const int32_t* __restrict__ perm_s = nullptr) {
+    const int32_t* __restrict__ perm_r = nullptr, const int32_t* __restrict__ perm_s = nullptr,
+    int kg_last = Mma<PREC>::GROUPS) {
     typedef TileGeom<BM, BN, WM, WN> TG;
     constexpr int NW = TG::NW;
     constexpr int WTM = TG::WTM, WTN = TG::WTN, FM = TG::FM, FN = TG::FN;
@@ -207,7 +238,7 @@ __device__ __forceinline__ void tile_body(
     const int h = lane >> 5, r32 = lane & 31;
 
     v16f acc[FM][FN];
-    tile_mainloop<PREC, BM, BN, WM, WN>(sm, A, B, info_r, info_s, Kp_bytes, tm, tn, acc);
+    tile_mainloop<PREC, BM, BN, WM, WN>(sm, A, B, info_r, info_s, Kp_bytes, tm, tn, acc, kg_last);
 
     // ---- epilogue ----
     // accumulator element e of block (i, j) of this lane sits at
@@ -315,11 +346,12 @@ __device__ __forceinline__ void big_tile_body(
     int64_t nR, int64_t nS, int tm, int tn, float lo, float hi, Pair* __restrict__ out,
     int64_t capacity, unsigned long long* __restrict__ out_ctr, void* __restrict__ band,
     int64_t band_cap, unsigned long long* __restrict__ band_ctr, int job = 0,
-    const int32_t* __restrict__ perm_r = nullptr, const int32_t* __restrict__ perm_s = nullptr) {
+    const int32_t* __restrict__ perm_r = nullptr, const int32_t* __restrict__ perm_s = nullptr,
+    int kg_last = Mma<PREC>::GROUPS) {
     typedef TileGeom<256, 256, 2, 2> TG;
     typedef typename BandEntryT<TAG>::type BE;
     v16f acc[TG::FM][TG::FN];
-    tile_mainloop<PREC, 256, 256, 2, 2>(sm, A, B, info_r, info_s, Kp_bytes, tm, tn, acc);
+    tile_mainloop<PREC, 256, 256, 2, 2>(sm, A, B, info_r, info_s, Kp_bytes, tm, tn, acc, kg_last);
     // the mainloop ends on a barrier: the operand LDS is free for staging
     constexpr int PER_WAVE = ST_OUT * (int)sizeof(Pair) + ST_BAND * (int)sizeof(BE);
     static_assert(4 * PER_WAVE <= (int)sizeof(sm.sA), "staging does not fit");
