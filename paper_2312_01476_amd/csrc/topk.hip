@@ -439,6 +439,192 @@ __global__ __launch_bounds__(256) void topk_finalize(
     }
 }
 
+// ---------------------------------------------------------------------------
+// wave-per-row finalize
+// ---------------------------------------------------------------------------
+// One wave owns one R row: no workgroup barriers.  The k-th best candidate
+// and the final order come from ranks (each lane counts the entries that beat
+// its own); the FP64 dots stage the row chunk and the 64 candidate rows of a
+// pass through the wave's LDS, so global reads are whole row segments while
+// each lane keeps the sequential order of its own sum.
+constexpr int FW_WAVES = 4;
+constexpr int FW_CH = 32;
+constexpr int FW_STRIDE = FW_CH + 1;
+
+struct FinSmem {
+    double v[FW_WAVES][256];
+    int j[FW_WAVES][256];
+    int live[FW_WAVES][256];
+    float rows[FW_WAVES][64 * FW_STRIDE];
+    float rch[FW_WAVES][FW_CH];
+    double lim[FW_WAVES];
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t lane_u32(uint64_t w, int i) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)w, i);
+}
+
+// lane l: sequential FP64 dot of the row `r` with S row sj (valid lanes only)
+__device__ __forceinline__ double wave_dot64(const float* __restrict__ r,
+                                             const float* __restrict__ S, int64_t ldS, int sj,
+                                             bool valid, int dim, float* rows, float* rch) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t sp = valid ? (uint64_t)(S + (int64_t)sj * ldS) : 0ull;
+    const uint64_t vmask = __ballot(valid);
+    double acc = 0.0;
+    for (int k0 = 0; k0 < dim; k0 += FW_CH) {
+        const int kn = min(FW_CH, dim - k0);
+        if (lane < kn) rch[lane] = r[k0 + lane];
+        // two candidate rows per load instruction (lanes 0-31 one, 32-63 the
+        // next), 16 instructions in flight before their values go to LDS
+        const int kk = lane & 31;
+        for (int b0 = 0; b0 < 64; b0 += 32) {
+            float vals[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i0 = b0 + 2 * q;
+                const int i = i0 + (lane >> 5);
+                const uint64_t p0 = ((uint64_t)lane_u32(sp >> 32, i0) << 32) | lane_u32(sp, i0);
+                const uint64_t p1 =
+                    ((uint64_t)lane_u32(sp >> 32, i0 + 1) << 32) | lane_u32(sp, i0 + 1);
+                const float* base = (const float*)(lane < 32 ? p0 : p1);
+                const bool have = (vmask >> i) & 1ull;
+                vals[q] = (have && kk < kn) ? base[k0 + kk] : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                rows[(b0 + 2 * q + (lane >> 5)) * FW_STRIDE + kk] = vals[q];
+        }
+        wave_sync();
+        if (valid) {
+            const float* mine = rows + lane * FW_STRIDE;
+            for (int kk = 0; kk < kn; ++kk) acc = acc + (double)rch[kk] * (double)mine[kk];
+        }
+        wave_sync();
+    }
+    return acc;
+}
+
+__global__ __launch_bounds__(256) void topk_finalize_w(
+    const float* __restrict__ R, int64_t ldR, const float* __restrict__ S, int64_t ldS, int dim,
+    int64_t nR, int64_t nS, const double* __restrict__ nr64, const double* __restrict__ ns64,
+    const RowInfo* __restrict__ info_r, const int* __restrict__ cnt,
+    const int2* __restrict__ cand, int Kc, int k, double fp32_terms,
+    const int* __restrict__ order, unsigned long long* __restrict__ hdr,
+    int* __restrict__ fb_rows, int32_t* __restrict__ out_idx, float* __restrict__ out_score) {
+    __shared__ FinSmem sm;
+    if (hdr[H_FLAGS] != 0) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double* v = sm.v[w];
+    int* jv = sm.j[w];
+    int* live = sm.live[w];
+    const float F = __uint_as_float((uint32_t)hdr[H_TOPK_F]);
+    const double es = (double)__uint_as_float((uint32_t)hdr[H_ENORM_S]) * 1.001 + 1e-7;
+    const int kk = (int)min((int64_t)k, nS);
+
+    for (int64_t rr = (int64_t)blockIdx.x * FW_WAVES + w; rr < nR;
+         rr += (int64_t)gridDim.x * FW_WAVES) {
+        const int64_t i = order ? order[rr] : rr;
+        if (nS == 0) {  // nothing to join: every slot is padding
+            for (int t = lane; t < k; t += 64) {
+                out_idx[i * k + t] = -1;
+                out_score[i * k + t] = -INFINITY;
+            }
+            continue;
+        }
+        const int c = cnt[i];
+        const int n = min(c, Kc);
+        const double er = (double)info_r[i].enorm * 1.001 + 1e-7;
+        const double di = er * (1.0 + es) + es + fp32_terms * (1.0 + er) * (1.0 + es);
+        for (int t = lane; t < 256; t += 64) {
+            if (t < n) {
+                const int2 e = cand[i * (int64_t)Kc + t];
+                v[t] = (double)__int_as_float(e.y);
+                jv[t] = e.x;
+            } else {
+                v[t] = -INFINITY;
+                jv[t] = 0x7fffffff;
+            }
+        }
+        if (lane == 0) sm.lim[w] = -INFINITY;
+        wave_sync();
+        bool ok = c <= Kc;
+        if (ok) {
+            if (F == -INFINITY) {
+                ok = (int64_t)n == nS;  // every column present
+            } else {
+                ok = n >= kk;
+                if (ok) {
+                    // the entry of rank kk-1 among the n candidates
+                    for (int t = lane; t < n; t += 64) {
+                        const double vt = v[t];
+                        const int jt = jv[t];
+                        int rank = 0;
+                        for (int u = 0; u < n; ++u) rank += better(v[u], jv[u], vt, jt);
+                        if (rank == kk - 1) sm.lim[w] = vt - 2.0 * di;
+                    }
+                    wave_sync();
+                    ok = sm.lim[w] >= (double)F;
+                }
+            }
+        }
+        if (!ok) {  // wave-uniform
+            if (lane == 0) {
+                const unsigned long long p = atomicAdd(hdr + H_TOPK_FB, 1ull);
+                fb_rows[p] = (int)i;
+            }
+            wave_sync();
+            continue;
+        }
+        const double lim = sm.lim[w];
+        // compact the candidates that can still be in the top k
+        int n_live = 0;
+        for (int t0 = 0; t0 < n; t0 += 64) {
+            const int t = t0 + lane;
+            const bool lv = t < n && v[t] >= lim;
+            const uint64_t m = __ballot(lv);
+            if (lv) live[n_live + lanes_below(m)] = jv[t];
+            n_live += __popcll(m);
+        }
+        wave_sync();
+        // FP64 rescore of the live candidates, 64 per pass
+        const float* rrow = R + i * ldR;
+        for (int p0 = 0; p0 < n_live; p0 += 64) {
+            const int t = p0 + lane;
+            const bool valid = t < n_live;
+            const int sj = valid ? live[t] : 0;
+            const double dot = wave_dot64(rrow, S, ldS, sj, valid, dim, sm.rows[w], sm.rch[w]);
+            if (valid) {
+                v[t] = sim64_from(dot, nr64[i], ns64[sj]);
+                jv[t] = sj;
+            }
+        }
+        wave_sync();
+        // final order by rank among the live entries
+        for (int t = lane; t < n_live; t += 64) {
+            const double vt = v[t];
+            const int jt = jv[t];
+            int rank = 0;
+            for (int u = 0; u < n_live; ++u) rank += better(v[u], jv[u], vt, jt);
+            if (rank < kk) {
+                out_idx[i * k + rank] = jt;
+                out_score[i * k + rank] = (float)vt;
+            }
+        }
+        for (int t = kk + lane; t < k; t += 64) {
+            out_idx[i * k + t] = -1;
+            out_score[i * k + t] = -INFINITY;
+        }
+        wave_sync();
+    }
+}
+
 // pilot rows: evenly spaced sample of R
 __global__ void pilot_rows(int* rows, int n_pilot, int64_t nR) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -505,8 +691,9 @@ hipError_t launch_topk_finalize(const TopkArgs& a, hipStream_t st) {
                            a.order);
         order = a.order;
     }
-    int64_t nb = a.nR < 65536 ? a.nR : 65536;
-    hipLaunchKernelGGL(topk_finalize, dim3((unsigned)nb), dim3(256), 0, st, a.R, a.ldR, a.S,
+    int64_t nb = (a.nR + FW_WAVES - 1) / FW_WAVES;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(topk_finalize_w, dim3((unsigned)nb), dim3(256), 0, st, a.R, a.ldR, a.S,
                        a.ldS, a.dim, a.nR, a.nS, a.nr64, a.ns64, a.info_r, a.cnt, a.cand, a.Kc,
                        a.k, a.fp32_terms, order, a.hdr, a.fb_rows, a.out_idx, a.out_score);
     return hipGetLastError();
