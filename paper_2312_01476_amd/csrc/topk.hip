@@ -64,10 +64,22 @@ __device__ double block_dots(const float* __restrict__ X, int64_t ldX,
     double acc = 0.0;
     for (int k0 = 0; k0 < dim; k0 += SD_CH) {
         const int kn = min(SD_CH, dim - k0);
-        for (int q = tid; q < 256 * SD_CH; q += 256) {
-            const int ri = q / SD_CH, kk = q - ri * SD_CH;
-            const int64_t row = sm.row_of[ri];
-            sm.tile[ri][kk] = (row >= 0 && kk < kn) ? X[row * ldX + k0 + kk] : 0.0f;
+        // 16 loads in flight per thread before their values go to LDS
+        for (int q0 = 0; q0 < 256 * SD_CH; q0 += 16 * 256) {
+            float vals[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int q = q0 + u * 256 + tid;
+                const int ri = q / SD_CH, kk = q - ri * SD_CH;
+                const int64_t row = sm.row_of[ri];
+                vals[u] = (row >= 0 && kk < kn) ? X[row * ldX + k0 + kk] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int q = q0 + u * 256 + tid;
+                const int ri = q / SD_CH, kk = q - ri * SD_CH;
+                sm.tile[ri][kk] = vals[u];
+            }
         }
         if (r && tid < kn) sm.rch[tid] = r[k0 + tid];
         __syncthreads();
