@@ -433,13 +433,26 @@ static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const vo
 #define EJ_RUN(KS_, RB_, CB_, OCC_) \
     return run_panel<PREC, KS_, RB_, CB_, OCC_, EPI>(A, B, ir, is, nR, nS, split_s, hdr, ep, st)
     if (two_waves) {
-        switch (ks) {
-            case 1: EJ_RUN(1, 1, 4, 2);
-            case 2: EJ_RUN(2, 1, 4, 2);
-            case 3: EJ_RUN(3, 1, 4, 2);
-            case 4: EJ_RUN(4, 1, 4, 2);
-            case 5: EJ_RUN(5, 1, 4, 2);
-            case 6: EJ_RUN(6, 1, 4, 2);
+        if constexpr (PREC == P_BF16) {
+            switch (ks) {
+                case 1: EJ_RUN(1, 1, 4, 2);
+                case 2: EJ_RUN(2, 1, 4, 2);
+                case 3: EJ_RUN(3, 1, 4, 2);
+                case 4: EJ_RUN(4, 1, 4, 2);
+                case 5: EJ_RUN(5, 1, 4, 2);
+                case 6: EJ_RUN(6, 1, 4, 2);
+            }
+        } else {
+            // FP8 fragments are twice as wide: one S block per tile keeps the
+            // deep panels within the register file at two workgroups per CU
+            switch (ks) {
+                case 1: EJ_RUN(1, 1, 4, 2);
+                case 2: EJ_RUN(2, 1, 2, 2);
+                case 3: EJ_RUN(3, 1, 1, 2);
+                case 4: EJ_RUN(4, 1, 1, 2);
+                case 5: EJ_RUN(5, 1, 1, 2);
+                case 6: EJ_RUN(6, 1, 1, 2);
+            }
         }
         return hipErrorInvalidValue;
     }
@@ -506,7 +519,7 @@ hipError_t launch_topk_candidates(int prec, const CandArgs& a, hipStream_t st) {
         return dispatch_panel<P_BF16, CandEpi>(ks, true, a.A, a.B, a.info_r, a.info_s, a.nR,
                                                a.nS, false, a.hdr, ep, st);
     if (prec == P_FP8)
-        return dispatch_panel<P_FP8, CandEpi>(ks, false, a.A, a.B, a.info_r, a.info_s, a.nR,
+        return dispatch_panel<P_FP8, CandEpi>(ks, true, a.A, a.B, a.info_r, a.info_s, a.nR,
                                               a.nS, false, a.hdr, ep, st);
     return hipErrorInvalidValue;
 }
