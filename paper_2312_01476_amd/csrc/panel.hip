@@ -24,8 +24,8 @@
 
 namespace ej {
 
-constexpr int PN_OUTCAP = 512;   // staged certain pairs per wave
-constexpr int PN_BANDCAP = 512;  // staged band pairs per wave
+constexpr int PN_OUTCAP = 384;   // staged certain pairs per wave
+constexpr int PN_BANDCAP = 384;  // staged band pairs per wave
 
 // Append the staged entries of one wave to a global list: one atomicAdd on
 // the list counter, then a coalesced copy.  Entries past `cap` are dropped
@@ -243,9 +243,110 @@ struct CandEpi {
 // ---------------------------------------------------------------------------
 // the panel kernel
 // ---------------------------------------------------------------------------
+// Wait until at most N global memory operations of this wave are in flight
+// and all its LDS operations are done (gfx9 s_waitcnt encoding: vmcnt in bits
+// 3:0 and 15:14, expcnt 6:4 left at its maximum, lgkmcnt 11:8 = 0).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt_lgkm0() {
+    static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
+
+// Workgroup barrier without a memory fence: the waits before it are the
+// caller's, and the direct-load fills in flight stay in flight across it.
+// The signal fences keep the compiler from moving memory accesses across.
+__device__ __forceinline__ void bare_barrier() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Fill ring slot `dst` with one K slice of an S tile (`src`: the slice's
+// first byte, the same for the whole wave) by direct global->LDS loads.
+// Instruction i of wave w fills LDS rows 8 (4 i + w) .. +7, lane l writing the
+// 16 bytes at l * 16 of that 1 KB block, so the lane loads the chunk that the
+// XOR swizzle of lds_off places there: row r = 8 (4 i + w) + l / 8, chunk
+// (l % 8) ^ ((r / 2) % 8).  The chunk does not depend on i (r / 2 moves by 16
+// per i), so the lane's source offset for instruction i is `loff` (that of
+// i = 0, see ring_lane_offset) plus i * 32 rows.
+template <int KPB, int PN_BN, int NCH>
+__device__ __forceinline__ void ring_fill(char* dst, const char* src, uint32_t loff, int wave) {
+#pragma unroll
+    for (int i = 0; i < NCH; ++i)
+        __builtin_amdgcn_global_load_lds((const void*)(src + loff + i * 32 * KPB),
+                                         (__attribute__((address_space(3))) void*)(dst + (4 * i + wave) * 1024),
+                                         16, 0, 0);
+}
+
+template <int KPB>
+__device__ __forceinline__ uint32_t ring_lane_offset(int wave, int lane) {
+    const int row = wave * 8 + (lane >> 3);
+    return (uint32_t)(row * KPB + (((lane & 7) ^ ((row >> 1) & 7)) << 4));
+}
+
+// The KS slices of S tile t on the three-slot direct-load ring: slice q sits
+// in slot q % 3 and is filled two slices ahead.  KS is a multiple of 3, so the
+// slot of every slice is known at compile time; the slots are three separate
+// LDS arrays, which lets the compiler see that the fills in flight never touch
+// the slot being read and keeps it from waiting for them before the LDS reads
+// (the waits for the fills are the explicit vmcnt waits below).
+template <int PREC, int KS, int RB, int CB>
+__device__ __forceinline__ void ring_tile(char* s0, char* s1, char* s2, const char* __restrict__ B,
+                                          uint32_t loff, int t, int t_last,
+                                          const typename Mma<PREC>::Frag (&af)[RB][KS * Mma<PREC>::GROUPS],
+                                          v16f (&acc)[RB][CB], const int (&sa)[RB],
+                                          const int (&sb)[CB], int wave, int lane) {
+    typedef Mma<PREC> M;
+    static_assert(KS % 3 == 0, "the ring slot of a slice must be static");
+    constexpr int G = M::GROUPS;
+    constexpr int KPB = KS * 128;
+    constexpr int PN_BN = 32 * CB;
+    constexpr int NCH = PN_BN * 8 / 256;
+    const int h = lane >> 5, r32 = lane & 31;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        // slice q has landed once at most the next slice's loads are in
+        // flight; the barrier then publishes every wave's part and retires
+        // all reads of slice q - 1, whose slot slice q + 2 takes.  The ring
+        // always runs two fills ahead: past the end of the sweep the fills
+        // reload the last tile (never read), which keeps every wait count
+        // static.
+        wait_vmcnt_lgkm0<NCH>();
+        bare_barrier();
+        {
+            char* dst = (ks + 2) % 3 == 0 ? s0 : (ks + 2) % 3 == 1 ? s1 : s2;
+            const int t2 = min(t + (ks + 2) / KS, t_last), k2 = (ks + 2) % KS;
+            ring_fill<KPB, PN_BN, NCH>(dst, B + (int64_t)t2 * PN_BN * KPB + k2 * 128, loff, wave);
+        }
+        const char* sl = ks % 3 == 0 ? s0 : ks % 3 == 1 ? s1 : s2;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            typename M::Frag fb[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const int row = cb * 32 + r32;
+#pragma unroll
+                for (int c = 0; c < M::CPL; ++c) {
+                    v4i v = *(const v4i*)(sl + lds_off(row, M::chunk(g, h, c)));
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) fb[cb][c * 4 + e] = v[e];
+                }
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    M::mma(af[rb][ks * G + g], fb[cb], acc[rb][cb], sa[rb], sb[cb]);
+        }
+    }
+}
+
 // RB 32-row blocks per wave (4 waves), CB 32-column blocks per S tile, KS
-// 128-byte K slices per row, OCC workgroups per CU.
-template <int PREC, int KS, int RB, int CB, int OCC, class EPI>
+// 128-byte K slices per row, OCC workgroups per CU.  DMA: the S slices go
+// straight from global memory into a three-slot LDS ring (no staging
+// registers) two slices ahead of the MFMAs; otherwise through registers into
+// a two-slot ring one slice ahead.
+template <int PREC, int KS, int RB, int CB, int OCC, bool DMA, class EPI>
 __global__ __launch_bounds__(256, OCC) void panel_kernel(
     const char* __restrict__ A, const char* __restrict__ B, const RowInfo* __restrict__ info_r,
     const RowInfo* __restrict__ info_s, int64_t nR, int64_t nS, int n_panels, int n_items,
@@ -258,8 +359,13 @@ __global__ __launch_bounds__(256, OCC) void panel_kernel(
     constexpr int PN_BN = 32 * CB;
     constexpr int PN_ROWS = 128 * RB;
     constexpr int NCH = PN_BN * 8 / 256;  // 16-byte chunks per thread per S slice
+    static_assert(!DMA || KS % 3 == 0, "direct loads need a static ring slot per slice");
 
-    __shared__ __attribute__((aligned(16))) char sB[2][PN_BN * 128];
+    // register-staged path: two-slot ring sB; direct-load path: slots sB
+    // (first half), sB1 and sB2
+    __shared__ __attribute__((aligned(16))) char sB[DMA ? 1 : 2][PN_BN * 128];
+    __shared__ __attribute__((aligned(16))) char sB1[DMA ? PN_BN * 128 : 16];
+    __shared__ __attribute__((aligned(16))) char sB2[DMA ? PN_BN * 128 : 16];
     __shared__ typename EPI::Smem esm;
 
     const int item = (int)(blockIdx.y * gridDim.x + blockIdx.x);
@@ -338,43 +444,66 @@ __global__ __launch_bounds__(256, OCC) void panel_kernel(
     EPI::init(ep, esm, est, ctx);
     const bool redge = (int64_t)panel * PN_ROWS + PN_ROWS > nR;
 
-    gload(0);
-    lstore(0);
-    __syncthreads();
+    // the wave index as a wave-uniform (scalar) value: the LDS address of a
+    // direct load goes through m0
+    const int wave_u = __builtin_amdgcn_readfirstlane(ctx.wave);
+    const uint32_t loff = ring_lane_offset<KPB>(wave_u, ctx.lane);
+    if constexpr (DMA) {
+        const char* src = B + (int64_t)t0 * PN_BN * KPB;
+        ring_fill<KPB, PN_BN, NCH>(sB[0], src, loff, wave_u);
+        ring_fill<KPB, PN_BN, NCH>(sB1, src + 128, loff, wave_u);
+    } else {
+        gload(0);
+        lstore(0);
+        __syncthreads();
+    }
+    // per-column FP8 scale exponents, read one S tile ahead
+    auto col_scales = [&](int t, int (&e)[CB]) {
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+            e[cb] = PREC == P_FP8
+                        ? 127 - ilogbf(info_s[(int64_t)t * PN_BN + cb * 32 + r32].qscale)
+                        : 127;
+    };
+    int sb_next[CB];
+    col_scales(t0, sb_next);
     for (int t = t0; t < t1; ++t) {
         int sb[CB];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-            sb[cb] = PREC == P_FP8
-                         ? 127 - ilogbf(info_s[(int64_t)t * PN_BN + cb * 32 + r32].qscale)
-                         : 127;
+        for (int cb = 0; cb < CB; ++cb) sb[cb] = sb_next[cb];
+        if (t + 1 < t1) col_scales(t + 1, sb_next);
+        if constexpr (DMA) {
+            ring_tile<PREC, KS, RB, CB>(sB[0], sB1, sB2, B, loff, t, t1 - 1, af, acc, sa, sb,
+                                        wave_u, ctx.lane);
+        } else {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int q = (t - t0) * KS + ks;
-            const bool more = q + 1 < nq;
-            if (more) gload(q + 1);
-            const char* sl = sB[q & 1];
+            for (int ks = 0; ks < KS; ++ks) {
+                const int q = (t - t0) * KS + ks;
+                const bool more = q + 1 < nq;
+                if (more) gload(q + 1);
+                const char* sl = sB[q & 1];
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                typename M::Frag fb[CB];
+                for (int g = 0; g < G; ++g) {
+                    typename M::Frag fb[CB];
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    const int row = cb * 32 + r32;
+                    for (int cb = 0; cb < CB; ++cb) {
+                        const int row = cb * 32 + r32;
 #pragma unroll
-                    for (int c = 0; c < M::CPL; ++c) {
-                        v4i v = *(const v4i*)(sl + lds_off(row, M::chunk(g, h, c)));
+                        for (int c = 0; c < M::CPL; ++c) {
+                            v4i v = *(const v4i*)(sl + lds_off(row, M::chunk(g, h, c)));
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) fb[cb][c * 4 + e] = v[e];
+                            for (int e = 0; e < 4; ++e) fb[cb][c * 4 + e] = v[e];
+                        }
                     }
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb)
+                            M::mma(af[rb][ks * G + g], fb[cb], acc[rb][cb], sa[rb], sb[cb]);
                 }
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                    for (int cb = 0; cb < CB; ++cb)
-                        M::mma(af[rb][ks * G + g], fb[cb], acc[rb][cb], sa[rb], sb[cb]);
+                if (more) lstore((q + 1) & 1);
+                __syncthreads();
             }
-            if (more) lstore((q + 1) & 1);
-            __syncthreads();
         }
 
         ctx.t = t;
@@ -387,13 +516,15 @@ __global__ __launch_bounds__(256, OCC) void panel_kernel(
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[rb][cb][e] = 0.0f;
     }
+    // the two fills past the end land before the workgroup's LDS is released
+    if constexpr (DMA) wait_vmcnt_lgkm0<0>();
     EPI::finish(ep, esm, est, ctx);
 }
 
 // S chunks per panel: the threshold sweep is split so that there are enough
 // workgroups to balance the 256 CUs (about 32 per CU); the top-k sweep must
 // see all of S in one workgroup (one chunk).
-template <int PREC, int KS, int RB, int CB, int OCC, class EPI>
+template <int PREC, int KS, int RB, int CB, int OCC, bool DMA, class EPI>
 static hipError_t run_panel(const void* A, const void* B, const RowInfo* info_r,
                             const RowInfo* info_s, int64_t nR, int64_t nS, bool split_s,
                             const unsigned long long* hdr, const typename EPI::Params& ep,
@@ -414,7 +545,7 @@ static hipError_t run_panel(const void* A, const void* B, const RowInfo* info_r,
     if (items > 0x7fffffffLL) return hipErrorInvalidValue;
     const int64_t gx = items < 65536 ? items : 65536;
     const int64_t gy = (items + gx - 1) / gx;
-    hipLaunchKernelGGL((panel_kernel<PREC, KS, RB, CB, OCC, EPI>), dim3((unsigned)gx, (unsigned)gy),
+    hipLaunchKernelGGL((panel_kernel<PREC, KS, RB, CB, OCC, DMA, EPI>), dim3((unsigned)gx, (unsigned)gy),
                        dim3(256), 0, st, (const char*)A, (const char*)B, info_r, info_s, nR, nS,
                        (int)n_panels, (int)items, (int)tpc, (int)n_stiles, hdr, ep);
     return hipGetLastError();
@@ -431,7 +562,8 @@ static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const vo
                                  bool split_s, const unsigned long long* hdr,
                                  const typename EPI::Params& ep, hipStream_t st) {
 #define EJ_RUN(KS_, RB_, CB_, OCC_) \
-    return run_panel<PREC, KS_, RB_, CB_, OCC_, EPI>(A, B, ir, is, nR, nS, split_s, hdr, ep, st)
+    return run_panel<PREC, KS_, RB_, CB_, OCC_, OCC_ == 2 && KS_ % 3 == 0, EPI>( \
+        A, B, ir, is, nR, nS, split_s, hdr, ep, st)
     if (two_waves) {
         if constexpr (PREC == P_BF16) {
             switch (ks) {
