@@ -2,14 +2,18 @@
 //
 // The tensor join's cache argument (Section IV.C: a block of vectors stays in
 // cache and is reused across many products) is taken here to the register
-// file.  A workgroup owns a panel of 128 * RB R rows (32 * RB per wave); each
-// wave loads its rows' BF16 or FP8 MFMA operand fragments into VGPRs once and
-// keeps them while the workgroup sweeps a range of S tiles (32 * CB columns
-// each).  S slices (128 bytes of K per row) stream through a double-buffered
-// LDS ring shared by the four waves, so per MFMA only the S operand is read
-// from LDS and only S traffic reaches L2.  With K short (a few hundred), this
-// removes the per-output-tile prologue that a classic tile kernel pays for
-// every block of D (Section V.B's mini-batch slowdown, at tile scale).
+// file.  A workgroup of NW waves owns a panel of 32 * RB * NW R rows (32 * RB
+// per wave); each wave loads its rows' BF16 or FP8 MFMA operand fragments
+// into VGPRs once and keeps them while the workgroup sweeps a range of S
+// tiles (32 * CB columns each).  S slices (128 bytes of K per row) stream
+// through an LDS ring shared by the waves, so per MFMA only the S operand is
+// read from LDS and only S traffic reaches L2.  With K short (a few hundred),
+// this removes the per-output-tile prologue that a classic tile kernel pays
+// for every block of D (Section V.B's mini-batch slowdown, at tile scale).
+//
+// The ring is filled either through registers (two slots, one slice ahead)
+// or by direct global->LDS loads into NSLOT slots, NSLOT - 1 slices ahead of
+// the MFMAs.
 //
 // The accumulators of each S tile go to an epilogue policy:
 //  * ThresholdEpi -- the threshold predicate of the E-theta-join, with hits
@@ -58,20 +62,23 @@ struct TileCtx {
 };
 
 // ---------------------------------------------------------------------------
-// threshold epilogue
+// threshold epilogue (NW waves per workgroup)
 // ---------------------------------------------------------------------------
+struct ThresholdParams {
+    float lo, hi;
+    Pair* out;
+    int64_t capacity;
+    int2* band;
+    int64_t band_cap;
+    unsigned long long* hdr;
+};
+
+template <int NW>
 struct ThresholdEpi {
-    struct Params {
-        float lo, hi;
-        Pair* out;
-        int64_t capacity;
-        int2* band;
-        int64_t band_cap;
-        unsigned long long* hdr;
-    };
+    typedef ThresholdParams Params;
     struct Smem {
-        Pair out[4][PN_OUTCAP];
-        int2 band[4][PN_BANDCAP];
+        Pair out[NW][PN_OUTCAP];
+        int2 band[NW][PN_BANDCAP];
     };
     struct State {
         int n_out, n_band;  // staged entries of this wave (wave-uniform)
@@ -163,15 +170,18 @@ struct ThresholdEpi {
 // top-k candidate epilogue: every (i, j) with approximate score >= floor goes
 // to slot cnt[i]++ of row i (slots past Kc are counted, not written)
 // ---------------------------------------------------------------------------
+struct CandParams {
+    const unsigned long long* hdr;  // floor as float bits in H_TOPK_F
+    int* cnt;                       // per R row, number of candidates seen
+    int2* cand;                     // per R row, Kc slots of (j, score bits)
+    int Kc;
+};
+
+template <int NW>
 struct CandEpi {
-    struct Params {
-        const unsigned long long* hdr;  // floor as float bits in H_TOPK_F
-        int* cnt;                       // per R row, number of candidates seen
-        int2* cand;                     // per R row, Kc slots of (j, score bits)
-        int Kc;
-    };
+    typedef CandParams Params;
     struct Smem {
-        int cnt[4][64];  // per wave, its (up to 64) rows
+        int cnt[NW][64];  // per wave, its (up to 64) rows
     };
     struct State {
         float floor;
@@ -261,21 +271,21 @@ __device__ __forceinline__ void bare_barrier() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Fill ring slot `dst` with one K slice of an S tile (`src`: the slice's
-// first byte, the same for the whole wave) by direct global->LDS loads.
-// Instruction i of wave w fills LDS rows 8 (4 i + w) .. +7, lane l writing the
-// 16 bytes at l * 16 of that 1 KB block, so the lane loads the chunk that the
-// XOR swizzle of lds_off places there: row r = 8 (4 i + w) + l / 8, chunk
-// (l % 8) ^ ((r / 2) % 8).  The chunk does not depend on i (r / 2 moves by 16
-// per i), so the lane's source offset for instruction i is `loff` (that of
-// i = 0, see ring_lane_offset) plus i * 32 rows.
-template <int KPB, int PN_BN, int NCH>
+// Direct-load fill of one ring slot with one K slice of an S tile (`src`: the
+// slice's first byte, the same for the whole wave).  A slice is PN_BN rows of
+// 128 bytes, i.e. PN_BN / 8 blocks of 1 KB; instruction i of wave w fills
+// block b = NW i + w (rows 8 b .. 8 b + 7), lane l writing the 16 bytes at
+// l * 16 of the block, so the lane loads the chunk that the XOR swizzle of
+// lds_off places there: row r = 8 b + l / 8, chunk (l % 8) ^ ((r / 2) % 8).
+// With NW even, r / 2 mod 8 does not depend on i, so the source offset of
+// instruction i is that of i = 0 (ring_lane_offset) plus 8 NW i rows.
+template <int KPB, int NW, int NCH>
 __device__ __forceinline__ void ring_fill(char* dst, const char* src, uint32_t loff, int wave) {
 #pragma unroll
     for (int i = 0; i < NCH; ++i)
-        __builtin_amdgcn_global_load_lds((const void*)(src + loff + i * 32 * KPB),
-                                         (__attribute__((address_space(3))) void*)(dst + (4 * i + wave) * 1024),
-                                         16, 0, 0);
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(src + loff + i * 8 * NW * KPB),
+            (__attribute__((address_space(3))) void*)(dst + (NW * i + wave) * 1024), 16, 0, 0);
 }
 
 template <int KPB>
@@ -284,89 +294,76 @@ __device__ __forceinline__ uint32_t ring_lane_offset(int wave, int lane) {
     return (uint32_t)(row * KPB + (((lane & 7) ^ ((row >> 1) & 7)) << 4));
 }
 
-// The KS slices of S tile t on the three-slot direct-load ring: slice q sits
-// in slot q % 3 and is filled two slices ahead.  KS is a multiple of 3, so the
-// slot of every slice is known at compile time; the slots are three separate
-// LDS arrays, which lets the compiler see that the fills in flight never touch
-// the slot being read and keeps it from waiting for them before the LDS reads
-// (the waits for the fills are the explicit vmcnt waits below).
+// One K slice of MFMAs: B fragments of slice `sl` from LDS against the
+// resident A fragments of K slice ks.
 template <int PREC, int KS, int RB, int CB>
-__device__ __forceinline__ void ring_tile(char* s0, char* s1, char* s2, const char* __restrict__ B,
-                                          uint32_t loff, int t, int t_last,
+__device__ __forceinline__ void slice_mma(const char* sl, int ks,
                                           const typename Mma<PREC>::Frag (&af)[RB][KS * Mma<PREC>::GROUPS],
                                           v16f (&acc)[RB][CB], const int (&sa)[RB],
-                                          const int (&sb)[CB], int wave, int lane) {
+                                          const int (&sb)[CB], int h, int r32) {
     typedef Mma<PREC> M;
-    static_assert(KS % 3 == 0, "the ring slot of a slice must be static");
     constexpr int G = M::GROUPS;
-    constexpr int KPB = KS * 128;
-    constexpr int PN_BN = 32 * CB;
-    constexpr int NCH = PN_BN * 8 / 256;
-    const int h = lane >> 5, r32 = lane & 31;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        // slice q has landed once at most the next slice's loads are in
-        // flight; the barrier then publishes every wave's part and retires
-        // all reads of slice q - 1, whose slot slice q + 2 takes.  The ring
-        // always runs two fills ahead: past the end of the sweep the fills
-        // reload the last tile (never read), which keeps every wait count
-        // static.
-        wait_vmcnt_lgkm0<NCH>();
-        bare_barrier();
-        {
-            char* dst = (ks + 2) % 3 == 0 ? s0 : (ks + 2) % 3 == 1 ? s1 : s2;
-            const int t2 = min(t + (ks + 2) / KS, t_last), k2 = (ks + 2) % KS;
-            ring_fill<KPB, PN_BN, NCH>(dst, B + (int64_t)t2 * PN_BN * KPB + k2 * 128, loff, wave);
-        }
-        const char* sl = ks % 3 == 0 ? s0 : ks % 3 == 1 ? s1 : s2;
+    for (int g = 0; g < G; ++g) {
+        typename M::Frag fb[CB];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            typename M::Frag fb[CB];
+        for (int cb = 0; cb < CB; ++cb) {
+            const int row = cb * 32 + r32;
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                const int row = cb * 32 + r32;
+            for (int c = 0; c < M::CPL; ++c) {
+                v4i v = *(const v4i*)(sl + lds_off(row, M::chunk(g, h, c)));
 #pragma unroll
-                for (int c = 0; c < M::CPL; ++c) {
-                    v4i v = *(const v4i*)(sl + lds_off(row, M::chunk(g, h, c)));
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) fb[cb][c * 4 + e] = v[e];
-                }
+                for (int e = 0; e < 4; ++e) fb[cb][c * 4 + e] = v[e];
             }
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb)
-                    M::mma(af[rb][ks * G + g], fb[cb], acc[rb][cb], sa[rb], sb[cb]);
         }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+                M::mma(af[rb][ks * G + g], fb[cb], acc[rb][cb], sa[rb], sb[cb]);
     }
 }
 
-// RB 32-row blocks per wave (4 waves), CB 32-column blocks per S tile, KS
-// 128-byte K slices per row, OCC workgroups per CU.  DMA: the S slices go
-// straight from global memory into a three-slot LDS ring (no staging
-// registers) two slices ahead of the MFMAs; otherwise through registers into
-// a two-slot ring one slice ahead.
-template <int PREC, int KS, int RB, int CB, int OCC, bool DMA, class EPI>
-__global__ __launch_bounds__(256, OCC) void panel_kernel(
+// Template parameters: RB 32-row blocks per wave, CB 32-column blocks per S
+// tile, KS 128-byte K slices per row, NW waves per workgroup, OCC workgroups
+// per CU, NSLOT ring slots of direct loads (0: the register-staged two-slot
+// ring).  With direct loads, slice q of the sweep sits in slot q % NSLOT and
+// is filled NSLOT - 1 slices ahead; KS is a multiple of NSLOT, so the slot of
+// every slice is known at compile time.  The slots are separate LDS arrays,
+// which lets the compiler see that the fills in flight never touch the slot
+// being read and keeps it from waiting for them before the LDS reads (the
+// waits for the fills are the explicit vmcnt waits).
+template <int PREC, int KS, int RB, int CB, int NW, int OCC, int NSLOT, class EPI>
+__global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
     const char* __restrict__ A, const char* __restrict__ B, const RowInfo* __restrict__ info_r,
     const RowInfo* __restrict__ info_s, int64_t nR, int64_t nS, int n_panels, int n_items,
     int tiles_per_chunk, int n_stiles, const unsigned long long* __restrict__ flags,
     typename EPI::Params ep) {
     typedef Mma<PREC> M;
     constexpr int G = M::GROUPS;
-    constexpr int NF = KS * G;       // A fragments per 32-row block
-    constexpr int KPB = KS * 128;    // bytes per operand row
+    constexpr int NF = KS * G;        // A fragments per 32-row block
+    constexpr int KPB = KS * 128;     // bytes per operand row
     constexpr int PN_BN = 32 * CB;
-    constexpr int PN_ROWS = 128 * RB;
-    constexpr int NCH = PN_BN * 8 / 256;  // 16-byte chunks per thread per S slice
-    static_assert(!DMA || KS % 3 == 0, "direct loads need a static ring slot per slice");
+    constexpr int PN_ROWS = 32 * RB * NW;
+    constexpr int NT = 64 * NW;       // threads
+    constexpr int SLOT = PN_BN * 128;
+    constexpr bool DMA = NSLOT > 0;
+    constexpr int NS = DMA ? NSLOT : 2;
+    constexpr int NCH = PN_BN * 8 / NT;  // 16-byte chunks per thread per S slice
+    static_assert(NCH >= 1 && NCH * NT == PN_BN * 8, "slice chunks must spread evenly");
+    static_assert(NW % 2 == 0, "the fill offsets assume an even wave count");
+    static_assert(!DMA || (NSLOT >= 2 && NSLOT <= 6 && KS % NSLOT == 0),
+                  "direct loads need a static ring slot per slice");
+    constexpr int D = NS - 1;  // fill distance of the direct-load ring
 
-    // register-staged path: two-slot ring sB; direct-load path: slots sB
-    // (first half), sB1 and sB2
-    __shared__ __attribute__((aligned(16))) char sB[DMA ? 1 : 2][PN_BN * 128];
-    __shared__ __attribute__((aligned(16))) char sB1[DMA ? PN_BN * 128 : 16];
-    __shared__ __attribute__((aligned(16))) char sB2[DMA ? PN_BN * 128 : 16];
+    __shared__ __attribute__((aligned(16))) char sL0[SLOT];
+    __shared__ __attribute__((aligned(16))) char sL1[SLOT];
+    __shared__ __attribute__((aligned(16))) char sL2[NS > 2 ? SLOT : 16];
+    __shared__ __attribute__((aligned(16))) char sL3[NS > 3 ? SLOT : 16];
+    __shared__ __attribute__((aligned(16))) char sL4[NS > 4 ? SLOT : 16];
+    __shared__ __attribute__((aligned(16))) char sL5[NS > 5 ? SLOT : 16];
     __shared__ typename EPI::Smem esm;
+    char* const slots[6] = {sL0, sL1, sL2, sL3, sL4, sL5};
 
     const int item = (int)(blockIdx.y * gridDim.x + blockIdx.x);
     if (item >= n_items) return;
@@ -421,6 +418,12 @@ __global__ __launch_bounds__(256, OCC) void panel_kernel(
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
 
+    typename EPI::State est;
+    EPI::init(ep, esm, est, ctx);
+    const bool redge = (int64_t)panel * PN_ROWS + PN_ROWS > nR;
+
+    // register-staged ring: slice q + 1 goes through registers into slot
+    // (q + 1) % 2 while slice q is multiplied
     const int nq = (t1 - t0) * KS;
     v4i rbuf[NCH];
     auto gload = [&](int q) {
@@ -428,33 +431,31 @@ __global__ __launch_bounds__(256, OCC) void panel_kernel(
         const char* base = B + (int64_t)t * PN_BN * KPB + ks * 128;
 #pragma unroll
         for (int i = 0; i < NCH; ++i) {
-            const int qq = tid + i * 256;
+            const int qq = tid + i * NT;
             rbuf[i] = *(const v4i*)(base + (int64_t)(qq >> 3) * KPB + (qq & 7) * 16);
         }
     };
-    auto lstore = [&](int slot) {
+    auto lstore = [&](char* slot) {
 #pragma unroll
         for (int i = 0; i < NCH; ++i) {
-            const int qq = tid + i * 256;
-            *(v4i*)(&sB[slot][lds_off(qq >> 3, qq & 7)]) = rbuf[i];
+            const int qq = tid + i * NT;
+            *(v4i*)(slot + lds_off(qq >> 3, qq & 7)) = rbuf[i];
         }
     };
-
-    typename EPI::State est;
-    EPI::init(ep, esm, est, ctx);
-    const bool redge = (int64_t)panel * PN_ROWS + PN_ROWS > nR;
 
     // the wave index as a wave-uniform (scalar) value: the LDS address of a
     // direct load goes through m0
     const int wave_u = __builtin_amdgcn_readfirstlane(ctx.wave);
     const uint32_t loff = ring_lane_offset<KPB>(wave_u, ctx.lane);
     if constexpr (DMA) {
-        const char* src = B + (int64_t)t0 * PN_BN * KPB;
-        ring_fill<KPB, PN_BN, NCH>(sB[0], src, loff, wave_u);
-        ring_fill<KPB, PN_BN, NCH>(sB1, src + 128, loff, wave_u);
+        // slices 0 .. D - 1 (the sweep has at least KS >= NSLOT > D slices)
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            ring_fill<KPB, NW, NCH>(slots[j], B + (int64_t)t0 * PN_BN * KPB + j * 128, loff,
+                                    wave_u);
     } else {
         gload(0);
-        lstore(0);
+        lstore(sL0);
         __syncthreads();
     }
     // per-column FP8 scale exponents, read one S tile ahead
@@ -472,36 +473,27 @@ __global__ __launch_bounds__(256, OCC) void panel_kernel(
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) sb[cb] = sb_next[cb];
         if (t + 1 < t1) col_scales(t + 1, sb_next);
-        if constexpr (DMA) {
-            ring_tile<PREC, KS, RB, CB>(sB[0], sB1, sB2, B, loff, t, t1 - 1, af, acc, sa, sb,
-                                        wave_u, ctx.lane);
-        } else {
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
+        for (int ks = 0; ks < KS; ++ks) {
+            if constexpr (DMA) {
+                // slice q has landed once at most the D - 1 later slices'
+                // loads are in flight; the barrier then publishes every
+                // wave's part and retires all reads of slice q - 1, whose
+                // slot slice q + D takes.  The ring always runs D fills
+                // ahead: past the end of the sweep the fills reload the last
+                // tile (never read), which keeps every wait count static.
+                wait_vmcnt_lgkm0<(D - 1) * NCH>();
+                bare_barrier();
+                const int t2 = min(t + (ks + D) / KS, t1 - 1), k2 = (ks + D) % KS;
+                ring_fill<KPB, NW, NCH>(slots[(ks + D) % NS], B + (int64_t)t2 * PN_BN * KPB + k2 * 128,
+                                        loff, wave_u);
+                slice_mma<PREC, KS, RB, CB>(slots[ks % NS], ks, af, acc, sa, sb, h, r32);
+            } else {
                 const int q = (t - t0) * KS + ks;
                 const bool more = q + 1 < nq;
                 if (more) gload(q + 1);
-                const char* sl = sB[q & 1];
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    typename M::Frag fb[CB];
-#pragma unroll
-                    for (int cb = 0; cb < CB; ++cb) {
-                        const int row = cb * 32 + r32;
-#pragma unroll
-                        for (int c = 0; c < M::CPL; ++c) {
-                            v4i v = *(const v4i*)(sl + lds_off(row, M::chunk(g, h, c)));
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) fb[cb][c * 4 + e] = v[e];
-                        }
-                    }
-#pragma unroll
-                    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                        for (int cb = 0; cb < CB; ++cb)
-                            M::mma(af[rb][ks * G + g], fb[cb], acc[rb][cb], sa[rb], sb[cb]);
-                }
-                if (more) lstore((q + 1) & 1);
+                slice_mma<PREC, KS, RB, CB>((q & 1) ? sL1 : sL0, ks, af, acc, sa, sb, h, r32);
+                if (more) lstore(((q + 1) & 1) ? sL1 : sL0);
                 __syncthreads();
             }
         }
@@ -516,7 +508,7 @@ __global__ __launch_bounds__(256, OCC) void panel_kernel(
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[rb][cb][e] = 0.0f;
     }
-    // the two fills past the end land before the workgroup's LDS is released
+    // the fills past the end land before the workgroup's LDS is released
     if constexpr (DMA) wait_vmcnt_lgkm0<0>();
     EPI::finish(ep, esm, est, ctx);
 }
@@ -524,13 +516,13 @@ __global__ __launch_bounds__(256, OCC) void panel_kernel(
 // S chunks per panel: the threshold sweep is split so that there are enough
 // workgroups to balance the 256 CUs (about 32 per CU); the top-k sweep must
 // see all of S in one workgroup (one chunk).
-template <int PREC, int KS, int RB, int CB, int OCC, bool DMA, class EPI>
+template <int PREC, int KS, int RB, int CB, int NW, int OCC, int NSLOT, class EPI>
 static hipError_t run_panel(const void* A, const void* B, const RowInfo* info_r,
                             const RowInfo* info_s, int64_t nR, int64_t nS, bool split_s,
                             const unsigned long long* hdr, const typename EPI::Params& ep,
                             hipStream_t st) {
     constexpr int PN_BN = 32 * CB;
-    constexpr int PN_ROWS = 128 * RB;
+    constexpr int PN_ROWS = 32 * RB * NW;
     const int64_t n_panels = (nR + PN_ROWS - 1) / PN_ROWS;
     const int64_t n_stiles = (nS + PN_BN - 1) / PN_BN;
     if (n_panels == 0 || n_stiles == 0) return hipSuccess;
@@ -545,67 +537,71 @@ static hipError_t run_panel(const void* A, const void* B, const RowInfo* info_r,
     if (items > 0x7fffffffLL) return hipErrorInvalidValue;
     const int64_t gx = items < 65536 ? items : 65536;
     const int64_t gy = (items + gx - 1) / gx;
-    hipLaunchKernelGGL((panel_kernel<PREC, KS, RB, CB, OCC, DMA, EPI>), dim3((unsigned)gx, (unsigned)gy),
-                       dim3(256), 0, st, (const char*)A, (const char*)B, info_r, info_s, nR, nS,
-                       (int)n_panels, (int)items, (int)tpc, (int)n_stiles, hdr, ep);
+    hipLaunchKernelGGL((panel_kernel<PREC, KS, RB, CB, NW, OCC, NSLOT, EPI>),
+                       dim3((unsigned)gx, (unsigned)gy), dim3(64 * NW), 0, st, (const char*)A,
+                       (const char*)B, info_r, info_s, nR, nS, (int)n_panels, (int)items, (int)tpc,
+                       (int)n_stiles, hdr, ep);
     return hipGetLastError();
 }
 
 // Kp * element size must be KS * 128 bytes with KS in 1..6.
-//  * two_waves: one 32-row block per wave, 128-column S tiles, two
-//    workgroups per CU (the epilogue of one overlaps the MFMAs of the other);
-//  * otherwise one workgroup per CU, two row blocks per wave while the
-//    resident fragments fit the register file.
-template <int PREC, class EPI>
+//  * two_waves: one 32-row block per wave, two workgroups of four waves per
+//    CU (the epilogue of one overlaps the MFMAs of the other); K slices on a
+//    three-slot direct-load ring when KS is a multiple of 3;
+//  * otherwise one workgroup per CU: for KS 3 .. 6 eight waves with one row
+//    block each, four 32-column blocks per tile and a direct-load ring of one
+//    slot per K slice (three for KS = 3); else four waves with two row blocks
+//    each.
+template <int PREC, template <int> class EPI>
 static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const void* B,
                                  const RowInfo* ir, const RowInfo* is, int64_t nR, int64_t nS,
                                  bool split_s, const unsigned long long* hdr,
-                                 const typename EPI::Params& ep, hipStream_t st) {
-#define EJ_RUN(KS_, RB_, CB_, OCC_) \
-    return run_panel<PREC, KS_, RB_, CB_, OCC_, OCC_ == 2 && KS_ % 3 == 0, EPI>( \
-        A, B, ir, is, nR, nS, split_s, hdr, ep, st)
+                                 const typename EPI<4>::Params& ep, hipStream_t st) {
+#define EJ_RUN(KS_, RB_, CB_, NW_, OCC_, NSLOT_)                                          \
+    return run_panel<PREC, KS_, RB_, CB_, NW_, OCC_, NSLOT_, EPI<NW_>>(A, B, ir, is, nR, nS, \
+                                                                       split_s, hdr, ep, st)
     if (two_waves) {
         if constexpr (PREC == P_BF16) {
             switch (ks) {
-                case 1: EJ_RUN(1, 1, 4, 2);
-                case 2: EJ_RUN(2, 1, 4, 2);
-                case 3: EJ_RUN(3, 1, 4, 2);
-                case 4: EJ_RUN(4, 1, 4, 2);
-                case 5: EJ_RUN(5, 1, 4, 2);
-                case 6: EJ_RUN(6, 1, 4, 2);
+                case 1: EJ_RUN(1, 1, 4, 4, 2, 0);
+                case 2: EJ_RUN(2, 1, 4, 4, 2, 0);
+                case 3: EJ_RUN(3, 1, 4, 4, 2, 3);
+                case 4: EJ_RUN(4, 1, 4, 4, 2, 0);
+                case 5: EJ_RUN(5, 1, 4, 4, 2, 0);
+                case 6: EJ_RUN(6, 1, 4, 4, 2, 3);
             }
         } else {
             // FP8 fragments are twice as wide: one S block per tile keeps the
             // deep panels within the register file at two workgroups per CU
             switch (ks) {
-                case 1: EJ_RUN(1, 1, 4, 2);
-                case 2: EJ_RUN(2, 1, 2, 2);
-                case 3: EJ_RUN(3, 1, 1, 2);
-                case 4: EJ_RUN(4, 1, 1, 2);
-                case 5: EJ_RUN(5, 1, 1, 2);
-                case 6: EJ_RUN(6, 1, 1, 2);
+                case 1: EJ_RUN(1, 1, 4, 4, 2, 0);
+                case 2: EJ_RUN(2, 1, 2, 4, 2, 0);
+                case 3: EJ_RUN(3, 1, 1, 4, 2, 3);
+                case 4: EJ_RUN(4, 1, 1, 4, 2, 0);
+                case 5: EJ_RUN(5, 1, 1, 4, 2, 0);
+                case 6: EJ_RUN(6, 1, 1, 4, 2, 3);
             }
         }
         return hipErrorInvalidValue;
     }
     if constexpr (PREC == P_BF16) {
         switch (ks) {
-            case 1: EJ_RUN(1, 2, 4, 1);
-            case 2: EJ_RUN(2, 2, 4, 1);
-            case 3: EJ_RUN(3, 2, 4, 1);
-            case 4: EJ_RUN(4, 2, 4, 1);
-            case 5: EJ_RUN(5, 1, 8, 1);
-            case 6: EJ_RUN(6, 1, 8, 1);
+            case 1: EJ_RUN(1, 2, 4, 4, 1, 0);
+            case 2: EJ_RUN(2, 2, 4, 4, 1, 0);
+            case 3: EJ_RUN(3, 1, 4, 8, 1, 3);
+            case 4: EJ_RUN(4, 1, 4, 8, 1, 4);
+            case 5: EJ_RUN(5, 1, 4, 8, 1, 5);
+            case 6: EJ_RUN(6, 1, 4, 8, 1, 6);
         }
     } else {
         // FP8 fragments are twice as wide per MFMA
         switch (ks) {
-            case 1: EJ_RUN(1, 2, 4, 1);
-            case 2: EJ_RUN(2, 2, 4, 1);
-            case 3: EJ_RUN(3, 1, 4, 1);
-            case 4: EJ_RUN(4, 1, 4, 1);
-            case 5: EJ_RUN(5, 1, 2, 1);
-            case 6: EJ_RUN(6, 1, 2, 1);
+            case 1: EJ_RUN(1, 2, 4, 4, 1, 0);
+            case 2: EJ_RUN(2, 2, 4, 4, 1, 0);
+            case 3: EJ_RUN(3, 1, 4, 8, 1, 3);
+            case 4: EJ_RUN(4, 1, 4, 8, 1, 4);
+            case 5: EJ_RUN(5, 1, 4, 8, 1, 5);
+            case 6: EJ_RUN(6, 1, 4, 8, 1, 6);
         }
     }
 #undef EJ_RUN
@@ -618,7 +614,7 @@ hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs&
                                   hipStream_t st) {
     const int kpb = a.Kp * (prec == P_BF16 ? 2 : 1);
     if (kpb % 128 != 0) return hipErrorInvalidValue;
-    ThresholdEpi::Params ep;
+    ThresholdParams ep;
     ep.lo = a.lo;
     ep.hi = a.hi;
     ep.out = a.out;
@@ -641,18 +637,39 @@ hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs&
 hipError_t launch_topk_candidates(int prec, const CandArgs& a, hipStream_t st) {
     const int kpb = a.Kp * (prec == P_BF16 ? 2 : 1);
     if (kpb % 128 != 0 || kpb > 768) return hipErrorInvalidValue;
-    CandEpi::Params ep;
+    CandParams ep;
     ep.hdr = a.hdr;
     ep.cnt = a.cnt;
     ep.cand = a.cand;
     ep.Kc = a.Kc;
     const int ks = slices(prec, a.Kp);
-    if (prec == P_BF16)
+#define EJ_RUN(P_, KS_, RB_, CB_, NW_, OCC_, NSLOT_)                                           \
+    return run_panel<P_, KS_, RB_, CB_, NW_, OCC_, NSLOT_, CandEpi<NW_>>(                       \
+        a.A, a.B, a.info_r, a.info_s, a.nR, a.nS, false, a.hdr, ep, st)
+    // K of three slices or more: eight waves (one row block each) and a
+    // direct-load ring of one slot per slice; 64-column FP8 tiles keep the
+    // epilogue of the FP8 sweep short
+    if (prec == P_BF16) {
+        switch (ks) {
+            case 3: EJ_RUN(P_BF16, 3, 1, 4, 8, 1, 3);
+            case 4: EJ_RUN(P_BF16, 4, 1, 4, 8, 1, 4);
+            case 5: EJ_RUN(P_BF16, 5, 1, 4, 8, 1, 5);
+            case 6: EJ_RUN(P_BF16, 6, 1, 4, 8, 1, 6);
+        }
         return dispatch_panel<P_BF16, CandEpi>(ks, true, a.A, a.B, a.info_r, a.info_s, a.nR,
                                                a.nS, false, a.hdr, ep, st);
-    if (prec == P_FP8)
+    }
+    if (prec == P_FP8) {
+        switch (ks) {
+            case 3: EJ_RUN(P_FP8, 3, 1, 2, 8, 1, 3);
+            case 4: EJ_RUN(P_FP8, 4, 1, 2, 8, 1, 4);
+            case 5: EJ_RUN(P_FP8, 5, 1, 2, 8, 1, 5);
+            case 6: EJ_RUN(P_FP8, 6, 1, 2, 8, 1, 6);
+        }
         return dispatch_panel<P_FP8, CandEpi>(ks, true, a.A, a.B, a.info_r, a.info_s, a.nR,
                                               a.nS, false, a.hdr, ep, st);
+    }
+#undef EJ_RUN
     return hipErrorInvalidValue;
 }
 

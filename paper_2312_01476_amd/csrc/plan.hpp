@@ -88,7 +88,10 @@ inline bool rel_ok(const ejoin_rel* X) {
 // whose rows fit it (up to 768 bytes of K), else the LDS tile kernel
 inline int default_tile(int prec, int Kp) {
     if (prec == P_FP32) return 1;
-    if (Kp * elem_bytes(prec) <= 768) return prec == P_BF16 ? 14 : 13;
+    // register panels: eight waves on a direct-load ring from three K slices
+    // of 128 bytes on, two workgroups of four waves below that (BF16)
+    if (Kp * elem_bytes(prec) <= 768)
+        return prec == P_FP8 ? 13 : (Kp * elem_bytes(prec) >= 384 ? 12 : 14);
     return prec == P_BF16 ? 3 : 5;
 }
 
