@@ -84,7 +84,7 @@ struct ThresholdEpi {
         int n_out, n_band;  // staged entries of this wave (wave-uniform)
     };
 
-    __device__ static void init(const Params&, Smem&, State& s, const TileCtx&) {
+    __device__ static __forceinline__ void init(const Params&, Smem&, State& s, const TileCtx&) {
         s.n_out = 0;
         s.n_band = 0;
     }
@@ -158,7 +158,7 @@ struct ThresholdEpi {
                 }
     }
 
-    __device__ static void finish(const Params& p, Smem& sm, State& s, const TileCtx& c) {
+    __device__ static __forceinline__ void finish(const Params& p, Smem& sm, State& s, const TileCtx& c) {
         if (s.n_out)
             flush_stage(sm.out[c.wave], s.n_out, p.out, p.capacity, p.hdr + H_OUT, c.lane);
         if (s.n_band)
@@ -187,7 +187,7 @@ struct CandEpi {
         float floor;
     };
 
-    __device__ static void init(const Params& p, Smem& sm, State& s, const TileCtx& c) {
+    __device__ static __forceinline__ void init(const Params& p, Smem& sm, State& s, const TileCtx& c) {
         s.floor = __uint_as_float((uint32_t)p.hdr[H_TOPK_F]);
         sm.cnt[c.wave][c.lane] = 0;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -244,7 +244,7 @@ struct CandEpi {
                 }
     }
 
-    __device__ static void finish(const Params& p, Smem& sm, State&, const TileCtx& c) {
+    __device__ static __forceinline__ void finish(const Params& p, Smem& sm, State&, const TileCtx& c) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if (c.lane < c.rows) p.cnt[c.r0 + c.lane] = sm.cnt[c.wave][c.lane];
     }
@@ -253,6 +253,11 @@ struct CandEpi {
 // ---------------------------------------------------------------------------
 // the panel kernel
 // ---------------------------------------------------------------------------
+// Exponent of a positive normal power of two (the FP8 row multipliers).
+__device__ __forceinline__ int pow2_exponent(float x) {
+    return (int)((__float_as_uint(x) >> 23) & 0xffu) - 127;
+}
+
 // Wait until at most N global memory operations of this wave are in flight
 // and all its LDS operations are done (gfx9 s_waitcnt encoding: vmcnt in bits
 // 3:0 and 15:14, expcnt 6:4 left at its maximum, lgkmcnt 11:8 = 0).
@@ -295,7 +300,9 @@ __device__ __forceinline__ uint32_t ring_lane_offset(int wave, int lane) {
 }
 
 // One K slice of MFMAs: B fragments of slice `sl` from LDS against the
-// resident A fragments of K slice ks.
+// resident A fragments of K slice ks.  The fragments of k-group g + 1 are read
+// before the MFMAs of group g are issued, so the LDS latency of one group is
+// hidden behind the matrix-core work of the previous one.
 template <int PREC, int KS, int RB, int CB>
 __device__ __forceinline__ void slice_mma(const char* sl, int ks,
                                           const typename Mma<PREC>::Frag (&af)[RB][KS * Mma<PREC>::GROUPS],
@@ -303,9 +310,8 @@ __device__ __forceinline__ void slice_mma(const char* sl, int ks,
                                           const int (&sb)[CB], int h, int r32) {
     typedef Mma<PREC> M;
     constexpr int G = M::GROUPS;
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        typename M::Frag fb[CB];
+    typename M::Frag fb[2][CB];
+    auto read = [&](int g, typename M::Frag (&f)[CB]) {
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             const int row = cb * 32 + r32;
@@ -313,15 +319,30 @@ __device__ __forceinline__ void slice_mma(const char* sl, int ks,
             for (int c = 0; c < M::CPL; ++c) {
                 v4i v = *(const v4i*)(sl + lds_off(row, M::chunk(g, h, c)));
 #pragma unroll
-                for (int e = 0; e < 4; ++e) fb[cb][c * 4 + e] = v[e];
+                for (int e = 0; e < 4; ++e) f[cb][c * 4 + e] = v[e];
             }
         }
+    };
+    read(0, fb[0]);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        if (g + 1 < G) read(g + 1, fb[(g + 1) & 1]);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb)
-                M::mma(af[rb][ks * G + g], fb[cb], acc[rb][cb], sa[rb], sb[cb]);
+                M::mma(af[rb][ks * G + g], fb[g & 1][cb], acc[rb][cb], sa[rb], sb[cb]);
     }
+    // schedule: the reads of group 0, then each MFMA of group g followed by
+    // one read of group g + 1
+    __builtin_amdgcn_sched_group_barrier(0x100, CB * M::CPL, 0);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int i = 0; i < RB * CB; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            if (g + 1 < G && i < CB * M::CPL) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
 }
 
 // Template parameters: RB 32-row blocks per wave, CB 32-column blocks per S
@@ -337,7 +358,7 @@ template <int PREC, int KS, int RB, int CB, int NW, int OCC, int NSLOT, class EP
 __global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
     const char* __restrict__ A, const char* __restrict__ B, const RowInfo* __restrict__ info_r,
     const RowInfo* __restrict__ info_s, int64_t nR, int64_t nS, int n_panels, int n_items,
-    int tiles_per_chunk, int n_stiles, const unsigned long long* __restrict__ flags,
+    int tiles_per_chunk, int n_stiles, const unsigned long long* __restrict__ flags, int grid_x,
     typename EPI::Params ep) {
     typedef Mma<PREC> M;
     constexpr int G = M::GROUPS;
@@ -365,7 +386,11 @@ __global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
     __shared__ typename EPI::Smem esm;
     char* const slots[6] = {sL0, sL1, sL2, sL3, sL4, sL5};
 
-    const int item = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    // (hardware ids through the builtins: with the kernel's size the inliner
+    // leaves library helpers as calls, which would put the ids in vector
+    // registers and hide their uniformity)
+    const int item =
+        (int)(__builtin_amdgcn_workgroup_id_y() * grid_x + __builtin_amdgcn_workgroup_id_x());
     if (item >= n_items) return;
     if (flags[H_FLAGS] != 0) return;
     const int chunk = item / n_panels;
@@ -375,7 +400,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
     if (t0 >= t1) return;
 
     TileCtx ctx;
-    const int tid = threadIdx.x;
+    const int tid = (int)__builtin_amdgcn_workitem_id_x();
     ctx.lane = tid & 63;
     ctx.wave = tid >> 6;
     ctx.h = ctx.lane >> 5;
@@ -408,7 +433,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
     int sa[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
-        sa[rb] = PREC == P_FP8 ? 127 - ilogbf(info_r[r0 + rb * 32 + r32].qscale) : 127;
+        sa[rb] = PREC == P_FP8 ? 127 - pow2_exponent(info_r[r0 + rb * 32 + r32].qscale) : 127;
 
     v16f acc[RB][CB];
 #pragma unroll
@@ -463,7 +488,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
             e[cb] = PREC == P_FP8
-                        ? 127 - ilogbf(info_s[(int64_t)t * PN_BN + cb * 32 + r32].qscale)
+                        ? 127 - pow2_exponent(info_s[(int64_t)t * PN_BN + cb * 32 + r32].qscale)
                         : 127;
     };
     int sb_next[CB];
@@ -540,7 +565,7 @@ static hipError_t run_panel(const void* A, const void* B, const RowInfo* info_r,
     hipLaunchKernelGGL((panel_kernel<PREC, KS, RB, CB, NW, OCC, NSLOT, EPI>),
                        dim3((unsigned)gx, (unsigned)gy), dim3(64 * NW), 0, st, (const char*)A,
                        (const char*)B, info_r, info_s, nR, nS, (int)n_panels, (int)items, (int)tpc,
-                       (int)n_stiles, hdr, ep);
+                       (int)n_stiles, hdr, (int)gx, ep);
     return hipGetLastError();
 }
 
