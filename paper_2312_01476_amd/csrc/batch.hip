@@ -22,7 +22,7 @@ template <int PREC, int BM, int BN, int WM, int WN, bool BIG = false>
 __global__ __launch_bounds__(WM* WN * 64, (BM * BN <= 128 * 128) ? 2 : 1) void batch_tile(const BatchHead* __restrict__ head,
                                                           const BatchJob* __restrict__ jobs,
                                                           unsigned long long* __restrict__ bctr) {
-    __shared__ TileSmem<BM, BN, WM * WN> sm;
+    EJ_TILE_SMEM(BM, BN, WM * WN, sm);
     __shared__ int64_t s_item;
     __shared__ int s_job;
     // dense mode: every tile of every job; prefilter mode: the work list

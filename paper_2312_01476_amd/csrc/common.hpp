@@ -48,6 +48,33 @@ struct Pair {
 };
 
 // ---------------------------------------------------------------------------
+// direct-load ring helpers
+// ---------------------------------------------------------------------------
+// Wait until at most N global memory operations of this wave are in flight
+// and all its LDS operations are done (gfx9 s_waitcnt encoding: vmcnt in bits
+// 3:0 and 15:14, expcnt 6:4 left at its maximum, lgkmcnt 11:8 = 0).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt_lgkm0() {
+    static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+}
+
+// Workgroup barrier without a memory fence: the waits before it are the
+// caller's, and direct-load fills in flight stay in flight across it.  The
+// signal fences keep the compiler from moving memory accesses across.
+__device__ __forceinline__ void bare_barrier() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// One 16-byte direct global->LDS load per lane: lane l writes the 16 bytes at
+// lds + 16 l (`lds` is the same for the whole wave).
+__device__ __forceinline__ void lds_fill16(const void* src, char* lds) {
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
 // wave-level helpers (wave64)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float wave_sum(float v) {

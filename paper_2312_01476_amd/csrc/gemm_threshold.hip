@@ -16,7 +16,7 @@ __global__ __launch_bounds__(WM* WN * 64, (BM * BN <= 128 * 128) ? 2 : 1) void t
     int tiles_m, int tiles_n, int ntiles, float lo, float hi, Pair* __restrict__ out,
     int64_t capacity, int2* __restrict__ band, int64_t band_cap,
     unsigned long long* __restrict__ hdr, int kg_last) {
-    __shared__ TileSmem<BM, BN, WM * WN> sm;
+    EJ_TILE_SMEM(BM, BN, WM * WN, sm);
     // 2-D grid (a 1-D grid of this many workgroups would overflow the 32-bit
     // dispatch size); workgroups past the last tile leave at once
     int bid = (int)(blockIdx.y * gridDim.x + blockIdx.x);

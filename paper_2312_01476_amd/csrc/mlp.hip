@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void mlp_l1(const uint16_t* __restrict__ X, in
                                               uint16_t* __restrict__ Hb) {
     constexpr int BM = 128, BN = 128, WM = 2, WN = 2;
     typedef TileGeom<BM, BN, WM, WN> TG;
-    __shared__ TileSmem<BM, BN, WM * WN> sm;
+    EJ_TILE_SMEM(BM, BN, WM * WN, sm);
     const int tm = blockIdx.y, tn = blockIdx.x;
     v16f acc[TG::FM][TG::FN];
     tile_mainloop<P_BF16, BM, BN, WM, WN>(sm, (const char*)X, (const char*)W1t, nullptr, nullptr,
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void mlp_l2(const uint16_t* __restrict__ Hb,
                                               float* __restrict__ Z) {
     constexpr int BM = 128, BN = 64, WM = 2, WN = 2;
     typedef TileGeom<BM, BN, WM, WN> TG;
-    __shared__ TileSmem<BM, BN, WM * WN> sm;
+    EJ_TILE_SMEM(BM, BN, WM * WN, sm);
     const int tm = blockIdx.x;
     v16f acc[TG::FM][TG::FN];
     tile_mainloop<P_BF16, BM, BN, WM, WN>(sm, (const char*)Hb, (const char*)W2t, nullptr, nullptr,

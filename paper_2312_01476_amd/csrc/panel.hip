@@ -258,24 +258,6 @@ __device__ __forceinline__ int pow2_exponent(float x) {
     return (int)((__float_as_uint(x) >> 23) & 0xffu) - 127;
 }
 
-// Wait until at most N global memory operations of this wave are in flight
-// and all its LDS operations are done (gfx9 s_waitcnt encoding: vmcnt in bits
-// 3:0 and 15:14, expcnt 6:4 left at its maximum, lgkmcnt 11:8 = 0).
-template <int N>
-__device__ __forceinline__ void wait_vmcnt_lgkm0() {
-    static_assert(N >= 0 && N < 64, "vmcnt is six bits");
-    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
-}
-
-// Workgroup barrier without a memory fence: the waits before it are the
-// caller's, and the direct-load fills in flight stay in flight across it.
-// The signal fences keep the compiler from moving memory accesses across.
-__device__ __forceinline__ void bare_barrier() {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_barrier();
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
 // Direct-load fill of one ring slot with one K slice of an S tile (`src`: the
 // slice's first byte, the same for the whole wave).  A slice is PN_BN rows of
 // 128 bytes, i.e. PN_BN / 8 blocks of 1 KB; instruction i of wave w fills
@@ -288,9 +270,7 @@ template <int KPB, int NW, int NCH>
 __device__ __forceinline__ void ring_fill(char* dst, const char* src, uint32_t loff, int wave) {
 #pragma unroll
     for (int i = 0; i < NCH; ++i)
-        __builtin_amdgcn_global_load_lds(
-            (const void*)(src + loff + i * 8 * NW * KPB),
-            (__attribute__((address_space(3))) void*)(dst + (NW * i + wave) * 1024), 16, 0, 0);
+        lds_fill16(src + loff + i * 8 * NW * KPB, dst + (NW * i + wave) * 1024);
 }
 
 template <int KPB>

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void pf_l1(const BatchHead* __restrict__ head,
                                              uint16_t* __restrict__ Hb) {
     constexpr int BM = 128, BN = 128, WM = 2, WN = 2;
     typedef TileGeom<BM, BN, WM, WN> TG;
-    __shared__ TileSmem<BM, BN, WM * WN> sm;
+    EJ_TILE_SMEM(BM, BN, WM * WN, sm);
     __shared__ int s_seg;
     const int64_t tile = (int64_t)blockIdx.y * gridDim.x / 2 + blockIdx.x / 2;
     const int tn = blockIdx.x & 1;
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void pf_l2(int64_t n_rows, const uint16_t* __r
                                              const float* __restrict__ b2, float* __restrict__ Z) {
     constexpr int BM = 128, BN = 64, WM = 2, WN = 2;
     typedef TileGeom<BM, BN, WM, WN> TG;
-    __shared__ TileSmem<BM, BN, WM * WN> sm;
+    EJ_TILE_SMEM(BM, BN, WM * WN, sm);
     const int64_t tm = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     if (tm * BM >= n_rows) return;
     v16f acc[TG::FM][TG::FN];
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void pf_assign(const BatchHead* __restrict__ h
                                                  int32_t* __restrict__ key) {
     constexpr int BM = 128, BN = 128, WM = 2, WN = 2;
     typedef TileGeom<BM, BN, WM, WN> TG;
-    __shared__ TileSmem<BM, BN, WM * WN> sm;
+    EJ_TILE_SMEM(BM, BN, WM * WN, sm);
     __shared__ float s_v[WN][BM];
     __shared__ int s_i[WN][BM];
     const int64_t tm = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(256) void pf_sidemax(const BatchHead* __restrict__ 
                                                   float* __restrict__ M2) {
     constexpr int BM = 128, BN = 128, WM = 2, WN = 2;
     typedef TileGeom<BM, BN, WM, WN> TG;
-    __shared__ TileSmem<BM, BN, WM * WN> sm;
+    EJ_TILE_SMEM(BM, BN, WM * WN, sm);
     __shared__ float s_v[WN][BM];
     const int64_t item = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     if (item >= head->n_side) return;

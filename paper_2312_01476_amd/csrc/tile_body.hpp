@@ -29,13 +29,27 @@
 
 namespace ej {
 
+// LDS of one tile: two slots per operand for the K slices.  The four slots
+// are separate LDS arrays (declared by EJ_TILE_SMEM in the kernel), so the
+// compiler can tell the slot being filled by direct loads from the slot being
+// read and does not wait for the fills before every LDS read.
 template <int BM, int BN, int NW>
 struct TileSmem {
-    __attribute__((aligned(16))) char sA[2][BM * 128];
-    __attribute__((aligned(16))) char sB[2][BN * 128];
-    uint32_t s_cnt[2 * NW];
-    unsigned long long s_base[2];
+    char* a[2];
+    char* b[2];
+    uint32_t* s_cnt;             // 2 * NW wave counts
+    unsigned long long* s_base;  // 2 list bases
 };
+
+#define EJ_TILE_SMEM(BM_, BN_, NW_, name)                                                  \
+    __shared__ __attribute__((aligned(16))) char name##_a0[(BM_) * 128];                   \
+    __shared__ __attribute__((aligned(16))) char name##_a1[(BM_) * 128];                   \
+    __shared__ __attribute__((aligned(16))) char name##_b0[(BN_) * 128];                   \
+    __shared__ __attribute__((aligned(16))) char name##_b1[(BN_) * 128];                   \
+    __shared__ uint32_t name##_cnt[2 * (NW_)];                                             \
+    __shared__ unsigned long long name##_base[2];                                          \
+    TileSmem<BM_, BN_, NW_> name = {{name##_a0, name##_a1}, {name##_b0, name##_b1}, name##_cnt, \
+                                    name##_base}
 
 // Grouped rasterisation of a tile index: GROUP_M tile rows at a time.
 __device__ __forceinline__ void raster_tile(int bid, int tiles_m, int tiles_n, int& tm, int& tn) {
@@ -70,6 +84,14 @@ struct TileGeom {
 // (unused otherwise).  Only the first kg_last k-groups of the last slice are
 // contracted (the rest of it is zero padding).  All threads of the workgroup
 // call this.
+//
+// K slices (128 bytes per row) go from global memory straight into LDS
+// (direct loads, no staging registers): slice kb + 1 is filled into one slot
+// while slice kb is multiplied out of the other.  A slice of R rows is R / 8
+// blocks of 1 KB; instruction i of wave w fills block NW i + w, lane l writing
+// the 16 bytes at l * 16, so the lane loads the chunk that the XOR swizzle of
+// lds_off places there (its row is 8 (NW i + w) + l / 8, its chunk
+// (l % 8) ^ ((row / 2) % 8), which does not depend on i for an even NW).
 template <int PREC, int BM, int BN, int WM, int WN>
 __device__ __forceinline__ void tile_mainloop(
     TileSmem<BM, BN, WM * WN>& sm, const char* __restrict__ A, const char* __restrict__ B,
@@ -77,12 +99,12 @@ __device__ __forceinline__ void tile_mainloop(
     int tn, v16f (&acc)[TileGeom<BM, BN, WM, WN>::FM][TileGeom<BM, BN, WM, WN>::FN],
     int kg_last = Mma<PREC>::GROUPS) {
     typedef TileGeom<BM, BN, WM, WN> TG;
-    constexpr int NT = TG::NT;
+    constexpr int NW = TG::NW;
     constexpr int WTM = TG::WTM, WTN = TG::WTN, FM = TG::FM, FN = TG::FN;
-    constexpr int CA = TG::CA, CB = TG::CB;
+    constexpr int NFA = BM / (8 * NW), NFB = BN / (8 * NW);  // fills per wave and slice
+    static_assert(NFA * 8 * NW == BM && NFB * 8 * NW == BN && NW % 2 == 0,
+                  "the tile rows must spread evenly over the waves' fills");
     typedef Mma<PREC> M;
-    auto& sA = sm.sA;
-    auto& sB = sm.sB;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -116,35 +138,28 @@ __device__ __forceinline__ void tile_mainloop(
             sb[j] = 127 - ilogbf(info_s[(int64_t)tn * BN + wn * WTN + j * 32 + r32].qscale);
     }
 
-    v4i ra[CA], rb[CB];
-    auto gload = [&](int kb) {
+    // the wave index as a wave-uniform value: the LDS address of a direct
+    // load goes through m0
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+    const int frow = wave_u * 8 + (lane >> 3);
+    const int64_t loff = (int64_t)frow * Kp_bytes + (((lane & 7) ^ ((frow >> 1) & 7)) << 4);
+    const int64_t istride = (int64_t)8 * NW * Kp_bytes;
+    auto fill = [&](auto st_c, int kb) {
+        constexpr int st = decltype(st_c)::value;
+        const char* ga = Ag + kb * 128 + loff;
+        const char* gb = Bg + kb * 128 + loff;
 #pragma unroll
-        for (int i = 0; i < CA; ++i) {
-            int q = tid + i * NT;
-            ra[i] = *(const v4i*)(Ag + (int64_t)(q >> 3) * Kp_bytes + kb * 128 + (q & 7) * 16);
-        }
+        for (int i = 0; i < NFA; ++i) lds_fill16(ga + i * istride, sm.a[st] + (NW * i + wave_u) * 1024);
 #pragma unroll
-        for (int i = 0; i < CB; ++i) {
-            int q = tid + i * NT;
-            rb[i] = *(const v4i*)(Bg + (int64_t)(q >> 3) * Kp_bytes + kb * 128 + (q & 7) * 16);
-        }
-    };
-    auto lstore = [&](int st) {
-#pragma unroll
-        for (int i = 0; i < CA; ++i) {
-            int q = tid + i * NT;
-            *(v4i*)(&sA[st][lds_off(q >> 3, q & 7)]) = ra[i];
-        }
-#pragma unroll
-        for (int i = 0; i < CB; ++i) {
-            int q = tid + i * NT;
-            *(v4i*)(&sB[st][lds_off(q >> 3, q & 7)]) = rb[i];
-        }
+        for (int i = 0; i < NFB; ++i) lds_fill16(gb + i * istride, sm.b[st] + (NW * i + wave_u) * 1024);
     };
 
-    // the matrix-core steps of the first NG k-groups of the slice in stage st
-    auto compute = [&](int st, auto ng_c) {
+    // the matrix-core steps of the first NG k-groups of the slice in slot st
+    auto compute = [&](auto st_c, auto ng_c) {
+        constexpr int st = decltype(st_c)::value;
         constexpr int NG = decltype(ng_c)::value;
+        const char* la = sm.a[st];
+        const char* lb = sm.b[st];
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             typename M::Frag fa[FM], fb[FN];
@@ -153,7 +168,7 @@ __device__ __forceinline__ void tile_mainloop(
                 const int row = wm * WTM + i * 32 + r32;
 #pragma unroll
                 for (int c = 0; c < M::CPL; ++c) {
-                    v4i v = *(const v4i*)(&sA[st][lds_off(row, M::chunk(g, h, c))]);
+                    v4i v = *(const v4i*)(la + lds_off(row, M::chunk(g, h, c)));
 #pragma unroll
                     for (int e = 0; e < 4; ++e) fa[i][c * 4 + e] = v[e];
                 }
@@ -163,7 +178,7 @@ __device__ __forceinline__ void tile_mainloop(
                 const int row = wn * WTN + j * 32 + r32;
 #pragma unroll
                 for (int c = 0; c < M::CPL; ++c) {
-                    v4i v = *(const v4i*)(&sB[st][lds_off(row, M::chunk(g, h, c))]);
+                    v4i v = *(const v4i*)(lb + lds_off(row, M::chunk(g, h, c)));
 #pragma unroll
                     for (int e = 0; e < 4; ++e) fb[j][c * 4 + e] = v[e];
                 }
@@ -179,34 +194,72 @@ __device__ __forceinline__ void tile_mainloop(
                         M::mma_sub(fa[i], fb[j], acc[i][j], sa[i], sb[j], u);
         }
     };
+    // last slice: only its k-groups that hold data (a uniform switch, so the
+    // steady-state steps keep their fully unrolled schedule); the largest
+    // tiles have no registers to spare for more copies of the slice code and
+    // contract it whole
+    auto last = [&](auto st_c) {
+        if constexpr (BM * BN > 128 * 128) {
+            compute(st_c, std::integral_constant<int, M::GROUPS>{});
+        } else {
+            switch (kg_last) {
+                case 1: compute(st_c, std::integral_constant<int, 1>{}); break;
+                case 2:
+                    if constexpr (M::GROUPS >= 2) compute(st_c, std::integral_constant<int, 2>{});
+                    break;
+                case 3:
+                    if constexpr (M::GROUPS >= 3) compute(st_c, std::integral_constant<int, 3>{});
+                    break;
+                default: compute(st_c, std::integral_constant<int, M::GROUPS>{}); break;
+            }
+        }
+    };
+    typedef std::integral_constant<int, 0> S0;
+    typedef std::integral_constant<int, 1> S1;
+    typedef std::integral_constant<int, M::GROUPS> GALL;
 
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int kb = 0; kb + 1 < nk; ++kb) {
-        const int st = kb & 1;
-        gload(kb + 1);
-        compute(st, std::integral_constant<int, M::GROUPS>{});
-        lstore(st ^ 1);
-        __syncthreads();
-    }
-    const int st_last = (nk - 1) & 1;
+    // Step over slice kb in slot kb % 2: its fills (issued one step earlier)
+    // have landed once this wave's loads are done; the barrier publishes every
+    // wave's part and retires the reads of slice kb - 1, whose slot slice
+    // kb + 1 takes.
+    fill(S0{}, 0);
     if constexpr (BM * BN > 128 * 128) {
-        // the largest tiles have no registers to spare for more copies of
-        // the slice code: they contract the last slice whole
-        compute(st_last, std::integral_constant<int, M::GROUPS>{});
+        // largest tiles: a branch-free loop over pairs of slices (the 256
+        // accumulators per lane leave the register allocator no room for
+        // the copies that merging branches would need); past the last slice
+        // the fill reloads it (never read)
+        const int nk2 = nk & ~1;
+        for (int kb = 0; kb < nk2; kb += 2) {
+            wait_vmcnt_lgkm0<0>();
+            bare_barrier();
+            fill(S1{}, kb + 1);
+            compute(S0{}, GALL{});
+            wait_vmcnt_lgkm0<0>();
+            bare_barrier();
+            fill(S0{}, min(kb + 2, nk - 1));
+            compute(S1{}, GALL{});
+        }
+        wait_vmcnt_lgkm0<0>();
+        bare_barrier();
+        if (nk & 1) compute(S0{}, GALL{});
     } else {
-        // last slice: only its k-groups that hold data (a uniform switch, so
-        // the steady-state loop above keeps its fully unrolled schedule)
-        switch (kg_last) {
-            case 1: compute(st_last, std::integral_constant<int, 1>{}); break;
-            case 2:
-                if constexpr (M::GROUPS >= 2) compute(st_last, std::integral_constant<int, 2>{});
-                break;
-            case 3:
-                if constexpr (M::GROUPS >= 3) compute(st_last, std::integral_constant<int, 3>{});
-                break;
-            default: compute(st_last, std::integral_constant<int, M::GROUPS>{}); break;
+        for (int kb = 0; kb < nk; kb += 2) {
+            wait_vmcnt_lgkm0<0>();
+            bare_barrier();
+            if (kb + 1 < nk) {
+                fill(S1{}, kb + 1);
+                compute(S0{}, GALL{});
+                wait_vmcnt_lgkm0<0>();
+                bare_barrier();
+                if (kb + 2 < nk) {
+                    fill(S0{}, kb + 2);
+                    compute(S1{}, GALL{});
+                } else {
+                    last(S1{});
+                }
+            } else {
+                last(S0{});
+            }
         }
     }
     __syncthreads();
@@ -353,11 +406,12 @@ __device__ __forceinline__ void big_tile_body(
     v16f acc[TG::FM][TG::FN];
     tile_mainloop<PREC, 256, 256, 2, 2>(sm, A, B, info_r, info_s, Kp_bytes, tm, tn, acc, kg_last);
     // the mainloop ends on a barrier: the operand LDS is free for staging
+    // (two waves per 32 KB operand slot)
     constexpr int PER_WAVE = ST_OUT * (int)sizeof(Pair) + ST_BAND * (int)sizeof(BE);
-    static_assert(4 * PER_WAVE <= (int)sizeof(sm.sA), "staging does not fit");
+    static_assert(2 * PER_WAVE <= 256 * 128, "staging does not fit");
     const int wave = threadIdx.x >> 6;
     const int wm = wave / 2, wn = wave % 2;
-    char* base = &sm.sA[0][0] + wave * PER_WAVE;
+    char* base = (wave < 2 ? sm.a[0] : sm.b[0]) + (wave & 1) * PER_WAVE;
     const bool edge = ((int64_t)(tm + 1) * 256 > nR) || ((int64_t)(tn + 1) * 256 > nS);
     stage_epilogue<TG::FM, TG::FN, TAG>(acc, (int64_t)tm * 256 + wm * TG::WTM,
                                         (int64_t)tn * 256 + wn * TG::WTN, edge, nR, nS, lo, hi,
