@@ -38,7 +38,7 @@ DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}
 # counter runs scaled by a plain copy of known size (the commands and the raw
 # figures are in profiles/threshold_fp32_100k_traffic.md); valid for the
 # kernel as it was when the counters were taken, keyed by workload and tile
-TRAFFIC = {("fp32_100k", "fp32:128x128x32"): 6204576.8 * 1024 * 2.0 + 613741.3 * 1024 * 1.0}
+TRAFFIC = {("fp32_100k", "fp32:128x128x32"): 6204551.8 * 1024 * 2.0 + 617169.5 * 1024 * 1.0}
 
 
 def log(*a):
@@ -93,6 +93,11 @@ def main():
                     help="batched workloads: time every tile first and use the fastest")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-verify", action="store_true", help="skip the sampled parity check")
+    ap.add_argument("--theta", type=float, default=None,
+                    help="threshold workloads, diagnostic: another theta (e.g. 0.999 for a "
+                         "run without result pairs); the line then reports the changed config")
+    ap.add_argument("--n-s", type=int, default=None,
+                    help="threshold workloads, diagnostic: generate only this many S rows")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -120,6 +125,12 @@ def main():
     if w.extra.get("batch"):
         return bench_batch(args, w)
     prec = w.prec
+    diagnostic = args.theta is not None or args.n_s is not None
+    if diagnostic:
+        import dataclasses
+        w = dataclasses.replace(w, theta=args.theta if args.theta is not None else w.theta,
+                                n_s=args.n_s if args.n_s is not None else w.n_s)
+        log(f"[bench] diagnostic config: theta {w.theta}, |S| {w.n_s}")
     log(f"[bench] workload {w.name}: {w.notes}")
     Rd, Sd, Rh, Sh, lr, ls = make_inputs(w, torch)
     torch.cuda.synchronize()
@@ -166,7 +177,7 @@ def main():
     unit, peak = PEAK[prec]
     tile_name = E.lib().ejoin_tile_name(st["tile"]).decode()
     kname = "panel_kernel<ThresholdEpi>" if "panel" in tile_name else "threshold_tile"
-    traffic = TRAFFIC.get((w.name, tile_name))
+    traffic = None if diagnostic else TRAFFIC.get((w.name, tile_name))
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4),
             "traffic": round(traffic) if traffic else None,
@@ -196,7 +207,7 @@ def main():
         else:
             err = None
         verify = {"subblock": f"{sub}x{sub}", "subblock_set_equal": bool(same),
-                  "count_equals_label_count": bool(n == expected),
+                  "count_equals_label_count": None if diagnostic else bool(n == expected),
                   "sampled_max_abs_score_err": err}
         log(f"[bench] verify {verify}")
 
@@ -223,7 +234,8 @@ def main():
         "config": {"workload": w.name, "n_r": w.n_r, "n_s": w.n_s, "dim": w.d, "ld": w.ld,
                    "theta": w.theta, "prec": prec, "clusters": w.n_clusters,
                    "sigma": w.sigma, "pairs_out": n, "band_pairs": st["n_band"],
-                   "tile": E.lib().ejoin_tile_name(st["tile"]).decode()},
+                   "tile": E.lib().ejoin_tile_name(st["tile"]).decode(),
+                   **({"diagnostic": True} if diagnostic else {})},
         "roofline": roof,
         "cpu_baseline": cpu,
         "verify": verify,
