@@ -523,6 +523,14 @@ __device__ __forceinline__ double wave_dot64(const float* __restrict__ r,
     return acc;
 }
 
+// The four waves of a workgroup take four consecutive rows of the
+// neighbourhood order, which mostly share their candidates.  When every wave
+// with live candidates holds the same live list, the workgroup rescores that
+// list together: each wave loads a quarter of every candidate chunk into LDS
+// and all four multiply it with their own row, so each candidate row is read
+// once per workgroup instead of once per wave.  Otherwise every wave rescores
+// its own list (wave_dot64).  Each lane's FP64 sum keeps the sequential order
+// of the canonical definition in both cases.
 __global__ __launch_bounds__(256) void topk_finalize_w(
     const float* __restrict__ R, int64_t ldR, const float* __restrict__ S, int64_t ldS, int dim,
     int64_t nR, int64_t nS, const double* __restrict__ nr64, const double* __restrict__ ns64,
@@ -531,6 +539,7 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
     const int* __restrict__ order, unsigned long long* __restrict__ hdr,
     int* __restrict__ fb_rows, int32_t* __restrict__ out_idx, float* __restrict__ out_score) {
     __shared__ FinSmem sm;
+    __shared__ int s_nl[FW_WAVES], s_same[FW_WAVES];
     if (hdr[H_FLAGS] != 0) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double* v = sm.v[w];
@@ -540,100 +549,194 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
     const double es = (double)__uint_as_float((uint32_t)hdr[H_ENORM_S]) * 1.001 + 1e-7;
     const int kk = (int)min((int64_t)k, nS);
 
-    for (int64_t rr = (int64_t)blockIdx.x * FW_WAVES + w; rr < nR;
-         rr += (int64_t)gridDim.x * FW_WAVES) {
-        const int64_t i = order ? order[rr] : rr;
-        if (nS == 0) {  // nothing to join: every slot is padding
-            for (int t = lane; t < k; t += 64) {
-                out_idx[i * k + t] = -1;
-                out_score[i * k + t] = -INFINITY;
-            }
-            continue;
-        }
-        const int c = cnt[i];
-        const int n = min(c, Kc);
-        const double er = (double)info_r[i].enorm * 1.001 + 1e-7;
-        const double di = er * (1.0 + es) + es + fp32_terms * (1.0 + er) * (1.0 + es);
-        for (int t = lane; t < 256; t += 64) {
-            if (t < n) {
-                const int2 e = cand[i * (int64_t)Kc + t];
-                v[t] = (double)__int_as_float(e.y);
-                jv[t] = e.x;
+    // workgroup-uniform loop: the barriers below need all four waves
+    for (int64_t base = (int64_t)blockIdx.x * FW_WAVES; base < nR;
+         base += (int64_t)gridDim.x * FW_WAVES) {
+        const int64_t rr = base + w;
+        int n_live = 0;  // wave-uniform: candidates this wave rescores
+        int64_t i = 0;
+        if (rr < nR) {
+            i = order ? order[rr] : rr;
+            if (nS == 0) {  // nothing to join: every slot is padding
+                for (int t = lane; t < k; t += 64) {
+                    out_idx[i * k + t] = -1;
+                    out_score[i * k + t] = -INFINITY;
+                }
             } else {
-                v[t] = -INFINITY;
-                jv[t] = 0x7fffffff;
-            }
-        }
-        if (lane == 0) sm.lim[w] = -INFINITY;
-        wave_sync();
-        bool ok = c <= Kc;
-        if (ok) {
-            if (F == -INFINITY) {
-                ok = (int64_t)n == nS;  // every column present
-            } else {
-                ok = n >= kk;
-                if (ok) {
-                    // the entry of rank kk-1 among the n candidates
-                    for (int t = lane; t < n; t += 64) {
-                        const double vt = v[t];
-                        const int jt = jv[t];
-                        int rank = 0;
-                        for (int u = 0; u < n; ++u) rank += better(v[u], jv[u], vt, jt);
-                        if (rank == kk - 1) sm.lim[w] = vt - 2.0 * di;
+                const int c = cnt[i];
+                const int n = min(c, Kc);
+                const double er = (double)info_r[i].enorm * 1.001 + 1e-7;
+                const double di = er * (1.0 + es) + es + fp32_terms * (1.0 + er) * (1.0 + es);
+                for (int t = lane; t < 256; t += 64) {
+                    if (t < n) {
+                        const int2 e = cand[i * (int64_t)Kc + t];
+                        v[t] = (double)__int_as_float(e.y);
+                        jv[t] = e.x;
+                    } else {
+                        v[t] = -INFINITY;
+                        jv[t] = 0x7fffffff;
                     }
-                    wave_sync();
-                    ok = sm.lim[w] >= (double)F;
+                }
+                if (lane == 0) sm.lim[w] = -INFINITY;
+                wave_sync();
+                bool ok = c <= Kc;
+                if (ok) {
+                    if (F == -INFINITY) {
+                        ok = (int64_t)n == nS;  // every column present
+                    } else {
+                        ok = n >= kk;
+                        if (ok) {
+                            // the entry of rank kk-1 among the n candidates
+                            for (int t = lane; t < n; t += 64) {
+                                const double vt = v[t];
+                                const int jt = jv[t];
+                                int rank = 0;
+                                for (int u = 0; u < n; ++u) rank += better(v[u], jv[u], vt, jt);
+                                if (rank == kk - 1) sm.lim[w] = vt - 2.0 * di;
+                            }
+                            wave_sync();
+                            ok = sm.lim[w] >= (double)F;
+                        }
+                    }
+                }
+                if (!ok) {  // wave-uniform
+                    if (lane == 0) {
+                        const unsigned long long p = atomicAdd(hdr + H_TOPK_FB, 1ull);
+                        fb_rows[p] = (int)i;
+                    }
+                } else {
+                    const double lim = sm.lim[w];
+                    // compact the candidates that can still be in the top k
+                    for (int t0 = 0; t0 < n; t0 += 64) {
+                        const int t = t0 + lane;
+                        const bool lv = t < n && v[t] >= lim;
+                        const uint64_t m = __ballot(lv);
+                        if (lv) live[n_live + lanes_below(m)] = jv[t];
+                        n_live += __popcll(m);
+                    }
                 }
             }
         }
-        if (!ok) {  // wave-uniform
-            if (lane == 0) {
-                const unsigned long long p = atomicAdd(hdr + H_TOPK_FB, 1ull);
-                fb_rows[p] = (int)i;
+        if (lane == 0) s_nl[w] = n_live;
+        __syncthreads();
+        // shared list: that of the first wave with one, if every other wave
+        // with a list holds the same
+        int ref = -1;
+        for (int u = 0; u < FW_WAVES; ++u)
+            if (ref < 0 && s_nl[u] > 0) ref = u;
+        if (n_live > 0) {
+            bool same = n_live == s_nl[ref];
+            if (same && w != ref) {
+                const int* L = sm.live[ref];
+                bool eq = true;
+                for (int t = lane; t < n_live; t += 64) eq = eq && live[t] == L[t];
+                same = __ballot(!eq) == 0;
             }
-            wave_sync();
-            continue;
+            if (lane == 0) s_same[w] = same ? 1 : 0;
+        } else if (lane == 0) {
+            s_same[w] = 1;
         }
-        const double lim = sm.lim[w];
-        // compact the candidates that can still be in the top k
-        int n_live = 0;
-        for (int t0 = 0; t0 < n; t0 += 64) {
-            const int t = t0 + lane;
-            const bool lv = t < n && v[t] >= lim;
-            const uint64_t m = __ballot(lv);
-            if (lv) live[n_live + lanes_below(m)] = jv[t];
-            n_live += __popcll(m);
-        }
-        wave_sync();
-        // FP64 rescore of the live candidates, 64 per pass
+        __syncthreads();
+        const bool coop =
+            ref >= 0 && s_same[0] && s_same[1] && s_same[2] && s_same[3];  // workgroup-uniform
         const float* rrow = R + i * ldR;
-        for (int p0 = 0; p0 < n_live; p0 += 64) {
-            const int t = p0 + lane;
-            const bool valid = t < n_live;
-            const int sj = valid ? live[t] : 0;
-            const double dot = wave_dot64(rrow, S, ldS, sj, valid, dim, sm.rows[w], sm.rch[w]);
-            if (valid) {
-                v[t] = sim64_from(dot, nr64[i], ns64[sj]);
-                jv[t] = sj;
+        if (coop) {
+            const int n = s_nl[ref];
+            const int* L = sm.live[ref];
+            // two chunk buffers (the candidate chunks of the workgroup and
+            // this wave's row chunk): chunk c + 1 is loaded while chunk c is
+            // multiplied
+            // the chunks are widened to FP64 once, when stored (each candidate
+            // value serves four rows); the four per-wave float buffers hold
+            // the two FP64 candidate buffers
+            static_assert(2 * 64 * FW_STRIDE * sizeof(double) <= sizeof(sm.rows),
+                          "FP64 chunk buffers do not fit");
+            double* const rows0 = (double*)&sm.rows[0][0];
+            double* const rows1 = rows0 + 64 * FW_STRIDE;
+            __shared__ double s_rch[2][FW_WAVES][FW_CH];
+            double* const rch0 = s_rch[0][w];
+            double* const rch1 = s_rch[1][w];
+            const int kk2 = lane & 31;
+            const int nch = (dim + FW_CH - 1) / FW_CH;
+            float vals[8];
+            float rv = 0.0f;
+            auto load = [&](int p0, int c) {
+                const int k0 = c * FW_CH, kn = min(FW_CH, dim - k0);
+                rv = (n_live > 0 && lane < kn) ? rrow[k0 + lane] : 0.0f;
+                // this wave's 16 of the pass's 64 candidate rows, two rows
+                // per load instruction (lanes 0-31 one, 32-63 the next)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int tb = p0 + 16 * w + 2 * q + (lane >> 5);
+                    vals[q] = (tb < n && kk2 < kn) ? S[(int64_t)L[tb] * ldS + k0 + kk2] : 0.0f;
+                }
+            };
+            auto store = [&](int c) {
+                double* r = (c & 1) ? rows1 : rows0;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    r[(16 * w + 2 * q + (lane >> 5)) * FW_STRIDE + kk2] = (double)vals[q];
+                if (lane < FW_CH) ((c & 1) ? rch1 : rch0)[lane] = (double)rv;
+            };
+            for (int p0 = 0; p0 < n; p0 += 64) {
+                const int t = p0 + lane;
+                const bool valid = t < n;
+                double acc = 0.0;
+                load(p0, 0);
+                store(0);
+                __syncthreads();
+                for (int c = 0; c < nch; ++c) {
+                    if (c + 1 < nch) load(p0, c + 1);
+                    if (n_live > 0 && valid) {
+                        const double* mine = ((c & 1) ? rows1 : rows0) + lane * FW_STRIDE;
+                        const double* rc = (c & 1) ? rch1 : rch0;
+                        const int kn = min(FW_CH, dim - c * FW_CH);
+                        for (int q = 0; q < kn; ++q) acc = acc + rc[q] * mine[q];
+                    }
+                    // buffer (c + 1) & 1 was last read for chunk c - 1, before
+                    // the previous barrier
+                    if (c + 1 < nch) store(c + 1);
+                    __syncthreads();
+                }
+                if (n_live > 0 && valid) {
+                    const int sj = L[t];
+                    v[t] = sim64_from(acc, nr64[i], ns64[sj]);
+                    jv[t] = sj;
+                }
+            }
+        } else if (n_live > 0) {
+            // FP64 rescore of this wave's live candidates, 64 per pass
+            for (int p0 = 0; p0 < n_live; p0 += 64) {
+                const int t = p0 + lane;
+                const bool valid = t < n_live;
+                const int sj = valid ? live[t] : 0;
+                const double dot =
+                    wave_dot64(rrow, S, ldS, sj, valid, dim, sm.rows[w], sm.rch[w]);
+                if (valid) {
+                    v[t] = sim64_from(dot, nr64[i], ns64[sj]);
+                    jv[t] = sj;
+                }
             }
         }
-        wave_sync();
-        // final order by rank among the live entries
-        for (int t = lane; t < n_live; t += 64) {
-            const double vt = v[t];
-            const int jt = jv[t];
-            int rank = 0;
-            for (int u = 0; u < n_live; ++u) rank += better(v[u], jv[u], vt, jt);
-            if (rank < kk) {
-                out_idx[i * k + rank] = jt;
-                out_score[i * k + rank] = (float)vt;
+        if (n_live > 0) {
+            wave_sync();
+            // final order by rank among the live entries
+            for (int t = lane; t < n_live; t += 64) {
+                const double vt = v[t];
+                const int jt = jv[t];
+                int rank = 0;
+                for (int u = 0; u < n_live; ++u) rank += better(v[u], jv[u], vt, jt);
+                if (rank < kk) {
+                    out_idx[i * k + rank] = jt;
+                    out_score[i * k + rank] = (float)vt;
+                }
+            }
+            for (int t = kk + lane; t < k; t += 64) {
+                out_idx[i * k + t] = -1;
+                out_score[i * k + t] = -INFINITY;
             }
         }
-        for (int t = kk + lane; t < k; t += 64) {
-            out_idx[i * k + t] = -1;
-            out_score[i * k + t] = -INFINITY;
-        }
-        wave_sync();
+        __syncthreads();  // the lists and buffers are reused by the next rows
     }
 }
 
