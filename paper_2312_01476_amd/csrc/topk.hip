@@ -7,9 +7,10 @@
 // (sequential sums from the float32 inputs, dot / sqrt(|r|^2 |s|^2)), ordered
 // by (similarity desc, S index asc):
 //
-//  1. a pilot computes the exact k-th similarity T_k of a few sample rows and
-//     sets the candidate floor F = min T_k - 2 D (D: largest error bound of
-//     the approximate scores);
+//  1. a pilot computes the exact k-th similarity T_k of a few sample rows
+//     (over a strided sample of the columns when S is large, which can only
+//     lower T_k) and sets the candidate floor F = min T_k - 2 D (D: largest
+//     error bound of the approximate scores);
 //  2. the contraction sweep (panel kernel, candidate epilogue) stores every
 //     column with approximate score a >= F in its row's candidate slots;
 //  3. per row: A_k = k-th largest candidate score, D_i = the row's error
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(256) void exact_topk_rows(
     const int* __restrict__ rows_list, const unsigned long long* __restrict__ n_rows_ptr,
     int n_rows_fixed, int row_base, int row_limit, int32_t* __restrict__ out_idx,
     float* __restrict__ out_score, double* __restrict__ kth_out, double* __restrict__ part_v,
-    int* __restrict__ part_j) {
+    int* __restrict__ part_j, int col_stride) {
     __shared__ StageSmem sm;
     __shared__ double bv[XK_BUF];
     __shared__ int bj[XK_BUF];
@@ -160,9 +161,12 @@ __global__ __launch_bounds__(256) void exact_topk_rows(
     const int n_rows_all = n_rows_ptr ? (int)*n_rows_ptr : n_rows_fixed;
     const int n_rows = min(n_rows_all, row_limit);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // the scanned columns are c * col_stride for c < n_col (every column
+    // with col_stride 1), split into n_rg ranges of c
+    const int64_t n_col = (nS + col_stride - 1) / col_stride;
     const int n_rg = gridDim.y, rg = blockIdx.y;
-    const int64_t per = (nS + n_rg - 1) / n_rg;
-    const int64_t s_lo = rg * per, s_hi = min(nS, s_lo + per);
+    const int64_t per = (n_col + n_rg - 1) / n_rg;
+    const int64_t s_lo = rg * per, s_hi = min(n_col, s_lo + per);
     for (int rr = row_base + blockIdx.x; rr < n_rows; rr += gridDim.x) {
         const int64_t i = rows_list[rr];
         const float* r = R + i * ldR;
@@ -173,14 +177,14 @@ __global__ __launch_bounds__(256) void exact_topk_rows(
             s_thr_j = 0x7fffffff;
         }
         __syncthreads();
-        for (int64_t j0 = s_lo; j0 < s_hi; j0 += 256) {
-            const int64_t jj = j0 + threadIdx.x;
-            sm.row_of[threadIdx.x] = jj < s_hi ? jj : -1;
+        for (int64_t c0 = s_lo; c0 < s_hi; c0 += 256) {
+            const int64_t jj = (c0 + threadIdx.x) * col_stride;
+            sm.row_of[threadIdx.x] = c0 + threadIdx.x < s_hi ? jj : -1;
             __syncthreads();
             const double dot = block_dots(S, ldS, r, dim, sm);
             double v = -INFINITY;
             bool cand = false;
-            if (jj < s_hi) {
+            if (c0 + threadIdx.x < s_hi) {
                 v = sim64_from(dot, nr, ns64[jj]);
                 cand = better(v, (int)jj, s_thr_v, s_thr_j);
             }
@@ -765,17 +769,19 @@ static int exact_ranges(int64_t nS) {
 }
 
 // exact top-k of list entries [row_base, row_base + n) (n <= part rows)
+// (col_stride > 1: over the columns c * col_stride only)
 static hipError_t exact_topk_batch(const TopkArgs& a, const int* rows,
                                    const unsigned long long* n_ptr, int n_fixed, int row_base,
                                    int n_rows_max, int32_t* oi, float* os, double* kth,
-                                   hipStream_t st) {
-    const int n_rg = exact_ranges(a.nS);
+                                   hipStream_t st, int col_stride = 1) {
+    const int64_t n_col = (a.nS + col_stride - 1) / col_stride;
+    const int n_rg = exact_ranges(n_col);
     hipLaunchKernelGGL(exact_topk_rows, dim3(n_rows_max, n_rg), dim3(256), 0, st, a.R, a.ldR,
                        a.S, a.ldS, a.dim, a.nS, a.nr64, a.ns64, a.k, rows, n_ptr, n_fixed,
                        row_base, row_base + n_rows_max, (int32_t*)nullptr, (float*)nullptr,
-                       (double*)nullptr, a.part_v, a.part_j);
+                       (double*)nullptr, a.part_v, a.part_j, col_stride);
     hipLaunchKernelGGL(exact_topk_merge, dim3(n_rows_max), dim3(256), 0, st, rows, n_ptr,
-                       n_fixed, row_base, row_base + n_rows_max, n_rg, a.k, a.nS,
+                       n_fixed, row_base, row_base + n_rows_max, n_rg, a.k, n_col,
                        (const double*)a.part_v, (const int*)a.part_j, oi, os, kth);
     return hipGetLastError();
 }
@@ -783,8 +789,12 @@ static hipError_t exact_topk_batch(const TopkArgs& a, const int* rows,
 hipError_t launch_topk_pilot(const TopkArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(pilot_rows, dim3((a.n_pilot + 255) / 256), dim3(256), 0, st, a.pilot_rows,
                        a.n_pilot, a.nR);
+    // the pilot scans every 4th column of a large S: the k-th similarity over
+    // that sample is a lower bound of the k-th over all of S, and any floor
+    // keeps the result exact (a lower floor only admits more candidates)
+    const int stride = a.nS >= 65536 ? 4 : 1;
     hipError_t e = exact_topk_batch(a, a.pilot_rows, nullptr, a.n_pilot, 0, a.n_pilot, nullptr,
-                                    nullptr, a.pilot_kth, st);
+                                    nullptr, a.pilot_kth, st, stride);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(topk_floor, dim3(1), dim3(64), 0, st, a.hdr, a.pilot_kth, a.n_pilot,
                        a.fp32_terms, a.all_columns ? 1 : 0);
@@ -825,7 +835,7 @@ hipError_t launch_topk_fallback(const TopkArgs& a, int64_t n_fb, hipStream_t st)
         hipLaunchKernelGGL(exact_topk_rows, dim3(1024, 1), dim3(256), 0, st, a.R, a.ldR, a.S,
                            a.ldS, a.dim, a.nS, a.nr64, a.ns64, a.k, (const int*)a.fb_rows, cnt,
                            0, 0, 0x7fffffff, a.out_idx, a.out_score, (double*)nullptr,
-                           (double*)nullptr, (int*)nullptr);
+                           (double*)nullptr, (int*)nullptr, 1);
         return hipGetLastError();
     }
     for (int64_t b = 0; b < n_fb; b += a.part_rows) {

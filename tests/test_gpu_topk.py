@@ -96,6 +96,17 @@ def test_depths_and_ragged(prec, d):
     _check(R, S, 10, prec)
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_large_s_strided_pilot(prec):
+    """|S| >= 65536: the pilot sets the floor from every 4th column; the
+    result must still be the exact top-k (rows checked in full)."""
+    cent = G.centres(64, 400, seed=21)
+    R, _ = G.clustered_points(cent, 256, 0.3, seed=22)
+    S, _ = G.clustered_points(cent, 70000, 0.3, seed=23)
+    st = _check(R, S, 10, prec)
+    assert st["n_fallback"] < R.shape[0] // 4
+
+
 def test_unsupported_and_invalid():
     R = _dev(G.gaussian_raw(10, 8, seed=1))
     with pytest.raises(E.EjoinError):
