@@ -42,12 +42,12 @@ ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts*
         const int t = o->tuner ? tuner_pick(o->tuner, 0, p.prec, p.dim, (double)p.nR * p.nS) : 0;
         const TileDesc* td = t > 0 ? tile_get(t) : nullptr;
         const bool fits = td && td->prec == p.prec &&
-                          !(td->bm == 0 && p.Kp * elem_bytes(p.prec) > 768);
+                          !(td->bm == 0 && !panel_fits(t, p.Kp * elem_bytes(p.prec)));
         p.tile = fits ? t : default_tile(p.prec, p.Kp);
     }
     const TileDesc* td = tile_get(p.tile);
     if (!td || td->prec != p.prec) return EJOIN_E_INVAL;
-    if (td->bm == 0 && p.Kp * elem_bytes(p.prec) > 768) return EJOIN_E_INVAL;
+    if (td->bm == 0 && !panel_fits(p.tile, p.Kp * elem_bytes(p.prec))) return EJOIN_E_INVAL;
     p.band_cap = o->band_capacity > 0 ? o->band_capacity
                                       : std::max<int64_t>(1 << 16, p.nR + p.nS);
     const size_t eb = (size_t)elem_bytes(p.prec);

@@ -549,7 +549,8 @@ static hipError_t run_panel(const void* A, const void* B, const RowInfo* info_r,
     return hipGetLastError();
 }
 
-// Kp * element size must be KS * 128 bytes with KS in 1..6.
+// Kp * element size must be KS * 128 bytes with KS in 1..6 (BF16 one
+// workgroup per CU: also 8, 9, 10, 12).
 //  * two_waves: one 32-row block per wave, two workgroups of four waves per
 //    CU (the epilogue of one overlaps the MFMAs of the other); K slices on a
 //    three-slot direct-load ring when KS is a multiple of 3;
@@ -597,6 +598,12 @@ static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const vo
             case 4: EJ_RUN(4, 1, 4, 8, 1, 4);
             case 5: EJ_RUN(5, 1, 4, 8, 1, 5);
             case 6: EJ_RUN(6, 1, 4, 8, 1, 6);
+            // deeper rows: the resident fragments of one 32-row block fill
+            // most of a 512-register wave, so four waves (one per SIMD)
+            case 8: EJ_RUN(8, 1, 4, 4, 1, 4);
+            case 9: EJ_RUN(9, 1, 4, 4, 1, 3);
+            case 10: EJ_RUN(10, 1, 4, 4, 1, 5);
+            case 12: EJ_RUN(12, 1, 4, 4, 1, 6);
         }
     } else {
         // FP8 fragments are twice as wide per MFMA

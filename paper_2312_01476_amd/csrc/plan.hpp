@@ -86,12 +86,20 @@ inline bool rel_ok(const ejoin_rel* X) {
 
 // planner default: the register-resident panel kernel for narrow formats
 // whose rows fit it (up to 768 bytes of K), else the LDS tile kernel
+// Row depths (K bytes) a panel tile takes: up to 768; the BF16 one-workgroup
+// panel (tile 12) also 1024, 1152, 1280 and 1536.
+inline bool panel_fits(int tile, int kpb) {
+    if (kpb <= 768) return true;
+    return tile == 12 && (kpb == 1024 || kpb == 1152 || kpb == 1280 || kpb == 1536);
+}
+
 inline int default_tile(int prec, int Kp) {
     if (prec == P_FP32) return 1;
     // register panels: eight waves on a direct-load ring from three K slices
     // of 128 bytes on, two workgroups of four waves below that (BF16)
     if (Kp * elem_bytes(prec) <= 768)
         return prec == P_FP8 ? 13 : (Kp * elem_bytes(prec) >= 384 ? 12 : 14);
+    if (prec == P_BF16 && panel_fits(12, Kp * 2)) return 12;
     return prec == P_BF16 ? 3 : 5;
 }
 

@@ -222,11 +222,13 @@ def test_tile_shapes_fp8(tile):
     _check(R, S, 0.8, d=w.d, prec="fp8", tile=tile)
 
 
-@pytest.mark.parametrize("prec,d", [("bf16", 64), ("bf16", 200), ("bf16", 384), ("fp8", 128),
+@pytest.mark.parametrize("prec,d", [("bf16", 64), ("bf16", 200), ("bf16", 384), ("bf16", 500),
+                                    ("bf16", 560), ("bf16", 640), ("bf16", 768), ("fp8", 128),
                                     ("fp8", 300), ("fp8", 700)])
 def test_panel_kernel_depths(prec, d):
     """Every resident-fragment depth of the panel kernel, ragged |R| and |S|
-    (several panels, S chunks and a partial last tile)."""
+    (several panels, S chunks and a partial last tile); BF16 500 / 560 / 640 /
+    768 are the deep rows (8, 9, 10, 12 K slices) of four waves per CU."""
     cent = G.centres(d, 40, seed=d)
     R, lr = G.clustered_points(cent, 1100, 0.3, seed=d + 1)
     S, ls = G.clustered_points(cent, 1900, 0.3, seed=d + 2)
