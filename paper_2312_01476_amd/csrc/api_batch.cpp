@@ -34,9 +34,19 @@ struct SplitMix64 {
 };
 constexpr int kRescoreGrid = 2048;  // batched rescore: grid-stride over the band list
 
-// measured on the 64-job 768-d workload: the 256 x 256 staged tile is the
-// fastest BF16 batch tile; FP32 and FP8 keep their 128 x 128 tiles
+// measured on the 64-job 768-d workload: BF16 register panels (tile 19) where
+// every job's row depth has one, else the 256 x 256 staged tile; FP32 and FP8
+// keep their 128 x 128 tiles
 int batch_default_tile(int prec) { return prec == P_FP32 ? 1 : prec == P_BF16 ? 16 : 5; }
+constexpr int kPanelChunkTiles = 16;  // S tiles (of 128 columns) per panel work item
+
+bool panel_jobs_ok(const ejoin_job* jobs, int n) {
+    for (int i = 0; i < n; ++i)
+        if (jobs[i].R.rows > 0 && jobs[i].S.rows > 0 &&
+            !batch_panel_depth(padded_k(EJOIN_BF16, jobs[i].R.dim) * 2))
+            return false;
+    return true;
+}
 
 bool job_ok(const ejoin_job& j) {
     if (!rel_ok(&j.R) || !rel_ok(&j.S) || j.R.dim != j.S.dim) return false;
@@ -81,8 +91,10 @@ int pick_batch_tile(const ejoin_opts& o, const ejoin_job* jobs, int n) {
         for (int i = 0; i < n; ++i) pairs += (double)jobs[i].R.rows * (double)jobs[i].S.rows;
         const int t = tuner_pick(o.tuner, 1, o.prec, dim, pairs);
         const TileDesc* td = t > 0 ? tile_get(t) : nullptr;
-        if (td && td->prec == o.prec && batch_has_tile(t)) return t;
+        if (td && td->prec == o.prec && batch_has_tile(t) && (t != 19 || panel_jobs_ok(jobs, n)))
+            return t;
     }
+    if (o.prec == EJOIN_BF16 && n > 0 && panel_jobs_ok(jobs, n)) return 19;
     return batch_default_tile(o.prec);
 }
 
@@ -104,6 +116,7 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
     if (o.prec < EJOIN_FP32 || o.prec > EJOIN_FP8_E4M3) return EJOIN_E_INVAL;
     const TileDesc* td = tile_get(tile);
     if (!td || td->prec != o.prec || !batch_has_tile(tile)) return EJOIN_E_INVAL;
+    if (tile == 19 && !panel_jobs_ok(jobs, n)) return EJOIN_E_INVAL;
     bp.prec = o.prec;
     bp.tile = tile;
     bp.bm = td->bm;
@@ -176,7 +189,14 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         b.kg_last = last_slice_groups(o.prec, dim);
         b.user = order[q];
         b.tile_base = tile_base;
-        tile_base += (int64_t)b.tiles_m * b.tiles_n;
+        b.chunk_tiles = 0;
+        if (tile == 19) {
+            // panel items: every 128-row panel over chunks of S tiles
+            b.chunk_tiles = kPanelChunkTiles;
+            tile_base += (int64_t)b.tiles_m * ((b.tiles_n + kPanelChunkTiles - 1) / kPanelChunkTiles);
+        } else {
+            tile_base += (int64_t)b.tiles_m * b.tiles_n;
+        }
         bp.pairs_total += u.R.rows * u.S.rows;
         if (empty) continue;
         band_default += std::max<int64_t>(65536, u.R.rows + u.S.rows);

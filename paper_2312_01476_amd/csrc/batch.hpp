@@ -35,6 +35,7 @@ struct BatchJob {
     int32_t Kp_bytes, dim;
     int32_t user;              // index of the job in the caller's array
     int32_t kg_last;           // k-groups of the last K slice that hold data
+    int32_t chunk_tiles;       // panel form: S tiles per work item
     // prefilter mode: the prepared rows are in code order; perm maps a
     // prepared row back to the caller's row, rtile0 / stile0 are the flat
     // indices of the first 128-row tiles of R and S

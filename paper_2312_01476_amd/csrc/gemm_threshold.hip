@@ -63,6 +63,8 @@ static const TileDesc kTiles[] = {
     {16, P_BF16, 256, 256, 64, "bf16:256x256x64/4w/staged"},
     {17, P_FP8, 256, 256, 128, "fp8:256x256x128/4w/staged"},
     {18, P_FP32, 256, 256, 32, "fp32:256x256x32/4w/staged"},
+    // batches only: BF16 register panels of 128 rows, 128-column S tiles
+    {19, P_BF16, 128, 128, 64, "bf16:panel/batch"},
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }

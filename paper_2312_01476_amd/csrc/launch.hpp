@@ -113,6 +113,12 @@ struct BatchHead;
 struct BatchJob;
 struct PrepSeg;
 bool batch_has_tile(int tile_id);  // the tile has a persistent batch form
+// batch form on BF16 register panels (tile 19): the K depths it takes, its
+// resident workgroups per CU, its launch
+bool batch_panel_depth(int kpb);
+int batch_panel_occupancy();
+hipError_t launch_batch_panel(const BatchHead* head, const BatchJob* jobs,
+                              unsigned long long* bctr, int grid, hipStream_t st);
 int batch_occupancy(int tile_id);  // resident workgroups per CU, 0: no batch form
 hipError_t launch_batch_zero(const BatchHead* head, unsigned long long* bctr, hipStream_t st);
 hipError_t launch_batch_prep(int prec, const BatchHead* head, const PrepSeg* segs, int grid,

@@ -22,7 +22,9 @@
 //  * CandEpi -- top-k candidates: every column with score >= a floor goes to
 //    its row's candidate slots (the workgroup sweeps all of S, so each row is
 //    owned by one wave and its counter lives in LDS).
+#include "batch.hpp"
 #include "common.hpp"
+#include "epi_stage.hpp"
 #include "launch.hpp"
 #include "mma.hpp"
 
@@ -68,17 +70,20 @@ struct ThresholdParams {
     float lo, hi;
     Pair* out;
     int64_t capacity;
-    int2* band;
+    unsigned long long* out_ctr;   // pairs appended to out
+    void* band;                    // int2 {r, s}, or int4 {r, s, job, 0} with TAG
     int64_t band_cap;
-    unsigned long long* hdr;
+    unsigned long long* band_ctr;  // band entries found
+    int job;
 };
 
-template <int NW>
-struct ThresholdEpi {
+template <int NW, bool TAG>
+struct ThresholdEpiT {
     typedef ThresholdParams Params;
+    typedef typename BandEntryT<TAG>::type BE;
     struct Smem {
         Pair out[NW][PN_OUTCAP];
-        int2 band[NW][PN_BANDCAP];
+        BE band[NW][PN_BANDCAP];
     };
     struct State {
         int n_out, n_band;  // staged entries of this wave (wave-uniform)
@@ -120,11 +125,11 @@ struct ThresholdEpi {
                     const int e4 = 4 * q4;
                     // room for the at most 4 x 64 hits of this group
                     if (s.n_out > PN_OUTCAP - 256)
-                        flush_stage(sm.out[c.wave], s.n_out, p.out, p.capacity, p.hdr + H_OUT,
+                        flush_stage(sm.out[c.wave], s.n_out, p.out, p.capacity, p.out_ctr,
                                     c.lane);
                     if (s.n_band > PN_BANDCAP - 256)
-                        flush_stage(sm.band[c.wave], s.n_band, p.band, p.band_cap,
-                                    p.hdr + H_BAND, c.lane);
+                        flush_stage(sm.band[c.wave], s.n_band, (BE*)p.band, p.band_cap,
+                                    p.band_ctr, c.lane);
                     const int gj = gj0 + cb * 32;
                     const bool vj = !c.edge || gj < c.nS;
                     uint64_t ml[4];
@@ -150,7 +155,12 @@ struct ThresholdEpi {
                             pr.score = a;
                             sm.out[c.wave][s.n_out + lanes_below(mhi)] = pr;
                         } else if (in_lo) {
-                            sm.band[c.wave][s.n_band + lanes_below(mb)] = make_int2(gi, gj);
+                            BE be;
+                            if constexpr (TAG)
+                                be = make_int4(gi, gj, p.job, 0);
+                            else
+                                be = make_int2(gi, gj);
+                            sm.band[c.wave][s.n_band + lanes_below(mb)] = be;
                         }
                         s.n_out += __popcll(mhi);
                         s.n_band += __popcll(mb);
@@ -160,9 +170,9 @@ struct ThresholdEpi {
 
     __device__ static __forceinline__ void finish(const Params& p, Smem& sm, State& s, const TileCtx& c) {
         if (s.n_out)
-            flush_stage(sm.out[c.wave], s.n_out, p.out, p.capacity, p.hdr + H_OUT, c.lane);
+            flush_stage(sm.out[c.wave], s.n_out, p.out, p.capacity, p.out_ctr, c.lane);
         if (s.n_band)
-            flush_stage(sm.band[c.wave], s.n_band, p.band, p.band_cap, p.hdr + H_BAND, c.lane);
+            flush_stage(sm.band[c.wave], s.n_band, (BE*)p.band, p.band_cap, p.band_ctr, c.lane);
     }
 };
 
@@ -170,6 +180,10 @@ struct ThresholdEpi {
 // top-k candidate epilogue: every (i, j) with approximate score >= floor goes
 // to slot cnt[i]++ of row i (slots past Kc are counted, not written)
 // ---------------------------------------------------------------------------
+// the single-join form (untagged band entries)
+template <int NW>
+using ThresholdEpi = ThresholdEpiT<NW, false>;
+
 struct CandParams {
     const unsigned long long* hdr;  // floor as float bits in H_TOPK_F
     int* cnt;                       // per R row, number of candidates seen
@@ -334,12 +348,18 @@ __device__ __forceinline__ void slice_mma(const char* sl, int ks,
 // which lets the compiler see that the fills in flight never touch the slot
 // being read and keeps it from waiting for them before the LDS reads (the
 // waits for the fills are the explicit vmcnt waits).
-template <int PREC, int KS, int RB, int CB, int NW, int OCC, int NSLOT, class EPI>
-__global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
-    const char* __restrict__ A, const char* __restrict__ B, const RowInfo* __restrict__ info_r,
-    const RowInfo* __restrict__ info_s, int64_t nR, int64_t nS, int n_panels, int n_items,
-    int tiles_per_chunk, int n_stiles, const unsigned long long* __restrict__ flags, int grid_x,
-    typename EPI::Params ep) {
+// The sweep of one R panel over S tiles [t0, t1): resident R fragments,
+// S slices through the LDS ring `slots` (see panel_kernel), one epilogue per
+// S tile.  All threads of the workgroup call this; it ends with every fill
+// landed and the epilogue's staging flushed.
+template <int PREC, int KS, int RB, int CB, int NW, int NSLOT, class EPI>
+__device__ __forceinline__ void panel_sweep(char* const (&slots)[6], typename EPI::Smem& esm,
+                                            const char* __restrict__ A,
+                                            const char* __restrict__ B,
+                                            const RowInfo* __restrict__ info_r,
+                                            const RowInfo* __restrict__ info_s, int64_t nR,
+                                            int64_t nS, int panel, int t0, int t1,
+                                            const typename EPI::Params& ep) {
     typedef Mma<PREC> M;
     constexpr int G = M::GROUPS;
     constexpr int NF = KS * G;        // A fragments per 32-row block
@@ -357,28 +377,8 @@ __global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
                   "direct loads need a static ring slot per slice");
     constexpr int D = NS - 1;  // fill distance of the direct-load ring
 
-    __shared__ __attribute__((aligned(16))) char sL0[SLOT];
-    __shared__ __attribute__((aligned(16))) char sL1[SLOT];
-    __shared__ __attribute__((aligned(16))) char sL2[NS > 2 ? SLOT : 16];
-    __shared__ __attribute__((aligned(16))) char sL3[NS > 3 ? SLOT : 16];
-    __shared__ __attribute__((aligned(16))) char sL4[NS > 4 ? SLOT : 16];
-    __shared__ __attribute__((aligned(16))) char sL5[NS > 5 ? SLOT : 16];
-    __shared__ typename EPI::Smem esm;
-    char* const slots[6] = {sL0, sL1, sL2, sL3, sL4, sL5};
-
-    // (hardware ids through the builtins: with the kernel's size the inliner
-    // leaves library helpers as calls, which would put the ids in vector
-    // registers and hide their uniformity)
-    const int item =
-        (int)(__builtin_amdgcn_workgroup_id_y() * grid_x + __builtin_amdgcn_workgroup_id_x());
-    if (item >= n_items) return;
-    if (flags[H_FLAGS] != 0) return;
-    const int chunk = item / n_panels;
-    const int panel = item - chunk * n_panels;
-    const int t0 = chunk * tiles_per_chunk;
-    const int t1 = min(t0 + tiles_per_chunk, n_stiles);
-    if (t0 >= t1) return;
-
+    char* const sL0 = slots[0];
+    char* const sL1 = slots[1];
     TileCtx ctx;
     const int tid = (int)__builtin_amdgcn_workitem_id_x();
     ctx.lane = tid & 63;
@@ -518,6 +518,146 @@ __global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
     EPI::finish(ep, esm, est, ctx);
 }
 
+template <int PREC, int KS, int RB, int CB, int NW, int OCC, int NSLOT, class EPI>
+__global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
+    const char* __restrict__ A, const char* __restrict__ B, const RowInfo* __restrict__ info_r,
+    const RowInfo* __restrict__ info_s, int64_t nR, int64_t nS, int n_panels, int n_items,
+    int tiles_per_chunk, int n_stiles, const unsigned long long* __restrict__ flags, int grid_x,
+    typename EPI::Params ep) {
+    constexpr int PN_BN = 32 * CB;
+    constexpr int SLOT = PN_BN * 128;
+    constexpr bool DMA = NSLOT > 0;
+    constexpr int NS = DMA ? NSLOT : 2;
+    __shared__ __attribute__((aligned(16))) char sL0[SLOT];
+    __shared__ __attribute__((aligned(16))) char sL1[SLOT];
+    __shared__ __attribute__((aligned(16))) char sL2[NS > 2 ? SLOT : 16];
+    __shared__ __attribute__((aligned(16))) char sL3[NS > 3 ? SLOT : 16];
+    __shared__ __attribute__((aligned(16))) char sL4[NS > 4 ? SLOT : 16];
+    __shared__ __attribute__((aligned(16))) char sL5[NS > 5 ? SLOT : 16];
+    __shared__ typename EPI::Smem esm;
+    char* const slots[6] = {sL0, sL1, sL2, sL3, sL4, sL5};
+
+    // (hardware ids through the builtins: with the kernel's size the inliner
+    // leaves library helpers as calls, which would put the ids in vector
+    // registers and hide their uniformity)
+    const int item =
+        (int)(__builtin_amdgcn_workgroup_id_y() * grid_x + __builtin_amdgcn_workgroup_id_x());
+    if (item >= n_items) return;
+    if (flags[H_FLAGS] != 0) return;
+    const int chunk = item / n_panels;
+    const int panel = item - chunk * n_panels;
+    const int t0 = chunk * tiles_per_chunk;
+    const int t1 = min(t0 + tiles_per_chunk, n_stiles);
+    if (t0 >= t1) return;
+
+    panel_sweep<PREC, KS, RB, CB, NW, NSLOT, EPI>(slots, esm, A, B, info_r, info_s, nR, nS, panel,
+                                                  t0, t1, ep);
+}
+
+// ---------------------------------------------------------------------------
+// batched threshold joins on deep register panels (BF16, 8 / 9 / 10 / 12 K
+// slices per row)
+// ---------------------------------------------------------------------------
+// One persistent launch for all jobs, as the tile form (batch.hip) but with
+// panel work items: job j owns items [tile_base_j, tile_base_j + tiles_m_j *
+// ceil(tiles_n_j / chunk_tiles_j)), tiles_m = 128-row R panels, tiles_n =
+// 128-column S tiles; an item is one panel's sweep over chunk_tiles S tiles
+// (panel index fastest, so the items running together share their S chunk).
+// The K depth of each job selects the sweep; band entries carry the job.
+constexpr int BP_SLOT = 128 * 128;
+
+template <int KS>
+__device__ __forceinline__ void batch_panel_item(char* const (&slots)[6],
+                                                 typename ThresholdEpiT<4, true>::Smem& esm,
+                                                 const BatchJob& J, int panel, int t0, int t1,
+                                                 const ThresholdParams& ep) {
+    constexpr int NSLOT = KS == 8 ? 4 : KS == 9 ? 3 : KS == 10 ? 5 : 6;
+    panel_sweep<P_BF16, KS, 1, 4, 4, NSLOT, ThresholdEpiT<4, true>>(
+        slots, esm, J.A, J.B, J.info_r, J.info_s, J.nR, J.nS, panel, t0, t1, ep);
+}
+
+__global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restrict__ head,
+                                                      const BatchJob* __restrict__ jobs,
+                                                      unsigned long long* __restrict__ bctr) {
+    __shared__ __attribute__((aligned(16))) char sL0[BP_SLOT];
+    __shared__ __attribute__((aligned(16))) char sL1[BP_SLOT];
+    __shared__ __attribute__((aligned(16))) char sL2[BP_SLOT];
+    __shared__ __attribute__((aligned(16))) char sL3[BP_SLOT];
+    __shared__ __attribute__((aligned(16))) char sL4[BP_SLOT];
+    __shared__ __attribute__((aligned(16))) char sL5[BP_SLOT];
+    __shared__ typename ThresholdEpiT<4, true>::Smem esm;
+    __shared__ int64_t s_item;
+    __shared__ int s_job;
+    char* const slots[6] = {sL0, sL1, sL2, sL3, sL4, sL5};
+    const int64_t total = head->n_tiles;
+    const int n_jobs = head->n_jobs;
+    const int tid = (int)__builtin_amdgcn_workitem_id_x();
+    for (;;) {
+        if (tid == 0) {
+            const int64_t item = (int64_t)atomicAdd(bctr + B_ITEM, 1ull);
+            int job = 0;
+            if (item < total) {
+                // last job whose first item is <= item
+                int lo = 0, hi = n_jobs - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (jobs[mid].tile_base <= item) lo = mid;
+                    else hi = mid - 1;
+                }
+                job = lo;
+            }
+            s_item = item;
+            s_job = job;
+        }
+        // (also: every wave is done with the previous item's ring slots)
+        __syncthreads();
+        const int64_t item = s_item;
+        const int job = __builtin_amdgcn_readfirstlane(s_job);
+        __syncthreads();  // the shared slots are rewritten by the next iteration
+        if (item >= total) break;
+        const BatchJob& J = jobs[job];
+        if (J.hdr[H_FLAGS] != 0) continue;  // bad input rows in this job
+        const int64_t local = item - J.tile_base;
+        const int panel = (int)(local % J.tiles_m);
+        const int t0 = (int)(local / J.tiles_m) * J.chunk_tiles;
+        const int t1 = min(t0 + J.chunk_tiles, J.tiles_n);
+        ThresholdParams ep;
+        ep.lo = J.lo;
+        ep.hi = J.hi;
+        ep.out = J.out;
+        ep.capacity = J.capacity;
+        ep.out_ctr = J.hdr + H_OUT;
+        ep.band = head->band;
+        ep.band_cap = head->band_cap;
+        ep.band_ctr = bctr + B_BAND;
+        ep.job = job;
+        switch (J.Kp_bytes) {  // uniform
+            case 8 * 128: batch_panel_item<8>(slots, esm, J, panel, t0, t1, ep); break;
+            case 9 * 128: batch_panel_item<9>(slots, esm, J, panel, t0, t1, ep); break;
+            case 10 * 128: batch_panel_item<10>(slots, esm, J, panel, t0, t1, ep); break;
+            default: batch_panel_item<12>(slots, esm, J, panel, t0, t1, ep); break;
+        }
+    }
+}
+
+// K bytes per row the batch panel form takes
+bool batch_panel_depth(int kpb) {
+    return kpb == 8 * 128 || kpb == 9 * 128 || kpb == 10 * 128 || kpb == 12 * 128;
+}
+
+int batch_panel_occupancy() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_panel, 256, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+
+hipError_t launch_batch_panel(const BatchHead* head, const BatchJob* jobs,
+                              unsigned long long* bctr, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(batch_panel, dim3((unsigned)grid), dim3(256), 0, st, head, jobs, bctr);
+    return hipGetLastError();
+}
+
 // S chunks per panel: the threshold sweep is split so that there are enough
 // workgroups to balance the 256 CUs (about 32 per CU); the top-k sweep must
 // see all of S in one workgroup (one chunk).
@@ -631,9 +771,11 @@ hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs&
     ep.hi = a.hi;
     ep.out = a.out;
     ep.capacity = a.capacity;
+    ep.out_ctr = a.hdr + H_OUT;
     ep.band = a.band;
     ep.band_cap = a.band_cap;
-    ep.hdr = a.hdr;
+    ep.band_ctr = a.hdr + H_BAND;
+    ep.job = 0;
     const int ks = slices(prec, a.Kp);
     if (prec == P_BF16)
         return dispatch_panel<P_BF16, ThresholdEpi>(ks, two_waves, a.A, a.B, a.info_r, a.info_s,

@@ -29,8 +29,11 @@ int size_bucket(double pairs) {
 bool tile_runs(int tile, int prec, int Kp, bool batch) {
     const TileDesc* td = tile_get(tile);
     if (!td || td->prec != prec) return false;
-    if (batch) return td->bm != 0 && batch_has_tile(tile);
-    return !(td->bm == 0 && Kp * elem_bytes(prec) > 768);
+    if (batch)
+        return td->bm != 0 && batch_has_tile(tile) &&
+               (tile != 19 || batch_panel_depth(Kp * elem_bytes(prec)));
+    if (tile == 19) return false;  // a batch-only form
+    return !(td->bm == 0 && !panel_fits(tile, Kp * elem_bytes(prec)));
 }
 
 }  // namespace

@@ -97,6 +97,15 @@ def test_batch_workspace_query():
         ot = E._opts("bf16", None, tile, 0, 0)
         assert L.ejoin_batch_workspace(ok, 1, C.byref(ot)) == 0
     assert L.ejoin_batch_workspace(ok, 1, C.byref(E._opts("bf16", None, 8, 0, 0))) > 0
+    # the batch panel form takes only depths it has a register panel for
+    # (BF16 rows of 8, 9, 10 or 12 K slices); empty jobs do not count
+    o19 = E._opts("bf16", None, 19, 0, 0)
+    assert L.ejoin_batch_workspace(ok, 1, C.byref(o19)) > 0
+    mixed = (E.Job * 3)(_job(E, 10, 10), _job(E, 10, 10, d=500), _job(E, 0, 10, d=96))
+    assert L.ejoin_batch_workspace(mixed, 3, C.byref(o19)) > 0
+    for d in (96, 384, 1024):
+        assert L.ejoin_batch_workspace((E.Job * 1)(_job(E, 10, 10, d=d)), 1, C.byref(o19)) == 0
+    assert L.ejoin_batch_workspace(ok, 1, C.byref(E._opts("fp32", None, 19, 0, 0))) == 0
     # empty batch is valid
     assert L.ejoin_batch_workspace(ok, 0, C.byref(o)) > 0
 

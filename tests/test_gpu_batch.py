@@ -123,6 +123,30 @@ def test_batch_tile_invariance_bf16(tile):
         _check_job(R, S, th, rr, "bf16", st["band"])
 
 
+def test_batch_panel_form_bf16():
+    """Tile 19 (register panels, 128-row panels swept over chunks of 16 S
+    tiles): jobs of 768-, 640-, 560- and 500-d rows in one batch, one job with
+    several panels and S chunks; it is the default for such a batch."""
+    host = _job_mix(d=768, seed=23)[:4] + _job_mix(d=640, seed=29)[4:7] + \
+        _job_mix(d=560, seed=31)[7:] + _job_mix(d=500, seed=33)[:3]
+    cent = G.centres(768, 20, seed=37)
+    R = G.clustered_points(cent, 300, 0.3, seed=38)[0]
+    S = G.clustered_points(cent, 5000, 0.3, seed=39)[0]
+    host.append((R, S, float(np.quantile(O.sim_matrix(R[:50], S), 0.99))))
+    jobs = _to_dev(host)
+    for tile in (19, 0):
+        res, st = E.batch(jobs, prec="bf16", tile=tile)
+        assert st["tile"] == 19
+        for (R_, S_, th), rr in zip(host, res):
+            _check_job(R_, S_, th, rr, "bf16", st["band"])
+
+
+def test_batch_panel_form_rejects_other_depths():
+    jobs = _to_dev(_job_mix(d=96, seed=41))
+    with pytest.raises(E.EjoinError):
+        E.batch(jobs, prec="bf16", tile=19)
+
+
 def test_batch_fp8_tiles():
     host = _job_mix(seed=19)
     jobs = _to_dev(host)
