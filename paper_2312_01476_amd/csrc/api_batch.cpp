@@ -66,8 +66,8 @@ struct BatchPlan {
     size_t off_hb = 0, off_z = 0, off_u = 0, off_key = 0, off_pa = 0, off_pb = 0, off_hist = 0,
            off_offs = 0, off_c = 0, off_rho = 0, off_cn = 0, off_alpha = 0, off_work = 0,
            off_ub = 0, off_aidx = 0, off_af = 0, off_ab = 0, off_lab = 0, off_up = 0,
-           off_dir = 0, off_m1 = 0, off_m2 = 0;
-    int64_t n_side = 0;
+           off_dir = 0, off_m1 = 0, off_m2 = 0, off_keep = 0, off_wmask = 0;
+    int64_t n_side = 0, n_chunks = 0;
     int n_anchor = 0;
     std::vector<int64_t> anchor_idx;  // flat rows whose codes are the anchors
     std::vector<char> image;  // head, jobs[table_jobs], segs[2 * table_jobs]
@@ -84,7 +84,9 @@ size_t table_size(int table_jobs) {
 
 int pick_batch_tile(const ejoin_opts& o, const ejoin_job* jobs, int n) {
     if (o.tile > 0) return o.tile;
-    if (o.flags & EJOIN_APPROX_PREFILTER) return 3;  // 128 x 128 tiles: the statistics' grain
+    // prefilter mode: 128 x 128 tiles or 128-row panels, the statistics' grain
+    if (o.flags & EJOIN_APPROX_PREFILTER)
+        return o.prec == EJOIN_BF16 && n > 0 && panel_jobs_ok(jobs, n) ? 19 : 3;
     if (o.tuner && n > 0) {
         double pairs = 0.0;
         int dim = jobs[0].R.dim;
@@ -108,7 +110,7 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
     if (bp.approx) {
         // the network reads BF16 prepared rows; tile statistics are per 128 rows
         if (o.prec != EJOIN_BF16 || !o.prefilter || !(o.prefilter_eps >= 0.0f)) return EJOIN_E_INVAL;
-        if (tile != 3) return EJOIN_E_INVAL;
+        if (tile != 3 && tile != 19) return EJOIN_E_INVAL;
         for (int i = 1; i < n; ++i)
             if (jobs && jobs[i].R.dim != jobs[0].R.dim) return EJOIN_E_INVAL;
         if (n > 0 && jobs && (jobs[0].R.dim < 1 || jobs[0].R.dim > 1024)) return EJOIN_E_UNSUPPORTED;
@@ -190,10 +192,16 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         b.user = order[q];
         b.tile_base = tile_base;
         b.chunk_tiles = 0;
+        b.chunk_base = bp.n_chunks;
         if (tile == 19) {
-            // panel items: every 128-row panel over chunks of S tiles
+            // panel items: every 128-row panel over chunks of S tiles; the
+            // prefilter keeps flat tile numbers for its statistics and
+            // lists the chunks separately
             b.chunk_tiles = kPanelChunkTiles;
-            tile_base += (int64_t)b.tiles_m * ((b.tiles_n + kPanelChunkTiles - 1) / kPanelChunkTiles);
+            const int64_t items =
+                (int64_t)b.tiles_m * ((b.tiles_n + kPanelChunkTiles - 1) / kPanelChunkTiles);
+            bp.n_chunks += items;
+            tile_base += bp.approx ? (int64_t)b.tiles_m * b.tiles_n : items;
         } else {
             tile_base += (int64_t)b.tiles_m * b.tiles_n;
         }
@@ -265,6 +273,10 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         bp.off_dir = take((nr / 128 + 128) * MLP_OUT * 2);
         bp.off_m1 = take((size_t)bp.n_tiles * 4);
         bp.off_m2 = take((size_t)bp.n_tiles * 4);
+        if (tile == 19) {
+            bp.off_keep = take((size_t)bp.n_tiles);
+            bp.off_wmask = take((size_t)bp.n_chunks * 4);
+        }
         for (int q = 0; q < n; ++q) {
             J[q].side_base = bp.n_side;
             bp.n_side += (int64_t)((J[q].tiles_m + 127) / 128) * J[q].tiles_n +
@@ -314,6 +326,10 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         h->work = (const int64_t*)at(bp.off_work);
         h->n_side = bp.n_side;
         h->n_work = (const unsigned long long*)at(B_WORK * sizeof(unsigned long long));
+        if (tile == 19) {
+            h->work_mask = (const uint32_t*)at(bp.off_wmask);
+            h->n_chunks = bp.n_chunks;
+        }
     }
     return EJOIN_OK;
 }
@@ -413,8 +429,14 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
                              (uint16_t*)(ws + bp.off_up), (uint16_t*)(ws + bp.off_dir),
                              (float*)(ws + bp.off_m1), (float*)(ws + bp.off_m2), bp.n_side,
                              o.prefilter_eps,
-                             (int64_t*)(ws + bp.off_work), bctr + B_WORK, bp.n_tiles, st)) !=
+                             (int64_t*)(ws + bp.off_work), bctr + B_WORK, bp.n_tiles,
+                             bp.tile == 19 ? (uint8_t*)(ws + bp.off_keep) : nullptr, st)) !=
         hipSuccess)
+        return e;
+    if (bp.tile == 19 &&
+        (e = launch_pf_chunks(head, jobs, (const uint8_t*)(ws + bp.off_keep),
+                              (int64_t*)(ws + bp.off_work), (uint32_t*)(ws + bp.off_wmask),
+                              bctr + B_WORK, bctr + B_KEPT, bp.n_chunks, st)) != hipSuccess)
         return e;
     if ((e = rec(1)) != hipSuccess) return e;
     const int tg = (int)std::max<int64_t>(1, std::min<int64_t>(tile_grid, bp.n_tiles));
@@ -521,7 +543,8 @@ ejoin_status ejoin_batch(const ejoin_job* jobs, int32_t n_jobs, const ejoin_opts
     }
     if (stats) {
         stats->tiles_total = bp.n_tiles;
-        stats->tiles_kept = bp.approx ? (int64_t)h[B_WORK] : bp.n_tiles;
+        stats->tiles_kept =
+            bp.approx ? (int64_t)h[bp.tile == 19 ? B_KEPT : B_WORK] : bp.n_tiles;
         stats->n_pairs = total;
         stats->n_band = (int64_t)band_found;
         stats->n_band_accepted = acc;

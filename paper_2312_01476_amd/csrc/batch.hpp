@@ -43,6 +43,7 @@ struct BatchJob {
     const int32_t* perm_s;
     int64_t rtile0, stile0;
     int64_t side_base;         // first item of this job's tile-to-rows bound pass
+    int64_t chunk_base;        // prefilter panel form: first (panel, S chunk) item
 };
 
 // One relation to prepare (R or S of a job; an aliased self-join has one).
@@ -71,13 +72,18 @@ struct BatchHead {
     const int64_t* work;
     const unsigned long long* n_work;
     int64_t n_side;            // items of the tile-to-rows bound pass
+    // prefilter panel form: work items are (job, panel, first S tile of a
+    // chunk); work_mask[i] has bit b set when S tile tn + b of item i is kept
+    const uint32_t* work_mask;
+    int64_t n_chunks;          // (panel, S chunk) items over all jobs
 };
 
 // Global counters of a batch pass.
 enum : int {
     B_ITEM = 0,     // next work item of the persistent kernel
     B_BAND = 1,     // band entries found (may exceed band_cap)
-    B_WORK = 2,     // prefilter: surviving tile pairs
+    B_WORK = 2,     // prefilter: surviving work items
+    B_KEPT = 3,     // prefilter panel form: surviving tile pairs
     B_COUNT = 32
 };
 

@@ -75,6 +75,10 @@ struct ThresholdParams {
     int64_t band_cap;
     unsigned long long* band_ctr;  // band entries found
     int job;
+    // with TAG (batch): prepared row -> caller's row maps of the prefilter
+    // order, or null
+    const int32_t* perm_r;
+    const int32_t* perm_s;
 };
 
 template <int NW, bool TAG>
@@ -148,18 +152,24 @@ struct ThresholdEpiT {
                         const bool in_hi = in_lo && a >= p.hi;
                         const uint64_t mhi = __ballot(in_hi);
                         const uint64_t mb = ml[k] & ~mhi;
+                        int ri = gi, si = gj;
+                        if constexpr (TAG)
+                            if (in_lo && p.perm_r) {
+                                ri = p.perm_r[gi];
+                                si = p.perm_s[gj];
+                            }
                         if (in_hi) {
                             Pair pr;
-                            pr.r = gi;
-                            pr.s = gj;
+                            pr.r = ri;
+                            pr.s = si;
                             pr.score = a;
                             sm.out[c.wave][s.n_out + lanes_below(mhi)] = pr;
                         } else if (in_lo) {
                             BE be;
                             if constexpr (TAG)
-                                be = make_int4(gi, gj, p.job, 0);
+                                be = make_int4(ri, si, p.job, 0);
                             else
-                                be = make_int2(gi, gj);
+                                be = make_int2(ri, si);
                             sm.band[c.wave][s.n_band + lanes_below(mb)] = be;
                         }
                         s.n_out += __popcll(mhi);
@@ -352,14 +362,14 @@ __device__ __forceinline__ void slice_mma(const char* sl, int ks,
 // S slices through the LDS ring `slots` (see panel_kernel), one epilogue per
 // S tile.  All threads of the workgroup call this; it ends with every fill
 // landed and the epilogue's staging flushed.
-template <int PREC, int KS, int RB, int CB, int NW, int NSLOT, class EPI>
+template <int PREC, int KS, int RB, int CB, int NW, int NSLOT, class EPI, bool MASK = false>
 __device__ __forceinline__ void panel_sweep(char* const (&slots)[6], typename EPI::Smem& esm,
                                             const char* __restrict__ A,
                                             const char* __restrict__ B,
                                             const RowInfo* __restrict__ info_r,
                                             const RowInfo* __restrict__ info_s, int64_t nR,
                                             int64_t nS, int panel, int t0, int t1,
-                                            const typename EPI::Params& ep) {
+                                            const typename EPI::Params& ep, uint32_t mask = 0) {
     typedef Mma<PREC> M;
     constexpr int G = M::GROUPS;
     constexpr int NF = KS * G;        // A fragments per 32-row block
@@ -375,7 +385,19 @@ __device__ __forceinline__ void panel_sweep(char* const (&slots)[6], typename EP
     static_assert(NW % 2 == 0, "the fill offsets assume an even wave count");
     static_assert(!DMA || (NSLOT >= 2 && NSLOT <= 6 && KS % NSLOT == 0),
                   "direct loads need a static ring slot per slice");
+    static_assert(!MASK || (DMA && NSLOT <= KS), "masked sweeps run on the direct-load ring");
     constexpr int D = NS - 1;  // fill distance of the direct-load ring
+    // MASK: the sweep visits only S tiles t0 + b for the set bits b of
+    // `mask` (at least one, all below t1 - t0 <= 32), in increasing order
+    auto next_tile = [&](int t) -> int {
+        if constexpr (MASK) {
+            const uint32_t above = t - t0 >= 31 ? 0u : mask & ~((2u << (t - t0)) - 1u);
+            return above ? t0 + __builtin_ctz(above) : t1;
+        } else {
+            return t + 1;
+        }
+    };
+    const int tfirst = MASK ? t0 + __builtin_ctz(mask) : t0;
 
     char* const sL0 = slots[0];
     char* const sL1 = slots[1];
@@ -390,7 +412,7 @@ __device__ __forceinline__ void panel_sweep(char* const (&slots)[6], typename EP
     ctx.bn = PN_BN;
     ctx.nR = nR;
     ctx.nS = nS;
-    ctx.t = t0;
+    ctx.t = tfirst;
     ctx.edge = false;
     const int h = ctx.h, r32 = ctx.r32, r0 = ctx.r0;
 
@@ -456,7 +478,7 @@ __device__ __forceinline__ void panel_sweep(char* const (&slots)[6], typename EP
         // slices 0 .. D - 1 (the sweep has at least KS >= NSLOT > D slices)
 #pragma unroll
         for (int j = 0; j < D; ++j)
-            ring_fill<KPB, NW, NCH>(slots[j], B + (int64_t)t0 * PN_BN * KPB + j * 128, loff,
+            ring_fill<KPB, NW, NCH>(slots[j], B + (int64_t)tfirst * PN_BN * KPB + j * 128, loff,
                                     wave_u);
     } else {
         gload(0);
@@ -472,12 +494,13 @@ __device__ __forceinline__ void panel_sweep(char* const (&slots)[6], typename EP
                         : 127;
     };
     int sb_next[CB];
-    col_scales(t0, sb_next);
-    for (int t = t0; t < t1; ++t) {
+    col_scales(tfirst, sb_next);
+    for (int t = tfirst; t < t1;) {
+        const int tn = next_tile(t);
         int sb[CB];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) sb[cb] = sb_next[cb];
-        if (t + 1 < t1) col_scales(t + 1, sb_next);
+        if (tn < t1) col_scales(tn, sb_next);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             if constexpr (DMA) {
@@ -489,7 +512,9 @@ __device__ __forceinline__ void panel_sweep(char* const (&slots)[6], typename EP
                 // tile (never read), which keeps every wait count static.
                 wait_vmcnt_lgkm0<(D - 1) * NCH>();
                 bare_barrier();
-                const int t2 = min(t + (ks + D) / KS, t1 - 1), k2 = (ks + D) % KS;
+                const int t2 = MASK ? ((ks + D) / KS && tn < t1 ? tn : t)
+                                    : min(t + (ks + D) / KS, t1 - 1);
+                const int k2 = (ks + D) % KS;
                 ring_fill<KPB, NW, NCH>(slots[(ks + D) % NS], B + (int64_t)t2 * PN_BN * KPB + k2 * 128,
                                         loff, wave_u);
                 slice_mma<PREC, KS, RB, CB>(slots[ks % NS], ks, af, acc, sa, sb, h, r32);
@@ -512,6 +537,7 @@ __device__ __forceinline__ void panel_sweep(char* const (&slots)[6], typename EP
             for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[rb][cb][e] = 0.0f;
+        t = tn;
     }
     // the fills past the end land before the workgroup's LDS is released
     if constexpr (DMA) wait_vmcnt_lgkm0<0>();
@@ -563,17 +589,20 @@ __global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
 // ceil(tiles_n_j / chunk_tiles_j)), tiles_m = 128-row R panels, tiles_n =
 // 128-column S tiles; an item is one panel's sweep over chunk_tiles S tiles
 // (panel index fastest, so the items running together share their S chunk).
-// The K depth of each job selects the sweep; band entries carry the job.
+// In prefilter mode the items come from the work list instead, each with the
+// mask of the chunk's S tiles that survived the bounds; the sweep visits only
+// those.  The K depth of each job selects the sweep; band entries carry the
+// job.
 constexpr int BP_SLOT = 128 * 128;
 
 template <int KS>
 __device__ __forceinline__ void batch_panel_item(char* const (&slots)[6],
                                                  typename ThresholdEpiT<4, true>::Smem& esm,
                                                  const BatchJob& J, int panel, int t0, int t1,
-                                                 const ThresholdParams& ep) {
+                                                 uint32_t mask, const ThresholdParams& ep) {
     constexpr int NSLOT = KS == 8 ? 4 : KS == 9 ? 3 : KS == 10 ? 5 : 6;
-    panel_sweep<P_BF16, KS, 1, 4, 4, NSLOT, ThresholdEpiT<4, true>>(
-        slots, esm, J.A, J.B, J.info_r, J.info_s, J.nR, J.nS, panel, t0, t1, ep);
+    panel_sweep<P_BF16, KS, 1, 4, 4, NSLOT, ThresholdEpiT<4, true>, true>(
+        slots, esm, J.A, J.B, J.info_r, J.info_s, J.nR, J.nS, panel, t0, t1, ep, mask);
 }
 
 __global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restrict__ head,
@@ -587,39 +616,61 @@ __global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restric
     __shared__ __attribute__((aligned(16))) char sL5[BP_SLOT];
     __shared__ typename ThresholdEpiT<4, true>::Smem esm;
     __shared__ int64_t s_item;
-    __shared__ int s_job;
+    __shared__ int s_job, s_panel, s_t0;
+    __shared__ uint32_t s_mask;
     char* const slots[6] = {sL0, sL1, sL2, sL3, sL4, sL5};
-    const int64_t total = head->n_tiles;
+    // dense mode: every (panel, chunk) of every job; prefilter mode: the
+    // work list
+    const int64_t* work = head->work;
+    const int64_t total = work ? (int64_t)*head->n_work : head->n_tiles;
     const int n_jobs = head->n_jobs;
     const int tid = (int)__builtin_amdgcn_workitem_id_x();
     for (;;) {
         if (tid == 0) {
             const int64_t item = (int64_t)atomicAdd(bctr + B_ITEM, 1ull);
-            int job = 0;
+            int job = 0, panel = 0, t0 = 0;
+            uint32_t mask = 0;
             if (item < total) {
-                // last job whose first item is <= item
-                int lo = 0, hi = n_jobs - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (jobs[mid].tile_base <= item) lo = mid;
-                    else hi = mid - 1;
+                if (work) {
+                    const int64_t w = work[item];
+                    job = (int)(w >> 48);
+                    panel = (int)((w >> 24) & 0xFFFFFF);
+                    t0 = (int)(w & 0xFFFFFF);
+                    mask = head->work_mask[item];
+                } else {
+                    // last job whose first item is <= item
+                    int lo = 0, hi = n_jobs - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (jobs[mid].tile_base <= item) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    job = lo;
+                    const BatchJob& J = jobs[lo];
+                    const int64_t local = item - J.tile_base;
+                    panel = (int)(local % J.tiles_m);
+                    t0 = (int)(local / J.tiles_m) * J.chunk_tiles;
+                    const int n = min(J.chunk_tiles, J.tiles_n - t0);
+                    mask = n >= 32 ? ~0u : (1u << n) - 1u;
                 }
-                job = lo;
             }
             s_item = item;
             s_job = job;
+            s_panel = panel;
+            s_t0 = t0;
+            s_mask = mask;
         }
         // (also: every wave is done with the previous item's ring slots)
         __syncthreads();
         const int64_t item = s_item;
         const int job = __builtin_amdgcn_readfirstlane(s_job);
+        const int panel = __builtin_amdgcn_readfirstlane(s_panel);
+        const int t0 = __builtin_amdgcn_readfirstlane(s_t0);
+        const uint32_t mask = __builtin_amdgcn_readfirstlane(s_mask);
         __syncthreads();  // the shared slots are rewritten by the next iteration
         if (item >= total) break;
         const BatchJob& J = jobs[job];
         if (J.hdr[H_FLAGS] != 0) continue;  // bad input rows in this job
-        const int64_t local = item - J.tile_base;
-        const int panel = (int)(local % J.tiles_m);
-        const int t0 = (int)(local / J.tiles_m) * J.chunk_tiles;
         const int t1 = min(t0 + J.chunk_tiles, J.tiles_n);
         ThresholdParams ep;
         ep.lo = J.lo;
@@ -631,11 +682,13 @@ __global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restric
         ep.band_cap = head->band_cap;
         ep.band_ctr = bctr + B_BAND;
         ep.job = job;
+        ep.perm_r = J.perm_r;
+        ep.perm_s = J.perm_s;
         switch (J.Kp_bytes) {  // uniform
-            case 8 * 128: batch_panel_item<8>(slots, esm, J, panel, t0, t1, ep); break;
-            case 9 * 128: batch_panel_item<9>(slots, esm, J, panel, t0, t1, ep); break;
-            case 10 * 128: batch_panel_item<10>(slots, esm, J, panel, t0, t1, ep); break;
-            default: batch_panel_item<12>(slots, esm, J, panel, t0, t1, ep); break;
+            case 8 * 128: batch_panel_item<8>(slots, esm, J, panel, t0, t1, mask, ep); break;
+            case 9 * 128: batch_panel_item<9>(slots, esm, J, panel, t0, t1, mask, ep); break;
+            case 10 * 128: batch_panel_item<10>(slots, esm, J, panel, t0, t1, mask, ep); break;
+            default: batch_panel_item<12>(slots, esm, J, panel, t0, t1, mask, ep); break;
         }
     }
 }
@@ -776,6 +829,8 @@ hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs&
     ep.band_cap = a.band_cap;
     ep.band_ctr = a.hdr + H_BAND;
     ep.job = 0;
+    ep.perm_r = nullptr;
+    ep.perm_s = nullptr;
     const int ks = slices(prec, a.Kp);
     if (prec == P_BF16)
         return dispatch_panel<P_BF16, ThresholdEpi>(ks, two_waves, a.A, a.B, a.info_r, a.info_s,

@@ -476,7 +476,8 @@ __global__ __launch_bounds__(256) void pf_bounds(const BatchHead* __restrict__ h
                                                  const float* __restrict__ M1,
                                                  const float* __restrict__ M2, float eps,
                                                  int64_t* __restrict__ work,
-                                                 unsigned long long* __restrict__ n_work) {
+                                                 unsigned long long* __restrict__ n_work,
+                                                 uint8_t* __restrict__ keep_flags) {
     const int lane = threadIdx.x & 63;
     const int64_t total = head->n_tiles;
     const int n_jobs = head->n_jobs;
@@ -531,6 +532,10 @@ __global__ __launch_bounds__(256) void pf_bounds(const BatchHead* __restrict__ h
                 packed = ((int64_t)lo << 48) | ((int64_t)tm << 24) | (int64_t)tn;
             }
         }
+        if (keep_flags) {  // per-tile flags for the panel form's chunks
+            if (item < total) keep_flags[item] = keep ? 1 : 0;
+            continue;
+        }
         const uint64_t m = __ballot(keep);
         if (m) {
             const int leader = __ffsll((unsigned long long)m) - 1;
@@ -540,6 +545,64 @@ __global__ __launch_bounds__(256) void pf_bounds(const BatchHead* __restrict__ h
             const uint32_t bhi = __shfl((uint32_t)(b0 >> 32), leader, 64);
             const unsigned long long bb = ((unsigned long long)bhi << 32) | blo;
             if (keep) work[bb + lanes_below(m)] = packed;
+        }
+    }
+}
+
+// One lane per (job, panel, S chunk) item: the chunk's kept-tile mask from
+// the per-tile flags, and a wave-compacted append of the items that keep any.
+__global__ __launch_bounds__(256) void pf_chunks(const BatchHead* __restrict__ head,
+                                                 const BatchJob* __restrict__ jobs,
+                                                 const uint8_t* __restrict__ keep,
+                                                 int64_t* __restrict__ work,
+                                                 uint32_t* __restrict__ work_mask,
+                                                 unsigned long long* __restrict__ n_work,
+                                                 unsigned long long* __restrict__ n_kept) {
+    const int lane = threadIdx.x & 63;
+    const int64_t total = head->n_chunks;
+    const int n_jobs = head->n_jobs;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < total;
+         base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t item = base + lane;
+        uint32_t mask = 0;
+        int64_t packed = 0;
+        if (item < total) {
+            int lo = 0, hi = n_jobs - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (jobs[mid].chunk_base <= item) lo = mid;
+                else hi = mid - 1;
+            }
+            const BatchJob& J = jobs[lo];
+            const int ct = J.chunk_tiles;
+            const int nch = (J.tiles_n + ct - 1) / ct;
+            const int64_t local = item - J.chunk_base;
+            const int tm = (int)(local / nch);
+            const int tn0 = (int)(local % nch) * ct;
+            const int n = min(ct, J.tiles_n - tn0);
+            const uint8_t* k = keep + J.tile_base + (int64_t)tm * J.tiles_n + tn0;
+            for (int b = 0; b < n; ++b) mask |= (uint32_t)(k[b] != 0) << b;
+            packed = ((int64_t)lo << 48) | ((int64_t)tm << 24) | (int64_t)tn0;
+        }
+        const uint64_t m = __ballot(mask != 0);
+        int kept = __popc(mask);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) kept += __shfl_xor(kept, o, 64);
+        if (m) {
+            const int leader = __ffsll((unsigned long long)m) - 1;
+            unsigned long long b0 = 0;
+            if (lane == leader) {
+                b0 = atomicAdd(n_work, (unsigned long long)__popcll(m));
+                atomicAdd(n_kept, (unsigned long long)kept);
+            }
+            const uint32_t blo = __shfl((uint32_t)b0, leader, 64);
+            const uint32_t bhi = __shfl((uint32_t)(b0 >> 32), leader, 64);
+            const unsigned long long bb = ((unsigned long long)bhi << 32) | blo;
+            if (mask) {
+                const unsigned long long at = bb + lanes_below(m);
+                work[at] = packed;
+                work_mask[at] = mask;
+            }
         }
     }
 }
@@ -609,7 +672,8 @@ hipError_t launch_pf_tiles(const BatchHead* head, const PrepSeg* segs, const Bat
                            int64_t n_rows, const float* U, const int32_t* perm, float* C,
                            float* rho, float* cnorm, float* alpha, uint16_t* Up, uint16_t* Dir,
                            float* M1, float* M2, int64_t n_side, float eps, int64_t* work,
-                           unsigned long long* n_work, int64_t n_tiles, hipStream_t st) {
+                           unsigned long long* n_work, int64_t n_tiles, uint8_t* keep,
+                           hipStream_t st) {
     if (n_rows <= 0) return hipSuccess;
     const int64_t tiles = n_rows / 128;
     hipLaunchKernelGGL(pf_tile_stats, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, head,
@@ -621,7 +685,17 @@ hipError_t launch_pf_tiles(const BatchHead* head, const PrepSeg* segs, const Bat
     }
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n_tiles + 255) / 256, 8192));
     hipLaunchKernelGGL(pf_bounds, dim3((unsigned)blocks), dim3(256), 0, st, head, jobs, C, rho,
-                       cnorm, alpha, M1, M2, eps, work, n_work);
+                       cnorm, alpha, M1, M2, eps, work, n_work, keep);
+    return hipGetLastError();
+}
+
+hipError_t launch_pf_chunks(const BatchHead* head, const BatchJob* jobs, const uint8_t* keep,
+                            int64_t* work, uint32_t* work_mask, unsigned long long* n_work,
+                            unsigned long long* n_kept, int64_t n_chunks, hipStream_t st) {
+    if (n_chunks <= 0) return hipSuccess;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n_chunks + 255) / 256, 8192));
+    hipLaunchKernelGGL(pf_chunks, dim3((unsigned)blocks), dim3(256), 0, st, head, jobs, keep, work,
+                       work_mask, n_work, n_kept);
     return hipGetLastError();
 }
 

@@ -31,11 +31,20 @@ hipError_t launch_pf_keys(const BatchHead* head, const PrepSeg* segs, int64_t n_
 hipError_t launch_pf_sort(const BatchHead* head, const PrepSeg* segs, int n_segs, int64_t n_rows,
                           const int32_t* key, int32_t* perm_a, int32_t* perm_b, int32_t* hist,
                           int32_t* offs, hipStream_t st);
-// 128-row tile statistics of the ordered rows and the surviving tile pairs
+// 128-row tile statistics of the ordered rows and the surviving tile pairs:
+// a compacted (job, tm, tn) work list, or with `keep` one flag per tile pair
+// (flat tile order) for launch_pf_chunks
 hipError_t launch_pf_tiles(const BatchHead* head, const PrepSeg* segs, const BatchJob* jobs,
                            int64_t n_rows, const float* U, const int32_t* perm, float* C,
                            float* rho, float* cnorm, float* alpha, uint16_t* Up, uint16_t* Dir,
                            float* M1, float* M2, int64_t n_side, float eps, int64_t* work,
-                           unsigned long long* n_work, int64_t n_tiles, hipStream_t st);
+                           unsigned long long* n_work, int64_t n_tiles, uint8_t* keep,
+                           hipStream_t st);
+// panel form: the (job, panel, S chunk) items with at least one kept tile,
+// packed job << 48 | tm << 24 | first tn, each with its mask of kept tiles;
+// n_kept counts the kept tile pairs
+hipError_t launch_pf_chunks(const BatchHead* head, const BatchJob* jobs, const uint8_t* keep,
+                            int64_t* work, uint32_t* work_mask, unsigned long long* n_work,
+                            unsigned long long* n_kept, int64_t n_chunks, hipStream_t st);
 
 }  // namespace ej

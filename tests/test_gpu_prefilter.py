@@ -27,10 +27,12 @@ def setup_module(module):
     E = ejoin
 
 
-D = 96
+# 96-d rows run on 128 x 128 tiles; 640-d rows on the batch panel form
+# (128-row panels sweeping only the kept tiles of each 16-tile S chunk)
+DIMS = {96: 3, 640: 19}
 
 
-def _jobs(seed=3):
+def _jobs(D, seed=3):
     """Clustered jobs of uneven size, thresholds across and above the
     within-cluster similarity, a self-join and an empty job."""
     cent = G.centres(D, 24, seed)
@@ -56,20 +58,23 @@ def _sets(res):
     return [set(zip(r.r.cpu().tolist(), r.s.cpu().tolist())) for r in res]
 
 
-def _net(seed):
+def _net(D, seed):
     flat = G.mlp_init(D, seed)
     return E.Mlp(D, torch.from_numpy(flat))
 
 
-@pytest.fixture(scope="module")
-def setup():
-    host, jobs = _jobs()
-    plain, _ = E.batch(jobs, prec="bf16")
-    return host, jobs, plain
+@pytest.fixture(scope="module", params=sorted(DIMS))
+def setup(request):
+    D = request.param
+    host, jobs = _jobs(D)
+    plain, st = E.batch(jobs, prec="bf16")
+    if DIMS[D] == 19:
+        assert st["tile"] == 19  # also the plain batch's default at this depth
+    return host, jobs, plain, D
 
 
 def test_plain_batch_matches_oracle_on_samples(setup):
-    host, jobs, plain = setup
+    host, jobs, plain, D = setup
     sets = _sets(plain)
     for (R, S, th), got in zip(host, sets):
         if R.shape[0] == 0:
@@ -84,9 +89,11 @@ def test_plain_batch_matches_oracle_on_samples(setup):
 def test_prefilter_keeping_every_tile_is_exact(setup):
     """eps = 4 keeps every tile pair: the reordered pass must give exactly
     the plain result (ordering, work list and back-mapping are lossless)."""
-    host, jobs, plain = setup
-    net = _net(5)
+    host, jobs, plain, D = setup
+    net = _net(D, 5)
     res, st = E.batch(jobs, prec="bf16", prefilter=net, eps=4.0)
+    assert st["tile"] == DIMS[D]
+    assert st["tiles_kept"] == st["tiles_total"]
     assert _sets(res) == _sets(plain)
 
 
@@ -105,10 +112,10 @@ def _train(net, jobs, plain, steps=200):
 
 
 def test_trained_prefilter_is_a_subset_with_high_recall(setup):
-    host, jobs, plain = setup
+    host, jobs, plain, D = setup
     want = _sets(plain)
     total = sum(len(w) for w in want)
-    net = _net(5)
+    net = _net(D, 5)
     losses = _train(net, jobs, plain)
     assert np.mean(losses[-20:]) < 0.5 * np.mean(losses[:5])
     res, st = E.batch(jobs, prec="bf16", prefilter=net, eps=0.1)
@@ -121,8 +128,15 @@ def test_trained_prefilter_is_a_subset_with_high_recall(setup):
     assert recall >= 0.95
     assert kept < 1.0
 
+    if DIMS[D] == 19:
+        # the 128 x 128 tile form visits exactly the same tile pairs and so
+        # returns the same set
+        res3, st3 = E.batch(jobs, prec="bf16", tile=3, prefilter=net, eps=0.1)
+        assert st3["tiles_kept"] == st["tiles_kept"]
+        assert _sets(res3) == got
+
     # the untrained network (same initial weights) at the same margin
-    raw = _net(5)
+    raw = _net(D, 5)
     res0, st0 = E.batch(jobs, prec="bf16", prefilter=raw, eps=0.1)
     got0 = _sets(res0)
     for g, w in zip(got0, want):
@@ -135,8 +149,8 @@ def test_trained_prefilter_is_a_subset_with_high_recall(setup):
 
 
 def test_prefilter_rejects_bad_options(setup):
-    host, jobs, plain = setup
-    net = _net(5)
+    host, jobs, plain, D = setup
+    net = _net(D, 5)
     with pytest.raises(E.EjoinError):
         E.batch(jobs, prec="fp32", prefilter=net, eps=0.1)
     with pytest.raises(E.EjoinError):
