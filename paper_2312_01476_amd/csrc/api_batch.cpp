@@ -440,7 +440,7 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
         return e;
     if ((e = rec(1)) != hipSuccess) return e;
     const int tg = (int)std::max<int64_t>(1, std::min<int64_t>(tile_grid, bp.n_tiles));
-    if ((e = launch_batch_tile(bp.tile, head, jobs, bctr, tg, st)) != hipSuccess) return e;
+    if ((e = launch_batch_tile(bp.tile, head, jobs, bctr, tg, st, true)) != hipSuccess) return e;
     if ((e = rec(2)) != hipSuccess) return e;
     const int rg =
         (int)std::max<int64_t>(1, std::min<int64_t>(kRescoreGrid, (bp.band_cap + 255) / 256));

@@ -159,7 +159,7 @@ int batch_occupancy(int tile_id) {
 }
 
 hipError_t launch_batch_tile(int tile_id, const BatchHead* head, const BatchJob* jobs,
-                             unsigned long long* bctr, int grid, hipStream_t st) {
+                             unsigned long long* bctr, int grid, hipStream_t st, bool worklist) {
     switch (tile_id) {
         case 1: return run_batch<P_FP32, 128, 128, 2, 2>(head, jobs, bctr, grid, st);
         case 2: return run_batch<P_FP32, 64, 64, 2, 2>(head, jobs, bctr, grid, st);
@@ -173,7 +173,7 @@ hipError_t launch_batch_tile(int tile_id, const BatchHead* head, const BatchJob*
         case 16: return run_batch<P_BF16, 256, 256, 2, 2, true>(head, jobs, bctr, grid, st);
         case 17: return run_batch<P_FP8, 256, 256, 2, 2, true>(head, jobs, bctr, grid, st);
         case 18: return run_batch<P_FP32, 256, 256, 2, 2, true>(head, jobs, bctr, grid, st);
-        case 19: return launch_batch_panel(head, jobs, bctr, grid, st);
+        case 19: return launch_batch_panel(head, jobs, bctr, grid, worklist, st);
         default: return hipErrorInvalidValue;
     }
 }

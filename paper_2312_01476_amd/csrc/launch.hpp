@@ -118,13 +118,15 @@ bool batch_has_tile(int tile_id);  // the tile has a persistent batch form
 bool batch_panel_depth(int kpb);
 int batch_panel_occupancy();
 hipError_t launch_batch_panel(const BatchHead* head, const BatchJob* jobs,
-                              unsigned long long* bctr, int grid, hipStream_t st);
+                              unsigned long long* bctr, int grid, bool worklist, hipStream_t st);
 int batch_occupancy(int tile_id);  // resident workgroups per CU, 0: no batch form
 hipError_t launch_batch_zero(const BatchHead* head, unsigned long long* bctr, hipStream_t st);
 hipError_t launch_batch_prep(int prec, const BatchHead* head, const PrepSeg* segs, int grid,
                              bool ordered, hipStream_t st);
+// worklist: the items come from the prefilter's work list (head->work)
 hipError_t launch_batch_tile(int tile_id, const BatchHead* head, const BatchJob* jobs,
-                             unsigned long long* bctr, int grid, hipStream_t st);
+                             unsigned long long* bctr, int grid, hipStream_t st,
+                             bool worklist = false);
 hipError_t launch_batch_rescore(const BatchHead* head, const BatchJob* jobs,
                                 const unsigned long long* bctr, int grid, hipStream_t st);
 hipError_t launch_batch_counts(const BatchHead* head, const BatchJob* jobs,

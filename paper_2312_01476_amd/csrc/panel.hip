@@ -75,13 +75,13 @@ struct ThresholdParams {
     int64_t band_cap;
     unsigned long long* band_ctr;  // band entries found
     int job;
-    // with TAG (batch): prepared row -> caller's row maps of the prefilter
-    // order, or null
+    // with PERM (prefiltered batch): prepared row -> caller's row maps of
+    // the prefilter order
     const int32_t* perm_r;
     const int32_t* perm_s;
 };
 
-template <int NW, bool TAG>
+template <int NW, bool TAG, bool PERM = false>
 struct ThresholdEpiT {
     typedef ThresholdParams Params;
     typedef typename BandEntryT<TAG>::type BE;
@@ -153,8 +153,8 @@ struct ThresholdEpiT {
                         const uint64_t mhi = __ballot(in_hi);
                         const uint64_t mb = ml[k] & ~mhi;
                         int ri = gi, si = gj;
-                        if constexpr (TAG)
-                            if (in_lo && p.perm_r) {
+                        if constexpr (PERM)
+                            if (in_lo) {
                                 ri = p.perm_r[gi];
                                 si = p.perm_s[gj];
                             }
@@ -192,7 +192,7 @@ struct ThresholdEpiT {
 // ---------------------------------------------------------------------------
 // the single-join form (untagged band entries)
 template <int NW>
-using ThresholdEpi = ThresholdEpiT<NW, false>;
+using ThresholdEpi = ThresholdEpiT<NW, false, false>;
 
 struct CandParams {
     const unsigned long long* hdr;  // floor as float bits in H_TOPK_F
@@ -595,16 +595,19 @@ __global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
 // job.
 constexpr int BP_SLOT = 128 * 128;
 
-template <int KS>
+template <int KS, bool WL>
 __device__ __forceinline__ void batch_panel_item(char* const (&slots)[6],
-                                                 typename ThresholdEpiT<4, true>::Smem& esm,
+                                                 typename ThresholdEpiT<4, true, WL>::Smem& esm,
                                                  const BatchJob& J, int panel, int t0, int t1,
                                                  uint32_t mask, const ThresholdParams& ep) {
     constexpr int NSLOT = KS == 8 ? 4 : KS == 9 ? 3 : KS == 10 ? 5 : 6;
-    panel_sweep<P_BF16, KS, 1, 4, 4, NSLOT, ThresholdEpiT<4, true>, true>(
+    panel_sweep<P_BF16, KS, 1, 4, 4, NSLOT, ThresholdEpiT<4, true, WL>, WL>(
         slots, esm, J.A, J.B, J.info_r, J.info_s, J.nR, J.nS, panel, t0, t1, ep, mask);
 }
 
+// WL: prefilter mode (masked work-list items, rows in the prefilter order);
+// else every (panel, chunk) item in full.
+template <bool WL>
 __global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restrict__ head,
                                                       const BatchJob* __restrict__ jobs,
                                                       unsigned long long* __restrict__ bctr) {
@@ -614,15 +617,13 @@ __global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restric
     __shared__ __attribute__((aligned(16))) char sL3[BP_SLOT];
     __shared__ __attribute__((aligned(16))) char sL4[BP_SLOT];
     __shared__ __attribute__((aligned(16))) char sL5[BP_SLOT];
-    __shared__ typename ThresholdEpiT<4, true>::Smem esm;
+    __shared__ typename ThresholdEpiT<4, true, WL>::Smem esm;
     __shared__ int64_t s_item;
     __shared__ int s_job, s_panel, s_t0;
     __shared__ uint32_t s_mask;
     char* const slots[6] = {sL0, sL1, sL2, sL3, sL4, sL5};
-    // dense mode: every (panel, chunk) of every job; prefilter mode: the
-    // work list
     const int64_t* work = head->work;
-    const int64_t total = work ? (int64_t)*head->n_work : head->n_tiles;
+    const int64_t total = WL ? (int64_t)*head->n_work : head->n_tiles;
     const int n_jobs = head->n_jobs;
     const int tid = (int)__builtin_amdgcn_workitem_id_x();
     for (;;) {
@@ -631,7 +632,7 @@ __global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restric
             int job = 0, panel = 0, t0 = 0;
             uint32_t mask = 0;
             if (item < total) {
-                if (work) {
+                if constexpr (WL) {
                     const int64_t w = work[item];
                     job = (int)(w >> 48);
                     panel = (int)((w >> 24) & 0xFFFFFF);
@@ -650,8 +651,6 @@ __global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restric
                     const int64_t local = item - J.tile_base;
                     panel = (int)(local % J.tiles_m);
                     t0 = (int)(local / J.tiles_m) * J.chunk_tiles;
-                    const int n = min(J.chunk_tiles, J.tiles_n - t0);
-                    mask = n >= 32 ? ~0u : (1u << n) - 1u;
                 }
             }
             s_item = item;
@@ -666,7 +665,7 @@ __global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restric
         const int job = __builtin_amdgcn_readfirstlane(s_job);
         const int panel = __builtin_amdgcn_readfirstlane(s_panel);
         const int t0 = __builtin_amdgcn_readfirstlane(s_t0);
-        const uint32_t mask = __builtin_amdgcn_readfirstlane(s_mask);
+        const uint32_t mask = WL ? __builtin_amdgcn_readfirstlane(s_mask) : 0u;
         __syncthreads();  // the shared slots are rewritten by the next iteration
         if (item >= total) break;
         const BatchJob& J = jobs[job];
@@ -685,10 +684,10 @@ __global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restric
         ep.perm_r = J.perm_r;
         ep.perm_s = J.perm_s;
         switch (J.Kp_bytes) {  // uniform
-            case 8 * 128: batch_panel_item<8>(slots, esm, J, panel, t0, t1, mask, ep); break;
-            case 9 * 128: batch_panel_item<9>(slots, esm, J, panel, t0, t1, mask, ep); break;
-            case 10 * 128: batch_panel_item<10>(slots, esm, J, panel, t0, t1, mask, ep); break;
-            default: batch_panel_item<12>(slots, esm, J, panel, t0, t1, mask, ep); break;
+            case 8 * 128: batch_panel_item<8, WL>(slots, esm, J, panel, t0, t1, mask, ep); break;
+            case 9 * 128: batch_panel_item<9, WL>(slots, esm, J, panel, t0, t1, mask, ep); break;
+            case 10 * 128: batch_panel_item<10, WL>(slots, esm, J, panel, t0, t1, mask, ep); break;
+            default: batch_panel_item<12, WL>(slots, esm, J, panel, t0, t1, mask, ep); break;
         }
     }
 }
@@ -700,14 +699,22 @@ bool batch_panel_depth(int kpb) {
 
 int batch_panel_occupancy() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_panel, 256, 0) != hipSuccess)
+    int m = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_panel<false>, 256, 0) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, batch_panel<true>, 256, 0) != hipSuccess)
         return 0;
-    return n;
+    return n < m ? n : m;
 }
 
 hipError_t launch_batch_panel(const BatchHead* head, const BatchJob* jobs,
-                              unsigned long long* bctr, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(batch_panel, dim3((unsigned)grid), dim3(256), 0, st, head, jobs, bctr);
+                              unsigned long long* bctr, int grid, bool worklist, hipStream_t st) {
+    if (worklist)
+        hipLaunchKernelGGL(batch_panel<true>, dim3((unsigned)grid), dim3(256), 0, st, head, jobs,
+                           bctr);
+    else
+        hipLaunchKernelGGL(batch_panel<false>, dim3((unsigned)grid), dim3(256), 0, st, head, jobs,
+                           bctr);
     return hipGetLastError();
 }
 
