@@ -66,7 +66,7 @@ struct BatchPlan {
     size_t off_hb = 0, off_z = 0, off_u = 0, off_key = 0, off_pa = 0, off_pb = 0, off_hist = 0,
            off_offs = 0, off_c = 0, off_rho = 0, off_cn = 0, off_alpha = 0, off_work = 0,
            off_ub = 0, off_aidx = 0, off_af = 0, off_ab = 0, off_lab = 0, off_up = 0,
-           off_dir = 0, off_m1 = 0, off_m2 = 0, off_keep = 0, off_wmask = 0;
+           off_dir = 0, off_m1 = 0, off_m2 = 0, off_keep = 0, off_wmask = 0, off_abits = 0;
     int64_t n_side = 0, n_chunks = 0;
     int n_anchor = 0;
     std::vector<int64_t> anchor_idx;  // flat rows whose codes are the anchors
@@ -290,6 +290,8 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         bp.off_af = take((size_t)std::max(1, bp.n_anchor) * MLP_OUT * 4);
         bp.off_ab = take((size_t)((bp.n_anchor + 127) / 128 * 128 + 128) * MLP_OUT * 2);
         bp.off_lab = take((size_t)std::max(1, bp.n_anchor) * 4);
+        bp.off_abits = take((size_t)std::max(1, bp.n_anchor) *
+                            (size_t)pf_anchor_words(std::max(1, bp.n_anchor)) * 8);
         if (ws) {
             SplitMix64 rng{kAnchorSeed};
             bp.anchor_idx.resize(bp.n_anchor);
@@ -414,7 +416,8 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
                                 (const uint16_t*)(ws + bp.off_ub),
                                 (const int64_t*)(ws + bp.off_aidx), bp.n_anchor, kAnchorTau,
                                 (float*)(ws + bp.off_af), (uint16_t*)(ws + bp.off_ab),
-                                (int32_t*)(ws + bp.off_lab), (int32_t*)(ws + bp.off_key), st)) !=
+                                (uint64_t*)(ws + bp.off_abits), (int32_t*)(ws + bp.off_lab),
+                                (int32_t*)(ws + bp.off_key), st)) !=
             hipSuccess)
             return e;
     }

@@ -142,35 +142,65 @@ __global__ void pf_anchor_gather(const float* __restrict__ U, const int64_t* __r
 
 // leader labels of the anchors, in anchor order: an anchor joins the first
 // leader whose code has cosine >= tau with it, else becomes a leader; the
-// label is the leader's rank.  One workgroup.
-__global__ __launch_bounds__(256) void pf_leaders(const float* __restrict__ Af, int K, float tau,
-                                                  int32_t* __restrict__ label) {
-    __shared__ int s_lead[PF_MAX_ANCHORS];
-    __shared__ int s_n, s_hit;
-    if (threadIdx.x == 0) s_n = 0;
-    __syncthreads();
-    for (int k = 0; k < K; ++k) {
-        if (threadIdx.x == 0) s_hit = 0x7fffffff;
-        __syncthreads();
-        const int nl = s_n;
+// label is the leader's rank.  Two steps: every anchor pair's test in
+// parallel (a bit matrix: bit b of word w of row k is set when anchor
+// 64 w + b passes with anchor k), then one wave walks the anchors in order
+// holding the leader set as a bit mask (lane w: anchors 64 w .. 64 w + 63):
+// the first leader an anchor passes with is the lowest set bit of its row
+// masked by the leader set, since leaders are taken in anchor order.
+__global__ __launch_bounds__(256) void pf_anchor_bits(const float* __restrict__ Af, int K, int W,
+                                                      float tau, uint64_t* __restrict__ bits) {
+    const int lane = threadIdx.x & 63;
+    const int64_t word = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // k * W + w
+    if (word >= (int64_t)K * W) return;  // whole waves
+    const int k = (int)(word / W), j = (int)(word % W) * 64 + lane;
+    bool pass = false;
+    if (j < K) {
         const float* a = Af + (int64_t)k * MLP_OUT;
-        for (int t = threadIdx.x; t < nl; t += blockDim.x) {
-            const float* b = Af + (int64_t)s_lead[t] * MLP_OUT;
-            float d = 0.0f;
-            for (int o = 0; o < MLP_OUT; ++o) d = fmaf(a[o], b[o], d);
-            if (d >= tau) atomicMin(&s_hit, t);
-        }
+        const float* b = Af + (int64_t)j * MLP_OUT;
+        float d = 0.0f;
+        for (int o = 0; o < MLP_OUT; ++o) d = fmaf(a[o], b[o], d);
+        pass = d >= tau;
+    }
+    const uint64_t m = __ballot(pass);
+    if (lane == 0) bits[word] = m;
+}
+
+__global__ __launch_bounds__(256) void pf_leaders(const uint64_t* __restrict__ bits, int K, int W,
+                                                  int32_t* __restrict__ label) {
+    constexpr int CH = 64;  // anchor rows staged in LDS at a time
+    __shared__ uint64_t s_rows[CH * 64];
+    __shared__ int s_rank[PF_MAX_ANCHORS];
+    const int tid = threadIdx.x, lane = tid & 63;
+    uint64_t lead = 0;  // wave 0, lane w: leader bits of anchors 64 w .. 64 w + 63
+    int n = 0;          // leaders so far (wave-uniform)
+    for (int k0 = 0; k0 < K; k0 += CH) {
+        const int rows = min(CH, K - k0);
+        __syncthreads();  // the previous chunk has been walked
+        for (int i = tid; i < rows * W; i += blockDim.x) s_rows[i] = bits[(int64_t)k0 * W + i];
         __syncthreads();
-        if (threadIdx.x == 0) {
-            if (s_hit == 0x7fffffff) {
-                s_lead[s_n] = k;
-                label[k] = s_n;
-                s_n = s_n + 1;
-            } else {
-                label[k] = s_hit;
+        if (tid < 64) {
+            for (int r = 0; r < rows; ++r) {
+                const int k = k0 + r;
+                const uint64_t h = lane < W ? (s_rows[r * W + lane] & lead) : 0ull;
+                const uint64_t any = __ballot(h != 0ull);
+                if (any == 0ull) {
+                    if (lane == (k >> 6)) lead |= 1ull << (k & 63);
+                    if (lane == 0) {
+                        s_rank[k] = n;
+                        label[k] = n;
+                    }
+                    ++n;
+                } else {
+                    const int w = __ffsll((unsigned long long)any) - 1;
+                    const uint32_t lo = __shfl((uint32_t)h, w, 64);
+                    const uint32_t hi = __shfl((uint32_t)(h >> 32), w, 64);
+                    const uint64_t hw = ((uint64_t)hi << 32) | lo;
+                    const int j = w * 64 + __ffsll((unsigned long long)hw) - 1;
+                    if (lane == 0) label[k] = s_rank[j];
+                }
             }
         }
-        __syncthreads();
     }
 }
 
@@ -633,14 +663,17 @@ hipError_t launch_pf_codes(const BatchHead* head, const PrepSeg* segs, int64_t n
 
 hipError_t launch_pf_keys(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
                           const float* U, const uint16_t* Ub, const int64_t* anchor_idx, int K,
-                          float tau, float* Af, uint16_t* Ab, int32_t* label, int32_t* key,
-                          hipStream_t st) {
+                          float tau, float* Af, uint16_t* Ab, uint64_t* abits, int32_t* label,
+                          int32_t* key, hipStream_t st) {
     if (n_rows <= 0 || K <= 0) return hipSuccess;
     if (K > PF_MAX_ANCHORS) return hipErrorInvalidValue;
     const int Kpad = (K + 127) / 128 * 128;
     hipLaunchKernelGGL(pf_anchor_gather, dim3((unsigned)Kpad), dim3(64), 0, st, U, anchor_idx, K,
                        Kpad, Af, Ab);
-    hipLaunchKernelGGL(pf_leaders, dim3(1), dim3(256), 0, st, Af, K, tau, label);
+    const int W = pf_anchor_words(K);
+    hipLaunchKernelGGL(pf_anchor_bits, dim3((unsigned)(((int64_t)K * W + 3) / 4)), dim3(256), 0, st,
+                       Af, K, W, tau, abits);
+    hipLaunchKernelGGL(pf_leaders, dim3(1), dim3(256), 0, st, abits, K, W, label);
     const int64_t tiles = n_rows / 128;
     const int64_t gx = std::min<int64_t>(tiles, 65536), gy = (tiles + gx - 1) / gx;
     hipLaunchKernelGGL(pf_assign, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, head, segs,

@@ -22,10 +22,13 @@ hipError_t launch_pf_codes(const BatchHead* head, const PrepSeg* segs, int64_t n
                            hipStream_t st);
 // ordering keys: K anchors = codes of the flat rows anchor_idx, leader
 // labels at cosine tau, key = label of the nearest anchor
+// 64-bit words per anchor row of the anchors' pair-test bit matrix (abits:
+// K x pf_anchor_words(K) words)
+inline int pf_anchor_words(int K) { return (K + 63) / 64; }
 hipError_t launch_pf_keys(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
                           const float* U, const uint16_t* Ub, const int64_t* anchor_idx, int K,
-                          float tau, float* Af, uint16_t* Ab, int32_t* label, int32_t* key,
-                          hipStream_t st);
+                          float tau, float* Af, uint16_t* Ab, uint64_t* abits, int32_t* label,
+                          int32_t* key, hipStream_t st);
 // stable order of every relation's rows by key: perm_a[row_base + i] is the
 // local row at ordered position i
 hipError_t launch_pf_sort(const BatchHead* head, const PrepSeg* segs, int n_segs, int64_t n_rows,

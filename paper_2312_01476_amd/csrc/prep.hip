@@ -126,31 +126,38 @@ __device__ __forceinline__ float prep_one_row(const float* __restrict__ X, int64
 // Register-resident form of prep_one_row for rows of at most 1024 elements:
 // the row is read from memory once (lane l holds elements l + 64 j) and every
 // pass works on the registers.  Same arithmetic in the same order as
-// prep_one_row, so both give identical bits.
+// prep_one_row, so both give identical bits.  The load is separate so that a
+// wave can fetch its next row while it finishes the current one.
 constexpr int kRegMax = 1024;
+constexpr int kRegNV = kRegMax / 64;
 
-template <int PREC>
-__device__ __forceinline__ float prep_row_reg(const float* __restrict__ X, int64_t rows, int dim,
-                                              int64_t ld, void* __restrict__ Xq, int Kp,
-                                              RowInfo* __restrict__ info,
-                                              unsigned long long* __restrict__ hdr, int64_t row,
-                                              int64_t src, int lane) {
-    constexpr int NV = kRegMax / 64;
-    float inv = 0.0f, qscale = 1.0f, enorm = 0.0f;
-    uint32_t flags = 0;
+__device__ __forceinline__ void load_row_reg(const float* __restrict__ X, int64_t rows, int dim,
+                                             int64_t ld, int64_t src, int lane,
+                                             float (&xv)[kRegNV]) {
     const float* x = X + src * ld;
     const bool real = src < rows;
-    float xv[NV];
+#pragma unroll
+    for (int j = 0; j < kRegNV; ++j) {
+        const int k = lane + 64 * j;
+        xv[j] = (real && k < dim) ? x[k] : 0.0f;
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ float prep_row_regs(const float (&xv)[kRegNV], bool real, int dim,
+                                               void* __restrict__ Xq, int Kp,
+                                               RowInfo* __restrict__ info,
+                                               unsigned long long* __restrict__ hdr, int64_t row,
+                                               int lane) {
+    constexpr int NV = kRegNV;
+    float inv = 0.0f, qscale = 1.0f, enorm = 0.0f;
+    uint32_t flags = 0;
     float amax = 0.0f;
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-        const int k = lane + 64 * j;
-        float v = 0.0f;
-        if (real && k < dim) v = x[k];
-        xv[j] = v;
-        bad |= !isfinite(v);
-        amax = fmaxf(amax, fabsf(v));
+        bad |= !isfinite(xv[j]);
+        amax = fmaxf(amax, fabsf(xv[j]));
     }
     if (real) {
         bad = __any(bad);
@@ -232,6 +239,17 @@ __device__ __forceinline__ float prep_row_reg(const float* __restrict__ X, int64
 }
 
 template <int PREC>
+__device__ __forceinline__ float prep_row_reg(const float* __restrict__ X, int64_t rows, int dim,
+                                              int64_t ld, void* __restrict__ Xq, int Kp,
+                                              RowInfo* __restrict__ info,
+                                              unsigned long long* __restrict__ hdr, int64_t row,
+                                              int64_t src, int lane) {
+    float xv[kRegNV];
+    load_row_reg(X, rows, dim, ld, src, lane, xv);
+    return prep_row_regs<PREC>(xv, src < rows, dim, Xq, Kp, info, hdr, row, lane);
+}
+
+template <int PREC>
 __device__ __forceinline__ float prep_row(const float* __restrict__ X, int64_t rows, int dim,
                                           int64_t ld, void* __restrict__ Xq, int Kp,
                                           RowInfo* __restrict__ info,
@@ -252,10 +270,26 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
                                                  int enorm_slot) {
     const int lane = threadIdx.x & 63;
     float wave_emax = 0.0f;  // largest error norm seen by this wave
-    for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < rows_pad;
-         row += (int64_t)gridDim.x * 4)
-        wave_emax = fmaxf(wave_emax,
-                          prep_row<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr, row, row, lane));
+    const int64_t first = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    if (Kp <= kRegMax) {
+        // rows in registers; the wave's next row is loaded before the
+        // current one is reduced and written
+        float xa[kRegNV], xb[kRegNV];
+        if (first < rows_pad) load_row_reg(X, rows, dim, ld, first, lane, xa);
+        for (int64_t row = first; row < rows_pad; row += stride) {
+            const int64_t next = row + stride;
+            if (next < rows_pad) load_row_reg(X, rows, dim, ld, next, lane, xb);
+            wave_emax = fmaxf(wave_emax, prep_row_regs<PREC>(xa, row < rows, dim, Xq, Kp, info,
+                                                             hdr, row, lane));
+#pragma unroll
+            for (int j = 0; j < kRegNV; ++j) xa[j] = xb[j];
+        }
+    } else {
+        for (int64_t row = first; row < rows_pad; row += stride)
+            wave_emax = fmaxf(wave_emax, prep_one_row<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr,
+                                                            row, row, lane));
+    }
     // one atomic per workgroup for the maximum error norm
     __shared__ float s_emax[4];
     if (lane == 0) s_emax[threadIdx.x >> 6] = wave_emax;
@@ -277,19 +311,54 @@ __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ 
     const int lane = threadIdx.x & 63;
     const int64_t n = head->n_rows;
     const int nseg = head->n_segs;
-    for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n;
-         row += (int64_t)gridDim.x * 4) {
+    // segment of a flat row (the last one starting at or before it)
+    auto seg_of = [&](int64_t row) {
         int lo = 0, hi = nseg - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (segs[mid].row_base <= row) lo = mid;
             else hi = mid - 1;
         }
-        const PrepSeg& g = segs[lo];
+        return lo;
+    };
+    // with an ordering, output row r holds input row perm[r]
+    auto src_of = [&](const PrepSeg& g, int64_t r) {
+        return (ordered && g.perm) ? (int64_t)g.perm[r] : r;
+    };
+    const int64_t first = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    if (first >= n) return;
+    int sa = seg_of(first);
+    bool regs = segs[sa].Kp <= kRegMax;
+    float xa[kRegNV], xb[kRegNV];
+    if (regs) {
+        const PrepSeg& g = segs[sa];
+        load_row_reg(g.X, g.rows, g.dim, g.ld, src_of(g, first - g.row_base), lane, xa);
+    }
+    for (int64_t row = first; row < n; row += stride) {
+        const PrepSeg& g = segs[sa];
         const int64_t r = row - g.row_base;
-        // with an ordering, output row r holds input row perm[r]
-        const int64_t src = (ordered && g.perm) ? (int64_t)g.perm[r] : r;
-        prep_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, r, src, lane);
+        // the wave's next row: its segment, and its data when it is held in
+        // registers, before this row is reduced and written
+        const int64_t next = row + stride;
+        int sb = sa;
+        bool nregs = false;
+        if (next < n) {
+            // a wave's rows increase: scan forward from this row's segment
+            while (sb + 1 < nseg && segs[sb + 1].row_base <= next) ++sb;
+            const PrepSeg& h = segs[sb];
+            nregs = h.Kp <= kRegMax;
+            if (nregs) load_row_reg(h.X, h.rows, h.dim, h.ld, src_of(h, next - h.row_base), lane, xb);
+        }
+        const int64_t src = src_of(g, r);
+        if (regs)
+            prep_row_regs<PREC>(xa, src < g.rows, g.dim, g.Xq, g.Kp, g.info, g.hdr, r, lane);
+        else
+            prep_one_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, r, src, lane);
+#pragma unroll
+        for (int j = 0; j < kRegNV; ++j) xa[j] = xb[j];
+        sa = sb;
+        regs = nregs;
     }
 }
 
