@@ -149,13 +149,25 @@ __global__ __launch_bounds__(256) void mlp_pair_loss(const float* __restrict__ Z
     if (lane == 0) atomicAdd(loss, ((p - tt) * (p - tt) + lam * under * under) / (float)B);
 }
 
-// column sums of an M x N matrix (bias gradients), one thread per column
-__global__ void mlp_colsum(const float* __restrict__ G, int M, int N, float* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
+// column sums of an M x N matrix (bias gradients): a workgroup per 64
+// columns, each of its 16 waves sums every 16th row (lane = column), then the
+// 16 partial sums are added in wave order (deterministic)
+constexpr int kColsumWaves = 16;
+__global__ __launch_bounds__(64 * kColsumWaves) void mlp_colsum(const float* __restrict__ G, int M,
+                                                                int N, float* __restrict__ out) {
+    __shared__ float s_part[kColsumWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + lane;
     float s = 0.0f;
-    for (int i = 0; i < M; ++i) s += G[(int64_t)i * N + j];
-    out[j] = s;
+    if (j < N)
+        for (int i = w; i < M; i += kColsumWaves) s += G[(int64_t)i * N + j];
+    s_part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && j < N) {
+        float t = 0.0f;
+        for (int q = 0; q < kColsumWaves; ++q) t += s_part[q][lane];
+        out[j] = t;
+    }
 }
 
 // Adam on the flat parameter vector; the step counter lives in the state
@@ -251,7 +263,8 @@ hipError_t launch_mlp_train_step(const MlpDev& m, const uint16_t* X, int64_t ldx
     if ((e = gemm<float, float>(H, O, R2, w.A1, 1, H, true, w.dZ, O, 1, gW2, O, nullptr, nullptr,
                                 st)) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(mlp_colsum, dim3(1), dim3(64), 0, st, w.dZ, R2, O, gb2);
+    hipLaunchKernelGGL(mlp_colsum, dim3((O + 63) / 64), dim3(64 * kColsumWaves), 0, st, w.dZ, R2, O,
+                       gb2);
     if ((e = gemm<float, uint16_t>(R2, H, O, w.dZ, O, 1, false, m.W2t, H, 1, w.dA1, H, nullptr,
                                    w.A1, st)) != hipSuccess)
         return e;
@@ -259,7 +272,8 @@ hipError_t launch_mlp_train_step(const MlpDev& m, const uint16_t* X, int64_t ldx
     if ((e = gemm<float, float>(D, H, R2, w.Xb, 1, Dp, false, w.dA1, H, 1, gW1, H, nullptr,
                                 nullptr, st)) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(mlp_colsum, dim3(1), dim3(256), 0, st, w.dA1, R2, H, gb1);
+    hipLaunchKernelGGL(mlp_colsum, dim3((H + 63) / 64), dim3(64 * kColsumWaves), 0, st, w.dA1, R2,
+                       H, gb1);
     if (hp.grad_only) return hipGetLastError();
     hipLaunchKernelGGL(mlp_adam, dim3(512), dim3(256), 0, st, m.P, m.G, m.M, m.V, m.np, m.step,
                        hp.lr, hp.beta1, hp.beta2, hp.eps);
