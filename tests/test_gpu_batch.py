@@ -147,6 +147,84 @@ def test_batch_panel_form_rejects_other_depths():
         E.batch(jobs, prec="bf16", tile=19)
 
 
+def test_batch_panel_form_retries_counts_nonfinite_and_graph():
+    """The batch panel form (640-d and 768-d jobs) through the raw call:
+    overflow and band-list retries, device counts, a job with a NaN isolated,
+    and a captured graph replayed for two batches with eager work between;
+    a graph of the panel form refuses jobs of another depth."""
+    host = _job_mix(d=640, seed=59)
+    jobs = _to_dev(host)
+    ref, st = E.batch(jobs, prec="bf16", tile=19)
+    assert st["tile"] == 19
+    for (R, S, th), rr in zip(host, ref):
+        _check_job(R, S, th, rr, "bf16", st["band"])
+    want = [set(zip(r.r.cpu().tolist(), r.s.cpu().tolist())) for r in ref]
+    # tiny outputs and band list: the raw call reports the true sizes
+    caps = [3] * len(jobs)
+    ws = torch.empty(E.batch_workspace(jobs, prec="bf16", tile=19, band_capacity=16),
+                     dtype=torch.uint8, device="cuda")
+    outs = [torch.empty((c, 3), dtype=torch.int32, device="cuda") for c in caps]
+    n_out = torch.zeros(len(jobs), dtype=torch.int64)
+    rc, st = E.batch_raw(jobs, outs, caps, ws, n_out, prec="bf16", tile=19, band_capacity=16)
+    assert rc == E.E_WORKSPACE and st["band_needed"] > 16
+    res, st = E.batch(jobs, prec="bf16", tile=19, capacities=caps, band_capacity=16)
+    assert [set(zip(r.r.cpu().tolist(), r.s.cpu().tolist())) for r in res] == want
+    # device counts
+    caps = [len(r) + 5 for r in ref]
+    ws = torch.empty(E.batch_workspace(jobs, prec="bf16", tile=19), dtype=torch.uint8,
+                     device="cuda")
+    outs = [torch.empty((max(c, 1), 3), dtype=torch.int32, device="cuda") for c in caps]
+    n_dev = torch.full((len(jobs),), -99, dtype=torch.int64, device="cuda")
+    rc, _ = E.batch_raw(jobs, outs, caps, ws, n_dev, prec="bf16", tile=19, flags=E.NO_SYNC)
+    assert rc == E.OK
+    torch.cuda.synchronize()
+    assert n_dev.cpu().tolist() == [len(r) for r in ref]
+    # a NaN in one job's R: that job fails, the others are exact
+    badh = list(host)
+    bad = host[3][0].copy()
+    bad[5, 3] = np.nan
+    badh[3] = (bad, host[3][1], host[3][2])
+    bjobs = _to_dev(badh)
+    caps = [200_000] * len(bjobs)
+    ws = torch.empty(E.batch_workspace(bjobs, prec="bf16", tile=19), dtype=torch.uint8,
+                     device="cuda")
+    outs = [torch.empty((c, 3), dtype=torch.int32, device="cuda") for c in caps]
+    n_out = torch.zeros(len(bjobs), dtype=torch.int64)
+    rc, _ = E.batch_raw(bjobs, outs, caps, ws, n_out, prec="bf16", tile=19)
+    assert rc == E.E_NONFINITE
+    assert int(n_out[3]) == 0
+    for q in range(len(bjobs)):
+        if q != 3:
+            c = int(n_out[q])
+            assert set(map(tuple, outs[q][:c, :2].cpu().tolist())) == want[q]
+    # a graph of the panel form, replayed for two batches
+    hostB = _job_mix(d=768, seed=61)[:6]
+    jobsB = _to_dev(hostB)
+    refB, _ = E.batch(jobsB, prec="bf16")
+    wantB = [set(zip(r.r.cpu().tolist(), r.s.cpu().tolist())) for r in refB]
+    ws_bytes = max(E.batch_workspace(jobs, prec="bf16", tile=19, band_capacity=1 << 20),
+                   E.batch_workspace(jobsB, prec="bf16", tile=19, band_capacity=1 << 20))
+    ws = torch.empty(ws_bytes + (1 << 16), dtype=torch.uint8, device="cuda")
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = E.BatchGraph(len(jobs), ws, prec="bf16", tile=19, band_capacity=1 << 20, stream=side)
+    try:
+        for js, rf, w in ((jobs, ref, want), (jobsB, refB, wantB), (jobs, ref, want)):
+            n, got = _graph_run(g, js, [len(r) + 8 for r in rf], side)
+            assert n == [len(x) for x in w]
+            assert got == w
+            E.batch(jobsB[:2], prec="bf16")
+            torch.cuda.synchronize()
+        small = _to_dev(_job_mix(d=96, seed=67)[:3])
+        outs = [torch.empty((8, 3), dtype=torch.int32, device="cuda") for _ in small]
+        n_dev = torch.zeros(len(small), dtype=torch.int64, device="cuda")
+        with pytest.raises(E.EjoinError):
+            g.launch(small, outs, [8] * len(small), n_dev, stream=side)
+        torch.cuda.synchronize()
+    finally:
+        g.close()
+
+
 def test_batch_fp8_tiles():
     host = _job_mix(seed=19)
     jobs = _to_dev(host)
