@@ -805,6 +805,21 @@ static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const vo
             case 10: EJ_RUN(10, 1, 4, 4, 1, 5);
             case 12: EJ_RUN(12, 1, 4, 4, 1, 6);
         }
+    } else if constexpr (PREC == P_FP32) {
+        // FP32 fragments take the same registers per K slice as BF16 (16 per
+        // 32-row block), with four times the matrix-core steps per slice
+        switch (ks) {
+            case 1: EJ_RUN(1, 2, 4, 4, 1, 0);
+            case 2: EJ_RUN(2, 2, 4, 4, 1, 0);
+            case 3: EJ_RUN(3, 1, 4, 8, 1, 3);
+            case 4: EJ_RUN(4, 1, 4, 8, 1, 4);
+            case 5: EJ_RUN(5, 1, 4, 8, 1, 5);
+            case 6: EJ_RUN(6, 1, 4, 8, 1, 6);
+            case 8: EJ_RUN(8, 1, 4, 4, 1, 4);
+            case 9: EJ_RUN(9, 1, 4, 4, 1, 3);
+            case 10: EJ_RUN(10, 1, 4, 4, 1, 5);
+            case 12: EJ_RUN(12, 1, 4, 4, 1, 6);
+        }
     } else {
         // FP8 fragments are twice as wide per MFMA
         switch (ks) {
@@ -820,11 +835,12 @@ static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const vo
     return hipErrorInvalidValue;
 }
 
-static int slices(int prec, int Kp) { return Kp * (prec == P_BF16 ? 2 : 1) / 128; }
+static int row_bytes(int prec, int Kp) { return Kp * (prec == P_FP32 ? 4 : prec == P_BF16 ? 2 : 1); }
+static int slices(int prec, int Kp) { return row_bytes(prec, Kp) / 128; }
 
 hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs& a,
                                   hipStream_t st) {
-    const int kpb = a.Kp * (prec == P_BF16 ? 2 : 1);
+    const int kpb = row_bytes(prec, a.Kp);
     if (kpb % 128 != 0) return hipErrorInvalidValue;
     ThresholdParams ep;
     ep.lo = a.lo;
@@ -845,6 +861,9 @@ hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs&
     if (prec == P_FP8)
         return dispatch_panel<P_FP8, ThresholdEpi>(ks, two_waves, a.A, a.B, a.info_r, a.info_s,
                                                    a.nR, a.nS, true, a.hdr, ep, st);
+    if (prec == P_FP32 && !two_waves)
+        return dispatch_panel<P_FP32, ThresholdEpi>(ks, false, a.A, a.B, a.info_r, a.info_s,
+                                                    a.nR, a.nS, true, a.hdr, ep, st);
     return hipErrorInvalidValue;
 }
 

@@ -86,11 +86,12 @@ inline bool rel_ok(const ejoin_rel* X) {
 
 // planner default: the register-resident panel kernel for narrow formats
 // whose rows fit it (up to 768 bytes of K), else the LDS tile kernel
-// Row depths (K bytes) a panel tile takes: up to 768; the BF16 one-workgroup
-// panel (tile 12) also 1024, 1152, 1280 and 1536.
+// Row depths (K bytes) a panel tile takes: up to 768; the one-workgroup BF16
+// and FP32 panels (tiles 12 and 20) also 1024, 1152, 1280 and 1536.
 inline bool panel_fits(int tile, int kpb) {
     if (kpb <= 768) return true;
-    return tile == 12 && (kpb == 1024 || kpb == 1152 || kpb == 1280 || kpb == 1536);
+    return (tile == 12 || tile == 20) &&
+           (kpb == 1024 || kpb == 1152 || kpb == 1280 || kpb == 1536);
 }
 
 inline int default_tile(int prec, int Kp) {
