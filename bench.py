@@ -38,7 +38,8 @@ DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}
 # counter runs scaled by a plain copy of known size (the commands and the raw
 # figures are in profiles/threshold_fp32_100k_traffic.md); valid for the
 # kernel as it was when the counters were taken, keyed by workload and tile
-TRAFFIC = {("fp32_100k", "fp32:128x128x32"): 6204551.8 * 1024 * 2.0 + 617169.5 * 1024 * 1.0}
+TRAFFIC = {("fp32_100k", "fp32:128x128x32"): 6204551.8 * 1024 * 2.0 + 617169.5 * 1024 * 1.0,
+           ("fp32_100k", "fp32:panel/2wg"): 2823477.625 * 1024 * 2.0 + 693820.0625 * 1024 * 1.0}
 
 
 def log(*a):

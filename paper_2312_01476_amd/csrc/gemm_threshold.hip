@@ -66,6 +66,7 @@ static const TileDesc kTiles[] = {
     // batches only: BF16 register panels of 128 rows, 128-column S tiles
     {19, P_BF16, 128, 128, 64, "bf16:panel/batch"},
     {20, P_FP32, 0, 0, 32, "fp32:panel"},
+    {21, P_FP32, 0, 0, 32, "fp32:panel/2wg"},
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -111,6 +112,7 @@ hipError_t launch_threshold(int tile_id, const ThresholdArgs& a, hipStream_t st)
         case 14: return launch_threshold_panel(P_BF16, true, a, st);
         case 15: return launch_threshold_panel(P_FP8, true, a, st);
         case 20: return launch_threshold_panel(P_FP32, false, a, st);
+        case 21: return launch_threshold_panel(P_FP32, true, a, st);
         case 16: return run<P_BF16, 256, 256, 2, 2, true>(a, st);
         case 17: return run<P_FP8, 256, 256, 2, 2, true>(a, st);
         case 18: return run<P_FP32, 256, 256, 2, 2, true>(a, st);

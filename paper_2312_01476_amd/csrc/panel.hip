@@ -767,7 +767,23 @@ static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const vo
     return run_panel<PREC, KS_, RB_, CB_, NW_, OCC_, NSLOT_, EPI<NW_>>(A, B, ir, is, nR, nS, \
                                                                        split_s, hdr, ep, st)
     if (two_waves) {
-        if constexpr (PREC == P_BF16) {
+        if constexpr (PREC == P_FP32) {
+            // two workgroups per CU, each with its own ring, so that one
+            // workgroup's epilogue runs beside the other's matrix work; deeper
+            // rows take 64- (32-) column S tiles to stay within 256 registers
+            switch (ks) {
+                case 1: EJ_RUN(1, 1, 4, 4, 2, 0);
+                case 2: EJ_RUN(2, 1, 4, 4, 2, 0);
+                case 3: EJ_RUN(3, 1, 4, 4, 2, 3);
+                case 4: EJ_RUN(4, 1, 4, 4, 2, 4);
+                case 5: EJ_RUN(5, 1, 2, 4, 2, 5);
+                case 6: EJ_RUN(6, 1, 2, 4, 2, 3);
+                case 8: EJ_RUN(8, 1, 2, 4, 2, 4);
+                case 9: EJ_RUN(9, 1, 2, 4, 2, 3);
+                case 10: EJ_RUN(10, 1, 2, 4, 2, 5);
+                case 12: EJ_RUN(12, 1, 1, 4, 2, 6);
+            }
+        } else if constexpr (PREC == P_BF16) {
             switch (ks) {
                 case 1: EJ_RUN(1, 1, 4, 4, 2, 0);
                 case 2: EJ_RUN(2, 1, 4, 4, 2, 0);
@@ -861,8 +877,8 @@ hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs&
     if (prec == P_FP8)
         return dispatch_panel<P_FP8, ThresholdEpi>(ks, two_waves, a.A, a.B, a.info_r, a.info_s,
                                                    a.nR, a.nS, true, a.hdr, ep, st);
-    if (prec == P_FP32 && !two_waves)
-        return dispatch_panel<P_FP32, ThresholdEpi>(ks, false, a.A, a.B, a.info_r, a.info_s,
+    if (prec == P_FP32)
+        return dispatch_panel<P_FP32, ThresholdEpi>(ks, two_waves, a.A, a.B, a.info_r, a.info_s,
                                                     a.nR, a.nS, true, a.hdr, ep, st);
     return hipErrorInvalidValue;
 }

@@ -87,15 +87,17 @@ inline bool rel_ok(const ejoin_rel* X) {
 // planner default: the register-resident panel kernel for narrow formats
 // whose rows fit it (up to 768 bytes of K), else the LDS tile kernel
 // Row depths (K bytes) a panel tile takes: up to 768; the one-workgroup BF16
-// and FP32 panels (tiles 12 and 20) also 1024, 1152, 1280 and 1536.
+// and the FP32 panels (tiles 12, 20, 21) also 1024, 1152, 1280 and 1536.
 inline bool panel_fits(int tile, int kpb) {
     if (kpb <= 768) return true;
-    return (tile == 12 || tile == 20) &&
+    return (tile == 12 || tile == 20 || tile == 21) &&
            (kpb == 1024 || kpb == 1152 || kpb == 1280 || kpb == 1536);
 }
 
 inline int default_tile(int prec, int Kp) {
-    if (prec == P_FP32) return 1;
+    // FP32: register panels in two workgroups per CU for rows of 8, 9 or 10
+    // K slices (225-320 dims), else the 128 x 128 tile
+    if (prec == P_FP32) return (Kp == 256 || Kp == 288 || Kp == 320) ? 21 : 1;
     // register panels: eight waves on a direct-load ring from three K slices
     // of 128 bytes on, two workgroups of four waves below that (BF16)
     if (Kp * elem_bytes(prec) <= 768)
