@@ -90,7 +90,7 @@ inline bool rel_ok(const ejoin_rel* X) {
 // and the FP32 panels (tiles 12, 20, 21) also 1024, 1152, 1280 and 1536.
 inline bool panel_fits(int tile, int kpb) {
     if (kpb <= 768) return true;
-    return (tile == 12 || tile == 20 || tile == 21) &&
+    return (tile == 12 || tile == 14 || tile == 20 || tile == 21) &&
            (kpb == 1024 || kpb == 1152 || kpb == 1280 || kpb == 1536);
 }
 
@@ -102,6 +102,10 @@ inline int default_tile(int prec, int Kp) {
     // of 128 bytes on, two workgroups of four waves below that (BF16)
     if (Kp * elem_bytes(prec) <= 768)
         return prec == P_FP8 ? 13 : (Kp * elem_bytes(prec) >= 384 ? 12 : 14);
+    // deeper BF16 rows: two workgroups per CU with 64-column S tiles for 8,
+    // 9 or 10 K slices; at 12 slices (705-768 dims) the R fragments leave no
+    // room for that, so one workgroup of four waves
+    if (prec == P_BF16 && (Kp == 512 || Kp == 576 || Kp == 640)) return 14;
     if (prec == P_BF16 && panel_fits(12, Kp * 2)) return 12;
     return prec == P_BF16 ? 3 : 5;
 }
