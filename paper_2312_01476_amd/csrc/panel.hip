@@ -792,11 +792,13 @@ static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const vo
                 case 5: EJ_RUN(5, 1, 4, 4, 2, 0);
                 case 6: EJ_RUN(6, 1, 4, 4, 2, 3);
                 // deep rows: 64-column S tiles keep a wave within 256
-                // registers (at 12 slices only with spills)
+                // registers; at 12 slices 32-column tiles (with a few spills
+                // outside the matrix loop: 56.5 ms against 59.1 ms for the
+                // one-workgroup panel on a 200k x 200k 768-d join)
                 case 8: EJ_RUN(8, 1, 2, 4, 2, 4);
                 case 9: EJ_RUN(9, 1, 2, 4, 2, 3);
                 case 10: EJ_RUN(10, 1, 2, 4, 2, 5);
-                case 12: EJ_RUN(12, 1, 2, 4, 2, 6);
+                case 12: EJ_RUN(12, 1, 1, 4, 2, 6);
             }
         } else {
             // FP8 fragments are twice as wide: one S block per tile keeps the

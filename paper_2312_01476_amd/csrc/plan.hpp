@@ -102,11 +102,9 @@ inline int default_tile(int prec, int Kp) {
     // of 128 bytes on, two workgroups of four waves below that (BF16)
     if (Kp * elem_bytes(prec) <= 768)
         return prec == P_FP8 ? 13 : (Kp * elem_bytes(prec) >= 384 ? 12 : 14);
-    // deeper BF16 rows: two workgroups per CU with 64-column S tiles for 8,
-    // 9 or 10 K slices; at 12 slices (705-768 dims) the R fragments leave no
-    // room for that, so one workgroup of four waves
-    if (prec == P_BF16 && (Kp == 512 || Kp == 576 || Kp == 640)) return 14;
-    if (prec == P_BF16 && panel_fits(12, Kp * 2)) return 12;
+    // deeper BF16 rows (8, 9, 10 or 12 K slices): two workgroups per CU,
+    // with 64-column S tiles (32-column at 12 slices)
+    if (prec == P_BF16 && panel_fits(14, Kp * 2)) return 14;
     return prec == P_BF16 ? 3 : 5;
 }
 
