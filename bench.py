@@ -445,7 +445,7 @@ def bench_batch(args, w):
     achieved = flops / (ms_main * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 4), "traffic": None,
-            "kernel": "batch_panel" if st["tile"] == 19 else "batch_tile",
+            "kernel": {19: "batch_panel", 22: "batch_panel2"}.get(st["tile"], "batch_tile"),
             "kernel_ms": round(ms_main, 4), "algorithmic_flops_per_launch": flops}
 
     verify = None

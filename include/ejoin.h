@@ -229,15 +229,17 @@ size_t ejoin_batch_workspace(const ejoin_job *jobs, int32_t n_jobs, const ejoin_
 /*
  * Run a batch of threshold joins.
  *   jobs, n_jobs  (host) 0 <= n_jobs <= 65536; all jobs use opts->prec.
- *   opts->tile    a tile of the LDS tile kernel for opts->prec; or 19, the
- *                 batch form of the BF16 register panels (128-row panels,
- *                 each work item one panel over 16 S tiles of 128 rows),
- *                 which needs every non-empty job's dim padded to 512, 576,
- *                 640 or 768 (dims 449-640 and 705-768), else EJOIN_E_INVAL;
- *                 the other register-panel tiles have no batch form
- *                 (EJOIN_E_INVAL); or 0: the tuner's choice, else 19 for a
- *                 BF16 batch whose every job has such a dim, else the
- *                 planner's default tile.
+ *   opts->tile    a tile of the LDS tile kernel for opts->prec; or 19 / 22,
+ *                 the batch forms of the BF16 register panels (128-row
+ *                 panels, each work item one panel over 16 S tiles of 128
+ *                 rows; one workgroup per CU, or two with 32-row S tiles,
+ *                 22 without the prefilter only), which need every non-empty
+ *                 job's dim padded to 512, 576, 640 or 768 (dims 449-640 and
+ *                 705-768), else EJOIN_E_INVAL; the other register-panel
+ *                 tiles have no batch form (EJOIN_E_INVAL); or 0: the tuner's
+ *                 choice, else 22 (19 with the prefilter) for a BF16 batch
+ *                 whose every job has such a dim, else the planner's default
+ *                 tile.
  *   n_out         (host) int64[n_jobs] receives each job's true match count;
  *                 with EJOIN_NO_SYNC a DEVICE int64[n_jobs] (negative status
  *                 codes as for EJOIN_NO_SYNC above).

@@ -41,12 +41,13 @@ ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts*
         // the tuner's measured choice for this shape when it has one that fits
         const int t = o->tuner ? tuner_pick(o->tuner, 0, p.prec, p.dim, (double)p.nR * p.nS) : 0;
         const TileDesc* td = t > 0 ? tile_get(t) : nullptr;
-        const bool fits = td && td->prec == p.prec && t != 19 &&
+        const bool fits = td && td->prec == p.prec && t != 19 && t != 22 &&
                           !(td->bm == 0 && !panel_fits(t, p.Kp * elem_bytes(p.prec)));
         p.tile = fits ? t : default_tile(p.prec, p.Kp);
     }
     const TileDesc* td = tile_get(p.tile);
-    if (!td || td->prec != p.prec || p.tile == 19) return EJOIN_E_INVAL;  // 19: batches only
+    if (!td || td->prec != p.prec || p.tile == 19 || p.tile == 22)
+        return EJOIN_E_INVAL;  // 19, 22: batches only
     if (td->bm == 0 && !panel_fits(p.tile, p.Kp * elem_bytes(p.prec))) return EJOIN_E_INVAL;
     p.band_cap = o->band_capacity > 0 ? o->band_capacity
                                       : std::max<int64_t>(1 << 16, p.nR + p.nS);

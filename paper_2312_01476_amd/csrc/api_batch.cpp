@@ -34,11 +34,16 @@ struct SplitMix64 {
 };
 constexpr int kRescoreGrid = 2048;  // batched rescore: grid-stride over the band list
 
-// measured on the 64-job 768-d workload: BF16 register panels (tile 19) where
-// every job's row depth has one, else the 256 x 256 staged tile; FP32 and FP8
-// keep their 128 x 128 tiles
+// measured on the 64-job 768-d workload: BF16 register panels in two
+// workgroups per CU (tile 22; tile 19 with the prefilter) where every job's
+// row depth has one, else the 256 x 256 staged tile; FP32 and FP8 keep their
+// 128 x 128 tiles
 int batch_default_tile(int prec) { return prec == P_FP32 ? 1 : prec == P_BF16 ? 16 : 5; }
 constexpr int kPanelChunkTiles = 16;  // S tiles (of 128 columns) per panel work item
+
+// the batch forms of the BF16 register panels: one (19) or two (22)
+// workgroups per CU
+bool batch_panel_tile(int tile) { return tile == 19 || tile == 22; }
 
 bool panel_jobs_ok(const ejoin_job* jobs, int n) {
     for (int i = 0; i < n; ++i)
@@ -93,10 +98,11 @@ int pick_batch_tile(const ejoin_opts& o, const ejoin_job* jobs, int n) {
         for (int i = 0; i < n; ++i) pairs += (double)jobs[i].R.rows * (double)jobs[i].S.rows;
         const int t = tuner_pick(o.tuner, 1, o.prec, dim, pairs);
         const TileDesc* td = t > 0 ? tile_get(t) : nullptr;
-        if (td && td->prec == o.prec && batch_has_tile(t) && (t != 19 || panel_jobs_ok(jobs, n)))
+        if (td && td->prec == o.prec && batch_has_tile(t) &&
+            (!batch_panel_tile(t) || panel_jobs_ok(jobs, n)))
             return t;
     }
-    if (o.prec == EJOIN_BF16 && n > 0 && panel_jobs_ok(jobs, n)) return 19;
+    if (o.prec == EJOIN_BF16 && n > 0 && panel_jobs_ok(jobs, n)) return 22;
     return batch_default_tile(o.prec);
 }
 
@@ -118,7 +124,7 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
     if (o.prec < EJOIN_FP32 || o.prec > EJOIN_FP8_E4M3) return EJOIN_E_INVAL;
     const TileDesc* td = tile_get(tile);
     if (!td || td->prec != o.prec || !batch_has_tile(tile)) return EJOIN_E_INVAL;
-    if (tile == 19 && !panel_jobs_ok(jobs, n)) return EJOIN_E_INVAL;
+    if (batch_panel_tile(tile) && !panel_jobs_ok(jobs, n)) return EJOIN_E_INVAL;
     bp.prec = o.prec;
     bp.tile = tile;
     bp.bm = td->bm;
@@ -193,7 +199,7 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         b.tile_base = tile_base;
         b.chunk_tiles = 0;
         b.chunk_base = bp.n_chunks;
-        if (tile == 19) {
+        if (batch_panel_tile(tile)) {
             // panel items: every 128-row panel over chunks of S tiles; the
             // prefilter keeps flat tile numbers for its statistics and
             // lists the chunks separately

@@ -131,7 +131,7 @@ static int occ_of() {
 bool batch_has_tile(int tile_id) {
     switch (tile_id) {
         case 1: case 2: case 3: case 4: case 5: case 6: case 8: case 10: case 11: case 16:
-        case 17: case 18: case 19:
+        case 17: case 18: case 19: case 22:
             return true;
         default: return false;
     }
@@ -154,6 +154,7 @@ int batch_occupancy(int tile_id) {
         case 17: return occ_of<P_FP8, 256, 256, 2, 2, true>();
         case 18: return occ_of<P_FP32, 256, 256, 2, 2, true>();
         case 19: return batch_panel_occupancy();
+        case 22: return batch_panel2_occupancy();
         default: return 0;
     }
 }
@@ -174,6 +175,7 @@ hipError_t launch_batch_tile(int tile_id, const BatchHead* head, const BatchJob*
         case 17: return run_batch<P_FP8, 256, 256, 2, 2, true>(head, jobs, bctr, grid, st);
         case 18: return run_batch<P_FP32, 256, 256, 2, 2, true>(head, jobs, bctr, grid, st);
         case 19: return launch_batch_panel(head, jobs, bctr, grid, worklist, st);
+        case 22: return worklist ? hipErrorInvalidValue : launch_batch_panel2(head, jobs, bctr, grid, st);
         default: return hipErrorInvalidValue;
     }
 }

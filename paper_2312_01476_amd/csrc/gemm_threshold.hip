@@ -67,6 +67,7 @@ static const TileDesc kTiles[] = {
     {19, P_BF16, 128, 128, 64, "bf16:panel/batch"},
     {20, P_FP32, 0, 0, 32, "fp32:panel"},
     {21, P_FP32, 0, 0, 32, "fp32:panel/2wg"},
+    {22, P_BF16, 128, 128, 64, "bf16:panel/batch/2wg"},
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }

@@ -104,8 +104,15 @@ struct ThresholdEpiT {
     template <int RB, int CB>
     __device__ static __forceinline__ void tile(const Params& p, Smem& sm, State& s,
                                                 v16f (&acc)[RB][CB], const TileCtx& c) {
-        const int gi0 = c.r0 + 4 * c.h;
+        // the row numbers are the same for every tile of the sweep; an opaque
+        // copy keeps the compiler from computing all of them once before the
+        // sweep and holding them (or spilling them) across the matrix loop
+        int gi0 = c.r0 + 4 * c.h;
+        __asm__ volatile("" : "+v"(gi0));
         const int gj0 = c.t * c.bn + c.r32;
+        // relation sizes below 2^31 rows: 32-bit bound tests
+        const int nR32 = c.nR < 0x7fffffff ? (int)c.nR : 0x7fffffff;
+        const int nS32 = c.nS < 0x7fffffff ? (int)c.nS : 0x7fffffff;
         uint64_t gmask[RB][CB][4];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
@@ -135,12 +142,12 @@ struct ThresholdEpiT {
                         flush_stage(sm.band[c.wave], s.n_band, (BE*)p.band, p.band_cap,
                                     p.band_ctr, c.lane);
                     const int gj = gj0 + cb * 32;
-                    const bool vj = !c.edge || gj < c.nS;
+                    const bool vj = !c.edge || gj < nS32;
                     uint64_t ml[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const int gi = gi0 + rb * 32 + 8 * q4 + k;
-                        const bool v = vj && (!c.edge || gi < c.nR);
+                        const bool v = vj && (!c.edge || gi < nR32);
                         ml[k] = __ballot(v && acc[rb][cb][e4 + k] >= p.lo);
                     }
 #pragma unroll
@@ -690,6 +697,104 @@ __global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restric
             default: batch_panel_item<12, WL>(slots, esm, J, panel, t0, t1, mask, ep); break;
         }
     }
+}
+
+// Two workgroups per CU for a dense batch (tile 22): 32-column S tiles keep
+// the R fragments of up to 12 K slices and the rest of a wave within 256
+// registers, and six 4 KB ring slots plus the staging leave LDS for two
+// workgroups, so that one workgroup's epilogue runs beside the other's
+// matrix work.  Items are those of the one-workgroup form (one 128-row
+// panel over 16 x 128 S columns), swept as 64 tiles of 32 columns.
+constexpr int BP2_SLOT = 32 * 128;
+
+template <int KS>
+__device__ __forceinline__ void batch_panel2_item(char* const (&slots)[6],
+                                                  typename ThresholdEpiT<4, true>::Smem& esm,
+                                                  const BatchJob& J, int panel, int t0, int t1,
+                                                  const ThresholdParams& ep) {
+    constexpr int NSLOT = KS == 8 ? 4 : KS == 9 ? 3 : KS == 10 ? 5 : 6;
+    panel_sweep<P_BF16, KS, 1, 1, 4, NSLOT, ThresholdEpiT<4, true>>(
+        slots, esm, J.A, J.B, J.info_r, J.info_s, J.nR, J.nS, panel, t0, t1, ep);
+}
+
+__global__ __launch_bounds__(256, 2) void batch_panel2(const BatchHead* __restrict__ head,
+                                                       const BatchJob* __restrict__ jobs,
+                                                       unsigned long long* __restrict__ bctr) {
+    __shared__ __attribute__((aligned(16))) char sL0[BP2_SLOT];
+    __shared__ __attribute__((aligned(16))) char sL1[BP2_SLOT];
+    __shared__ __attribute__((aligned(16))) char sL2[BP2_SLOT];
+    __shared__ __attribute__((aligned(16))) char sL3[BP2_SLOT];
+    __shared__ __attribute__((aligned(16))) char sL4[BP2_SLOT];
+    __shared__ __attribute__((aligned(16))) char sL5[BP2_SLOT];
+    __shared__ typename ThresholdEpiT<4, true>::Smem esm;
+    __shared__ int64_t s_item;
+    __shared__ int s_job;
+    char* const slots[6] = {sL0, sL1, sL2, sL3, sL4, sL5};
+    constexpr int SUB = 128 / 32;  // 32-column tiles per 128-column tile
+    const int64_t total = head->n_tiles;
+    const int n_jobs = head->n_jobs;
+    const int tid = (int)__builtin_amdgcn_workitem_id_x();
+    for (;;) {
+        if (tid == 0) {
+            const int64_t item = (int64_t)atomicAdd(bctr + B_ITEM, 1ull);
+            int job = 0;
+            if (item < total) {
+                // last job whose first item is <= item
+                int lo = 0, hi = n_jobs - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (jobs[mid].tile_base <= item) lo = mid;
+                    else hi = mid - 1;
+                }
+                job = lo;
+            }
+            s_item = item;
+            s_job = job;
+        }
+        // (also: every wave is done with the previous item's ring slots)
+        __syncthreads();
+        const int64_t item = s_item;
+        const int job = __builtin_amdgcn_readfirstlane(s_job);
+        __syncthreads();  // the shared slots are rewritten by the next iteration
+        if (item >= total) break;
+        const BatchJob& J = jobs[job];
+        if (J.hdr[H_FLAGS] != 0) continue;  // bad input rows in this job
+        const int64_t local = item - J.tile_base;
+        const int panel = (int)(local % J.tiles_m);
+        const int t0 = (int)(local / J.tiles_m) * J.chunk_tiles * SUB;
+        const int t1 = min(t0 + J.chunk_tiles * SUB, (int)((J.nS + 31) / 32));
+        ThresholdParams ep;
+        ep.lo = J.lo;
+        ep.hi = J.hi;
+        ep.out = J.out;
+        ep.capacity = J.capacity;
+        ep.out_ctr = J.hdr + H_OUT;
+        ep.band = head->band;
+        ep.band_cap = head->band_cap;
+        ep.band_ctr = bctr + B_BAND;
+        ep.job = job;
+        ep.perm_r = nullptr;
+        ep.perm_s = nullptr;
+        switch (J.Kp_bytes) {  // uniform
+            case 8 * 128: batch_panel2_item<8>(slots, esm, J, panel, t0, t1, ep); break;
+            case 9 * 128: batch_panel2_item<9>(slots, esm, J, panel, t0, t1, ep); break;
+            case 10 * 128: batch_panel2_item<10>(slots, esm, J, panel, t0, t1, ep); break;
+            default: batch_panel2_item<12>(slots, esm, J, panel, t0, t1, ep); break;
+        }
+    }
+}
+
+int batch_panel2_occupancy() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_panel2, 256, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+
+hipError_t launch_batch_panel2(const BatchHead* head, const BatchJob* jobs,
+                               unsigned long long* bctr, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(batch_panel2, dim3((unsigned)grid), dim3(256), 0, st, head, jobs, bctr);
+    return hipGetLastError();
 }
 
 // K bytes per row the batch panel form takes

@@ -31,8 +31,8 @@ bool tile_runs(int tile, int prec, int Kp, bool batch) {
     if (!td || td->prec != prec) return false;
     if (batch)
         return td->bm != 0 && batch_has_tile(tile) &&
-               (tile != 19 || batch_panel_depth(Kp * elem_bytes(prec)));
-    if (tile == 19) return false;  // a batch-only form
+               ((tile != 19 && tile != 22) || batch_panel_depth(Kp * elem_bytes(prec)));
+    if (tile == 19 || tile == 22) return false;  // batch-only forms
     return !(td->bm == 0 && !panel_fits(tile, Kp * elem_bytes(prec)));
 }
 

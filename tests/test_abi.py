@@ -106,6 +106,9 @@ def test_batch_workspace_query():
     for d in (96, 384, 1024):
         assert L.ejoin_batch_workspace((E.Job * 1)(_job(E, 10, 10, d=d)), 1, C.byref(o19)) == 0
     assert L.ejoin_batch_workspace(ok, 1, C.byref(E._opts("fp32", None, 19, 0, 0))) == 0
+    o22 = E._opts("bf16", None, 22, 0, 0)
+    assert L.ejoin_batch_workspace(mixed, 3, C.byref(o22)) > 0
+    assert L.ejoin_batch_workspace((E.Job * 1)(_job(E, 10, 10, d=96)), 1, C.byref(o22)) == 0
     # empty batch is valid
     assert L.ejoin_batch_workspace(ok, 0, C.byref(o)) > 0
 

@@ -124,9 +124,10 @@ def test_batch_tile_invariance_bf16(tile):
 
 
 def test_batch_panel_form_bf16():
-    """Tile 19 (register panels, 128-row panels swept over chunks of 16 S
-    tiles): jobs of 768-, 640-, 560- and 500-d rows in one batch, one job with
-    several panels and S chunks; it is the default for such a batch."""
+    """Tiles 19 and 22 (register panels, 128-row panels swept over chunks of
+    16 x 128 S columns; one or two workgroups per CU): jobs of 768-, 640-,
+    560- and 500-d rows in one batch, one job with several panels and S
+    chunks; one of them is the default for such a batch."""
     host = _job_mix(d=768, seed=23)[:4] + _job_mix(d=640, seed=29)[4:7] + \
         _job_mix(d=560, seed=31)[7:] + _job_mix(d=500, seed=33)[:3]
     cent = G.centres(768, 20, seed=37)
@@ -134,9 +135,9 @@ def test_batch_panel_form_bf16():
     S = G.clustered_points(cent, 5000, 0.3, seed=39)[0]
     host.append((R, S, float(np.quantile(O.sim_matrix(R[:50], S), 0.99))))
     jobs = _to_dev(host)
-    for tile in (19, 0):
+    for tile in (19, 22, 0):
         res, st = E.batch(jobs, prec="bf16", tile=tile)
-        assert st["tile"] == 19
+        assert st["tile"] == tile if tile else st["tile"] in (19, 22)
         for (R_, S_, th), rr in zip(host, res):
             _check_job(R_, S_, th, rr, "bf16", st["band"])
 
@@ -147,35 +148,36 @@ def test_batch_panel_form_rejects_other_depths():
         E.batch(jobs, prec="bf16", tile=19)
 
 
-def test_batch_panel_form_retries_counts_nonfinite_and_graph():
+@pytest.mark.parametrize("tile", [19, 22])
+def test_batch_panel_form_retries_counts_nonfinite_and_graph(tile):
     """The batch panel form (640-d and 768-d jobs) through the raw call:
     overflow and band-list retries, device counts, a job with a NaN isolated,
     and a captured graph replayed for two batches with eager work between;
     a graph of the panel form refuses jobs of another depth."""
     host = _job_mix(d=640, seed=59)
     jobs = _to_dev(host)
-    ref, st = E.batch(jobs, prec="bf16", tile=19)
-    assert st["tile"] == 19
+    ref, st = E.batch(jobs, prec="bf16", tile=tile)
+    assert st["tile"] == tile
     for (R, S, th), rr in zip(host, ref):
         _check_job(R, S, th, rr, "bf16", st["band"])
     want = [set(zip(r.r.cpu().tolist(), r.s.cpu().tolist())) for r in ref]
     # tiny outputs and band list: the raw call reports the true sizes
     caps = [3] * len(jobs)
-    ws = torch.empty(E.batch_workspace(jobs, prec="bf16", tile=19, band_capacity=16),
+    ws = torch.empty(E.batch_workspace(jobs, prec="bf16", tile=tile, band_capacity=16),
                      dtype=torch.uint8, device="cuda")
     outs = [torch.empty((c, 3), dtype=torch.int32, device="cuda") for c in caps]
     n_out = torch.zeros(len(jobs), dtype=torch.int64)
-    rc, st = E.batch_raw(jobs, outs, caps, ws, n_out, prec="bf16", tile=19, band_capacity=16)
+    rc, st = E.batch_raw(jobs, outs, caps, ws, n_out, prec="bf16", tile=tile, band_capacity=16)
     assert rc == E.E_WORKSPACE and st["band_needed"] > 16
-    res, st = E.batch(jobs, prec="bf16", tile=19, capacities=caps, band_capacity=16)
+    res, st = E.batch(jobs, prec="bf16", tile=tile, capacities=caps, band_capacity=16)
     assert [set(zip(r.r.cpu().tolist(), r.s.cpu().tolist())) for r in res] == want
     # device counts
     caps = [len(r) + 5 for r in ref]
-    ws = torch.empty(E.batch_workspace(jobs, prec="bf16", tile=19), dtype=torch.uint8,
+    ws = torch.empty(E.batch_workspace(jobs, prec="bf16", tile=tile), dtype=torch.uint8,
                      device="cuda")
     outs = [torch.empty((max(c, 1), 3), dtype=torch.int32, device="cuda") for c in caps]
     n_dev = torch.full((len(jobs),), -99, dtype=torch.int64, device="cuda")
-    rc, _ = E.batch_raw(jobs, outs, caps, ws, n_dev, prec="bf16", tile=19, flags=E.NO_SYNC)
+    rc, _ = E.batch_raw(jobs, outs, caps, ws, n_dev, prec="bf16", tile=tile, flags=E.NO_SYNC)
     assert rc == E.OK
     torch.cuda.synchronize()
     assert n_dev.cpu().tolist() == [len(r) for r in ref]
@@ -186,11 +188,11 @@ def test_batch_panel_form_retries_counts_nonfinite_and_graph():
     badh[3] = (bad, host[3][1], host[3][2])
     bjobs = _to_dev(badh)
     caps = [200_000] * len(bjobs)
-    ws = torch.empty(E.batch_workspace(bjobs, prec="bf16", tile=19), dtype=torch.uint8,
+    ws = torch.empty(E.batch_workspace(bjobs, prec="bf16", tile=tile), dtype=torch.uint8,
                      device="cuda")
     outs = [torch.empty((c, 3), dtype=torch.int32, device="cuda") for c in caps]
     n_out = torch.zeros(len(bjobs), dtype=torch.int64)
-    rc, _ = E.batch_raw(bjobs, outs, caps, ws, n_out, prec="bf16", tile=19)
+    rc, _ = E.batch_raw(bjobs, outs, caps, ws, n_out, prec="bf16", tile=tile)
     assert rc == E.E_NONFINITE
     assert int(n_out[3]) == 0
     for q in range(len(bjobs)):
@@ -202,12 +204,12 @@ def test_batch_panel_form_retries_counts_nonfinite_and_graph():
     jobsB = _to_dev(hostB)
     refB, _ = E.batch(jobsB, prec="bf16")
     wantB = [set(zip(r.r.cpu().tolist(), r.s.cpu().tolist())) for r in refB]
-    ws_bytes = max(E.batch_workspace(jobs, prec="bf16", tile=19, band_capacity=1 << 20),
-                   E.batch_workspace(jobsB, prec="bf16", tile=19, band_capacity=1 << 20))
+    ws_bytes = max(E.batch_workspace(jobs, prec="bf16", tile=tile, band_capacity=1 << 20),
+                   E.batch_workspace(jobsB, prec="bf16", tile=tile, band_capacity=1 << 20))
     ws = torch.empty(ws_bytes + (1 << 16), dtype=torch.uint8, device="cuda")
     side = torch.cuda.Stream()
     torch.cuda.synchronize()
-    g = E.BatchGraph(len(jobs), ws, prec="bf16", tile=19, band_capacity=1 << 20, stream=side)
+    g = E.BatchGraph(len(jobs), ws, prec="bf16", tile=tile, band_capacity=1 << 20, stream=side)
     try:
         for js, rf, w in ((jobs, ref, want), (jobsB, refB, wantB), (jobs, ref, want)):
             n, got = _graph_run(g, js, [len(r) + 8 for r in rf], side)
