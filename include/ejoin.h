@@ -159,9 +159,10 @@ size_t ejoin_threshold_workspace(const ejoin_rel *R, const ejoin_rel *S,
  *   theta     finite threshold.
  *   opts      (host, may be NULL = defaults).  opts->tile: 0 or a tile id of
  *             opts->prec (ejoin_tile_name); the register-panel tiles (12 BF16,
- *             13 FP8, 14 / 15 two workgroups per CU, 20 FP32) take rows of at
- *             most 768 bytes of padded K, tiles 12 and 20 also of 1024, 1152,
- *             1280 or 1536 bytes; other depths give EJOIN_E_INVAL.
+ *             13 FP8, 14 / 15 BF16 / FP8 in two workgroups per CU, 20 / 21
+ *             FP32 in one / two) take rows of at most 768 bytes of padded K,
+ *             tiles 12, 14, 20 and 21 also of 1024, 1152, 1280 or 1536 bytes;
+ *             other depths give EJOIN_E_INVAL; 19 and 22 are batch-only.
  *   out       device array of `capacity` pairs; order of pairs is unspecified.
  *   n_out     (host) receives the number of matching pairs, or, with
  *             EJOIN_NO_SYNC, a DEVICE int64 that will hold it.

@@ -44,6 +44,8 @@ def test_host_helpers():
     L = E.lib()
     assert L.ejoin_strerror(2).decode().startswith("output capacity")
     assert L.ejoin_tile_name(0).decode() == "auto"
+    assert names[20] == "fp32:panel" and names[21] == "fp32:panel/2wg"
+    assert names[19] == "bf16:panel/batch" and names[22] == "bf16:panel/batch/2wg"
 
 
 def test_workspace_query_is_bounded_not_dense():
