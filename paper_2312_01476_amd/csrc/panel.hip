@@ -857,8 +857,9 @@ static hipError_t run_panel(const void* A, const void* B, const RowInfo* info_r,
 // Kp * element size must be KS * 128 bytes with KS in 1..6 (BF16 one
 // workgroup per CU: also 8, 9, 10, 12).
 //  * two_waves: one 32-row block per wave, two workgroups of four waves per
-//    CU (the epilogue of one overlaps the MFMAs of the other); K slices on a
-//    three-slot direct-load ring when KS is a multiple of 3;
+//    CU (the epilogue of one overlaps the MFMAs of the other); BF16 K slices
+//    on a direct-load ring from three slices on (64-column S tiles where the
+//    ring or the R fragments would not fit otherwise);
 //  * otherwise one workgroup per CU: for KS 3 .. 6 eight waves with one row
 //    block each, four 32-column blocks per tile and a direct-load ring of one
 //    slot per K slice (three for KS = 3); else four waves with two row blocks
@@ -893,8 +894,8 @@ static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const vo
                 case 1: EJ_RUN(1, 1, 4, 4, 2, 0);
                 case 2: EJ_RUN(2, 1, 4, 4, 2, 0);
                 case 3: EJ_RUN(3, 1, 4, 4, 2, 3);
-                case 4: EJ_RUN(4, 1, 4, 4, 2, 0);
-                case 5: EJ_RUN(5, 1, 4, 4, 2, 0);
+                case 4: EJ_RUN(4, 1, 4, 4, 2, 2);
+                case 5: EJ_RUN(5, 1, 2, 4, 2, 5);
                 case 6: EJ_RUN(6, 1, 4, 4, 2, 3);
                 // deep rows: 64-column S tiles keep a wave within 256
                 // registers; at 12 slices 32-column tiles (with a few spills

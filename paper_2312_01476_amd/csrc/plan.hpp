@@ -98,10 +98,11 @@ inline int default_tile(int prec, int Kp) {
     // FP32: register panels in two workgroups per CU for rows of 8, 9 or 10
     // K slices (225-320 dims), else the 128 x 128 tile
     if (prec == P_FP32) return (Kp == 256 || Kp == 288 || Kp == 320) ? 21 : 1;
-    // register panels: eight waves on a direct-load ring from three K slices
-    // of 128 bytes on, two workgroups of four waves below that (BF16)
+    // register panels: BF16 rows of up to four K slices of 128 bytes in two
+    // workgroups of four waves per CU, of five or six in one workgroup of
+    // eight waves (both on direct-load rings where the slices divide evenly)
     if (Kp * elem_bytes(prec) <= 768)
-        return prec == P_FP8 ? 13 : (Kp * elem_bytes(prec) >= 384 ? 12 : 14);
+        return prec == P_FP8 ? 13 : (Kp * elem_bytes(prec) >= 640 ? 12 : 14);
     // deeper BF16 rows (8, 9, 10 or 12 K slices): two workgroups per CU,
     // with 64-column S tiles (32-column at 12 slices)
     if (prec == P_BF16 && panel_fits(14, Kp * 2)) return 14;

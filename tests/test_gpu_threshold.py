@@ -222,7 +222,8 @@ def test_tile_shapes_fp8(tile):
     _check(R, S, 0.8, d=w.d, prec="fp8", tile=tile)
 
 
-@pytest.mark.parametrize("prec,d", [("bf16", 64), ("bf16", 200), ("bf16", 384), ("bf16", 500),
+@pytest.mark.parametrize("prec,d", [("bf16", 64), ("bf16", 160), ("bf16", 200), ("bf16", 300),
+                                    ("bf16", 384), ("bf16", 500),
                                     ("bf16", 560), ("bf16", 640), ("bf16", 768), ("fp8", 128),
                                     ("fp8", 300), ("fp8", 700), ("fp32", 40), ("fp32", 100),
                                     ("fp32", 160), ("fp32", 250), ("fp32", 280), ("fp32", 300),
@@ -230,14 +231,14 @@ def test_tile_shapes_fp8(tile):
 def test_panel_kernel_depths(prec, d):
     """Every resident-fragment depth of the panel kernel, ragged |R| and |S|
     (several panels, S chunks and a partial last tile); BF16 500 / 560 / 640 /
-    768 are the deep rows (8, 9, 10, 12 K slices), run as one workgroup of
-    four waves (tile 12) and as two workgroups per CU (tile 14); the FP32
+    768 are the deep rows (8, 9, 10, 12 K slices); BF16 runs as one workgroup
+    (tile 12) and as two workgroups per CU (tile 14) at every depth; the FP32
     panels (tile 20 one workgroup, 21 two workgroups per CU) take the same
     slice counts (40 .. 384 floats)."""
     cent = G.centres(d, 40, seed=d)
     R, lr = G.clustered_points(cent, 1100, 0.3, seed=d + 1)
     S, ls = G.clustered_points(cent, 1900, 0.3, seed=d + 2)
-    tiles = {"bf16": (12, 14) if d >= 449 else (12,), "fp8": (13,), "fp32": (20, 21)}[prec]
+    tiles = {"bf16": (12, 14), "fp8": (13,), "fp32": (20, 21)}[prec]
     for tile in tiles:
         st = _check(R, S, 0.7, prec=prec, tile=tile)
         assert st["tile"] == tile
