@@ -36,10 +36,14 @@ DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}
 
 # HBM bytes per launch of the dominant kernel from FETCH_SIZE / WRITE_SIZE
 # counter runs scaled by a plain copy of known size (the commands and the raw
-# figures are in profiles/threshold_fp32_100k_traffic.md); valid for the
+# figures are in profiles/threshold_fp32_100k_traffic.md and
+# profiles/hbm_traffic_bf16_kernels.md); valid for the
 # kernel as it was when the counters were taken, keyed by workload and tile
 TRAFFIC = {("fp32_100k", "fp32:128x128x32"): 6204551.8 * 1024 * 2.0 + 617169.5 * 1024 * 1.0,
-           ("fp32_100k", "fp32:panel/2wg"): 2823477.625 * 1024 * 2.0 + 693820.0625 * 1024 * 1.0}
+           ("fp32_100k", "fp32:panel/2wg"): 2823477.625 * 1024 * 2.0 + 693820.0625 * 1024 * 1.0,
+           ("bf16_1m", "bf16:panel"): 500277725.25 * 1024 * 2.0 + 12169225.65625 * 1024 * 1.0,
+           ("batch64_bf16", "bf16:panel/batch/2wg"):
+               49107465.4375 * 1024 * 2.0 + 941978.71875 * 1024 * 1.0}
 
 
 def log(*a):
@@ -444,7 +448,8 @@ def bench_batch(args, w):
     unit, peak = PEAK[w.prec]
     achieved = flops / (ms_main * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": unit,
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4),
+            "traffic": TRAFFIC.get((w.name, E.lib().ejoin_tile_name(st["tile"]).decode())),
             "kernel": {19: "batch_panel", 22: "batch_panel2"}.get(st["tile"], "batch_tile"),
             "kernel_ms": round(ms_main, 4), "algorithmic_flops_per_launch": flops}
 
