@@ -233,18 +233,17 @@ size_t ejoin_batch_workspace(const ejoin_job *jobs, int32_t n_jobs, const ejoin_
  *   opts->tile    a tile of the LDS tile kernel for opts->prec; or 19 / 22,
  *                 the batch forms of the BF16 register panels (128-row
  *                 panels, each work item one panel over 16 S tiles of 128
- *                 rows; one workgroup per CU, or two with 32-row S tiles,
- *                 22 without the prefilter only), which need every non-empty
+ *                 rows; one workgroup per CU, or two with 32-row S tiles),
+ *                 which need every non-empty
  *                 job's dim padded to 512, 576, 640 or 768 (dims 449-640 and
  *                 705-768), else EJOIN_E_INVAL; the other register-panel
  *                 tiles have no batch form (EJOIN_E_INVAL); or 0: the tuner's
- *                 choice, else 22 (19 with the prefilter) for a BF16 batch
- *                 whose every job has such a dim, else the planner's default
- *                 tile.
+ *                 choice, else 22 for a BF16 batch whose every job has such
+ *                 a dim, else the planner's default tile.
  *   n_out         (host) int64[n_jobs] receives each job's true match count;
  *                 with EJOIN_NO_SYNC a DEVICE int64[n_jobs] (negative status
  *                 codes as for EJOIN_NO_SYNC above).
- * With EJOIN_APPROX_PREFILTER (BF16, tile 3, 19 or 0, every job of the same dim
+ * With EJOIN_APPROX_PREFILTER (BF16, tile 3, 19, 22 or 0, every job of the same dim
  * as the network, eager calls only): the prepared rows are coded by the
  * network; 2048 anchor codes drawn from the rows (SplitMix64, seed
  * 0x5EED) are grouped by leader clustering at cosine 0.6 and every relation
@@ -255,9 +254,9 @@ size_t ejoin_batch_workspace(const ejoin_job *jobs, int32_t n_jobs, const ejoin_
  *     cos(max(0, angle(c_T, c_U) - a_T - a_U))
  * (c: mean code of a tile, rho: largest distance of a code from c, a:
  * largest angle of a code from c's direction); pairs are mapped back to the
- * caller's row numbers.  Tile 19 contracts the same tile pairs: a panel
- * sweeps only the kept S tiles of its 16-tile chunk, and chunks with none
- * are not visited.
+ * caller's row numbers.  Tiles 19 and 22 contract the same tile pairs: a
+ * panel sweeps only the kept S tiles of its 16-tile chunk, and chunks with
+ * none are not visited.
  * Returns EJOIN_E_OVERFLOW if any job matched more pairs than its capacity
  * (that job's `out` holds an arbitrary capacity-sized subset; re-run it with
  * more room), EJOIN_E_WORKSPACE if the shared band list was too small

@@ -35,7 +35,7 @@ struct SplitMix64 {
 constexpr int kRescoreGrid = 2048;  // batched rescore: grid-stride over the band list
 
 // measured on the 64-job 768-d workload: BF16 register panels in two
-// workgroups per CU (tile 22; tile 19 with the prefilter) where every job's
+// workgroups per CU (tile 22, also with the prefilter) where every job's
 // row depth has one, else the 256 x 256 staged tile; FP32 and FP8 keep their
 // 128 x 128 tiles
 int batch_default_tile(int prec) { return prec == P_FP32 ? 1 : prec == P_BF16 ? 16 : 5; }
@@ -91,7 +91,7 @@ int pick_batch_tile(const ejoin_opts& o, const ejoin_job* jobs, int n) {
     if (o.tile > 0) return o.tile;
     // prefilter mode: 128 x 128 tiles or 128-row panels, the statistics' grain
     if (o.flags & EJOIN_APPROX_PREFILTER)
-        return o.prec == EJOIN_BF16 && n > 0 && panel_jobs_ok(jobs, n) ? 19 : 3;
+        return o.prec == EJOIN_BF16 && n > 0 && panel_jobs_ok(jobs, n) ? 22 : 3;
     if (o.tuner && n > 0) {
         double pairs = 0.0;
         int dim = jobs[0].R.dim;
@@ -116,7 +116,7 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
     if (bp.approx) {
         // the network reads BF16 prepared rows; tile statistics are per 128 rows
         if (o.prec != EJOIN_BF16 || !o.prefilter || !(o.prefilter_eps >= 0.0f)) return EJOIN_E_INVAL;
-        if (tile != 3 && tile != 19) return EJOIN_E_INVAL;
+        if (tile != 3 && !batch_panel_tile(tile)) return EJOIN_E_INVAL;
         for (int i = 1; i < n; ++i)
             if (jobs && jobs[i].R.dim != jobs[0].R.dim) return EJOIN_E_INVAL;
         if (n > 0 && jobs && (jobs[0].R.dim < 1 || jobs[0].R.dim > 1024)) return EJOIN_E_UNSUPPORTED;
@@ -279,7 +279,7 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         bp.off_dir = take((nr / 128 + 128) * MLP_OUT * 2);
         bp.off_m1 = take((size_t)bp.n_tiles * 4);
         bp.off_m2 = take((size_t)bp.n_tiles * 4);
-        if (tile == 19) {
+        if (batch_panel_tile(tile)) {
             bp.off_keep = take((size_t)bp.n_tiles);
             bp.off_wmask = take((size_t)bp.n_chunks * 4);
         }
@@ -334,7 +334,7 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         h->work = (const int64_t*)at(bp.off_work);
         h->n_side = bp.n_side;
         h->n_work = (const unsigned long long*)at(B_WORK * sizeof(unsigned long long));
-        if (tile == 19) {
+        if (batch_panel_tile(tile)) {
             h->work_mask = (const uint32_t*)at(bp.off_wmask);
             h->n_chunks = bp.n_chunks;
         }
@@ -439,10 +439,11 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
                              (float*)(ws + bp.off_m1), (float*)(ws + bp.off_m2), bp.n_side,
                              o.prefilter_eps,
                              (int64_t*)(ws + bp.off_work), bctr + B_WORK, bp.n_tiles,
-                             bp.tile == 19 ? (uint8_t*)(ws + bp.off_keep) : nullptr, st)) !=
+                             batch_panel_tile(bp.tile) ? (uint8_t*)(ws + bp.off_keep) : nullptr,
+                             st)) !=
         hipSuccess)
         return e;
-    if (bp.tile == 19 &&
+    if (batch_panel_tile(bp.tile) &&
         (e = launch_pf_chunks(head, jobs, (const uint8_t*)(ws + bp.off_keep),
                               (int64_t*)(ws + bp.off_work), (uint32_t*)(ws + bp.off_wmask),
                               bctr + B_WORK, bctr + B_KEPT, bp.n_chunks, st)) != hipSuccess)
@@ -553,7 +554,7 @@ ejoin_status ejoin_batch(const ejoin_job* jobs, int32_t n_jobs, const ejoin_opts
     if (stats) {
         stats->tiles_total = bp.n_tiles;
         stats->tiles_kept =
-            bp.approx ? (int64_t)h[bp.tile == 19 ? B_KEPT : B_WORK] : bp.n_tiles;
+            bp.approx ? (int64_t)h[batch_panel_tile(bp.tile) ? B_KEPT : B_WORK] : bp.n_tiles;
         stats->n_pairs = total;
         stats->n_band = (int64_t)band_found;
         stats->n_band_accepted = acc;

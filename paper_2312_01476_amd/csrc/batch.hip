@@ -175,7 +175,7 @@ hipError_t launch_batch_tile(int tile_id, const BatchHead* head, const BatchJob*
         case 17: return run_batch<P_FP8, 256, 256, 2, 2, true>(head, jobs, bctr, grid, st);
         case 18: return run_batch<P_FP32, 256, 256, 2, 2, true>(head, jobs, bctr, grid, st);
         case 19: return launch_batch_panel(head, jobs, bctr, grid, worklist, st);
-        case 22: return worklist ? hipErrorInvalidValue : launch_batch_panel2(head, jobs, bctr, grid, st);
+        case 22: return launch_batch_panel2(head, jobs, bctr, grid, worklist, st);
         default: return hipErrorInvalidValue;
     }
 }

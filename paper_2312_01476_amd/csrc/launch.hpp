@@ -119,10 +119,10 @@ bool batch_panel_depth(int kpb);
 int batch_panel_occupancy();
 hipError_t launch_batch_panel(const BatchHead* head, const BatchJob* jobs,
                               unsigned long long* bctr, int grid, bool worklist, hipStream_t st);
-// the same form in two workgroups per CU (tile 22; dense batches only)
+// the same form in two workgroups per CU (tile 22)
 int batch_panel2_occupancy();
 hipError_t launch_batch_panel2(const BatchHead* head, const BatchJob* jobs,
-                               unsigned long long* bctr, int grid, hipStream_t st);
+                               unsigned long long* bctr, int grid, bool worklist, hipStream_t st);
 int batch_occupancy(int tile_id);  // resident workgroups per CU, 0: no batch form
 hipError_t launch_batch_zero(const BatchHead* head, unsigned long long* bctr, hipStream_t st);
 hipError_t launch_batch_prep(int prec, const BatchHead* head, const PrepSeg* segs, int grid,

@@ -376,7 +376,7 @@ __device__ __forceinline__ void panel_sweep(char* const (&slots)[6], typename EP
                                             const RowInfo* __restrict__ info_r,
                                             const RowInfo* __restrict__ info_s, int64_t nR,
                                             int64_t nS, int panel, int t0, int t1,
-                                            const typename EPI::Params& ep, uint32_t mask = 0) {
+                                            const typename EPI::Params& ep, uint64_t mask = 0) {
     typedef Mma<PREC> M;
     constexpr int G = M::GROUPS;
     constexpr int NF = KS * G;        // A fragments per 32-row block
@@ -395,16 +395,17 @@ __device__ __forceinline__ void panel_sweep(char* const (&slots)[6], typename EP
     static_assert(!MASK || (DMA && NSLOT <= KS), "masked sweeps run on the direct-load ring");
     constexpr int D = NS - 1;  // fill distance of the direct-load ring
     // MASK: the sweep visits only S tiles t0 + b for the set bits b of
-    // `mask` (at least one, all below t1 - t0 <= 32), in increasing order
+    // `mask` (at least one, all below t1 - t0 <= 64), in increasing order
     auto next_tile = [&](int t) -> int {
         if constexpr (MASK) {
-            const uint32_t above = t - t0 >= 31 ? 0u : mask & ~((2u << (t - t0)) - 1u);
-            return above ? t0 + __builtin_ctz(above) : t1;
+            const uint64_t above =
+                t - t0 >= 63 ? 0ull : mask & ~((2ull << (t - t0)) - 1ull);
+            return above ? t0 + __builtin_ctzll(above) : t1;
         } else {
             return t + 1;
         }
     };
-    const int tfirst = MASK ? t0 + __builtin_ctz(mask) : t0;
+    const int tfirst = MASK ? t0 + __builtin_ctzll(mask) : t0;
 
     char* const sL0 = slots[0];
     char* const sL1 = slots[1];
@@ -707,16 +708,19 @@ __global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restric
 // panel over 16 x 128 S columns), swept as 64 tiles of 32 columns.
 constexpr int BP2_SLOT = 32 * 128;
 
-template <int KS>
+template <int KS, bool WL>
 __device__ __forceinline__ void batch_panel2_item(char* const (&slots)[6],
-                                                  typename ThresholdEpiT<4, true>::Smem& esm,
+                                                  typename ThresholdEpiT<4, true, WL>::Smem& esm,
                                                   const BatchJob& J, int panel, int t0, int t1,
-                                                  const ThresholdParams& ep) {
+                                                  uint64_t mask, const ThresholdParams& ep) {
     constexpr int NSLOT = KS == 8 ? 4 : KS == 9 ? 3 : KS == 10 ? 5 : 6;
-    panel_sweep<P_BF16, KS, 1, 1, 4, NSLOT, ThresholdEpiT<4, true>>(
-        slots, esm, J.A, J.B, J.info_r, J.info_s, J.nR, J.nS, panel, t0, t1, ep);
+    panel_sweep<P_BF16, KS, 1, 1, 4, NSLOT, ThresholdEpiT<4, true, WL>, WL>(
+        slots, esm, J.A, J.B, J.info_r, J.info_s, J.nR, J.nS, panel, t0, t1, ep, mask);
 }
 
+// WL: prefilter mode (work-list items; each kept 128-column tile of the
+// item's mask becomes four kept 32-column tiles; rows in the prefilter order)
+template <bool WL>
 __global__ __launch_bounds__(256, 2) void batch_panel2(const BatchHead* __restrict__ head,
                                                        const BatchJob* __restrict__ jobs,
                                                        unsigned long long* __restrict__ bctr) {
@@ -726,42 +730,67 @@ __global__ __launch_bounds__(256, 2) void batch_panel2(const BatchHead* __restri
     __shared__ __attribute__((aligned(16))) char sL3[BP2_SLOT];
     __shared__ __attribute__((aligned(16))) char sL4[BP2_SLOT];
     __shared__ __attribute__((aligned(16))) char sL5[BP2_SLOT];
-    __shared__ typename ThresholdEpiT<4, true>::Smem esm;
+    __shared__ typename ThresholdEpiT<4, true, WL>::Smem esm;
     __shared__ int64_t s_item;
-    __shared__ int s_job;
+    __shared__ int s_job, s_panel, s_t0;
+    __shared__ uint64_t s_mask;
     char* const slots[6] = {sL0, sL1, sL2, sL3, sL4, sL5};
     constexpr int SUB = 128 / 32;  // 32-column tiles per 128-column tile
-    const int64_t total = head->n_tiles;
+    const int64_t* work = head->work;
+    const int64_t total = WL ? (int64_t)*head->n_work : head->n_tiles;
     const int n_jobs = head->n_jobs;
     const int tid = (int)__builtin_amdgcn_workitem_id_x();
     for (;;) {
         if (tid == 0) {
             const int64_t item = (int64_t)atomicAdd(bctr + B_ITEM, 1ull);
-            int job = 0;
+            int job = 0, panel = 0, t0 = 0;
+            uint64_t mask = 0;
             if (item < total) {
-                // last job whose first item is <= item
-                int lo = 0, hi = n_jobs - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (jobs[mid].tile_base <= item) lo = mid;
-                    else hi = mid - 1;
+                if constexpr (WL) {
+                    const int64_t w = work[item];
+                    job = (int)(w >> 48);
+                    panel = (int)((w >> 24) & 0xFFFFFF);
+                    t0 = (int)(w & 0xFFFFFF) * SUB;
+                    const uint32_t m16 = head->work_mask[item];
+                    for (int b = 0; b < 16; ++b)
+                        if ((m16 >> b) & 1u) mask |= 0xFull << (SUB * b);
+                } else {
+                    // last job whose first item is <= item
+                    int lo = 0, hi = n_jobs - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (jobs[mid].tile_base <= item) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    job = lo;
+                    const int64_t local = item - jobs[lo].tile_base;
+                    panel = (int)(local % jobs[lo].tiles_m);
+                    t0 = (int)(local / jobs[lo].tiles_m) * jobs[lo].chunk_tiles * SUB;
                 }
-                job = lo;
             }
             s_item = item;
             s_job = job;
+            s_panel = panel;
+            s_t0 = t0;
+            s_mask = mask;
         }
         // (also: every wave is done with the previous item's ring slots)
         __syncthreads();
         const int64_t item = s_item;
         const int job = __builtin_amdgcn_readfirstlane(s_job);
+        const int panel = __builtin_amdgcn_readfirstlane(s_panel);
+        const int t0 = __builtin_amdgcn_readfirstlane(s_t0);
+        uint64_t mask = 0;
+        if constexpr (WL) {
+            const uint64_t m = s_mask;
+            mask = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(m >> 32))
+                    << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)m);
+        }
         __syncthreads();  // the shared slots are rewritten by the next iteration
         if (item >= total) break;
         const BatchJob& J = jobs[job];
         if (J.hdr[H_FLAGS] != 0) continue;  // bad input rows in this job
-        const int64_t local = item - J.tile_base;
-        const int panel = (int)(local % J.tiles_m);
-        const int t0 = (int)(local / J.tiles_m) * J.chunk_tiles * SUB;
         const int t1 = min(t0 + J.chunk_tiles * SUB, (int)((J.nS + 31) / 32));
         ThresholdParams ep;
         ep.lo = J.lo;
@@ -773,27 +802,34 @@ __global__ __launch_bounds__(256, 2) void batch_panel2(const BatchHead* __restri
         ep.band_cap = head->band_cap;
         ep.band_ctr = bctr + B_BAND;
         ep.job = job;
-        ep.perm_r = nullptr;
-        ep.perm_s = nullptr;
+        ep.perm_r = J.perm_r;
+        ep.perm_s = J.perm_s;
         switch (J.Kp_bytes) {  // uniform
-            case 8 * 128: batch_panel2_item<8>(slots, esm, J, panel, t0, t1, ep); break;
-            case 9 * 128: batch_panel2_item<9>(slots, esm, J, panel, t0, t1, ep); break;
-            case 10 * 128: batch_panel2_item<10>(slots, esm, J, panel, t0, t1, ep); break;
-            default: batch_panel2_item<12>(slots, esm, J, panel, t0, t1, ep); break;
+            case 8 * 128: batch_panel2_item<8, WL>(slots, esm, J, panel, t0, t1, mask, ep); break;
+            case 9 * 128: batch_panel2_item<9, WL>(slots, esm, J, panel, t0, t1, mask, ep); break;
+            case 10 * 128: batch_panel2_item<10, WL>(slots, esm, J, panel, t0, t1, mask, ep); break;
+            default: batch_panel2_item<12, WL>(slots, esm, J, panel, t0, t1, mask, ep); break;
         }
     }
 }
 
 int batch_panel2_occupancy() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_panel2, 256, 0) != hipSuccess)
+    int n = 0, m = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_panel2<false>, 256, 0) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, batch_panel2<true>, 256, 0) != hipSuccess)
         return 0;
-    return n;
+    return n < m ? n : m;
 }
 
 hipError_t launch_batch_panel2(const BatchHead* head, const BatchJob* jobs,
-                               unsigned long long* bctr, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(batch_panel2, dim3((unsigned)grid), dim3(256), 0, st, head, jobs, bctr);
+                               unsigned long long* bctr, int grid, bool worklist, hipStream_t st) {
+    if (worklist)
+        hipLaunchKernelGGL(batch_panel2<true>, dim3((unsigned)grid), dim3(256), 0, st, head, jobs,
+                           bctr);
+    else
+        hipLaunchKernelGGL(batch_panel2<false>, dim3((unsigned)grid), dim3(256), 0, st, head, jobs,
+                           bctr);
     return hipGetLastError();
 }
 

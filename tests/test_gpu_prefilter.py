@@ -28,8 +28,9 @@ def setup_module(module):
 
 
 # 96-d rows run on 128 x 128 tiles; 640-d rows on the batch panel form
-# (128-row panels sweeping only the kept tiles of each 16-tile S chunk)
-DIMS = {96: 3, 640: 19}
+# (128-row panels sweeping only the kept tiles of each 16-tile S chunk, two
+# workgroups per CU; tile 19 is the one-workgroup form)
+DIMS = {96: 3, 640: 22}
 
 
 def _jobs(D, seed=3):
@@ -68,8 +69,8 @@ def setup(request):
     D = request.param
     host, jobs = _jobs(D)
     plain, st = E.batch(jobs, prec="bf16")
-    if DIMS[D] == 19:
-        assert st["tile"] == 22  # the plain batch: two workgroups per CU
+    if DIMS[D] == 22:
+        assert st["tile"] == 22  # also the plain batch's default
     return host, jobs, plain, D
 
 
@@ -128,12 +129,14 @@ def test_trained_prefilter_is_a_subset_with_high_recall(setup):
     assert recall >= 0.95
     assert kept < 1.0
 
-    if DIMS[D] == 19:
-        # the 128 x 128 tile form visits exactly the same tile pairs and so
-        # returns the same set
-        res3, st3 = E.batch(jobs, prec="bf16", tile=3, prefilter=net, eps=0.1)
-        assert st3["tiles_kept"] == st["tiles_kept"]
-        assert _sets(res3) == got
+    if DIMS[D] == 22:
+        # the one-workgroup panel form and the 128 x 128 tile form visit
+        # exactly the same tile pairs and so return the same set
+        for t in (19, 3):
+            res3, st3 = E.batch(jobs, prec="bf16", tile=t, prefilter=net, eps=0.1)
+            assert st3["tile"] == t
+            assert st3["tiles_kept"] == st["tiles_kept"]
+            assert _sets(res3) == got
 
     # the untrained network (same initial weights) at the same margin
     raw = _net(D, 5)
