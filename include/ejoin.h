@@ -31,7 +31,8 @@
  *    returned set is exactly { (i,j) : sim64(r_i,s_j) >= theta } in every
  *    precision.
  *  - Errors are returned, never printed or aborted on.  No global mutable
- *    state: calls with distinct workspaces may run concurrently.
+ *    state (except the scratch array of ejoin_threshold_noalloc): calls with
+ *    distinct workspaces may run concurrently.
  *  - Rows with a non-finite element give EJOIN_E_NONFINITE; rows whose L2 norm
  *    is non-zero but outside [2^-100, 2^100] give EJOIN_E_RANGE (rescale such
  *    input; zero rows are fine and have similarity 0 with everything).
@@ -176,6 +177,31 @@ ejoin_status ejoin_threshold(const ejoin_rel *R, const ejoin_rel *S, double thet
                              const ejoin_opts *opts, ejoin_pair *out, int64_t capacity,
                              int64_t *n_out, void *ws, size_t ws_bytes,
                              hipStream_t stream, ejoin_stats *stats);
+
+/*
+ * Allocation-free threshold join, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, semantics and results as
+ * ejoin_threshold, without the workspace: the call runs on a scratch array of
+ * EJOIN_NOALLOC_SCRATCH_BYTES that the library holds in device memory on every
+ * GPU it runs on until the process ends.  It calls no allocator.
+ *   - Joins whose workspace (ejoin_threshold_workspace with the same
+ *     arguments) exceeds EJOIN_NOALLOC_SCRATCH_BYTES are refused with
+ *     EJOIN_E_WORKSPACE (stats->ws_needed holds the size they need); for
+ *     FP32 rows of 300 dims that is about 48k rows of R and S together.
+ *   - All calls on one GPU share that GPU's array: calls that overlap in time
+ *     on one GPU (different streams, or different host threads) race and give
+ *     undefined results.  Calls ordered on one stream are safe.  Every call
+ *     starts by clearing the counters it uses; it reads nothing else that an
+ *     earlier call left there.
+ *   - EJOIN_TIMING is ignored (it would create events).
+ */
+#define EJOIN_NOALLOC_SCRATCH_BYTES (64u << 20)
+ejoin_status ejoin_threshold_noalloc(const ejoin_rel *R, const ejoin_rel *S, double theta,
+                                     const ejoin_opts *opts, ejoin_pair *out, int64_t capacity,
+                                     int64_t *n_out, hipStream_t stream, ejoin_stats *stats);
+/* EJOIN_NOALLOC_SCRATCH_BYTES as built into the library. */
+size_t ejoin_noalloc_scratch_bytes(void);
 
 /*
  * Workspace bytes needed by ejoin_topk (host arguments; 0 on bad arguments or

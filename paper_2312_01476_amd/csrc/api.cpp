@@ -2,6 +2,8 @@
 // sizes, band, tile), workspace carve-up and the launch sequence.
 #include "plan.hpp"
 
+#include <mutex>
+
 using namespace ej;
 
 namespace {
@@ -301,24 +303,16 @@ ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const
     return EJOIN_OK;
 }
 
-ejoin_status ejoin_threshold(const ejoin_rel* R, const ejoin_rel* S, double theta,
-                             const ejoin_opts* opts, ejoin_pair* out, int64_t capacity,
-                             int64_t* n_out, void* ws, size_t ws_bytes, hipStream_t stream,
-                             ejoin_stats* stats) {
-    if (!isfinite(theta) || capacity < 0 || !n_out) return EJOIN_E_INVAL;
-    if (capacity > 0 && !out) return EJOIN_E_INVAL;
-    ejoin_opts o = opts_or_default(opts);
-    Plan p;
-    ejoin_status s = make_plan(R, S, &o, p);
-    if (s != EJOIN_OK) return s;
+}  // extern "C"
+
+namespace {
+
+// The threshold join on a workspace that is already known to be large enough
+// for plan p (both entry points below check that first).
+ejoin_status threshold_run(const ejoin_rel* R, const ejoin_rel* S, double theta,
+                           const ejoin_opts& o, const Plan& p, ejoin_pair* out, int64_t capacity,
+                           int64_t* n_out, void* ws, hipStream_t stream, ejoin_stats* stats) {
     const bool sync = !(o.flags & EJOIN_NO_SYNC);
-    if (stats) {
-        memset(stats, 0, sizeof(*stats));
-        stats->ws_needed = p.total;
-        stats->band = p.band;
-        stats->tile = p.tile;
-    }
-    if (!ws || ws_bytes < p.total) return EJOIN_E_WORKSPACE;
     if (p.nR == 0 || p.nS == 0) {
         if (sync) {
             *n_out = 0;
@@ -404,5 +398,77 @@ ejoin_status ejoin_threshold(const ejoin_rel* R, const ejoin_rel* S, double thet
     if ((int64_t)h[H_OUT] > capacity) return EJOIN_E_OVERFLOW;
     return EJOIN_OK;
 }
+
+ejoin_status threshold_args(const ejoin_rel* R, const ejoin_rel* S, double theta,
+                            const ejoin_opts& o, ejoin_pair* out, int64_t capacity,
+                            int64_t* n_out, Plan& p, ejoin_stats* stats) {
+    if (!isfinite(theta) || capacity < 0 || !n_out) return EJOIN_E_INVAL;
+    if (capacity > 0 && !out) return EJOIN_E_INVAL;
+    ejoin_status s = make_plan(R, S, &o, p);
+    if (s != EJOIN_OK) return s;
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->ws_needed = p.total;
+        stats->band = p.band;
+        stats->tile = p.tile;
+    }
+    return EJOIN_OK;
+}
+
+// ---- the allocation-free variant's scratch ----
+// One array per GPU in the library's code object, resident until the process
+// ends.  Host code never passes `scratch` itself to a kernel: its device
+// address is looked up once per device (hipGetSymbolAddress with that device
+// current) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[EJOIN_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (nullptr on failure).
+void* scratch_address() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+ejoin_status ejoin_threshold(const ejoin_rel* R, const ejoin_rel* S, double theta,
+                             const ejoin_opts* opts, ejoin_pair* out, int64_t capacity,
+                             int64_t* n_out, void* ws, size_t ws_bytes, hipStream_t stream,
+                             ejoin_stats* stats) {
+    ejoin_opts o = opts_or_default(opts);
+    Plan p;
+    ejoin_status s = threshold_args(R, S, theta, o, out, capacity, n_out, p, stats);
+    if (s != EJOIN_OK) return s;
+    if (!ws || ws_bytes < p.total) return EJOIN_E_WORKSPACE;
+    return threshold_run(R, S, theta, o, p, out, capacity, n_out, ws, stream, stats);
+}
+
+ejoin_status ejoin_threshold_noalloc(const ejoin_rel* R, const ejoin_rel* S, double theta,
+                                     const ejoin_opts* opts, ejoin_pair* out, int64_t capacity,
+                                     int64_t* n_out, hipStream_t stream, ejoin_stats* stats) {
+    ejoin_opts o = opts_or_default(opts);
+    o.flags &= ~EJOIN_TIMING;  // timing would create events
+    Plan p;
+    ejoin_status s = threshold_args(R, S, theta, o, out, capacity, n_out, p, stats);
+    if (s != EJOIN_OK) return s;
+    if (p.total > (size_t)EJOIN_NOALLOC_SCRATCH_BYTES) return EJOIN_E_WORKSPACE;
+    void* ws = scratch_address();
+    if (!ws) return EJOIN_E_HIP;
+    return threshold_run(R, S, theta, o, p, out, capacity, n_out, ws, stream, stats);
+}
+
+size_t ejoin_noalloc_scratch_bytes(void) { return (size_t)EJOIN_NOALLOC_SCRATCH_BYTES; }
 
 }  // extern "C"

@@ -85,6 +85,11 @@ def lib():
         L.ejoin_threshold.argtypes = [P(Rel), P(Rel), C.c_double, P(Opts), C.c_void_p,
                                       C.c_int64, P(C.c_int64), C.c_void_p, C.c_size_t,
                                       C.c_void_p, P(Stats)]
+        L.ejoin_threshold_noalloc.restype = C.c_int
+        L.ejoin_threshold_noalloc.argtypes = [P(Rel), P(Rel), C.c_double, P(Opts), C.c_void_p,
+                                              C.c_int64, P(C.c_int64), C.c_void_p, P(Stats)]
+        L.ejoin_noalloc_scratch_bytes.restype = C.c_size_t
+        L.ejoin_noalloc_scratch_bytes.argtypes = []
         L.ejoin_topk_workspace.restype = C.c_size_t
         L.ejoin_topk_workspace.argtypes = [P(Rel), P(Rel), C.c_int32, P(Opts)]
         L.ejoin_topk.restype = C.c_int
@@ -212,6 +217,28 @@ def threshold_raw(R, S, theta, out, capacity, ws, *, d=None, prec="fp32", band=N
                                int(capacity), nptr, C.c_void_p(ws.data_ptr()),
                                int(ws.numel()), _stream(stream), C.byref(st))
     return rc, int(n.value), st.as_dict()
+
+
+def threshold_noalloc_raw(R, S, theta, out, capacity, *, d=None, prec="fp32", band=None, tile=0,
+                          band_capacity=0, flags=0, stream=None, n_out_dev=None):
+    """One ejoin_threshold_noalloc call (no workspace: the library's own
+    scratch array).  Returns (status, n_out, stats dict)."""
+    r, s = _rel(R, d), _rel(S, d)
+    o = _opts(prec, band, tile, band_capacity, flags)
+    st = Stats()
+    n = C.c_int64(0)
+    if flags & NO_SYNC:
+        nptr = C.cast(C.c_void_p(n_out_dev.data_ptr()), C.POINTER(C.c_int64))
+    else:
+        nptr = C.byref(n)
+    rc = lib().ejoin_threshold_noalloc(C.byref(r), C.byref(s), float(theta), C.byref(o),
+                                       C.c_void_p(out.data_ptr() if capacity > 0 else 0),
+                                       int(capacity), nptr, _stream(stream), C.byref(st))
+    return rc, int(n.value), st.as_dict()
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().ejoin_noalloc_scratch_bytes())
 
 
 def threshold(R, S, theta: float, *, d=None, prec="fp32", band=None, tile=0, capacity=None,
