@@ -228,3 +228,15 @@ def tile_pair_bound_angular(cT, aT, cU, aU) -> float:
     gap = np.arccos(np.clip(cphi, -1.0, 1.0)) - aT - aU
     return float(np.cos(gap)) if gap > 0.0 else 1.0
 
+
+
+def tile_rows_bound(dT, aT, V, slack: float = 0.0) -> float:
+    """Upper bound of u . v over unit u within angle aT of the unit direction
+    dT and every row v of V (unit codes): the angle between u and v is at
+    least angle(dT, v) - aT, so u . v <= cos(max(0, acos(max_v dT . v) - aT)).
+    `slack` widens the largest dot before the arccos (the library adds a
+    margin there for its BF16 copies of the codes)."""
+    dT = np.asarray(dT, np.float64)
+    m = float(np.max(np.asarray(V, np.float64) @ dT)) + slack
+    gap = np.arccos(np.clip(m, -1.0, 1.0)) - aT
+    return float(np.cos(gap)) if gap > 0.0 else 1.0

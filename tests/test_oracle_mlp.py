@@ -208,3 +208,83 @@ def test_anchor_key_groups_tight_clusters_and_orders_stably():
     assert L[0] == 0 and L.max() == len(set(L.tolist())) - 1
     keys = np.array([3, 1, 3, 0, 1])
     assert M.order_by_key(keys).tolist() == [3, 1, 4, 0, 2]
+
+
+def test_tile_rows_bound_dominates_brute_force():
+    """cos(max(0, acos(max_v dir_T . v) - a_T)) bounds every u . v of the
+    tile pair from above (slack 0), is tight for a one-row tile, and the
+    library's margin only loosens it."""
+    rng = np.random.default_rng(23)
+    base = rng.standard_normal((6, 64))
+    V = np.repeat(base, 32, axis=0) + 0.1 * rng.standard_normal((192, 64))
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    C, rho = M.tile_stats(V, 32)
+    A = M.tile_angles(V, 32)
+    tighter = 0
+    for i in range(6):
+        di = C[i] / np.linalg.norm(C[i])
+        for j in range(6):
+            bi, bj = V[i * 32:(i + 1) * 32], V[j * 32:(j + 1) * 32]
+            true_max = (bi @ bj.T).max()
+            b = M.tile_rows_bound(di, A[i], bj)
+            assert b >= true_max - 1e-12
+            assert M.tile_rows_bound(di, A[i], bj, 0.02) >= b
+            tighter += b < M.tile_pair_bound_angular(C[i], A[i], C[j], A[j]) - 1e-9
+    assert tighter > 0
+    # one-row tile T: direction = the row, angle 0: the bound is the best dot
+    for j in range(6):
+        bj = V[j * 32:(j + 1) * 32]
+        assert np.isclose(M.tile_rows_bound(V[0], 0.0, bj), (bj @ V[0]).max())
+
+
+def test_splitmix64_reference_outputs():
+    import json
+    import os
+    from oracle import prefilter as P
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "splitmix64_seed1234567.json")))
+    rng = P.SplitMix64(g["seed"])
+    assert [rng.next() for _ in g["outputs"]] == [int(x) for x in g["outputs"]]
+    # draws below n are the high words of next() * n: uniform in [0, n)
+    rng = P.SplitMix64(5)
+    d = np.array([rng.below(7) for _ in range(7000)])
+    assert d.min() == 0 and d.max() == 6 and np.all(np.abs(np.bincount(d) - 1000) < 150)
+
+
+def test_prefilter_plan_invariants():
+    """The reference plan on small clustered jobs: orders are permutations
+    sorted by key, self-joins share one order, empty jobs are skipped, and
+    the bound of every tile pair dominates the largest code product of its
+    rows (the library's margin only adds to it)."""
+    from oracle import prefilter as P
+    rng = np.random.default_rng(29)
+    D = 24
+    cent = rng.standard_normal((5, D))
+    def pts(n):
+        X = cent[rng.integers(0, 5, n)] + 0.05 * rng.standard_normal((n, D))
+        return X.astype(np.float32)
+    X = pts(300)
+    jobs = [(pts(200), pts(330), 0.8, False), (np.zeros((0, D), np.float32), pts(5), 0.5, False),
+            (X, X, 0.9, True)]
+    W1 = (rng.standard_normal((D, 256)) / np.sqrt(D)).astype(np.float32)
+    W2 = (rng.standard_normal((256, 64)) / 16).astype(np.float32)
+    params = {"W1": W1, "b1": np.zeros(256, np.float32), "W2": W2, "b2": np.zeros(64, np.float32)}
+    pl = P.plan(jobs, params, D, eps=0.1)
+    assert pl["segs"] == [(2, "r"), (0, "r"), (0, "s")]  # most tiles first, empty job left out
+    assert pl["A"].shape[0] == 830
+    for (R, S, th, alias), J in zip(jobs, pl["jobs"]):
+        if R.shape[0] == 0:
+            assert J["bound"].size == 0
+            continue
+        assert sorted(J["order_r"].tolist()) == list(range(R.shape[0]))
+        if alias:
+            assert np.array_equal(J["order_r"], J["order_s"])
+        ur = P.codes(params, R, D)[J["order_r"]]
+        us = P.codes(params, S, D)[J["order_s"]]
+        for a in range(J["bound"].shape[0]):
+            for b in range(J["bound"].shape[1]):
+                best = (ur[a * 128:(a + 1) * 128] @ us[b * 128:(b + 1) * 128].T).max()
+                assert J["bound"][a, b] >= best - 1e-9
+        assert np.array_equal(J["keep"], J["bound"] >= th - 0.1)
+    k0 = pl["keys"][1]
+    assert np.all(np.diff(k0[pl["jobs"][0]["order_r"]]) >= 0)
