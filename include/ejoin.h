@@ -215,9 +215,12 @@ size_t ejoin_topk_workspace(const ejoin_rel *R, const ejoin_rel *S, int32_t k,
  * the first min(k, |S|) S indices in the order (sim64 desc, index asc).
  *   out_idx    device int32 [|R| * k], row-major; slots past |S| hold -1.
  *   out_score  device float [|R| * k]: float(sim64); -inf in empty slots.
- *   opts->prec EJOIN_BF16 (dim <= 384) or EJOIN_FP8_E4M3 (dim <= 768) for the
- *              contraction sweep; the result is exact in both (EJOIN_FP32 and
- *              larger dims return EJOIN_E_UNSUPPORTED).
+ *   opts->prec precision of the contraction sweep: EJOIN_FP32 (the plain
+ *              form), EJOIN_BF16 or EJOIN_FP8_E4M3, any dim; the result is
+ *              exact in all three.  Rows of up to six 128-byte K slices (BF16
+ *              and FP32 also 8, 9, 10 or 12) sweep on register panels, other
+ *              depths on the 128 x 128 LDS tile kernel (stats->tile names the
+ *              form).
  *   opts->topk_cand  candidate slots per row (k..256; <= 0: 256).
  * 1 <= k <= 256.  The call runs a pilot (exact FP64 top-k of up to 256 sample
  * rows) to set a candidate floor, one contraction sweep that keeps every

@@ -74,6 +74,7 @@ struct TopkPlan {
     Plan base;      // prep part (no band list)
     int Kc = 0, n_pilot = 0;
     bool all_columns = false;
+    bool panel = true;
     size_t off_nr = 0, off_ns = 0, off_cnt = 0, off_cand = 0, off_fb = 0, off_prow = 0,
            off_pkth = 0, off_keys = 0, off_counts = 0, off_order = 0, off_partv = 0,
            off_partj = 0, total = 0;
@@ -85,9 +86,7 @@ ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, c
     if (k < 1) return EJOIN_E_INVAL;
     if (k > 256) return EJOIN_E_UNSUPPORTED;
     if (!rel_ok(R) || !rel_ok(S) || R->dim != S->dim) return EJOIN_E_INVAL;
-    if (o->prec != EJOIN_BF16 && o->prec != EJOIN_FP8_E4M3)
-        return o->prec == EJOIN_FP32 ? EJOIN_E_UNSUPPORTED : EJOIN_E_INVAL;
-    if (padded_k(o->prec, R->dim) * elem_bytes(o->prec) > 768) return EJOIN_E_UNSUPPORTED;
+    if (o->prec < EJOIN_FP32 || o->prec > EJOIN_FP8_E4M3) return EJOIN_E_INVAL;
     ejoin_opts ob = *o;
     ob.tile = 0;
     ob.band = -1.0;
@@ -95,6 +94,9 @@ ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, c
     ejoin_status s = make_plan(R, S, &ob, tp.base);
     if (s != EJOIN_OK) return s;
     Plan& p = tp.base;
+    // candidate sweep: register panels where the row depth has a panel
+    // form, else the LDS tile kernel (any depth)
+    tp.panel = topk_panel_depth(p.prec, p.Kp * elem_bytes(p.prec));
     tp.Kc = o->topk_cand > 0 ? o->topk_cand : 256;
     if (tp.Kc < k) tp.Kc = k;
     if (tp.Kc > 256) return EJOIN_E_INVAL;
@@ -195,7 +197,9 @@ ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const
         memset(stats, 0, sizeof(*stats));
         stats->ws_needed = tp.total;
         stats->topk_slots = tp.Kc;
-        stats->tile = p.prec == P_BF16 ? 14 : 13;
+        // the sweep's form: the panel tile of the precision, or its 128 x 128 tile
+        stats->tile = tp.panel ? (p.prec == P_BF16 ? 14 : p.prec == P_FP8 ? 13 : 21)
+                               : (p.prec == P_BF16 ? 3 : p.prec == P_FP8 ? 5 : 1);
     }
     if (p.nR == 0) return EJOIN_OK;
     if (!out_idx || !out_score) return EJOIN_E_INVAL;
@@ -272,7 +276,12 @@ ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const
         ca.cnt = (int*)(w + tp.off_cnt);
         ca.cand = (int2*)(w + tp.off_cand);
         ca.Kc = tp.Kc;
-        HIP_TRY(launch_topk_candidates(p.prec, ca, stream));
+        if (tp.panel) {
+            HIP_TRY(launch_topk_candidates(p.prec, ca, stream));
+        } else {
+            HIP_TRY(launch_fill_int(ca.cnt, p.padR, 0, stream));
+            HIP_TRY(launch_topk_candidates_tile(p.prec, ca, stream));
+        }
     }
     HIP_TRY(rec(2));
     HIP_TRY(launch_topk_finalize(ta, stream));

@@ -39,7 +39,6 @@ constexpr int kRescoreGrid = 2048;  // batched rescore: grid-stride over the ban
 // row depth has one, else the 256 x 256 staged tile; FP32 and FP8 keep their
 // 128 x 128 tiles
 int batch_default_tile(int prec) { return prec == P_FP32 ? 1 : prec == P_BF16 ? 16 : 5; }
-constexpr int kPanelChunkTiles = 16;  // S tiles (of 128 columns) per panel work item
 
 // the batch forms of the BF16 register panels: one (19) or two (22)
 // workgroups per CU

@@ -14,6 +14,13 @@
 
 namespace ej {
 
+// Panel form of the batch (tiles 19 and 22): S tiles of 128 columns per
+// work item.  The prefilter's kept-tile mask of an item is one bit per tile
+// (32 bits), and the two-workgroup form widens it to four 32-column tiles per
+// bit in a 64-bit mask, so at most 16 tiles per item.
+constexpr int kPanelChunkTiles = 16;
+static_assert(kPanelChunkTiles * 4 <= 64, "the widened kept-tile mask holds 64 32-column tiles");
+
 // One join of the batch.  Jobs are stored largest first (by tile count), so
 // the work items handed out last are the small tiles of small jobs.
 struct BatchJob {

@@ -40,6 +40,88 @@ __global__ __launch_bounds__(WM* WN * 64, (BM * BN <= 128 * 128) ? 2 : 1) void t
 }
 
 // ---------------------------------------------------------------------------
+// top-k candidate sweep on the LDS tile kernel (any row depth)
+// ---------------------------------------------------------------------------
+// Every accumulator at or above the floor F (float bits in hdr[H_TOPK_F])
+// becomes a candidate (column, score) of its R row: the row's counter is
+// raised by one atomicAdd per half-wave (the 32 lanes of a half hold one row
+// of a 32x32 block, at different columns) and each hit takes the next slot;
+// hits past Kc slots are counted, not written.  Counters start at zero.
+template <int PREC>
+__global__ __launch_bounds__(256, 2) void topk_cand_tile(
+    const char* __restrict__ A, const char* __restrict__ B, const RowInfo* __restrict__ info_r,
+    const RowInfo* __restrict__ info_s, int Kp_bytes, int64_t nR, int64_t nS, int tiles_m,
+    int tiles_n, int ntiles, const unsigned long long* __restrict__ hdr, int* __restrict__ cnt,
+    int2* __restrict__ cand, int Kc) {
+    constexpr int BM = 128, BN = 128, WM = 2, WN = 2;
+    typedef TileGeom<BM, BN, WM, WN> TG;
+    EJ_TILE_SMEM(BM, BN, WM * WN, sm);
+    int bid = (int)(blockIdx.y * gridDim.x + blockIdx.x);
+    if (bid >= ntiles) return;
+    if (hdr[H_FLAGS] != 0) return;
+    const int full = ntiles & ~7;
+    if (bid < full) bid = (bid & 7) * (full >> 3) + (bid >> 3);
+    int tm, tn;
+    raster_tile(bid, tiles_m, tiles_n, tm, tn);
+    v16f acc[TG::FM][TG::FN];
+    tile_mainloop<PREC, BM, BN, WM, WN>(sm, A, B, info_r, info_s, Kp_bytes, tm, tn, acc);
+    const float F = __uint_as_float((uint32_t)hdr[H_TOPK_F]);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave / WN, wn = wave % WN, h = lane >> 5, r32 = lane & 31;
+    const uint32_t below_half = (1u << r32) - 1u;
+#pragma unroll
+    for (int i = 0; i < TG::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < TG::FN; ++j) {
+            const int64_t gj = (int64_t)tn * BN + wn * TG::WTN + j * 32 + r32;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int64_t gi =
+                    (int64_t)tm * BM + wm * TG::WTM + i * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                const float a = acc[i][j][e];
+                const bool hit = gi < nR && gj < nS && a >= F;
+                const uint64_t m = __ballot(hit);
+                if (!m) continue;
+                const uint32_t mh = h ? (uint32_t)(m >> 32) : (uint32_t)m;
+                // the lowest hitting lane of each half takes the half's slots
+                const int leader = mh ? 32 * h + __builtin_ctz(mh) : lane;
+                int base = 0;
+                if (hit && lane == leader) base = atomicAdd(cnt + gi, __popc(mh));
+                base = __shfl(base, leader, 64);
+                if (hit) {
+                    const int pos = base + __popc(mh & below_half);
+                    if (pos < Kc) cand[gi * Kc + pos] = make_int2((int)gj, __float_as_int(a));
+                }
+            }
+        }
+}
+
+template <int PREC>
+static hipError_t run_cand_tile(const CandArgs& a, hipStream_t st) {
+    const int64_t tm = (a.nR + 127) / 128, tn = (a.nS + 127) / 128;
+    const int64_t nblocks = tm * tn;
+    if (nblocks == 0) return hipSuccess;
+    if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int64_t gx = nblocks < 65536 ? nblocks : 65536;
+    const int64_t gy = (nblocks + gx - 1) / gx;
+    if (gy > 65535) return hipErrorInvalidValue;
+    const int kpb = a.Kp * (PREC == P_FP32 ? 4 : PREC == P_BF16 ? 2 : 1);
+    hipLaunchKernelGGL((topk_cand_tile<PREC>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st,
+                       (const char*)a.A, (const char*)a.B, a.info_r, a.info_s, kpb, a.nR, a.nS,
+                       (int)tm, (int)tn, (int)nblocks, a.hdr, a.cnt, a.cand, a.Kc);
+    return hipGetLastError();
+}
+
+hipError_t launch_topk_candidates_tile(int prec, const CandArgs& a, hipStream_t st) {
+    switch (prec) {
+        case P_FP32: return run_cand_tile<P_FP32>(a, st);
+        case P_BF16: return run_cand_tile<P_BF16>(a, st);
+        case P_FP8: return run_cand_tile<P_FP8>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // tile table and launcher
 // ---------------------------------------------------------------------------
 static const TileDesc kTiles[] = {

@@ -59,7 +59,12 @@ struct CandArgs {
     int2* cand;               // per padded R row, Kc slots
     int Kc;
 };
+// register-panel form: returns hipErrorInvalidValue for row depths without
+// a panel form (then the tile form below takes any depth; its per-row
+// counters must be zero first)
 hipError_t launch_topk_candidates(int prec, const CandArgs& a, hipStream_t st);
+bool topk_panel_depth(int prec, int kpb);
+hipError_t launch_topk_candidates_tile(int prec, const CandArgs& a, hipStream_t st);
 
 // exact top-k: pilot + floor, per-row finalize and fallback
 struct TopkArgs {
@@ -92,6 +97,7 @@ struct TopkArgs {
     int32_t* out_idx;
     float* out_score;
 };
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st);
 hipError_t launch_norms64(const float* X, int64_t rows, int dim, int64_t ld, double* out,
                           hipStream_t st);
 hipError_t launch_topk_pilot(const TopkArgs& a, hipStream_t st);

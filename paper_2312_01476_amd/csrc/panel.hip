@@ -570,6 +570,10 @@ __global__ __launch_bounds__(64 * NW, OCC) void panel_kernel(
     __shared__ __attribute__((aligned(16))) char sL5[NS > 5 ? SLOT : 16];
     __shared__ typename EPI::Smem esm;
     char* const slots[6] = {sL0, sL1, sL2, sL3, sL4, sL5};
+    // OCC workgroups must fit the CU's 160 KB of LDS together
+    constexpr size_t kLds = 2 * SLOT + (NS > 2 ? SLOT : 16) + (NS > 3 ? SLOT : 16) +
+                            (NS > 4 ? SLOT : 16) + (NS > 5 ? SLOT : 16) + sizeof(typename EPI::Smem);
+    static_assert(OCC * kLds <= 160 * 1024, "LDS of OCC workgroups exceeds the CU's 160 KB");
 
     // (hardware ids through the builtins: with the kernel's size the inliner
     // leaves library helpers as calls, which would put the ids in vector
@@ -752,7 +756,8 @@ __global__ __launch_bounds__(256, 2) void batch_panel2(const BatchHead* __restri
                     panel = (int)((w >> 24) & 0xFFFFFF);
                     t0 = (int)(w & 0xFFFFFF) * SUB;
                     const uint32_t m16 = head->work_mask[item];
-                    for (int b = 0; b < 16; ++b)
+                    static_assert(SUB == 4, "one 32-column tile per mask bit per quarter");
+                    for (int b = 0; b < kPanelChunkTiles; ++b)
                         if ((m16 >> b) & 1u) mask |= 0xFull << (SUB * b);
                 } else {
                     // last job whose first item is <= item
@@ -917,7 +922,7 @@ static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const vo
                 case 1: EJ_RUN(1, 1, 4, 4, 2, 0);
                 case 2: EJ_RUN(2, 1, 4, 4, 2, 0);
                 case 3: EJ_RUN(3, 1, 4, 4, 2, 3);
-                case 4: EJ_RUN(4, 1, 4, 4, 2, 4);
+                case 4: EJ_RUN(4, 1, 4, 4, 2, 2);
                 case 5: EJ_RUN(5, 1, 2, 4, 2, 5);
                 case 6: EJ_RUN(6, 1, 2, 4, 2, 3);
                 case 8: EJ_RUN(8, 1, 2, 4, 2, 4);
@@ -1033,11 +1038,21 @@ hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs&
     return hipErrorInvalidValue;
 }
 
+// Row depths (bytes of K) that the top-k candidate sweep runs on register
+// panels: up to six K slices in every format; BF16 and FP32 also eight,
+// nine, ten or twelve.
+bool topk_panel_depth(int prec, int kpb) {
+    if (kpb % 128 != 0 || kpb <= 0) return false;
+    const int ks = kpb / 128;
+    if (ks <= 6) return true;
+    return prec != P_FP8 && (ks == 8 || ks == 9 || ks == 10 || ks == 12);
+}
+
 // Top-k candidate sweep.  Every workgroup sweeps all of S for its rows.  The
 // counter table holds 64 rows per wave, which covers both layouts.
 hipError_t launch_topk_candidates(int prec, const CandArgs& a, hipStream_t st) {
-    const int kpb = a.Kp * (prec == P_BF16 ? 2 : 1);
-    if (kpb % 128 != 0 || kpb > 768) return hipErrorInvalidValue;
+    const int kpb = row_bytes(prec, a.Kp);
+    if (!topk_panel_depth(prec, kpb)) return hipErrorInvalidValue;
     CandParams ep;
     ep.hdr = a.hdr;
     ep.cnt = a.cnt;
@@ -1070,6 +1085,9 @@ hipError_t launch_topk_candidates(int prec, const CandArgs& a, hipStream_t st) {
         return dispatch_panel<P_FP8, CandEpi>(ks, true, a.A, a.B, a.info_r, a.info_s, a.nR,
                                               a.nS, false, a.hdr, ep, st);
     }
+    if (prec == P_FP32)  // two workgroups per CU (the FP32 threshold default)
+        return dispatch_panel<P_FP32, CandEpi>(ks, true, a.A, a.B, a.info_r, a.info_s, a.nR,
+                                               a.nS, false, a.hdr, ep, st);
 #undef EJ_RUN
     return hipErrorInvalidValue;
 }

@@ -786,6 +786,12 @@ static hipError_t exact_topk_batch(const TopkArgs& a, const int* rows,
     return hipGetLastError();
 }
 
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_int, dim3(1024), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_topk_pilot(const TopkArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(pilot_rows, dim3((a.n_pilot + 255) / 256), dim3(256), 0, st, a.pilot_rows,
                        a.n_pilot, a.nR);

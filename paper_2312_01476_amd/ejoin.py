@@ -280,7 +280,7 @@ def topk_workspace(R, S, k, *, d=None, prec="bf16", topk_cand=0):
     o = _opts(prec, None, 0, 0, 0, topk_cand)
     n = lib().ejoin_topk_workspace(C.byref(r), C.byref(s), int(k), C.byref(o))
     if n == 0:
-        raise EjoinError(E_INVAL if prec != "fp32" else E_UNSUPPORTED, "ejoin_topk_workspace")
+        raise EjoinError(E_INVAL, "ejoin_topk_workspace")
     return int(n)
 
 

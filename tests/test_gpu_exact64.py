@@ -99,7 +99,7 @@ def test_threshold_cut_inside_ulp_spread(prec, d):
                                       sims[0, s[row0]].astype(np.float32))
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("cand", [0, 10])
 def test_topk_ranked_by_last_ulps(prec, cand):
     """Candidates a few ulps apart are ranked by their exact sim64 (ties by

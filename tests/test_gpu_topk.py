@@ -39,7 +39,7 @@ def _check(R, S, k, prec, d=None, **kw):
     return st
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("k", [1, 3, 10, 37])
 def test_clustered(prec, k):
     cent = G.centres(128, 30, seed=1)
@@ -107,11 +107,56 @@ def test_large_s_strided_pilot(prec):
     assert st["n_fallback"] < R.shape[0] // 4
 
 
-def test_unsupported_and_invalid():
+def test_invalid():
     R = _dev(G.gaussian_raw(10, 8, seed=1))
-    with pytest.raises(E.EjoinError):
-        E.topk(R, R, 4, prec="fp32")
     with pytest.raises(E.EjoinError):
         E.topk(R, R, 0, prec="bf16")
     with pytest.raises(E.EjoinError):
         E.topk(R, R, 300, prec="bf16")
+
+
+@pytest.mark.parametrize("prec,d", [("fp32", 40), ("fp32", 300), ("fp32", 384), ("fp32", 500),
+                                    ("fp32", 1024), ("bf16", 448), ("bf16", 640),
+                                    ("bf16", 768), ("bf16", 1024), ("fp8", 1024)])
+def test_every_depth(prec, d):
+    """Register-panel sweeps (FP32 up to 12 K slices, BF16 8-12) and the
+    tile-kernel sweep for the other depths (FP32 500- and 1024-d, BF16 448-
+    and 1024-d, FP8 1024-d): indices and scores exact."""
+    cent = G.centres(d, 40, seed=d + 5)
+    R, _ = G.clustered_points(cent, 300, 0.3, seed=d + 6)
+    S, _ = G.clustered_points(cent, 3100, 0.3, seed=d + 7)
+    S[50:60] = S[7]                            # exact ties
+    st = _check(R, S, 10, prec)
+    assert st["n_fallback"] < R.shape[0] // 10
+
+
+@pytest.mark.parametrize("prec,d", [("fp32", 300), ("bf16", 1024)])
+def test_deep_and_plain_forced_fallback(prec, d):
+    cent = G.centres(d, 5, seed=30)
+    R, _ = G.clustered_points(cent, 200, 0.3, seed=31)
+    S, _ = G.clustered_points(cent, 1500, 0.3, seed=32)
+    st = _check(R, S, 8, prec, topk_cand=8)
+    assert st["n_fallback"] > 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("cand", [0, 8])
+def test_async_call(prec, cand):
+    """EJOIN_NO_SYNC: no host wait inside the call; uncertified rows take the
+    device-side fallback (one workgroup per listed row).  With 8 slots for
+    k = 8 most rows overflow and go that way."""
+    cent = G.centres(96, 5, seed=40)
+    R, _ = G.clustered_points(cent, 333, 0.3, seed=41)
+    S, _ = G.clustered_points(cent, 2100, 0.3, seed=42)
+    Rd, Sd = _dev(R), _dev(S)
+    k = 8
+    ws = torch.empty(E.topk_workspace(Rd, Sd, k, prec=prec, topk_cand=cand), dtype=torch.uint8,
+                     device="cuda")
+    idx = torch.full((R.shape[0], k), -7, dtype=torch.int32, device="cuda")
+    sc = torch.zeros((R.shape[0], k), dtype=torch.float32, device="cuda")
+    rc, _ = E.topk_raw(Rd, Sd, k, idx, sc, ws, prec=prec, topk_cand=cand, flags=E.NO_SYNC)
+    assert rc == E.OK
+    torch.cuda.synchronize()
+    oi, osc = O.topk(R, S, k)
+    np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi)
+    np.testing.assert_array_equal(sc.cpu().numpy(), osc.astype(np.float32))
