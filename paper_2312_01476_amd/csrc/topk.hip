@@ -322,16 +322,21 @@ __global__ void fill_int(int* p, int64_t n, int v) {
 
 // key[i] = smallest candidate index of row i (nS if none); counts[key]++.
 // Rows whose candidate sets coincide (one neighbourhood) get the same key.
+// Nothing runs after a failed input check: the sweep then left the candidate
+// counters unwritten.
 __global__ __launch_bounds__(256) void topk_keys(const int* __restrict__ cnt,
                                                  const int2* __restrict__ cand, int Kc,
                                                  int64_t nR, int64_t nS, int* __restrict__ key,
-                                                 int* __restrict__ counts) {
+                                                 int* __restrict__ counts,
+                                                 const unsigned long long* __restrict__ hdr) {
+    if (hdr[H_FLAGS] != 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < nR; i += (int64_t)gridDim.x * 4) {
-        const int n = min(cnt[i], Kc);
+        const int n = max(0, min(cnt[i], Kc));
         int bj = (int)nS;
         for (int t = lane; t < n; t += 64) bj = min(bj, cand[i * (int64_t)Kc + t].x);
         for (int o = 32; o > 0; o >>= 1) bj = min(bj, __shfl_xor(bj, o, 64));
+        bj = max(bj, 0);  // candidate columns lie in [0, nS)
         if (lane == 0) {
             key[i] = bj;
             atomicAdd(counts + bj, 1);
@@ -366,7 +371,8 @@ __global__ __launch_bounds__(256) void scan_counts(int* counts, int64_t n) {
 }
 
 __global__ void scatter_order(const int* __restrict__ key, int64_t nR, int* __restrict__ offs,
-                              int* __restrict__ order) {
+                              int* __restrict__ order, const unsigned long long* __restrict__ hdr) {
+    if (hdr[H_FLAGS] != 0) return;  // keys were not written
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nR;
          i += (int64_t)gridDim.x * blockDim.x)
         order[atomicAdd(offs + key[i], 1)] = (int)i;
@@ -816,10 +822,10 @@ hipError_t launch_topk_finalize(const TopkArgs& a, hipStream_t st) {
         int64_t nb = (a.nR + 3) / 4;
         if (nb > 16384) nb = 16384;
         hipLaunchKernelGGL(topk_keys, dim3((unsigned)nb), dim3(256), 0, st, a.cnt, a.cand, a.Kc,
-                           a.nR, a.nS, a.keys, a.counts);
+                           a.nR, a.nS, a.keys, a.counts, (const unsigned long long*)a.hdr);
         hipLaunchKernelGGL(scan_counts, dim3(1), dim3(256), 0, st, a.counts, a.nS + 1);
         hipLaunchKernelGGL(scatter_order, dim3(1024), dim3(256), 0, st, a.keys, a.nR, a.counts,
-                           a.order);
+                           a.order, (const unsigned long long*)a.hdr);
         order = a.order;
     }
     int64_t nb = (a.nR + FW_WAVES - 1) / FW_WAVES;

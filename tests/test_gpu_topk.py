@@ -160,3 +160,27 @@ def test_async_call(prec, cand):
     oi, osc = O.topk(R, S, k)
     np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi)
     np.testing.assert_array_equal(sc.cpu().numpy(), osc.astype(np.float32))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("flags", [0, 1])
+def test_failed_input_check_leaves_stale_workspace_unread(prec, flags):
+    """A NaN row fails the input check, so the sweep writes no candidate
+    counters; the finalize must not read the workspace's stale contents.  The
+    workspace is filled with a pattern whose int32 counters read as 5 and
+    whose candidate columns read as -1000000 (an index out of every buffer)."""
+    R = G.gaussian_raw(200, 64, seed=50)
+    S = G.gaussian_raw(700, 64, seed=51)
+    R[17, 3] = np.nan
+    Rd, Sd = _dev(R), _dev(S)
+    k = 4
+    n = E.topk_workspace(Rd, Sd, k, prec=prec)
+    word = (5 << 32) | ((-1000000) & 0xFFFFFFFF)
+    pat = torch.full(((n + 7) // 8,), word, dtype=torch.int64, device="cuda")
+    ws = pat.view(torch.uint8)[:n]
+    idx = torch.zeros((200, k), dtype=torch.int32, device="cuda")
+    sc = torch.zeros((200, k), dtype=torch.float32, device="cuda")
+    rc, _ = E.topk_raw(Rd, Sd, k, idx, sc, ws, prec=prec, flags=flags)
+    torch.cuda.synchronize()
+    assert rc == (E.OK if flags else E.E_NONFINITE)
+    assert int(idx.abs().max()) == 0   # outputs untouched
