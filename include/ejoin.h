@@ -234,6 +234,66 @@ ejoin_status ejoin_topk(const ejoin_rel *R, const ejoin_rel *S, int32_t k, const
                         hipStream_t stream, ejoin_stats *stats);
 
 /* ------------------------------------------------------------------------
+ * Relational selections pushed below the join
+ * ------------------------------------------------------------------------
+ * The scan-versus-probe study of the paper (Section VI.E) runs the E-join
+ * after a relational pre-filter on another attribute, at selectivities from
+ * 1% to 100%; the tensor (scan) join then contracts only the tuples that
+ * pass (the selection is pushed below the join, Section III.C's equivalences
+ * of selections and joins).  A selection is the list of a relation's rows
+ * that passed, as device int32 row ids in strictly ascending order, each in
+ * [0, rows); a NULL selection keeps every row.  Results name the caller's
+ * rows: offsets in threshold pairs and indices in top-k output are row ids of
+ * R and S, not positions in the lists.  A list that is not strictly
+ * ascending or holds an id out of range gives EJOIN_E_INVAL (found on the
+ * device; with EJOIN_NO_SYNC the device count holds -EJOIN_E_INVAL). */
+typedef struct {
+    const int32_t *ids;  /* device, n ids, strictly ascending */
+    int64_t n;           /* 0 <= n <= rows of the relation */
+} ejoin_sel;
+
+/*
+ * sigma(lo <= col[i] < hi) over a float attribute column of n rows (device),
+ * as a selection: ids (device, room for n) receives the passing row ids in
+ * ascending order and n_sel (DEVICE int64) their number.  NaN never passes.
+ * ws: device workspace of ejoin_select_workspace() bytes.  Asynchronous (no
+ * host wait).  n < 2^31.
+ */
+size_t ejoin_select_workspace(void);
+ejoin_status ejoin_select_range(const float *col, int64_t n, float lo, float hi, int32_t *ids,
+                                int64_t *n_sel, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Threshold join over selections: every (i, j) with i in sel_r, j in sel_s
+ * and sim64(R_i, S_j) >= theta, i and j being row ids of R and S.  The prep
+ * pass reads the selected rows through the lists (no copy of the relations)
+ * and only they are contracted; band pairs are rescored from the caller's
+ * rows; the emitted offsets are mapped back to row ids at the end.  Other
+ * arguments as ejoin_threshold; R and S alias only with the same selection.
+ */
+size_t ejoin_threshold_sel_workspace(const ejoin_rel *R, const ejoin_sel *sel_r,
+                                     const ejoin_rel *S, const ejoin_sel *sel_s,
+                                     const ejoin_opts *opts);
+ejoin_status ejoin_threshold_sel(const ejoin_rel *R, const ejoin_sel *sel_r, const ejoin_rel *S,
+                                 const ejoin_sel *sel_s, double theta, const ejoin_opts *opts,
+                                 ejoin_pair *out, int64_t capacity, int64_t *n_out, void *ws,
+                                 size_t ws_bytes, hipStream_t stream, ejoin_stats *stats);
+
+/*
+ * Top-k join over selections: for the i-th selected R row (output row i,
+ * out_idx and out_score hold sel_r->n * k entries, or |R| * k without a
+ * selection) the first min(k, |sel_s|) selected S rows in the order (sim64
+ * desc, S row id asc), as S row ids.  The selected rows are copied into
+ * compact buffers in the workspace first.  Other arguments as ejoin_topk.
+ */
+size_t ejoin_topk_sel_workspace(const ejoin_rel *R, const ejoin_sel *sel_r, const ejoin_rel *S,
+                                const ejoin_sel *sel_s, int32_t k, const ejoin_opts *opts);
+ejoin_status ejoin_topk_sel(const ejoin_rel *R, const ejoin_sel *sel_r, const ejoin_rel *S,
+                            const ejoin_sel *sel_s, int32_t k, const ejoin_opts *opts,
+                            int32_t *out_idx, float *out_score, void *ws, size_t ws_bytes,
+                            hipStream_t stream, ejoin_stats *stats);
+
+/* ------------------------------------------------------------------------
  * Batched threshold joins
  * ------------------------------------------------------------------------
  * Many independent threshold joins (each its own R, S, theta, output) run
@@ -438,6 +498,28 @@ size_t ejoin_prefilter_train_workspace(int32_t n_jobs, int32_t dim, int32_t batc
 ejoin_status ejoin_prefilter_train(void *state, const ejoin_job *jobs, int32_t n_jobs,
                                    const int64_t *n_out, const ejoin_prefilter_train_opts *to,
                                    void *ws, size_t ws_bytes, float *losses, hipStream_t stream);
+
+/*
+ * Checkpoint and resume of a prefilter network (host file).  save writes the
+ * state block's FP32 masters, Adam moments and step count for inputs of width
+ * dim, with the caller's margin eps and training seed, to `path` (a binary
+ * file: an 8-byte magic "EJPFNET1", int32 dim, int32 0, int64 n_params,
+ * int64 step, float eps, uint32 0, uint64 seed, then masters, first and
+ * second moments as n_params little-endian FP32 values each) and
+ * synchronises the stream.  load restores such a file into a state block of
+ * the same dim: masters, moments and step as saved, gradients zero, BF16
+ * copies rebuilt (codes and further training steps equal the saved
+ * network's); eps and seed (host, may be NULL) receive the saved values.
+ * EJOIN_E_INVAL: bad arguments, a file that cannot be read or written, a
+ * different dim or a malformed file (checked before the device is touched);
+ * EJOIN_E_NONFINITE: a non-finite value in the file.  The state block is
+ * caller-owned device memory, so there is nothing to free.
+ */
+ejoin_status ejoin_prefilter_save(const void *state, int32_t dim, float eps, uint64_t seed,
+                                  const char *path /* host */, hipStream_t stream);
+ejoin_status ejoin_prefilter_load(void *state, int32_t dim, const char *path /* host */,
+                                  float *eps /* host */, uint64_t *seed /* host */,
+                                  hipStream_t stream);
 
 /* Number of tile shapes the library was built with, and the name of one
  * ("prec:BMxBNxBK"); id 0 is "planner's choice".  Static storage. */

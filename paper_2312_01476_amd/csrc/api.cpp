@@ -19,7 +19,8 @@ struct Plan {
     size_t off_info_r = 0, off_info_s = 0, off_xr = 0, off_xs = 0, off_band = 0, total = 0;
 };
 
-ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts* o, Plan& p) {
+ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts* o, Plan& p,
+                       bool may_alias = true) {
     if (!rel_ok(R) || !rel_ok(S) || R->dim != S->dim) return EJOIN_E_INVAL;
     if (o->prec < EJOIN_FP32 || o->prec > EJOIN_FP8_E4M3) return EJOIN_E_INVAL;
     p.prec = o->prec;
@@ -28,7 +29,7 @@ ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts*
     p.Kp = padded_k(p.prec, p.dim);
     p.nR = R->rows;
     p.nS = S->rows;
-    p.alias = R->data == S->data && R->rows == S->rows && R->ld == S->ld;
+    p.alias = may_alias && R->data == S->data && R->rows == S->rows && R->ld == S->ld;
     p.padR = padded_rows(p.nR);
     p.padS = p.alias ? p.padR : padded_rows(p.nS);
     const double rig = band_rigorous(p.prec, p.dim);
@@ -82,7 +83,7 @@ struct TopkPlan {
 };
 
 ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const ejoin_opts* o,
-                            TopkPlan& tp) {
+                            TopkPlan& tp, bool may_alias = true) {
     if (k < 1) return EJOIN_E_INVAL;
     if (k > 256) return EJOIN_E_UNSUPPORTED;
     if (!rel_ok(R) || !rel_ok(S) || R->dim != S->dim) return EJOIN_E_INVAL;
@@ -91,7 +92,7 @@ ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, c
     ob.tile = 0;
     ob.band = -1.0;
     ob.band_capacity = 1;
-    ejoin_status s = make_plan(R, S, &ob, tp.base);
+    ejoin_status s = make_plan(R, S, &ob, tp.base, may_alias);
     if (s != EJOIN_OK) return s;
     Plan& p = tp.base;
     // candidate sweep: register panels where the row depth has a panel
@@ -130,6 +131,29 @@ ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, c
     off = align256(off + (size_t)tp.part_rows * 64 * k * sizeof(int));
     tp.total = off;
     return EJOIN_OK;
+}
+
+// A selection pushed below the join: the positions 0..n-1 of the joined
+// relation stand for the caller's rows ids[0..n-1].
+struct SelArgs {
+    const int32_t* r = nullptr;
+    const int32_t* s = nullptr;
+    int64_t src_r = 0, src_s = 0;  // rows of the caller's relations
+};
+
+// The relation a selection leaves (rows = selected count) and its checks.
+bool sel_view(const ejoin_rel* X, const ejoin_sel* sel, ejoin_rel& v) {
+    if (!X) return false;
+    v = *X;
+    if (!sel) return true;
+    if (sel->n < 0 || sel->n > X->rows || (sel->n > 0 && !sel->ids)) return false;
+    v.rows = sel->n;
+    return true;
+}
+
+bool same_selection(const ejoin_sel* a, const ejoin_sel* b) {
+    if (!a || !b) return a == b;
+    return a->ids == b->ids && a->n == b->n;
 }
 
 }  // namespace
@@ -184,18 +208,28 @@ size_t ejoin_topk_workspace(const ejoin_rel* R, const ejoin_rel* S, int32_t k,
     return tp.total;
 }
 
-ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const ejoin_opts* opts,
-                        int32_t* out_idx, float* out_score, void* ws, size_t ws_bytes,
-                        hipStream_t stream, ejoin_stats* stats) {
-    ejoin_opts o = opts_or_default(opts);
-    TopkPlan tp;
-    ejoin_status s = make_topk_plan(R, S, k, &o, tp);
-    if (s != EJOIN_OK) return s;
+// Selections of a top-k join: the selected rows are first copied into
+// compact buffers at the end of the workspace (offsets off_r, off_s), the
+// join runs on those, and the S indices of the result are mapped back.
+struct TopkGather {
+    const ejoin_rel* R = nullptr;  // the caller's relations (null: no selection)
+    const ejoin_rel* S = nullptr;
+    const int32_t* sel_r = nullptr;
+    const int32_t* sel_s = nullptr;  // null also when S is R with R's selection
+    const int32_t* map_s = nullptr;  // result indices: selection positions -> S ids
+    size_t off_r = 0, off_s = 0, total = 0;
+};
+
+static ejoin_status topk_run(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const ejoin_opts& o,
+                             const TopkPlan& tp, int32_t* out_idx, float* out_score, void* ws,
+                             size_t ws_bytes, hipStream_t stream, ejoin_stats* stats,
+                             const TopkGather& g) {
     const Plan& p = tp.base;
+    const size_t need = g.total ? g.total : tp.total;
     const bool sync = !(o.flags & EJOIN_NO_SYNC);
     if (stats) {
         memset(stats, 0, sizeof(*stats));
-        stats->ws_needed = tp.total;
+        stats->ws_needed = need;
         stats->topk_slots = tp.Kc;
         // the sweep's form: the panel tile of the precision, or its 128 x 128 tile
         stats->tile = tp.panel ? (p.prec == P_BF16 ? 14 : p.prec == P_FP8 ? 13 : 21)
@@ -203,7 +237,7 @@ ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const
     }
     if (p.nR == 0) return EJOIN_OK;
     if (!out_idx || !out_score) return EJOIN_E_INVAL;
-    if (!ws || ws_bytes < tp.total) return EJOIN_E_WORKSPACE;
+    if (!ws || ws_bytes < need) return EJOIN_E_WORKSPACE;
 
     char* w = (char*)ws;
     unsigned long long* hdr = (unsigned long long*)w;
@@ -217,6 +251,23 @@ ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const
 
     HIP_TRY(rec(0));
     HIP_TRY(launch_zero_header(hdr, stream));
+    ejoin_rel Rg = *R, Sg = *S;  // a selected side: its compact copy
+    if (g.sel_r) {
+        Rg.data = (const float*)(w + g.off_r);
+        Rg.ld = p.dim;
+        HIP_TRY(launch_gather_rows(g.R->data, g.R->ld, p.dim, g.sel_r, p.nR, g.R->rows,
+                                   (float*)(w + g.off_r), hdr, stream));
+    }
+    if (p.alias) {
+        Sg = Rg;
+    } else if (g.sel_s) {
+        Sg.data = (const float*)(w + g.off_s);
+        Sg.ld = p.dim;
+        HIP_TRY(launch_gather_rows(g.S->data, g.S->ld, p.dim, g.sel_s, p.nS, g.S->rows,
+                                   (float*)(w + g.off_s), hdr, stream));
+    }
+    R = &Rg;
+    S = &Sg;
     HIP_TRY(launch_prep(p.prec, R->data, p.nR, p.dim, R->ld, w + p.off_xr, p.Kp, p.padR, info_r,
                         hdr, H_ENORM_R, stream));
     if (!p.alias)
@@ -287,12 +338,16 @@ ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const
     HIP_TRY(launch_topk_finalize(ta, stream));
     if (!sync) {
         HIP_TRY(launch_topk_fallback(ta, -1, stream));
+        HIP_TRY(launch_map_topk(out_idx, p.nR * k, g.map_s, p.nS, hdr, stream));
         return EJOIN_OK;
     }
     unsigned long long h[H_COUNT];
     HIP_TRY(hipMemcpyAsync(h, hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
-    if (h[H_FLAGS] == 0) HIP_TRY(launch_topk_fallback(ta, (int64_t)h[H_TOPK_FB], stream));
+    if (h[H_FLAGS] == 0) {
+        HIP_TRY(launch_topk_fallback(ta, (int64_t)h[H_TOPK_FB], stream));
+        HIP_TRY(launch_map_topk(out_idx, p.nR * k, g.map_s, p.nS, hdr, stream));
+    }
     HIP_TRY(rec(3));
     HIP_TRY(hipStreamSynchronize(stream));
     if (timing) {
@@ -302,6 +357,7 @@ ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const
         hipEventElapsedTime(&stats->ms_total, ev[0], ev[3]);
         for (auto& e : ev) hipEventDestroy(e);
     }
+    if (h[H_FLAGS] & F_BADSEL) return EJOIN_E_INVAL;
     if (h[H_FLAGS] & F_NONFINITE) return EJOIN_E_NONFINITE;
     if (h[H_FLAGS] & F_RANGE) return EJOIN_E_RANGE;
     if (stats) {
@@ -312,6 +368,63 @@ ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const
     return EJOIN_OK;
 }
 
+ejoin_status ejoin_topk(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const ejoin_opts* opts,
+                        int32_t* out_idx, float* out_score, void* ws, size_t ws_bytes,
+                        hipStream_t stream, ejoin_stats* stats) {
+    ejoin_opts o = opts_or_default(opts);
+    TopkPlan tp;
+    ejoin_status s = make_topk_plan(R, S, k, &o, tp);
+    if (s != EJOIN_OK) return s;
+    return topk_run(R, S, k, o, tp, out_idx, out_score, ws, ws_bytes, stream, stats, TopkGather());
+}
+
+// plan of a top-k join over selections: the join's own plan on the selected
+// row counts, then the two compact copies
+static ejoin_status topk_sel_plan(const ejoin_rel* R, const ejoin_sel* sel_r, const ejoin_rel* S,
+                                  const ejoin_sel* sel_s, int32_t k, const ejoin_opts& o,
+                                  ejoin_rel& Rv, ejoin_rel& Sv, TopkPlan& tp, TopkGather& g) {
+    if (!sel_view(R, sel_r, Rv) || !sel_view(S, sel_s, Sv)) return EJOIN_E_INVAL;
+    ejoin_status s = make_topk_plan(&Rv, &Sv, k, &o, tp, same_selection(sel_r, sel_s));
+    if (s != EJOIN_OK) return s;
+    if (!sel_r && !sel_s) return EJOIN_OK;  // nothing to gather
+    const Plan& p = tp.base;
+    g.R = R;
+    g.S = S;
+    g.sel_r = sel_r ? sel_r->ids : nullptr;
+    g.sel_s = sel_s && !p.alias ? sel_s->ids : nullptr;
+    g.map_s = sel_s ? sel_s->ids : nullptr;
+    size_t off = align256(tp.total);
+    g.off_r = off;
+    if (g.sel_r) off = align256(off + (size_t)p.nR * p.dim * 4);
+    g.off_s = off;
+    if (g.sel_s) off = align256(off + (size_t)p.nS * p.dim * 4);
+    g.total = off;
+    return EJOIN_OK;
+}
+
+size_t ejoin_topk_sel_workspace(const ejoin_rel* R, const ejoin_sel* sel_r, const ejoin_rel* S,
+                                const ejoin_sel* sel_s, int32_t k, const ejoin_opts* opts) {
+    ejoin_opts o = opts_or_default(opts);
+    ejoin_rel Rv, Sv;
+    TopkPlan tp;
+    TopkGather g;
+    if (topk_sel_plan(R, sel_r, S, sel_s, k, o, Rv, Sv, tp, g) != EJOIN_OK) return 0;
+    return g.total ? g.total : tp.total;
+}
+
+ejoin_status ejoin_topk_sel(const ejoin_rel* R, const ejoin_sel* sel_r, const ejoin_rel* S,
+                            const ejoin_sel* sel_s, int32_t k, const ejoin_opts* opts,
+                            int32_t* out_idx, float* out_score, void* ws, size_t ws_bytes,
+                            hipStream_t stream, ejoin_stats* stats) {
+    ejoin_opts o = opts_or_default(opts);
+    ejoin_rel Rv, Sv;
+    TopkPlan tp;
+    TopkGather g;
+    ejoin_status s = topk_sel_plan(R, sel_r, S, sel_s, k, o, Rv, Sv, tp, g);
+    if (s != EJOIN_OK) return s;
+    return topk_run(&Rv, &Sv, k, o, tp, out_idx, out_score, ws, ws_bytes, stream, stats, g);
+}
+
 }  // extern "C"
 
 namespace {
@@ -320,7 +433,8 @@ namespace {
 // for plan p (both entry points below check that first).
 ejoin_status threshold_run(const ejoin_rel* R, const ejoin_rel* S, double theta,
                            const ejoin_opts& o, const Plan& p, ejoin_pair* out, int64_t capacity,
-                           int64_t* n_out, void* ws, hipStream_t stream, ejoin_stats* stats) {
+                           int64_t* n_out, void* ws, hipStream_t stream, ejoin_stats* stats,
+                           const SelArgs& sel = SelArgs()) {
     const bool sync = !(o.flags & EJOIN_NO_SYNC);
     if (p.nR == 0 || p.nS == 0) {
         if (sync) {
@@ -351,10 +465,10 @@ ejoin_status threshold_run(const ejoin_rel* R, const ejoin_rel* S, double theta,
     HIP_TRY(rec(0));
     HIP_TRY(launch_zero_header(hdr, stream));
     HIP_TRY(launch_prep(p.prec, R->data, p.nR, p.dim, R->ld, xr, p.Kp, p.padR, info_r, hdr,
-                        H_ENORM_R, stream));
+                        H_ENORM_R, stream, sel.r, sel.src_r));
     if (!p.alias)
         HIP_TRY(launch_prep(p.prec, S->data, p.nS, p.dim, S->ld, xs, p.Kp, p.padS, info_s, hdr,
-                            H_ENORM_S, stream));
+                            H_ENORM_S, stream, sel.s, sel.src_s));
     HIP_TRY(rec(1));
 
     ThresholdArgs a;
@@ -376,7 +490,8 @@ ejoin_status threshold_run(const ejoin_rel* R, const ejoin_rel* S, double theta,
     HIP_TRY(launch_threshold(p.tile, a, stream));
     HIP_TRY(rec(2));
     HIP_TRY(launch_rescore_band(R->data, R->ld, S->data, S->ld, p.dim, band, p.band_cap, theta,
-                                (Pair*)out, capacity, hdr, stream));
+                                (Pair*)out, capacity, hdr, stream, sel.r, sel.s));
+    HIP_TRY(launch_map_pairs((Pair*)out, capacity, hdr, sel.r, sel.s, stream));
     HIP_TRY(rec(3));
 
     if (!sync) {
@@ -393,6 +508,7 @@ ejoin_status threshold_run(const ejoin_rel* R, const ejoin_rel* S, double theta,
         hipEventElapsedTime(&stats->ms_total, ev[0], ev[3]);
         for (auto& e : ev) hipEventDestroy(e);
     }
+    if (h[H_FLAGS] & F_BADSEL) return EJOIN_E_INVAL;
     if (h[H_FLAGS] & F_NONFINITE) return EJOIN_E_NONFINITE;
     if (h[H_FLAGS] & F_RANGE) return EJOIN_E_RANGE;
     *n_out = (int64_t)h[H_OUT];
@@ -410,10 +526,10 @@ ejoin_status threshold_run(const ejoin_rel* R, const ejoin_rel* S, double theta,
 
 ejoin_status threshold_args(const ejoin_rel* R, const ejoin_rel* S, double theta,
                             const ejoin_opts& o, ejoin_pair* out, int64_t capacity,
-                            int64_t* n_out, Plan& p, ejoin_stats* stats) {
+                            int64_t* n_out, Plan& p, ejoin_stats* stats, bool may_alias = true) {
     if (!isfinite(theta) || capacity < 0 || !n_out) return EJOIN_E_INVAL;
     if (capacity > 0 && !out) return EJOIN_E_INVAL;
-    ejoin_status s = make_plan(R, S, &o, p);
+    ejoin_status s = make_plan(R, S, &o, p, may_alias);
     if (s != EJOIN_OK) return s;
     if (stats) {
         memset(stats, 0, sizeof(*stats));
@@ -479,5 +595,47 @@ ejoin_status ejoin_threshold_noalloc(const ejoin_rel* R, const ejoin_rel* S, dou
 }
 
 size_t ejoin_noalloc_scratch_bytes(void) { return (size_t)EJOIN_NOALLOC_SCRATCH_BYTES; }
+
+size_t ejoin_threshold_sel_workspace(const ejoin_rel* R, const ejoin_sel* sel_r,
+                                     const ejoin_rel* S, const ejoin_sel* sel_s,
+                                     const ejoin_opts* opts) {
+    ejoin_opts o = opts_or_default(opts);
+    ejoin_rel Rv, Sv;
+    Plan p;
+    if (!sel_view(R, sel_r, Rv) || !sel_view(S, sel_s, Sv)) return 0;
+    if (make_plan(&Rv, &Sv, &o, p, same_selection(sel_r, sel_s)) != EJOIN_OK) return 0;
+    return p.total;
+}
+
+ejoin_status ejoin_threshold_sel(const ejoin_rel* R, const ejoin_sel* sel_r, const ejoin_rel* S,
+                                 const ejoin_sel* sel_s, double theta, const ejoin_opts* opts,
+                                 ejoin_pair* out, int64_t capacity, int64_t* n_out, void* ws,
+                                 size_t ws_bytes, hipStream_t stream, ejoin_stats* stats) {
+    ejoin_opts o = opts_or_default(opts);
+    ejoin_rel Rv, Sv;
+    if (!sel_view(R, sel_r, Rv) || !sel_view(S, sel_s, Sv)) return EJOIN_E_INVAL;
+    Plan p;
+    ejoin_status s = threshold_args(&Rv, &Sv, theta, o, out, capacity, n_out, p, stats,
+                                    same_selection(sel_r, sel_s));
+    if (s != EJOIN_OK) return s;
+    if (!ws || ws_bytes < p.total) return EJOIN_E_WORKSPACE;
+    SelArgs sa;
+    sa.r = sel_r ? sel_r->ids : nullptr;
+    sa.s = sel_s ? sel_s->ids : nullptr;
+    sa.src_r = R->rows;
+    sa.src_s = S->rows;
+    return threshold_run(&Rv, &Sv, theta, o, p, out, capacity, n_out, ws, stream, stats, sa);
+}
+
+size_t ejoin_select_workspace(void) { return select_range_workspace(); }
+
+ejoin_status ejoin_select_range(const float* col, int64_t n, float lo, float hi, int32_t* ids,
+                                int64_t* n_sel, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (n < 0 || n > 0x7fffffffLL || !n_sel || isnan(lo) || isnan(hi)) return EJOIN_E_INVAL;
+    if (n > 0 && (!col || !ids)) return EJOIN_E_INVAL;
+    if (!ws || ws_bytes < select_range_workspace()) return EJOIN_E_WORKSPACE;
+    HIP_TRY(launch_select_range(col, n, lo, hi, ids, n_sel, ws, stream));
+    return EJOIN_OK;
+}
 
 }  // extern "C"

@@ -2,6 +2,8 @@
 // training step and inference.
 #include <hip/hip_runtime.h>
 
+#include <stdio.h>
+
 #include <vector>
 
 #include "batch.hpp"
@@ -247,6 +249,79 @@ void ejoin_mlp_hparams_default(ejoin_mlp_hparams* hp) {
     hp->lambda = 4.0f;
     hp->theta_lo = 0.7f;
     hp->flags = 0;
+}
+
+// ---- checkpoints: masters, Adam moments and step count in a host file ----
+namespace {
+constexpr char kCkptMagic[8] = {'E', 'J', 'P', 'F', 'N', 'E', 'T', '1'};
+struct CkptHead {
+    char magic[8];
+    int32_t dim, reserved;
+    int64_t n_params, step;
+    float eps;
+    uint32_t pad;
+    uint64_t seed;
+};
+static_assert(sizeof(CkptHead) == 48, "checkpoint header layout");
+}  // namespace
+
+ejoin_status ejoin_prefilter_save(const void* state, int32_t dim, float eps, uint64_t seed,
+                                  const char* path, hipStream_t stream) {
+    ejoin_mlp_layout L;
+    if (!state || !path || !layout_of(dim, L)) return EJOIN_E_INVAL;
+    const size_t n = (size_t)L.n_params;
+    std::vector<float> buf(3 * n);
+    CkptHead h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, kCkptMagic, 8);
+    h.dim = dim;
+    h.n_params = L.n_params;
+    h.eps = eps;
+    h.seed = seed;
+    const char* b = (const char*)state;
+    HIP_TRY(hipMemcpyAsync(buf.data(), b + L.off_params, n * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(buf.data() + n, b + L.off_m, n * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(buf.data() + 2 * n, b + L.off_v, n * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(&h.step, b + L.off_step, 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    FILE* f = fopen(path, "wb");
+    if (!f) return EJOIN_E_INVAL;
+    const bool ok = fwrite(&h, sizeof(h), 1, f) == 1 && fwrite(buf.data(), 4, 3 * n, f) == 3 * n;
+    if (fclose(f) != 0 || !ok) return EJOIN_E_INVAL;
+    return EJOIN_OK;
+}
+
+ejoin_status ejoin_prefilter_load(void* state, int32_t dim, const char* path, float* eps,
+                                  uint64_t* seed, hipStream_t stream) {
+    ejoin_mlp_layout L;
+    if (!state || !path || !layout_of(dim, L)) return EJOIN_E_INVAL;
+    FILE* f = fopen(path, "rb");
+    if (!f) return EJOIN_E_INVAL;
+    CkptHead h;
+    const size_t n = (size_t)L.n_params;
+    std::vector<float> buf(3 * n);
+    bool ok = fread(&h, sizeof(h), 1, f) == 1 && memcmp(h.magic, kCkptMagic, 8) == 0 &&
+              h.dim == dim && h.n_params == L.n_params && h.step >= 0 &&
+              fread(buf.data(), 4, 3 * n, f) == 3 * n;
+    if (ok) {  // nothing may follow the three vectors
+        char extra;
+        ok = fread(&extra, 1, 1, f) == 0;
+    }
+    fclose(f);
+    if (!ok) return EJOIN_E_INVAL;
+    for (size_t i = 0; i < 3 * n; ++i)
+        if (!isfinite(buf[i])) return EJOIN_E_NONFINITE;
+    char* b = (char*)state;
+    const MlpDev m = dev_of(state, L);
+    HIP_TRY(hipMemcpyAsync(b + L.off_params, buf.data(), n * 4, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(b + L.off_m, buf.data() + n, n * 4, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(b + L.off_v, buf.data() + 2 * n, n * 4, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(b + L.off_step, &h.step, 8, hipMemcpyHostToDevice, stream));
+    HIP_TRY(launch_mlp_restored(m, stream));
+    HIP_TRY(hipStreamSynchronize(stream));  // the host buffers go out of scope
+    if (eps) *eps = h.eps;
+    if (seed) *seed = h.seed;
+    return EJOIN_OK;
 }
 
 ejoin_status ejoin_mlp_init(void* state, int32_t dim, const float* params, hipStream_t stream) {

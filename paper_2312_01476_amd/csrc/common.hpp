@@ -30,7 +30,8 @@ enum : int {
     H_COUNT = 32      // header size in int64 (256 bytes)
 };
 
-enum : uint32_t { F_NONFINITE = 1u, F_RANGE = 2u };
+enum : uint32_t { F_NONFINITE = 1u, F_RANGE = 2u, F_BADSEL = 4u };  // F_BADSEL: a selection id
+                                                                        // out of range or out of order
 
 // Per-row information written by the prep kernel.
 struct RowInfo {

@@ -23,9 +23,12 @@ const TileDesc* tile_get(int id); // nullptr if unknown
 
 hipError_t launch_zero_header(unsigned long long* hdr, hipStream_t st);
 
+// sel (may be null): output row i < rows is input row sel[i] of a relation
+// of n_src rows (ids strictly ascending; violations raise F_BADSEL)
 hipError_t launch_prep(int prec, const float* X, int64_t rows, int dim, int64_t ld, void* Xq,
                        int Kp, int64_t rows_pad, RowInfo* info, unsigned long long* hdr,
-                       int enorm_slot, hipStream_t st);
+                       int enorm_slot, hipStream_t st, const int32_t* sel = nullptr,
+                       int64_t n_src = 0);
 
 struct ThresholdArgs {
     const void* A;   // normalised R copy, rows_pad_r x Kp
@@ -104,9 +107,29 @@ hipError_t launch_topk_pilot(const TopkArgs& a, hipStream_t st);
 hipError_t launch_topk_finalize(const TopkArgs& a, hipStream_t st);
 hipError_t launch_topk_fallback(const TopkArgs& a, int64_t n_fb, hipStream_t st);
 
+// sel_r / sel_s (may be null): band entries hold selection positions; the
+// FP64 rule reads the caller's rows sel[position]
 hipError_t launch_rescore_band(const float* R, int64_t ldR, const float* S, int64_t ldS, int dim,
                                const int2* band, int64_t band_cap, double theta, Pair* out,
-                               int64_t capacity, unsigned long long* hdr, hipStream_t st);
+                               int64_t capacity, unsigned long long* hdr, hipStream_t st,
+                               const int32_t* sel_r = nullptr, const int32_t* sel_s = nullptr);
+// Rewrite the first min(count, capacity) emitted pairs from selection
+// positions to the caller's row ids (a null selection keeps its side).
+hipError_t launch_map_pairs(Pair* out, int64_t capacity, const unsigned long long* hdr,
+                            const int32_t* sel_r, const int32_t* sel_s, hipStream_t st);
+// Copy the selected rows (ids strictly ascending, in [0, n_src)) into a
+// compact row-major buffer (ld = dim); violations raise F_BADSEL.
+hipError_t launch_gather_rows(const float* X, int64_t ld, int dim, const int32_t* sel, int64_t n,
+                              int64_t n_src, float* dst, unsigned long long* hdr, hipStream_t st);
+// Top-k output indices from selection positions (n_sel of them) to the
+// caller's S ids; skipped after a failed input check (flags in hdr).
+hipError_t launch_map_topk(int32_t* idx, int64_t n, const int32_t* sel_s, int64_t n_sel,
+                           const unsigned long long* hdr, hipStream_t st);
+// sigma(lo <= col[i] < hi) as a strictly ascending id list: counts per
+// block, a scan, then a stable write; n_sel is a device int64.
+size_t select_range_workspace();
+hipError_t launch_select_range(const float* col, int64_t n, float lo, float hi, int32_t* ids,
+                               int64_t* n_sel, void* ws, hipStream_t st);
 
 hipError_t launch_copy_count(const unsigned long long* hdr, int64_t band_cap, int64_t* dst,
                              hipStream_t st);

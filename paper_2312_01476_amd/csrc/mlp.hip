@@ -233,6 +233,12 @@ hipError_t launch_mlp_init(const MlpDev& m, const float* params, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_mlp_restored(const MlpDev& m, hipStream_t st) {
+    hipLaunchKernelGGL(mlp_copy, dim3(256), dim3(256), 0, st, m.G, (const float*)nullptr, m.np);
+    hipLaunchKernelGGL(mlp_refresh, dim3(256), dim3(256), 0, st, m.P, m.dim, m.Dp, m.W1t, m.W2t);
+    return hipGetLastError();
+}
+
 hipError_t launch_mlp_train_step(const MlpDev& m, const uint16_t* X, int64_t ldx, int64_t rows,
                                  const int32_t* pr, const int32_t* ps, const float* t, int B,
                                  const MlpHyper& hp, const MlpTrainWs& w, float* loss,

@@ -40,6 +40,9 @@ struct MlpTrainWs {
 };
 
 hipError_t launch_mlp_init(const MlpDev& m, const float* params, hipStream_t st);
+// after masters, moments and step were written into the block: zero the
+// gradients and rebuild the BF16 copies
+hipError_t launch_mlp_restored(const MlpDev& m, hipStream_t st);
 hipError_t launch_mlp_train_step(const MlpDev& m, const uint16_t* X, int64_t ldx, int64_t rows,
                                  const int32_t* pr, const int32_t* ps, const float* t, int B,
                                  const MlpHyper& hp, const MlpTrainWs& w, float* loss,

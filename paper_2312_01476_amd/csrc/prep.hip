@@ -22,11 +22,11 @@ __device__ __forceinline__ float prep_one_row(const float* __restrict__ X, int64
                                               int64_t ld, void* __restrict__ Xq, int Kp,
                                               RowInfo* __restrict__ info,
                                               unsigned long long* __restrict__ hdr, int64_t row,
-                                              int64_t src, int lane) {
+                                              int64_t src, int lane, int real_ = -1) {
     float inv = 0.0f, qscale = 1.0f, enorm = 0.0f;
     uint32_t flags = 0;
     const float* x = X + src * ld;
-    const bool real = src < rows;
+    const bool real = real_ < 0 ? src < rows : real_ != 0;
 
     if (real) {
         // pass 1: finiteness and max |x|
@@ -131,11 +131,10 @@ __device__ __forceinline__ float prep_one_row(const float* __restrict__ X, int64
 constexpr int kRegMax = 1024;
 constexpr int kRegNV = kRegMax / 64;
 
-__device__ __forceinline__ void load_row_reg(const float* __restrict__ X, int64_t rows, int dim,
+__device__ __forceinline__ void load_row_reg(const float* __restrict__ X, bool real, int dim,
                                              int64_t ld, int64_t src, int lane,
                                              float (&xv)[kRegNV]) {
     const float* x = X + src * ld;
-    const bool real = src < rows;
 #pragma unroll
     for (int j = 0; j < kRegNV; ++j) {
         const int k = lane + 64 * j;
@@ -245,7 +244,7 @@ __device__ __forceinline__ float prep_row_reg(const float* __restrict__ X, int64
                                               unsigned long long* __restrict__ hdr, int64_t row,
                                               int64_t src, int lane) {
     float xv[kRegNV];
-    load_row_reg(X, rows, dim, ld, src, lane, xv);
+    load_row_reg(X, src < rows, dim, ld, src, lane, xv);
     return prep_row_regs<PREC>(xv, src < rows, dim, Xq, Kp, info, hdr, row, lane);
 }
 
@@ -261,13 +260,33 @@ __device__ __forceinline__ float prep_row(const float* __restrict__ X, int64_t r
 }
 
 // One wave per row, grid-stride.
+// With a selection (sel != nullptr) output row i < rows is input row sel[i]
+// of a relation of n_src rows; the ids must be strictly ascending and in
+// range, else the row is prepared as a zero row and F_BADSEL is raised.
+__device__ __forceinline__ int64_t sel_source(const int32_t* __restrict__ sel, int64_t n_src,
+                                              int64_t row, int64_t rows,
+                                              unsigned long long* __restrict__ hdr, int lane,
+                                              bool& real) {
+    real = row < rows;
+    if (!sel || !real) return row;
+    const int64_t id = sel[row];
+    const bool ok = id >= 0 && id < n_src && (row == 0 || (int64_t)sel[row - 1] < id);
+    if (!ok) {
+        if (lane == 0) atomicOr(hdr + H_FLAGS, (unsigned long long)F_BADSEL);
+        real = false;
+        return 0;
+    }
+    return id;
+}
+
 template <int PREC>
 __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, int64_t rows,
                                                  int dim, int64_t ld, void* __restrict__ Xq,
                                                  int Kp, int64_t rows_pad,
                                                  RowInfo* __restrict__ info,
                                                  unsigned long long* __restrict__ hdr,
-                                                 int enorm_slot) {
+                                                 int enorm_slot, const int32_t* __restrict__ sel,
+                                                 int64_t n_src) {
     const int lane = threadIdx.x & 63;
     float wave_emax = 0.0f;  // largest error norm seen by this wave
     const int64_t first = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -276,19 +295,30 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
         // rows in registers; the wave's next row is loaded before the
         // current one is reduced and written
         float xa[kRegNV], xb[kRegNV];
-        if (first < rows_pad) load_row_reg(X, rows, dim, ld, first, lane, xa);
+        bool ra = false, rb = false;
+        if (first < rows_pad) {
+            const int64_t s0 = sel_source(sel, n_src, first, rows, hdr, lane, ra);
+            load_row_reg(X, ra, dim, ld, s0, lane, xa);
+        }
         for (int64_t row = first; row < rows_pad; row += stride) {
             const int64_t next = row + stride;
-            if (next < rows_pad) load_row_reg(X, rows, dim, ld, next, lane, xb);
-            wave_emax = fmaxf(wave_emax, prep_row_regs<PREC>(xa, row < rows, dim, Xq, Kp, info,
-                                                             hdr, row, lane));
+            if (next < rows_pad) {
+                const int64_t s1 = sel_source(sel, n_src, next, rows, hdr, lane, rb);
+                load_row_reg(X, rb, dim, ld, s1, lane, xb);
+            }
+            wave_emax = fmaxf(wave_emax, prep_row_regs<PREC>(xa, ra, dim, Xq, Kp, info, hdr,
+                                                             row, lane));
 #pragma unroll
             for (int j = 0; j < kRegNV; ++j) xa[j] = xb[j];
+            ra = rb;
         }
     } else {
-        for (int64_t row = first; row < rows_pad; row += stride)
+        for (int64_t row = first; row < rows_pad; row += stride) {
+            bool real;
+            const int64_t src = sel_source(sel, n_src, row, rows, hdr, lane, real);
             wave_emax = fmaxf(wave_emax, prep_one_row<PREC>(X, rows, dim, ld, Xq, Kp, info, hdr,
-                                                            row, row, lane));
+                                                            row, src, lane, real ? 1 : 0));
+        }
     }
     // one atomic per workgroup for the maximum error norm
     __shared__ float s_emax[4];
@@ -333,7 +363,8 @@ __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ 
     float xa[kRegNV], xb[kRegNV];
     if (regs) {
         const PrepSeg& g = segs[sa];
-        load_row_reg(g.X, g.rows, g.dim, g.ld, src_of(g, first - g.row_base), lane, xa);
+        const int64_t s0 = src_of(g, first - g.row_base);
+        load_row_reg(g.X, s0 < g.rows, g.dim, g.ld, s0, lane, xa);
     }
     for (int64_t row = first; row < n; row += stride) {
         const PrepSeg& g = segs[sa];
@@ -348,7 +379,10 @@ __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ 
             while (sb + 1 < nseg && segs[sb + 1].row_base <= next) ++sb;
             const PrepSeg& h = segs[sb];
             nregs = h.Kp <= kRegMax;
-            if (nregs) load_row_reg(h.X, h.rows, h.dim, h.ld, src_of(h, next - h.row_base), lane, xb);
+            if (nregs) {
+                const int64_t s1 = src_of(h, next - h.row_base);
+                load_row_reg(h.X, s1 < h.rows, h.dim, h.ld, s1, lane, xb);
+            }
         }
         const int64_t src = src_of(g, r);
         if (regs)
@@ -419,7 +453,7 @@ hipError_t launch_zero_header(unsigned long long* hdr, hipStream_t st) {
 
 hipError_t launch_prep(int prec, const float* X, int64_t rows, int dim, int64_t ld, void* Xq,
                        int Kp, int64_t rows_pad, RowInfo* info, unsigned long long* hdr,
-                       int enorm_slot, hipStream_t st) {
+                       int enorm_slot, hipStream_t st, const int32_t* sel, int64_t n_src) {
     if (rows_pad <= 0) return hipSuccess;
     int64_t nb = (rows_pad + 3) / 4;
     if (nb > 4096) nb = 4096;  // 16 workgroups per CU, a few rows per wave
@@ -427,15 +461,15 @@ hipError_t launch_prep(int prec, const float* X, int64_t rows, int dim, int64_t 
     switch (prec) {
         case P_FP32:
             hipLaunchKernelGGL(prep_rows<P_FP32>, grid, block, 0, st, X, rows, dim, ld, Xq, Kp,
-                               rows_pad, info, hdr, enorm_slot);
+                               rows_pad, info, hdr, enorm_slot, sel, n_src);
             break;
         case P_BF16:
             hipLaunchKernelGGL(prep_rows<P_BF16>, grid, block, 0, st, X, rows, dim, ld, Xq, Kp,
-                               rows_pad, info, hdr, enorm_slot);
+                               rows_pad, info, hdr, enorm_slot, sel, n_src);
             break;
         default:
             hipLaunchKernelGGL(prep_rows<P_FP8>, grid, block, 0, st, X, rows, dim, ld, Xq, Kp,
-                               rows_pad, info, hdr, enorm_slot);
+                               rows_pad, info, hdr, enorm_slot, sel, n_src);
             break;
     }
     return hipGetLastError();

@@ -94,7 +94,9 @@ __global__ __launch_bounds__(256) void rescore_band(const float* __restrict__ R,
                                                     int dim, const int2* __restrict__ band,
                                                     int64_t band_cap, double theta,
                                                     Pair* __restrict__ out, int64_t capacity,
-                                                    unsigned long long* __restrict__ hdr) {
+                                                    unsigned long long* __restrict__ hdr,
+                                                    const int32_t* __restrict__ sel_r,
+                                                    const int32_t* __restrict__ sel_s) {
     if (hdr[H_FLAGS] != 0) return;
     __shared__ float s_rows[4][64 * kPairStride];
     float* lds = s_rows[threadIdx.x >> 6];
@@ -108,7 +110,9 @@ __global__ __launch_bounds__(256) void rescore_band(const float* __restrict__ R,
         double sim = 0.0;
         int2 e = make_int2(0, 0);
         if (p < n) e = band[p];
-        sim = wave_sim64(R + (int64_t)e.x * ldR, S + (int64_t)e.y * ldS, dim, p < n, lds);
+        const int64_t ri = (p < n && sel_r) ? (int64_t)sel_r[e.x] : (int64_t)e.x;
+        const int64_t si = (p < n && sel_s) ? (int64_t)sel_s[e.y] : (int64_t)e.y;
+        sim = wave_sim64(R + ri * ldR, S + si * ldS, dim, p < n, lds);
         acc = p < n && sim >= theta;
         const uint64_t m = __ballot(acc);
         if (m) {
@@ -137,12 +141,94 @@ __global__ __launch_bounds__(256) void rescore_band(const float* __restrict__ R,
 
 hipError_t launch_rescore_band(const float* R, int64_t ldR, const float* S, int64_t ldS, int dim,
                                const int2* band, int64_t band_cap, double theta, Pair* out,
-                               int64_t capacity, unsigned long long* hdr, hipStream_t st) {
+                               int64_t capacity, unsigned long long* hdr, hipStream_t st,
+                               const int32_t* sel_r, const int32_t* sel_s) {
     if (band_cap <= 0) return hipSuccess;
     int64_t blocks = (band_cap + 255) / 256;
     if (blocks > 2048) blocks = 2048;
     hipLaunchKernelGGL(rescore_band, dim3((unsigned)blocks), dim3(256), 0, st, R, ldR, S, ldS, dim,
-                       band, band_cap, theta, out, capacity, hdr);
+                       band, band_cap, theta, out, capacity, hdr, sel_r, sel_s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// selections pushed below the join: offsets back to the caller's row ids
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void map_pairs(Pair* __restrict__ out, int64_t capacity,
+                                                 const unsigned long long* __restrict__ hdr,
+                                                 const int32_t* __restrict__ sel_r,
+                                                 const int32_t* __restrict__ sel_s) {
+    if (hdr[H_FLAGS] != 0) return;
+    const int64_t n = min((int64_t)hdr[H_OUT], capacity);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        Pair p = out[q];
+        if (sel_r) p.r = sel_r[p.r];
+        if (sel_s) p.s = sel_s[p.s];
+        out[q] = p;
+    }
+}
+
+hipError_t launch_map_pairs(Pair* out, int64_t capacity, const unsigned long long* hdr,
+                            const int32_t* sel_r, const int32_t* sel_s, hipStream_t st) {
+    if (capacity <= 0 || (!sel_r && !sel_s)) return hipSuccess;
+    int64_t blocks = (capacity + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(map_pairs, dim3((unsigned)blocks), dim3(256), 0, st, out, capacity, hdr,
+                       sel_r, sel_s);
+    return hipGetLastError();
+}
+
+// one wave per selected row: check the id, copy the row
+__global__ __launch_bounds__(256) void gather_rows(const float* __restrict__ X, int64_t ld, int dim,
+                                                   const int32_t* __restrict__ sel, int64_t n,
+                                                   int64_t n_src, float* __restrict__ dst,
+                                                   unsigned long long* __restrict__ hdr) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n;
+         i += (int64_t)gridDim.x * 4) {
+        const int64_t id = sel[i];
+        const bool ok = id >= 0 && id < n_src && (i == 0 || (int64_t)sel[i - 1] < id);
+        float* d = dst + i * (int64_t)dim;
+        if (!ok) {
+            if (lane == 0) atomicOr(hdr + H_FLAGS, (unsigned long long)F_BADSEL);
+            for (int k = lane; k < dim; k += 64) d[k] = 0.0f;
+            continue;
+        }
+        const float* x = X + id * ld;
+        for (int k = lane; k < dim; k += 64) d[k] = x[k];
+    }
+}
+
+hipError_t launch_gather_rows(const float* X, int64_t ld, int dim, const int32_t* sel, int64_t n,
+                              int64_t n_src, float* dst, unsigned long long* hdr, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 3) / 4;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(gather_rows, dim3((unsigned)blocks), dim3(256), 0, st, X, ld, dim, sel, n,
+                       n_src, dst, hdr);
+    return hipGetLastError();
+}
+
+// After a failed input check the outputs were never written: nothing runs.
+__global__ __launch_bounds__(256) void map_topk(int32_t* __restrict__ idx, int64_t n,
+                                                const int32_t* __restrict__ sel_s, int64_t n_sel,
+                                                const unsigned long long* __restrict__ hdr) {
+    if (hdr[H_FLAGS] != 0) return;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = idx[q];
+        if (j >= 0 && j < n_sel) idx[q] = sel_s[j];
+    }
+}
+
+hipError_t launch_map_topk(int32_t* idx, int64_t n, const int32_t* sel_s, int64_t n_sel,
+                           const unsigned long long* hdr, hipStream_t st) {
+    if (n <= 0 || !sel_s) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(map_topk, dim3((unsigned)blocks), dim3(256), 0, st, idx, n, sel_s, n_sel,
+                       hdr);
     return hipGetLastError();
 }
 
@@ -258,7 +344,8 @@ hipError_t launch_train_targets(const TrainJob* jobs, const int4* samples, int B
 __global__ void copy_count(const unsigned long long* hdr, int64_t band_cap, int64_t* dst) {
     if (threadIdx.x != 0) return;
     int64_t v = (int64_t)hdr[H_OUT];
-    if (hdr[H_FLAGS] & F_NONFINITE) v = -4;             // EJOIN_E_NONFINITE
+    if (hdr[H_FLAGS] & F_BADSEL) v = -1;                // EJOIN_E_INVAL
+    else if (hdr[H_FLAGS] & F_NONFINITE) v = -4;        // EJOIN_E_NONFINITE
     else if (hdr[H_FLAGS] & F_RANGE) v = -7;            // EJOIN_E_RANGE
     else if ((int64_t)hdr[H_BAND] > band_cap) v = -3;   // EJOIN_E_WORKSPACE
     dst[0] = v;

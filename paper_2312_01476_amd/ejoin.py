@@ -32,6 +32,10 @@ class Opts(C.Structure):
                 ("tuner", C.c_void_p), ("prefilter", C.c_void_p), ("prefilter_eps", C.c_float)]
 
 
+class Sel(C.Structure):
+    _fields_ = [("ids", C.c_void_p), ("n", C.c_int64)]
+
+
 class Job(C.Structure):
     _fields_ = [("R", Rel), ("S", Rel), ("theta", C.c_double), ("out", C.c_void_p),
                 ("capacity", C.c_int64)]
@@ -90,6 +94,24 @@ def lib():
                                               C.c_int64, P(C.c_int64), C.c_void_p, P(Stats)]
         L.ejoin_noalloc_scratch_bytes.restype = C.c_size_t
         L.ejoin_noalloc_scratch_bytes.argtypes = []
+        L.ejoin_select_workspace.restype = C.c_size_t
+        L.ejoin_select_workspace.argtypes = []
+        L.ejoin_select_range.restype = C.c_int
+        L.ejoin_select_range.argtypes = [C.c_void_p, C.c_int64, C.c_float, C.c_float, C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.ejoin_threshold_sel_workspace.restype = C.c_size_t
+        L.ejoin_threshold_sel_workspace.argtypes = [P(Rel), P(Sel), P(Rel), P(Sel), P(Opts)]
+        L.ejoin_threshold_sel.restype = C.c_int
+        L.ejoin_threshold_sel.argtypes = [P(Rel), P(Sel), P(Rel), P(Sel), C.c_double, P(Opts),
+                                          C.c_void_p, C.c_int64, P(C.c_int64), C.c_void_p,
+                                          C.c_size_t, C.c_void_p, P(Stats)]
+        L.ejoin_topk_sel_workspace.restype = C.c_size_t
+        L.ejoin_topk_sel_workspace.argtypes = [P(Rel), P(Sel), P(Rel), P(Sel), C.c_int32,
+                                               P(Opts)]
+        L.ejoin_topk_sel.restype = C.c_int
+        L.ejoin_topk_sel.argtypes = [P(Rel), P(Sel), P(Rel), P(Sel), C.c_int32, P(Opts),
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
+                                     P(Stats)]
         L.ejoin_topk_workspace.restype = C.c_size_t
         L.ejoin_topk_workspace.argtypes = [P(Rel), P(Rel), C.c_int32, P(Opts)]
         L.ejoin_topk.restype = C.c_int
@@ -317,6 +339,137 @@ def topk(R, S, k: int, *, d=None, prec="bf16", topk_cand=0, timing=False, stream
 
 
 # ---------------------------------------------------------------------------
+# relational selections pushed below the join
+# ---------------------------------------------------------------------------
+
+def _sel(ids):
+    """ids: None (every row) or an int32 CUDA tensor of ascending row ids."""
+    import torch
+    if ids is None:
+        return None
+    if not isinstance(ids, torch.Tensor) or ids.device.type != "cuda" or \
+            ids.dtype != torch.int32 or ids.dim() != 1 or (ids.numel() > 1 and ids.stride(0) != 1):
+        raise TypeError("a selection is a contiguous 1-D int32 CUDA tensor of row ids")
+    return Sel(ids.data_ptr() if ids.numel() else None, ids.numel())
+
+
+def _ref(x):
+    return C.byref(x) if x is not None else None
+
+
+def select_range(col, lo, hi, *, stream=None):
+    """Row ids i (ascending) with lo <= col[i] < hi, computed on the device.
+    Returns an int32 CUDA tensor."""
+    import torch
+    if col.dtype != torch.float32 or col.dim() != 1 or col.device.type != "cuda":
+        raise TypeError("col must be a 1-D float32 CUDA tensor")
+    col = col.contiguous()
+    n = col.numel()
+    ids = torch.empty(max(n, 1), dtype=torch.int32, device=col.device)
+    n_sel = torch.zeros(1, dtype=torch.int64, device=col.device)
+    ws = torch.empty(lib().ejoin_select_workspace(), dtype=torch.uint8, device=col.device)
+    rc = lib().ejoin_select_range(C.c_void_p(col.data_ptr() if n else 0), n, float(lo),
+                                  float(hi), C.c_void_p(ids.data_ptr()),
+                                  C.c_void_p(n_sel.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                  ws.numel(), _stream(stream))
+    if rc != OK:
+        raise EjoinError(rc, "ejoin_select_range")
+    return ids[:int(n_sel.item())]
+
+
+def threshold_sel_raw(R, sel_r, S, sel_s, theta, out, capacity, ws, *, d=None, prec="fp32",
+                      band=None, tile=0, band_capacity=0, flags=0, stream=None, n_out_dev=None):
+    """One ejoin_threshold_sel call on caller buffers.  Returns (status,
+    n_out, stats dict)."""
+    r, s = _rel(R, d), _rel(S, d)
+    a, b = _sel(sel_r), _sel(sel_s)
+    o = _opts(prec, band, tile, band_capacity, flags)
+    st = Stats()
+    n = C.c_int64(0)
+    if flags & NO_SYNC:
+        nptr = C.cast(C.c_void_p(n_out_dev.data_ptr()), C.POINTER(C.c_int64))
+    else:
+        nptr = C.byref(n)
+    rc = lib().ejoin_threshold_sel(C.byref(r), _ref(a), C.byref(s), _ref(b), float(theta),
+                                   C.byref(o), C.c_void_p(out.data_ptr() if capacity > 0 else 0),
+                                   int(capacity), nptr, C.c_void_p(ws.data_ptr()),
+                                   int(ws.numel()), _stream(stream), C.byref(st))
+    return rc, int(n.value), st.as_dict()
+
+
+def threshold_sel_workspace(R, sel_r, S, sel_s, *, d=None, prec="fp32", band=None, tile=0,
+                            band_capacity=0):
+    r, s = _rel(R, d), _rel(S, d)
+    a, b = _sel(sel_r), _sel(sel_s)
+    o = _opts(prec, band, tile, band_capacity, 0)
+    n = lib().ejoin_threshold_sel_workspace(C.byref(r), _ref(a), C.byref(s), _ref(b),
+                                            C.byref(o))
+    if n == 0:
+        raise EjoinError(E_INVAL, "ejoin_threshold_sel_workspace")
+    return int(n)
+
+
+def threshold_sel(R, sel_r, S, sel_s, theta: float, *, d=None, prec="fp32", band=None, tile=0,
+                  capacity=None, band_capacity=0, timing=False, stream=None) -> Pairs:
+    """Threshold join restricted to the selected rows (row ids in the
+    result); grows buffers and retries like ``threshold``."""
+    import torch
+    dev = R.device
+    nR = R.shape[0] if sel_r is None else sel_r.numel()
+    nS = S.shape[0] if sel_s is None else sel_s.numel()
+    if capacity is None:
+        capacity = max(1 << 16, min(nR * nS, (nR + nS) * 64))
+    flags = TIMING if timing else 0
+    for _ in range(4):
+        ws = torch.empty(threshold_sel_workspace(R, sel_r, S, sel_s, d=d, prec=prec, band=band,
+                                                 tile=tile, band_capacity=band_capacity),
+                         dtype=torch.uint8, device=dev)
+        out = torch.empty((max(capacity, 1), 3), dtype=torch.int32, device=dev)
+        rc, n, st = threshold_sel_raw(R, sel_r, S, sel_s, theta, out, capacity, ws, d=d,
+                                      prec=prec, band=band, tile=tile,
+                                      band_capacity=band_capacity, flags=flags, stream=stream)
+        if rc == OK:
+            o = out[:n]
+            return Pairs(o[:, 0], o[:, 1], o[:, 2].view(torch.float32), st)
+        if rc == E_OVERFLOW:
+            capacity = n
+            continue
+        if rc == E_WORKSPACE and st["band_needed"] > 0:
+            band_capacity = int(st["band_needed"] * 1.25) + 1024
+            continue
+        raise EjoinError(rc, "ejoin_threshold_sel")
+    raise EjoinError(rc, "ejoin_threshold_sel (retries exhausted)")
+
+
+def topk_sel(R, sel_r, S, sel_s, k: int, *, d=None, prec="bf16", topk_cand=0, timing=False,
+             flags=0, stream=None):
+    """Top-k over the selected rows: output row i is the i-th selected R row;
+    indices are S row ids.  Returns (idx, score, stats)."""
+    import torch
+    dev = R.device
+    r, s = _rel(R, d), _rel(S, d)
+    a, b = _sel(sel_r), _sel(sel_s)
+    o = _opts(prec, None, 0, 0, flags | (TIMING if timing else 0), topk_cand)
+    L = lib()
+    need = L.ejoin_topk_sel_workspace(C.byref(r), _ref(a), C.byref(s), _ref(b), int(k),
+                                      C.byref(o))
+    if need == 0:
+        raise EjoinError(E_INVAL, "ejoin_topk_sel_workspace")
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    nR = R.shape[0] if sel_r is None else sel_r.numel()
+    idx = torch.empty((nR, k), dtype=torch.int32, device=dev)
+    sc = torch.empty((nR, k), dtype=torch.float32, device=dev)
+    st = Stats()
+    rc = L.ejoin_topk_sel(C.byref(r), _ref(a), C.byref(s), _ref(b), int(k), C.byref(o),
+                          C.c_void_p(idx.data_ptr() if idx.numel() else 0),
+                          C.c_void_p(sc.data_ptr() if sc.numel() else 0),
+                          C.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream), C.byref(st))
+    if rc != OK:
+        raise EjoinError(rc, "ejoin_topk_sel")
+    return idx, sc, st.as_dict()
+
+
+# ---------------------------------------------------------------------------
 # batched threshold joins
 # ---------------------------------------------------------------------------
 
@@ -532,6 +685,42 @@ def _mlp_sigs(L):
     L.ejoin_mlp_forward.restype = C.c_int
     L.ejoin_mlp_forward.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
                                     C.c_void_p, C.c_size_t, C.c_void_p]
+
+
+def _ckpt_sigs(L):
+    if hasattr(L, "_ckpt_sigs"):
+        return
+    L.ejoin_prefilter_save.restype = C.c_int
+    L.ejoin_prefilter_save.argtypes = [C.c_void_p, C.c_int32, C.c_float, C.c_uint64, C.c_char_p,
+                                       C.c_void_p]
+    L.ejoin_prefilter_load.restype = C.c_int
+    L.ejoin_prefilter_load.argtypes = [C.c_void_p, C.c_int32, C.c_char_p,
+                                       C.POINTER(C.c_float), C.POINTER(C.c_uint64), C.c_void_p]
+    L._ckpt_sigs = True
+
+
+def prefilter_save(net, path, *, eps=0.0, seed=0, stream=None):
+    """Write the network's masters, Adam moments and step to a host file."""
+    L = lib()
+    _ckpt_sigs(L)
+    rc = L.ejoin_prefilter_save(C.c_void_p(net.state.data_ptr()), net.dim, float(eps), int(seed),
+                                str(path).encode(), _stream(stream))
+    if rc != OK:
+        raise EjoinError(rc, "ejoin_prefilter_save")
+
+
+def prefilter_load(net, path, *, stream=None):
+    """Restore a checkpoint into ``net`` (same dim).  Returns (eps, seed)."""
+    L = lib()
+    _ckpt_sigs(L)
+    eps = C.c_float(0.0)
+    seed = C.c_uint64(0)
+    rc = L.ejoin_prefilter_load(C.c_void_p(net.state.data_ptr()) if net is not None else None,
+                                net.dim if net is not None else 1, str(path).encode(),
+                                C.byref(eps), C.byref(seed), _stream(stream))
+    if rc != OK:
+        raise EjoinError(rc, "ejoin_prefilter_load")
+    return float(eps.value), int(seed.value)
 
 
 def mlp_layout(dim):

@@ -143,3 +143,33 @@ def test_tuner_file_roundtrip_and_nearest_bucket(tmp_path):
         r.write_text(line)
         with pytest.raises(E.EjoinError):
             E.Tuner().load(r)
+
+
+def test_prefilter_load_refuses_bad_files_before_touching_the_device(tmp_path):
+    """The checkpoint file is validated on the host: a missing file, a wrong
+    magic, another dim or a truncated file are EJOIN_E_INVAL without any
+    device call (the state pointer here is not device memory)."""
+    import struct
+    from paper_2312_01476_amd import ejoin as E
+    L = E.lib()
+    E._ckpt_sigs(L)
+    fake = C.c_void_p(0x1000)
+    n_params = 96 * 256 + 256 + 256 * 64 + 64
+
+    def load(path, dim=96):
+        return L.ejoin_prefilter_load(fake, dim, str(path).encode(), None, None, None)
+
+    assert load(tmp_path / "missing") == E.E_INVAL
+    head = lambda magic, dim, n: magic + struct.pack("<iiqqfIQ", dim, 0, n, 3, 0.05, 0, 7)
+    body = b"\0" * (3 * n_params * 4)
+    bad_magic = tmp_path / "m"
+    bad_magic.write_bytes(head(b"EJPFNETX", 96, n_params) + body)
+    other_dim = tmp_path / "d"
+    other_dim.write_bytes(head(b"EJPFNET1", 128, 128 * 256 + 256 + 256 * 64 + 64) + body)
+    short = tmp_path / "s"
+    short.write_bytes(head(b"EJPFNET1", 96, n_params) + body[:-4])
+    longer = tmp_path / "l"
+    longer.write_bytes(head(b"EJPFNET1", 96, n_params) + body + b"\0")
+    for p in (bad_magic, other_dim, short, longer):
+        assert load(p) == E.E_INVAL, p
+    assert L.ejoin_prefilter_load(fake, 2000, str(short).encode(), None, None, None) == E.E_INVAL

@@ -149,3 +149,39 @@ def test_forward_codes_match_reference(d, n):
     # straddle a rounding boundary: a few units of 2^-9 relative on some h
     assert np.abs(got - want).max() <= 5e-3
     assert np.mean(np.abs(got - want)) <= 2e-4
+
+
+def test_checkpoint_roundtrip_and_resume(tmp_path):
+    """save -> load into a differently initialised block: masters, moments,
+    step, BF16 copies (hence codes) identical; training continued from the
+    checkpoint equals training continued from the original."""
+    d, B = 96, 256
+    flat, net, X, Xd, pr, ps, t, (prd, psd, td) = _setup(d, 384, B, 31)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for _ in range(7):
+        net.train_step(Xd, prd, psd, td, loss)
+    path = tmp_path / "net.ejpf"
+    E.prefilter_save(net, path, eps=0.05, seed=1234)
+    other = E.Mlp(d, torch.from_numpy(G.mlp_init(d, 999)))
+    eps, seed = E.prefilter_load(other, path)
+    assert abs(eps - 0.05) < 1e-7 and seed == 1234
+    st_a, st_b = net.state.cpu().numpy(), other.state.cpu().numpy()
+    lay = net.lay
+    # everything but the gradients (zero after a load) is bitwise equal
+    g0, g1 = lay.off_grads, lay.off_m
+    assert np.array_equal(np.delete(st_a, np.s_[g0:g1]), np.delete(st_b, np.s_[g0:g1]))
+    assert not other.grads().any()
+    _, Xp = _rows_bf16(200, d, 5, pad_to=(256, lay.dim_pad))
+    ua = torch.zeros((200, 64), dtype=torch.float32, device="cuda")
+    ub = torch.zeros_like(ua)
+    net.forward(Xp, 200, ua)
+    other.forward(Xp, 200, ub)
+    assert torch.equal(ua, ub)
+    for _ in range(3):
+        net.train_step(Xd, prd, psd, td, loss)
+        other.train_step(Xd, prd, psd, td, loss)
+    assert torch.equal(net.params(), other.params())
+    # a checkpoint of another width is refused
+    wide = E.Mlp(128, torch.from_numpy(G.mlp_init(128, 1)))
+    with pytest.raises(E.EjoinError):
+        E.prefilter_load(wide, path)
