@@ -64,15 +64,16 @@ def make_inputs(w, torch):
     return Rd, Sd, None, None, lr.cpu(), ls.cpu()
 
 
-def cpu_baseline(Rh, Sh, w, budget_s=15.0):
-    """FP64 oracle on a bounded row sample of the same workload."""
+def cpu_baseline(Rh, Sh, w, budget_s=15.0, threads=0):
+    """FP64 oracle on a bounded row sample of the same workload (threads 0:
+    every host core)."""
     from oracle import oracle as O
-    threads = O.max_threads()
-    rows = 8
+    threads = threads or O.max_threads()
+    rows = 8 if threads > 1 else 1
     t = 0.0
     while True:
         t0 = time.perf_counter()
-        O.threshold(Rh[:rows], Sh, w.theta, d=w.d)
+        O.threshold(Rh[:rows], Sh, w.theta, d=w.d, threads=threads)
         t = time.perf_counter() - t0
         if t >= budget_s / 4 or rows >= Rh.shape[0]:
             break
@@ -81,7 +82,171 @@ def cpu_baseline(Rh, Sh, w, budget_s=15.0):
     return {"value": pairs / t / 1e9, "unit": "Gpairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{rows} R rows x all {Sh.shape[0]} S rows of the workload "
                       f"({pairs:.3g} pairs, {t:.1f} s, FP64 sequential dots, "
-                      f"{threads} OpenMP threads)"}
+                      f"{threads} OpenMP thread{'s' if threads > 1 else ''})"}
+
+
+def _timed(fn):
+    """Wall time of fn() in ms, with a device synchronisation on both sides."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3, r
+
+
+def extra_nlj(Rd, Sd, w, out, capacity, n_tensor, ms_tensor):
+    """The nested-loop comparator (tile 23: one pair per wavefront, no
+    tiling) on the same inputs and the same exact result rule."""
+    from paper_2312_01476_amd import ejoin as E
+    import torch
+    ws = torch.empty(E.threshold_workspace(Rd, Sd, d=w.d, tile=23), dtype=torch.uint8,
+                     device="cuda")
+    E.threshold_raw(Rd[:512], Sd[:512], w.theta, out, capacity, ws, d=w.d, tile=23)  # load
+    ms, (rc, n, st) = _timed(lambda: E.threshold_raw(Rd, Sd, w.theta, out, capacity, ws, d=w.d,
+                                                     tile=23, flags=E.TIMING))
+    if rc != E.OK:
+        raise E.EjoinError(rc, "ejoin_threshold (nlj)")
+    res = {"ms": round(ms, 2), "kernel_ms": round(st["ms_main"], 2), "pairs_out": n,
+           "same_count_as_tensor": n == n_tensor,
+           "time_ratio_nlj_over_tensor": round(ms / ms_tensor, 2),
+           "form": "one pair per wavefront, lanes over the 300 dims, no tiling (tile 23)"}
+    log(f"[bench] nlj comparator {res}")
+    return res
+
+
+def extra_bf16_1m(args):
+    """The 1M x 1M 384-d workload: the BF16 join (bulk contraction in BF16,
+    FP64 band recheck) with its roofline and sampled score error against the
+    FP64 rule, and the plain FP32 join on the same inputs for the speedup."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    from paper_2312_01476_amd import datagen as G
+    from paper_2312_01476_amd import ejoin as E
+    w = G.WORKLOADS["bf16_1m"]
+    cs, rs, ss = w.seeds
+    Rd, lr = G.clustered_points_torch(w.n_r, w.d, w.n_clusters, w.sigma, rs, cs, ld=w.ld)
+    Sd, ls = G.clustered_points_torch(w.n_s, w.d, w.n_clusters, w.sigma, ss, cs, ld=w.ld)
+    cnt_r = torch.bincount(lr, minlength=w.n_clusters).double()
+    cnt_s = torch.bincount(ls, minlength=w.n_clusters).double()
+    expected = int((cnt_r * cnt_s).sum().item())
+    capacity = int(expected * 1.05) + (1 << 20)
+    out = torch.empty((capacity, 3), dtype=torch.int32, device="cuda")
+    nb = max(E.threshold_workspace(Rd, Sd, d=w.d, prec="bf16", band=w.band),
+             E.threshold_workspace(Rd, Sd, d=w.d, prec="fp32"))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    log(f"[bench] bf16_1m inputs resident, label count {expected}")
+
+    def run(prec, flags=0, R=Rd, S=Sd):
+        rc, n, st = E.threshold_raw(R, S, w.theta, out, capacity, ws, d=w.d, prec=prec,
+                                    band=w.band if prec == "bf16" else None, flags=flags)
+        if rc != E.OK:
+            raise E.EjoinError(rc, f"ejoin_threshold ({prec})")
+        return n, st
+
+    run("bf16")
+    steps = 2
+    t = []
+    mains = []
+    for _ in range(steps):
+        ms, (n, st) = _timed(lambda: run("bf16", E.TIMING))
+        t.append(ms)
+        mains.append(st["ms_main"])
+    ms_bf16 = float(np.mean(t))
+    flops = 2.0 * w.d * w.n_r * w.n_s
+    k_ms = float(np.mean(mains))
+    tile = E.lib().ejoin_tile_name(st["tile"]).decode()
+    # sampled score error of the emitted scores against the FP64 rule
+    res = out[:n]
+    rng = np.random.Generator(np.random.PCG64(3))
+    pick = torch.from_numpy(rng.integers(0, n, size=min(n, 20000))).cuda()
+    pr = res[pick, 0].long()
+    ps = res[pick, 1].long()
+    sc = res[pick, 2].view(torch.float32).cpu().numpy().astype(np.float64)
+    Rs = Rd[pr].cpu().numpy()
+    Ss = Sd[ps].cpu().numpy()
+    i = np.arange(Rs.shape[0])
+    ref = O.sim64_pairs(Rs, Ss, i, i, d=w.d)
+    err = np.abs(sc - ref)
+    # exact set on a leading sub-block
+    sub = 2000
+    r_all = res[:, 0]
+    s_all = res[:, 1]
+    m = (r_all < sub) & (s_all < sub)
+    got = set(zip(r_all[m].cpu().tolist(), s_all[m].cpu().tolist()))
+    ori, osi, _, _ = O.threshold(Rd[:sub].cpu().numpy(), Sd[:sub].cpu().numpy(), w.theta, d=w.d)
+    same = got == set(zip(ori.tolist(), osi.tolist()))
+    n_bf16, band_pairs = n, st["n_band"]
+    # the plain FP32 join on the same inputs (one call; its kernel loaded on a sub-block)
+    run("fp32", 0, Rd[:1024], Sd[:1024])
+    ms_fp32, (n32, st32) = _timed(lambda: run("fp32", E.TIMING))
+    r = {"value": round(w.n_r * w.n_s / (ms_bf16 * 1e-3) / 1e9, 3), "unit": "Gpairs/s",
+         "ms_per_step": round(ms_bf16, 2), "steps": steps, "warmup": 1, "dtype": "bf16",
+         "config": {"workload": w.name, "n_r": w.n_r, "n_s": w.n_s, "dim": w.d,
+                    "theta": w.theta, "band": w.band, "clusters": w.n_clusters,
+                    "sigma": w.sigma, "tile": tile, "pairs_out": n_bf16,
+                    "band_pairs": band_pairs},
+         "roofline": {"bound": "mfma", "achieved": round(flops / (k_ms * 1e-3) / 1e12, 2),
+                      "peak": PEAK["bf16"][1], "unit": "TFLOP/s",
+                      "frac": round(flops / (k_ms * 1e-3) / 1e12 / PEAK["bf16"][1], 4),
+                      "traffic": None, "kernel": "panel_kernel<ThresholdEpi>",
+                      "kernel_ms": round(k_ms, 3), "algorithmic_flops_per_launch": flops},
+         "score_error_vs_fp64": {"sampled_pairs": int(err.size),
+                                 "max_abs": float(err.max()) if err.size else 0.0,
+                                 "rms": float(np.sqrt(np.mean(err ** 2))) if err.size else 0.0},
+         "verify": {"count_equals_label_count": n_bf16 == expected,
+                    "subblock": f"{sub}x{sub}", "subblock_set_equal": bool(same)},
+         "fp32_same_inputs": {"ms": round(ms_fp32, 2), "kernel_ms": round(st32["ms_main"], 2),
+                              "tile": E.lib().ejoin_tile_name(st32["tile"]).decode(),
+                              "pairs_out": n32, "same_count": n32 == n_bf16},
+         "speedup_vs_fp32_same_config": round(ms_fp32 / ms_bf16, 3)}
+    log(f"[bench] bf16_1m {r}")
+    del out, ws, Rd, Sd
+    torch.cuda.empty_cache()
+    return r
+
+
+def extra_selectivity(args):
+    """The paper's pre-filter sweep on the scan side: a range predicate on a
+    relational attribute of S keeps 1-100% of its rows (evaluated on the
+    device), then the FP32 E-join of 10k queries with the kept rows, for the
+    range predicate sim >= 0.9 and top-1 / top-32."""
+    import torch
+    from paper_2312_01476_amd import datagen as G
+    from paper_2312_01476_amd import ejoin as E
+    w = G.WORKLOADS["sel_10k_1m"]
+    cs, rs, ss = w.seeds
+    Rd, _ = G.clustered_points_torch(w.n_r, w.d, w.n_clusters, w.sigma, rs, cs, ld=w.ld)
+    Sd, _ = G.clustered_points_torch(w.n_s, w.d, w.n_clusters, w.sigma, ss, cs, ld=w.ld)
+    attr = G.attribute_column_torch(w.n_s, w.extra["attr_seed"])
+    points = []
+    # kernels loaded once outside the timings
+    ids = E.select_range(attr, 0.0, 0.01)
+    E.threshold_sel(Rd, None, Sd, ids, w.theta, d=w.d)
+    E.topk_sel(Rd, None, Sd, ids, 1, d=w.d, prec="fp32")
+    E.topk_sel(Rd, None, Sd, ids, 32, d=w.d, prec="fp32")
+    for sel in (0.01, 0.1, 0.5, 1.0):
+        ms_sel, ids = _timed(lambda: E.select_range(attr, 0.0, sel))
+        kept = int(ids.numel())
+        pairs = w.n_r * kept
+        ms_range, res = _timed(lambda: E.threshold_sel(Rd, None, Sd, ids, w.theta, d=w.d))
+        ms_t1, _ = _timed(lambda: E.topk_sel(Rd, None, Sd, ids, 1, d=w.d, prec="fp32"))
+        ms_t32, _ = _timed(lambda: E.topk_sel(Rd, None, Sd, ids, 32, d=w.d, prec="fp32"))
+        pt = {"selectivity": sel, "kept_rows": kept, "select_ms": round(ms_sel, 3),
+              "range_ms": round(ms_range, 2), "range_pairs_out": len(res),
+              "top1_ms": round(ms_t1, 2), "top32_ms": round(ms_t32, 2),
+              "range_gpairs_s": round(pairs / (ms_range * 1e-3) / 1e9, 1)}
+        points.append(pt)
+        log(f"[bench] selectivity {pt}")
+    ms_plain, res = _timed(lambda: E.threshold(Rd, Sd, w.theta, d=w.d))
+    r = {"config": {"workload": w.name, "n_r": w.n_r, "n_s": w.n_s, "dim": w.d,
+                    "prec": "fp32", "theta": w.theta, "predicate": "attr < selectivity on S"},
+         "points": points, "no_selection_range_ms": round(ms_plain, 2),
+         "no_selection_pairs_out": len(res)}
+    del Rd, Sd, attr
+    torch.cuda.empty_cache()
+    return r
 
 
 def main():
@@ -98,6 +263,9 @@ def main():
                     help="batched workloads: time every tile first and use the fastest")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-verify", action="store_true", help="skip the sampled parity check")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: skip the nested-loop comparator, the 1M x 1M "
+                         "BF16 line with its same-input FP32 speedup and the selectivity sweep")
     ap.add_argument("--theta", type=float, default=None,
                     help="threshold workloads, diagnostic: another theta (e.g. 0.999 for a "
                          "run without result pairs); the line then reports the changed config")
@@ -216,12 +384,22 @@ def main():
                   "sampled_max_abs_score_err": err}
         log(f"[bench] verify {verify}")
 
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu:
         Rh_ = Rh if Rh is not None else Rd[:4096].cpu().numpy()
         Sh_ = Sh if Sh is not None else Sd.cpu().numpy()
         cpu = cpu_baseline(Rh_, Sh_, w)
         log(f"[bench] cpu baseline {cpu}")
+        cpu1 = cpu_baseline(Rh_, Sh_, w, budget_s=8.0, threads=1)
+        log(f"[bench] cpu baseline, one core {cpu1}")
+
+    extras = {}
+    if w.name == "fp32_100k" and not diagnostic and not args.no_extras:
+        extras["nlj_comparator"] = extra_nlj(Rd, Sd, w, out, capacity, n, ms)
+        del out
+        torch.cuda.empty_cache()
+        extras["bf16_1m"] = extra_bf16_1m(args)
+        extras["selectivity_sweep"] = extra_selectivity(args)
 
     line = {
         "metric": "Gpairs/s similarity-join throughput at exact result set",
@@ -243,7 +421,9 @@ def main():
                    **({"diagnostic": True} if diagnostic else {})},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cpu_baseline_1core": cpu1,
         "verify": verify,
+        **extras,
     }
     print(json.dumps(line), flush=True)
 

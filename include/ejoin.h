@@ -164,6 +164,11 @@ size_t ejoin_threshold_workspace(const ejoin_rel *R, const ejoin_rel *S,
  *             FP32 in one / two) take rows of at most 768 bytes of padded K,
  *             tiles 12, 14, 20 and 21 also of 1024, 1152, 1280 or 1536 bytes;
  *             other depths give EJOIN_E_INVAL; 19 and 22 are batch-only.
+ *             Tile 23 (FP32, dim <= 1024) is the nested-loop comparator of
+ *             Section V.A: one pair per wavefront, the lanes splitting the
+ *             dimension, no tiling and no matrix cores; same exact result,
+ *             only for measuring the tensor form against it (never chosen
+ *             by the planner or the tuner).
  *   out       device array of `capacity` pairs; order of pairs is unspecified.
  *   n_out     (host) receives the number of matching pairs, or, with
  *             EJOIN_NO_SYNC, a DEVICE int64 that will hold it.
@@ -220,7 +225,12 @@ size_t ejoin_topk_workspace(const ejoin_rel *R, const ejoin_rel *S, int32_t k,
  *              exact in all three.  Rows of up to six 128-byte K slices (BF16
  *              and FP32 also 8, 9, 10 or 12) sweep on register panels, other
  *              depths on the 128 x 128 LDS tile kernel (stats->tile names the
- *              form).
+ *              form).  The panels give each workgroup all of S for 128 R rows,
+ *              so the planner (opts->tile 0) takes them for |R| >= 65536 and
+ *              the tile kernel below that; opts->tile forces the form: a
+ *              panel tile of the precision (12-15, 20, 21; rows of a depth
+ *              with a panel form) or its 128 x 128 tile (1 FP32, 3 BF16,
+ *              5 FP8); other ids give EJOIN_E_INVAL.
  *   opts->topk_cand  candidate slots per row (k..256; <= 0: 256).
  * 1 <= k <= 256.  The call runs a pilot (exact FP64 top-k of up to 256 sample
  * rows) to set a candidate floor, one contraction sweep that keeps every

@@ -44,14 +44,18 @@ ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts*
         // the tuner's measured choice for this shape when it has one that fits
         const int t = o->tuner ? tuner_pick(o->tuner, 0, p.prec, p.dim, (double)p.nR * p.nS) : 0;
         const TileDesc* td = t > 0 ? tile_get(t) : nullptr;
-        const bool fits = td && td->prec == p.prec && t != 19 && t != 22 &&
+        const bool fits = td && td->prec == p.prec && t != 19 && t != 22 && t != kTileNlj &&
                           !(td->bm == 0 && !panel_fits(t, p.Kp * elem_bytes(p.prec)));
         p.tile = fits ? t : default_tile(p.prec, p.Kp);
     }
     const TileDesc* td = tile_get(p.tile);
     if (!td || td->prec != p.prec || p.tile == 19 || p.tile == 22)
         return EJOIN_E_INVAL;  // 19, 22: batches only
-    if (td->bm == 0 && !panel_fits(p.tile, p.Kp * elem_bytes(p.prec))) return EJOIN_E_INVAL;
+    if (p.tile == kTileNlj) {
+        if (p.Kp > 1024) return EJOIN_E_UNSUPPORTED;
+    } else if (td->bm == 0 && !panel_fits(p.tile, p.Kp * elem_bytes(p.prec))) {
+        return EJOIN_E_INVAL;
+    }
     p.band_cap = o->band_capacity > 0 ? o->band_capacity
                                       : std::max<int64_t>(1 << 16, p.nR + p.nS);
     const size_t eb = (size_t)elem_bytes(p.prec);
@@ -95,9 +99,22 @@ ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, c
     ejoin_status s = make_plan(R, S, &ob, tp.base, may_alias);
     if (s != EJOIN_OK) return s;
     Plan& p = tp.base;
-    // candidate sweep: register panels where the row depth has a panel
-    // form, else the LDS tile kernel (any depth)
-    tp.panel = topk_panel_depth(p.prec, p.Kp * elem_bytes(p.prec));
+    // candidate sweep: register panels where the row depth has a panel form
+    // and R fills the chip with 128-row panels (each panel sweeps all of S),
+    // else the LDS tile kernel (any depth, one workgroup per 128 x 128 tile).
+    // opts->tile forces a form: a panel tile of the precision, or its
+    // 128 x 128 tile (1 FP32, 3 BF16, 5 FP8).
+    const bool depth_ok = topk_panel_depth(p.prec, p.Kp * elem_bytes(p.prec));
+    if (o->tile == 0) {
+        tp.panel = depth_ok && p.nR >= 65536;
+    } else {
+        const TileDesc* td = tile_get(o->tile);
+        if (!td || td->prec != p.prec) return EJOIN_E_INVAL;
+        const bool square = o->tile == (p.prec == P_FP32 ? 1 : p.prec == P_BF16 ? 3 : 5);
+        const bool panel = td->bm == 0 && o->tile != kTileNlj;
+        if (!square && !(panel && depth_ok)) return EJOIN_E_INVAL;
+        tp.panel = panel;
+    }
     tp.Kc = o->topk_cand > 0 ? o->topk_cand : 256;
     if (tp.Kc < k) tp.Kc = k;
     if (tp.Kc > 256) return EJOIN_E_INVAL;

@@ -150,6 +150,8 @@ static const TileDesc kTiles[] = {
     {20, P_FP32, 0, 0, 32, "fp32:panel"},
     {21, P_FP32, 0, 0, 32, "fp32:panel/2wg"},
     {22, P_BF16, 128, 128, 64, "bf16:panel/batch/2wg"},
+    // the nested-loop comparator: one pair per wavefront, no tiling
+    {kTileNlj, P_FP32, 0, 0, 32, "fp32:nlj"},
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -199,6 +201,7 @@ hipError_t launch_threshold(int tile_id, const ThresholdArgs& a, hipStream_t st)
         case 16: return run<P_BF16, 256, 256, 2, 2, true>(a, st);
         case 17: return run<P_FP8, 256, 256, 2, 2, true>(a, st);
         case 18: return run<P_FP32, 256, 256, 2, 2, true>(a, st);
+        case kTileNlj: return launch_threshold_nlj(a, st);
         default: return hipErrorInvalidValue;
     }
 }

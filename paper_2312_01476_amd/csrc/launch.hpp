@@ -46,6 +46,10 @@ struct ThresholdArgs {
     int kg_last;     // k-groups of the last K slice that hold data
 };
 hipError_t launch_threshold(int tile_id, const ThresholdArgs& a, hipStream_t st);
+// the nested-loop comparator (FP32, rows of up to 1024 elements): one pair
+// per wavefront, no tiling; never chosen by the planner or the tuner
+constexpr int kTileNlj = 23;
+hipError_t launch_threshold_nlj(const ThresholdArgs& a, hipStream_t st);
 hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs& a,
                                   hipStream_t st);
 

@@ -33,6 +33,7 @@ bool tile_runs(int tile, int prec, int Kp, bool batch) {
         return td->bm != 0 && batch_has_tile(tile) &&
                ((tile != 19 && tile != 22) || batch_panel_depth(Kp * elem_bytes(prec)));
     if (tile == 19 || tile == 22) return false;  // batch-only forms
+    if (tile == kTileNlj) return false;          // the comparator is never tuned
     return !(td->bm == 0 && !panel_fits(tile, Kp * elem_bytes(prec)));
 }
 

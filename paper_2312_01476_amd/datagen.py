@@ -203,7 +203,24 @@ WORKLOADS = {
                                        "mlp_seed": 601, "train_steps": 300,
                                        "train_batch": 4096, "eps": 0.05},
                                 notes="64 uneven joins, 768-d, learned prefilter (approximate)"),
+    # the scan side of the scan-versus-probe study: 10k query tuples joined
+    # with 1M data tuples after a relational pre-filter on the data side
+    # (selectivity 1-100% of an attribute drawn uniformly in [0, 1)), range
+    # predicate sim >= 0.9 and top-1 / top-32, 300-d (ld 320), fp32; 10k
+    # clusters (sigma 0.25), so a query has ~100 same-cluster rows in all of S
+    "sel_10k_1m": Workload("sel_10k_1m", 10_000, 1_000_000, 300, 320, 10_000, 0.25,
+                           theta=0.9, seeds=(701, 702, 703), extra={"attr_seed": 704},
+                           notes="10k x 1M, 300-d, fp32, pre-filter on S at 1-100%"),
 }
+
+
+def attribute_column_torch(n: int, seed: int, device: str = "cuda"):
+    """A relational attribute drawn uniformly in [0, 1) (float32, on the
+    device): a range predicate a < s on it keeps a fraction s of the rows."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return torch.rand((n,), generator=g, device=device, dtype=torch.float32)
 
 
 def micro_sweep_side(ops: int, dim: int) -> int:

@@ -297,9 +297,9 @@ def threshold(R, S, theta: float, *, d=None, prec="fp32", band=None, tile=0, cap
     raise EjoinError(rc, "ejoin_threshold (retries exhausted)")
 
 
-def topk_workspace(R, S, k, *, d=None, prec="bf16", topk_cand=0):
+def topk_workspace(R, S, k, *, d=None, prec="bf16", topk_cand=0, tile=0):
     r, s = _rel(R, d), _rel(S, d)
-    o = _opts(prec, None, 0, 0, 0, topk_cand)
+    o = _opts(prec, None, tile, 0, 0, topk_cand)
     n = lib().ejoin_topk_workspace(C.byref(r), C.byref(s), int(k), C.byref(o))
     if n == 0:
         raise EjoinError(E_INVAL, "ejoin_topk_workspace")
@@ -307,10 +307,10 @@ def topk_workspace(R, S, k, *, d=None, prec="bf16", topk_cand=0):
 
 
 def topk_raw(R, S, k, out_idx, out_score, ws, *, d=None, prec="bf16", topk_cand=0, flags=0,
-             stream=None):
+             stream=None, tile=0):
     """One ejoin_topk call on caller buffers.  Returns (status, stats dict)."""
     r, s = _rel(R, d), _rel(S, d)
-    o = _opts(prec, None, 0, 0, flags, topk_cand)
+    o = _opts(prec, None, tile, 0, flags, topk_cand)
     st = Stats()
     rc = lib().ejoin_topk(C.byref(r), C.byref(s), int(k), C.byref(o),
                           C.c_void_p(out_idx.data_ptr() if out_idx.numel() else 0),
@@ -320,19 +320,19 @@ def topk_raw(R, S, k, out_idx, out_score, ws, *, d=None, prec="bf16", topk_cand=
     return rc, st.as_dict()
 
 
-def topk(R, S, k: int, *, d=None, prec="bf16", topk_cand=0, timing=False, stream=None):
+def topk(R, S, k: int, *, d=None, prec="bf16", topk_cand=0, timing=False, stream=None, tile=0):
     """Top-k E-join on the GPU: per R row the k most similar S rows, ordered by
     (sim64 desc, index asc).  Returns (idx int32 (|R|, k), score float32
     (|R|, k), stats); empty slots hold (-1, -inf)."""
     import torch
     dev = R.device
     nR = R.shape[0]
-    ws = torch.empty(topk_workspace(R, S, k, d=d, prec=prec, topk_cand=topk_cand),
+    ws = torch.empty(topk_workspace(R, S, k, d=d, prec=prec, topk_cand=topk_cand, tile=tile),
                      dtype=torch.uint8, device=dev)
     idx = torch.empty((nR, k), dtype=torch.int32, device=dev)
     sc = torch.empty((nR, k), dtype=torch.float32, device=dev)
     rc, st = topk_raw(R, S, k, idx, sc, ws, d=d, prec=prec, topk_cand=topk_cand,
-                      flags=TIMING if timing else 0, stream=stream)
+                      flags=TIMING if timing else 0, stream=stream, tile=tile)
     if rc != OK:
         raise EjoinError(rc, "ejoin_topk")
     return idx, sc, st
@@ -442,14 +442,14 @@ def threshold_sel(R, sel_r, S, sel_s, theta: float, *, d=None, prec="fp32", band
 
 
 def topk_sel(R, sel_r, S, sel_s, k: int, *, d=None, prec="bf16", topk_cand=0, timing=False,
-             flags=0, stream=None):
+             flags=0, stream=None, tile=0):
     """Top-k over the selected rows: output row i is the i-th selected R row;
     indices are S row ids.  Returns (idx, score, stats)."""
     import torch
     dev = R.device
     r, s = _rel(R, d), _rel(S, d)
     a, b = _sel(sel_r), _sel(sel_s)
-    o = _opts(prec, None, 0, 0, flags | (TIMING if timing else 0), topk_cand)
+    o = _opts(prec, None, tile, 0, flags | (TIMING if timing else 0), topk_cand)
     L = lib()
     need = L.ejoin_topk_sel_workspace(C.byref(r), _ref(a), C.byref(s), _ref(b), int(k),
                                       C.byref(o))

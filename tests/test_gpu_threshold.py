@@ -242,3 +242,29 @@ def test_panel_kernel_depths(prec, d):
     for tile in tiles:
         st = _check(R, S, 0.7, prec=prec, tile=tile)
         assert st["tile"] == tile
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (130, 257, 33), (300, 129, 300), (257, 513, 768),
+                                   (70, 1100, 1024)])
+def test_nlj_comparator_is_exact(shape):
+    """The nested-loop comparator (tile 23: one pair per wavefront, no
+    tiling) goes through the same band and FP64 rescore: its set equals the
+    oracle's, ragged shapes and depths up to 1024 included."""
+    nr, ns, d = shape
+    R = G.gaussian_raw(nr, d, seed=nr + 3 * d)
+    S = G.gaussian_raw(ns, d, seed=ns + 5 * d)
+    sims = O.sim_matrix(R, S)
+    for q in (0.5, 0.99):
+        _check(R, S, float(np.quantile(sims, q)), tile=23)
+
+
+def test_nlj_comparator_words_and_limits():
+    w = G.WORKLOADS["words_1k"]
+    R, S, lr, ls = G.make_host(w)
+    st = _check(R, S, w.theta, d=w.d, tile=23)
+    assert st["tile"] == 23 and st["n_pairs"] == int((lr[:, None] == ls[None, :]).sum())
+    Rd = _dev(G.gaussian_raw(8, 1100, seed=1))
+    with pytest.raises(E.EjoinError):        # rows deeper than 1024 elements
+        E.threshold(Rd, Rd, 0.5, tile=23)
+    with pytest.raises(E.EjoinError):        # FP32 only
+        E.threshold(Rd[:, :64], Rd[:, :64], 0.5, prec="bf16", tile=23)

@@ -28,6 +28,10 @@ def _dev(X):
     return torch.from_numpy(np.ascontiguousarray(X)).to("cuda")
 
 
+PANEL = {"fp32": 21, "bf16": 14, "fp8": 13}   # register-panel sweep
+SQUARE = {"fp32": 1, "bf16": 3, "fp8": 5}     # 128 x 128 tile sweep
+
+
 def _check(R, S, k, prec, d=None, **kw):
     idx, sc, st = E.topk(_dev(R), _dev(S), k, d=d, prec=prec, **kw)
     oi, osc = O.topk(R, S, k, d=d)
@@ -39,13 +43,16 @@ def _check(R, S, k, prec, d=None, **kw):
     return st
 
 
+@pytest.mark.parametrize("form", ["panel", "tile"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 @pytest.mark.parametrize("k", [1, 3, 10, 37])
-def test_clustered(prec, k):
+def test_clustered(prec, k, form):
     cent = G.centres(128, 30, seed=1)
     R, _ = G.clustered_points(cent, 700, 0.3, seed=2)
     S, _ = G.clustered_points(cent, 3000, 0.3, seed=3)
-    st = _check(R, S, k, prec)
+    tile = (PANEL if form == "panel" else SQUARE)[prec]
+    st = _check(R, S, k, prec, tile=tile)
+    assert st["tile"] == tile
     assert st["n_fallback"] < R.shape[0] // 10
 
 
@@ -58,7 +65,8 @@ def test_ties_and_duplicates(prec):
     S[200] = S[5] * np.float32(4.0)           # scaled copy: same similarity
     R[7] = S[5]
     R[8] = 0.0                                # zero row: all similarities 0
-    _check(R, S, 16, prec)
+    _check(R, S, 16, prec, tile=PANEL[prec])
+    _check(R, S, 16, prec, tile=SQUARE[prec])
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
@@ -77,7 +85,9 @@ def test_forced_fallback_is_exact(prec):
     cent = G.centres(96, 5, seed=10)
     R, _ = G.clustered_points(cent, 400, 0.3, seed=11)
     S, _ = G.clustered_points(cent, 2500, 0.3, seed=12)
-    st = _check(R, S, 8, prec, topk_cand=8)
+    st = _check(R, S, 8, prec, topk_cand=8, tile=PANEL[prec])
+    assert st["n_fallback"] > 0
+    st = _check(R, S, 8, prec, topk_cand=8, tile=SQUARE[prec])
     assert st["n_fallback"] > 0
 
 
@@ -103,12 +113,19 @@ def test_large_s_strided_pilot(prec):
     cent = G.centres(64, 400, seed=21)
     R, _ = G.clustered_points(cent, 256, 0.3, seed=22)
     S, _ = G.clustered_points(cent, 70000, 0.3, seed=23)
-    st = _check(R, S, 10, prec)
-    assert st["n_fallback"] < R.shape[0] // 4
+    for tile in (PANEL[prec], SQUARE[prec]):
+        st = _check(R, S, 10, prec, tile=tile)
+        assert st["n_fallback"] < R.shape[0] // 4
 
 
 def test_invalid():
     R = _dev(G.gaussian_raw(10, 8, seed=1))
+    for tile in (2, 12, 16, 23):              # not a top-k form of FP32
+        with pytest.raises(E.EjoinError):
+            E.topk(R, R, 4, prec="fp32", tile=tile)
+    with pytest.raises(E.EjoinError):         # a panel form at a depth without one
+        E.topk(_dev(G.gaussian_raw(10, 1024, seed=1)), _dev(G.gaussian_raw(10, 1024, seed=2)),
+               4, prec="fp32", tile=21)
     with pytest.raises(E.EjoinError):
         E.topk(R, R, 0, prec="bf16")
     with pytest.raises(E.EjoinError):
@@ -128,6 +145,9 @@ def test_every_depth(prec, d):
     S[50:60] = S[7]                            # exact ties
     st = _check(R, S, 10, prec)
     assert st["n_fallback"] < R.shape[0] // 10
+    if d in (40, 300, 384, 640, 768):          # depths with a panel form
+        st = _check(R, S, 10, prec, tile=PANEL[prec])
+        assert st["tile"] == PANEL[prec]
 
 
 @pytest.mark.parametrize("prec,d", [("fp32", 300), ("bf16", 1024)])
