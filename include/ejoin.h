@@ -129,6 +129,7 @@ typedef struct {
     int32_t topk_slots;     /* top-k: candidate slots per row */
     int64_t tiles_total;    /* batch: tile pairs of all jobs */
     int64_t tiles_kept;     /* batch: tile pairs contracted (all of them unless prefiltered) */
+    int64_t topk_refined;   /* top-k: rows swept again with a floor of their own */
 } ejoin_stats;
 
 /* Library version string (static storage). */
@@ -236,8 +237,12 @@ size_t ejoin_topk_workspace(const ejoin_rel *R, const ejoin_rel *S, int32_t k,
  * rows) to set a candidate floor, one contraction sweep that keeps every
  * column above the floor, and a per-row finalize that certifies the candidate
  * set (no slot overflow, k-th score minus twice the row's error bound at or
- * above the floor), rescores it in FP64 and sorts it; rows that fail the
- * certificate take an exact FP64 scan (reported in stats->n_fallback).
+ * above the floor), rescores it in FP64 and sorts it.  Rows whose slots
+ * overflowed are swept again (synchronous calls) with a floor of their own:
+ * their k-th best kept approximate score minus twice their error bound, a
+ * lower bound of every exact top-k member's approximate score (counted in
+ * stats->topk_refined); rows that still fail take an exact FP64 scan
+ * (stats->n_fallback).
  */
 ejoin_status ejoin_topk(const ejoin_rel *R, const ejoin_rel *S, int32_t k, const ejoin_opts *opts,
                         int32_t *out_idx, float *out_score, void *ws, size_t ws_bytes,

@@ -82,8 +82,9 @@ struct TopkPlan {
     bool panel = true;
     size_t off_nr = 0, off_ns = 0, off_cnt = 0, off_cand = 0, off_fb = 0, off_prow = 0,
            off_pkth = 0, off_keys = 0, off_counts = 0, off_order = 0, off_partv = 0,
-           off_partj = 0, total = 0;
+           off_partj = 0, off_ref = 0, off_floor = 0, off_ca = 0, off_ci = 0, total = 0;
     int part_rows = 256;
+    int64_t refine_rows = 0;  // rows one refinement pass gathers
 };
 
 ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, const ejoin_opts* o,
@@ -146,6 +147,17 @@ ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, c
     off = align256(off + (size_t)tp.part_rows * 64 * k * sizeof(double));
     tp.off_partj = off;
     off = align256(off + (size_t)tp.part_rows * 64 * k * sizeof(int));
+    // refinement of overflowed rows: their list, per-row floors, and their
+    // prepared rows and row data gathered in passes of up to 65536 rows
+    tp.refine_rows = std::min<int64_t>(p.padR, 65536);
+    tp.off_ref = off;
+    off = align256(off + (size_t)p.padR * sizeof(int));
+    tp.off_floor = off;
+    off = align256(off + (size_t)p.padR * sizeof(float));
+    tp.off_ca = off;
+    off = align256(off + (size_t)tp.refine_rows * p.Kp * elem_bytes(p.prec));
+    tp.off_ci = off;
+    off = align256(off + (size_t)tp.refine_rows * sizeof(RowInfo));
     tp.total = off;
     return EJOIN_OK;
 }
@@ -361,6 +373,46 @@ static ejoin_status topk_run(const ejoin_rel* R, const ejoin_rel* S, int32_t k, 
     unsigned long long h[H_COUNT];
     HIP_TRY(hipMemcpyAsync(h, hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    int64_t n_refined = 0;
+    if (h[H_FLAGS] == 0 && h[H_TOPK_FB] > 0 && !tp.all_columns) {
+        // rows that failed the certificate: those whose slots overflowed are
+        // swept again with a floor of their own, then certified again
+        const int64_t n_fb = (int64_t)h[H_TOPK_FB];
+        int* ref = (int*)(w + tp.off_ref);
+        float* floors = (float*)(w + tp.off_floor);
+        HIP_TRY(hipMemcpyAsync(ref, ta.fb_rows, (size_t)n_fb * sizeof(int),
+                               hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(launch_fill_int((int*)(hdr + H_TOPK_FB), 2, 0, stream));
+        HIP_TRY(launch_topk_refine_floor(ta, ref, n_fb, floors, stream));
+        const int kpb = p.Kp * elem_bytes(p.prec);
+        for (int64_t b0 = 0; b0 < n_fb; b0 += tp.refine_rows) {
+            const int64_t nb = std::min<int64_t>(tp.refine_rows, n_fb - b0);
+            const int64_t nb_pad = (nb + 127) / 128 * 128;
+            HIP_TRY(launch_gather_prepared(w + p.off_xr, kpb, ref + b0, nb, nb_pad, w + tp.off_ca,
+                                           stream));
+            HIP_TRY(launch_gather_prepared(info_r, (int)sizeof(RowInfo), ref + b0, nb, nb_pad,
+                                           w + tp.off_ci, stream));
+            CandArgs cr;
+            cr.A = w + tp.off_ca;
+            cr.B = w + p.off_xs;
+            cr.info_r = (const RowInfo*)(w + tp.off_ci);
+            cr.info_s = info_s;
+            cr.Kp = p.Kp;
+            cr.nR = nb;
+            cr.nS = p.nS;
+            cr.hdr = hdr;
+            cr.cnt = (int*)(w + tp.off_cnt);
+            cr.cand = (int2*)(w + tp.off_cand);
+            cr.Kc = tp.Kc;
+            cr.row_map = ref + b0;
+            cr.floors = floors + b0;
+            HIP_TRY(launch_topk_candidates_tile(p.prec, cr, stream));
+        }
+        HIP_TRY(launch_topk_finalize_rows(ta, ref, n_fb, floors, stream));
+        HIP_TRY(hipMemcpyAsync(h, hdr, sizeof(h), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        n_refined = n_fb;
+    }
     if (h[H_FLAGS] == 0) {
         HIP_TRY(launch_topk_fallback(ta, (int64_t)h[H_TOPK_FB], stream));
         HIP_TRY(launch_map_topk(out_idx, p.nR * k, g.map_s, p.nS, hdr, stream));
@@ -379,6 +431,7 @@ static ejoin_status topk_run(const ejoin_rel* R, const ejoin_rel* S, int32_t k, 
     if (h[H_FLAGS] & F_RANGE) return EJOIN_E_RANGE;
     if (stats) {
         stats->n_fallback = (int32_t)h[H_TOPK_FB];
+        stats->topk_refined = n_refined;
         stats->topk_floor = (double)__builtin_bit_cast(float, (uint32_t)h[H_TOPK_F]);
         stats->band = (double)__builtin_bit_cast(float, (uint32_t)h[H_TOPK_EMAX]);
     }

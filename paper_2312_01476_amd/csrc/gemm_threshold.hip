@@ -52,7 +52,8 @@ __global__ __launch_bounds__(256, 2) void topk_cand_tile(
     const char* __restrict__ A, const char* __restrict__ B, const RowInfo* __restrict__ info_r,
     const RowInfo* __restrict__ info_s, int Kp_bytes, int64_t nR, int64_t nS, int tiles_m,
     int tiles_n, int ntiles, const unsigned long long* __restrict__ hdr, int* __restrict__ cnt,
-    int2* __restrict__ cand, int Kc) {
+    int2* __restrict__ cand, int Kc, const int* __restrict__ row_map,
+    const float* __restrict__ floors) {
     constexpr int BM = 128, BN = 128, WM = 2, WN = 2;
     typedef TileGeom<BM, BN, WM, WN> TG;
     EJ_TILE_SMEM(BM, BN, WM * WN, sm);
@@ -65,7 +66,9 @@ __global__ __launch_bounds__(256, 2) void topk_cand_tile(
     raster_tile(bid, tiles_m, tiles_n, tm, tn);
     v16f acc[TG::FM][TG::FN];
     tile_mainloop<PREC, BM, BN, WM, WN>(sm, A, B, info_r, info_s, Kp_bytes, tm, tn, acc);
-    const float F = __uint_as_float((uint32_t)hdr[H_TOPK_F]);
+    // with a row map, A holds gathered rows: row gi is R row row_map[gi],
+    // swept with its own floor floors[gi]
+    const float F0 = __uint_as_float((uint32_t)hdr[H_TOPK_F]);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WN, wn = wave % WN, h = lane >> 5, r32 = lane & 31;
     const uint32_t below_half = (1u << r32) - 1u;
@@ -79,18 +82,21 @@ __global__ __launch_bounds__(256, 2) void topk_cand_tile(
                 const int64_t gi =
                     (int64_t)tm * BM + wm * TG::WTM + i * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
                 const float a = acc[i][j][e];
-                const bool hit = gi < nR && gj < nS && a >= F;
+                const bool rin = gi < nR;
+                const float F = (floors && rin) ? floors[gi] : F0;
+                const bool hit = rin && gj < nS && a >= F;
                 const uint64_t m = __ballot(hit);
                 if (!m) continue;
+                const int64_t ri = (row_map && rin) ? (int64_t)row_map[gi] : gi;
                 const uint32_t mh = h ? (uint32_t)(m >> 32) : (uint32_t)m;
                 // the lowest hitting lane of each half takes the half's slots
                 const int leader = mh ? 32 * h + __builtin_ctz(mh) : lane;
                 int base = 0;
-                if (hit && lane == leader) base = atomicAdd(cnt + gi, __popc(mh));
+                if (hit && lane == leader) base = atomicAdd(cnt + ri, __popc(mh));
                 base = __shfl(base, leader, 64);
                 if (hit) {
                     const int pos = base + __popc(mh & below_half);
-                    if (pos < Kc) cand[gi * Kc + pos] = make_int2((int)gj, __float_as_int(a));
+                    if (pos < Kc) cand[ri * Kc + pos] = make_int2((int)gj, __float_as_int(a));
                 }
             }
         }
@@ -108,7 +114,8 @@ static hipError_t run_cand_tile(const CandArgs& a, hipStream_t st) {
     const int kpb = a.Kp * (PREC == P_FP32 ? 4 : PREC == P_BF16 ? 2 : 1);
     hipLaunchKernelGGL((topk_cand_tile<PREC>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st,
                        (const char*)a.A, (const char*)a.B, a.info_r, a.info_s, kpb, a.nR, a.nS,
-                       (int)tm, (int)tn, (int)nblocks, a.hdr, a.cnt, a.cand, a.Kc);
+                       (int)tm, (int)tn, (int)nblocks, a.hdr, a.cnt, a.cand, a.Kc, a.row_map,
+                       a.floors);
     return hipGetLastError();
 }
 

@@ -65,6 +65,10 @@ struct CandArgs {
     int* cnt;                 // per padded R row
     int2* cand;               // per padded R row, Kc slots
     int Kc;
+    // tile form only: A holds gathered rows, row gi standing for R row
+    // row_map[gi] (its cnt / cand entries) swept with floor floors[gi]
+    const int* row_map = nullptr;
+    const float* floors = nullptr;
 };
 // register-panel form: returns hipErrorInvalidValue for row depths without
 // a panel form (then the tile form below takes any depth; its per-row
@@ -110,6 +114,14 @@ hipError_t launch_norms64(const float* X, int64_t rows, int dim, int64_t ld, dou
 hipError_t launch_topk_pilot(const TopkArgs& a, hipStream_t st);
 hipError_t launch_topk_finalize(const TopkArgs& a, hipStream_t st);
 hipError_t launch_topk_fallback(const TopkArgs& a, int64_t n_fb, hipStream_t st);
+// refinement of overflowed rows (rows[0 .. n): the first finalize's failures):
+// per-row floors (+inf for rows that did not overflow) and counters reset
+hipError_t launch_topk_refine_floor(const TopkArgs& a, const int* rows, int64_t n, float* floors,
+                                    hipStream_t st);
+hipError_t launch_topk_finalize_rows(const TopkArgs& a, const int* order, int64_t n,
+                                     const float* floors, hipStream_t st);
+hipError_t launch_gather_prepared(const void* X, int row_bytes, const int* rows, int64_t n,
+                                  int64_t n_pad, void* dst, hipStream_t st);
 
 // sel_r / sel_s (may be null): band entries hold selection positions; the
 // FP64 rule reads the caller's rows sel[position]

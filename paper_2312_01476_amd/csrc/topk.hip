@@ -547,7 +547,8 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
     const RowInfo* __restrict__ info_r, const int* __restrict__ cnt,
     const int2* __restrict__ cand, int Kc, int k, double fp32_terms,
     const int* __restrict__ order, unsigned long long* __restrict__ hdr,
-    int* __restrict__ fb_rows, int32_t* __restrict__ out_idx, float* __restrict__ out_score) {
+    int* __restrict__ fb_rows, int32_t* __restrict__ out_idx, float* __restrict__ out_score,
+    const float* __restrict__ floors, int64_t n_rows) {
     __shared__ FinSmem sm;
     __shared__ int s_nl[FW_WAVES], s_same[FW_WAVES];
     if (hdr[H_FLAGS] != 0) return;
@@ -555,18 +556,21 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
     double* v = sm.v[w];
     int* jv = sm.j[w];
     int* live = sm.live[w];
-    const float F = __uint_as_float((uint32_t)hdr[H_TOPK_F]);
+    const float F0 = __uint_as_float((uint32_t)hdr[H_TOPK_F]);
     const double es = (double)__uint_as_float((uint32_t)hdr[H_ENORM_S]) * 1.001 + 1e-7;
     const int kk = (int)min((int64_t)k, nS);
 
-    // workgroup-uniform loop: the barriers below need all four waves
-    for (int64_t base = (int64_t)blockIdx.x * FW_WAVES; base < nR;
+    // workgroup-uniform loop: the barriers below need all four waves.  Rows
+    // order[0 .. n_rows) (all rows without an order); with `floors` the
+    // candidates of position rr were swept with floor floors[rr].
+    for (int64_t base = (int64_t)blockIdx.x * FW_WAVES; base < n_rows;
          base += (int64_t)gridDim.x * FW_WAVES) {
         const int64_t rr = base + w;
         int n_live = 0;  // wave-uniform: candidates this wave rescores
         int64_t i = 0;
-        if (rr < nR) {
+        if (rr < n_rows) {
             i = order ? order[rr] : rr;
+            const float F = floors ? floors[rr] : F0;
             if (nS == 0) {  // nothing to join: every slot is padding
                 for (int t = lane; t < k; t += 64) {
                     out_idx[i * k + t] = -1;
@@ -832,7 +836,117 @@ hipError_t launch_topk_finalize(const TopkArgs& a, hipStream_t st) {
     if (nb > 65536) nb = 65536;
     hipLaunchKernelGGL(topk_finalize_w, dim3((unsigned)nb), dim3(256), 0, st, a.R, a.ldR, a.S,
                        a.ldS, a.dim, a.nR, a.nS, a.nr64, a.ns64, a.info_r, a.cnt, a.cand, a.Kc,
-                       a.k, a.fp32_terms, order, a.hdr, a.fb_rows, a.out_idx, a.out_score);
+                       a.k, a.fp32_terms, order, a.hdr, a.fb_rows, a.out_idx, a.out_score,
+                       (const float*)nullptr, a.nR);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// refinement of rows whose candidate slots overflowed
+// ---------------------------------------------------------------------------
+// A row that saw more than Kc columns at or above the global floor F holds
+// Kc of them (whichever came first).  Their k-th best approximate score A'_k
+// is at most the row's k-th best over all columns A_k, and every column of
+// the exact top k has an approximate score >= A_k - 2 D_i >= A'_k - 2 D_i,
+// so F_i = A'_k - 2 D_i (rounded down to float) is a valid floor for that
+// row alone, usually far above F.  One wave per listed row: rows that
+// overflowed get F_i and their counter reset; the others (too few good
+// candidates: no better floor exists) get +inf and keep their state, so the
+// second finalize sends them to the exact scan again.
+__global__ __launch_bounds__(256) void topk_refine_floor(
+    const int* __restrict__ rows, int64_t n, int* __restrict__ cnt,
+    const int2* __restrict__ cand, int Kc, int k, int64_t nS,
+    const RowInfo* __restrict__ info_r, double fp32_terms,
+    const unsigned long long* __restrict__ hdr, float* __restrict__ floors) {
+    __shared__ double sv[4][256];
+    __shared__ int sj[4][256];
+    __shared__ double s_lim[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const double es = (double)__uint_as_float((uint32_t)hdr[H_ENORM_S]) * 1.001 + 1e-7;
+    const int kk = (int)min((int64_t)k, nS);
+    for (int64_t c = (int64_t)blockIdx.x * 4 + w; c < n; c += (int64_t)gridDim.x * 4) {
+        const int64_t i = rows[c];
+        const int cn = cnt[i];
+        if (cn <= Kc) {  // wave-uniform
+            if (lane == 0) floors[c] = INFINITY;
+            continue;
+        }
+        for (int t = lane; t < Kc; t += 64) {
+            const int2 e = cand[i * (int64_t)Kc + t];
+            sv[w][t] = (double)__int_as_float(e.y);
+            sj[w][t] = e.x;
+        }
+        if (lane == 0) s_lim[w] = -INFINITY;
+        wave_sync();
+        for (int t = lane; t < Kc; t += 64) {
+            const double vt = sv[w][t];
+            const int jt = sj[w][t];
+            int rank = 0;
+            for (int u = 0; u < Kc; ++u) rank += better(sv[w][u], sj[w][u], vt, jt);
+            if (rank == kk - 1) s_lim[w] = vt;
+        }
+        wave_sync();
+        if (lane == 0) {
+            const double er = (double)info_r[i].enorm * 1.001 + 1e-7;
+            const double di = er * (1.0 + es) + es + fp32_terms * (1.0 + er) * (1.0 + es);
+            const double f = s_lim[w] - 2.0 * di;
+            float ff = (float)f;
+            if ((double)ff > f) ff = next_down(ff);
+            floors[c] = ff;
+            cnt[i] = 0;
+        }
+        wave_sync();
+    }
+}
+
+hipError_t launch_topk_refine_floor(const TopkArgs& a, const int* rows, int64_t n, float* floors,
+                                    hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 3) / 4;
+    if (nb > 16384) nb = 16384;
+    hipLaunchKernelGGL(topk_refine_floor, dim3((unsigned)nb), dim3(256), 0, st, rows, n,
+                       (int*)a.cnt, a.cand, a.Kc, a.k, a.nS, a.info_r, a.fp32_terms,
+                       (const unsigned long long*)a.hdr, floors);
+    return hipGetLastError();
+}
+
+// The second finalize: rows order[0 .. n) swept with per-position floors.
+hipError_t launch_topk_finalize_rows(const TopkArgs& a, const int* order, int64_t n,
+                                     const float* floors, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + FW_WAVES - 1) / FW_WAVES;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(topk_finalize_w, dim3((unsigned)nb), dim3(256), 0, st, a.R, a.ldR, a.S,
+                       a.ldS, a.dim, a.nR, a.nS, a.nr64, a.ns64, a.info_r, a.cnt, a.cand, a.Kc,
+                       a.k, a.fp32_terms, order, a.hdr, a.fb_rows, a.out_idx, a.out_score, floors,
+                       n);
+    return hipGetLastError();
+}
+
+// Prepared rows rows[0 .. n) of X (row_bytes each, a multiple of 16) copied
+// into a compact buffer of n_pad rows (rows n .. n_pad - 1 zero).
+__global__ __launch_bounds__(256) void gather_prepared(const char* __restrict__ X,
+                                                       int row_bytes, const int* __restrict__ rows,
+                                                       int64_t n, int64_t n_pad,
+                                                       char* __restrict__ dst) {
+    const int per = row_bytes / 16;
+    const int64_t total = n_pad * per;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = q / per, o = q - c * per;
+        v4i v = {0, 0, 0, 0};
+        if (c < n) v = *(const v4i*)(X + (int64_t)rows[c] * row_bytes + o * 16);
+        *(v4i*)(dst + c * row_bytes + o * 16) = v;
+    }
+}
+
+hipError_t launch_gather_prepared(const void* X, int row_bytes, const int* rows, int64_t n,
+                                  int64_t n_pad, void* dst, hipStream_t st) {
+    if (n_pad <= 0) return hipSuccess;
+    int64_t nb = (n_pad * (row_bytes / 16) + 255) / 256;
+    if (nb > 8192) nb = 8192;
+    hipLaunchKernelGGL(gather_prepared, dim3((unsigned)nb), dim3(256), 0, st, (const char*)X,
+                       row_bytes, rows, n, n_pad, (char*)dst);
     return hipGetLastError();
 }
 

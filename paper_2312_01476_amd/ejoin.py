@@ -48,7 +48,8 @@ class Stats(C.Structure):
                 ("n_fallback", C.c_int32), ("ms_prep", C.c_float), ("ms_main", C.c_float),
                 ("ms_rescore", C.c_float), ("ms_total", C.c_float),
                 ("topk_floor", C.c_double), ("topk_slots", C.c_int32),
-                ("tiles_total", C.c_int64), ("tiles_kept", C.c_int64)]
+                ("tiles_total", C.c_int64), ("tiles_kept", C.c_int64),
+                ("topk_refined", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -204,3 +204,22 @@ def test_failed_input_check_leaves_stale_workspace_unread(prec, flags):
     torch.cuda.synchronize()
     assert rc == (E.OK if flags else E.E_NONFINITE)
     assert int(idx.abs().max()) == 0   # outputs untouched
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("form", ["panel", "tile"])
+def test_overflowed_rows_are_refined(prec, form):
+    """Clusters of ~600 rows against k = 32 and 256 slots: every row's slots
+    overflow at the pilot's floor; the second sweep with per-row floors must
+    certify them (exact indices and scores) without the exact scan in FP32
+    and BF16.  FP8's error bound (about 0.06 per score here) keeps a whole
+    cluster within twice the bound of the k-th score, more than 256 slots, so
+    its rows still take the exact scan: the result is exact either way."""
+    cent = G.centres(96, 8, seed=60)
+    R, _ = G.clustered_points(cent, 300, 0.3, seed=61)
+    S, _ = G.clustered_points(cent, 5000, 0.3, seed=62)
+    tile = (PANEL if form == "panel" else SQUARE)[prec]
+    st = _check(R, S, 32, prec, tile=tile)
+    assert st["topk_refined"] > R.shape[0] // 2
+    if prec != "fp8":
+        assert st["n_fallback"] < R.shape[0] // 10
