@@ -211,7 +211,8 @@ def extra_selectivity(args):
     """The paper's pre-filter sweep on the scan side: a range predicate on a
     relational attribute of S keeps 1-100% of its rows (evaluated on the
     device), then the FP32 E-join of 10k queries with the kept rows, for the
-    range predicate sim >= 0.9 and top-1 / top-32."""
+    range predicate sim >= 0.9, top-1, top-32 and the range predicate with a
+    cap of k = 32."""
     import torch
     from paper_2312_01476_amd import datagen as G
     from paper_2312_01476_amd import ejoin as E
@@ -226,6 +227,7 @@ def extra_selectivity(args):
     E.threshold_sel(Rd, None, Sd, ids, w.theta, d=w.d)
     E.topk_sel(Rd, None, Sd, ids, 1, d=w.d, prec="fp32")
     E.topk_sel(Rd, None, Sd, ids, 32, d=w.d, prec="fp32")
+    E.topk_sel(Rd, None, Sd, ids, 32, d=w.d, prec="fp32", min_sim=w.theta)
     for sel in (0.01, 0.1, 0.5, 1.0):
         ms_sel, ids = _timed(lambda: E.select_range(attr, 0.0, sel))
         kept = int(ids.numel())
@@ -233,9 +235,12 @@ def extra_selectivity(args):
         ms_range, res = _timed(lambda: E.threshold_sel(Rd, None, Sd, ids, w.theta, d=w.d))
         ms_t1, _ = _timed(lambda: E.topk_sel(Rd, None, Sd, ids, 1, d=w.d, prec="fp32"))
         ms_t32, _ = _timed(lambda: E.topk_sel(Rd, None, Sd, ids, 32, d=w.d, prec="fp32"))
+        ms_rk, _ = _timed(lambda: E.topk_sel(Rd, None, Sd, ids, 32, d=w.d, prec="fp32",
+                                             min_sim=w.theta))
         pt = {"selectivity": sel, "kept_rows": kept, "select_ms": round(ms_sel, 3),
               "range_ms": round(ms_range, 2), "range_pairs_out": len(res),
               "top1_ms": round(ms_t1, 2), "top32_ms": round(ms_t32, 2),
+              "range_top32_ms": round(ms_rk, 2),
               "range_gpairs_s": round(pairs / (ms_range * 1e-3) / 1e9, 1)}
         points.append(pt)
         log(f"[bench] selectivity {pt}")

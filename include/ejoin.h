@@ -95,6 +95,9 @@ typedef struct {
                                         theta - opts->prefilter_eps.  Approximate: the result
                                         of each job is a SUBSET of its exact join (every pair
                                         returned is exact); see ejoin_batch. */
+#define EJOIN_TOPK_MIN_SIM 0x8u  /* top-k: only S rows with sim64 >= opts->topk_min_sim count
+                                    (the range predicate combined with the top-k condition);
+                                    rows with fewer passing S rows are padded */
 
 /* Autotuned tile choices (opaque; see ejoin_tuner_create). */
 typedef struct ejoin_tuner ejoin_tuner;
@@ -111,6 +114,7 @@ typedef struct {
     const void *prefilter;  /* EJOIN_APPROX_PREFILTER: device state block of a prefilter
                                network (ejoin_mlp_*) for the jobs' dim */
     float prefilter_eps;    /* EJOIN_APPROX_PREFILTER: margin below theta */
+    double topk_min_sim;    /* EJOIN_TOPK_MIN_SIM: the range bound (finite) */
 } ejoin_opts;
 
 /* Optional per-call report (host struct, may be NULL). */
@@ -233,6 +237,11 @@ size_t ejoin_topk_workspace(const ejoin_rel *R, const ejoin_rel *S, int32_t k,
  *              with a panel form) or its 128 x 128 tile (1 FP32, 3 BF16,
  *              5 FP8); other ids give EJOIN_E_INVAL.
  *   opts->topk_cand  candidate slots per row (k..256; <= 0: 256).
+ * With EJOIN_TOPK_MIN_SIM the condition is the range predicate combined
+ * with the top-k one (Section VI.E evaluates such a range join with k = 32):
+ * per R row the first min(k, m) of the m S rows with sim64 >= topk_min_sim
+ * in the same order, the other slots padded; the candidate floor is raised
+ * to topk_min_sim minus the error bound.
  * 1 <= k <= 256.  The call runs a pilot (exact FP64 top-k of up to 256 sample
  * rows) to set a candidate floor, one contraction sweep that keeps every
  * column above the floor, and a per-row finalize that certifies the candidate

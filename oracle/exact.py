@@ -81,3 +81,20 @@ def topk(R, S, k: int, d: int | None = None):
         row += [-1] * (k - len(row))
         out.append(row)
     return np.array(out, dtype=np.int64).reshape(len(Rq), k)
+
+
+def topk_range(R, S, k: int, theta: float, d: int | None = None):
+    """The range predicate combined with the top-k condition: per R row the
+    first min(k, m) of the m S indices with cos >= theta, by (cos desc, index
+    asc), decided exactly; padded with -1."""
+    d = np.asarray(R).shape[1] if d is None else d
+    Rq = _rows(R, d)
+    Sq = _rows(S, d)
+    out = []
+    for r in Rq:
+        keys = [(-sim_key(r, s), j) for j, s in enumerate(Sq) if matches(r, s, theta)]
+        keys.sort()
+        row = [j for _, j in keys[:k]]
+        row += [-1] * (k - len(row))
+        out.append(row)
+    return np.array(out, dtype=np.int64).reshape(len(Rq), k)

@@ -168,3 +168,25 @@ def topk(R, S, k: int, d=None, threads: int = 0):
     if rc != 0:
         raise OracleError("allocation failure")
     return idx, sc
+
+
+def topk_range(R, S, k: int, theta: float, d=None, threads: int = 0):
+    """The range predicate combined with the top-k condition (the range join
+    with a k cap of the scan-versus-probe study, Section VI.E): per R row the
+    first min(k, m) of the m S indices with sim64 >= theta, ordered by
+    (sim64 desc, index asc); missing slots are (-1, -inf).  Written out from
+    the two definitions above: the threshold join's pairs of each row, sorted.
+    Returns (idx int64 (|R|, k), score float64 (|R|, k))."""
+    R, nR, _, d = _prep(R, d)
+    ri, si, sc, _ = threshold(R, S, theta, d=d, threads=threads)
+    idx = np.full((nR, k), -1, dtype=np.int64)
+    out = np.full((nR, k), -np.inf, dtype=np.float64)
+    order = np.lexsort((si, -sc, ri))          # by row, then sim64 desc, then index
+    ri, si, sc = ri[order], si[order], sc[order]
+    starts = np.searchsorted(ri, np.arange(nR), side="left")
+    ends = np.searchsorted(ri, np.arange(nR), side="right")
+    for i in range(nR):
+        m = min(k, ends[i] - starts[i])
+        idx[i, :m] = si[starts[i]:starts[i] + m]
+        out[i, :m] = sc[starts[i]:starts[i] + m]
+    return idx, out

@@ -93,6 +93,7 @@ ejoin_status make_topk_plan(const ejoin_rel* R, const ejoin_rel* S, int32_t k, c
     if (k > 256) return EJOIN_E_UNSUPPORTED;
     if (!rel_ok(R) || !rel_ok(S) || R->dim != S->dim) return EJOIN_E_INVAL;
     if (o->prec < EJOIN_FP32 || o->prec > EJOIN_FP8_E4M3) return EJOIN_E_INVAL;
+    if ((o->flags & EJOIN_TOPK_MIN_SIM) && !isfinite(o->topk_min_sim)) return EJOIN_E_INVAL;
     ejoin_opts ob = *o;
     ob.tile = 0;
     ob.band = -1.0;
@@ -340,6 +341,7 @@ static ejoin_status topk_run(const ejoin_rel* R, const ejoin_rel* S, int32_t k, 
     ta.all_columns = tp.all_columns;
     ta.out_idx = out_idx;
     ta.out_score = out_score;
+    ta.min_sim = (o.flags & EJOIN_TOPK_MIN_SIM) ? o.topk_min_sim : -INFINITY;
     if (p.nS > 0) HIP_TRY(launch_topk_pilot(ta, stream));
     HIP_TRY(rec(1));
 

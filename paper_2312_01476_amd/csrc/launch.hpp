@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace ej {
@@ -107,6 +108,7 @@ struct TopkArgs {
     bool all_columns;         // |S| <= Kc: every column is a candidate
     int32_t* out_idx;
     float* out_score;
+    double min_sim = -INFINITY;  // only columns with sim64 >= min_sim count
 };
 hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st);
 hipError_t launch_norms64(const float* X, int64_t rows, int dim, int64_t ld, double* out,

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void exact_topk_rows(
     const int* __restrict__ rows_list, const unsigned long long* __restrict__ n_rows_ptr,
     int n_rows_fixed, int row_base, int row_limit, int32_t* __restrict__ out_idx,
     float* __restrict__ out_score, double* __restrict__ kth_out, double* __restrict__ part_v,
-    int* __restrict__ part_j, int col_stride) {
+    int* __restrict__ part_j, int col_stride, double min_sim) {
     __shared__ StageSmem sm;
     __shared__ double bv[XK_BUF];
     __shared__ int bj[XK_BUF];
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void exact_topk_rows(
             bool cand = false;
             if (c0 + threadIdx.x < s_hi) {
                 v = sim64_from(dot, nr, ns64[jj]);
-                cand = better(v, (int)jj, s_thr_v, s_thr_j);
+                cand = v >= min_sim && better(v, (int)jj, s_thr_v, s_thr_j);
             }
             // block compaction into the buffer
             const uint64_t m = __ballot(cand);
@@ -279,14 +279,17 @@ __global__ __launch_bounds__(256) void exact_topk_merge(
                 n = k;
             }
         }
-        const int have = (int)min((int64_t)k, nS);
+        // sorted descending: the entries are the finite ones (the ranges'
+        // lists hold only columns that passed the minimum similarity)
+        (void)nS;
         for (int t = threadIdx.x; t < k; t += blockDim.x) {
             if (out_idx) {
-                out_idx[i * k + t] = t < have ? bj[t] : -1;
-                out_score[i * k + t] = t < have ? (float)bv[t] : -INFINITY;
+                const bool have = bv[t] > -INFINITY;
+                out_idx[i * k + t] = have ? bj[t] : -1;
+                out_score[i * k + t] = have ? (float)bv[t] : -INFINITY;
             }
         }
-        if (kth_out && threadIdx.x == 0) kth_out[rr] = have == k ? bv[k - 1] : -INFINITY;
+        if (kth_out && threadIdx.x == 0) kth_out[rr] = bv[k - 1];
         __syncthreads();
     }
 }
@@ -295,7 +298,7 @@ __global__ __launch_bounds__(256) void exact_topk_merge(
 // similarity, minus twice the largest error bound of any approximate score.
 // With few S rows every column is a candidate (F = -inf).
 __global__ void topk_floor(unsigned long long* hdr, const double* __restrict__ kth, int n_pilot,
-                           double fp32_terms, int all_columns) {
+                           double fp32_terms, int all_columns, double min_sim) {
     if (threadIdx.x != 0) return;
     const double er = (double)__uint_as_float((uint32_t)hdr[H_ENORM_R]) * 1.001 + 1e-7;
     const double es = (double)__uint_as_float((uint32_t)hdr[H_ENORM_S]) * 1.001 + 1e-7;
@@ -303,6 +306,8 @@ __global__ void topk_floor(unsigned long long* hdr, const double* __restrict__ k
     double m = INFINITY;
     for (int p = 0; p < n_pilot; ++p) m = fmin(m, kth[p]);
     double F = m - 2.0 * dmax - 1e-6;
+    // a column with sim64 >= min_sim has an approximate score >= min_sim - dmax
+    if (min_sim > -INFINITY) F = fmax(F, min_sim - dmax - 1e-6);
     if (all_columns || !(F > -1e30)) F = -INFINITY;
     float Ff = (float)F;
     if ((double)Ff > F) Ff = next_down(Ff);
@@ -548,7 +553,7 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
     const int2* __restrict__ cand, int Kc, int k, double fp32_terms,
     const int* __restrict__ order, unsigned long long* __restrict__ hdr,
     int* __restrict__ fb_rows, int32_t* __restrict__ out_idx, float* __restrict__ out_score,
-    const float* __restrict__ floors, int64_t n_rows) {
+    const float* __restrict__ floors, int64_t n_rows, double min_sim) {
     __shared__ FinSmem sm;
     __shared__ int s_nl[FW_WAVES], s_same[FW_WAVES];
     if (hdr[H_FLAGS] != 0) return;
@@ -560,6 +565,11 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
     const double es = (double)__uint_as_float((uint32_t)hdr[H_ENORM_S]) * 1.001 + 1e-7;
     const int kk = (int)min((int64_t)k, nS);
 
+    // With a minimum similarity (min_sim > -inf) only columns with
+    // sim64 >= min_sim count: a certified row needs every such column of its
+    // top k among its candidates, i.e. no overflow and the larger of
+    // (k-th candidate score - 2 D_i) and (min_sim - D_i) at or above the
+    // floor; fewer than k passing columns are then a complete answer.
     // workgroup-uniform loop: the barriers below need all four waves.  Rows
     // order[0 .. n_rows) (all rows without an order); with `floors` the
     // candidates of position rr were swept with floor floors[rr].
@@ -567,6 +577,7 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
          base += (int64_t)gridDim.x * FW_WAVES) {
         const int64_t rr = base + w;
         int n_live = 0;  // wave-uniform: candidates this wave rescores
+        bool done = false;  // wave-uniform: the row is certified (outputs below)
         int64_t i = 0;
         if (rr < n_rows) {
             i = order ? order[rr] : rr;
@@ -598,8 +609,7 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
                     if (F == -INFINITY) {
                         ok = (int64_t)n == nS;  // every column present
                     } else {
-                        ok = n >= kk;
-                        if (ok) {
+                        if (n >= kk) {
                             // the entry of rank kk-1 among the n candidates
                             for (int t = lane; t < n; t += 64) {
                                 const double vt = v[t];
@@ -609,8 +619,11 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
                                 if (rank == kk - 1) sm.lim[w] = vt - 2.0 * di;
                             }
                             wave_sync();
-                            ok = sm.lim[w] >= (double)F;
                         }
+                        if (min_sim > -INFINITY && lane == 0)
+                            sm.lim[w] = fmax(sm.lim[w], min_sim - di);
+                        wave_sync();
+                        ok = sm.lim[w] >= (double)F;
                     }
                 }
                 if (!ok) {  // wave-uniform
@@ -619,6 +632,7 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
                         fb_rows[p] = (int)i;
                     }
                 } else {
+                    done = true;
                     const double lim = sm.lim[w];
                     // compact the candidates that can still be in the top k
                     for (int t0 = 0; t0 < n; t0 += 64) {
@@ -732,20 +746,25 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
                 }
             }
         }
-        if (n_live > 0) {
+        if (done) {
             wave_sync();
-            // final order by rank among the live entries
+            // final order by rank among the live entries that pass min_sim
+            int n_pass = 0;
             for (int t = lane; t < n_live; t += 64) {
                 const double vt = v[t];
+                if (!(vt >= min_sim)) continue;
+                ++n_pass;
                 const int jt = jv[t];
                 int rank = 0;
-                for (int u = 0; u < n_live; ++u) rank += better(v[u], jv[u], vt, jt);
+                for (int u = 0; u < n_live; ++u)
+                    rank += v[u] >= min_sim && better(v[u], jv[u], vt, jt);
                 if (rank < kk) {
                     out_idx[i * k + rank] = jt;
                     out_score[i * k + rank] = (float)vt;
                 }
             }
-            for (int t = kk + lane; t < k; t += 64) {
+            for (int o = 32; o > 0; o >>= 1) n_pass += __shfl_xor(n_pass, o, 64);
+            for (int t = min(kk, n_pass) + lane; t < k; t += 64) {
                 out_idx[i * k + t] = -1;
                 out_score[i * k + t] = -INFINITY;
             }
@@ -783,13 +802,14 @@ static int exact_ranges(int64_t nS) {
 static hipError_t exact_topk_batch(const TopkArgs& a, const int* rows,
                                    const unsigned long long* n_ptr, int n_fixed, int row_base,
                                    int n_rows_max, int32_t* oi, float* os, double* kth,
-                                   hipStream_t st, int col_stride = 1) {
+                                   hipStream_t st, int col_stride = 1,
+                                   double min_sim = -INFINITY) {
     const int64_t n_col = (a.nS + col_stride - 1) / col_stride;
     const int n_rg = exact_ranges(n_col);
     hipLaunchKernelGGL(exact_topk_rows, dim3(n_rows_max, n_rg), dim3(256), 0, st, a.R, a.ldR,
                        a.S, a.ldS, a.dim, a.nS, a.nr64, a.ns64, a.k, rows, n_ptr, n_fixed,
                        row_base, row_base + n_rows_max, (int32_t*)nullptr, (float*)nullptr,
-                       (double*)nullptr, a.part_v, a.part_j, col_stride);
+                       (double*)nullptr, a.part_v, a.part_j, col_stride, min_sim);
     hipLaunchKernelGGL(exact_topk_merge, dim3(n_rows_max), dim3(256), 0, st, rows, n_ptr,
                        n_fixed, row_base, row_base + n_rows_max, n_rg, a.k, n_col,
                        (const double*)a.part_v, (const int*)a.part_j, oi, os, kth);
@@ -813,7 +833,7 @@ hipError_t launch_topk_pilot(const TopkArgs& a, hipStream_t st) {
                                     nullptr, a.pilot_kth, st, stride);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(topk_floor, dim3(1), dim3(64), 0, st, a.hdr, a.pilot_kth, a.n_pilot,
-                       a.fp32_terms, a.all_columns ? 1 : 0);
+                       a.fp32_terms, a.all_columns ? 1 : 0, a.min_sim);
     return hipGetLastError();
 }
 
@@ -837,7 +857,7 @@ hipError_t launch_topk_finalize(const TopkArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(topk_finalize_w, dim3((unsigned)nb), dim3(256), 0, st, a.R, a.ldR, a.S,
                        a.ldS, a.dim, a.nR, a.nS, a.nr64, a.ns64, a.info_r, a.cnt, a.cand, a.Kc,
                        a.k, a.fp32_terms, order, a.hdr, a.fb_rows, a.out_idx, a.out_score,
-                       (const float*)nullptr, a.nR);
+                       (const float*)nullptr, a.nR, a.min_sim);
     return hipGetLastError();
 }
 
@@ -857,7 +877,7 @@ __global__ __launch_bounds__(256) void topk_refine_floor(
     const int* __restrict__ rows, int64_t n, int* __restrict__ cnt,
     const int2* __restrict__ cand, int Kc, int k, int64_t nS,
     const RowInfo* __restrict__ info_r, double fp32_terms,
-    const unsigned long long* __restrict__ hdr, float* __restrict__ floors) {
+    const unsigned long long* __restrict__ hdr, float* __restrict__ floors, double min_sim) {
     __shared__ double sv[4][256];
     __shared__ int sj[4][256];
     __shared__ double s_lim[4];
@@ -889,7 +909,7 @@ __global__ __launch_bounds__(256) void topk_refine_floor(
         if (lane == 0) {
             const double er = (double)info_r[i].enorm * 1.001 + 1e-7;
             const double di = er * (1.0 + es) + es + fp32_terms * (1.0 + er) * (1.0 + es);
-            const double f = s_lim[w] - 2.0 * di;
+            const double f = fmax(s_lim[w] - 2.0 * di, min_sim - di);
             float ff = (float)f;
             if ((double)ff > f) ff = next_down(ff);
             floors[c] = ff;
@@ -906,7 +926,7 @@ hipError_t launch_topk_refine_floor(const TopkArgs& a, const int* rows, int64_t 
     if (nb > 16384) nb = 16384;
     hipLaunchKernelGGL(topk_refine_floor, dim3((unsigned)nb), dim3(256), 0, st, rows, n,
                        (int*)a.cnt, a.cand, a.Kc, a.k, a.nS, a.info_r, a.fp32_terms,
-                       (const unsigned long long*)a.hdr, floors);
+                       (const unsigned long long*)a.hdr, floors, a.min_sim);
     return hipGetLastError();
 }
 
@@ -919,7 +939,7 @@ hipError_t launch_topk_finalize_rows(const TopkArgs& a, const int* order, int64_
     hipLaunchKernelGGL(topk_finalize_w, dim3((unsigned)nb), dim3(256), 0, st, a.R, a.ldR, a.S,
                        a.ldS, a.dim, a.nR, a.nS, a.nr64, a.ns64, a.info_r, a.cnt, a.cand, a.Kc,
                        a.k, a.fp32_terms, order, a.hdr, a.fb_rows, a.out_idx, a.out_score, floors,
-                       n);
+                       n, a.min_sim);
     return hipGetLastError();
 }
 
@@ -961,12 +981,12 @@ hipError_t launch_topk_fallback(const TopkArgs& a, int64_t n_fb, hipStream_t st)
         hipLaunchKernelGGL(exact_topk_rows, dim3(1024, 1), dim3(256), 0, st, a.R, a.ldR, a.S,
                            a.ldS, a.dim, a.nS, a.nr64, a.ns64, a.k, (const int*)a.fb_rows, cnt,
                            0, 0, 0x7fffffff, a.out_idx, a.out_score, (double*)nullptr,
-                           (double*)nullptr, (int*)nullptr, 1);
+                           (double*)nullptr, (int*)nullptr, 1, a.min_sim);
         return hipGetLastError();
     }
     for (int64_t b = 0; b < n_fb; b += a.part_rows) {
         hipError_t e = exact_topk_batch(a, a.fb_rows, cnt, 0, (int)b, a.part_rows, a.out_idx,
-                                        a.out_score, nullptr, st);
+                                        a.out_score, nullptr, st, 1, a.min_sim);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -20,6 +20,7 @@ PREC = {"fp32": 0, "bf16": 1, "fp8": 2, "fp8_e4m3": 2}
 NO_SYNC = 0x1
 TIMING = 0x2
 APPROX_PREFILTER = 0x4
+TOPK_MIN_SIM = 0x8
 
 
 class Rel(C.Structure):
@@ -29,7 +30,8 @@ class Rel(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("prec", C.c_int32), ("tile", C.c_int32), ("band", C.c_double),
                 ("band_capacity", C.c_int64), ("flags", C.c_uint32), ("topk_cand", C.c_int32),
-                ("tuner", C.c_void_p), ("prefilter", C.c_void_p), ("prefilter_eps", C.c_float)]
+                ("tuner", C.c_void_p), ("prefilter", C.c_void_p), ("prefilter_eps", C.c_float),
+                ("topk_min_sim", C.c_double)]
 
 
 class Sel(C.Structure):
@@ -176,7 +178,7 @@ def _rel(X, d):
 
 
 def _opts(prec, band, tile, band_capacity, flags, topk_cand=0, tuner=None, prefilter=None,
-          eps=0.0):
+          eps=0.0, min_sim=None):
     o = Opts()
     lib().ejoin_opts_default(C.byref(o))
     o.prec = PREC[prec]
@@ -190,6 +192,9 @@ def _opts(prec, band, tile, band_capacity, flags, topk_cand=0, tuner=None, prefi
         o.flags |= APPROX_PREFILTER
         o.prefilter = prefilter.state.data_ptr()
         o.prefilter_eps = float(eps)
+    if min_sim is not None:
+        o.flags |= TOPK_MIN_SIM
+        o.topk_min_sim = float(min_sim)
     return o
 
 
@@ -298,9 +303,9 @@ def threshold(R, S, theta: float, *, d=None, prec="fp32", band=None, tile=0, cap
     raise EjoinError(rc, "ejoin_threshold (retries exhausted)")
 
 
-def topk_workspace(R, S, k, *, d=None, prec="bf16", topk_cand=0, tile=0):
+def topk_workspace(R, S, k, *, d=None, prec="bf16", topk_cand=0, tile=0, min_sim=None):
     r, s = _rel(R, d), _rel(S, d)
-    o = _opts(prec, None, tile, 0, 0, topk_cand)
+    o = _opts(prec, None, tile, 0, 0, topk_cand, min_sim=min_sim)
     n = lib().ejoin_topk_workspace(C.byref(r), C.byref(s), int(k), C.byref(o))
     if n == 0:
         raise EjoinError(E_INVAL, "ejoin_topk_workspace")
@@ -308,10 +313,10 @@ def topk_workspace(R, S, k, *, d=None, prec="bf16", topk_cand=0, tile=0):
 
 
 def topk_raw(R, S, k, out_idx, out_score, ws, *, d=None, prec="bf16", topk_cand=0, flags=0,
-             stream=None, tile=0):
+             stream=None, tile=0, min_sim=None):
     """One ejoin_topk call on caller buffers.  Returns (status, stats dict)."""
     r, s = _rel(R, d), _rel(S, d)
-    o = _opts(prec, None, tile, 0, flags, topk_cand)
+    o = _opts(prec, None, tile, 0, flags, topk_cand, min_sim=min_sim)
     st = Stats()
     rc = lib().ejoin_topk(C.byref(r), C.byref(s), int(k), C.byref(o),
                           C.c_void_p(out_idx.data_ptr() if out_idx.numel() else 0),
@@ -321,19 +326,20 @@ def topk_raw(R, S, k, out_idx, out_score, ws, *, d=None, prec="bf16", topk_cand=
     return rc, st.as_dict()
 
 
-def topk(R, S, k: int, *, d=None, prec="bf16", topk_cand=0, timing=False, stream=None, tile=0):
+def topk(R, S, k: int, *, d=None, prec="bf16", topk_cand=0, timing=False, stream=None, tile=0,
+         min_sim=None):
     """Top-k E-join on the GPU: per R row the k most similar S rows, ordered by
     (sim64 desc, index asc).  Returns (idx int32 (|R|, k), score float32
     (|R|, k), stats); empty slots hold (-1, -inf)."""
     import torch
     dev = R.device
     nR = R.shape[0]
-    ws = torch.empty(topk_workspace(R, S, k, d=d, prec=prec, topk_cand=topk_cand, tile=tile),
-                     dtype=torch.uint8, device=dev)
+    ws = torch.empty(topk_workspace(R, S, k, d=d, prec=prec, topk_cand=topk_cand, tile=tile,
+                                    min_sim=min_sim), dtype=torch.uint8, device=dev)
     idx = torch.empty((nR, k), dtype=torch.int32, device=dev)
     sc = torch.empty((nR, k), dtype=torch.float32, device=dev)
     rc, st = topk_raw(R, S, k, idx, sc, ws, d=d, prec=prec, topk_cand=topk_cand,
-                      flags=TIMING if timing else 0, stream=stream, tile=tile)
+                      flags=TIMING if timing else 0, stream=stream, tile=tile, min_sim=min_sim)
     if rc != OK:
         raise EjoinError(rc, "ejoin_topk")
     return idx, sc, st
@@ -443,14 +449,14 @@ def threshold_sel(R, sel_r, S, sel_s, theta: float, *, d=None, prec="fp32", band
 
 
 def topk_sel(R, sel_r, S, sel_s, k: int, *, d=None, prec="bf16", topk_cand=0, timing=False,
-             flags=0, stream=None, tile=0):
+             flags=0, stream=None, tile=0, min_sim=None):
     """Top-k over the selected rows: output row i is the i-th selected R row;
     indices are S row ids.  Returns (idx, score, stats)."""
     import torch
     dev = R.device
     r, s = _rel(R, d), _rel(S, d)
     a, b = _sel(sel_r), _sel(sel_s)
-    o = _opts(prec, None, tile, 0, flags | (TIMING if timing else 0), topk_cand)
+    o = _opts(prec, None, tile, 0, flags | (TIMING if timing else 0), topk_cand, min_sim=min_sim)
     L = lib()
     need = L.ejoin_topk_sel_workspace(C.byref(r), _ref(a), C.byref(s), _ref(b), int(k),
                                       C.byref(o))

@@ -151,3 +151,18 @@ def test_bad_selections_are_refused():
     # a selection longer than its relation is refused on the host
     with pytest.raises(E.EjoinError):
         E.threshold_sel(R, _dev(np.arange(301, dtype=np.int32)), R, None, 0.5)
+
+
+def test_range_top_k_over_a_selection():
+    """The paper's range join with k = 32 after a pre-filter on S."""
+    cent = G.centres(300, 100, seed=9)
+    R, _ = G.clustered_points(cent, 300, 0.25, seed=10)
+    S, _ = G.clustered_points(cent, 20000, 0.25, seed=11)
+    attr = np.random.default_rng(12).random(S.shape[0]).astype(np.float32)
+    sel = E.select_range(_dev(attr), 0.0, 0.4)
+    is_ = _ids(attr < 0.4)
+    idx, sc, _ = E.topk_sel(_dev(R), None, _dev(S), sel, 32, prec="fp32", min_sim=0.9)
+    oi, osc = O.topk_range(R, S[is_], 32, 0.9)
+    want = np.where(oi >= 0, is_[np.maximum(oi, 0)], -1)
+    np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), want)
+    np.testing.assert_array_equal(sc.cpu().numpy(), osc.astype(np.float32))

@@ -223,3 +223,69 @@ def test_overflowed_rows_are_refined(prec, form):
     assert st["topk_refined"] > R.shape[0] // 2
     if prec != "fp8":
         assert st["n_fallback"] < R.shape[0] // 10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("form", ["panel", "tile"])
+@pytest.mark.parametrize("theta,k", [(0.9, 32), (0.93, 5), (0.5, 10), (-1.0, 7), (0.99, 3)])
+def test_range_with_k_cap(prec, form, theta, k):
+    """sim >= theta combined with the top-k condition: per row the first
+    min(k, m) of its m passing S rows, padded; decided in FP64 (scores exact,
+    indices exact, ties by index)."""
+    cent = G.centres(128, 20, seed=70)
+    R, _ = G.clustered_points(cent, 400, 0.3, seed=71)
+    S, _ = G.clustered_points(cent, 3000, 0.3, seed=72)
+    S[10:20] = S[0]
+    tile = (PANEL if form == "panel" else SQUARE)[prec]
+    idx, sc, st = E.topk(_dev(R), _dev(S), k, prec=prec, tile=tile, min_sim=theta)
+    oi, osc = O.topk_range(R, S, k, theta)
+    np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi)
+    np.testing.assert_array_equal(sc.cpu().numpy(), osc.astype(np.float32))
+    if theta > 0.9:
+        assert (oi < 0).any()        # rows with fewer than k passing S rows
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_range_with_k_cap_fallback_and_async(prec):
+    cent = G.centres(96, 5, seed=73)
+    R, _ = G.clustered_points(cent, 200, 0.3, seed=74)
+    S, _ = G.clustered_points(cent, 2000, 0.3, seed=75)
+    Rd, Sd = _dev(R), _dev(S)
+    oi, osc = O.topk_range(R, S, 8, 0.9)
+    # 8 slots for k = 8: overflow, refinement and exact scans with the bound
+    idx, sc, st = E.topk(Rd, Sd, 8, prec=prec, topk_cand=8, min_sim=0.9)
+    np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi)
+    np.testing.assert_array_equal(sc.cpu().numpy(), osc.astype(np.float32))
+    ws = torch.empty(E.topk_workspace(Rd, Sd, 8, prec=prec, topk_cand=8, min_sim=0.9),
+                     dtype=torch.uint8, device="cuda")
+    idx = torch.empty((200, 8), dtype=torch.int32, device="cuda")
+    sc = torch.empty((200, 8), dtype=torch.float32, device="cuda")
+    rc, _ = E.topk_raw(Rd, Sd, 8, idx, sc, ws, prec=prec, topk_cand=8, flags=E.NO_SYNC,
+                       min_sim=0.9)
+    torch.cuda.synchronize()
+    assert rc == E.OK
+    np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi)
+    with pytest.raises(E.EjoinError):
+        E.topk(Rd, Sd, 8, prec=prec, min_sim=float("nan"))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("nq", [1, 7, 100])
+def test_e_selection_query_batches(prec, nq):
+    """E-selection: a batch of query vectors as R against a relation,
+    answered by the same join (threshold, top-k and range + top-k)."""
+    cent = G.centres(200, 50, seed=80)
+    Q, _ = G.clustered_points(cent, nq, 0.3, seed=81)
+    S, _ = G.clustered_points(cent, 20000, 0.3, seed=82)
+    Qd, Sd = _dev(Q), _dev(S)
+    res = E.threshold(Qd, Sd, 0.85, prec=prec)
+    got = set(zip(res.r.cpu().tolist(), res.s.cpu().tolist()))
+    ri, si, _, _ = O.threshold(Q, S, 0.85)
+    assert got == set(zip(ri.tolist(), si.tolist()))
+    idx, sc, _ = E.topk(Qd, Sd, 12, prec=prec)
+    oi, osc = O.topk(Q, S, 12)
+    np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi)
+    idx, sc, _ = E.topk(Qd, Sd, 12, prec=prec, min_sim=0.9)
+    oi, osc = O.topk_range(Q, S, 12, 0.9)
+    np.testing.assert_array_equal(idx.cpu().numpy().astype(np.int64), oi)
+    np.testing.assert_array_equal(sc.cpu().numpy(), osc.astype(np.float32))

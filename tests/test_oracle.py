@@ -236,3 +236,39 @@ def test_paper_printed_sizes():
     assert math.isclose(dense, dn["approx_bytes"], rel_tol=1e-9)
     l1 = gold["l1_capacity"]
     assert l1["cache_bytes"] // (l1["dim"] * l1["bytes_per_value"]) == l1["vectors"]
+
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_topk_range_matches_exact_rational(seed):
+    """Range + top-k: the FP64 definition agrees with the exact-rational
+    brute force (ties planted by duplicate rows; thresholds inside the
+    similarity range so that rows have fewer, more or exactly k matches)."""
+    rng = np.random.default_rng(seed)
+    R = rng.standard_normal((7, 5)).astype(np.float32)
+    S = rng.standard_normal((23, 5)).astype(np.float32)
+    S[4] = S[9]
+    S[11] = 2 * S[3]
+    for theta in (-0.2, 0.1, 0.4, 0.95):
+        gi, gs = O.topk_range(R, S, 4, theta)
+        want = exact.topk_range(R, S, 4, theta)
+        np.testing.assert_array_equal(gi, want)
+        assert np.all(np.isfinite(gs) == (gi >= 0))
+        assert np.all(gs[gi >= 0] >= theta)
+
+
+def test_topk_range_reduces_to_topk_and_to_threshold():
+    """theta <= -1 keeps every column (plain top-k); k >= |S| gives each
+    row's whole threshold set, sorted."""
+    rng = np.random.default_rng(5)
+    R = rng.standard_normal((9, 12)).astype(np.float32)
+    S = rng.standard_normal((40, 12)).astype(np.float32)
+    gi, gs = O.topk_range(R, S, 6, -1.0)
+    ti, ts = O.topk(R, S, 6)
+    np.testing.assert_array_equal(gi, ti)
+    np.testing.assert_array_equal(gs, ts)
+    gi, gs = O.topk_range(R, S, 40, 0.2)
+    ri, si, sc, _ = O.threshold(R, S, 0.2)
+    for i in range(9):
+        m = ri == i
+        assert sorted(gi[i][gi[i] >= 0].tolist()) == sorted(si[m].tolist())
