@@ -95,6 +95,8 @@ typedef struct {
                                         theta - opts->prefilter_eps.  Approximate: the result
                                         of each job is a SUBSET of its exact join (every pair
                                         returned is exact); see ejoin_batch. */
+#define EJOIN_EXACT_PRUNE 0x10u  /* ejoin_batch: skip the 128 x 128 tile pairs whose every pair is
+                                    certified below theta (exact; see ejoin_batch) */
 #define EJOIN_TOPK_MIN_SIM 0x8u  /* top-k: only S rows with sim64 >= opts->topk_min_sim count
                                     (the range predicate combined with the top-k condition);
                                     rows with fewer passing S rows are padded */
@@ -370,6 +372,17 @@ size_t ejoin_batch_workspace(const ejoin_job *jobs, int32_t n_jobs, const ejoin_
  * caller's row numbers.  Tiles 19 and 22 contract the same tile pairs: a
  * panel sweeps only the kept S tiles of its 16-tile chunk, and chunks with
  * none are not visited.
+ * With EJOIN_EXACT_PRUNE (BF16, tile 3, 19, 22 or 0, every job of one dim up
+ * to 1024, eager calls only; not with EJOIN_APPROX_PREFILTER) the result is
+ * the exact join: the rows are ordered as above but by the codes of a fixed
+ * random +-1 projection to 64 dimensions, and a tile pair is skipped only
+ * when, in the original space, for T's mean direction d_T and angular radius
+ * A_T (largest angle of a row from d_T, widened by the rows' rounding error
+ * norms) and the largest d_T . s over U's rows (widened likewise),
+ *     cos(max(0, acos(max_s d_T . s) - A_T)) < theta,
+ * or the same with T and U exchanged; every pair of such a tile pair has
+ * cosine below theta.  Jobs with theta <= 0 are not pruned.
+ * stats->tiles_kept counts the contracted tile pairs.
  * Returns EJOIN_E_OVERFLOW if any job matched more pairs than its capacity
  * (that job's `out` holds an arbitrary capacity-sized subset; re-run it with
  * more room), EJOIN_E_WORKSPACE if the shared band list was too small

@@ -31,7 +31,7 @@ PER_FILE = {
     "panel.hip": ["-mno-amdgpu-ieee", "-fno-honor-nans"],
 }
 SOURCES = ["prep.hip", "gemm_threshold.hip", "panel.hip", "rescore.hip", "topk.hip", "batch.hip",
-           "select.hip", "nlj.hip",
+           "select.hip", "nlj.hip", "prune.hip",
            "mlp.hip", "prefilter.hip", "api.cpp", "api_batch.cpp", "api_mlp.cpp", "tune.cpp"]
 
 

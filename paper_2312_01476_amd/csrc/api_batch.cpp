@@ -65,8 +65,11 @@ struct BatchPlan {
     double band_max = 0.0;
     int64_t band_cap = 0, n_tiles = 0, n_rows = 0, pairs_total = 0;
     size_t off_table = 0, table_bytes = 0, off_hdrs = 0, off_band = 0, total = 0;
-    // prefilter mode
-    bool approx = false;
+    // prefilter mode (approx) and exact pruning (approx and exact: the same
+    // ordering and work-list machinery with certified bounds)
+    bool approx = false, exact = false;
+    int kp = 0;            // exact pruning: padded depth of the jobs (BF16 elements)
+    size_t off_proj = 0;   // exact pruning: the 64 x kp projection
     size_t off_hb = 0, off_z = 0, off_u = 0, off_key = 0, off_pa = 0, off_pb = 0, off_hist = 0,
            off_offs = 0, off_c = 0, off_rho = 0, off_cn = 0, off_alpha = 0, off_work = 0,
            off_ub = 0, off_aidx = 0, off_af = 0, off_ab = 0, off_lab = 0, off_up = 0,
@@ -89,7 +92,7 @@ size_t table_size(int table_jobs) {
 int pick_batch_tile(const ejoin_opts& o, const ejoin_job* jobs, int n) {
     if (o.tile > 0) return o.tile;
     // prefilter mode: 128 x 128 tiles or 128-row panels, the statistics' grain
-    if (o.flags & EJOIN_APPROX_PREFILTER)
+    if (o.flags & (EJOIN_APPROX_PREFILTER | EJOIN_EXACT_PRUNE))
         return o.prec == EJOIN_BF16 && n > 0 && panel_jobs_ok(jobs, n) ? 22 : 3;
     if (o.tuner && n > 0) {
         double pairs = 0.0;
@@ -111,10 +114,14 @@ int pick_batch_tile(const ejoin_opts& o, const ejoin_job* jobs, int n) {
 ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, int tile,
                              int table_jobs, char* ws, int64_t* n_out_dev, BatchPlan& bp) {
     if (n < 0 || n > 65536 || (n > 0 && !jobs) || table_jobs < n) return EJOIN_E_INVAL;
-    bp.approx = (o.flags & EJOIN_APPROX_PREFILTER) != 0;
+    bp.exact = (o.flags & EJOIN_EXACT_PRUNE) != 0;
+    bp.approx = (o.flags & EJOIN_APPROX_PREFILTER) != 0 || bp.exact;
+    if ((o.flags & EJOIN_APPROX_PREFILTER) && bp.exact) return EJOIN_E_INVAL;
     if (bp.approx) {
-        // the network reads BF16 prepared rows; tile statistics are per 128 rows
-        if (o.prec != EJOIN_BF16 || !o.prefilter || !(o.prefilter_eps >= 0.0f)) return EJOIN_E_INVAL;
+        // the network (or the projection) reads BF16 prepared rows; tile
+        // statistics are per 128 rows
+        if (o.prec != EJOIN_BF16) return EJOIN_E_INVAL;
+        if (!bp.exact && (!o.prefilter || !(o.prefilter_eps >= 0.0f))) return EJOIN_E_INVAL;
         if (tile != 3 && !batch_panel_tile(tile)) return EJOIN_E_INVAL;
         for (int i = 1; i < n; ++i)
             if (jobs && jobs[i].R.dim != jobs[0].R.dim) return EJOIN_E_INVAL;
@@ -268,14 +275,17 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         bp.off_pb = take(nr * 4);
         bp.off_hist = take(nr / 256 * 64 * 4);
         bp.off_offs = take(nr / 256 * 64 * 4);
+        bp.kp = n > 0 && jobs ? padded_k(EJOIN_BF16, jobs[0].R.dim) : MLP_OUT;
+        const size_t wid = bp.exact ? (size_t)bp.kp : (size_t)MLP_OUT;  // direction width
         bp.off_c = take(nr / 128 * MLP_OUT * 4);
         bp.off_rho = take(nr / 128 * 4);
         bp.off_cn = take(nr / 128 * 4);
         bp.off_alpha = take(nr / 128 * 4);
         bp.off_work = take((size_t)bp.n_tiles * 8);
+        bp.off_proj = take((size_t)MLP_OUT * wid * 2);
         bp.off_ub = take(nr * MLP_OUT * 2);
         bp.off_up = take(nr * MLP_OUT * 2);
-        bp.off_dir = take((nr / 128 + 128) * MLP_OUT * 2);
+        bp.off_dir = take((nr / 128 + 128) * wid * 2);
         bp.off_m1 = take((size_t)bp.n_tiles * 4);
         bp.off_m2 = take((size_t)bp.n_tiles * 4);
         if (batch_panel_tile(tile)) {
@@ -390,12 +400,11 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
     const int n_segs = ((const BatchHead*)bp.image.data())->n_segs;
     hipError_t e;
     auto rec = [&](int i) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
+    const int dim0 = bp.n_jobs ? ((const BatchJob*)(bp.image.data() + sizeof(BatchHead)))[0].dim : 1;
     ejoin_mlp_layout L;
-    if (ejoin_mlp_layout_get(bp.n_jobs ? ((const BatchJob*)(bp.image.data() + sizeof(BatchHead)))[0].dim : 1,
-                             &L) != EJOIN_OK)
-        return hipErrorInvalidValue;
+    if (ejoin_mlp_layout_get(dim0, &L) != EJOIN_OK) return hipErrorInvalidValue;
     MlpDev m;
-    {
+    if (!bp.exact) {
         char* b = (char*)o.prefilter;
         m.dim = L.dim;
         m.Dp = L.dim_pad;
@@ -409,10 +418,21 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
     if ((e = launch_batch_zero(head, bctr, st)) != hipSuccess) return e;
     if ((e = launch_batch_prep(bp.prec, head, segs, pg, false, st)) != hipSuccess) return e;
     int32_t* perm_a = (int32_t*)(ws + bp.off_pa);
-    if ((e = launch_pf_codes(head, segs, bp.n_rows, m, (uint16_t*)(ws + bp.off_hb),
-                             (float*)(ws + bp.off_z), (float*)(ws + bp.off_u),
-                             (uint16_t*)(ws + bp.off_ub), st)) != hipSuccess)
+    if (bp.exact) {
+        // codes of the fixed projection, normalised
+        if ((e = launch_xp_codes(head, segs, bp.n_rows, dim0, bp.kp,
+                                 (uint16_t*)(ws + bp.off_proj), (float*)(ws + bp.off_z), st)) !=
+            hipSuccess)
+            return e;
+        if ((e = launch_pf_normalise(head, segs, bp.n_rows, (const float*)(ws + bp.off_z),
+                                     (float*)(ws + bp.off_u), (uint16_t*)(ws + bp.off_ub), st)) !=
+            hipSuccess)
+            return e;
+    } else if ((e = launch_pf_codes(head, segs, bp.n_rows, m, (uint16_t*)(ws + bp.off_hb),
+                                    (float*)(ws + bp.off_z), (float*)(ws + bp.off_u),
+                                    (uint16_t*)(ws + bp.off_ub), st)) != hipSuccess) {
         return e;
+    }
     if (bp.n_anchor > 0) {
         if ((e = hipMemcpyAsync(ws + bp.off_aidx, bp.anchor_idx.data(), bp.n_anchor * 8,
                                 hipMemcpyHostToDevice, st)) != hipSuccess)
@@ -431,7 +451,16 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
                             (int32_t*)(ws + bp.off_offs), st)) != hipSuccess)
         return e;
     if ((e = launch_batch_prep(bp.prec, head, segs, pg, true, st)) != hipSuccess) return e;
-    if ((e = launch_pf_tiles(head, segs, jobs, bp.n_rows, (const float*)(ws + bp.off_u), perm_a,
+    if (bp.exact) {
+        if ((e = launch_xp_tiles(head, segs, jobs, bp.n_rows, bp.kp, (uint16_t*)(ws + bp.off_dir),
+                                 (float*)(ws + bp.off_alpha), (float*)(ws + bp.off_rho),
+                                 (float*)(ws + bp.off_m1), (float*)(ws + bp.off_m2), bp.n_side,
+                                 (int64_t*)(ws + bp.off_work), bctr + B_WORK, bp.n_tiles,
+                                 batch_panel_tile(bp.tile) ? (uint8_t*)(ws + bp.off_keep)
+                                                           : nullptr,
+                                 st)) != hipSuccess)
+            return e;
+    } else if ((e = launch_pf_tiles(head, segs, jobs, bp.n_rows, (const float*)(ws + bp.off_u), perm_a,
                              (float*)(ws + bp.off_c), (float*)(ws + bp.off_rho),
                              (float*)(ws + bp.off_cn), (float*)(ws + bp.off_alpha),
                              (uint16_t*)(ws + bp.off_up), (uint16_t*)(ws + bp.off_dir),
@@ -575,7 +604,7 @@ ejoin_status ejoin_batch_graph_create(int32_t max_jobs, const ejoin_opts* opts, 
     ejoin_opts o = opts_or_default(opts);
     o.flags |= EJOIN_NO_SYNC;
     if (o.prec < EJOIN_FP32 || o.prec > EJOIN_FP8_E4M3) return EJOIN_E_INVAL;
-    if (o.flags & EJOIN_APPROX_PREFILTER) return EJOIN_E_UNSUPPORTED;
+    if (o.flags & (EJOIN_APPROX_PREFILTER | EJOIN_EXACT_PRUNE)) return EJOIN_E_UNSUPPORTED;
     const int tile = o.tile > 0 ? o.tile : batch_default_tile(o.prec);
     const TileDesc* td = tile_get(tile);
     if (!td || td->prec != o.prec || !batch_has_tile(tile)) return EJOIN_E_INVAL;

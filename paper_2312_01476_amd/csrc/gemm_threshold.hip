@@ -159,6 +159,9 @@ static const TileDesc kTiles[] = {
     {22, P_BF16, 128, 128, 64, "bf16:panel/batch/2wg"},
     // the nested-loop comparator: one pair per wavefront, no tiling
     {kTileNlj, P_FP32, 0, 0, 32, "fp32:nlj"},
+    // register panels with two 32-row blocks per wave (rows of 3-6 K slices)
+    {24, P_BF16, 0, 0, 64, "bf16:panel/rb2"},
+    {25, P_FP8, 0, 0, 128, "fp8:panel/rb2"},
 };
 
 int tile_count() { return (int)(sizeof(kTiles) / sizeof(kTiles[0])); }
@@ -199,12 +202,14 @@ hipError_t launch_threshold(int tile_id, const ThresholdArgs& a, hipStream_t st)
         case 9: return run<P_FP8, 256, 256, 2, 2>(a, st);
         case 10: return run<P_FP8, 256, 256, 2, 4>(a, st);
         case 11: return run<P_FP32, 256, 128, 2, 2>(a, st);
-        case 12: return launch_threshold_panel(P_BF16, false, a, st);
-        case 13: return launch_threshold_panel(P_FP8, false, a, st);
-        case 14: return launch_threshold_panel(P_BF16, true, a, st);
-        case 15: return launch_threshold_panel(P_FP8, true, a, st);
-        case 20: return launch_threshold_panel(P_FP32, false, a, st);
-        case 21: return launch_threshold_panel(P_FP32, true, a, st);
+        case 12: return launch_threshold_panel(P_BF16, 0, a, st);
+        case 13: return launch_threshold_panel(P_FP8, 0, a, st);
+        case 14: return launch_threshold_panel(P_BF16, 1, a, st);
+        case 15: return launch_threshold_panel(P_FP8, 1, a, st);
+        case 20: return launch_threshold_panel(P_FP32, 0, a, st);
+        case 21: return launch_threshold_panel(P_FP32, 1, a, st);
+        case 24: return launch_threshold_panel(P_BF16, 2, a, st);
+        case 25: return launch_threshold_panel(P_FP8, 2, a, st);
         case 16: return run<P_BF16, 256, 256, 2, 2, true>(a, st);
         case 17: return run<P_FP8, 256, 256, 2, 2, true>(a, st);
         case 18: return run<P_FP32, 256, 256, 2, 2, true>(a, st);

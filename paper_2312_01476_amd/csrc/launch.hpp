@@ -51,7 +51,9 @@ hipError_t launch_threshold(int tile_id, const ThresholdArgs& a, hipStream_t st)
 // per wavefront, no tiling; never chosen by the planner or the tuner
 constexpr int kTileNlj = 23;
 hipError_t launch_threshold_nlj(const ThresholdArgs& a, hipStream_t st);
-hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs& a,
+// form 0: one workgroup per CU, 1: two workgroups per CU, 2: two 32-row
+// blocks per wave (BF16 / FP8 rows of 3 to 6 K slices)
+hipError_t launch_threshold_panel(int prec, int form, const ThresholdArgs& a,
                                   hipStream_t st);
 
 // top-k candidate sweep (panel kernel with the candidate epilogue)

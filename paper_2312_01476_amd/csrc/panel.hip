@@ -906,13 +906,29 @@ static hipError_t run_panel(const void* A, const void* B, const RowInfo* info_r,
 //    slot per K slice (three for KS = 3); else four waves with two row blocks
 //    each.
 template <int PREC, template <int> class EPI>
-static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const void* B,
+static hipError_t dispatch_panel(int ks, int form, const void* A, const void* B,
                                  const RowInfo* ir, const RowInfo* is, int64_t nR, int64_t nS,
                                  bool split_s, const unsigned long long* hdr,
                                  const typename EPI<4>::Params& ep, hipStream_t st) {
 #define EJ_RUN(KS_, RB_, CB_, NW_, OCC_, NSLOT_)                                          \
     return run_panel<PREC, KS_, RB_, CB_, NW_, OCC_, NSLOT_, EPI<NW_>>(A, B, ir, is, nR, nS, \
                                                                        split_s, hdr, ep, st)
+    if (form == 2) {
+        // two 32-row blocks per wave, one wave per SIMD: every B fragment read
+        // from LDS feeds two MFMAs (half the LDS traffic per flop of the
+        // one-block forms); R fragments and accumulators take up to 352 of
+        // the 512 registers a lone wave has
+        if constexpr (PREC != P_FP32) {
+            switch (ks) {
+                case 3: EJ_RUN(3, 2, 4, 4, 1, 3);
+                case 4: EJ_RUN(4, 2, 4, 4, 1, 4);
+                case 5: EJ_RUN(5, 2, 4, 4, 1, 5);
+                case 6: EJ_RUN(6, 2, 4, 4, 1, 6);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
+    const bool two_waves = form == 1;
     if (two_waves) {
         if constexpr (PREC == P_FP32) {
             // two workgroups per CU, each with its own ring, so that one
@@ -1009,7 +1025,7 @@ static hipError_t dispatch_panel(int ks, bool two_waves, const void* A, const vo
 static int row_bytes(int prec, int Kp) { return Kp * (prec == P_FP32 ? 4 : prec == P_BF16 ? 2 : 1); }
 static int slices(int prec, int Kp) { return row_bytes(prec, Kp) / 128; }
 
-hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs& a,
+hipError_t launch_threshold_panel(int prec, int form, const ThresholdArgs& a,
                                   hipStream_t st) {
     const int kpb = row_bytes(prec, a.Kp);
     if (kpb % 128 != 0) return hipErrorInvalidValue;
@@ -1027,13 +1043,13 @@ hipError_t launch_threshold_panel(int prec, bool two_waves, const ThresholdArgs&
     ep.perm_s = nullptr;
     const int ks = slices(prec, a.Kp);
     if (prec == P_BF16)
-        return dispatch_panel<P_BF16, ThresholdEpi>(ks, two_waves, a.A, a.B, a.info_r, a.info_s,
+        return dispatch_panel<P_BF16, ThresholdEpi>(ks, form, a.A, a.B, a.info_r, a.info_s,
                                                     a.nR, a.nS, true, a.hdr, ep, st);
     if (prec == P_FP8)
-        return dispatch_panel<P_FP8, ThresholdEpi>(ks, two_waves, a.A, a.B, a.info_r, a.info_s,
+        return dispatch_panel<P_FP8, ThresholdEpi>(ks, form, a.A, a.B, a.info_r, a.info_s,
                                                    a.nR, a.nS, true, a.hdr, ep, st);
     if (prec == P_FP32)
-        return dispatch_panel<P_FP32, ThresholdEpi>(ks, two_waves, a.A, a.B, a.info_r, a.info_s,
+        return dispatch_panel<P_FP32, ThresholdEpi>(ks, form, a.A, a.B, a.info_r, a.info_s,
                                                     a.nR, a.nS, true, a.hdr, ep, st);
     return hipErrorInvalidValue;
 }
@@ -1072,7 +1088,7 @@ hipError_t launch_topk_candidates(int prec, const CandArgs& a, hipStream_t st) {
             case 5: EJ_RUN(P_BF16, 5, 1, 4, 8, 1, 5);
             case 6: EJ_RUN(P_BF16, 6, 1, 4, 8, 1, 6);
         }
-        return dispatch_panel<P_BF16, CandEpi>(ks, true, a.A, a.B, a.info_r, a.info_s, a.nR,
+        return dispatch_panel<P_BF16, CandEpi>(ks, 1, a.A, a.B, a.info_r, a.info_s, a.nR,
                                                a.nS, false, a.hdr, ep, st);
     }
     if (prec == P_FP8) {
@@ -1082,11 +1098,11 @@ hipError_t launch_topk_candidates(int prec, const CandArgs& a, hipStream_t st) {
             case 5: EJ_RUN(P_FP8, 5, 1, 2, 8, 1, 5);
             case 6: EJ_RUN(P_FP8, 6, 1, 2, 8, 1, 6);
         }
-        return dispatch_panel<P_FP8, CandEpi>(ks, true, a.A, a.B, a.info_r, a.info_s, a.nR,
+        return dispatch_panel<P_FP8, CandEpi>(ks, 1, a.A, a.B, a.info_r, a.info_s, a.nR,
                                               a.nS, false, a.hdr, ep, st);
     }
     if (prec == P_FP32)  // two workgroups per CU (the FP32 threshold default)
-        return dispatch_panel<P_FP32, CandEpi>(ks, true, a.A, a.B, a.info_r, a.info_s, a.nR,
+        return dispatch_panel<P_FP32, CandEpi>(ks, 1, a.A, a.B, a.info_r, a.info_s, a.nR,
                                                a.nS, false, a.hdr, ep, st);
 #undef EJ_RUN
     return hipErrorInvalidValue;

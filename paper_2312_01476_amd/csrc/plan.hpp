@@ -89,6 +89,7 @@ inline bool rel_ok(const ejoin_rel* X) {
 // Row depths (K bytes) a panel tile takes: up to 768; the one-workgroup BF16
 // and the FP32 panels (tiles 12, 20, 21) also 1024, 1152, 1280 and 1536.
 inline bool panel_fits(int tile, int kpb) {
+    if (tile == 24 || tile == 25) return kpb >= 384 && kpb <= 768;  // 3 to 6 K slices
     if (kpb <= 768) return true;
     return (tile == 12 || tile == 14 || tile == 20 || tile == 21) &&
            (kpb == 1024 || kpb == 1152 || kpb == 1280 || kpb == 1536);

@@ -661,6 +661,14 @@ hipError_t launch_pf_codes(const BatchHead* head, const PrepSeg* segs, int64_t n
     return hipGetLastError();
 }
 
+hipError_t launch_pf_normalise(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
+                               const float* Z, float* U, uint16_t* Ub, hipStream_t st) {
+    if (n_rows <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n_rows + 3) / 4, 16384);
+    hipLaunchKernelGGL(pf_code, dim3((unsigned)blocks), dim3(256), 0, st, head, segs, Z, U, Ub);
+    return hipGetLastError();
+}
+
 hipError_t launch_pf_keys(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
                           const float* U, const uint16_t* Ub, const int64_t* anchor_idx, int K,
                           float tau, float* Af, uint16_t* Ab, uint64_t* abits, int32_t* label,

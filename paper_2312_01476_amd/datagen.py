@@ -203,6 +203,12 @@ WORKLOADS = {
                                        "mlp_seed": 601, "train_steps": 300,
                                        "train_batch": 4096, "eps": 0.05},
                                 notes="64 uneven joins, 768-d, learned prefilter (approximate)"),
+    # the same 64 joins with exact tile pruning (certified bounds in the
+    # original space; the result is the exact join)
+    "batch64_exact": Workload("batch64_exact", 0, 0, 768, 768, 1000, 0.3, prec="bf16",
+                              seeds=(500, 0, 0),
+                              extra={"batch": 64, "job_seed": 501, "exact_prune": True},
+                              notes="64 uneven joins, 768-d, bf16, exact tile pruning"),
     # the scan side of the scan-versus-probe study: 10k query tuples joined
     # with 1M data tuples after a relational pre-filter on the data side
     # (selectivity 1-100% of an attribute drawn uniformly in [0, 1)), range

@@ -21,6 +21,7 @@ NO_SYNC = 0x1
 TIMING = 0x2
 APPROX_PREFILTER = 0x4
 TOPK_MIN_SIM = 0x8
+EXACT_PRUNE = 0x10
 
 
 class Rel(C.Structure):
@@ -492,10 +493,10 @@ def _jobs(jobs, outs, caps, d):
 
 
 def batch_workspace(jobs, *, d=None, prec="fp32", band=None, tile=0, band_capacity=0,
-                    tuner=None, prefilter=None, eps=0.0):
+                    tuner=None, prefilter=None, eps=0.0, flags=0):
     """Workspace bytes for ejoin_batch; ``jobs`` is a list of (R, S, theta)."""
     arr = _jobs(jobs, None, [0] * len(jobs), d)
-    o = _opts(prec, band, tile, band_capacity, 0, tuner=tuner, prefilter=prefilter, eps=eps)
+    o = _opts(prec, band, tile, band_capacity, flags, tuner=tuner, prefilter=prefilter, eps=eps)
     n = lib().ejoin_batch_workspace(arr, len(jobs), C.byref(o))
     if n == 0:
         raise EjoinError(E_INVAL, "ejoin_batch_workspace")
@@ -517,7 +518,7 @@ def batch_raw(jobs, outs, caps, ws, n_out, *, d=None, prec="fp32", band=None, ti
 
 
 def batch(jobs, *, d=None, prec="fp32", band=None, tile=0, capacities=None, band_capacity=0,
-          timing=False, stream=None, tuner=None, prefilter=None, eps=0.0):
+          timing=False, stream=None, tuner=None, prefilter=None, eps=0.0, exact_prune=False):
     """Run many threshold joins as one batch pass.  ``jobs``: list of
     (R, S, theta).  Returns (list of Pairs, stats dict).  Jobs whose output
     overflowed are run again (as a smaller batch) with exactly enough room."""
@@ -532,13 +533,14 @@ def batch(jobs, *, d=None, prec="fp32", band=None, tile=0, capacities=None, band
     results = [None] * n
     todo = list(range(n))
     stats = {}
-    flags = TIMING if timing else 0
+    flags = (TIMING if timing else 0) | (EXACT_PRUNE if exact_prune else 0)
     for _ in range(6):
         sub = [jobs[i] for i in todo]
         sub_caps = [caps[i] for i in todo]
         ws = torch.empty(batch_workspace(sub, d=d, prec=prec, band=band, tile=tile,
                                          band_capacity=band_capacity, tuner=tuner,
-                                         prefilter=prefilter, eps=eps),
+                                         prefilter=prefilter, eps=eps,
+                                         flags=flags & EXACT_PRUNE),
                          dtype=torch.uint8, device=dev)
         outs = [torch.empty((max(c, 1), 3), dtype=torch.int32, device=dev) for c in sub_caps]
         n_out = torch.zeros(len(sub), dtype=torch.int64)

@@ -1,0 +1,96 @@
+"""Exact tile pruning of the batched join (EJOIN_EXACT_PRUNE) against the
+oracle.
+
+The pruned pass must return exactly each job's threshold join: the skipped
+tile pairs are certified below theta by the tile-to-rows bound in the
+original embedding space (pinned against brute force on the CPU in
+tests/test_oracle_mlp.py), with margins for the BF16 rounding of the rows.
+The data are clustered tightly enough that many tile pairs are skipped, with
+thresholds across the similarity range, planted pairs just above and below
+theta across clusters, zero rows and a theta <= 0 job (never pruned).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2312_01476_amd import datagen as G
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+E = None
+
+
+def setup_module(module):
+    global E
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_01476_amd import ejoin
+    E = ejoin
+
+
+def _jobs(D, seed):
+    cent = G.centres(D, 12, seed)
+    shapes = [(3000, 1500), (900, 2500), (1200, 1200), (257, 700), (0, 300), (2000, 129)]
+    thetas = [0.80, 0.85, 0.75, 0.90, 0.8, 0.70]
+    host = []
+    for i, ((nr, ns), th) in enumerate(zip(shapes, thetas)):
+        R = G.clustered_points(cent, nr, 0.25, seed * 100 + 2 * i)[0] if nr else \
+            np.zeros((0, D), np.float32)
+        S = G.clustered_points(cent, ns, 0.25, seed * 100 + 2 * i + 1)[0]
+        host.append([R, S, th])
+    # planted pairs across clusters just above / below theta of job 1
+    R, S, th = host[1]
+    rng = np.random.default_rng(seed)
+    for q in range(20):
+        a, b = rng.integers(0, R.shape[0]), rng.integers(0, S.shape[0])
+        u = R[a].astype(np.float64)
+        u /= np.linalg.norm(u)
+        w = rng.standard_normal(D)
+        w -= (w @ u) * u
+        w /= np.linalg.norm(w)
+        c = th + (1e-6 if q % 2 == 0 else -1e-6)
+        S[b] = (c * u + np.sqrt(1 - c * c) * w).astype(np.float32)
+    R[5] = 0.0                                   # a zero row
+    X = G.clustered_points(cent, 1500, 0.25, seed * 100 + 77)[0]
+    host.append([X, X, 0.82])
+    host.append([G.clustered_points(cent, 400, 0.25, seed * 100 + 78)[0],
+                 G.clustered_points(cent, 300, 0.25, seed * 100 + 79)[0], -0.05])
+    return host
+
+
+def _run(host, **kw):
+    jobs = []
+    for R, S, th in host:
+        Rd = torch.from_numpy(R).cuda()
+        jobs.append((Rd, Rd if S is R else torch.from_numpy(S).cuda(), th))
+    caps = [max(1, R.shape[0] * S.shape[0]) for R, S, _ in host]
+    return E.batch(jobs, prec="bf16", capacities=caps, **kw)
+
+
+@pytest.mark.parametrize("D,tile", [(96, 3), (640, 22), (640, 19)])
+def test_exact_pruning_returns_the_exact_join(D, tile):
+    host = _jobs(D, seed=4)
+    res, st = _run(host, tile=tile, exact_prune=True)
+    assert st["tile"] == tile
+    assert st["tiles_kept"] < 0.8 * st["tiles_total"], (st["tiles_kept"], st["tiles_total"])
+    for q, ((R, S, th), got) in enumerate(zip(host, res)):
+        ri, si, _, _ = O.threshold(R, S, th)
+        want = set(zip(ri.tolist(), si.tolist()))
+        got = set(zip(got.r.cpu().tolist(), got.s.cpu().tolist()))
+        assert got == want, (q, len(want - got), len(got - want))
+
+
+def test_exact_pruning_equals_the_plain_batch_and_is_refused_where_unsupported():
+    host = _jobs(96, seed=5)
+    plain, st0 = _run(host, tile=3)
+    pruned, st1 = _run(host, tile=3, exact_prune=True)
+    assert st1["tiles_kept"] < st1["tiles_total"] == st0["tiles_total"]
+    for a, b in zip(plain, pruned):
+        assert set(zip(a.r.cpu().tolist(), a.s.cpu().tolist())) == \
+            set(zip(b.r.cpu().tolist(), b.s.cpu().tolist()))
+    R0, S0 = torch.from_numpy(host[0][0]).cuda(), torch.from_numpy(host[0][1]).cuda()
+    with pytest.raises(E.EjoinError):          # FP32 has no pruned form
+        E.batch([(R0, S0, 0.8)], prec="fp32", exact_prune=True)
+    with pytest.raises(E.EjoinError):          # nor the 256 x 256 tile
+        E.batch([(R0, S0, 0.8)], prec="bf16", tile=16, exact_prune=True)

@@ -207,7 +207,7 @@ def test_tile_shapes_give_identical_sets_fp32(tile):
     _check(R, S, w.theta, d=w.d, tile=tile)
 
 
-@pytest.mark.parametrize("tile", [3, 4, 8, 12, 14, 16])
+@pytest.mark.parametrize("tile", [3, 4, 8, 12, 14, 16, 24])
 def test_tile_shapes_bf16(tile):
     w = G.WORKLOADS["bf16_1m"]
     R, S, lr, ls = G.make_host(w, n_r=2000, n_s=3000)
@@ -215,7 +215,7 @@ def test_tile_shapes_bf16(tile):
     assert st["n_pairs"] == int((lr[:, None] == ls[None, :]).sum())
 
 
-@pytest.mark.parametrize("tile", [5, 6, 10, 13, 17])
+@pytest.mark.parametrize("tile", [5, 6, 10, 13, 17, 25])
 def test_tile_shapes_fp8(tile):
     w = G.WORKLOADS["fp8_topk_2m"]
     R, S, lr, ls = G.make_host(w, n_r=1000, n_s=1500)

@@ -288,3 +288,26 @@ def test_prefilter_plan_invariants():
         assert np.array_equal(J["keep"], J["bound"] >= th - 0.1)
     k0 = pl["keys"][1]
     assert np.all(np.diff(k0[pl["jobs"][0]["order_r"]]) >= 0)
+
+
+
+def test_tile_rows_bound_in_the_embedding_space():
+    """The same bound on 300-d unit rows (the exact pruning of the batched
+    join uses it in the original space): it dominates every pair's cosine of
+    clustered tiles, and it separates tiles of different clusters."""
+    rng = np.random.default_rng(31)
+    cent = rng.standard_normal((4, 300))
+    cent /= np.linalg.norm(cent, axis=1, keepdims=True)
+    V = np.repeat(cent, 32, axis=0) + 0.25 / np.sqrt(300) * rng.standard_normal((128, 300))
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    C, _ = M.tile_stats(V, 32)
+    A = M.tile_angles(V, 32)
+    separated = 0
+    for i in range(4):
+        di = C[i] / np.linalg.norm(C[i])
+        for j in range(4):
+            bj = V[j * 32:(j + 1) * 32]
+            b = M.tile_rows_bound(di, A[i], bj)
+            assert b >= (V[i * 32:(i + 1) * 32] @ bj.T).max() - 1e-12
+            separated += i != j and b < 0.75
+    assert separated == 12
