@@ -107,8 +107,11 @@ typedef struct ejoin_tuner ejoin_tuner;
 typedef struct {
     int32_t prec;           /* ejoin_prec */
     int32_t tile;           /* 0: planner's choice; otherwise a tile id from ejoin_tile_name */
-    double band;            /* < 0: the rigorous default for prec and dim; otherwise the band
-                               half-width (must be >= the rigorous bound, else EJOIN_E_INVAL) */
+    double band;            /* < 0: the default: the rigorous bound for prec and dim, which
+                               BF16 / FP8 single threshold joins narrow on the device with
+                               the largest quantisation error norm measured on each side
+                               (stats->band reports it); otherwise the band half-width (must
+                               be >= the rigorous bound, else EJOIN_E_INVAL) */
     int64_t band_capacity;  /* <= 0: default; number of band pairs the workspace can hold */
     uint32_t flags;         /* EJOIN_* flags */
     int32_t topk_cand;      /* top-k: per-row candidate capacity (<= 0: default) */

@@ -34,7 +34,7 @@ ejoin_status make_plan(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts*
     p.padS = p.alias ? p.padR : padded_rows(p.nS);
     const double rig = band_rigorous(p.prec, p.dim);
     if (o->band < 0) {
-        p.band = rig;  // FP8: refined on the device from the measured error norms
+        p.band = rig;  // BF16 / FP8 single joins: narrowed on the device (threshold_run)
     } else {
         if (!(o->band >= rig) || !isfinite(o->band)) return EJOIN_E_INVAL;
         p.band = o->band;
@@ -553,6 +553,13 @@ ejoin_status threshold_run(const ejoin_rel* R, const ejoin_rel* S, double theta,
     a.nS = p.nS;
     a.lo = round_down_f(theta - p.band);
     a.hi = round_up_f(theta + p.band);
+    // the default band of the narrow formats: measured on the device from the
+    // rows' quantisation error norms (never wider than the rigorous bound)
+    const bool measured = o.band < 0 && p.prec != P_FP32;
+    if (measured) {
+        HIP_TRY(launch_band_edges(hdr, theta, band_fp32_terms(p.Kp), p.band, p.alias, stream));
+        a.lohi = hdr + H_LO;
+    }
     a.out = (Pair*)out;
     a.capacity = capacity;
     a.band = band;
@@ -585,6 +592,7 @@ ejoin_status threshold_run(const ejoin_rel* R, const ejoin_rel* S, double theta,
     if (h[H_FLAGS] & F_RANGE) return EJOIN_E_RANGE;
     *n_out = (int64_t)h[H_OUT];
     if (stats) {
+        if (measured) stats->band = __builtin_bit_cast(double, (uint64_t)h[H_BAND_W]);
         stats->n_pairs = (int64_t)h[H_OUT];
         stats->n_band = (int64_t)h[H_BAND];
         stats->n_band_accepted = (int64_t)h[H_BAND_ACC];

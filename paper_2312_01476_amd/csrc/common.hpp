@@ -27,6 +27,9 @@ enum : int {
     H_TOPK_F = 8,     // top-k candidate floor (float bits)
     H_TOPK_FB = 9,    // top-k rows sent to the exact fallback
     H_TOPK_EMAX = 10, // top-k: largest per-row error bound (float bits)
+    H_LO = 11,        // threshold band edges from the measured error norms (float bits)
+    H_HI = 12,
+    H_BAND_W = 13,    // the band half-width they come from (double bits)
     H_COUNT = 32      // header size in int64 (256 bytes)
 };
 

@@ -15,13 +15,17 @@ __global__ __launch_bounds__(WM* WN * 64, (BM * BN <= 128 * 128) ? 2 : 1) void t
     const RowInfo* __restrict__ info_s, int Kp_bytes, int64_t nR, int64_t nS,
     int tiles_m, int tiles_n, int ntiles, float lo, float hi, Pair* __restrict__ out,
     int64_t capacity, int2* __restrict__ band, int64_t band_cap,
-    unsigned long long* __restrict__ hdr, int kg_last) {
+    unsigned long long* __restrict__ hdr, int kg_last, int lohi_dev) {
     EJ_TILE_SMEM(BM, BN, WM * WN, sm);
     // 2-D grid (a 1-D grid of this many workgroups would overflow the 32-bit
     // dispatch size); workgroups past the last tile leave at once
     int bid = (int)(blockIdx.y * gridDim.x + blockIdx.x);
     if (bid >= ntiles) return;
     if (hdr[H_FLAGS] != 0) return;  // bad input rows: nothing to compute
+    if (lohi_dev) {  // band edges measured on the device after prep
+        lo = __uint_as_float((uint32_t)hdr[H_LO]);
+        hi = __uint_as_float((uint32_t)hdr[H_HI]);
+    }
     // Workgroups are dispatched to the 8 XCDs round-robin; remapping gives
     // each XCD a contiguous range of tiles, so the tiles that run together
     // on one XCD share operand panels in that XCD's L2.
@@ -185,7 +189,7 @@ static hipError_t run(const ThresholdArgs& a, hipStream_t st) {
                        dim3(WM * WN * 64), 0, st, (const char*)a.A, (const char*)a.B, a.info_r,
                        a.info_s, kpb, a.nR,
                        a.nS, (int)tm, (int)tn, (int)nblocks, a.lo, a.hi, a.out, a.capacity, a.band, a.band_cap,
-                       a.hdr, a.kg_last);
+                       a.hdr, a.kg_last, a.lohi ? 1 : 0);
     return hipGetLastError();
 }
 

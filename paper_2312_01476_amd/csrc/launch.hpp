@@ -39,6 +39,9 @@ struct ThresholdArgs {
     int Kp;
     int64_t nR, nS;
     float lo, hi;    // approximate-score band edges (rounded outward)
+    // when set: the edges measured on the device (lohi[0], lohi[1] as float
+    // bits, written by launch_band_edges after prep) replace lo, hi
+    const unsigned long long* lohi = nullptr;
     Pair* out;
     int64_t capacity;
     int2* band;
@@ -151,6 +154,12 @@ size_t select_range_workspace();
 hipError_t launch_select_range(const float* col, int64_t n, float lo, float hi, int32_t* ids,
                                int64_t* n_sel, void* ws, hipStream_t st);
 
+// Band edges from the measured quantisation error norms (hdr[H_ENORM_R/S]):
+// delta = eR (1 + eS) + eS + f (1 + eR)(1 + eS), at most `rigorous`; writes
+// round_down(theta - delta), round_up(theta + delta) to hdr[H_LO], hdr[H_HI]
+// and delta to hdr[H_BAND_W].
+hipError_t launch_band_edges(unsigned long long* hdr, double theta, double fp32_terms,
+                             double rigorous, bool alias, hipStream_t st);
 hipError_t launch_copy_count(const unsigned long long* hdr, int64_t band_cap, int64_t* dst,
                              hipStream_t st);
 

@@ -68,6 +68,9 @@ struct TileCtx {
 // ---------------------------------------------------------------------------
 struct ThresholdParams {
     float lo, hi;
+    // when set: the band edges are read from lohi[0], lohi[1] (float bits)
+    // at the start of the sweep instead of lo, hi
+    const unsigned long long* lohi;
     Pair* out;
     int64_t capacity;
     unsigned long long* out_ctr;   // pairs appended to out
@@ -91,11 +94,14 @@ struct ThresholdEpiT {
     };
     struct State {
         int n_out, n_band;  // staged entries of this wave (wave-uniform)
+        float lo, hi;       // band edges of this sweep
     };
 
-    __device__ static __forceinline__ void init(const Params&, Smem&, State& s, const TileCtx&) {
+    __device__ static __forceinline__ void init(const Params& p, Smem&, State& s, const TileCtx&) {
         s.n_out = 0;
         s.n_band = 0;
+        s.lo = p.lohi ? __uint_as_float((uint32_t)p.lohi[0]) : p.lo;
+        s.hi = p.lohi ? __uint_as_float((uint32_t)p.lohi[1]) : p.hi;
     }
 
     // Phase 1 (no branches): one wave mask per group of four accumulators
@@ -124,7 +130,7 @@ struct ThresholdEpiT {
                     const float m4 =
                         __builtin_fmaxf(__builtin_fmaxf(acc[rb][cb][e4], acc[rb][cb][e4 + 1]),
                                         __builtin_fmaxf(acc[rb][cb][e4 + 2], acc[rb][cb][e4 + 3]));
-                    gmask[rb][cb][q4] = __ballot(m4 >= p.lo);
+                    gmask[rb][cb][q4] = __ballot(m4 >= s.lo);
                 }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
@@ -148,7 +154,7 @@ struct ThresholdEpiT {
                     for (int k = 0; k < 4; ++k) {
                         const int gi = gi0 + rb * 32 + 8 * q4 + k;
                         const bool v = vj && (!c.edge || gi < nR32);
-                        ml[k] = __ballot(v && acc[rb][cb][e4 + k] >= p.lo);
+                        ml[k] = __ballot(v && acc[rb][cb][e4 + k] >= s.lo);
                     }
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
@@ -156,7 +162,7 @@ struct ThresholdEpiT {
                         const float a = acc[rb][cb][e4 + k];
                         const int gi = gi0 + rb * 32 + 8 * q4 + k;
                         const bool in_lo = (ml[k] >> c.lane) & 1ull;
-                        const bool in_hi = in_lo && a >= p.hi;
+                        const bool in_hi = in_lo && a >= s.hi;
                         const uint64_t mhi = __ballot(in_hi);
                         const uint64_t mb = ml[k] & ~mhi;
                         int ri = gi, si = gj;
@@ -686,6 +692,7 @@ __global__ __launch_bounds__(256, 1) void batch_panel(const BatchHead* __restric
         ThresholdParams ep;
         ep.lo = J.lo;
         ep.hi = J.hi;
+        ep.lohi = nullptr;
         ep.out = J.out;
         ep.capacity = J.capacity;
         ep.out_ctr = J.hdr + H_OUT;
@@ -800,6 +807,7 @@ __global__ __launch_bounds__(256, 2) void batch_panel2(const BatchHead* __restri
         ThresholdParams ep;
         ep.lo = J.lo;
         ep.hi = J.hi;
+        ep.lohi = nullptr;
         ep.out = J.out;
         ep.capacity = J.capacity;
         ep.out_ctr = J.hdr + H_OUT;
@@ -1032,6 +1040,7 @@ hipError_t launch_threshold_panel(int prec, int form, const ThresholdArgs& a,
     ThresholdParams ep;
     ep.lo = a.lo;
     ep.hi = a.hi;
+    ep.lohi = a.lohi;
     ep.out = a.out;
     ep.capacity = a.capacity;
     ep.out_ctr = a.hdr + H_OUT;

@@ -339,6 +339,34 @@ hipError_t launch_train_targets(const TrainJob* jobs, const int4* samples, int B
     return hipGetLastError();
 }
 
+// The measured band: the same bound as the rigorous one with the error norms
+// the prep pass measured instead of their worst case (each read as float,
+// widened by 0.1% for the FP32 evaluation of the norms).
+__global__ void band_edges(unsigned long long* hdr, double theta, double f, double rigorous,
+                           int alias) {
+    if (threadIdx.x != 0) return;
+    const double er = (double)__uint_as_float((uint32_t)hdr[H_ENORM_R]) * 1.001 + 1e-7;
+    // a self-join prepares one copy: its rows' norms serve both sides
+    const double es =
+        (double)__uint_as_float((uint32_t)hdr[alias ? H_ENORM_R : H_ENORM_S]) * 1.001 + 1e-7;
+    double d = er * (1.0 + es) + es + f * (1.0 + er) * (1.0 + es);
+    if (!(d <= rigorous)) d = rigorous;
+    const double lo = theta - d, hi = theta + d;
+    float flo = (float)lo, fhi = (float)hi;
+    if ((double)flo > lo) flo = nextafterf(flo, -INFINITY);
+    if ((double)fhi < hi) fhi = nextafterf(fhi, INFINITY);
+    hdr[H_LO] = (unsigned long long)__float_as_uint(flo);
+    hdr[H_HI] = (unsigned long long)__float_as_uint(fhi);
+    hdr[H_BAND_W] = (unsigned long long)__double_as_longlong(d);
+}
+
+hipError_t launch_band_edges(unsigned long long* hdr, double theta, double fp32_terms,
+                             double rigorous, bool alias, hipStream_t st) {
+    hipLaunchKernelGGL(band_edges, dim3(1), dim3(64), 0, st, hdr, theta, fp32_terms, rigorous,
+                       alias ? 1 : 0);
+    return hipGetLastError();
+}
+
 // Device-side copy of the output count (asynchronous mode): the count, or
 // minus the status code of a failure found on the device.
 __global__ void copy_count(const unsigned long long* hdr, int64_t band_cap, int64_t* dst) {

@@ -209,6 +209,21 @@ WORKLOADS = {
                               seeds=(500, 0, 0),
                               extra={"batch": 64, "job_seed": 501, "exact_prune": True},
                               notes="64 uneven joins, 768-d, bf16, exact tile pruning"),
+    # the same job shapes and thresholds over 100 clusters (about ten times
+    # more rows per cluster in every relation, so that 128-row tiles hold
+    # one cluster): where tile pruning can pay; a different data
+    # distribution from the 64-job workload above
+    "batch64_exact_c100": Workload("batch64_exact_c100", 0, 0, 768, 768, 100, 0.3,
+                                   prec="bf16", seeds=(500, 0, 0),
+                                   extra={"batch": 64, "job_seed": 501, "exact_prune": True},
+                                   notes="64 uneven joins, 768-d, 100 clusters, exact pruning"),
+    "batch64_learned_c100": Workload("batch64_learned_c100", 0, 0, 768, 768, 100, 0.3,
+                                     prec="bf16", seeds=(500, 0, 0),
+                                     extra={"batch": 64, "job_seed": 501, "prefilter": True,
+                                            "mlp_seed": 601, "train_steps": 300,
+                                            "train_batch": 4096, "eps": 0.05},
+                                     notes="64 uneven joins, 768-d, 100 clusters, learned "
+                                           "prefilter (approximate)"),
     # the scan side of the scan-versus-probe study: 10k query tuples joined
     # with 1M data tuples after a relational pre-filter on the data side
     # (selectivity 1-100% of an attribute drawn uniformly in [0, 1)), range

@@ -268,3 +268,22 @@ def test_nlj_comparator_words_and_limits():
         E.threshold(Rd, Rd, 0.5, tile=23)
     with pytest.raises(E.EjoinError):        # FP32 only
         E.threshold(Rd[:, :64], Rd[:, :64], 0.5, prec="bf16", tile=23)
+
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("self_join", [False, True])
+def test_measured_band_is_narrower_and_exact(prec, self_join):
+    """The default band of a BF16 / FP8 single join is measured on the device
+    from the rows' quantisation error norms: well inside the worst-case
+    bound, so fewer pairs go to the FP64 rescore, and the set stays exact."""
+    cent = G.centres(300, 20, seed=90)
+    R, _ = G.clustered_points(cent, 1500, 0.3, seed=91)
+    S = R if self_join else G.clustered_points(cent, 1200, 0.3, seed=92)[0]
+    sims = O.sim_matrix(R, S)
+    theta = float(np.quantile(sims, 0.97))
+    st = _check(R, S, theta, prec=prec)
+    worst = E.band_default(prec, 300)
+    assert st["band"] < 0.8 * worst, (st["band"], worst)
+    near = lambda b: int((np.abs(sims - theta) < b).sum())
+    assert st["n_band"] <= near(st["band"] + 1e-3) <= near(worst)
