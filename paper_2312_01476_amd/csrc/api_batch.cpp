@@ -196,6 +196,10 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         b.theta = u.theta;
         b.lo = round_down_f(u.theta - band);
         b.hi = round_up_f(u.theta + band);
+        b.measured = o.band < 0 && o.prec != EJOIN_FP32 ? 1 : 0;
+        b.alias = alias ? 1 : 0;
+        b.band_f = band_fp32_terms(Kp);
+        b.band_rig = band;
         b.tiles_m = empty ? 0 : (int32_t)((u.R.rows + bp.bm - 1) / bp.bm);
         b.tiles_n = empty ? 0 : (int32_t)((u.S.rows + bp.bn - 1) / bp.bn);
         b.Kp_bytes = Kp * (int)eb;
@@ -239,8 +243,9 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         b.B = at(o_xs);
         b.info_r = (const RowInfo*)at(o_ir);
         b.info_s = (const RowInfo*)at(o_is);
-        auto seg = [&](const ejoin_rel& X, size_t o_x, size_t o_i, int64_t pad) {
+        auto seg = [&](const ejoin_rel& X, size_t o_x, size_t o_i, int64_t pad, int slot) {
             PrepSeg& g = G[nseg++];
+            g.enorm_slot = slot;
             g.X = X.data;
             g.Xq = at(o_x);
             g.info = (RowInfo*)at(o_i);
@@ -254,9 +259,9 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
             row_base += pad;
         };
         rb_r[q] = row_base;
-        seg(u.R, o_xr, o_ir, padR);
+        seg(u.R, o_xr, o_ir, padR, H_ENORM_R);
         rb_s[q] = alias ? rb_r[q] : row_base;
-        if (!alias) seg(u.S, o_xs, o_is, padS);
+        if (!alias) seg(u.S, o_xs, o_is, padS, H_ENORM_S);
     }
     bp.n_tiles = tile_base;
     bp.n_rows = row_base;
@@ -375,6 +380,7 @@ hipError_t launch_pass(const BatchPlan& bp, char* ws, int tile_grid, bool fixed,
     int pg = kPrepGrid;
     if (!fixed) pg = (int)std::max<int64_t>(1, std::min<int64_t>(kPrepGrid, (bp.n_rows + 3) / 4));
     if ((e = launch_batch_prep(bp.prec, head, segs, pg, false, st)) != hipSuccess) return e;
+    if ((e = launch_batch_band_edges(head, (BatchJob*)jobs, st)) != hipSuccess) return e;
     if ((e = rec(1)) != hipSuccess) return e;
     int tg = tile_grid;
     if (!fixed) tg = (int)std::max<int64_t>(1, std::min<int64_t>(tile_grid, bp.n_tiles));
@@ -451,6 +457,7 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
                             (int32_t*)(ws + bp.off_offs), st)) != hipSuccess)
         return e;
     if ((e = launch_batch_prep(bp.prec, head, segs, pg, true, st)) != hipSuccess) return e;
+    if ((e = launch_batch_band_edges(head, (BatchJob*)jobs, st)) != hipSuccess) return e;
     if (bp.exact) {
         if ((e = launch_xp_tiles(head, segs, jobs, bp.n_rows, bp.kp, (uint16_t*)(ws + bp.off_dir),
                                  (float*)(ws + bp.off_alpha), (float*)(ws + bp.off_rho),

@@ -180,6 +180,35 @@ hipError_t launch_batch_tile(int tile_id, const BatchHead* head, const BatchJob*
     }
 }
 
+// Per job with a measured band: the band edges from the largest error norms
+// its prep found (the bound of the single join's band_edges), written into
+// the job table that the contraction kernels read.
+__global__ void batch_band_edges(const BatchHead* __restrict__ head, BatchJob* __restrict__ jobs) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < head->n_jobs;
+         j += gridDim.x * blockDim.x) {
+        BatchJob& J = jobs[j];
+        if (!J.measured) continue;
+        const unsigned long long* h = J.hdr;
+        const double er = (double)__uint_as_float((uint32_t)h[H_ENORM_R]) * 1.001 + 1e-7;
+        const double es =
+            (double)__uint_as_float((uint32_t)h[J.alias ? H_ENORM_R : H_ENORM_S]) * 1.001 + 1e-7;
+        const double f = J.band_f;
+        double d = er * (1.0 + es) + es + f * (1.0 + er) * (1.0 + es);
+        if (!(d <= J.band_rig)) d = J.band_rig;
+        const double lo = J.theta - d, hi = J.theta + d;
+        float flo = (float)lo, fhi = (float)hi;
+        if ((double)flo > lo) flo = nextafterf(flo, -INFINITY);
+        if ((double)fhi < hi) fhi = nextafterf(fhi, INFINITY);
+        J.lo = flo;
+        J.hi = fhi;
+    }
+}
+
+hipError_t launch_batch_band_edges(const BatchHead* head, BatchJob* jobs, hipStream_t st) {
+    hipLaunchKernelGGL(batch_band_edges, dim3(4), dim3(256), 0, st, head, jobs);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_zero(const BatchHead* head, unsigned long long* bctr, hipStream_t st) {
     hipLaunchKernelGGL(batch_zero, dim3(64), dim3(256), 0, st, head, bctr);
     return hipGetLastError();

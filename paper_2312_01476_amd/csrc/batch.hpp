@@ -51,6 +51,12 @@ struct BatchJob {
     int64_t rtile0, stile0;
     int64_t side_base;         // first item of this job's tile-to-rows bound pass
     int64_t chunk_base;        // prefilter panel form: first (panel, S chunk) item
+    // measured band (BF16 / FP8 with the default band): after prep, lo and hi
+    // are narrowed on the device from the largest quantisation error norms
+    // of the job's rows (hdr[H_ENORM_R / S]); band_f: the FP32 part of the
+    // bound, band_rig: the worst case it never exceeds
+    double band_f, band_rig;
+    int32_t measured, alias;
 };
 
 // One relation to prepare (R or S of a job; an aliased self-join has one).
@@ -63,6 +69,8 @@ struct PrepSeg {
     int64_t rows, rows_pad, ld;
     int64_t row_base;          // first flat prep row of this segment
     int32_t dim, Kp;
+    int32_t enorm_slot;        // hdr slot of the largest error norm (H_ENORM_R or _S)
+    int32_t pad_;
 };
 
 struct BatchHead {

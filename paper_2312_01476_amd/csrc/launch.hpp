@@ -183,6 +183,8 @@ hipError_t launch_batch_panel2(const BatchHead* head, const BatchJob* jobs,
                                unsigned long long* bctr, int grid, bool worklist, hipStream_t st);
 int batch_occupancy(int tile_id);  // resident workgroups per CU, 0: no batch form
 hipError_t launch_batch_zero(const BatchHead* head, unsigned long long* bctr, hipStream_t st);
+// after prep: measured band edges of the jobs that use one (job table on the device)
+hipError_t launch_batch_band_edges(const BatchHead* head, BatchJob* jobs, hipStream_t st);
 hipError_t launch_batch_prep(int prec, const BatchHead* head, const PrepSeg* segs, int grid,
                              bool ordered, hipStream_t st);
 // worklist: the items come from the prefilter's work list (head->work)

@@ -332,8 +332,8 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
 
 // Batched prep: the rows of every relation of a batch form one flat range;
 // each wave finds its row's relation by binary search over the segment
-// starts.  The error-norm maximum is not needed by the threshold join and is
-// not collected here.
+// starts.  The largest error norm of each side of a job goes to the job's
+// counters for its measured band.
 template <int PREC>
 __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ head,
                                                   const PrepSeg* __restrict__ segs,
@@ -385,10 +385,13 @@ __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ 
             }
         }
         const int64_t src = src_of(g, r);
-        if (regs)
-            prep_row_regs<PREC>(xa, src < g.rows, g.dim, g.Xq, g.Kp, g.info, g.hdr, r, lane);
-        else
-            prep_one_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, r, src, lane);
+        const float en =
+            regs ? prep_row_regs<PREC>(xa, src < g.rows, g.dim, g.Xq, g.Kp, g.info, g.hdr, r, lane)
+                 : prep_one_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, r, src,
+                                      lane);
+        // the job's largest error norm per side (the measured band)
+        if (PREC != P_FP32 && lane == 0 && en > 0.0f)
+            atomicMax((unsigned int*)(g.hdr + g.enorm_slot), __float_as_uint(en));
 #pragma unroll
         for (int j = 0; j < kRegNV; ++j) xa[j] = xb[j];
         sa = sb;
