@@ -100,6 +100,13 @@ typedef struct {
 #define EJOIN_TOPK_MIN_SIM 0x8u  /* top-k: only S rows with sim64 >= opts->topk_min_sim count
                                     (the range predicate combined with the top-k condition);
                                     rows with fewer passing S rows are padded */
+#define EJOIN_FP64_SCORES 0x20u  /* threshold joins (single, selection, batch): no pair is
+                                    accepted on its approximate score; every pair at or above
+                                    the band's lower edge goes to the FP64 rescore, so every
+                                    returned score is float(sim64).  The band list must then
+                                    hold all those pairs (opts->band_capacity; the
+                                    EJOIN_E_WORKSPACE retry reports band_needed).  Top-k
+                                    scores are always float(sim64) and ignore the flag. */
 
 /* Autotuned tile choices (opaque; see ejoin_tuner_create). */
 typedef struct ejoin_tuner ejoin_tuner;

@@ -556,8 +556,11 @@ ejoin_status threshold_run(const ejoin_rel* R, const ejoin_rel* S, double theta,
     // the default band of the narrow formats: measured on the device from the
     // rows' quantisation error norms (never wider than the rigorous bound)
     const bool measured = o.band < 0 && p.prec != P_FP32;
+    const bool all64 = (o.flags & EJOIN_FP64_SCORES) != 0;
+    if (all64) a.hi = INFINITY;  // no pair is certain: every candidate is rescored
     if (measured) {
-        HIP_TRY(launch_band_edges(hdr, theta, band_fp32_terms(p.Kp), p.band, p.alias, stream));
+        HIP_TRY(launch_band_edges(hdr, theta, band_fp32_terms(p.Kp), p.band, p.alias, all64,
+                                  stream));
         a.lohi = hdr + H_LO;
     }
     a.out = (Pair*)out;

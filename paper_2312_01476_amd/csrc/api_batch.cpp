@@ -196,6 +196,8 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         b.theta = u.theta;
         b.lo = round_down_f(u.theta - band);
         b.hi = round_up_f(u.theta + band);
+        b.all64 = (o.flags & EJOIN_FP64_SCORES) ? 1 : 0;
+        if (b.all64) b.hi = INFINITY;  // no pair is certain: every candidate is rescored
         b.measured = o.band < 0 && o.prec != EJOIN_FP32 ? 1 : 0;
         b.alias = alias ? 1 : 0;
         b.band_f = band_fp32_terms(Kp);

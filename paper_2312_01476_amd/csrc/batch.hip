@@ -199,6 +199,7 @@ __global__ void batch_band_edges(const BatchHead* __restrict__ head, BatchJob* _
         float flo = (float)lo, fhi = (float)hi;
         if ((double)flo > lo) flo = nextafterf(flo, -INFINITY);
         if ((double)fhi < hi) fhi = nextafterf(fhi, INFINITY);
+        if (J.all64) fhi = INFINITY;
         J.lo = flo;
         J.hi = fhi;
     }

@@ -54,9 +54,10 @@ struct BatchJob {
     // measured band (BF16 / FP8 with the default band): after prep, lo and hi
     // are narrowed on the device from the largest quantisation error norms
     // of the job's rows (hdr[H_ENORM_R / S]); band_f: the FP32 part of the
-    // bound, band_rig: the worst case it never exceeds
+    // bound, band_rig: the worst case it never exceeds; all64: hi stays +inf
+    // (EJOIN_FP64_SCORES: every candidate is rescored)
     double band_f, band_rig;
-    int32_t measured, alias;
+    int32_t measured, alias, all64, pad2_;
 };
 
 // One relation to prepare (R or S of a job; an aliased self-join has one).

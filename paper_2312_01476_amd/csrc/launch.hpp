@@ -157,9 +157,10 @@ hipError_t launch_select_range(const float* col, int64_t n, float lo, float hi, 
 // Band edges from the measured quantisation error norms (hdr[H_ENORM_R/S]):
 // delta = eR (1 + eS) + eS + f (1 + eR)(1 + eS), at most `rigorous`; writes
 // round_down(theta - delta), round_up(theta + delta) to hdr[H_LO], hdr[H_HI]
-// and delta to hdr[H_BAND_W].
+// and delta to hdr[H_BAND_W]; all64: the upper edge is +inf (every candidate
+// is rescored).
 hipError_t launch_band_edges(unsigned long long* hdr, double theta, double fp32_terms,
-                             double rigorous, bool alias, hipStream_t st);
+                             double rigorous, bool alias, bool all64, hipStream_t st);
 hipError_t launch_copy_count(const unsigned long long* hdr, int64_t band_cap, int64_t* dst,
                              hipStream_t st);
 

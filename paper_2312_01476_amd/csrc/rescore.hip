@@ -343,7 +343,7 @@ hipError_t launch_train_targets(const TrainJob* jobs, const int4* samples, int B
 // the prep pass measured instead of their worst case (each read as float,
 // widened by 0.1% for the FP32 evaluation of the norms).
 __global__ void band_edges(unsigned long long* hdr, double theta, double f, double rigorous,
-                           int alias) {
+                           int alias, int all64) {
     if (threadIdx.x != 0) return;
     const double er = (double)__uint_as_float((uint32_t)hdr[H_ENORM_R]) * 1.001 + 1e-7;
     // a self-join prepares one copy: its rows' norms serve both sides
@@ -355,15 +355,16 @@ __global__ void band_edges(unsigned long long* hdr, double theta, double f, doub
     float flo = (float)lo, fhi = (float)hi;
     if ((double)flo > lo) flo = nextafterf(flo, -INFINITY);
     if ((double)fhi < hi) fhi = nextafterf(fhi, INFINITY);
+    if (all64) fhi = INFINITY;  // every candidate goes to the rescore
     hdr[H_LO] = (unsigned long long)__float_as_uint(flo);
     hdr[H_HI] = (unsigned long long)__float_as_uint(fhi);
     hdr[H_BAND_W] = (unsigned long long)__double_as_longlong(d);
 }
 
 hipError_t launch_band_edges(unsigned long long* hdr, double theta, double fp32_terms,
-                             double rigorous, bool alias, hipStream_t st) {
+                             double rigorous, bool alias, bool all64, hipStream_t st) {
     hipLaunchKernelGGL(band_edges, dim3(1), dim3(64), 0, st, hdr, theta, fp32_terms, rigorous,
-                       alias ? 1 : 0);
+                       alias ? 1 : 0, all64 ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ TIMING = 0x2
 APPROX_PREFILTER = 0x4
 TOPK_MIN_SIM = 0x8
 EXACT_PRUNE = 0x10
+FP64_SCORES = 0x20
 
 
 class Rel(C.Structure):
@@ -271,18 +272,20 @@ def noalloc_scratch_bytes() -> int:
 
 
 def threshold(R, S, theta: float, *, d=None, prec="fp32", band=None, tile=0, capacity=None,
-              band_capacity=0, timing=False, stream=None, tuner=None) -> Pairs:
+              band_capacity=0, timing=False, stream=None, tuner=None,
+              fp64_scores=False) -> Pairs:
     """Threshold E-join on the GPU: all (i, j) with sim64(R_i, S_j) >= theta.
 
     R, S: float32 CUDA tensors (n, ld) with unit column stride; ``d`` is the
     embedding dimension (default: all columns).  Grows the output and band
-    buffers and retries when the library reports they were too small."""
+    buffers and retries when the library reports they were too small.
+    ``fp64_scores``: every returned score is float(sim64) (EJOIN_FP64_SCORES)."""
     import torch
     dev = R.device
     nR, nS = R.shape[0], S.shape[0]
     if capacity is None:
         capacity = max(1 << 16, min(nR * nS, (nR + nS) * 64))
-    flags = TIMING if timing else 0
+    flags = (TIMING if timing else 0) | (FP64_SCORES if fp64_scores else 0)
     for _ in range(4):
         ws_bytes = threshold_workspace(R, S, d=d, prec=prec, band=band, tile=tile,
                                        band_capacity=band_capacity, tuner=tuner)
@@ -418,7 +421,8 @@ def threshold_sel_workspace(R, sel_r, S, sel_s, *, d=None, prec="fp32", band=Non
 
 
 def threshold_sel(R, sel_r, S, sel_s, theta: float, *, d=None, prec="fp32", band=None, tile=0,
-                  capacity=None, band_capacity=0, timing=False, stream=None) -> Pairs:
+                  capacity=None, band_capacity=0, timing=False, stream=None,
+                  fp64_scores=False) -> Pairs:
     """Threshold join restricted to the selected rows (row ids in the
     result); grows buffers and retries like ``threshold``."""
     import torch
@@ -427,7 +431,7 @@ def threshold_sel(R, sel_r, S, sel_s, theta: float, *, d=None, prec="fp32", band
     nS = S.shape[0] if sel_s is None else sel_s.numel()
     if capacity is None:
         capacity = max(1 << 16, min(nR * nS, (nR + nS) * 64))
-    flags = TIMING if timing else 0
+    flags = (TIMING if timing else 0) | (FP64_SCORES if fp64_scores else 0)
     for _ in range(4):
         ws = torch.empty(threshold_sel_workspace(R, sel_r, S, sel_s, d=d, prec=prec, band=band,
                                                  tile=tile, band_capacity=band_capacity),
@@ -518,7 +522,8 @@ def batch_raw(jobs, outs, caps, ws, n_out, *, d=None, prec="fp32", band=None, ti
 
 
 def batch(jobs, *, d=None, prec="fp32", band=None, tile=0, capacities=None, band_capacity=0,
-          timing=False, stream=None, tuner=None, prefilter=None, eps=0.0, exact_prune=False):
+          timing=False, stream=None, tuner=None, prefilter=None, eps=0.0, exact_prune=False,
+          fp64_scores=False):
     """Run many threshold joins as one batch pass.  ``jobs``: list of
     (R, S, theta).  Returns (list of Pairs, stats dict).  Jobs whose output
     overflowed are run again (as a smaller batch) with exactly enough room."""
@@ -533,7 +538,8 @@ def batch(jobs, *, d=None, prec="fp32", band=None, tile=0, capacities=None, band
     results = [None] * n
     todo = list(range(n))
     stats = {}
-    flags = (TIMING if timing else 0) | (EXACT_PRUNE if exact_prune else 0)
+    flags = (TIMING if timing else 0) | (EXACT_PRUNE if exact_prune else 0) | \
+        (FP64_SCORES if fp64_scores else 0)
     for _ in range(6):
         sub = [jobs[i] for i in todo]
         sub_caps = [caps[i] for i in todo]

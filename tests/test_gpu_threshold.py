@@ -287,3 +287,70 @@ def test_measured_band_is_narrower_and_exact(prec, self_join):
     assert st["band"] < 0.8 * worst, (st["band"], worst)
     near = lambda b: int((np.abs(sims - theta) < b).sum())
     assert st["n_band"] <= near(st["band"] + 1e-3) <= near(worst)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_approximate_score_error_against_fp64(prec):
+    """Scores accepted straight from the narrow-format contraction carry the
+    format's error: measured here over every returned pair.  BF16 stays
+    within 1e-3 of sim64 at 300-d and above (at 33-d it does not: the error
+    of a few quantised terms does not average out); FP8 e4m3 with per-row
+    scales is within its band only.  The exact set does not depend on it."""
+    w = G.WORKLOADS["words_1k"]
+    R, S, _, _ = G.make_host(w)
+    r, s, sc, st = _run(R, S, w.theta, d=w.d, prec=prec)
+    err = np.abs(sc - O.sim64_pairs(R, S, r, s, d=w.d))
+    assert st["n_certain"] > 0
+    if prec == "bf16":
+        assert err.max() <= 1e-3, err.max()
+    else:
+        assert 1e-3 < err.max() <= st["band"], (err.max(), st["band"])
+    R = G.gaussian_raw(257, 768, seed=257 * 7 + 768)
+    S = G.gaussian_raw(513, 768, seed=513 * 11 + 768)
+    theta = float(np.quantile(O.sim_matrix(R, S), 0.9))
+    r, s, sc, st = _run(R, S, theta, prec=prec)
+    err = np.abs(sc - O.sim64_pairs(R, S, r, s))
+    assert err.max() <= (1e-3 if prec == "bf16" else st["band"])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("shape", [(5, 7, 3), (130, 257, 33), (300, 1100, 300)])
+def test_fp64_scores_flag_returns_exact_scores(prec, shape):
+    """EJOIN_FP64_SCORES: nothing is accepted on its approximate score, so
+    every returned score is float32(sim64) in every precision (within 1e-3
+    of sim64 whatever the format's error) and the set is still exact."""
+    nr, ns, d = shape
+    R = G.gaussian_raw(nr, d, seed=nr * 3 + d)
+    S = G.gaussian_raw(ns, d, seed=ns * 5 + d)
+    sims = O.sim_matrix(R, S)
+    for q in (0.5, 0.95):
+        theta = float(np.quantile(sims, q))
+        r, s, sc, st = _run(R, S, theta, prec=prec, fp64_scores=True, band_capacity=nr * ns + 16)
+        ori, osi, _, _ = O.threshold(R, S, theta)
+        assert set(zip(r.tolist(), s.tolist())) == set(zip(ori.tolist(), osi.tolist()))
+        ref = O.sim64_pairs(R, S, r, s).astype(np.float32).astype(np.float64)
+        np.testing.assert_array_equal(sc, ref)
+        assert st["n_certain"] == 0 and st["n_band_accepted"] == len(r)
+
+
+def test_fp64_scores_flag_over_selections_and_in_a_batch():
+    w = G.WORKLOADS["words_1k"]
+    R, S, _, _ = G.make_host(w, n_r=700, n_s=900)
+    Rd, Sd = _dev(R), _dev(S)
+    ir = np.arange(1, 700, 2, dtype=np.int32)
+    res = E.threshold_sel(Rd, _dev(ir), Sd, None, w.theta, d=w.d, prec="fp8", fp64_scores=True)
+    r, s = res.r.cpu().numpy(), res.s.cpu().numpy()
+    ref = O.sim64_pairs(R, S, r, s, d=w.d).astype(np.float32)
+    np.testing.assert_array_equal(res.score.cpu().numpy(), ref)
+    ori, osi, _, _ = O.threshold(R[ir], S, w.theta, d=w.d)
+    assert set(zip(r.tolist(), s.tolist())) == set(zip(ir[ori].tolist(), osi.tolist()))
+    jobs = [(Rd, Sd, w.theta), (Rd[:300], Rd[:300], 0.9), (Sd[:50], Rd, 0.85)]
+    host = [(R, S, w.theta), (R[:300], R[:300], 0.9), (S[:50], R, 0.85)]
+    for prec in ("bf16", "fp8"):
+        out, _ = E.batch(jobs, d=w.d, prec=prec, fp64_scores=True)
+        for got, (Rh, Sh, th) in zip(out, host):
+            r, s = got.r.cpu().numpy(), got.s.cpu().numpy()
+            ori, osi, _, _ = O.threshold(Rh, Sh, th, d=w.d)
+            assert set(zip(r.tolist(), s.tolist())) == set(zip(ori.tolist(), osi.tolist()))
+            ref = O.sim64_pairs(Rh, Sh, r, s, d=w.d).astype(np.float32)
+            np.testing.assert_array_equal(got.score.cpu().numpy(), ref)
