@@ -254,6 +254,36 @@ def extra_selectivity(args):
     return r
 
 
+def calibrate_gemm(torch):
+    """Dense BF16 GEMM C = A B^T through torch.matmul (hipBLASLt) at square
+    and join-shaped sizes: the practical matrix-core rate of this chip, with
+    no epilogue, for comparison with the join's contraction."""
+    points = []
+    for m, n, k in [(16384, 16384, 16384), (16384, 16384, 4096), (65536, 65536, 384),
+                    (32768, 32768, 768)]:
+        a = torch.randn(m, k, device="cuda", dtype=torch.bfloat16)
+        b = torch.randn(n, k, device="cuda", dtype=torch.bfloat16)
+        c = torch.empty(m, n, device="cuda", dtype=torch.bfloat16)
+        for _ in range(3):
+            torch.matmul(a, b.t(), out=c)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        it = 10
+        e0.record()
+        for _ in range(it):
+            torch.matmul(a, b.t(), out=c)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / it
+        tf = 2.0 * m * n * k / (ms * 1e-3) / 1e12
+        points.append({"m": m, "n": n, "k": k, "ms": round(ms, 3), "tflops": round(tf, 1),
+                       "frac_of_dense_bf16_peak": round(tf / PEAK["bf16"][1], 4)})
+        log(f"[bench] bf16 gemm {m}x{n}x{k}: {ms:.3f} ms, {tf:.1f} TF/s")
+        del a, b, c
+        torch.cuda.empty_cache()
+    return {"calibration": "bf16 gemm, torch.matmul", "points": points}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +294,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only copy a BYTES-sized device buffer 3 times (reference kernel "
                          "for scaling the HBM traffic counters) and exit")
+    ap.add_argument("--calibrate-gemm", action="store_true",
+                    help="only time the vendor BF16 GEMM (torch.matmul) at a few shapes, "
+                         "the practical matrix-core ceiling the join is compared with, and exit")
     ap.add_argument("--autotune", action="store_true",
                     help="batched workloads: time every tile first and use the fastest")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -295,6 +328,10 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         log(f"[bench] copied {n * 4} bytes 3 times")
+        return
+
+    if args.calibrate_gemm:
+        print(json.dumps(calibrate_gemm(torch)), flush=True)
         return
 
     w = G.WORKLOADS[args.workload]

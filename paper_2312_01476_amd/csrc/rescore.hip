@@ -19,69 +19,94 @@
 
 namespace ej {
 
-// Each lane of a wave holds one pair (rp, sp, dim; valid=false for none) and
-// gets sim64 of it.  The rule is sequential in k, so one lane sums one pair;
-// the rows are brought in through LDS in chunks of 32 elements so that every
-// global load instruction reads whole row segments (lanes 0-31 one R chunk,
-// lanes 32-63 the matching S chunk of one pair) instead of 64 scattered
-// words.  Per pair the chunk is stored at stride 65 floats, so the lanes'
-// sequential reads fall in 64 distinct banks.
-constexpr int kChunk = 32;
+// Each lane of a wave holds one pair (rp, sp, dim; valid = false for none)
+// and gets sim64 of it: the rule is sequential in k, so one lane sums one
+// pair.  The rows come in through LDS in chunks of 16 elements so that every
+// global load reads whole row segments: load j of a chunk serves pairs 2j and
+// 2j + 1, each quarter of the wave reading 64 contiguous bytes of one row
+// (R or S of one pair) at the address it takes from the wave's pair table in
+// LDS.  The next chunk's loads are in flight in registers while the current
+// chunk is summed.  Elements past a pair's dim are zero and are summed like
+// the others: x + 0 * 0 = x exactly, so the sums are those of the sequential
+// definition over k < dim.  A lane without a pair borrows lane 0's (every
+// calling wave has one there) and its result is not used.
+constexpr int kChunk = 16;
+constexpr int kPairStride = 2 * kChunk + 1;  // floats per pair: R chunk, S chunk, pad
 
-// 32-bit word `w` of lane i (uniform i), zero-extended.
-__device__ __forceinline__ uint32_t lane_word(uint64_t w, int i) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)w, i);
+typedef __attribute__((address_space(1))) const float* grow_ptr;
+
+struct PairLds {
+    uint64_t ptr[64][2];  // the wave's pairs: R row, S row (global addresses)
+    int kmax[64];         // elements of each pair
+    float buf[64 * kPairStride];
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-constexpr int kPairStride = 2 * kChunk + 1;
 
 __device__ __forceinline__ double wave_sim64(const float* rp, const float* sp, int dim, bool valid,
-                                             float* __restrict__ lds) {
+                                             PairLds& L) {
     const int lane = threadIdx.x & 63;
-    const int kmax = valid ? dim : 0;
-    int dmax = kmax;
+    // lane 0's pair stands in for lanes without one
+    const uint64_t r0 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
+                             (int)(uint32_t)((uint64_t)rp >> 32), 0) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)rp, 0);
+    const uint64_t s0 = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
+                             (int)(uint32_t)((uint64_t)sp >> 32), 0) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)sp, 0);
+    const int d0 = __builtin_amdgcn_readlane(dim, 0);
+    const int kmax = valid ? dim : d0;
+    L.ptr[lane][0] = valid ? (uint64_t)rp : r0;
+    L.ptr[lane][1] = valid ? (uint64_t)sp : s0;
+    L.kmax[lane] = kmax;
+    int dmax = kmax, dmin = kmax;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dmax = max(dmax, __shfl_xor(dmax, o, 64));
-    const uint64_t ru = (uint64_t)rp, su = (uint64_t)sp;
-    const int half = lane >> 5, kk = lane & 31;
-    double dot = 0.0, nr = 0.0, ns = 0.0;
-    for (int k0 = 0; k0 < dmax; k0 += kChunk) {
-        // 16 pairs at a time: their loads are independent and in flight
-        // together, then the values go to LDS
-        for (int i0 = 0; i0 < 64; i0 += 16) {
-            float vals[16];
+    for (int o = 32; o > 0; o >>= 1) {
+        dmax = max(dmax, __shfl_xor(dmax, o, 64));
+        dmin = min(dmin, __shfl_xor(dmin, o, 64));
+    }
+    wave_lds_sync();
+    // this lane's part of load j: pair 2j + half, row `side`, element e
+    const int q = lane >> 4, e = lane & 15;
+    const int half = q >> 1, side = q & 1;
+    float v[32];
+    auto load = [&](int k0) {
+        const int k = k0 + e;
+        if (k0 + kChunk <= dmin) {  // wave-uniform: every pair has the whole chunk
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int i = i0 + q;
-                const int di = __builtin_amdgcn_readlane(kmax, i);
-                // pair i's row pointers (scalar), then each half takes its
-                // row; readlane returns int, so each half goes through
-                // uint32_t before widening (a sign-extended low half would be
-                // a wild address)
-                const uint64_t r_i = ((uint64_t)lane_word(ru >> 32, i) << 32) | lane_word(ru, i);
-                const uint64_t s_i = ((uint64_t)lane_word(su >> 32, i) << 32) | lane_word(su, i);
-                const float* base = (const float*)(half ? s_i : r_i);
-                float v = 0.0f;
-                if (k0 + kk < di) v = base[k0 + kk];
-                vals[q] = v;
+            for (int j = 0; j < 32; ++j) v[j] = ((grow_ptr)L.ptr[2 * j + half][side])[k];
+        } else {
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                const bool ok = k < L.kmax[2 * j + half];
+                const float x = ((grow_ptr)L.ptr[2 * j + half][side])[ok ? k : 0];
+                v[j] = ok ? x : 0.0f;
             }
-#pragma unroll
-            for (int q = 0; q < 16; ++q) lds[(i0 + q) * kPairStride + half * kChunk + kk] = vals[q];
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int n = min(kChunk, kmax - k0);
-        const float* mine = lds + lane * kPairStride;
-        for (int k = 0; k < n; ++k) {
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int j = 0; j < 32; ++j) L.buf[(2 * j + half) * kPairStride + side * kChunk + e] = v[j];
+    };
+    double dot = 0.0, nr = 0.0, ns = 0.0;
+    const float* mine = L.buf + lane * kPairStride;
+    load(0);
+    for (int k0 = 0; k0 < dmax; k0 += kChunk) {
+        store();
+        wave_lds_sync();
+        if (k0 + kChunk < dmax) load(k0 + kChunk);  // in flight while this chunk is summed
+#pragma unroll
+        for (int k = 0; k < kChunk; ++k) {
             const double a = (double)mine[k];
             const double b = (double)mine[kChunk + k];
             dot = dot + a * b;
             nr = nr + a * a;
             ns = ns + b * b;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_lds_sync();
     }
     if (nr == 0.0 || ns == 0.0) return 0.0;
     return dot / __builtin_sqrt(nr * ns);
@@ -98,8 +123,8 @@ __global__ __launch_bounds__(256) void rescore_band(const float* __restrict__ R,
                                                     const int32_t* __restrict__ sel_r,
                                                     const int32_t* __restrict__ sel_s) {
     if (hdr[H_FLAGS] != 0) return;
-    __shared__ float s_rows[4][64 * kPairStride];
-    float* lds = s_rows[threadIdx.x >> 6];
+    __shared__ PairLds s_pairs[4];
+    PairLds& lds = s_pairs[threadIdx.x >> 6];
     const int64_t n = min((int64_t)hdr[H_BAND], band_cap);
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -242,8 +267,8 @@ __global__ __launch_bounds__(256) void batch_rescore(const BatchHead* __restrict
                                                      const unsigned long long* __restrict__ bctr) {
     const int64_t n = min((int64_t)bctr[B_BAND], head->band_cap);
     const int4* __restrict__ band = head->band;
-    __shared__ float s_rows[4][64 * kPairStride];
-    float* lds = s_rows[threadIdx.x >> 6];
+    __shared__ PairLds s_pairs[4];
+    PairLds& lds = s_pairs[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n;
@@ -305,8 +330,8 @@ hipError_t launch_batch_rescore(const BatchHead* head, const BatchJob* jobs,
 __global__ __launch_bounds__(256) void train_targets(const TrainJob* __restrict__ jobs,
                                                      const int4* __restrict__ samples, int B,
                                                      float* __restrict__ t) {
-    __shared__ float s_rows[4][64 * kPairStride];
-    float* lds = s_rows[threadIdx.x >> 6];
+    __shared__ PairLds s_pairs[4];
+    PairLds& lds = s_pairs[threadIdx.x >> 6];
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < B;
          base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = base + (threadIdx.x & 63);
