@@ -331,9 +331,9 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
 }
 
 // Batched prep: the rows of every relation of a batch form one flat range;
-// each wave finds its row's relation by binary search over the segment
-// starts.  The largest error norm of each side of a job goes to the job's
-// counters for its measured band.
+// a wave finds its first row's relation by binary search over the segment
+// starts and then walks forward.  The largest error norm of each side of a
+// job goes to the job's counters for its measured band.
 template <int PREC>
 __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ head,
                                                   const PrepSeg* __restrict__ segs,
@@ -355,9 +355,14 @@ __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ 
     auto src_of = [&](const PrepSeg& g, int64_t r) {
         return (ordered && g.perm) ? (int64_t)g.perm[r] : r;
     };
-    const int64_t first = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t stride = (int64_t)gridDim.x * 4;
-    if (first >= n) return;
+    // each wave takes a contiguous range of rows, so that its consecutive
+    // rows mostly share a segment: the largest error norm is kept per wave
+    // and segment and sent with one atomic when the segment changes
+    const int64_t n_waves = (int64_t)gridDim.x * 4;
+    const int64_t per = (n + n_waves - 1) / n_waves;
+    const int64_t first = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * per;
+    const int64_t last = min(n, first + per);
+    if (first >= last) return;
     int sa = seg_of(first);
     bool regs = segs[sa].Kp <= kRegMax;
     float xa[kRegNV], xb[kRegNV];
@@ -366,16 +371,22 @@ __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ 
         const int64_t s0 = src_of(g, first - g.row_base);
         load_row_reg(g.X, s0 < g.rows, g.dim, g.ld, s0, lane, xa);
     }
-    for (int64_t row = first; row < n; row += stride) {
+    float emax = 0.0f;  // largest error norm of segment eseg among this wave's rows
+    int eseg = sa;
+    auto flush = [&]() {
+        if (PREC != P_FP32 && lane == 0 && emax > 0.0f)
+            atomicMax((unsigned int*)(segs[eseg].hdr + segs[eseg].enorm_slot),
+                      __float_as_uint(emax));
+    };
+    for (int64_t row = first; row < last; ++row) {
         const PrepSeg& g = segs[sa];
         const int64_t r = row - g.row_base;
         // the wave's next row: its segment, and its data when it is held in
         // registers, before this row is reduced and written
-        const int64_t next = row + stride;
+        const int64_t next = row + 1;
         int sb = sa;
         bool nregs = false;
-        if (next < n) {
-            // a wave's rows increase: scan forward from this row's segment
+        if (next < last) {
             while (sb + 1 < nseg && segs[sb + 1].row_base <= next) ++sb;
             const PrepSeg& h = segs[sb];
             nregs = h.Kp <= kRegMax;
@@ -389,14 +400,18 @@ __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ 
             regs ? prep_row_regs<PREC>(xa, src < g.rows, g.dim, g.Xq, g.Kp, g.info, g.hdr, r, lane)
                  : prep_one_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, r, src,
                                       lane);
-        // the job's largest error norm per side (the measured band)
-        if (PREC != P_FP32 && lane == 0 && en > 0.0f)
-            atomicMax((unsigned int*)(g.hdr + g.enorm_slot), __float_as_uint(en));
+        if (sa != eseg) {
+            flush();
+            emax = 0.0f;
+            eseg = sa;
+        }
+        emax = fmaxf(emax, en);
 #pragma unroll
         for (int j = 0; j < kRegNV; ++j) xa[j] = xb[j];
         sa = sb;
         regs = nregs;
     }
+    flush();
 }
 
 hipError_t launch_batch_prep(int prec, const BatchHead* head, const PrepSeg* segs, int grid,

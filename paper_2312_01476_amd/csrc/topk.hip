@@ -493,49 +493,46 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint32_t lane_u32(uint64_t w, int i) {
-    return (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)w, i);
-}
+typedef __attribute__((address_space(1))) const float* gfloat_ptr;
 
-// lane l: sequential FP64 dot of the row `r` with S row sj (valid lanes only)
+// Lane l: sequential FP64 dot of the row `r` with S row live[p0 + l] (lanes
+// with p0 + l >= n_live get 0; p0 < n_live).  Candidate chunks of 32
+// elements go through LDS, two candidate rows per load instruction (lanes
+// 0-31 one, 32-63 the next) at the row the lane half reads from the live list,
+// all 32 loads of a chunk in flight together.  Chunk entries past dim are
+// zero on both sides, so the unrolled sum adds exact zeros: the sequential
+// FP64 sum over k < dim is unchanged.
 __device__ __forceinline__ double wave_dot64(const float* __restrict__ r,
-                                             const float* __restrict__ S, int64_t ldS, int sj,
-                                             bool valid, int dim, float* rows, float* rch) {
+                                             const float* __restrict__ S, int64_t ldS,
+                                             const int* live, int p0, int n_live, int dim,
+                                             float* rows, float* rch) {
     const int lane = threadIdx.x & 63;
-    const uint64_t sp = valid ? (uint64_t)(S + (int64_t)sj * ldS) : 0ull;
-    const uint64_t vmask = __ballot(valid);
+    const int kk = lane & 31, hl = lane >> 5;
+    const gfloat_ptr Sg = (gfloat_ptr)S;
     double acc = 0.0;
     for (int k0 = 0; k0 < dim; k0 += FW_CH) {
         const int kn = min(FW_CH, dim - k0);
-        if (lane < kn) rch[lane] = r[k0 + lane];
-        // two candidate rows per load instruction (lanes 0-31 one, 32-63 the
-        // next), 16 instructions in flight before their values go to LDS
-        const int kk = lane & 31;
-        for (int b0 = 0; b0 < 64; b0 += 32) {
-            float vals[16];
+        if (lane < FW_CH) rch[lane] = lane < kn ? r[k0 + lane] : 0.0f;
+        const bool kin = kk < kn;
+        const int kq = k0 + (kin ? kk : 0);
+        float vals[32];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int i0 = b0 + 2 * q;
-                const int i = i0 + (lane >> 5);
-                const uint64_t p0 = ((uint64_t)lane_u32(sp >> 32, i0) << 32) | lane_u32(sp, i0);
-                const uint64_t p1 =
-                    ((uint64_t)lane_u32(sp >> 32, i0 + 1) << 32) | lane_u32(sp, i0 + 1);
-                const float* base = (const float*)(lane < 32 ? p0 : p1);
-                const bool have = (vmask >> i) & 1ull;
-                vals[q] = (have && kk < kn) ? base[k0 + kk] : 0.0f;
-            }
-#pragma unroll
-            for (int q = 0; q < 16; ++q)
-                rows[(b0 + 2 * q + (lane >> 5)) * FW_STRIDE + kk] = vals[q];
+        for (int q = 0; q < 32; ++q) {
+            const int i = p0 + 2 * q + hl;
+            const bool have = i < n_live;
+            const int c = live[have ? i : p0];
+            const float x = Sg[(int64_t)c * ldS + kq];
+            vals[q] = (have && kin) ? x : 0.0f;
         }
+#pragma unroll
+        for (int q = 0; q < 32; ++q) rows[(2 * q + hl) * FW_STRIDE + kk] = vals[q];
         wave_sync();
-        if (valid) {
-            const float* mine = rows + lane * FW_STRIDE;
-            for (int kk = 0; kk < kn; ++kk) acc = acc + (double)rch[kk] * (double)mine[kk];
-        }
+        const float* mine = rows + lane * FW_STRIDE;
+#pragma unroll
+        for (int q = 0; q < FW_CH; ++q) acc = acc + (double)rch[q] * (double)mine[q];
         wave_sync();
     }
-    return acc;
+    return p0 + lane < n_live ? acc : 0.0;
 }
 
 // The four waves of a workgroup take four consecutive rows of the
@@ -718,8 +715,9 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
                     if (n_live > 0 && valid) {
                         const double* mine = ((c & 1) ? rows1 : rows0) + lane * FW_STRIDE;
                         const double* rc = (c & 1) ? rch1 : rch0;
-                        const int kn = min(FW_CH, dim - c * FW_CH);
-                        for (int q = 0; q < kn; ++q) acc = acc + rc[q] * mine[q];
+                        // (the chunks are zero past dim: the extra terms add exact zeros)
+#pragma unroll
+                        for (int q = 0; q < FW_CH; ++q) acc = acc + rc[q] * mine[q];
                     }
                     // buffer (c + 1) & 1 was last read for chunk c - 1, before
                     // the previous barrier
@@ -739,7 +737,7 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
                 const bool valid = t < n_live;
                 const int sj = valid ? live[t] : 0;
                 const double dot =
-                    wave_dot64(rrow, S, ldS, sj, valid, dim, sm.rows[w], sm.rch[w]);
+                    wave_dot64(rrow, S, ldS, live, p0, n_live, dim, sm.rows[w], sm.rch[w]);
                 if (valid) {
                     v[t] = sim64_from(dot, nr64[i], ns64[sj]);
                     jv[t] = sj;
