@@ -39,11 +39,8 @@ DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}
 # figures are in profiles/threshold_fp32_100k_traffic.md and
 # profiles/hbm_traffic_bf16_kernels.md); valid for the
 # kernel as it was when the counters were taken, keyed by workload and tile
-TRAFFIC = {("fp32_100k", "fp32:128x128x32"): 6204551.8 * 1024 * 2.0 + 617169.5 * 1024 * 1.0,
-           ("fp32_100k", "fp32:panel/2wg"): 2823477.625 * 1024 * 2.0 + 693820.0625 * 1024 * 1.0,
-           ("bf16_1m", "bf16:panel"): 500277725.25 * 1024 * 2.0 + 12169225.65625 * 1024 * 1.0,
-           ("batch64_bf16", "bf16:panel/batch/2wg"):
-               48481474.75 * 1024 * 2.0 + 941741.5625 * 1024 * 1.0}
+TRAFFIC = {("fp32_100k", "fp32:panel/2wg"): 2678102.375 * 1024 * 2.0 + 607665.53125 * 1024 * 1.0,
+           ("bf16_1m", "bf16:panel"): 531217166.25 * 1024 * 2.0 + 12168750.9375 * 1024 * 1.0}
 
 
 def log(*a):
@@ -190,7 +187,9 @@ def extra_bf16_1m(args):
          "roofline": {"bound": "mfma", "achieved": round(flops / (k_ms * 1e-3) / 1e12, 2),
                       "peak": PEAK["bf16"][1], "unit": "TFLOP/s",
                       "frac": round(flops / (k_ms * 1e-3) / 1e12 / PEAK["bf16"][1], 4),
-                      "traffic": None, "kernel": "panel_kernel<ThresholdEpi>",
+                      "traffic": (round(TRAFFIC[(w.name, tile)])
+                                  if (w.name, tile) in TRAFFIC else None),
+                      "kernel": "panel_kernel<ThresholdEpi>",
                       "kernel_ms": round(k_ms, 3), "algorithmic_flops_per_launch": flops},
          "score_error_vs_fp64": {"sampled_pairs": int(err.size),
                                  "max_abs": float(err.max()) if err.size else 0.0,
