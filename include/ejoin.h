@@ -573,6 +573,15 @@ ejoin_status ejoin_prefilter_load(void *state, int32_t dim, const char *path /* 
 int32_t ejoin_tile_count(void);
 const char *ejoin_tile_name(int32_t tile);
 
+/* Resident workgroups per CU of the register-panel kernel that a threshold
+ * join with `tile` (12, 13, 14, 15, 20, 21, 24, 25) and rows of `dim`
+ * elements would launch: *designed (host) receives the count the kernel is
+ * laid out for (its launch bound; the two-workgroup forms 14, 15 and 21 are
+ * laid out for 2), *resident (host) what the runtime reports for the
+ * compiled kernel on the current device.  Nothing is launched.  Returns
+ * EJOIN_E_INVAL for another tile or a depth the tile does not take. */
+ejoin_status ejoin_tile_occupancy(int32_t tile, int32_t dim, int32_t *designed, int32_t *resident);
+
 #ifdef __cplusplus
 }
 #endif

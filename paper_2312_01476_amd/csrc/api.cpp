@@ -223,6 +223,32 @@ const char* ejoin_tile_name(int32_t tile) {
     return t ? t->name : nullptr;
 }
 
+ejoin_status ejoin_tile_occupancy(int32_t tile, int32_t dim, int32_t* designed,
+                                  int32_t* resident) {
+    if (!designed || !resident || dim < 1) return EJOIN_E_INVAL;
+    int prec, form;
+    switch (tile) {
+        case 12: prec = P_BF16; form = 0; break;
+        case 13: prec = P_FP8; form = 0; break;
+        case 14: prec = P_BF16; form = 1; break;
+        case 15: prec = P_FP8; form = 1; break;
+        case 20: prec = P_FP32; form = 0; break;
+        case 21: prec = P_FP32; form = 1; break;
+        case 24: prec = P_BF16; form = 2; break;
+        case 25: prec = P_FP8; form = 2; break;
+        default: return EJOIN_E_INVAL;
+    }
+    // K padded to whole 128-byte slices, as the planner pads it
+    const int per = 128 / (int)elem_bytes(prec);
+    const int Kp = (dim + per - 1) / per * per;
+    if (!panel_fits(tile, Kp * (int)elem_bytes(prec))) return EJOIN_E_INVAL;
+    PanelQuery q = {0, 0, 0};
+    if (panel_query(prec, form, Kp, &q) != hipSuccess) return EJOIN_E_INVAL;
+    *designed = q.designed;
+    *resident = q.resident;
+    return EJOIN_OK;
+}
+
 size_t ejoin_threshold_workspace(const ejoin_rel* R, const ejoin_rel* S, const ejoin_opts* opts) {
     ejoin_opts o = opts_or_default(opts);
     Plan p;

@@ -56,6 +56,13 @@ constexpr int kTileNlj = 23;
 hipError_t launch_threshold_nlj(const ThresholdArgs& a, hipStream_t st);
 // form 0: one workgroup per CU, 1: two workgroups per CU, 2: two 32-row
 // blocks per wave (BF16 / FP8 rows of 3 to 6 K slices)
+// Designed and actual resident workgroups per CU of the panel kernel that a
+// threshold join of this precision, form (0 one workgroup, 1 two workgroups,
+// 2 two row blocks per wave) and padded depth Kp would launch; no launch.
+struct PanelQuery {
+    int designed, resident, waves;
+};
+hipError_t panel_query(int prec, int form, int Kp, PanelQuery* q);
 hipError_t launch_threshold_panel(int prec, int form, const ThresholdArgs& a,
                                   hipStream_t st);
 

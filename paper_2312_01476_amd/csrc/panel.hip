@@ -879,7 +879,13 @@ template <int PREC, int KS, int RB, int CB, int NW, int OCC, int NSLOT, class EP
 static hipError_t run_panel(const void* A, const void* B, const RowInfo* info_r,
                             const RowInfo* info_s, int64_t nR, int64_t nS, bool split_s,
                             const unsigned long long* hdr, const typename EPI::Params& ep,
-                            hipStream_t st) {
+                            hipStream_t st, PanelQuery* q = nullptr) {
+    if (q) {  // the instantiation's designed and actual workgroups per CU; no launch
+        q->designed = OCC;
+        q->waves = NW;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &q->resident, panel_kernel<PREC, KS, RB, CB, NW, OCC, NSLOT, EPI>, 64 * NW, 0);
+    }
     constexpr int PN_BN = 32 * CB;
     constexpr int PN_ROWS = 32 * RB * NW;
     const int64_t n_panels = (nR + PN_ROWS - 1) / PN_ROWS;
@@ -917,10 +923,11 @@ template <int PREC, template <int> class EPI>
 static hipError_t dispatch_panel(int ks, int form, const void* A, const void* B,
                                  const RowInfo* ir, const RowInfo* is, int64_t nR, int64_t nS,
                                  bool split_s, const unsigned long long* hdr,
-                                 const typename EPI<4>::Params& ep, hipStream_t st) {
+                                 const typename EPI<4>::Params& ep, hipStream_t st,
+                                 PanelQuery* q = nullptr) {
 #define EJ_RUN(KS_, RB_, CB_, NW_, OCC_, NSLOT_)                                          \
     return run_panel<PREC, KS_, RB_, CB_, NW_, OCC_, NSLOT_, EPI<NW_>>(A, B, ir, is, nR, nS, \
-                                                                       split_s, hdr, ep, st)
+                                                                       split_s, hdr, ep, st, q)
     if (form == 2) {
         // two 32-row blocks per wave, one wave per SIMD: every B fragment read
         // from LDS feeds two MFMAs (half the LDS traffic per flop of the
@@ -1066,6 +1073,23 @@ hipError_t launch_threshold_panel(int prec, int form, const ThresholdArgs& a,
 // Row depths (bytes of K) that the top-k candidate sweep runs on register
 // panels: up to six K slices in every format; BF16 and FP32 also eight,
 // nine, ten or twelve.
+hipError_t panel_query(int prec, int form, int Kp, PanelQuery* q) {
+    const int kpb = row_bytes(prec, Kp);
+    if (kpb % 128 != 0 || !q) return hipErrorInvalidValue;
+    const int ks = slices(prec, Kp);
+    ThresholdParams ep = {};
+    if (prec == P_BF16)
+        return dispatch_panel<P_BF16, ThresholdEpi>(ks, form, nullptr, nullptr, nullptr, nullptr,
+                                                    0, 0, true, nullptr, ep, nullptr, q);
+    if (prec == P_FP8)
+        return dispatch_panel<P_FP8, ThresholdEpi>(ks, form, nullptr, nullptr, nullptr, nullptr,
+                                                   0, 0, true, nullptr, ep, nullptr, q);
+    if (prec == P_FP32)
+        return dispatch_panel<P_FP32, ThresholdEpi>(ks, form, nullptr, nullptr, nullptr, nullptr,
+                                                    0, 0, true, nullptr, ep, nullptr, q);
+    return hipErrorInvalidValue;
+}
+
 bool topk_panel_depth(int prec, int kpb) {
     if (kpb % 128 != 0 || kpb <= 0) return false;
     const int ks = kpb / 128;

@@ -88,6 +88,8 @@ def lib():
         L.ejoin_tile_count.restype = C.c_int32
         L.ejoin_tile_name.restype = C.c_char_p
         L.ejoin_tile_name.argtypes = [C.c_int32]
+        L.ejoin_tile_occupancy.restype = C.c_int
+        L.ejoin_tile_occupancy.argtypes = [C.c_int32, C.c_int32, P(C.c_int32), P(C.c_int32)]
         L.ejoin_threshold_workspace.restype = C.c_size_t
         L.ejoin_threshold_workspace.argtypes = [P(Rel), P(Rel), P(Opts)]
         L.ejoin_threshold.restype = C.c_int
@@ -164,6 +166,19 @@ def band_default(prec: str, dim: int) -> float:
 def tiles():
     L = lib()
     return {i: L.ejoin_tile_name(i).decode() for i in range(1, L.ejoin_tile_count() + 1)}
+
+
+def tile_occupancy(tile: int, dim: int):
+    """(designed, resident) workgroups per CU of the panel kernel of `tile`
+    for rows of `dim` elements (ejoin_tile_occupancy); None if the tile does
+    not take that depth."""
+    d, r = C.c_int32(0), C.c_int32(0)
+    rc = lib().ejoin_tile_occupancy(int(tile), int(dim), C.byref(d), C.byref(r))
+    if rc == E_INVAL:
+        return None
+    if rc != OK:
+        raise EjoinError(rc, "ejoin_tile_occupancy")
+    return d.value, r.value
 
 
 def _rel(X, d):

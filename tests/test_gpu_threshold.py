@@ -354,3 +354,29 @@ def test_fp64_scores_flag_over_selections_and_in_a_batch():
             assert set(zip(r.tolist(), s.tolist())) == set(zip(ori.tolist(), osi.tolist()))
             ref = O.sim64_pairs(Rh, Sh, r, s, d=w.d).astype(np.float32)
             np.testing.assert_array_equal(got.score.cpu().numpy(), ref)
+
+
+def test_panel_kernels_fit_the_workgroups_they_are_laid_out_for():
+    """Every register-panel instantiation a threshold join can launch: the
+    runtime's resident workgroups per CU reach the count the kernel's LDS
+    ring, staging and registers were sized for (two for the two-workgroup
+    forms, whose epilogues rely on the other workgroup's matrix work)."""
+    depths = {"bf16": [64 * k for k in (1, 2, 3, 4, 5, 6, 8, 9, 10, 12)],
+              "fp8": [128 * k for k in (1, 2, 3, 4, 5, 6)],
+              "fp32": [32 * k for k in (1, 2, 3, 4, 5, 6, 8, 9, 10, 12)]}
+    tiles = {12: "bf16", 13: "fp8", 14: "bf16", 15: "fp8", 20: "fp32", 21: "fp32",
+             24: "bf16", 25: "fp8"}
+    checked = 0
+    for tile, prec in tiles.items():
+        for d in depths[prec]:
+            occ = E.tile_occupancy(tile, d)
+            if occ is None:
+                continue
+            designed, resident = occ
+            assert designed in (1, 2), (tile, d, designed)
+            if tile in (14, 15, 21):
+                assert designed == 2, (tile, d)
+            assert resident >= designed, (tile, d, designed, resident)
+            checked += 1
+    assert checked >= 40
+    assert E.tile_occupancy(3, 384) is None and E.tile_occupancy(14, 100000) is None
