@@ -106,7 +106,8 @@ struct ThresholdEpiT {
 
     // Phase 1 (no branches): one wave mask per group of four accumulators
     // from a compare of their maximum.  Phase 2: only groups with a possible
-    // hit are split per register; interior tiles skip the bounds test.
+    // hit are split per register (both masks of the four rows at once);
+    // interior tiles skip the bounds test.
     template <int RB, int CB>
     __device__ static __forceinline__ void tile(const Params& p, Smem& sm, State& s,
                                                 v16f (&acc)[RB][CB], const TileCtx& c) {
@@ -149,44 +150,59 @@ struct ThresholdEpiT {
                                     p.band_ctr, c.lane);
                     const int gj = gj0 + cb * 32;
                     const bool vj = !c.edge || gj < nS32;
-                    uint64_t ml[4];
+                    // the four rows' masks at once: >= lo (a match or a band
+                    // pair) and >= hi (certain); certain pairs are staged from
+                    // their compare masks, band pairs only when there are any
+                    uint64_t mlo[4], mhi[4];
+                    bool hit[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const int gi = gi0 + rb * 32 + 8 * q4 + k;
                         const bool v = vj && (!c.edge || gi < nR32);
-                        ml[k] = __ballot(v && acc[rb][cb][e4 + k] >= s.lo);
+                        const float a = acc[rb][cb][e4 + k];
+                        mlo[k] = __ballot(v && a >= s.lo);
+                        hit[k] = v && a >= s.hi;
+                        mhi[k] = __ballot(hit[k]);
                     }
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        if (!ml[k]) continue;
-                        const float a = acc[rb][cb][e4 + k];
-                        const int gi = gi0 + rb * 32 + 8 * q4 + k;
-                        const bool in_lo = (ml[k] >> c.lane) & 1ull;
-                        const bool in_hi = in_lo && a >= s.hi;
-                        const uint64_t mhi = __ballot(in_hi);
-                        const uint64_t mb = ml[k] & ~mhi;
-                        int ri = gi, si = gj;
-                        if constexpr (PERM)
-                            if (in_lo) {
-                                ri = p.perm_r[gi];
-                                si = p.perm_s[gj];
-                            }
-                        if (in_hi) {
+                        if (!mhi[k]) continue;
+                        if (hit[k]) {
+                            const int gi = gi0 + rb * 32 + 8 * q4 + k;
                             Pair pr;
-                            pr.r = ri;
-                            pr.s = si;
-                            pr.score = a;
-                            sm.out[c.wave][s.n_out + lanes_below(mhi)] = pr;
-                        } else if (in_lo) {
-                            BE be;
-                            if constexpr (TAG)
-                                be = make_int4(ri, si, p.job, 0);
-                            else
-                                be = make_int2(ri, si);
-                            sm.band[c.wave][s.n_band + lanes_below(mb)] = be;
+                            pr.r = gi;
+                            pr.s = gj;
+                            if constexpr (PERM) {
+                                pr.r = p.perm_r[gi];
+                                pr.s = p.perm_s[gj];
+                            }
+                            pr.score = acc[rb][cb][e4 + k];
+                            sm.out[c.wave][s.n_out + lanes_below(mhi[k])] = pr;
                         }
-                        s.n_out += __popcll(mhi);
-                        s.n_band += __popcll(mb);
+                        s.n_out += __popcll(mhi[k]);
+                    }
+                    if ((mlo[0] & ~mhi[0]) | (mlo[1] & ~mhi[1]) | (mlo[2] & ~mhi[2]) |
+                        (mlo[3] & ~mhi[3])) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const uint64_t mb = mlo[k] & ~mhi[k];
+                            if (!mb) continue;
+                            if ((mb >> c.lane) & 1ull) {
+                                const int gi = gi0 + rb * 32 + 8 * q4 + k;
+                                int ri = gi, si = gj;
+                                if constexpr (PERM) {
+                                    ri = p.perm_r[gi];
+                                    si = p.perm_s[gj];
+                                }
+                                BE be;
+                                if constexpr (TAG)
+                                    be = make_int4(ri, si, p.job, 0);
+                                else
+                                    be = make_int2(ri, si);
+                                sm.band[c.wave][s.n_band + lanes_below(mb)] = be;
+                            }
+                            s.n_band += __popcll(mb);
+                        }
                     }
                 }
     }
@@ -206,6 +222,7 @@ struct ThresholdEpiT {
 // the single-join form (untagged band entries)
 template <int NW>
 using ThresholdEpi = ThresholdEpiT<NW, false, false>;
+
 
 struct CandParams {
     const unsigned long long* hdr;  // floor as float bits in H_TOPK_F
