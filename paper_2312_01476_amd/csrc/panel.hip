@@ -1128,9 +1128,10 @@ hipError_t launch_topk_candidates(int prec, const CandArgs& a, hipStream_t st) {
 #define EJ_RUN(P_, KS_, RB_, CB_, NW_, OCC_, NSLOT_)                                           \
     return run_panel<P_, KS_, RB_, CB_, NW_, OCC_, NSLOT_, CandEpi<NW_>>(                       \
         a.A, a.B, a.info_r, a.info_s, a.nR, a.nS, false, a.hdr, ep, st)
-    // K of three slices or more: eight waves (one row block each) and a
-    // direct-load ring of one slot per slice; 64-column FP8 tiles keep the
-    // epilogue of the FP8 sweep short
+    // K of three slices or more: eight waves (one row block each), 128-column
+    // S tiles and a direct-load ring of one slot per slice (FP8 at 768-d fits
+    // 255 registers with 128-column tiles: 235 against 247 ms on the 2M x 200k
+    // top-10 sweep with 64-column ones)
     if (prec == P_BF16) {
         switch (ks) {
             case 3: EJ_RUN(P_BF16, 3, 1, 4, 8, 1, 3);
@@ -1143,10 +1144,10 @@ hipError_t launch_topk_candidates(int prec, const CandArgs& a, hipStream_t st) {
     }
     if (prec == P_FP8) {
         switch (ks) {
-            case 3: EJ_RUN(P_FP8, 3, 1, 2, 8, 1, 3);
-            case 4: EJ_RUN(P_FP8, 4, 1, 2, 8, 1, 4);
-            case 5: EJ_RUN(P_FP8, 5, 1, 2, 8, 1, 5);
-            case 6: EJ_RUN(P_FP8, 6, 1, 2, 8, 1, 6);
+            case 3: EJ_RUN(P_FP8, 3, 1, 4, 8, 1, 3);
+            case 4: EJ_RUN(P_FP8, 4, 1, 4, 8, 1, 4);
+            case 5: EJ_RUN(P_FP8, 5, 1, 4, 8, 1, 5);
+            case 6: EJ_RUN(P_FP8, 6, 1, 4, 8, 1, 6);
         }
         return dispatch_panel<P_FP8, CandEpi>(ks, 1, a.A, a.B, a.info_r, a.info_s, a.nR,
                                               a.nS, false, a.hdr, ep, st);
