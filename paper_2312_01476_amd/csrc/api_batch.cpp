@@ -274,8 +274,9 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
             off = align256(off + bytes);
             return at_;
         };
-        bp.off_hb = take(nr * MLP_HIDDEN * 2);
-        bp.off_z = take(nr * MLP_OUT * 4);
+        // the network's hidden layer and raw codes: learned pass only
+        bp.off_hb = take(bp.exact ? 0 : nr * MLP_HIDDEN * 2);
+        bp.off_z = take(bp.exact ? 0 : nr * MLP_OUT * 4);
         bp.off_u = take(nr * MLP_OUT * 4);
         bp.off_key = take(nr * 4);
         bp.off_pa = take(nr * 4);
@@ -424,17 +425,16 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
     const int pg = (int)std::max<int64_t>(1, std::min<int64_t>(kPrepGrid, (bp.n_rows + 3) / 4));
     if ((e = rec(0)) != hipSuccess) return e;
     if ((e = launch_batch_zero(head, bctr, st)) != hipSuccess) return e;
-    if ((e = launch_batch_prep(bp.prec, head, segs, pg, false, st)) != hipSuccess) return e;
+    // the learned codes read prepared rows; the exact pass codes the
+    // caller's rows directly and prepares them once, in the pruning order
+    if (!bp.exact && (e = launch_batch_prep(bp.prec, head, segs, pg, false, st)) != hipSuccess)
+        return e;
     int32_t* perm_a = (int32_t*)(ws + bp.off_pa);
     if (bp.exact) {
         // codes of the fixed projection, normalised
         if ((e = launch_xp_codes(head, segs, bp.n_rows, dim0, bp.kp,
-                                 (uint16_t*)(ws + bp.off_proj), (float*)(ws + bp.off_z), st)) !=
-            hipSuccess)
-            return e;
-        if ((e = launch_pf_normalise(head, segs, bp.n_rows, (const float*)(ws + bp.off_z),
-                                     (float*)(ws + bp.off_u), (uint16_t*)(ws + bp.off_ub), st)) !=
-            hipSuccess)
+                                 (uint16_t*)(ws + bp.off_proj), (float*)(ws + bp.off_u),
+                                 (uint16_t*)(ws + bp.off_ub), st)) != hipSuccess)
             return e;
     } else if ((e = launch_pf_codes(head, segs, bp.n_rows, m, (uint16_t*)(ws + bp.off_hb),
                                     (float*)(ws + bp.off_z), (float*)(ws + bp.off_u),

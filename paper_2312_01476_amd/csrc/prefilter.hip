@@ -205,76 +205,88 @@ __global__ __launch_bounds__(256) void pf_leaders(const uint64_t* __restrict__ b
 }
 
 // ordering key of every row: the label of its nearest anchor (largest code
-// dot product, ties to the lower anchor), on the matrix cores: 128 rows per
-// workgroup against all anchors, 128 at a time; padding rows get PF_PAD_KEY
+// dot product, ties to the lower anchor), on the matrix cores.  A workgroup
+// takes 128 rows, a wave 32 of them with their codes held in registers (one
+// fragment per 16 code elements); the anchors pass through LDS 128 at a time
+// (swizzled 128-byte rows) and every wave sweeps them in blocks of 32,
+// keeping per lane the best anchor of each of its 16 accumulator rows.
+// Every dot product is the same four matrix-core steps in the same order as
+// any other tile kernel over these codes.  Padding rows get PF_PAD_KEY.
 __global__ __launch_bounds__(256) void pf_assign(const BatchHead* __restrict__ head,
                                                  const PrepSeg* __restrict__ segs,
                                                  const uint16_t* __restrict__ Ub,
                                                  const uint16_t* __restrict__ Ab, int K, int Kpad,
                                                  const int32_t* __restrict__ label,
                                                  int32_t* __restrict__ key) {
-    constexpr int BM = 128, BN = 128, WM = 2, WN = 2;
-    typedef TileGeom<BM, BN, WM, WN> TG;
-    EJ_TILE_SMEM(BM, BN, WM * WN, sm);
-    __shared__ float s_v[WN][BM];
-    __shared__ int s_i[WN][BM];
+    __shared__ __attribute__((aligned(16))) char s_a[128 * 128];
     const int64_t tm = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    if (tm * BM >= head->n_rows) return;
+    if (tm * 128 >= head->n_rows) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave / WN, wn = wave % WN, h = lane >> 5, r32 = lane & 31;
-    float bv[TG::FM][16];
-    int bi[TG::FM][16];
+    const int rr = lane & 31, kh = lane >> 5;
+    const int64_t row0 = tm * 128 + 32 * wave;
+    typedef __attribute__((address_space(1))) const v4i* gv4_ptr;
+    v4i a[4];
 #pragma unroll
-    for (int i = 0; i < TG::FM; ++i)
+    for (int t = 0; t < 4; ++t)
+        a[t] = *(gv4_ptr)(Ub + (row0 + rr) * MLP_OUT + 16 * t + 8 * kh);
+    float bv[16];
+    int bi[16];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            bv[i][e] = -3.0f;
-            bi[i][e] = 0x7fffffff;
+    for (int e = 0; e < 16; ++e) {
+        bv[e] = -3.0f;
+        bi[e] = 0x7fffffff;
+    }
+    for (int c0 = 0; c0 < Kpad; c0 += 128) {
+        __syncthreads();  // the previous chunk has been read
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = threadIdx.x + 256 * q;  // 16-byte piece: anchor idx / 8, chunk idx % 8
+            const int ar = idx >> 3, ch = idx & 7;
+            *(v4i*)(s_a + lds_off(ar, ch)) = *(gv4_ptr)(Ab + (int64_t)(c0 + ar) * MLP_OUT + 8 * ch);
         }
-    for (int at = 0; at < Kpad / BN; ++at) {
-        v16f acc[TG::FM][TG::FN];
-        tile_mainloop<P_BF16, BM, BN, WM, WN>(sm, (const char*)(Ub + tm * BM * MLP_OUT),
-                                              (const char*)Ab, nullptr, nullptr, MLP_OUT * 2, 0,
-                                              at, acc);
+        __syncthreads();
 #pragma unroll
-        for (int j = 0; j < TG::FN; ++j) {
-            const int col = at * BN + wn * TG::WTN + j * 32 + r32;
+        for (int blk = 0; blk < 4; ++blk) {
+            const int ar = 32 * blk + rr;
+            v16f acc;
 #pragma unroll
-            for (int i = 0; i < TG::FM; ++i)
+            for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const v4i b = *(const v4i*)(s_a + lds_off(ar, 2 * t + kh));
+                Mma<P_BF16>::mma(a[t], b, acc, 0, 0);
+            }
+            const int col = c0 + ar;
+            if (col < K) {
 #pragma unroll
                 for (int e = 0; e < 16; ++e)
-                    if (col < K && acc[i][j][e] > bv[i][e]) {  // columns ascend: ties keep the lower
-                        bv[i][e] = acc[i][j][e];
-                        bi[i][e] = col;
+                    if (acc[e] > bv[e]) {  // anchors ascend per lane: ties keep the lower
+                        bv[e] = acc[e];
+                        bi[e] = col;
                     }
+            }
         }
     }
     // best over the 32 lanes of a half (same rows, different anchors)
 #pragma unroll
-    for (int i = 0; i < TG::FM; ++i)
+    for (int e = 0; e < 16; ++e) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-#pragma unroll
-            for (int o = 16; o > 0; o >>= 1) {
-                const float ov = __shfl_xor(bv[i][e], o, 64);
-                const int oi = __shfl_xor(bi[i][e], o, 64);
-                if (ov > bv[i][e] || (ov == bv[i][e] && oi < bi[i][e])) {
-                    bv[i][e] = ov;
-                    bi[i][e] = oi;
-                }
-            }
-            if (r32 == 0) {
-                const int rl = wm * TG::WTM + i * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
-                s_v[wn][rl] = bv[i][e];
-                s_i[wn][rl] = bi[i][e];
+        for (int o = 16; o > 0; o >>= 1) {
+            const float ov = __shfl_xor(bv[e], o, 64);
+            const int oi = __shfl_xor(bi[e], o, 64);
+            if (ov > bv[e] || (ov == bv[e] && oi < bi[e])) {
+                bv[e] = ov;
+                bi[e] = oi;
             }
         }
-    __syncthreads();
-    if (threadIdx.x < BM) {
-        const int t = threadIdx.x;
-        int best = s_i[0][t];
-        if (s_v[1][t] > s_v[0][t] || (s_v[1][t] == s_v[0][t] && s_i[1][t] < best)) best = s_i[1][t];
-        const int64_t row = tm * BM + t;
+    }
+    // lane rr == e of each half writes row 8 (e / 4) + 4 kh + e % 4
+    int best = bi[0];
+#pragma unroll
+    for (int e = 1; e < 16; ++e)
+        if (rr == e) best = bi[e];
+    if (rr < 16) {
+        const int64_t row = row0 + 8 * (rr >> 2) + 4 * kh + (rr & 3);
         const PrepSeg& g = segs[seg_of(segs, head->n_segs, row)];
         const bool real = row - g.row_base < g.rows;
         key[row] = (real && best < K) ? label[best] : PF_PAD_KEY;
@@ -656,14 +668,6 @@ hipError_t launch_pf_codes(const BatchHead* head, const PrepSeg* segs, int64_t n
     const int64_t gx2 = std::min<int64_t>(tiles, 65536), gy2 = (tiles + gx2 - 1) / gx2;
     hipLaunchKernelGGL(pf_l2, dim3((unsigned)gx2, (unsigned)gy2), dim3(256), 0, st, n_rows, Hb,
                        m.W2t, b2, Z);
-    const int64_t blocks = std::min<int64_t>((n_rows + 3) / 4, 16384);
-    hipLaunchKernelGGL(pf_code, dim3((unsigned)blocks), dim3(256), 0, st, head, segs, Z, U, Ub);
-    return hipGetLastError();
-}
-
-hipError_t launch_pf_normalise(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
-                               const float* Z, float* U, uint16_t* Ub, hipStream_t st) {
-    if (n_rows <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>((n_rows + 3) / 4, 16384);
     hipLaunchKernelGGL(pf_code, dim3((unsigned)blocks), dim3(256), 0, st, head, segs, Z, U, Ub);
     return hipGetLastError();

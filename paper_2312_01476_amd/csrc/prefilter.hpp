@@ -20,15 +20,13 @@ constexpr int PF_MAX_ANCHORS = 4094;        // anchors of the ordering key (labe
 hipError_t launch_pf_codes(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
                            const MlpDev& m, uint16_t* Hb, float* Z, float* U, uint16_t* Ub,
                            hipStream_t st);
-// u = z / ||z|| of codes Z already computed (zero for padding rows)
-hipError_t launch_pf_normalise(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
-                               const float* Z, float* U, uint16_t* Ub, hipStream_t st);
-// exact pruning (prune.hip): codes of a fixed +-1 projection (P: 64 x Dp
-// BF16 scratch), then per-tile directions / angular radii in the original
-// space, tile-to-rows maxima and the kept tile pairs (outputs as
-// launch_pf_tiles; err: tiles floats)
+// exact pruning (prune.hip): normalised codes (U, and the BF16 copy Ub) of
+// the input rows under a fixed +-1 projection (P: 64 x Dp BF16 scratch),
+// then per-tile directions / angular radii in the original space,
+// tile-to-rows maxima and the kept tile pairs (outputs as launch_pf_tiles;
+// err: tiles floats)
 hipError_t launch_xp_codes(const BatchHead* head, const PrepSeg* segs, int64_t n_rows, int dim,
-                           int Dp, uint16_t* P, float* Z, hipStream_t st);
+                           int Dp, uint16_t* P, float* U, uint16_t* Ub, hipStream_t st);
 hipError_t launch_xp_tiles(const BatchHead* head, const PrepSeg* segs, const BatchJob* jobs,
                            int64_t n_rows, int Dp, uint16_t* Dir, float* alpha, float* err,
                            float* M1, float* M2, int64_t n_side, int64_t* work,

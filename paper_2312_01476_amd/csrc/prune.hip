@@ -7,7 +7,7 @@
 // embedding space, lies below theta.  The skipped pairs then all have
 // sim64 < theta and the result is the exact join.
 //
-//  * Order: the prepared rows are coded by a fixed random +-1 projection to
+//  * Order: the input rows are coded by a fixed random +-1 projection to
 //    64 dimensions (no training), normalised; the anchor keys and the stable
 //    per-relation sort of the prefilter follow (prefilter.hip).  The order
 //    only decides how tight the tiles are, never what is returned.
@@ -16,7 +16,7 @@
 //    angle between d_T and every exact unit row r / |r| of T: the largest
 //    angle measured on the prepared rows, plus the angle their rounding can
 //    hide (|x_r - r/|r|| <= e_r, the row's quantisation error norm plus the
-//    FP32 normalisation error), plus slack for the FP32 acos.
+//    FP32 normalisation error), plus slack for the FP32 evaluation.
 //  * Tile to rows (on the matrix cores): M1 = max over the rows s of U of
 //    d_T . x_s, M2 = max over the rows r of T of d_U . x_r.  Raised by the
 //    BF16 rounding of d and the rows' error norms, m1 bounds d_T . s/|s| for
@@ -76,112 +76,322 @@ __global__ void xp_proj(int dim, int Dp, uint16_t* __restrict__ P) {
     }
 }
 
-// Z = X P^T over the flat row space (128-row tiles of the prepared rows of
-// every segment, 64 code columns).
-__global__ __launch_bounds__(256) void xp_codes(const BatchHead* __restrict__ head,
-                                                const PrepSeg* __restrict__ segs,
-                                                const uint16_t* __restrict__ P, int Dp,
-                                                float* __restrict__ Z) {
-    constexpr int BM = 128, BN = 64, WM = 2, WN = 2;
-    typedef TileGeom<BM, BN, WM, WN> TG;
-    EJ_TILE_SMEM(BM, BN, WM * WN, sm);
-    __shared__ int s_seg;
-    const int64_t tile = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    const int64_t row0 = tile * BM;
-    if (row0 >= head->n_rows) return;
-    if (threadIdx.x == 0) s_seg = xp_seg_of(segs, head->n_segs, row0);
-    __syncthreads();
-    const PrepSeg& g = segs[s_seg];
-    const int tm = (int)((row0 - g.row_base) / BM);
-    v16f acc[TG::FM][TG::FN];
-    tile_mainloop<P_BF16, BM, BN, WM, WN>(sm, (const char*)g.Xq, (const char*)P, nullptr,
-                                          nullptr, Dp * 2, tm, 0, acc);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wm = wave / WN, wn = wave % WN, h = lane >> 5, r32 = lane & 31;
+// Totals over the wave of 16 per-lane values (transposed butterfly: half of
+// the values cross at each step); lane l returns the total of value
+// (l >> 2) & 15.
+template <int H, int M>
+__device__ __forceinline__ void xp_fold(float (&v)[16], int lane) {
+    const bool up = lane & M;
 #pragma unroll
-    for (int j = 0; j < TG::FN; ++j) {
-        const int col = wn * TG::WTN + j * 32 + r32;
+    for (int i = 0; i < H; ++i) {
+        const float send = up ? v[i] : v[i + H];
+        const float keep = up ? v[i + H] : v[i];
+        v[i] = keep + __shfl_xor(send, M, 64);
+    }
+}
+__device__ __forceinline__ float xp_wave_sum16(float (&v)[16]) {
+    const int lane = threadIdx.x & 63;
+    xp_fold<8, 32>(v, lane);
+    xp_fold<4, 16>(v, lane);
+    xp_fold<2, 8>(v, lane);
+    xp_fold<1, 4>(v, lane);
+    float s = v[0];
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 1, 64);
+    return s;
+}
+
+// Codes u = z / |z|, z = X P^T, straight from the caller's FP32 rows (row
+// order of the input, before any preparation): 32 rows per wave, four waves
+// per 128-row tile, the 64 code columns as two 32-column matrix-core blocks.
+// A lane holds the eight consecutive elements of its row that the BF16 step
+// takes from it (row lane % 32, elements 8 (lane / 32) .. + 8 of every 16),
+// rounded to BF16 on the way in; P's fragments come from memory (64 x Dp,
+// held in the caches).  The normalisation makes the rows' own norms drop
+// out; elements past dim, and padding rows, are zero.
+template <bool VEC>
+__device__ __forceinline__ void xp_load8(const float* __restrict__ x, int k, int dim, float (&v)[8]) {
+    if (VEC && k + 8 <= dim) {
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        typedef __attribute__((address_space(1))) const v4f* gf4_ptr;
+        const v4f a = *(gf4_ptr)(x + k);
+        const v4f b = *(gf4_ptr)(x + k + 4);
 #pragma unroll
-        for (int i = 0; i < TG::FM; ++i)
+        for (int j = 0; j < 4; ++j) {
+            v[j] = a[j];
+            v[4 + j] = b[j];
+        }
+    } else {
+        typedef __attribute__((address_space(1))) const float* gf_ptr;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int64_t row = row0 + wm * TG::WTM + i * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
-                Z[row * MLP_OUT + col] = acc[i][j][e];
-            }
+        for (int j = 0; j < 8; ++j) v[j] = k + j < dim ? *(gf_ptr)(x + k + j) : 0.0f;
     }
 }
 
-// One wave per 128-row tile of the ordered prepared rows: direction d_T (BF16
-// into Dir, zero for an empty or directionless tile), the angular radius
-// A_T with its margins (alpha; 4 for a directionless tile: the bound is void;
-// -1 for an empty tile) and the largest row error e_T (err).
-__global__ __launch_bounds__(256) void xp_tile_stats(const BatchHead* __restrict__ head,
+template <bool VEC>
+__device__ __forceinline__ void xp_codes_rows(const PrepSeg& g, int64_t l0,
+                                              const uint16_t* __restrict__ P, int Dp,
+                                              float* __restrict__ U, uint16_t* __restrict__ Ub,
+                                              int64_t zrow0) {
+    const int lane = threadIdx.x & 63, rr = lane & 31, kh = lane >> 5;
+    const int64_t r = l0 + rr;
+    const bool real = r < g.rows;  // padding lanes read row 0 and drop it
+    const float* x = g.X + (real ? r : 0) * g.ld;
+    typedef __attribute__((address_space(1))) const v4i* gv4_ptr;
+    const uint16_t* p0 = P + (int64_t)rr * Dp + 8 * kh;
+    const uint16_t* p1 = P + (int64_t)(32 + rr) * Dp + 8 * kh;
+    v16f acc0, acc1;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        acc0[e] = 0.0f;
+        acc1[e] = 0.0f;
+    }
+    // chunks of 64 elements (four matrix-core steps): every load of a chunk
+    // is issued before its steps; P is zero past dim, up to Dp
+    const int nch = (g.dim + 63) / 64;
+    for (int c = 0; c < nch; ++c) {
+        float v[4][8];
+        v4i b0[4], b1[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = 64 * c + 16 * t + 8 * kh;
+            xp_load8<VEC>(x, k, g.dim, v[t]);
+            b0[t] = *(gv4_ptr)(p0 + 64 * c + 16 * t);
+            b1[t] = *(gv4_ptr)(p1 + 64 * c + 16 * t);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            v4i a;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float lo = real ? v[t][2 * j] : 0.0f, hi = real ? v[t][2 * j + 1] : 0.0f;
+                a[j] = (int)((uint32_t)f32_to_bf16_rne(lo) | ((uint32_t)f32_to_bf16_rne(hi) << 16));
+            }
+            Mma<P_BF16>::mma(a, b0[t], acc0, 0, 0);
+            Mma<P_BF16>::mma(a, b1[t], acc1, 0, 0);
+        }
+    }
+    // u = z / |z| per row (zero for zero, padding and non-finite rows), FP32
+    // and BF16.  Lane (rr, kh) holds column rr (and 32 + rr) of rows
+    // 8 (e / 4) + 4 kh + e % 4: the squares are totalled over the 32 lanes of
+    // each half, row e's total landing in lane 2 e of the half.
+    float q[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) q[e] = acc0[e] * acc0[e] + acc1[e] * acc1[e];
+    xp_fold<8, 16>(q, lane);
+    xp_fold<4, 8>(q, lane);
+    xp_fold<2, 4>(q, lane);
+    xp_fold<1, 2>(q, lane);
+    const float qt = q[0] + __shfl_xor(q[0], 1, 64);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const float nz = sqrtf(__shfl(qt, 32 * kh + 2 * e, 64));
+        const float u0 = nz > 0.0f ? acc0[e] / nz : 0.0f;
+        const float u1 = nz > 0.0f ? acc1[e] / nz : 0.0f;
+        const int64_t row = zrow0 + 8 * (e >> 2) + 4 * kh + (e & 3);
+        U[row * MLP_OUT + rr] = u0;
+        U[row * MLP_OUT + 32 + rr] = u1;
+        Ub[row * MLP_OUT + rr] = f32_to_bf16_rne(u0);
+        Ub[row * MLP_OUT + 32 + rr] = f32_to_bf16_rne(u1);
+    }
+}
+
+__global__ __launch_bounds__(256) void xp_codes_raw(const BatchHead* __restrict__ head,
+                                                    const PrepSeg* __restrict__ segs,
+                                                    const uint16_t* __restrict__ P, int Dp,
+                                                    float* __restrict__ U,
+                                                    uint16_t* __restrict__ Ub) {
+    const int64_t tile = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int64_t row0 = tile * 128 + 32 * (threadIdx.x >> 6);
+    if (row0 >= head->n_rows) return;
+    const PrepSeg& g = segs[xp_seg_of(segs, head->n_segs, row0)];
+    const int64_t l0 = row0 - g.row_base;
+    // 16-byte loads where every row of the relation starts on 16 bytes
+    if (((uintptr_t)g.X & 15) == 0 && (g.ld & 3) == 0)
+        xp_codes_rows<true>(g, l0, P, Dp, U, Ub, row0);
+    else
+        xp_codes_rows<false>(g, l0, P, Dp, U, Ub, row0);
+}
+
+// One workgroup of eight waves per 128-row tile of the ordered prepared rows
+// (each wave holds 16 rows in registers, lane l elements 4 (l + 64 v) .. +3,
+// so the tile is read from memory once): direction d_T (BF16 into Dir, zero
+// for an empty or directionless tile), the angular radius A_T with its
+// margins (alpha; 4 for a directionless tile: the bound is void; -1 for an
+// empty tile) and the largest row error e_T (err).
+//
+// The angle between a prepared row x and d is taken from the chord,
+// 2 asin(|x/|x| - d| / 2), which FP32 evaluates to within ~1e-4 for every
+// angle up to 2 pi / 3 (an arccos of the cosine loses up to the square root
+// of the cosine's error next to angle 0, where tight tiles live); a larger
+// radius is taken as pi.
+template <int NV>
+__global__ __launch_bounds__(512) void xp_tile_stats(const BatchHead* __restrict__ head,
                                                      const PrepSeg* __restrict__ segs, int Dp,
                                                      uint16_t* __restrict__ Dir,
                                                      float* __restrict__ alpha,
                                                      float* __restrict__ err) {
-    constexpr int NV = 16;  // Dp <= 1024
-    const int lane = threadIdx.x & 63;
-    const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    constexpr int RW = 16;  // rows per wave
+    __shared__ float4 s_c[8][NV * 64];
+    __shared__ float s_e[8], s_a[8];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t tile = blockIdx.x;
     const int64_t row0 = tile * 128;
     if (row0 >= head->n_rows) return;
     const PrepSeg& g = segs[xp_seg_of(segs, head->n_segs, row0)];
     const int64_t l0 = row0 - g.row_base;
     const int cnt = (int)max<int64_t>(0, min<int64_t>(128, g.rows - l0));
-    const uint16_t* X = (const uint16_t*)g.Xq + l0 * Dp;
-    float c[NV];
+    const int rb = wave * RW;
+    const int nr = max(0, min(RW, cnt - rb));
+    const int nu = Dp >> 2;  // 8-byte units per row
+    // every tile lies inside one relation's prepared copy, padded with zero
+    // rows to whole tiles: the wave reads its 16 rows whatever the count
+    // (a uniform row address plus a 32-bit lane offset per load)
+    typedef __attribute__((address_space(1))) const char* gbyte_ptr;
+    const gbyte_ptr X = (gbyte_ptr)((const uint16_t*)g.Xq + (l0 + rb) * Dp);
+    uint2 x[RW][NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) c[v] = 0.0f;
-    float emax = 0.0f;
-    for (int i = 0; i < cnt; ++i) {
+    for (int i = 0; i < RW; ++i) {
+        const gbyte_ptr xr = X + (size_t)i * (size_t)(2 * Dp);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const int k = lane + 64 * v;
-            if (k < Dp) c[v] += bf16_to_f32(X[(int64_t)i * Dp + k]);
+            // lanes past the row's end read its last unit and drop it
+            const uint32_t u = (uint32_t)(lane + 64 * v);
+            const uint32_t uc = min(u, (uint32_t)nu - 1u);
+            uint64_t w = *(__attribute__((address_space(1))) const uint64_t*)(xr + (uc << 3));
+            if (u >= (uint32_t)nu) w = 0ull;
+            x[i][v] = make_uint2((uint32_t)w, (uint32_t)(w >> 32));
         }
-        emax = fmaxf(emax, g.info[l0 + i].enorm);
     }
+    // three unpackings of the BF16 pairs: shifts and masks for the column
+    // sums, byte permutes for the squares and other byte permutes for the
+    // chords; the compiler does not merge them, so every unpacked value dies
+    // at once and the rows stay packed
+    auto lo = [](uint32_t w) { return __uint_as_float(w << 16); };
+    auto hi = [](uint32_t w) { return __uint_as_float(w & 0xffff0000u); };
+    auto lo2 = [](uint32_t w) { return __uint_as_float(__builtin_amdgcn_perm(w, 0u, 0x05040c0cu)); };
+    auto hi2 = [](uint32_t w) { return __uint_as_float(__builtin_amdgcn_perm(w, 0u, 0x07060c0cu)); };
+    // (the chord pass takes its low bytes from the zero operand instead)
+    auto lo3 = [](uint32_t w) { return __uint_as_float(__builtin_amdgcn_perm(w, 0u, 0x05040100u)); };
+    auto hi3 = [](uint32_t w) { return __uint_as_float(__builtin_amdgcn_perm(w, 0u, 0x07060100u)); };
+    // column sums of the wave's rows and the rows' squared norms
+    float4 c[NV];
+    float nn[RW];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) c[v] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        float s = 0.0f;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            c[v].x += lo(x[i][v].x);
+            c[v].y += hi(x[i][v].x);
+            c[v].z += lo(x[i][v].y);
+            c[v].w += hi(x[i][v].y);
+            const float a = lo2(x[i][v].x), b = hi2(x[i][v].x);
+            const float e = lo2(x[i][v].y), f = hi2(x[i][v].y);
+            s = fmaf(a, a, s);
+            s = fmaf(b, b, s);
+            s = fmaf(e, e, s);
+            s = fmaf(f, f, s);
+        }
+        nn[i] = s;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s_c[wave][lane + 64 * v] = c[v];
+    const float en = lane < nr ? g.info[l0 + rb + lane].enorm : 0.0f;
+    const float ew = wave_max(en);
+    if (lane == 0) s_e[wave] = ew;
+    __syncthreads();
+    // the tile's column sums, added in wave order (every wave gets the same)
     float cc = 0.0f;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) cc += c[v] * c[v];
+    for (int v = 0; v < NV; ++v) {
+        float4 t = s_c[0][lane + 64 * v];
+#pragma unroll
+        for (int w = 1; w < 8; ++w) {
+            const float4 q = s_c[w][lane + 64 * v];
+            t.x += q.x;
+            t.y += q.y;
+            t.z += q.z;
+            t.w += q.w;
+        }
+        c[v] = t;
+        cc += t.x * t.x + t.y * t.y + t.z * t.z + t.w * t.w;
+    }
     const float cn = sqrtf(wave_sum(cc));
     const bool dir = cnt > 0 && cn > 1e-3f * (float)cnt;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) c[v] = dir ? c[v] / cn : 0.0f;
-    // largest angle between a prepared row and the direction
-    float cmin = 1.0f;
-    if (dir) {
-        for (int i = 0; i < cnt; ++i) {
-            float dot = 0.0f, nn = 0.0f;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const int k = lane + 64 * v;
-                if (k < Dp) {
-                    const float x = bf16_to_f32(X[(int64_t)i * Dp + k]);
-                    dot = fmaf(x, c[v], dot);
-                    nn = fmaf(x, x, nn);
-                }
-            }
-            dot = wave_sum(dot);
-            nn = wave_sum(nn);
-            if (nn > 0.0f) cmin = fminf(cmin, dot / sqrtf(nn));  // zero rows: cos 0 with all
-        }
-    }
+    const float ic = dir ? 1.0f / cn : 0.0f;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const int k = lane + 64 * v;
-        if (k < Dp) Dir[tile * Dp + k] = f32_to_bf16_rne(c[v]);
+        c[v].x *= ic;
+        c[v].y *= ic;
+        c[v].z *= ic;
+        c[v].w *= ic;
     }
-    if (lane == 0) {
-        // rows are the exact unit rows up to e: quantisation error norm plus
-        // the FP32 normalisation (relative (d + 8) 2^-24, counted 1.5 times)
-        const float e = emax + 1.5f * (float)(g.dim + 8) * 5.9604645e-8f + 1e-6f;
-        err[tile] = e;
-        float a;
-        if (cnt == 0) a = -1.0f;
-        else if (!dir) a = 4.0f;
-        else a = acosf(fmaxf(-1.0f, fminf(1.0f, cmin))) + 1.1f * e + 1e-3f;
-        alpha[tile] = a;
+    // largest angle between a prepared row of the wave and the direction
+    float amax = 0.0f;
+    if (dir) {
+        const float nt = xp_wave_sum16(nn);  // lane l: row (l >> 2) & 15
+        float ch[RW];
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const float n_i = __shfl(nt, 4 * i, 64);
+            const float inv = n_i > 0.0f ? rsqrtf(n_i) : 0.0f;
+            float s = 0.0f;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const float a = fmaf(lo3(x[i][v].x), inv, -c[v].x);
+                const float b = fmaf(hi3(x[i][v].x), inv, -c[v].y);
+                const float e = fmaf(lo3(x[i][v].y), inv, -c[v].z);
+                const float f = fmaf(hi3(x[i][v].y), inv, -c[v].w);
+                s = fmaf(a, a, s);
+                s = fmaf(b, b, s);
+                s = fmaf(e, e, s);
+                s = fmaf(f, f, s);
+            }
+            ch[i] = s;
+        }
+        const float ct = xp_wave_sum16(ch);
+        const int i = (lane >> 2) & 15;
+        // zero rows (similarity 0 with every row) and rows past the tile's
+        // end do not count
+        if (i < nr && nt > 0.0f) {
+            const float chord = sqrtf(ct);
+            amax = chord <= 1.7320508f ? 2.0f * asinf(0.5f * chord) : 3.14159274f;
+        }
+        amax = wave_max(amax);
+    }
+    if (lane == 0) s_a[wave] = amax;
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int u = lane + 64 * v;
+            if (u < nu) {
+                uint2 b;
+                b.x = (uint32_t)f32_to_bf16_rne(c[v].x) | ((uint32_t)f32_to_bf16_rne(c[v].y) << 16);
+                b.y = (uint32_t)f32_to_bf16_rne(c[v].z) | ((uint32_t)f32_to_bf16_rne(c[v].w) << 16);
+                ((uint2*)(Dir + tile * Dp))[u] = b;
+            }
+        }
+        if (lane == 0) {
+            float em = 0.0f, am = 0.0f;
+            for (int w = 0; w < 8; ++w) {
+                em = fmaxf(em, s_e[w]);
+                am = fmaxf(am, s_a[w]);
+            }
+            // rows are the exact unit rows up to e: quantisation error norm
+            // plus the FP32 normalisation (relative (d + 8) 2^-24, counted
+            // 1.5 times)
+            const float e = em + 1.5f * (float)(g.dim + 8) * 5.9604645e-8f + 1e-6f;
+            err[tile] = e;
+            float a;
+            if (cnt == 0) a = -1.0f;
+            else if (!dir) a = 4.0f;
+            else a = am + 1.1f * e + 1e-3f;
+            alpha[tile] = a;
+        }
     }
 }
 
@@ -320,14 +530,14 @@ __global__ __launch_bounds__(256) void xp_bounds(const BatchHead* __restrict__ h
 }
 
 hipError_t launch_xp_codes(const BatchHead* head, const PrepSeg* segs, int64_t n_rows, int dim,
-                           int Dp, uint16_t* P, float* Z, hipStream_t st) {
+                           int Dp, uint16_t* P, float* U, uint16_t* Ub, hipStream_t st) {
     if (n_rows <= 0) return hipSuccess;
     if (Dp > 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(xp_proj, dim3(64), dim3(256), 0, st, dim, Dp, P);
     const int64_t tiles = n_rows / 128;
     const int64_t gx = std::min<int64_t>(tiles, 65536), gy = (tiles + gx - 1) / gx;
-    hipLaunchKernelGGL(xp_codes, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, head, segs,
-                       (const uint16_t*)P, Dp, Z);
+    hipLaunchKernelGGL(xp_codes_raw, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, head,
+                       segs, (const uint16_t*)P, Dp, U, Ub);
     return hipGetLastError();
 }
 
@@ -337,10 +547,15 @@ hipError_t launch_xp_tiles(const BatchHead* head, const PrepSeg* segs, const Bat
                            unsigned long long* n_work, int64_t n_tiles, uint8_t* keep,
                            hipStream_t st) {
     if (n_rows <= 0) return hipSuccess;
-    if (Dp > 1024) return hipErrorInvalidValue;
+    if (Dp > 1024 || (Dp & 3)) return hipErrorInvalidValue;
     const int64_t tiles = n_rows / 128;
-    hipLaunchKernelGGL(xp_tile_stats, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, head,
-                       segs, Dp, Dir, alpha, err);
+    const dim3 tg((unsigned)tiles), tb(512);
+    switch ((Dp + 255) / 256) {
+        case 1: hipLaunchKernelGGL(xp_tile_stats<1>, tg, tb, 0, st, head, segs, Dp, Dir, alpha, err); break;
+        case 2: hipLaunchKernelGGL(xp_tile_stats<2>, tg, tb, 0, st, head, segs, Dp, Dir, alpha, err); break;
+        case 3: hipLaunchKernelGGL(xp_tile_stats<3>, tg, tb, 0, st, head, segs, Dp, Dir, alpha, err); break;
+        default: hipLaunchKernelGGL(xp_tile_stats<4>, tg, tb, 0, st, head, segs, Dp, Dir, alpha, err); break;
+    }
     if (n_side > 0) {
         const int64_t gx = std::min<int64_t>(n_side, 65536), gy = (n_side + gx - 1) / gx;
         hipLaunchKernelGGL(xp_sidemax, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, head,
