@@ -76,6 +76,14 @@ __global__ void xp_proj(int dim, int Dp, uint16_t* __restrict__ P) {
     }
 }
 
+// LDS written by some lanes of a wave and read by others: order the
+// accesses (LDS operations of one wave complete in issue order)
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Totals over the wave of 16 per-lane values (transposed butterfly: half of
 // the values cross at each step); lane l returns the total of value
 // (l >> 2) & 15.
@@ -104,27 +112,24 @@ __device__ __forceinline__ float xp_wave_sum16(float (&v)[16]) {
 // Codes u = z / |z|, z = X P^T, straight from the caller's FP32 rows (row
 // order of the input, before any preparation): 32 rows per wave, four waves
 // per 128-row tile, the 64 code columns as two 32-column matrix-core blocks.
-// A lane holds the eight consecutive elements of its row that the BF16 step
-// takes from it (row lane % 32, elements 8 (lane / 32) .. + 8 of every 16),
-// rounded to BF16 on the way in; P's fragments come from memory (64 x Dp,
-// held in the caches).  The normalisation makes the rows' own norms drop
-// out; elements past dim, and padding rows, are zero.
+// The rows go through LDS in chunks of 64 elements: sixteen lanes read 256
+// contiguous bytes of a row (four rows per load), round them to BF16 and
+// store them as swizzled 128-byte rows, from which every lane takes the
+// fragment of its row for each of the chunk's four BF16 steps.  P's
+// fragments come from memory (64 x Dp, held in the caches).  The
+// normalisation makes the rows' own norms drop out; elements past dim, and
+// padding rows, are zero.
 template <bool VEC>
-__device__ __forceinline__ void xp_load8(const float* __restrict__ x, int k, int dim, float (&v)[8]) {
-    if (VEC && k + 8 <= dim) {
+__device__ __forceinline__ void xp_load4(const float* __restrict__ x, int k, int dim, float (&v)[4]) {
+    typedef __attribute__((address_space(1))) const float* gf_ptr;
+    if (VEC && k + 4 <= dim) {
         typedef float v4f __attribute__((ext_vector_type(4)));
-        typedef __attribute__((address_space(1))) const v4f* gf4_ptr;
-        const v4f a = *(gf4_ptr)(x + k);
-        const v4f b = *(gf4_ptr)(x + k + 4);
+        const v4f a = *(__attribute__((address_space(1))) const v4f*)(x + k);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            v[j] = a[j];
-            v[4 + j] = b[j];
-        }
+        for (int j = 0; j < 4; ++j) v[j] = a[j];
     } else {
-        typedef __attribute__((address_space(1))) const float* gf_ptr;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = k + j < dim ? *(gf_ptr)(x + k + j) : 0.0f;
+        for (int j = 0; j < 4; ++j) v[j] = k + j < dim ? *(gf_ptr)(x + k + j) : 0.0f;
     }
 }
 
@@ -132,11 +137,18 @@ template <bool VEC>
 __device__ __forceinline__ void xp_codes_rows(const PrepSeg& g, int64_t l0,
                                               const uint16_t* __restrict__ P, int Dp,
                                               float* __restrict__ U, uint16_t* __restrict__ Ub,
-                                              int64_t zrow0) {
+                                              int64_t zrow0, char* __restrict__ sx) {
     const int lane = threadIdx.x & 63, rr = lane & 31, kh = lane >> 5;
-    const int64_t r = l0 + rr;
-    const bool real = r < g.rows;  // padding lanes read row 0 and drop it
-    const float* x = g.X + (real ? r : 0) * g.ld;
+    // loader view: row 4 i + lane / 16 of the wave's 32, elements 4 (lane % 16) .. + 4
+    const int lr = lane >> 4, lc = lane & 15;
+    const float* xrow[8];
+    bool live[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int64_t r = l0 + 4 * i + lr;
+        live[i] = r < g.rows;  // padding rows read row 0 and drop it
+        xrow[i] = g.X + (live[i] ? r : 0) * g.ld;
+    }
     typedef __attribute__((address_space(1))) const v4i* gv4_ptr;
     const uint16_t* p0 = P + (int64_t)rr * Dp + 8 * kh;
     const uint16_t* p1 = P + (int64_t)(32 + rr) * Dp + 8 * kh;
@@ -146,27 +158,31 @@ __device__ __forceinline__ void xp_codes_rows(const PrepSeg& g, int64_t l0,
         acc0[e] = 0.0f;
         acc1[e] = 0.0f;
     }
-    // chunks of 64 elements (four matrix-core steps): every load of a chunk
-    // is issued before its steps; P is zero past dim, up to Dp
     const int nch = (g.dim + 63) / 64;
     for (int c = 0; c < nch; ++c) {
-        float v[4][8];
+        float v[8][4];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xp_load4<VEC>(xrow[i], 64 * c + 4 * lc, g.dim, v[i]);
         v4i b0[4], b1[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int k = 64 * c + 16 * t + 8 * kh;
-            xp_load8<VEC>(x, k, g.dim, v[t]);
             b0[t] = *(gv4_ptr)(p0 + 64 * c + 16 * t);
             b1[t] = *(gv4_ptr)(p1 + 64 * c + 16 * t);
         }
+        wave_lds_fence();  // the previous chunk's fragments have been read
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            uint2 w;
+            w.x = (uint32_t)f32_to_bf16_rne(live[i] ? v[i][0] : 0.0f) |
+                  ((uint32_t)f32_to_bf16_rne(live[i] ? v[i][1] : 0.0f) << 16);
+            w.y = (uint32_t)f32_to_bf16_rne(live[i] ? v[i][2] : 0.0f) |
+                  ((uint32_t)f32_to_bf16_rne(live[i] ? v[i][3] : 0.0f) << 16);
+            *(uint2*)(sx + lds_off(4 * i + lr, lc >> 1) + 8 * (lc & 1)) = w;
+        }
+        wave_lds_fence();
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            v4i a;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float lo = real ? v[t][2 * j] : 0.0f, hi = real ? v[t][2 * j + 1] : 0.0f;
-                a[j] = (int)((uint32_t)f32_to_bf16_rne(lo) | ((uint32_t)f32_to_bf16_rne(hi) << 16));
-            }
+            const v4i a = *(const v4i*)(sx + lds_off(rr, 2 * t + kh));
             Mma<P_BF16>::mma(a, b0[t], acc0, 0, 0);
             Mma<P_BF16>::mma(a, b1[t], acc1, 0, 0);
         }
@@ -204,13 +220,15 @@ __global__ __launch_bounds__(256) void xp_codes_raw(const BatchHead* __restrict_
     const int64_t tile = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
     const int64_t row0 = tile * 128 + 32 * (threadIdx.x >> 6);
     if (row0 >= head->n_rows) return;
+    __shared__ __attribute__((aligned(16))) char s_x[4][32 * 128];
     const PrepSeg& g = segs[xp_seg_of(segs, head->n_segs, row0)];
     const int64_t l0 = row0 - g.row_base;
+    char* sx = s_x[threadIdx.x >> 6];
     // 16-byte loads where every row of the relation starts on 16 bytes
     if (((uintptr_t)g.X & 15) == 0 && (g.ld & 3) == 0)
-        xp_codes_rows<true>(g, l0, P, Dp, U, Ub, row0);
+        xp_codes_rows<true>(g, l0, P, Dp, U, Ub, row0, sx);
     else
-        xp_codes_rows<false>(g, l0, P, Dp, U, Ub, row0);
+        xp_codes_rows<false>(g, l0, P, Dp, U, Ub, row0, sx);
 }
 
 // One workgroup of eight waves per 128-row tile of the ordered prepared rows
