@@ -15,7 +15,6 @@ using namespace ej::plan;
 
 namespace {
 
-constexpr int kPrepGrid = 4096;     // batched prep: grid-stride over all rows
 constexpr int kAnchors = 2048;      // prefilter: anchor codes of the ordering key
 constexpr float kAnchorTau = 0.6f;  // prefilter: leader-clustering cosine of the anchors
 constexpr uint64_t kAnchorSeed = 0x5EED;
@@ -69,6 +68,7 @@ struct BatchPlan {
     // ordering and work-list machinery with certified bounds)
     bool approx = false, exact = false;
     int kp = 0;            // exact pruning: padded depth of the jobs (BF16 elements)
+    int kp_max = 0;        // deepest padded row of the batch (elements)
     size_t off_proj = 0;   // exact pruning: the 64 x kp projection
     size_t off_hb = 0, off_z = 0, off_u = 0, off_key = 0, off_pa = 0, off_pb = 0, off_hist = 0,
            off_offs = 0, off_c = 0, off_rho = 0, off_cn = 0, off_alpha = 0, off_work = 0,
@@ -174,6 +174,7 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
         BatchJob& b = J[q];
         const int dim = u.R.dim;
         const int Kp = padded_k(o.prec, dim);
+        bp.kp_max = std::max(bp.kp_max, Kp);
         const double rig = band_rigorous(o.prec, dim);
         double band = rig;
         if (o.band >= 0) {
@@ -380,9 +381,9 @@ hipError_t launch_pass(const BatchPlan& bp, char* ws, int tile_grid, bool fixed,
     auto rec = [&](int i) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
     if ((e = rec(0)) != hipSuccess) return e;
     if ((e = launch_batch_zero(head, bctr, st)) != hipSuccess) return e;
-    int pg = kPrepGrid;
-    if (!fixed) pg = (int)std::max<int64_t>(1, std::min<int64_t>(kPrepGrid, (bp.n_rows + 3) / 4));
-    if ((e = launch_batch_prep(bp.prec, head, segs, pg, false, st)) != hipSuccess) return e;
+    // a captured pass may be replayed on deeper rows than its first batch
+    const int kp_prep = fixed ? 1024 : bp.kp_max;
+    if ((e = launch_batch_prep(bp.prec, kp_prep, head, segs, false, st)) != hipSuccess) return e;
     if ((e = launch_batch_band_edges(head, (BatchJob*)jobs, st)) != hipSuccess) return e;
     if ((e = rec(1)) != hipSuccess) return e;
     int tg = tile_grid;
@@ -422,12 +423,12 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
         m.W1t = (uint16_t*)(b + L.off_w1t);
         m.W2t = (uint16_t*)(b + L.off_w2t);
     }
-    const int pg = (int)std::max<int64_t>(1, std::min<int64_t>(kPrepGrid, (bp.n_rows + 3) / 4));
     if ((e = rec(0)) != hipSuccess) return e;
     if ((e = launch_batch_zero(head, bctr, st)) != hipSuccess) return e;
     // the learned codes read prepared rows; the exact pass codes the
     // caller's rows directly and prepares them once, in the pruning order
-    if (!bp.exact && (e = launch_batch_prep(bp.prec, head, segs, pg, false, st)) != hipSuccess)
+    if (!bp.exact &&
+        (e = launch_batch_prep(bp.prec, bp.kp_max, head, segs, false, st)) != hipSuccess)
         return e;
     int32_t* perm_a = (int32_t*)(ws + bp.off_pa);
     if (bp.exact) {
@@ -458,7 +459,7 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
                             perm_a, (int32_t*)(ws + bp.off_pb), (int32_t*)(ws + bp.off_hist),
                             (int32_t*)(ws + bp.off_offs), st)) != hipSuccess)
         return e;
-    if ((e = launch_batch_prep(bp.prec, head, segs, pg, true, st)) != hipSuccess) return e;
+    if ((e = launch_batch_prep(bp.prec, bp.kp_max, head, segs, true, st)) != hipSuccess) return e;
     if ((e = launch_batch_band_edges(head, (BatchJob*)jobs, st)) != hipSuccess) return e;
     if (bp.exact) {
         if ((e = launch_xp_tiles(head, segs, jobs, bp.n_rows, bp.kp, (uint16_t*)(ws + bp.off_dir),

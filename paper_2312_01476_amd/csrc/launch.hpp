@@ -193,7 +193,10 @@ int batch_occupancy(int tile_id);  // resident workgroups per CU, 0: no batch fo
 hipError_t launch_batch_zero(const BatchHead* head, unsigned long long* bctr, hipStream_t st);
 // after prep: measured band edges of the jobs that use one (job table on the device)
 hipError_t launch_batch_band_edges(const BatchHead* head, BatchJob* jobs, hipStream_t st);
-hipError_t launch_batch_prep(int prec, const BatchHead* head, const PrepSeg* segs, int grid,
+// kp_max: the deepest padded row of the batch (sizes the per-lane registers;
+// deeper rows still take the unregistered form); the grid is the device's
+// resident workgroups of the kernel
+hipError_t launch_batch_prep(int prec, int kp_max, const BatchHead* head, const PrepSeg* segs,
                              bool ordered, hipStream_t st);
 // worklist: the items come from the prefilter's work list (head->work)
 hipError_t launch_batch_tile(int tile_id, const BatchHead* head, const BatchJob* jobs,

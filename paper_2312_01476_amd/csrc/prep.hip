@@ -131,24 +131,27 @@ __device__ __forceinline__ float prep_one_row(const float* __restrict__ X, int64
 constexpr int kRegMax = 1024;
 constexpr int kRegNV = kRegMax / 64;
 
+// NV registers per lane hold rows of up to 64 NV elements; every loop below
+// runs over the same k = lane + 64 j in the same order whatever NV is, so a
+// smaller NV gives the same bits.
+template <int NV>
 __device__ __forceinline__ void load_row_reg(const float* __restrict__ X, bool real, int dim,
                                              int64_t ld, int64_t src, int lane,
-                                             float (&xv)[kRegNV]) {
+                                             float (&xv)[NV]) {
     const float* x = X + src * ld;
 #pragma unroll
-    for (int j = 0; j < kRegNV; ++j) {
+    for (int j = 0; j < NV; ++j) {
         const int k = lane + 64 * j;
         xv[j] = (real && k < dim) ? x[k] : 0.0f;
     }
 }
 
-template <int PREC>
-__device__ __forceinline__ float prep_row_regs(const float (&xv)[kRegNV], bool real, int dim,
+template <int PREC, int NV>
+__device__ __forceinline__ float prep_row_regs(const float (&xv)[NV], bool real, int dim,
                                                void* __restrict__ Xq, int Kp,
                                                RowInfo* __restrict__ info,
                                                unsigned long long* __restrict__ hdr, int64_t row,
                                                int lane) {
-    constexpr int NV = kRegNV;
     float inv = 0.0f, qscale = 1.0f, enorm = 0.0f;
     uint32_t flags = 0;
     float amax = 0.0f;
@@ -244,8 +247,8 @@ __device__ __forceinline__ float prep_row_reg(const float* __restrict__ X, int64
                                               unsigned long long* __restrict__ hdr, int64_t row,
                                               int64_t src, int lane) {
     float xv[kRegNV];
-    load_row_reg(X, src < rows, dim, ld, src, lane, xv);
-    return prep_row_regs<PREC>(xv, src < rows, dim, Xq, Kp, info, hdr, row, lane);
+    load_row_reg<kRegNV>(X, src < rows, dim, ld, src, lane, xv);
+    return prep_row_regs<PREC, kRegNV>(xv, src < rows, dim, Xq, Kp, info, hdr, row, lane);
 }
 
 template <int PREC>
@@ -298,16 +301,16 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
         bool ra = false, rb = false;
         if (first < rows_pad) {
             const int64_t s0 = sel_source(sel, n_src, first, rows, hdr, lane, ra);
-            load_row_reg(X, ra, dim, ld, s0, lane, xa);
+            load_row_reg<kRegNV>(X, ra, dim, ld, s0, lane, xa);
         }
         for (int64_t row = first; row < rows_pad; row += stride) {
             const int64_t next = row + stride;
             if (next < rows_pad) {
                 const int64_t s1 = sel_source(sel, n_src, next, rows, hdr, lane, rb);
-                load_row_reg(X, rb, dim, ld, s1, lane, xb);
+                load_row_reg<kRegNV>(X, rb, dim, ld, s1, lane, xb);
             }
-            wave_emax = fmaxf(wave_emax, prep_row_regs<PREC>(xa, ra, dim, Xq, Kp, info, hdr,
-                                                             row, lane));
+            wave_emax = fmaxf(wave_emax, prep_row_regs<PREC, kRegNV>(xa, ra, dim, Xq, Kp, info,
+                                                                     hdr, row, lane));
 #pragma unroll
             for (int j = 0; j < kRegNV; ++j) xa[j] = xb[j];
             ra = rb;
@@ -332,97 +335,141 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
 
 // Batched prep: the rows of every relation of a batch form one flat range;
 // a wave finds its first row's relation by binary search over the segment
-// starts and then walks forward.  The largest error norm of each side of a
-// job goes to the job's counters for its measured band.
-template <int PREC>
+// starts and then walks forward.  Each wave takes a contiguous range of rows
+// and keeps the next two rows' loads in flight while it prepares one (rows
+// of relations whose depth exceeds the NV registers go through the
+// unregistered form).  The grid is the number of workgroups the GPU holds at
+// once, so every wave runs from the start.  The largest error norm of each
+// side of a job goes to the job's counters for its measured band.
+template <int PREC, int NV>
 __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ head,
                                                   const PrepSeg* __restrict__ segs,
                                                   bool ordered) {
     const int lane = threadIdx.x & 63;
     const int64_t n = head->n_rows;
     const int nseg = head->n_segs;
-    // segment of a flat row (the last one starting at or before it)
-    auto seg_of = [&](int64_t row) {
-        int lo = 0, hi = nseg - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (segs[mid].row_base <= row) lo = mid;
-            else hi = mid - 1;
-        }
-        return lo;
-    };
+    int lo = 0, hi = nseg - 1;
     // with an ordering, output row r holds input row perm[r]
     auto src_of = [&](const PrepSeg& g, int64_t r) {
         return (ordered && g.perm) ? (int64_t)g.perm[r] : r;
     };
-    // each wave takes a contiguous range of rows, so that its consecutive
-    // rows mostly share a segment: the largest error norm is kept per wave
-    // and segment and sent with one atomic when the segment changes
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int64_t per = (n + n_waves - 1) / n_waves;
     const int64_t first = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * per;
     const int64_t last = min(n, first + per);
     if (first >= last) return;
-    int sa = seg_of(first);
-    bool regs = segs[sa].Kp <= kRegMax;
-    float xa[kRegNV], xb[kRegNV];
-    if (regs) {
-        const PrepSeg& g = segs[sa];
-        const int64_t s0 = src_of(g, first - g.row_base);
-        load_row_reg(g.X, s0 < g.rows, g.dim, g.ld, s0, lane, xa);
+    // segment of the first row (the last one starting at or before it)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].row_base <= first) lo = mid;
+        else hi = mid - 1;
+    }
+    auto advance = [&](int sg, int64_t row) {
+        while (sg + 1 < nseg && segs[sg + 1].row_base <= row) ++sg;
+        return sg;
+    };
+    auto fetch = [&](int sg, int64_t row, float (&x)[NV]) {
+        const PrepSeg& h = segs[sg];
+        if (h.Kp <= 64 * NV) {
+            const int64_t sr = src_of(h, row - h.row_base);
+            load_row_reg<NV>(h.X, sr < h.rows, h.dim, h.ld, sr, lane, x);
+        }
+    };
+    float x0[NV], x1[NV], x2[NV];
+    int g0 = lo, g1 = lo, g2 = lo;
+    fetch(g0, first, x0);
+    if (first + 1 < last) {
+        g1 = advance(g0, first + 1);
+        fetch(g1, first + 1, x1);
     }
     float emax = 0.0f;  // largest error norm of segment eseg among this wave's rows
-    int eseg = sa;
+    int eseg = g0;
     auto flush = [&]() {
         if (PREC != P_FP32 && lane == 0 && emax > 0.0f)
             atomicMax((unsigned int*)(segs[eseg].hdr + segs[eseg].enorm_slot),
                       __float_as_uint(emax));
     };
     for (int64_t row = first; row < last; ++row) {
-        const PrepSeg& g = segs[sa];
-        const int64_t r = row - g.row_base;
-        // the wave's next row: its segment, and its data when it is held in
-        // registers, before this row is reduced and written
-        const int64_t next = row + 1;
-        int sb = sa;
-        bool nregs = false;
-        if (next < last) {
-            while (sb + 1 < nseg && segs[sb + 1].row_base <= next) ++sb;
-            const PrepSeg& h = segs[sb];
-            nregs = h.Kp <= kRegMax;
-            if (nregs) {
-                const int64_t s1 = src_of(h, next - h.row_base);
-                load_row_reg(h.X, s1 < h.rows, h.dim, h.ld, s1, lane, xb);
-            }
+        if (row + 2 < last) {
+            g2 = advance(g1, row + 2);
+            fetch(g2, row + 2, x2);
         }
+        const PrepSeg& g = segs[g0];
+        const int64_t r = row - g.row_base;
         const int64_t src = src_of(g, r);
         const float en =
-            regs ? prep_row_regs<PREC>(xa, src < g.rows, g.dim, g.Xq, g.Kp, g.info, g.hdr, r, lane)
-                 : prep_one_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, r, src,
-                                      lane);
-        if (sa != eseg) {
+            g.Kp <= 64 * NV
+                ? prep_row_regs<PREC, NV>(x0, src < g.rows, g.dim, g.Xq, g.Kp, g.info, g.hdr, r,
+                                          lane)
+                : prep_one_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, r, src,
+                                     lane);
+        if (g0 != eseg) {
             flush();
             emax = 0.0f;
-            eseg = sa;
+            eseg = g0;
         }
         emax = fmaxf(emax, en);
 #pragma unroll
-        for (int j = 0; j < kRegNV; ++j) xa[j] = xb[j];
-        sa = sb;
-        regs = nregs;
+        for (int j = 0; j < NV; ++j) {
+            x0[j] = x1[j];
+            x1[j] = x2[j];
+        }
+        g0 = g1;
+        g1 = g2;
     }
     flush();
 }
 
-hipError_t launch_batch_prep(int prec, const BatchHead* head, const PrepSeg* segs, int grid,
-                             bool ordered, hipStream_t st) {
-    dim3 g((unsigned)grid), b(256);
-    switch (prec) {
-        case P_FP32: hipLaunchKernelGGL(batch_prep<P_FP32>, g, b, 0, st, head, segs, ordered); break;
-        case P_BF16: hipLaunchKernelGGL(batch_prep<P_BF16>, g, b, 0, st, head, segs, ordered); break;
-        default: hipLaunchKernelGGL(batch_prep<P_FP8>, g, b, 0, st, head, segs, ordered); break;
+// registers per lane of the batched prep for the deepest relation of a batch
+// (rows deeper than 1024 elements take the unregistered form)
+inline int batch_prep_nv(int kp_max) {
+    const int nv = (kp_max + 63) / 64;
+    return nv <= 4 ? 4 : nv <= 8 ? 8 : nv <= 12 ? 12 : 16;
+}
+
+template <int PREC, int NV>
+int batch_prep_grid() {
+    static int grid = 0;  // resident workgroups of the device in use first
+    if (grid == 0) {
+        int dev = 0, cus = 0, occ = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_prep<PREC, NV>, 256, 0) !=
+                hipSuccess ||
+            cus < 1 || occ < 1)
+            return 1024;
+        grid = cus * occ;
     }
+    return grid;
+}
+
+template <int PREC, int NV>
+hipError_t launch_batch_prep_nv(const BatchHead* head, const PrepSeg* segs, bool ordered,
+                                hipStream_t st) {
+    hipLaunchKernelGGL((batch_prep<PREC, NV>), dim3((unsigned)batch_prep_grid<PREC, NV>()),
+                       dim3(256), 0, st, head, segs, ordered);
     return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_batch_prep_p(int kp_max, const BatchHead* head, const PrepSeg* segs,
+                               bool ordered, hipStream_t st) {
+    switch (batch_prep_nv(kp_max)) {
+        case 4: return launch_batch_prep_nv<PREC, 4>(head, segs, ordered, st);
+        case 8: return launch_batch_prep_nv<PREC, 8>(head, segs, ordered, st);
+        case 12: return launch_batch_prep_nv<PREC, 12>(head, segs, ordered, st);
+        default: return launch_batch_prep_nv<PREC, 16>(head, segs, ordered, st);
+    }
+}
+
+hipError_t launch_batch_prep(int prec, int kp_max, const BatchHead* head, const PrepSeg* segs,
+                             bool ordered, hipStream_t st) {
+    switch (prec) {
+        case P_FP32: return launch_batch_prep_p<P_FP32>(kp_max, head, segs, ordered, st);
+        case P_BF16: return launch_batch_prep_p<P_BF16>(kp_max, head, segs, ordered, st);
+        default: return launch_batch_prep_p<P_FP8>(kp_max, head, segs, ordered, st);
+    }
 }
 
 // Prefilter training rows: slot i < B is the R row of drawn pair i, slot
