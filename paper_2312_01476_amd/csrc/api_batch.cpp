@@ -70,7 +70,7 @@ struct BatchPlan {
     int kp = 0;            // exact pruning: padded depth of the jobs (BF16 elements)
     int kp_max = 0;        // deepest padded row of the batch (elements)
     size_t off_proj = 0;   // exact pruning: the 64 x kp projection
-    size_t off_hb = 0, off_z = 0, off_u = 0, off_key = 0, off_pa = 0, off_pb = 0, off_hist = 0,
+    size_t off_hb = 0, off_u = 0, off_key = 0, off_pa = 0, off_pb = 0, off_hist = 0,
            off_offs = 0, off_c = 0, off_rho = 0, off_cn = 0, off_alpha = 0, off_work = 0,
            off_ub = 0, off_aidx = 0, off_af = 0, off_ab = 0, off_lab = 0, off_up = 0,
            off_dir = 0, off_m1 = 0, off_m2 = 0, off_keep = 0, off_wmask = 0, off_abits = 0;
@@ -275,9 +275,8 @@ ejoin_status make_batch_plan(const ejoin_job* jobs, int n, const ejoin_opts& o, 
             off = align256(off + bytes);
             return at_;
         };
-        // the network's hidden layer and raw codes: learned pass only
+        // the network's hidden layer: learned pass only
         bp.off_hb = take(bp.exact ? 0 : nr * MLP_HIDDEN * 2);
-        bp.off_z = take(bp.exact ? 0 : nr * MLP_OUT * 4);
         bp.off_u = take(nr * MLP_OUT * 4);
         bp.off_key = take(nr * 4);
         bp.off_pa = take(nr * 4);
@@ -438,7 +437,7 @@ hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, cons
                                  (uint16_t*)(ws + bp.off_ub), st)) != hipSuccess)
             return e;
     } else if ((e = launch_pf_codes(head, segs, bp.n_rows, m, (uint16_t*)(ws + bp.off_hb),
-                                    (float*)(ws + bp.off_z), (float*)(ws + bp.off_u),
+                                    (float*)(ws + bp.off_u),
                                     (uint16_t*)(ws + bp.off_ub), st)) != hipSuccess) {
         return e;
     }

@@ -78,15 +78,38 @@ __global__ __launch_bounds__(256) void pf_l1(const BatchHead* __restrict__ head,
     }
 }
 
-// layer 2 over the flat row space: Z = H W2 + b2
-__global__ __launch_bounds__(256) void pf_l2(int64_t n_rows, const uint16_t* __restrict__ Hb,
+// one step of a transposed wave sum: values [H, 2H) cross lane bit M, the
+// lower half keeps its values and adds the partner's
+template <int N, int H, int M>
+__device__ __forceinline__ void pf_fold(float (&v)[N], int lane) {
+    const bool up = lane & M;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const float send = up ? v[i] : v[i + H];
+        const float keep = up ? v[i + H] : v[i];
+        v[i] = keep + __shfl_xor(send, M, 64);
+    }
+}
+
+// layer 2 over the flat row space with the normalisation of the codes:
+// z = H W2 + b2, u = z / ||z|| (FP32, and a BF16 copy for the anchor
+// assignment; zero for padding, zero and non-finite codes).  A wave holds 32
+// of a row's 64 columns: its squares are totalled over the 32 lanes of each
+// half (lane r ends with value r of the wave's 32 rows) and the two column
+// halves meet in LDS.
+__global__ __launch_bounds__(256) void pf_l2(const BatchHead* __restrict__ head,
+                                             const PrepSeg* __restrict__ segs,
+                                             const uint16_t* __restrict__ Hb,
                                              const uint16_t* __restrict__ W2t,
-                                             const float* __restrict__ b2, float* __restrict__ Z) {
+                                             const float* __restrict__ b2, float* __restrict__ U,
+                                             uint16_t* __restrict__ Ub) {
     constexpr int BM = 128, BN = 64, WM = 2, WN = 2;
     typedef TileGeom<BM, BN, WM, WN> TG;
+    static_assert(TG::FM == 2 && TG::FN == 1, "one 32-column block per wave");
     EJ_TILE_SMEM(BM, BN, WM * WN, sm);
+    __shared__ float s_q[WN][BM];
     const int64_t tm = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    if (tm * BM >= n_rows) return;
+    if (tm * BM >= head->n_rows) return;
     v16f acc[TG::FM][TG::FN];
     // the mainloop addresses tile tm of A from its base; pass the tile's rows
     tile_mainloop<P_BF16, BM, BN, WM, WN>(sm, (const char*)(Hb + tm * BM * MLP_HIDDEN),
@@ -94,38 +117,39 @@ __global__ __launch_bounds__(256) void pf_l2(int64_t n_rows, const uint16_t* __r
                                           0, acc);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave / WN, wn = wave % WN, h = lane >> 5, r32 = lane & 31;
+    const int col = wn * TG::WTN + r32;
+    const float bias = bf16v(b2[col]);
+    float q[32];
 #pragma unroll
-    for (int j = 0; j < TG::FN; ++j) {
-        const int col = wn * TG::WTN + j * 32 + r32;
-        const float bias = bf16v(b2[col]);
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < TG::FM; ++i)
+        for (int e = 0; e < 16; ++e) {
+            acc[i][0][e] += bias;
+            q[16 * i + e] = acc[i][0][e] * acc[i][0][e];
+        }
+    pf_fold<32, 16, 16>(q, lane);
+    pf_fold<32, 8, 8>(q, lane);
+    pf_fold<32, 4, 4>(q, lane);
+    pf_fold<32, 2, 2>(q, lane);
+    pf_fold<32, 1, 1>(q, lane);
+    auto row_in_tile = [&](int i, int e) {
+        return wm * TG::WTM + i * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+    };
+    s_q[wn][row_in_tile(r32 >> 4, r32 & 15)] = q[0];
+    __syncthreads();
+    const PrepSeg& g = segs[seg_of(segs, head->n_segs, tm * BM)];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int64_t row = tm * BM + wm * TG::WTM + i * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
-                Z[row * MLP_OUT + col] = acc[i][j][e] + bias;
-            }
-    }
-}
-
-// u = z / ||z|| (FP32, and a BF16 copy for the anchor assignment); codes
-// of padding rows are zero
-__global__ __launch_bounds__(256) void pf_code(const BatchHead* __restrict__ head,
-                                               const PrepSeg* __restrict__ segs,
-                                               const float* __restrict__ Z, float* __restrict__ U,
-                                               uint16_t* __restrict__ Ub) {
-    const int lane = threadIdx.x & 63;
-    const int64_t n = head->n_rows;
-    for (int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); row < n;
-         row += (int64_t)gridDim.x * 4) {
-        const PrepSeg& g = segs[seg_of(segs, head->n_segs, row)];
-        const bool real = row - g.row_base < g.rows;
-        const float z = Z[row * MLP_OUT + lane];
-        const float nz = sqrtf(wave_sum(z * z));
-        const float u = real && nz > 0.0f ? z / nz : 0.0f;
-        U[row * MLP_OUT + lane] = u;
-        Ub[row * MLP_OUT + lane] = f32_to_bf16_rne(u);
-    }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int rl = row_in_tile(i, e);
+            const int64_t row = tm * BM + rl;
+            const float nz = sqrtf(s_q[0][rl] + s_q[1][rl]);
+            const bool real = row - g.row_base < g.rows;
+            const float u = real && nz > 0.0f ? acc[i][0][e] / nz : 0.0f;
+            U[row * MLP_OUT + col] = u;
+            Ub[row * MLP_OUT + col] = f32_to_bf16_rne(u);
+        }
 }
 
 // anchors: the codes of sampled rows (FP32, and BF16 zero-padded to a
@@ -654,7 +678,7 @@ __global__ __launch_bounds__(256) void pf_chunks(const BatchHead* __restrict__ h
 // ---------------------------------------------------------------------------
 
 hipError_t launch_pf_codes(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
-                           const MlpDev& m, uint16_t* Hb, float* Z, float* U, uint16_t* Ub,
+                           const MlpDev& m, uint16_t* Hb, float* U, uint16_t* Ub,
                            hipStream_t st) {
     if (n_rows <= 0) return hipSuccess;
     const int64_t tiles = n_rows / 128;  // n_rows is a multiple of 256
@@ -666,10 +690,8 @@ hipError_t launch_pf_codes(const BatchHead* head, const PrepSeg* segs, int64_t n
     hipLaunchKernelGGL(pf_l1, dim3((unsigned)gx1, (unsigned)gy1), dim3(256), 0, st, head, segs,
                        m.W1t, b1, m.Dp, Hb);
     const int64_t gx2 = std::min<int64_t>(tiles, 65536), gy2 = (tiles + gx2 - 1) / gx2;
-    hipLaunchKernelGGL(pf_l2, dim3((unsigned)gx2, (unsigned)gy2), dim3(256), 0, st, n_rows, Hb,
-                       m.W2t, b2, Z);
-    const int64_t blocks = std::min<int64_t>((n_rows + 3) / 4, 16384);
-    hipLaunchKernelGGL(pf_code, dim3((unsigned)blocks), dim3(256), 0, st, head, segs, Z, U, Ub);
+    hipLaunchKernelGGL(pf_l2, dim3((unsigned)gx2, (unsigned)gy2), dim3(256), 0, st, head, segs,
+                       Hb, m.W2t, b2, U, Ub);
     return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ constexpr int PF_MAX_ANCHORS = 4094;        // anchors of the ordering key (labe
 
 // codes U (flat rows x 64, and a BF16 copy Ub) of every prepared row
 hipError_t launch_pf_codes(const BatchHead* head, const PrepSeg* segs, int64_t n_rows,
-                           const MlpDev& m, uint16_t* Hb, float* Z, float* U, uint16_t* Ub,
+                           const MlpDev& m, uint16_t* Hb, float* U, uint16_t* Ub,
                            hipStream_t st);
 // exact pruning (prune.hip): normalised codes (U, and the BF16 copy Ub) of
 // the input rows under a fixed +-1 projection (P: 64 x Dp BF16 scratch),

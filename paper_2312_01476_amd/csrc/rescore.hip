@@ -5,8 +5,12 @@
 // with the canonical FP64 rule, evaluated from the caller's original float32
 // rows:
 //     dot(a,b) = (((0 + a0 b0) + a1 b1) + ...)  sequential, one rounding per
-//                product and per sum (this file is compiled without FP
-//                contraction, so no fused multiply-add appears);
+//                product and per sum.  The product of two float32 values is
+//                exact in float64 (at most 48 significant bits, exponents far
+//                inside the range), so its rounding changes nothing and each
+//                step is computed as one fused multiply-add, whose single
+//                rounding is the sum's; no other contraction appears (the
+//                file is compiled without it);
 //     sim64    = dot(r,s) / sqrt(dot(r,r) dot(s,s)),  0 for a zero row;
 //     accept   iff sim64 >= theta.
 // The same rule defines the exact result set, so a pair accepted here is a
@@ -102,9 +106,9 @@ __device__ __forceinline__ double wave_sim64(const float* rp, const float* sp, i
         for (int k = 0; k < kChunk; ++k) {
             const double a = (double)mine[k];
             const double b = (double)mine[kChunk + k];
-            dot = dot + a * b;
-            nr = nr + a * a;
-            ns = ns + b * b;
+            dot = __builtin_fma(a, b, dot);  // a * b exact: the sum's rounding only
+            nr = __builtin_fma(a, a, nr);
+            ns = __builtin_fma(b, b, ns);
         }
         wave_lds_sync();
     }

@@ -23,6 +23,9 @@
 // owns one (row, column) dot; the column rows are staged through LDS in
 // 32-float chunks loaded with coalesced reads, and every thread sums its own
 // row chunk by chunk, so the order of the sum stays k = 0, 1, ..., d-1.
+// Each step is one fused multiply-add: the product of two float32 values is
+// exact in float64, so the single rounding is the sum's, as in the
+// sequential definition.
 #include <math.h>
 
 #include "common.hpp"
@@ -88,7 +91,7 @@ __device__ double block_dots(const float* __restrict__ X, int64_t ldX,
             for (int kk = 0; kk < kn; ++kk) {
                 const double a = (double)sm.tile[tid][kk];
                 const double b = r ? (double)sm.rch[kk] : a;
-                acc = acc + a * b;
+                acc = __builtin_fma(a, b, acc);  // a * b exact in FP64
             }
         }
         __syncthreads();
@@ -529,7 +532,8 @@ __device__ __forceinline__ double wave_dot64(const float* __restrict__ r,
         wave_sync();
         const float* mine = rows + lane * FW_STRIDE;
 #pragma unroll
-        for (int q = 0; q < FW_CH; ++q) acc = acc + (double)rch[q] * (double)mine[q];
+        for (int q = 0; q < FW_CH; ++q)
+            acc = __builtin_fma((double)rch[q], (double)mine[q], acc);  // exact product
         wave_sync();
     }
     return p0 + lane < n_live ? acc : 0.0;
