@@ -94,3 +94,42 @@ def test_exact_pruning_equals_the_plain_batch_and_is_refused_where_unsupported()
         E.batch([(R0, S0, 0.8)], prec="fp32", exact_prune=True)
     with pytest.raises(E.EjoinError):          # nor the 256 x 256 tile
         E.batch([(R0, S0, 0.8)], prec="bf16", tile=16, exact_prune=True)
+
+
+def _tight_jobs(D, seed):
+    """Tiles of identical and near-identical rows (angular radius 0 and
+    ~1e-5, where the radius comes only from the margins) against S rows
+    planted at cosine theta +- 1e-6 and +- 1e-4 with the R direction, and
+    duplicated rows on both sides."""
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal(D)
+    u /= np.linalg.norm(u)
+    th = 0.87
+    R_id = np.tile(u.astype(np.float32), (300, 1))                      # radius 0
+    noise = rng.standard_normal((300, D)) * 1e-5
+    R_near = (u + noise).astype(np.float32)                             # radius ~1e-5
+    rows = []
+    for q in range(260):
+        w = rng.standard_normal(D)
+        w -= (w @ u) * u
+        w /= np.linalg.norm(w)
+        c = th + (1e-6, -1e-6, 1e-4, -1e-4)[q % 4]
+        rows.append(c * u + np.sqrt(1 - c * c) * w)
+    far = rng.standard_normal((400, D))                                 # prunable tiles
+    far -= np.outer(far @ u, u) * 1.2
+    S = np.concatenate([np.array(rows), far]).astype(np.float32)
+    S[300:310] = S[0]                                                   # duplicates
+    return [[R_id, S, th], [R_near, S, th], [R_near, R_near, 1.0 - 1e-9]]
+
+
+@pytest.mark.parametrize("D,tile", [(96, 3), (640, 22)])
+def test_exact_pruning_keeps_pairs_next_to_theta_from_tight_tiles(D, tile):
+    host = _tight_jobs(D, seed=6)
+    res, st = _run(host, tile=tile, exact_prune=True)
+    assert st["tiles_kept"] < st["tiles_total"], (st["tiles_kept"], st["tiles_total"])
+    for q, ((R, S, th), got) in enumerate(zip(host, res)):
+        ri, si, _, _ = O.threshold(R, S, th)
+        want = set(zip(ri.tolist(), si.tolist()))
+        got = set(zip(got.r.cpu().tolist(), got.s.cpu().tolist()))
+        assert len(want) > 0 or q == 2
+        assert got == want, (q, len(want - got), len(got - want))
