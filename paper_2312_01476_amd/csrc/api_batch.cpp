@@ -647,6 +647,7 @@ ejoin_status ejoin_batch_graph_create(int32_t max_jobs, const ejoin_opts* opts, 
     memset(g->staging, 0, g->table_bytes);
     if (hipEventCreateWithFlags(&g->done, hipEventDisableTiming) != hipSuccess)
         return fail(EJOIN_E_HIP);
+    batch_prep_query(bp.prec, 1024);  // device queries outside the capture
     if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(EJOIN_E_HIP);
     hipError_t e = hipMemcpyAsync(g->ws + g->off_table, g->staging, g->table_bytes,

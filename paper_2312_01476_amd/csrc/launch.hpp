@@ -198,6 +198,9 @@ hipError_t launch_batch_band_edges(const BatchHead* head, BatchJob* jobs, hipStr
 // resident workgroups of the kernel
 hipError_t launch_batch_prep(int prec, int kp_max, const BatchHead* head, const PrepSeg* segs,
                              bool ordered, hipStream_t st);
+// the grid launch_batch_prep uses (its device query runs once per kernel:
+// call this before a stream capture so that none runs inside it)
+int batch_prep_query(int prec, int kp_max);
 // worklist: the items come from the prefilter's work list (head->work)
 hipError_t launch_batch_tile(int tile_id, const BatchHead* head, const BatchJob* jobs,
                              unsigned long long* bctr, int grid, hipStream_t st,

@@ -463,6 +463,22 @@ hipError_t launch_batch_prep_p(int kp_max, const BatchHead* head, const PrepSeg*
     }
 }
 
+template <int PREC>
+int batch_prep_grid_p(int kp_max) {
+    switch (batch_prep_nv(kp_max)) {
+        case 4: return batch_prep_grid<PREC, 4>();
+        case 8: return batch_prep_grid<PREC, 8>();
+        case 12: return batch_prep_grid<PREC, 12>();
+        default: return batch_prep_grid<PREC, 16>();
+    }
+}
+
+int batch_prep_query(int prec, int kp_max) {
+    return prec == P_FP32   ? batch_prep_grid_p<P_FP32>(kp_max)
+           : prec == P_BF16 ? batch_prep_grid_p<P_BF16>(kp_max)
+                            : batch_prep_grid_p<P_FP8>(kp_max);
+}
+
 hipError_t launch_batch_prep(int prec, int kp_max, const BatchHead* head, const PrepSeg* segs,
                              bool ordered, hipStream_t st) {
     switch (prec) {
