@@ -26,23 +26,26 @@ namespace ej {
 // Each lane of a wave holds one pair (rp, sp, dim; valid = false for none)
 // and gets sim64 of it: the rule is sequential in k, so one lane sums one
 // pair.  The rows come in through LDS in chunks of 16 elements so that every
-// global load reads whole row segments: load j of a chunk serves pairs 2j and
-// 2j + 1, each quarter of the wave reading 64 contiguous bytes of one row
-// (R or S of one pair) at the address it takes from the wave's pair table in
-// LDS.  The next chunk's loads are in flight in registers while the current
-// chunk is summed.  Elements past a pair's dim are zero and are summed like
-// the others: x + 0 * 0 = x exactly, so the sums are those of the sequential
-// definition over k < dim.  A lane without a pair borrows lane 0's (every
-// calling wave has one there) and its result is not used.
+// global load reads whole row segments: four lanes take the 64-byte segment
+// of one row (R or S of one pair) at the address they find in the wave's
+// pair table in LDS, 16 segments per load, 16 bytes per lane (as four 4-byte
+// loads when some row of the wave does not start on 16 bytes); the LDS
+// stores and every lane's reads of its own pair also move 16 bytes.  The
+// next chunk's loads are in flight in registers while the current chunk is
+// summed.  Elements past a pair's dim are zero and are
+// summed like the others: x + 0 * 0 = x exactly, so the sums are those of
+// the sequential definition over k < dim.  A lane without a pair borrows lane
+// 0's (every calling wave has one there) and its result is not used.
 constexpr int kChunk = 16;
-constexpr int kPairStride = 2 * kChunk + 1;  // floats per pair: R chunk, S chunk, pad
+// floats per pair: R chunk, S chunk, pad to an odd number of 16-byte groups,
+// so that 16 lanes reading 16 bytes of 16 pairs hit 16 different bank groups
+constexpr int kPairStride = 2 * kChunk + 4;
 
 typedef __attribute__((address_space(1))) const float* grow_ptr;
 
-struct PairLds {
+struct alignas(16) PairLds {
     uint64_t ptr[64][2];  // the wave's pairs: R row, S row (global addresses)
-    int kmax[64];         // elements of each pair
-    float buf[64 * kPairStride];
+    float buf[64 * kPairStride];  // 10 KB a wave with the table: four workgroups per CU
 };
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -65,35 +68,58 @@ __device__ __forceinline__ double wave_sim64(const float* rp, const float* sp, i
     const int kmax = valid ? dim : d0;
     L.ptr[lane][0] = valid ? (uint64_t)rp : r0;
     L.ptr[lane][1] = valid ? (uint64_t)sp : s0;
-    L.kmax[lane] = kmax;
     int dmax = kmax, dmin = kmax;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         dmax = max(dmax, __shfl_xor(dmax, o, 64));
         dmin = min(dmin, __shfl_xor(dmin, o, 64));
     }
+    // every row of the wave on 16 bytes (lanes without a pair stand in lane
+    // 0's): 16-byte loads, else four 4-byte loads of the same elements
+    const bool vec = __all(!valid || ((((uint64_t)rp | (uint64_t)sp) & 15) == 0)) &&
+                     (((r0 | s0) & 15) == 0);
     wave_lds_sync();
-    // this lane's part of load j: pair 2j + half, row `side`, element e
-    const int q = lane >> 4, e = lane & 15;
-    const int half = q >> 1, side = q & 1;
-    float v[32];
+    // load j: row segment 16 j + lane / 4 (pair (16 j + lane / 4) / 2, R or S
+    // by its parity), elements 4 (lane % 4) .. + 4 of the chunk
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(1))) const v4f* gv4f_ptr;
+    const int piece = lane & 3, rcl = lane >> 2;
+    v4f v[8];
     auto load = [&](int k0) {
-        const int k = k0 + e;
+        const int k = k0 + 4 * piece;
         if (k0 + kChunk <= dmin) {  // wave-uniform: every pair has the whole chunk
 #pragma unroll
-            for (int j = 0; j < 32; ++j) v[j] = ((grow_ptr)L.ptr[2 * j + half][side])[k];
+            for (int j = 0; j < 8; ++j) {
+                const int rc = 16 * j + rcl;
+                const grow_ptr x = (grow_ptr)L.ptr[rc >> 1][rc & 1] + k;
+                if (vec) {
+                    v[j] = *(gv4f_ptr)x;
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) v[j][t] = x[t];
+                }
+            }
         } else {
 #pragma unroll
-            for (int j = 0; j < 32; ++j) {
-                const bool ok = k < L.kmax[2 * j + half];
-                const float x = ((grow_ptr)L.ptr[2 * j + half][side])[ok ? k : 0];
-                v[j] = ok ? x : 0.0f;
+            for (int j = 0; j < 8; ++j) {
+                const int rc = 16 * j + rcl;
+                const grow_ptr x = (grow_ptr)L.ptr[rc >> 1][rc & 1];
+                const int km = __shfl(kmax, rc >> 1, 64);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bool ok = k + t < km;
+                    const float xv = x[ok ? k + t : 0];
+                    v[j][t] = ok ? xv : 0.0f;
+                }
             }
         }
     };
     auto store = [&]() {
 #pragma unroll
-        for (int j = 0; j < 32; ++j) L.buf[(2 * j + half) * kPairStride + side * kChunk + e] = v[j];
+        for (int j = 0; j < 8; ++j) {
+            const int rc = 16 * j + rcl;
+            *(v4f*)(L.buf + (rc >> 1) * kPairStride + (rc & 1) * kChunk + 4 * piece) = v[j];
+        }
     };
     double dot = 0.0, nr = 0.0, ns = 0.0;
     const float* mine = L.buf + lane * kPairStride;
@@ -103,12 +129,17 @@ __device__ __forceinline__ double wave_sim64(const float* rp, const float* sp, i
         wave_lds_sync();
         if (k0 + kChunk < dmax) load(k0 + kChunk);  // in flight while this chunk is summed
 #pragma unroll
-        for (int k = 0; k < kChunk; ++k) {
-            const double a = (double)mine[k];
-            const double b = (double)mine[kChunk + k];
-            dot = __builtin_fma(a, b, dot);  // a * b exact: the sum's rounding only
-            nr = __builtin_fma(a, a, nr);
-            ns = __builtin_fma(b, b, ns);
+        for (int t = 0; t < 4; ++t) {
+            const v4f ra = *(const v4f*)(mine + 4 * t);
+            const v4f sa = *(const v4f*)(mine + kChunk + 4 * t);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double x = (double)ra[c];
+                const double y = (double)sa[c];
+                dot = __builtin_fma(x, y, dot);  // x * y exact: the sum's rounding only
+                nr = __builtin_fma(x, x, nr);
+                ns = __builtin_fma(y, y, ns);
+            }
         }
         wave_lds_sync();
     }

@@ -719,9 +719,10 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
                     if (n_live > 0 && valid) {
                         const double* mine = ((c & 1) ? rows1 : rows0) + lane * FW_STRIDE;
                         const double* rc = (c & 1) ? rch1 : rch0;
-                        // (the chunks are zero past dim: the extra terms add exact zeros)
+                        // (the chunks are zero past dim: the extra terms add exact zeros;
+                        // the products of the widened float32 values are exact)
 #pragma unroll
-                        for (int q = 0; q < FW_CH; ++q) acc = acc + rc[q] * mine[q];
+                        for (int q = 0; q < FW_CH; ++q) acc = __builtin_fma(rc[q], mine[q], acc);
                     }
                     // buffer (c + 1) & 1 was last read for chunk c - 1, before
                     // the previous barrier
