@@ -396,8 +396,9 @@ hipError_t launch_pass(const BatchPlan& bp, char* ws, int tile_grid, bool fixed,
     return launch_batch_counts(head, jobs, bctr, st);
 }
 
-// The prefiltered pass: prep in input order, codes and keys, per-relation
-// order, prep again in that order, tile statistics and bounds (work list),
+// The pruned passes: codes and keys (learned: the network on rows prepared
+// in input order; exact: the projection of the input rows), per-relation
+// order, prep in that order, tile statistics and bounds (work list),
 // persistent tiles over the work list, rescore, counts.
 hipError_t launch_pass_approx(const BatchPlan& bp, char* ws, int tile_grid, const ejoin_opts& o,
                               hipStream_t st, hipEvent_t* ev) {
