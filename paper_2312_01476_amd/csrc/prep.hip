@@ -14,6 +14,36 @@
 
 namespace ej {
 
+// Every memory access of the prep kernels goes through global (not generic)
+// pointers: a generic access may be served by LDS as well, and while one is
+// in flight the compiler waits for every outstanding load before it uses any
+// loaded register, which would drain the rows kept in flight.
+typedef __attribute__((address_space(1))) const float* gsrc_ptr;
+
+__device__ __forceinline__ void global_or(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_fetch_or((__attribute__((address_space(1))) unsigned long long*)p, v,
+                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void global_max_u32(unsigned long long* slot, float v) {
+    __hip_atomic_fetch_max((__attribute__((address_space(1))) unsigned int*)slot,
+                           __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+// one 16-byte global store of a row's RowInfo
+__device__ __forceinline__ void store_info(RowInfo* info, int64_t row, float inv, float qscale,
+                                           float enorm, uint32_t flags) {
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    v4u w;
+    w[0] = __float_as_uint(inv);
+    w[1] = __float_as_uint(qscale);
+    w[2] = __float_as_uint(enorm);
+    w[3] = flags;
+    *(__attribute__((address_space(1))) v4u*)(info + row) = w;
+}
+
 // Prepare input row `src` into output row `row` (one wave; src >= rows is
 // tile padding, written as zeros).  Returns the row's quantisation error
 // norm (0 for FP32).
@@ -25,7 +55,7 @@ __device__ __forceinline__ float prep_one_row(const float* __restrict__ X, int64
                                               int64_t src, int lane, int real_ = -1) {
     float inv = 0.0f, qscale = 1.0f, enorm = 0.0f;
     uint32_t flags = 0;
-    const float* x = X + src * ld;
+    const gsrc_ptr x = (gsrc_ptr)(X + src * ld);
     const bool real = real_ < 0 ? src < rows : real_ != 0;
 
     if (real) {
@@ -60,7 +90,7 @@ __device__ __forceinline__ float prep_one_row(const float* __restrict__ X, int64
             }
         }
     }
-    if (flags != 0 && lane == 0) atomicOr(hdr + H_FLAGS, (unsigned long long)flags);
+    if (flags != 0 && lane == 0) global_or(hdr + H_FLAGS, (unsigned long long)flags);
 
     // FP8: choose the largest power of two p with max|x_hat| * 2^p <= 448
     if (PREC == P_FP8 && inv != 0.0f) {
@@ -76,13 +106,13 @@ __device__ __forceinline__ float prep_one_row(const float* __restrict__ X, int64
     // pass 3: write the normalised, rounded, zero-padded row
     float esq = 0.0f;
     if (PREC == P_FP32) {
-        float* out = (float*)Xq + row * (int64_t)Kp;
+        const auto out = gptr((float*)Xq + row * (int64_t)Kp);
         for (int k = lane; k < Kp; k += 64) {
             float v = (k < dim && inv != 0.0f) ? x[k] * inv : 0.0f;
             out[k] = v;
         }
     } else if (PREC == P_BF16) {
-        uint16_t* out = (uint16_t*)Xq + row * (int64_t)Kp;
+        const auto out = gptr((uint16_t*)Xq + row * (int64_t)Kp);
         for (int k = lane; k < Kp; k += 64) {
             uint16_t b = 0;
             if (k < dim && inv != 0.0f) {
@@ -94,7 +124,7 @@ __device__ __forceinline__ float prep_one_row(const float* __restrict__ X, int64
             out[k] = b;
         }
     } else {
-        uint8_t* out = (uint8_t*)Xq + row * (int64_t)Kp;
+        const auto out = gptr((uint8_t*)Xq + row * (int64_t)Kp);
         const float rq = 1.0f / qscale;  // exact: power of two
         for (int k = lane; k < Kp; k += 64) {
             uint8_t b = 0;
@@ -112,14 +142,7 @@ __device__ __forceinline__ float prep_one_row(const float* __restrict__ X, int64
         esq = wave_sum(esq);
         enorm = sqrtf(esq);
     }
-    if (lane == 0) {
-        RowInfo ri;
-        ri.inv = inv;
-        ri.qscale = qscale;
-        ri.enorm = enorm;
-        ri.flags = flags;
-        info[row] = ri;
-    }
+    if (lane == 0) store_info(info, row, inv, qscale, enorm, flags);
     return enorm;
 }
 
@@ -134,24 +157,30 @@ constexpr int kRegNV = kRegMax / 64;
 // NV registers per lane hold rows of up to 64 NV elements; every loop below
 // runs over the same k = lane + 64 j in the same order whatever NV is, so a
 // smaller NV gives the same bits.
+// Every lane issues all NV loads, whatever the row and its length (a row that
+// is not real reads row 0, a lane past dim the row's last element), so that
+// the number of loads in flight never depends on a branch and the compiler
+// can wait for one row while the next ones load.  The values are raw: the
+// elements that are not the row's are zeroed by prep_row_regs, where they
+// are first used.  X must hold a row 0.
 template <int NV>
 __device__ __forceinline__ void load_row_reg(const float* __restrict__ X, bool real, int dim,
                                              int64_t ld, int64_t src, int lane,
                                              float (&xv)[NV]) {
-    const float* x = X + src * ld;
+    const gsrc_ptr x = (gsrc_ptr)(X + (real ? src : 0) * ld);
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int k = lane + 64 * j;
-        xv[j] = (real && k < dim) ? x[k] : 0.0f;
-    }
+    for (int j = 0; j < NV; ++j) xv[j] = x[min(lane + 64 * j, dim - 1)];
 }
 
 template <int PREC, int NV>
-__device__ __forceinline__ float prep_row_regs(const float (&xv)[NV], bool real, int dim,
+__device__ __forceinline__ float prep_row_regs(const float (&xraw)[NV], bool real, int dim,
                                                void* __restrict__ Xq, int Kp,
                                                RowInfo* __restrict__ info,
                                                unsigned long long* __restrict__ hdr, int64_t row,
                                                int lane) {
+    float xv[NV];  // the row's elements, zero past dim and for a row that is not real
+#pragma unroll
+    for (int j = 0; j < NV; ++j) xv[j] = (real && lane + 64 * j < dim) ? xraw[j] : 0.0f;
     float inv = 0.0f, qscale = 1.0f, enorm = 0.0f;
     uint32_t flags = 0;
     float amax = 0.0f;
@@ -182,7 +211,7 @@ __device__ __forceinline__ float prep_row_regs(const float (&xv)[NV], bool real,
             else inv = ldexpf(1.0f / sqrtf(ss), -e);
         }
     }
-    if (flags != 0 && lane == 0) atomicOr(hdr + H_FLAGS, (unsigned long long)flags);
+    if (flags != 0 && lane == 0) global_or(hdr + H_FLAGS, (unsigned long long)flags);
 
     if (PREC == P_FP8 && inv != 0.0f) {
         float am = 0.0f;
@@ -203,7 +232,8 @@ __device__ __forceinline__ float prep_row_regs(const float (&xv)[NV], bool real,
         if (k >= Kp) break;
         const bool live = k < dim && inv != 0.0f;
         if (PREC == P_FP32) {
-            ((float*)Xq)[row * (int64_t)Kp + k] = live ? xv[j] * inv : 0.0f;
+            ((__attribute__((address_space(1))) float*)Xq)[row * (int64_t)Kp + k] =
+                live ? xv[j] * inv : 0.0f;
         } else if (PREC == P_BF16) {
             uint16_t b = 0;
             if (live) {
@@ -212,7 +242,7 @@ __device__ __forceinline__ float prep_row_regs(const float (&xv)[NV], bool real,
                 float e = bf16_to_f32(b) - v;
                 esq = fmaf(e, e, esq);
             }
-            ((uint16_t*)Xq)[row * (int64_t)Kp + k] = b;
+            ((__attribute__((address_space(1))) uint16_t*)Xq)[row * (int64_t)Kp + k] = b;
         } else {
             uint8_t b = 0;
             if (live) {
@@ -222,21 +252,14 @@ __device__ __forceinline__ float prep_row_regs(const float (&xv)[NV], bool real,
                 float e = q * (1.0f / qscale) - v;
                 esq = fmaf(e, e, esq);
             }
-            ((uint8_t*)Xq)[row * (int64_t)Kp + k] = b;
+            ((__attribute__((address_space(1))) uint8_t*)Xq)[row * (int64_t)Kp + k] = b;
         }
     }
     if (PREC != P_FP32) {
         esq = wave_sum(esq);
         enorm = sqrtf(esq);
     }
-    if (lane == 0) {
-        RowInfo ri;
-        ri.inv = inv;
-        ri.qscale = qscale;
-        ri.enorm = enorm;
-        ri.flags = flags;
-        info[row] = ri;
-    }
+    if (lane == 0) store_info(info, row, inv, qscale, enorm, flags);
     return enorm;
 }
 
@@ -272,10 +295,12 @@ __device__ __forceinline__ int64_t sel_source(const int32_t* __restrict__ sel, i
                                               bool& real) {
     real = row < rows;
     if (!sel || !real) return row;
-    const int64_t id = sel[row];
-    const bool ok = id >= 0 && id < n_src && (row == 0 || (int64_t)sel[row - 1] < id);
+    typedef const __attribute__((address_space(4))) int32_t* csel_ptr;  // scalar loads
+    const int64_t id = ((csel_ptr)sel)[row];
+    const bool ok =
+        id >= 0 && id < n_src && (row == 0 || (int64_t)((csel_ptr)sel)[row - 1] < id);
     if (!ok) {
-        if (lane == 0) atomicOr(hdr + H_FLAGS, (unsigned long long)F_BADSEL);
+        if (lane == 0) global_or(hdr + H_FLAGS, (unsigned long long)F_BADSEL);
         real = false;
         return 0;
     }
@@ -292,30 +317,45 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
                                                  int64_t n_src) {
     const int lane = threadIdx.x & 63;
     float wave_emax = 0.0f;  // largest error norm seen by this wave
-    const int64_t first = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // the wave index made visibly uniform: row numbers, selection ids and
+    // table fields then come through scalar loads, whose waits leave the
+    // vector loads of the rows in flight
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t first = (int64_t)blockIdx.x * 4 + wv;
     const int64_t stride = (int64_t)gridDim.x * 4;
-    if (Kp <= kRegMax) {
-        // rows in registers; the wave's next row is loaded before the
-        // current one is reduced and written
-        float xa[kRegNV], xb[kRegNV];
-        bool ra = false, rb = false;
-        if (first < rows_pad) {
-            const int64_t s0 = sel_source(sel, n_src, first, rows, hdr, lane, ra);
-            load_row_reg<kRegNV>(X, ra, dim, ld, s0, lane, xa);
+    // rows in registers when some input row exists to stand in for padding
+    const bool x_rows = sel ? n_src > 0 : rows > 0;
+    if (Kp <= kRegMax && x_rows && first < rows_pad) {
+        // three row buffers in a fixed rotation: the wave's next two rows are
+        // loaded before the current one is reduced and written (the loop is
+        // unrolled by three rather than copying buffers: a copy of a register
+        // whose load is in flight would wait for it); prefetches past the end
+        // load the last row again
+        float x0[kRegNV], x1[kRegNV], x2[kRegNV];
+        bool r0, r1, r2;
+        auto fetch = [&](int64_t row, float (&x)[kRegNV], bool& rl) {
+            const int64_t rc = min(row, rows_pad - 1);
+            const int64_t src = sel_source(sel, n_src, rc, rows, hdr, lane, rl);
+            load_row_reg<kRegNV>(X, rl, dim, ld, src, lane, x);
+        };
+        auto body = [&](int64_t row, const float (&x)[kRegNV], bool rl) {
+            wave_emax = fmaxf(wave_emax,
+                              prep_row_regs<PREC, kRegNV>(x, rl, dim, Xq, Kp, info, hdr, row, lane));
+        };
+        fetch(first, x0, r0);
+        fetch(first + stride, x1, r1);
+        for (int64_t row = first;;) {
+            fetch(row + 2 * stride, x2, r2);
+            body(row, x0, r0);
+            if ((row += stride) >= rows_pad) break;
+            fetch(row + 2 * stride, x0, r0);
+            body(row, x1, r1);
+            if ((row += stride) >= rows_pad) break;
+            fetch(row + 2 * stride, x1, r1);
+            body(row, x2, r2);
+            if ((row += stride) >= rows_pad) break;
         }
-        for (int64_t row = first; row < rows_pad; row += stride) {
-            const int64_t next = row + stride;
-            if (next < rows_pad) {
-                const int64_t s1 = sel_source(sel, n_src, next, rows, hdr, lane, rb);
-                load_row_reg<kRegNV>(X, rb, dim, ld, s1, lane, xb);
-            }
-            wave_emax = fmaxf(wave_emax, prep_row_regs<PREC, kRegNV>(xa, ra, dim, Xq, Kp, info,
-                                                                     hdr, row, lane));
-#pragma unroll
-            for (int j = 0; j < kRegNV; ++j) xa[j] = xb[j];
-            ra = rb;
-        }
-    } else {
+    } else if (Kp > kRegMax || !x_rows) {
         for (int64_t row = first; row < rows_pad; row += stride) {
             bool real;
             const int64_t src = sel_source(sel, n_src, row, rows, hdr, lane, real);
@@ -329,7 +369,7 @@ __global__ __launch_bounds__(256) void prep_rows(const float* __restrict__ X, in
     __syncthreads();
     if (threadIdx.x == 0) {
         const float m = fmaxf(fmaxf(s_emax[0], s_emax[1]), fmaxf(s_emax[2], s_emax[3]));
-        if (m > 0.0f) atomicMax((unsigned int*)(hdr + enorm_slot), __float_as_uint(m));
+        if (m > 0.0f) global_max_u32(hdr + enorm_slot, m);
     }
 }
 
@@ -350,12 +390,21 @@ __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ 
     const int nseg = head->n_segs;
     int lo = 0, hi = nseg - 1;
     // with an ordering, output row r holds input row perm[r]
+    // (the permutation is read through the constant address space: one
+    // scalar load of a uniform address, waited for apart from the rows)
     auto src_of = [&](const PrepSeg& g, int64_t r) {
-        return (ordered && g.perm) ? (int64_t)g.perm[r] : r;
+        const int ri = __builtin_amdgcn_readfirstlane((int)r);  // r < 2^31, uniform
+        return (ordered && g.perm)
+                   ? (int64_t)((const __attribute__((address_space(4))) int32_t*)g.perm)[ri]
+                   : r;
     };
     const int64_t n_waves = (int64_t)gridDim.x * 4;
     const int64_t per = (n + n_waves - 1) / n_waves;
-    const int64_t first = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * per;
+    // the wave index made visibly uniform: segment fields, permutation
+    // entries and row numbers then come through scalar loads, whose waits
+    // leave the vector loads of the next rows in flight
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t first = ((int64_t)blockIdx.x * 4 + wv) * per;
     const int64_t last = min(n, first + per);
     if (first >= last) return;
     // segment of the first row (the last one starting at or before it)
@@ -368,54 +417,66 @@ __global__ __launch_bounds__(256) void batch_prep(const BatchHead* __restrict__ 
         while (sg + 1 < nseg && segs[sg + 1].row_base <= row) ++sg;
         return sg;
     };
+    // every fetch loads (see load_row_reg), also for a relation deeper than
+    // the registers (its first 1024 elements, unused) and past the wave's
+    // last row (the last row again); every relation with rows in the flat
+    // range has a row 0
     auto fetch = [&](int sg, int64_t row, float (&x)[NV]) {
         const PrepSeg& h = segs[sg];
-        if (h.Kp <= 64 * NV) {
-            const int64_t sr = src_of(h, row - h.row_base);
-            load_row_reg<NV>(h.X, sr < h.rows, h.dim, h.ld, sr, lane, x);
-        }
+        const int64_t sr = src_of(h, row - h.row_base);
+        load_row_reg<NV>(h.X, sr < h.rows, h.dim, h.ld, sr, lane, x);
     };
+    // three row buffers in a fixed rotation (the loop is unrolled by three
+    // rather than copying buffers: a copy of a register whose load is in
+    // flight would wait for that load)
     float x0[NV], x1[NV], x2[NV];
-    int g0 = lo, g1 = lo, g2 = lo;
-    fetch(g0, first, x0);
-    if (first + 1 < last) {
-        g1 = advance(g0, first + 1);
-        fetch(g1, first + 1, x1);
-    }
+    int ga = lo, gb = lo, gc = lo;  // segments of the rows in x0, x1, x2
+    fetch(ga, first, x0);
+    gb = advance(ga, min(first + 1, last - 1));
+    fetch(gb, min(first + 1, last - 1), x1);
     float emax = 0.0f;  // largest error norm of segment eseg among this wave's rows
-    int eseg = g0;
+    int eseg = ga;
     auto flush = [&]() {
         if (PREC != P_FP32 && lane == 0 && emax > 0.0f)
-            atomicMax((unsigned int*)(segs[eseg].hdr + segs[eseg].enorm_slot),
-                      __float_as_uint(emax));
+            global_max_u32(segs[eseg].hdr + segs[eseg].enorm_slot, emax);
     };
-    for (int64_t row = first; row < last; ++row) {
-        if (row + 2 < last) {
-            g2 = advance(g1, row + 2);
-            fetch(g2, row + 2, x2);
-        }
-        const PrepSeg& g = segs[g0];
+    auto body = [&](int64_t row, const float (&x)[NV], int sg) {
+        const PrepSeg& g = segs[sg];
         const int64_t r = row - g.row_base;
         const int64_t src = src_of(g, r);
+        // (only the 16-register form meets relations deeper than its registers)
         const float en =
-            g.Kp <= 64 * NV
-                ? prep_row_regs<PREC, NV>(x0, src < g.rows, g.dim, g.Xq, g.Kp, g.info, g.hdr, r,
-                                          lane)
-                : prep_one_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, r, src,
-                                     lane);
-        if (g0 != eseg) {
+            (NV == kRegNV && g.Kp > 64 * NV)
+                ? prep_one_row<PREC>(g.X, g.rows, g.dim, g.ld, g.Xq, g.Kp, g.info, g.hdr, r, src,
+                                     lane)
+                : prep_row_regs<PREC, NV>(x, src < g.rows, g.dim, g.Xq, g.Kp, g.info, g.hdr, r,
+                                          lane);
+        if (sg != eseg) {
             flush();
             emax = 0.0f;
-            eseg = g0;
+            eseg = sg;
         }
         emax = fmaxf(emax, en);
-#pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            x0[j] = x1[j];
-            x1[j] = x2[j];
-        }
-        g0 = g1;
-        g1 = g2;
+    };
+    for (int64_t row = first;;) {
+        // x0: row, x1: row + 1; row + 2 goes to x2
+        const int64_t p2 = min(row + 2, last - 1);
+        gc = advance(gb, p2);
+        fetch(gc, p2, x2);
+        body(row, x0, ga);
+        if (++row >= last) break;
+        // x1: row, x2: row + 1; row + 2 goes to x0
+        const int64_t p0 = min(row + 2, last - 1);
+        ga = advance(gc, p0);
+        fetch(ga, p0, x0);
+        body(row, x1, gb);
+        if (++row >= last) break;
+        // x2: row, x0: row + 1; row + 2 goes to x1
+        const int64_t p1 = min(row + 2, last - 1);
+        gb = advance(ga, p1);
+        fetch(gb, p1, x1);
+        body(row, x2, gc);
+        if (++row >= last) break;
     }
     flush();
 }
