@@ -48,6 +48,60 @@ __device__ __forceinline__ bool better(double va, int ja, double vb, int jb) {
     return va > vb || (va == vb && ja < jb);
 }
 
+// The m best of a wave's entries (v[t], j[t]), t < n <= 256, in LDS, by
+// `better` (value, then the lower index), among those with v >= floor: m
+// rounds each take the best entry not taken yet (a per-lane best of the
+// lane's four entries, then across the wave); emit(r, v, j) receives the
+// entry of rank r.  Stops early when fewer than m entries pass.  The indices
+// are distinct (columns of one row).  Returns the number of ranks emitted.
+// (k rounds instead of each entry counting the entries above it: O(k n)
+// work instead of O(n^2).)
+template <typename Emit>
+__device__ __forceinline__ int wave_best_m(const double* v, const int* jv, int n, int m,
+                                           double floor, Emit emit) {
+    const int lane = threadIdx.x & 63;
+    double mv[4];
+    int mj[4];
+    bool mine[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int t = lane + 64 * q;
+        mine[q] = t < n;
+        mv[q] = mine[q] ? v[t] : 0.0;
+        mj[q] = mine[q] ? jv[t] : 0;
+        mine[q] = mine[q] && mv[q] >= floor;
+    }
+    for (int r = 0; r < m; ++r) {
+        bool found = false;
+        double bv = 0.0;
+        int bj = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (mine[q] && (!found || better(mv[q], mj[q], bv, bj))) {
+                bv = mv[q];
+                bj = mj[q];
+                found = true;
+            }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(bv, o, 64);
+            const int oj = __shfl_xor(bj, o, 64);
+            const bool of = __shfl_xor(found ? 1 : 0, o, 64) != 0;
+            if (of && (!found || better(ov, oj, bv, bj))) {
+                bv = ov;
+                bj = oj;
+                found = true;
+            }
+        }
+        if (!found) return r;  // wave-uniform after the reduction
+        emit(r, bv, bj);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (mine[q] && mj[q] == bj) mine[q] = false;
+    }
+    return m;
+}
+
 // ---------------------------------------------------------------------------
 // block-wide canonical FP64 dots (256 threads)
 // ---------------------------------------------------------------------------
@@ -612,12 +666,19 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
                     } else {
                         if (n >= kk) {
                             // the entry of rank kk-1 among the n candidates
-                            for (int t = lane; t < n; t += 64) {
-                                const double vt = v[t];
-                                const int jt = jv[t];
-                                int rank = 0;
-                                for (int u = 0; u < n; ++u) rank += better(v[u], jv[u], vt, jt);
-                                if (rank == kk - 1) sm.lim[w] = vt - 2.0 * di;
+                            if (kk <= 32) {
+                                wave_best_m(v, jv, n, kk, -INFINITY, [&](int r, double bv, int) {
+                                    if (r == kk - 1 && lane == 0) sm.lim[w] = bv - 2.0 * di;
+                                });
+                            } else {
+                                for (int t = lane; t < n; t += 64) {
+                                    const double vt = v[t];
+                                    const int jt = jv[t];
+                                    int rank = 0;
+                                    for (int u = 0; u < n; ++u)
+                                        rank += better(v[u], jv[u], vt, jt);
+                                    if (rank == kk - 1) sm.lim[w] = vt - 2.0 * di;
+                                }
                             }
                             wave_sync();
                         }
@@ -753,20 +814,29 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
             wave_sync();
             // final order by rank among the live entries that pass min_sim
             int n_pass = 0;
-            for (int t = lane; t < n_live; t += 64) {
-                const double vt = v[t];
-                if (!(vt >= min_sim)) continue;
-                ++n_pass;
-                const int jt = jv[t];
-                int rank = 0;
-                for (int u = 0; u < n_live; ++u)
-                    rank += v[u] >= min_sim && better(v[u], jv[u], vt, jt);
-                if (rank < kk) {
-                    out_idx[i * k + rank] = jt;
-                    out_score[i * k + rank] = (float)vt;
+            if (kk <= 32) {
+                n_pass = wave_best_m(v, jv, n_live, kk, min_sim, [&](int r, double bv, int bj) {
+                    if (lane == 0) {
+                        out_idx[i * k + r] = bj;
+                        out_score[i * k + r] = (float)bv;
+                    }
+                });
+            } else {
+                for (int t = lane; t < n_live; t += 64) {
+                    const double vt = v[t];
+                    if (!(vt >= min_sim)) continue;
+                    ++n_pass;
+                    const int jt = jv[t];
+                    int rank = 0;
+                    for (int u = 0; u < n_live; ++u)
+                        rank += v[u] >= min_sim && better(v[u], jv[u], vt, jt);
+                    if (rank < kk) {
+                        out_idx[i * k + rank] = jt;
+                        out_score[i * k + rank] = (float)vt;
+                    }
                 }
+                for (int o = 32; o > 0; o >>= 1) n_pass += __shfl_xor(n_pass, o, 64);
             }
-            for (int o = 32; o > 0; o >>= 1) n_pass += __shfl_xor(n_pass, o, 64);
             for (int t = min(kk, n_pass) + lane; t < k; t += 64) {
                 out_idx[i * k + t] = -1;
                 out_score[i * k + t] = -INFINITY;
