@@ -54,6 +54,110 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const v4f* gv4f_ptr;
+
+// The sequential sums of the wave's pairs (table in L, pair lengths kmax,
+// smallest and largest dmin, dmax).  Load j of a chunk: row segment
+// 16 j + lane / 4 (pair (16 j + lane / 4) / 2, R or S by its parity),
+// elements 4 (lane % 4) .. + 4 of the chunk.  The chunks inside every pair
+// run with two chunks' loads in flight (every load issued whatever the
+// chunk, so that the compiler waits for one chunk while the next loads); the
+// chunks past some pair's end follow one at a time.
+template <bool VEC>
+__device__ __forceinline__ void sim64_sums(PairLds& L, int dmin, int dmax, int kmax, double& dot,
+                                           double& nr, double& ns) {
+    const int lane = threadIdx.x & 63;
+    const int piece = lane & 3, rcl = lane >> 2;
+    const float* mine = L.buf + lane * kPairStride;
+    auto load_full = [&](int c, v4f (&v)[8]) {
+        const int k = kChunk * c + 4 * piece;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int rc = 16 * j + rcl;
+            const grow_ptr x = (grow_ptr)L.ptr[rc >> 1][rc & 1] + k;
+            if (VEC) {
+                v[j] = *(gv4f_ptr)x;
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) v[j][t] = x[t];
+            }
+        }
+    };
+    auto load_tail = [&](int c, v4f (&v)[8]) {
+        const int k = kChunk * c + 4 * piece;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int rc = 16 * j + rcl;
+            const grow_ptr x = (grow_ptr)L.ptr[rc >> 1][rc & 1];
+            const int km = __shfl(kmax, rc >> 1, 64);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bool ok = k + t < km;
+                const float xv = x[ok ? k + t : 0];
+                v[j][t] = ok ? xv : 0.0f;
+            }
+        }
+    };
+    auto store = [&](const v4f (&v)[8]) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int rc = 16 * j + rcl;
+            *(v4f*)(L.buf + (rc >> 1) * kPairStride + (rc & 1) * kChunk + 4 * piece) = v[j];
+        }
+    };
+    auto sum = [&]() {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const v4f ra = *(const v4f*)(mine + 4 * t);
+            const v4f sa = *(const v4f*)(mine + kChunk + 4 * t);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double x = (double)ra[c];
+                const double y = (double)sa[c];
+                dot = __builtin_fma(x, y, dot);  // x * y exact: the sum's rounding only
+                nr = __builtin_fma(x, x, nr);
+                ns = __builtin_fma(y, y, ns);
+            }
+        }
+    };
+    const int nfull = dmin / kChunk;  // chunks inside every pair (wave-uniform)
+    if (nfull > 0) {
+        // two buffers in a fixed rotation; past the last full chunk the
+        // loads repeat it (unused)
+        v4f va[8], vb[8];
+        load_full(0, va);
+        load_full(min(1, nfull - 1), vb);
+        int c = 0;
+        for (; c + 1 < nfull; c += 2) {
+            store(va);
+            wave_lds_sync();
+            load_full(min(c + 2, nfull - 1), va);
+            sum();
+            wave_lds_sync();
+            store(vb);
+            wave_lds_sync();
+            load_full(min(c + 3, nfull - 1), vb);
+            sum();
+            wave_lds_sync();
+        }
+        if (c < nfull) {
+            store(va);
+            wave_lds_sync();
+            sum();
+            wave_lds_sync();
+        }
+    }
+    for (int c = nfull; kChunk * c < dmax; ++c) {
+        v4f vt[8];
+        load_tail(c, vt);
+        store(vt);
+        wave_lds_sync();
+        sum();
+        wave_lds_sync();
+    }
+}
+
 __device__ __forceinline__ double wave_sim64(const float* rp, const float* sp, int dim, bool valid,
                                              PairLds& L) {
     const int lane = threadIdx.x & 63;
@@ -79,70 +183,9 @@ __device__ __forceinline__ double wave_sim64(const float* rp, const float* sp, i
     const bool vec = __all(!valid || ((((uint64_t)rp | (uint64_t)sp) & 15) == 0)) &&
                      (((r0 | s0) & 15) == 0);
     wave_lds_sync();
-    // load j: row segment 16 j + lane / 4 (pair (16 j + lane / 4) / 2, R or S
-    // by its parity), elements 4 (lane % 4) .. + 4 of the chunk
-    typedef float v4f __attribute__((ext_vector_type(4)));
-    typedef __attribute__((address_space(1))) const v4f* gv4f_ptr;
-    const int piece = lane & 3, rcl = lane >> 2;
-    v4f v[8];
-    auto load = [&](int k0) {
-        const int k = k0 + 4 * piece;
-        if (k0 + kChunk <= dmin) {  // wave-uniform: every pair has the whole chunk
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int rc = 16 * j + rcl;
-                const grow_ptr x = (grow_ptr)L.ptr[rc >> 1][rc & 1] + k;
-                if (vec) {
-                    v[j] = *(gv4f_ptr)x;
-                } else {
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) v[j][t] = x[t];
-                }
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int rc = 16 * j + rcl;
-                const grow_ptr x = (grow_ptr)L.ptr[rc >> 1][rc & 1];
-                const int km = __shfl(kmax, rc >> 1, 64);
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const bool ok = k + t < km;
-                    const float xv = x[ok ? k + t : 0];
-                    v[j][t] = ok ? xv : 0.0f;
-                }
-            }
-        }
-    };
-    auto store = [&]() {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int rc = 16 * j + rcl;
-            *(v4f*)(L.buf + (rc >> 1) * kPairStride + (rc & 1) * kChunk + 4 * piece) = v[j];
-        }
-    };
     double dot = 0.0, nr = 0.0, ns = 0.0;
-    const float* mine = L.buf + lane * kPairStride;
-    load(0);
-    for (int k0 = 0; k0 < dmax; k0 += kChunk) {
-        store();
-        wave_lds_sync();
-        if (k0 + kChunk < dmax) load(k0 + kChunk);  // in flight while this chunk is summed
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const v4f ra = *(const v4f*)(mine + 4 * t);
-            const v4f sa = *(const v4f*)(mine + kChunk + 4 * t);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const double x = (double)ra[c];
-                const double y = (double)sa[c];
-                dot = __builtin_fma(x, y, dot);  // x * y exact: the sum's rounding only
-                nr = __builtin_fma(x, x, nr);
-                ns = __builtin_fma(y, y, ns);
-            }
-        }
-        wave_lds_sync();
-    }
+    if (vec) sim64_sums<true>(L, dmin, dmax, kmax, dot, nr, ns);
+    else sim64_sums<false>(L, dmin, dmax, kmax, dot, nr, ns);
     if (nr == 0.0 || ns == 0.0) return 0.0;
     return dot / __builtin_sqrt(nr * ns);
 }
