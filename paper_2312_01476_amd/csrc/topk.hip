@@ -535,7 +535,7 @@ constexpr int FW_WAVES = 4;
 constexpr int FW_CH = 32;
 constexpr int FW_STRIDE = FW_CH + 1;
 
-struct FinSmem {
+struct alignas(16) FinSmem {
     double v[FW_WAVES][256];
     int j[FW_WAVES][256];
     int live[FW_WAVES][256];
@@ -735,14 +735,15 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
             const int* L = sm.live[ref];
             // two chunk buffers (the candidate chunks of the workgroup and
             // this wave's row chunk): chunk c + 1 is loaded while chunk c is
-            // multiplied
-            // the chunks are widened to FP64 once, when stored (each candidate
-            // value serves four rows); the four per-wave float buffers hold
-            // the two FP64 candidate buffers
-            static_assert(2 * 64 * FW_STRIDE * sizeof(double) <= sizeof(sm.rows),
-                          "FP64 chunk buffers do not fit");
-            double* const rows0 = (double*)&sm.rows[0][0];
-            double* const rows1 = rows0 + 64 * FW_STRIDE;
+            // multiplied.  The candidate chunks stay float32 in LDS (36
+            // floats per candidate: 16-byte reads of 16 lanes hit 16
+            // different bank groups) and are widened as each lane reads
+            // them; the row chunk is widened once, when stored
+            constexpr int FWS = FW_CH + 4;
+            static_assert(2 * 64 * FWS * sizeof(float) <= sizeof(sm.rows),
+                          "chunk buffers do not fit");
+            float* const rows0 = &sm.rows[0][0];
+            float* const rows1 = rows0 + 64 * FWS;
             __shared__ double s_rch[2][FW_WAVES][FW_CH];
             double* const rch0 = s_rch[0][w];
             double* const rch1 = s_rch[1][w];
@@ -762,10 +763,10 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
                 }
             };
             auto store = [&](int c) {
-                double* r = (c & 1) ? rows1 : rows0;
+                float* r = (c & 1) ? rows1 : rows0;
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
-                    r[(16 * w + 2 * q + (lane >> 5)) * FW_STRIDE + kk2] = (double)vals[q];
+                    r[(16 * w + 2 * q + (lane >> 5)) * FWS + kk2] = vals[q];
                 if (lane < FW_CH) ((c & 1) ? rch1 : rch0)[lane] = (double)rv;
             };
             for (int p0 = 0; p0 < n; p0 += 64) {
@@ -778,12 +779,18 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
                 for (int c = 0; c < nch; ++c) {
                     if (c + 1 < nch) load(p0, c + 1);
                     if (n_live > 0 && valid) {
-                        const double* mine = ((c & 1) ? rows1 : rows0) + lane * FW_STRIDE;
+                        typedef float v4f __attribute__((ext_vector_type(4)));
+                        const v4f* mine = (const v4f*)(((c & 1) ? rows1 : rows0) + lane * FWS);
                         const double* rc = (c & 1) ? rch1 : rch0;
                         // (the chunks are zero past dim: the extra terms add exact zeros;
                         // the products of the widened float32 values are exact)
 #pragma unroll
-                        for (int q = 0; q < FW_CH; ++q) acc = __builtin_fma(rc[q], mine[q], acc);
+                        for (int q4 = 0; q4 < FW_CH / 4; ++q4) {
+                            const v4f m = mine[q4];
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                acc = __builtin_fma(rc[4 * q4 + e], (double)m[e], acc);
+                        }
                     }
                     // buffer (c + 1) & 1 was last read for chunk c - 1, before
                     // the previous barrier
