@@ -749,52 +749,72 @@ __global__ __launch_bounds__(256) void topk_finalize_w(
             double* const rch1 = s_rch[1][w];
             const int kk2 = lane & 31;
             const int nch = (dim + FW_CH - 1) / FW_CH;
-            float vals[8];
-            float rv = 0.0f;
-            auto load = [&](int p0, int c) {
-                const int k0 = c * FW_CH, kn = min(FW_CH, dim - k0);
-                rv = (n_live > 0 && lane < kn) ? rrow[k0 + lane] : 0.0f;
-                // this wave's 16 of the pass's 64 candidate rows, two rows
-                // per load instruction (lanes 0-31 one, 32-63 the next)
+            // Two chunks' loads in flight, in two register sets used in turn
+            // (the loop is unrolled by two).  Every load is issued, so that
+            // the compiler can wait for one chunk while the next loads: past
+            // the pass's candidates, the row's end or the last chunk the
+            // loads repeat valid addresses and the values are zeroed when
+            // stored.  This wave's 16 of the pass's 64 candidate rows, two
+            // rows per load instruction (lanes 0-31 one, 32-63 the next).
+            auto load = [&](int p0, int c, float (&vals)[8], float& rv) {
+                const int k0 = min(c, nch - 1) * FW_CH;
+                rv = rrow[min(k0 + kk2, dim - 1)];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int tb = min(p0 + 16 * w + 2 * q + (lane >> 5), n - 1);
+                    vals[q] = S[(int64_t)L[tb] * ldS + min(k0 + kk2, dim - 1)];
+                }
+            };
+            auto store = [&](int p0, int c, const float (&vals)[8], float rv) {
+                const int k0 = c * FW_CH;
+                const bool in_row = k0 + kk2 < dim;
+                float* r = (c & 1) ? rows1 : rows0;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const int tb = p0 + 16 * w + 2 * q + (lane >> 5);
-                    vals[q] = (tb < n && kk2 < kn) ? S[(int64_t)L[tb] * ldS + k0 + kk2] : 0.0f;
+                    r[(16 * w + 2 * q + (lane >> 5)) * FWS + kk2] =
+                        (tb < n && in_row) ? vals[q] : 0.0f;
+                }
+                if (lane < FW_CH)
+                    ((c & 1) ? rch1 : rch0)[lane] = (n_live > 0 && in_row) ? (double)rv : 0.0;
+            };
+            auto dot_chunk = [&](int c, bool valid, double& acc) {
+                if (n_live > 0 && valid) {
+                    typedef float v4f __attribute__((ext_vector_type(4)));
+                    const v4f* mine = (const v4f*)(((c & 1) ? rows1 : rows0) + lane * FWS);
+                    const double* rc = (c & 1) ? rch1 : rch0;
+                    // (the chunks are zero past dim: the extra terms add exact zeros;
+                    // the products of the widened float32 values are exact)
+#pragma unroll
+                    for (int q4 = 0; q4 < FW_CH / 4; ++q4) {
+                        const v4f m = mine[q4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            acc = __builtin_fma(rc[4 * q4 + e], (double)m[e], acc);
+                    }
                 }
             };
-            auto store = [&](int c) {
-                float* r = (c & 1) ? rows1 : rows0;
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    r[(16 * w + 2 * q + (lane >> 5)) * FWS + kk2] = vals[q];
-                if (lane < FW_CH) ((c & 1) ? rch1 : rch0)[lane] = (double)rv;
-            };
+            float va[8], vb[8];
+            float ra, rb;
             for (int p0 = 0; p0 < n; p0 += 64) {
                 const int t = p0 + lane;
                 const bool valid = t < n;
                 double acc = 0.0;
-                load(p0, 0);
-                store(0);
+                load(p0, 0, va, ra);
+                load(p0, 1, vb, rb);
+                store(p0, 0, va, ra);
                 __syncthreads();
-                for (int c = 0; c < nch; ++c) {
-                    if (c + 1 < nch) load(p0, c + 1);
-                    if (n_live > 0 && valid) {
-                        typedef float v4f __attribute__((ext_vector_type(4)));
-                        const v4f* mine = (const v4f*)(((c & 1) ? rows1 : rows0) + lane * FWS);
-                        const double* rc = (c & 1) ? rch1 : rch0;
-                        // (the chunks are zero past dim: the extra terms add exact zeros;
-                        // the products of the widened float32 values are exact)
-#pragma unroll
-                        for (int q4 = 0; q4 < FW_CH / 4; ++q4) {
-                            const v4f m = mine[q4];
-#pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                acc = __builtin_fma(rc[4 * q4 + e], (double)m[e], acc);
-                        }
-                    }
-                    // buffer (c + 1) & 1 was last read for chunk c - 1, before
-                    // the previous barrier
-                    if (c + 1 < nch) store(c + 1);
+                // buffer (c + 1) & 1 is written after chunk c is multiplied;
+                // it was last read for chunk c - 1, before the previous barrier
+                for (int c = 0; c < nch; c += 2) {
+                    load(p0, c + 2, va, ra);
+                    dot_chunk(c, valid, acc);
+                    if (c + 1 < nch) store(p0, c + 1, vb, rb);
+                    __syncthreads();
+                    if (c + 1 >= nch) break;
+                    load(p0, c + 3, vb, rb);
+                    dot_chunk(c + 1, valid, acc);
+                    if (c + 2 < nch) store(p0, c + 2, va, ra);
                     __syncthreads();
                 }
                 if (n_live > 0 && valid) {
