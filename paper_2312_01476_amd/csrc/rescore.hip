@@ -31,11 +31,11 @@ namespace ej {
 // pair table in LDS, 16 segments per load, 16 bytes per lane (as four 4-byte
 // loads when some row of the wave does not start on 16 bytes); the LDS
 // stores and every lane's reads of its own pair also move 16 bytes.  The
-// next chunk's loads are in flight in registers while the current chunk is
-// summed.  Elements past a pair's dim are zero and are
-// summed like the others: x + 0 * 0 = x exactly, so the sums are those of
-// the sequential definition over k < dim.  A lane without a pair borrows lane
-// 0's (every calling wave has one there) and its result is not used.
+// next two chunks' loads are in flight in registers while a chunk is summed.
+// Elements past a pair's dim are zero and are summed like the others:
+// x + 0 * 0 = x exactly, so the sums are those of the sequential definition
+// over k < dim.  A lane without a pair borrows lane 0's (every calling wave
+// has one there) and its result is not used.
 constexpr int kChunk = 16;
 // floats per pair: R chunk, S chunk, pad to an odd number of 16-byte groups,
 // so that 16 lanes reading 16 bytes of 16 pairs hit 16 different bank groups
