@@ -133,3 +133,29 @@ def test_exact_pruning_keeps_pairs_next_to_theta_from_tight_tiles(D, tile):
         got = set(zip(got.r.cpu().tolist(), got.s.cpu().tolist()))
         assert len(want) > 0 or q == 2
         assert got == want, (q, len(want - got), len(got - want))
+
+
+def test_exact_pruning_on_rows_not_on_16_bytes():
+    """Rows of a strided view whose stride (D + 3 floats) puts them off
+    16-byte boundaries: the projection codes take their 4-byte load form and
+    the band rescore its 4-byte form; the result is still the exact join."""
+    D = 96
+    host = _jobs(D, seed=7)[:4]
+    jobs, views = [], []
+    for R, S, th in host:
+        def strided(X):
+            buf = torch.zeros((max(1, X.shape[0]), D + 3), dtype=torch.float32)
+            buf[:X.shape[0], :D] = torch.from_numpy(X)
+            return buf.cuda()[:X.shape[0], :D]
+        Rv, Sv = strided(R), strided(S)
+        assert Rv.shape[0] < 2 or Rv.stride(0) == D + 3
+        jobs.append((Rv, Sv, th))
+        views.append((R, S, th))
+    caps = [max(1, R.shape[0] * S.shape[0]) for R, S, _ in views]
+    res, st = E.batch(jobs, prec="bf16", capacities=caps, tile=3, exact_prune=True)
+    assert st["tiles_kept"] < st["tiles_total"], (st["tiles_kept"], st["tiles_total"])
+    for q, ((R, S, th), got) in enumerate(zip(views, res)):
+        ri, si, _, _ = O.threshold(R, S, th)
+        want = set(zip(ri.tolist(), si.tolist()))
+        got = set(zip(got.r.cpu().tolist(), got.s.cpu().tolist()))
+        assert got == want, (q, len(want - got), len(got - want))
