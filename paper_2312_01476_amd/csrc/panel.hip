@@ -16,9 +16,10 @@
 // the MFMAs.
 //
 // The accumulators of each S tile go to an epilogue policy:
-//  * ThresholdEpi -- the threshold predicate of the E-theta-join, with hits
-//    staged per wave in LDS and flushed with one atomicAdd per few hundred
-//    pairs;
+//  * ThresholdEpi -- the threshold predicate of the E-theta-join: groups of
+//    four scores that may reach the band are staged per wave in LDS as
+//    records and split into certain and band pairs when the stage is
+//    written out, with one atomicAdd per list and 64 records;
 //  * CandEpi -- top-k candidates: every column with score >= a floor goes to
 //    its row's candidate slots (the workgroup sweeps all of S, so each row is
 //    owned by one wave and its counter lives in LDS).
@@ -30,25 +31,29 @@
 
 namespace ej {
 
-constexpr int PN_OUTCAP = 384;   // staged certain pairs per wave
-constexpr int PN_BANDCAP = 384;  // staged band pairs per wave
+// Staged candidate records per wave.  A record is one lane's group of four
+// accumulators (four rows of one S column) whose maximum reaches the band;
+// records are split into certain pairs and band pairs only when the stage
+// is written out.
+constexpr int PN_RECCAP = 320;
 
-// Append the staged entries of one wave to a global list: one atomicAdd on
-// the list counter, then a coalesced copy.  Entries past `cap` are dropped
-// (the counter still counts them, so the caller learns the true size).
-template <typename T>
-__device__ __forceinline__ void flush_stage(T* stage, int& n, T* __restrict__ dst, int64_t cap,
-                                            unsigned long long* ctr, int lane) {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+// Exclusive prefix sum over the lanes of a wave of a per-lane count in
+// [0, 7] (one ballot per bit), and the wave's total.
+__device__ __forceinline__ uint32_t lane_prefix7(uint32_t c, uint32_t& total) {
+    const uint64_t b0 = __ballot(c & 1u), b1 = __ballot(c & 2u), b2 = __ballot(c & 4u);
+    total = (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) + 4u * (uint32_t)__popcll(b2);
+    return lanes_below(b0) + 2u * lanes_below(b1) + 4u * lanes_below(b2);
+}
+
+// n places of a global list: lane 0's atomicAdd on the list counter; the
+// first place, read from lane 0, is wave-uniform.
+__device__ __forceinline__ unsigned long long reserve_places(uint32_t n, unsigned long long* ctr,
+                                                             int lane) {
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(ctr, (unsigned long long)n);
-    const uint32_t blo = __shfl((uint32_t)base, 0, 64);
-    const uint32_t bhi = __shfl((uint32_t)(base >> 32), 0, 64);
-    const unsigned long long b = ((unsigned long long)bhi << 32) | blo;
-    for (int e = lane; e < n; e += 64)
-        if ((int64_t)(b + e) < cap) dst[b + e] = stage[e];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    n = 0;
+    const uint32_t blo = __builtin_amdgcn_readlane((uint32_t)base, 0);
+    const uint32_t bhi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), 0);
+    return ((unsigned long long)bhi << 32) | blo;
 }
 
 // Position of the accumulators: element e of 32x32 block (rb, cb) of a lane
@@ -89,25 +94,94 @@ struct ThresholdEpiT {
     typedef ThresholdParams Params;
     typedef typename BandEntryT<TAG>::type BE;
     struct Smem {
-        Pair out[NW][PN_OUTCAP];
-        BE band[NW][PN_BANDCAP];
+        float4 val[NW][PN_RECCAP];  // a record's four scores (rows r .. r + 3)
+        int2 pos[NW][PN_RECCAP];    // its first row r and its column
     };
     struct State {
-        int n_out, n_band;  // staged entries of this wave (wave-uniform)
-        float lo, hi;       // band edges of this sweep
+        int n_rec;       // staged records of this wave (wave-uniform)
+        float lo, hi;    // band edges of this sweep
     };
 
     __device__ static __forceinline__ void init(const Params& p, Smem&, State& s, const TileCtx&) {
-        s.n_out = 0;
-        s.n_band = 0;
+        s.n_rec = 0;
         s.lo = p.lohi ? __uint_as_float((uint32_t)p.lohi[0]) : p.lo;
         s.hi = p.lohi ? __uint_as_float((uint32_t)p.lohi[1]) : p.hi;
     }
 
-    // Phase 1 (no branches): one wave mask per group of four accumulators
-    // from a compare of their maximum.  Phase 2: only groups with a possible
-    // hit are split per register (both masks of the four rows at once);
-    // interior tiles skip the bounds test.
+    // Write the staged records out, one per lane: the rows inside R and S
+    // are split into certain pairs (score >= hi) and band pairs (lo <= score
+    // < hi), and each list takes one atomicAdd per 64 records for its
+    // places.  Entries past a list's capacity are dropped (its counter still
+    // counts them, so the caller learns the true size).
+    __device__ static __forceinline__ void flush(const Params& p, Smem& sm, State& s,
+                                                 const TileCtx& c) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int nR32 = c.nR < 0x7fffffff ? (int)c.nR : 0x7fffffff;
+        const int nS32 = c.nS < 0x7fffffff ? (int)c.nS : 0x7fffffff;
+        for (int e0 = 0; e0 < s.n_rec; e0 += 64) {
+            const int e = e0 + c.lane;
+            const bool have = e < s.n_rec;
+            const float4 a4 = sm.val[c.wave][have ? e : 0];
+            const int2 rc = sm.pos[c.wave][have ? e : 0];
+            const float a[4] = {a4.x, a4.y, a4.z, a4.w};
+            const bool col = have && rc.y < nS32;
+            uint32_t mo = 0, mb = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool ok = col && rc.x + k < nR32;
+                mo |= (uint32_t)(ok && a[k] >= s.hi) << k;
+                mb |= (uint32_t)(ok && a[k] >= s.lo && a[k] < s.hi) << k;
+            }
+            uint32_t no, nb;
+            uint32_t po = lane_prefix7(__popc(mo), no);
+            uint32_t pb = lane_prefix7(__popc(mb), nb);
+            int32_t sj = rc.y;
+            if constexpr (PERM) {
+                if (mo | mb) sj = p.perm_s[rc.y];
+            }
+            if (no) {
+                const unsigned long long b = reserve_places(no, p.out_ctr, c.lane);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if ((mo >> k) & 1u) {
+                        const unsigned long long q = b + po++;
+                        if ((int64_t)q < p.capacity) {
+                            Pair pr;
+                            pr.r = PERM ? p.perm_r[rc.x + k] : rc.x + k;
+                            pr.s = sj;
+                            pr.score = a[k];
+                            p.out[q] = pr;
+                        }
+                    }
+                }
+            }
+            if (nb) {
+                const unsigned long long b = reserve_places(nb, p.band_ctr, c.lane);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if ((mb >> k) & 1u) {
+                        const unsigned long long q = b + pb++;
+                        if ((int64_t)q < p.band_cap) {
+                            const int32_t ri = PERM ? p.perm_r[rc.x + k] : rc.x + k;
+                            BE be;
+                            if constexpr (TAG)
+                                be = make_int4(ri, sj, p.job, 0);
+                            else
+                                be = make_int2(ri, sj);
+                            ((BE*)p.band)[q] = be;
+                        }
+                    }
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        s.n_rec = 0;
+    }
+
+    // Screening (no branches): one wave mask per group of four accumulators
+    // from a compare of their maximum with lo.  Each flagged lane of a group
+    // stages the group as one record; a 32 x 32 block first makes room for
+    // all of its records, so a flush is inlined once per block.
     template <int RB, int CB>
     __device__ static __forceinline__ void tile(const Params& p, Smem& sm, State& s,
                                                 v16f (&acc)[RB][CB], const TileCtx& c) {
@@ -117,9 +191,7 @@ struct ThresholdEpiT {
         int gi0 = c.r0 + 4 * c.h;
         __asm__ volatile("" : "+v"(gi0));
         const int gj0 = c.t * c.bn + c.r32;
-        // relation sizes below 2^31 rows: 32-bit bound tests
-        const int nR32 = c.nR < 0x7fffffff ? (int)c.nR : 0x7fffffff;
-        const int nS32 = c.nS < 0x7fffffff ? (int)c.nS : 0x7fffffff;
+        bool hit[RB][CB][4];
         uint64_t gmask[RB][CB][4];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
@@ -131,87 +203,34 @@ struct ThresholdEpiT {
                     const float m4 =
                         __builtin_fmaxf(__builtin_fmaxf(acc[rb][cb][e4], acc[rb][cb][e4 + 1]),
                                         __builtin_fmaxf(acc[rb][cb][e4 + 2], acc[rb][cb][e4 + 3]));
-                    gmask[rb][cb][q4] = __ballot(m4 >= s.lo);
+                    hit[rb][cb][q4] = m4 >= s.lo;
+                    gmask[rb][cb][q4] = __ballot(hit[rb][cb][q4]);
                 }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
+            for (int cb = 0; cb < CB; ++cb) {
+                const uint64_t* g = gmask[rb][cb];
+                if (!(g[0] | g[1] | g[2] | g[3])) continue;
+                const int need = __popcll(g[0]) + __popcll(g[1]) + __popcll(g[2]) + __popcll(g[3]);
+                if (s.n_rec + need > PN_RECCAP) flush(p, sm, s, c);
 #pragma unroll
                 for (int q4 = 0; q4 < 4; ++q4) {
-                    if (!gmask[rb][cb][q4]) continue;
-                    const int e4 = 4 * q4;
-                    // room for the at most 4 x 64 hits of this group
-                    if (s.n_out > PN_OUTCAP - 256)
-                        flush_stage(sm.out[c.wave], s.n_out, p.out, p.capacity, p.out_ctr,
-                                    c.lane);
-                    if (s.n_band > PN_BANDCAP - 256)
-                        flush_stage(sm.band[c.wave], s.n_band, (BE*)p.band, p.band_cap,
-                                    p.band_ctr, c.lane);
-                    const int gj = gj0 + cb * 32;
-                    const bool vj = !c.edge || gj < nS32;
-                    // the four rows' masks at once: >= lo (a match or a band
-                    // pair) and >= hi (certain); certain pairs are staged from
-                    // their compare masks, band pairs only when there are any
-                    uint64_t mlo[4], mhi[4];
-                    bool hit[4];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int gi = gi0 + rb * 32 + 8 * q4 + k;
-                        const bool v = vj && (!c.edge || gi < nR32);
-                        const float a = acc[rb][cb][e4 + k];
-                        mlo[k] = __ballot(v && a >= s.lo);
-                        hit[k] = v && a >= s.hi;
-                        mhi[k] = __ballot(hit[k]);
+                    if (!g[q4]) continue;
+                    if (hit[rb][cb][q4]) {
+                        const int e = s.n_rec + (int)lanes_below(g[q4]);
+                        const int e4 = 4 * q4;
+                        sm.val[c.wave][e] = make_float4(acc[rb][cb][e4], acc[rb][cb][e4 + 1],
+                                                        acc[rb][cb][e4 + 2], acc[rb][cb][e4 + 3]);
+                        sm.pos[c.wave][e] = make_int2(gi0 + rb * 32 + 8 * q4, gj0 + cb * 32);
                     }
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        if (!mhi[k]) continue;
-                        if (hit[k]) {
-                            const int gi = gi0 + rb * 32 + 8 * q4 + k;
-                            Pair pr;
-                            pr.r = gi;
-                            pr.s = gj;
-                            if constexpr (PERM) {
-                                pr.r = p.perm_r[gi];
-                                pr.s = p.perm_s[gj];
-                            }
-                            pr.score = acc[rb][cb][e4 + k];
-                            sm.out[c.wave][s.n_out + lanes_below(mhi[k])] = pr;
-                        }
-                        s.n_out += __popcll(mhi[k]);
-                    }
-                    if ((mlo[0] & ~mhi[0]) | (mlo[1] & ~mhi[1]) | (mlo[2] & ~mhi[2]) |
-                        (mlo[3] & ~mhi[3])) {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const uint64_t mb = mlo[k] & ~mhi[k];
-                            if (!mb) continue;
-                            if ((mb >> c.lane) & 1ull) {
-                                const int gi = gi0 + rb * 32 + 8 * q4 + k;
-                                int ri = gi, si = gj;
-                                if constexpr (PERM) {
-                                    ri = p.perm_r[gi];
-                                    si = p.perm_s[gj];
-                                }
-                                BE be;
-                                if constexpr (TAG)
-                                    be = make_int4(ri, si, p.job, 0);
-                                else
-                                    be = make_int2(ri, si);
-                                sm.band[c.wave][s.n_band + lanes_below(mb)] = be;
-                            }
-                            s.n_band += __popcll(mb);
-                        }
-                    }
+                    s.n_rec += __popcll(g[q4]);
                 }
+            }
     }
 
     __device__ static __forceinline__ void finish(const Params& p, Smem& sm, State& s, const TileCtx& c) {
-        if (s.n_out)
-            flush_stage(sm.out[c.wave], s.n_out, p.out, p.capacity, p.out_ctr, c.lane);
-        if (s.n_band)
-            flush_stage(sm.band[c.wave], s.n_band, (BE*)p.band, p.band_cap, p.band_ctr, c.lane);
+        if (s.n_rec) flush(p, sm, s, c);
     }
 };
 
