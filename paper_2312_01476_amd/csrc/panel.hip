@@ -35,7 +35,8 @@ namespace ej {
 // accumulators (four rows of one S column) whose maximum reaches the band;
 // records are split into certain pairs and band pairs only when the stage
 // is written out.
-constexpr int PN_RECCAP = 320;
+constexpr int PN_RECCAP = 320;   // threshold epilogue
+constexpr int PN_CANDCAP = 256;  // top-k candidate epilogue
 
 // Exclusive prefix sum over the lanes of a wave of a per-lane count in
 // [0, 7] (one ballot per bit), and the wave's total.
@@ -54,6 +55,54 @@ __device__ __forceinline__ unsigned long long reserve_places(uint32_t n, unsigne
     const uint32_t blo = __builtin_amdgcn_readlane((uint32_t)base, 0);
     const uint32_t bhi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), 0);
     return ((unsigned long long)bhi << 32) | blo;
+}
+
+// Screening of one wave's S tile against lo: one wave mask per group of
+// four accumulators (four rows of one column) from a compare of their
+// maximum, no branches.  Each flagged lane of a group then stages the group
+// as one record (the four scores; the first row and the column) at
+// val/pos[n]; a 32 x 32 block first calls make_room() when its records would
+// not fit in CAP, so that call is inlined once per block.
+template <int RB, int CB, int CAP, class MakeRoom>
+__device__ __forceinline__ void stage_records(v16f (&acc)[RB][CB], float lo, float4* val,
+                                              int2* pos, int& n, int gi0, int gj0,
+                                              MakeRoom&& make_room) {
+    bool hit[RB][CB][4];
+    uint64_t gmask[RB][CB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const int e4 = 4 * q4;
+                const float m4 =
+                    __builtin_fmaxf(__builtin_fmaxf(acc[rb][cb][e4], acc[rb][cb][e4 + 1]),
+                                    __builtin_fmaxf(acc[rb][cb][e4 + 2], acc[rb][cb][e4 + 3]));
+                hit[rb][cb][q4] = m4 >= lo;
+                gmask[rb][cb][q4] = __ballot(hit[rb][cb][q4]);
+            }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const uint64_t* g = gmask[rb][cb];
+            if (!(g[0] | g[1] | g[2] | g[3])) continue;
+            const int need = __popcll(g[0]) + __popcll(g[1]) + __popcll(g[2]) + __popcll(g[3]);
+            if (n + need > CAP) make_room();
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                if (!g[q4]) continue;
+                if (hit[rb][cb][q4]) {
+                    const int e = n + (int)lanes_below(g[q4]);
+                    const int e4 = 4 * q4;
+                    val[e] = make_float4(acc[rb][cb][e4], acc[rb][cb][e4 + 1], acc[rb][cb][e4 + 2],
+                                         acc[rb][cb][e4 + 3]);
+                    pos[e] = make_int2(gi0 + rb * 32 + 8 * q4, gj0 + cb * 32);
+                }
+                n += __popcll(g[q4]);
+            }
+        }
 }
 
 // Position of the accumulators: element e of 32x32 block (rb, cb) of a lane
@@ -178,10 +227,6 @@ struct ThresholdEpiT {
         s.n_rec = 0;
     }
 
-    // Screening (no branches): one wave mask per group of four accumulators
-    // from a compare of their maximum with lo.  Each flagged lane of a group
-    // stages the group as one record; a 32 x 32 block first makes room for
-    // all of its records, so a flush is inlined once per block.
     template <int RB, int CB>
     __device__ static __forceinline__ void tile(const Params& p, Smem& sm, State& s,
                                                 v16f (&acc)[RB][CB], const TileCtx& c) {
@@ -190,43 +235,8 @@ struct ThresholdEpiT {
         // sweep and holding them (or spilling them) across the matrix loop
         int gi0 = c.r0 + 4 * c.h;
         __asm__ volatile("" : "+v"(gi0));
-        const int gj0 = c.t * c.bn + c.r32;
-        bool hit[RB][CB][4];
-        uint64_t gmask[RB][CB][4];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    const int e4 = 4 * q4;
-                    const float m4 =
-                        __builtin_fmaxf(__builtin_fmaxf(acc[rb][cb][e4], acc[rb][cb][e4 + 1]),
-                                        __builtin_fmaxf(acc[rb][cb][e4 + 2], acc[rb][cb][e4 + 3]));
-                    hit[rb][cb][q4] = m4 >= s.lo;
-                    gmask[rb][cb][q4] = __ballot(hit[rb][cb][q4]);
-                }
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                const uint64_t* g = gmask[rb][cb];
-                if (!(g[0] | g[1] | g[2] | g[3])) continue;
-                const int need = __popcll(g[0]) + __popcll(g[1]) + __popcll(g[2]) + __popcll(g[3]);
-                if (s.n_rec + need > PN_RECCAP) flush(p, sm, s, c);
-#pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    if (!g[q4]) continue;
-                    if (hit[rb][cb][q4]) {
-                        const int e = s.n_rec + (int)lanes_below(g[q4]);
-                        const int e4 = 4 * q4;
-                        sm.val[c.wave][e] = make_float4(acc[rb][cb][e4], acc[rb][cb][e4 + 1],
-                                                        acc[rb][cb][e4 + 2], acc[rb][cb][e4 + 3]);
-                        sm.pos[c.wave][e] = make_int2(gi0 + rb * 32 + 8 * q4, gj0 + cb * 32);
-                    }
-                    s.n_rec += __popcll(g[q4]);
-                }
-            }
+        stage_records<RB, CB, PN_RECCAP>(acc, s.lo, sm.val[c.wave], sm.pos[c.wave], s.n_rec, gi0,
+                                         c.t * c.bn + c.r32, [&] { flush(p, sm, s, c); });
     }
 
     __device__ static __forceinline__ void finish(const Params& p, Smem& sm, State& s, const TileCtx& c) {
@@ -254,70 +264,61 @@ template <int NW>
 struct CandEpi {
     typedef CandParams Params;
     struct Smem {
-        int cnt[NW][64];  // per wave, its (up to 64) rows
+        int cnt[NW][64];              // per wave, its (up to 64) rows
+        float4 val[NW][PN_CANDCAP];   // staged records (see stage_records)
+        int2 pos[NW][PN_CANDCAP];
     };
     struct State {
+        int n_rec;  // staged records of this wave (wave-uniform)
         float floor;
     };
 
     __device__ static __forceinline__ void init(const Params& p, Smem& sm, State& s, const TileCtx& c) {
+        s.n_rec = 0;
         s.floor = __uint_as_float((uint32_t)p.hdr[H_TOPK_F]);
         sm.cnt[c.wave][c.lane] = 0;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     }
 
+    // Write the staged records out, one per lane: every score >= floor of a
+    // row inside R and a column inside S takes the next slot of its row (an
+    // LDS atomic on the row's counter; slots past Kc are counted, not
+    // written).  The order of a row's slots carries no meaning.
+    __device__ static __forceinline__ void flush(const Params& p, Smem& sm, State& s,
+                                                 const TileCtx& c) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (int e0 = 0; e0 < s.n_rec; e0 += 64) {
+            const int e = e0 + c.lane;
+            const bool have = e < s.n_rec;
+            const float4 a4 = sm.val[c.wave][have ? e : 0];
+            const int2 rc = sm.pos[c.wave][have ? e : 0];
+            const float a[4] = {a4.x, a4.y, a4.z, a4.w};
+            const bool col = have && rc.y < c.nS;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int gi = rc.x + k;
+                if (col && gi < c.nR && a[k] >= s.floor) {
+                    const int slot = atomicAdd(&sm.cnt[c.wave][gi - c.r0], 1);
+                    if (slot < p.Kc)
+                        p.cand[(int64_t)gi * p.Kc + slot] = make_int2(rc.y, __float_as_int(a[k]));
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        s.n_rec = 0;
+    }
+
     template <int RB, int CB>
     __device__ static __forceinline__ void tile(const Params& p, Smem& sm, State& s,
                                                 v16f (&acc)[RB][CB], const TileCtx& c) {
-        const float F = s.floor;
-        uint64_t gmask[RB][CB][4];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    const int e4 = 4 * q4;
-                    const float m4 =
-                        __builtin_fmaxf(__builtin_fmaxf(acc[rb][cb][e4], acc[rb][cb][e4 + 1]),
-                                        __builtin_fmaxf(acc[rb][cb][e4 + 2], acc[rb][cb][e4 + 3]));
-                    gmask[rb][cb][q4] = __ballot(m4 >= F);
-                }
-        const uint32_t below_half = (1u << c.r32) - 1u;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    if (!gmask[rb][cb][q4]) continue;
-                    const int e4 = 4 * q4;
-                    const int gj = c.t * c.bn + cb * 32 + c.r32;
-                    const bool vj = !c.edge || gj < c.nS;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int lr = rb * 32 + 8 * q4 + 4 * c.h + k;  // row within the wave
-                        const int gi = c.r0 + lr;
-                        const float a = acc[rb][cb][e4 + k];
-                        const bool hit = vj && (!c.edge || gi < c.nR) && a >= F;
-                        const uint64_t m = __ballot(hit);
-                        if (!m) continue;
-                        // lanes of one half share a row: count within the half
-                        const uint32_t mh = c.h ? (uint32_t)(m >> 32) : (uint32_t)m;
-                        const int base = sm.cnt[c.wave][lr];
-                        if (hit) {
-                            const int pos = base + __popc(mh & below_half);
-                            if (pos < p.Kc)
-                                p.cand[(int64_t)gi * p.Kc + pos] = make_int2(gj, __float_as_int(a));
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                        if (c.r32 == 0) sm.cnt[c.wave][lr] = base + __popc(mh);
-                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    }
-                }
+        int gi0 = c.r0 + 4 * c.h;
+        __asm__ volatile("" : "+v"(gi0));
+        stage_records<RB, CB, PN_CANDCAP>(acc, s.floor, sm.val[c.wave], sm.pos[c.wave], s.n_rec,
+                                          gi0, c.t * c.bn + c.r32, [&] { flush(p, sm, s, c); });
     }
 
-    __device__ static __forceinline__ void finish(const Params& p, Smem& sm, State&, const TileCtx& c) {
+    __device__ static __forceinline__ void finish(const Params& p, Smem& sm, State& s, const TileCtx& c) {
+        if (s.n_rec) flush(p, sm, s, c);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if (c.lane < c.rows) p.cnt[c.r0 + c.lane] = sm.cnt[c.wave][c.lane];
     }
