@@ -19,7 +19,7 @@
 //  * ThresholdEpi -- the threshold predicate of the E-theta-join: groups of
 //    four scores that may reach the band are staged per wave in LDS as
 //    records and split into certain and band pairs when the stage is
-//    written out, with one atomicAdd per list and 64 records;
+//    written out, with one atomicAdd per list and stage;
 //  * CandEpi -- top-k candidates: every column with score >= a floor goes to
 //    its row's candidate slots (the workgroup sweeps all of S, so each row is
 //    owned by one wave and its counter lives in LDS).
@@ -44,17 +44,6 @@ __device__ __forceinline__ uint32_t lane_prefix7(uint32_t c, uint32_t& total) {
     const uint64_t b0 = __ballot(c & 1u), b1 = __ballot(c & 2u), b2 = __ballot(c & 4u);
     total = (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) + 4u * (uint32_t)__popcll(b2);
     return lanes_below(b0) + 2u * lanes_below(b1) + 4u * lanes_below(b2);
-}
-
-// n places of a global list: lane 0's atomicAdd on the list counter; the
-// first place, read from lane 0, is wave-uniform.
-__device__ __forceinline__ unsigned long long reserve_places(uint32_t n, unsigned long long* ctr,
-                                                             int lane) {
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(ctr, (unsigned long long)n);
-    const uint32_t blo = __builtin_amdgcn_readlane((uint32_t)base, 0);
-    const uint32_t bhi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), 0);
-    return ((unsigned long long)bhi << 32) | blo;
 }
 
 // Screening of one wave's S tile against lo: one wave mask per group of
@@ -157,71 +146,107 @@ struct ThresholdEpiT {
         s.hi = p.lohi ? __uint_as_float((uint32_t)p.lohi[1]) : p.hi;
     }
 
+    // Certain (score >= hi) and band (lo <= score < hi) masks of the four
+    // rows of staged record e, for rows inside R and a column inside S.
+    __device__ static __forceinline__ void record_masks(const Smem& sm, const State& s,
+                                                        const TileCtx& c, int e, int nR32,
+                                                        int nS32, float (&a)[4], int2& rc,
+                                                        uint32_t& mo, uint32_t& mb) {
+        const bool have = e < s.n_rec;
+        const float4 a4 = sm.val[c.wave][have ? e : 0];
+        rc = sm.pos[c.wave][have ? e : 0];
+        a[0] = a4.x;
+        a[1] = a4.y;
+        a[2] = a4.z;
+        a[3] = a4.w;
+        const bool col = have && rc.y < nS32;
+        mo = 0;
+        mb = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const bool ok = col && rc.x + k < nR32;
+            mo |= (uint32_t)(ok && a[k] >= s.hi) << k;
+            mb |= (uint32_t)(ok && a[k] >= s.lo && a[k] < s.hi) << k;
+        }
+    }
+
     // Write the staged records out, one per lane: the rows inside R and S
-    // are split into certain pairs (score >= hi) and band pairs (lo <= score
-    // < hi), and each list takes one atomicAdd per 64 records for its
-    // places.  Entries past a list's capacity are dropped (its counter still
-    // counts them, so the caller learns the true size).
+    // are split into certain pairs and band pairs.  A first pass over the
+    // records sizes both lists' shares, so that each list takes one
+    // atomicAdd (both in flight together); one more pass per list writes
+    // its entries.
+    // Entries past a list's capacity are dropped (its counter still counts
+    // them, so the caller learns the true size).
     __device__ static __forceinline__ void flush(const Params& p, Smem& sm, State& s,
                                                  const TileCtx& c) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const int nR32 = c.nR < 0x7fffffff ? (int)c.nR : 0x7fffffff;
         const int nS32 = c.nS < 0x7fffffff ? (int)c.nS : 0x7fffffff;
+        uint32_t tot_o = 0, tot_b = 0;  // wave-uniform
         for (int e0 = 0; e0 < s.n_rec; e0 += 64) {
-            const int e = e0 + c.lane;
-            const bool have = e < s.n_rec;
-            const float4 a4 = sm.val[c.wave][have ? e : 0];
-            const int2 rc = sm.pos[c.wave][have ? e : 0];
-            const float a[4] = {a4.x, a4.y, a4.z, a4.w};
-            const bool col = have && rc.y < nS32;
-            uint32_t mo = 0, mb = 0;
+            float a[4];
+            int2 rc;
+            uint32_t mo, mb, no, nb;
+            record_masks(sm, s, c, e0 + c.lane, nR32, nS32, a, rc, mo, mb);
+            lane_prefix7(__popc(mo), no);
+            lane_prefix7(__popc(mb), nb);
+            tot_o += no;
+            tot_b += nb;
+        }
+        unsigned long long bo = 0, bb = 0;
+        if (c.lane == 0) {
+            if (tot_o) bo = atomicAdd(p.out_ctr, (unsigned long long)tot_o);
+            if (tot_b) bb = atomicAdd(p.band_ctr, (unsigned long long)tot_b);
+        }
+        bo = ((unsigned long long)__builtin_amdgcn_readlane((uint32_t)(bo >> 32), 0) << 32) |
+             __builtin_amdgcn_readlane((uint32_t)bo, 0);
+        bb = ((unsigned long long)__builtin_amdgcn_readlane((uint32_t)(bb >> 32), 0) << 32) |
+             __builtin_amdgcn_readlane((uint32_t)bb, 0);
+        for (int e0 = 0; tot_o && e0 < s.n_rec; e0 += 64) {
+            float a[4];
+            int2 rc;
+            uint32_t mo, mb, no;
+            record_masks(sm, s, c, e0 + c.lane, nR32, nS32, a, rc, mo, mb);
+            uint32_t po = lane_prefix7(__popc(mo), no);
+            const int32_t sj = PERM && mo ? p.perm_s[rc.y] : rc.y;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const bool ok = col && rc.x + k < nR32;
-                mo |= (uint32_t)(ok && a[k] >= s.hi) << k;
-                mb |= (uint32_t)(ok && a[k] >= s.lo && a[k] < s.hi) << k;
+                if ((mo >> k) & 1u) {
+                    const unsigned long long q = bo + po++;
+                    if ((int64_t)q < p.capacity) {
+                        Pair pr;
+                        pr.r = PERM ? p.perm_r[rc.x + k] : rc.x + k;
+                        pr.s = sj;
+                        pr.score = a[k];
+                        p.out[q] = pr;
+                    }
+                }
             }
-            uint32_t no, nb;
-            uint32_t po = lane_prefix7(__popc(mo), no);
+            bo += no;
+        }
+        for (int e0 = 0; tot_b && e0 < s.n_rec; e0 += 64) {
+            float a[4];
+            int2 rc;
+            uint32_t mo, mb, nb;
+            record_masks(sm, s, c, e0 + c.lane, nR32, nS32, a, rc, mo, mb);
             uint32_t pb = lane_prefix7(__popc(mb), nb);
-            int32_t sj = rc.y;
-            if constexpr (PERM) {
-                if (mo | mb) sj = p.perm_s[rc.y];
-            }
-            if (no) {
-                const unsigned long long b = reserve_places(no, p.out_ctr, c.lane);
+            const int32_t sj = PERM && mb ? p.perm_s[rc.y] : rc.y;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if ((mo >> k) & 1u) {
-                        const unsigned long long q = b + po++;
-                        if ((int64_t)q < p.capacity) {
-                            Pair pr;
-                            pr.r = PERM ? p.perm_r[rc.x + k] : rc.x + k;
-                            pr.s = sj;
-                            pr.score = a[k];
-                            p.out[q] = pr;
-                        }
+            for (int k = 0; k < 4; ++k) {
+                if ((mb >> k) & 1u) {
+                    const unsigned long long q = bb + pb++;
+                    if ((int64_t)q < p.band_cap) {
+                        const int32_t ri = PERM ? p.perm_r[rc.x + k] : rc.x + k;
+                        BE be;
+                        if constexpr (TAG)
+                            be = make_int4(ri, sj, p.job, 0);
+                        else
+                            be = make_int2(ri, sj);
+                        ((BE*)p.band)[q] = be;
                     }
                 }
             }
-            if (nb) {
-                const unsigned long long b = reserve_places(nb, p.band_ctr, c.lane);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if ((mb >> k) & 1u) {
-                        const unsigned long long q = b + pb++;
-                        if ((int64_t)q < p.band_cap) {
-                            const int32_t ri = PERM ? p.perm_r[rc.x + k] : rc.x + k;
-                            BE be;
-                            if constexpr (TAG)
-                                be = make_int4(ri, sj, p.job, 0);
-                            else
-                                be = make_int2(ri, sj);
-                            ((BE*)p.band)[q] = be;
-                        }
-                    }
-                }
-            }
+            bb += nb;
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         s.n_rec = 0;
