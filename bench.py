@@ -39,8 +39,8 @@ DTYPE = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8_e4m3"}
 # figures are in profiles/threshold_fp32_100k_traffic.md and
 # profiles/hbm_traffic_bf16_kernels.md); valid for the
 # kernel as it was when the counters were taken, keyed by workload and tile
-TRAFFIC = {("fp32_100k", "fp32:panel/2wg"): 3086065.0 * 1024 * 2.0 + 595312.97 * 1024 * 1.0,
-           ("bf16_1m", "bf16:panel"): 647930837.81 * 1024 * 2.0 + 11891103.41 * 1024 * 1.0}
+TRAFFIC = {("fp32_100k", "fp32:panel/2wg"): 2673670.375 * 1024 * 2.0 + 600664.40625 * 1024 * 1.0,
+           ("bf16_1m", "bf16:panel"): 51713273.375 * 1024 * 2.0 + 11982635.28125 * 1024 * 1.0}
 
 
 def log(*a):

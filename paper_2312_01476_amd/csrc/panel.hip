@@ -50,11 +50,12 @@ __device__ __forceinline__ uint32_t lane_prefix7(uint32_t c, uint32_t& total) {
 // four accumulators (four rows of one column) from a compare of their
 // maximum, no branches.  Each flagged lane of a group then stages the group
 // as one record (the four scores; the first row and the column) at
-// val/pos[n]; a 32 x 32 block first calls make_room() when its records would
-// not fit in CAP, so that call is inlined once per block.
-template <int RB, int CB, int CAP, class MakeRoom>
+// val/pos[n]; pre() runs between the screening and the staging, and a
+// 32 x 32 block first calls make_room() when its records would not fit in
+// CAP, so that call is inlined once per block.
+template <int RB, int CB, int CAP, class Pre, class MakeRoom>
 __device__ __forceinline__ void stage_records(v16f (&acc)[RB][CB], float lo, float4* val,
-                                              int2* pos, int& n, int gi0, int gj0,
+                                              int2* pos, int& n, int gi0, int gj0, Pre&& pre,
                                               MakeRoom&& make_room) {
     bool hit[RB][CB][4];
     uint64_t gmask[RB][CB][4];
@@ -71,6 +72,7 @@ __device__ __forceinline__ void stage_records(v16f (&acc)[RB][CB], float lo, flo
                 hit[rb][cb][q4] = m4 >= lo;
                 gmask[rb][cb][q4] = __ballot(hit[rb][cb][q4]);
             }
+    pre();
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -134,14 +136,20 @@ struct ThresholdEpiT {
     struct Smem {
         float4 val[NW][PN_RECCAP];  // a record's four scores (rows r .. r + 3)
         int2 pos[NW][PN_RECCAP];    // its first row r and its column
+        int flush_at;               // the tile step at which every wave writes out
     };
     struct State {
         int n_rec;       // staged records of this wave (wave-uniform)
+        int step;        // S tiles of the sweep so far (the same in every wave)
         float lo, hi;    // band edges of this sweep
     };
+    // staged records from which a wave asks the workgroup to write out
+    static constexpr int kWriteOutAt = PN_RECCAP / 2;
 
-    __device__ static __forceinline__ void init(const Params& p, Smem&, State& s, const TileCtx&) {
+    __device__ static __forceinline__ void init(const Params& p, Smem& sm, State& s, const TileCtx&) {
         s.n_rec = 0;
+        s.step = 0;
+        __hip_atomic_store(&sm.flush_at, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         s.lo = p.lohi ? __uint_as_float((uint32_t)p.lohi[0]) : p.lo;
         s.hi = p.lohi ? __uint_as_float((uint32_t)p.lohi[1]) : p.hi;
     }
@@ -260,8 +268,32 @@ struct ThresholdEpiT {
         // sweep and holding them (or spilling them) across the matrix loop
         int gi0 = c.r0 + 4 * c.h;
         __asm__ volatile("" : "+v"(gi0));
-        stage_records<RB, CB, PN_RECCAP>(acc, s.lo, sm.val[c.wave], sm.pos[c.wave], s.n_rec, gi0,
-                                         c.t * c.bn + c.r32, [&] { flush(p, sm, s, c); });
+        // The waves of a single join's workgroup write out together: a wave
+        // whose stage passes kWriteOutAt names the next tile step, and at
+        // that step every wave writes out what it holds.  Apart, each wave's
+        // write-out would hold the other waves at the next barrier; together
+        // they overlap.  (Only the timing depends on this flag: a block that
+        // does not fit writes out at once.)  The batch kernels, whose jobs
+        // are small and dense, write out on their own.
+        if constexpr (!TAG) {
+            const int fa =
+                __hip_atomic_load(&sm.flush_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            stage_records<RB, CB, PN_RECCAP>(
+                acc, s.lo, sm.val[c.wave], sm.pos[c.wave], s.n_rec, gi0, c.t * c.bn + c.r32,
+                [&] {
+                    if (__builtin_amdgcn_readfirstlane(fa) == s.step && s.n_rec)
+                        flush(p, sm, s, c);
+                },
+                [&] { flush(p, sm, s, c); });
+            if (s.n_rec > kWriteOutAt)
+                __hip_atomic_store(&sm.flush_at, s.step + 1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            ++s.step;
+        } else {
+            stage_records<RB, CB, PN_RECCAP>(acc, s.lo, sm.val[c.wave], sm.pos[c.wave], s.n_rec,
+                                             gi0, c.t * c.bn + c.r32, [] {},
+                                             [&] { flush(p, sm, s, c); });
+        }
     }
 
     __device__ static __forceinline__ void finish(const Params& p, Smem& sm, State& s, const TileCtx& c) {
@@ -339,7 +371,8 @@ struct CandEpi {
         int gi0 = c.r0 + 4 * c.h;
         __asm__ volatile("" : "+v"(gi0));
         stage_records<RB, CB, PN_CANDCAP>(acc, s.floor, sm.val[c.wave], sm.pos[c.wave], s.n_rec,
-                                          gi0, c.t * c.bn + c.r32, [&] { flush(p, sm, s, c); });
+                                          gi0, c.t * c.bn + c.r32, [] {},
+                                          [&] { flush(p, sm, s, c); });
     }
 
     __device__ static __forceinline__ void finish(const Params& p, Smem& sm, State& s, const TileCtx& c) {
