@@ -380,3 +380,38 @@ def test_panel_kernels_fit_the_workgroups_they_are_laid_out_for():
             checked += 1
     assert checked >= 40
     assert E.tile_occupancy(3, 384) is None and E.tile_occupancy(14, 100000) is None
+
+
+@pytest.mark.parametrize("prec,tile,d", [("bf16", 12, 96), ("bf16", 14, 96), ("fp8", 13, 128),
+                                         ("fp32", 20, 64), ("fp32", 21, 64)])
+def test_panel_epilogue_dense_hits(prec, tile, d):
+    """The register panels' staged-record epilogue where hits are dense:
+    every pair (each 32 x 32 block fills most of a wave's stage, so stages
+    are written out inside a tile, and in the single join the workgroup's
+    write-out step is called on every tile), half of the pairs (theta at the
+    median: records mix certain pairs, band pairs and misses), and a pair
+    list too small for the result (the true count, only valid distinct pairs
+    written, then the exact set on retry).  Ragged |R| and |S| over several
+    panels and S tiles."""
+    R = G.gaussian_raw(600, d, seed=d + 31)
+    S = G.gaussian_raw(900, d, seed=d + 32)
+    Rn = R / np.linalg.norm(R, axis=1, keepdims=True)
+    Sn = S / np.linalg.norm(S, axis=1, keepdims=True)
+    median = float(np.median(Rn @ Sn.T))
+    for theta in (-1.0, median):
+        st = _check(R, S, theta, prec=prec, tile=tile)
+        assert st["tile"] == tile
+    Rd, Sd = _dev(R), _dev(S)
+    ws = torch.empty(E.threshold_workspace(Rd, Sd, prec=prec, tile=tile), dtype=torch.uint8,
+                     device="cuda")
+    cap = 1000
+    out = torch.empty((cap, 3), dtype=torch.int32, device="cuda")
+    rc, n, st = E.threshold_raw(Rd, Sd, -1.0, out, cap, ws, prec=prec, tile=tile)
+    assert rc == E.E_OVERFLOW and n == 600 * 900
+    o = out.cpu().numpy()
+    assert o[:, 0].min() >= 0 and o[:, 0].max() < 600
+    assert o[:, 1].min() >= 0 and o[:, 1].max() < 900
+    assert len(set(zip(o[:, 0].tolist(), o[:, 1].tolist()))) == cap
+    out = torch.empty((n, 3), dtype=torch.int32, device="cuda")
+    rc, n2, st = E.threshold_raw(Rd, Sd, -1.0, out, n, ws, prec=prec, tile=tile)
+    assert rc == E.OK and n2 == n
