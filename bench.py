@@ -10,7 +10,12 @@ Default workload: 100k x 100k tuples, 300-d float32 embeddings (row stride
 FP64 band recheck.  The printed JSON line carries the throughput
 (Gpairs/s = |R| |S| / step time), the roofline position of the dominant
 kernel (the MFMA tile kernel, timed with HIP events on the stream it runs on)
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+and the FP64 CPU oracle timed on a bounded sample of the same workload.  The
+default line also carries, each measured in the same run: the nested-loop
+comparator on the same inputs, the 1M x 1M BF16 join (and the plain FP32 join
+on its inputs), the selectivity sweep, and the FP8 2M x 200k top-10, the
+64-job BF16 batch and that batch's shapes over 100 clusters with exact tile
+pruning (these three in child processes, each line as its own run prints it).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -253,6 +258,22 @@ def extra_selectivity(args):
     return r
 
 
+def extra_child(workload: str, steps: int = 3, warmup: int = 1):
+    """One more workload measured by a child process of this script (its
+    own seeded inputs, warm-up and timed steps, in HBM before its timed
+    region); its progress goes to this process's stderr and its JSON line is
+    embedded as printed."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", workload, "--steps",
+           str(steps), "--warmup", str(warmup), "--no-cpu"]
+    log(f"[bench] extra {workload}: {' '.join(cmd[1:])}")
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": f"exit status {r.returncode}"}
+    return json.loads(lines[-1])
+
+
 def calibrate_gemm(torch):
     """Dense BF16 GEMM C = A B^T through torch.matmul (hipBLASLt) at square
     and join-shaped sizes: the practical matrix-core rate of this chip, with
@@ -441,6 +462,9 @@ def main():
         torch.cuda.empty_cache()
         extras["bf16_1m"] = extra_bf16_1m(args)
         extras["selectivity_sweep"] = extra_selectivity(args)
+        # the top-k and batch workloads, each in a child process
+        for wl in ("fp8_topk_2m", "batch64_bf16", "batch64_exact_c100"):
+            extras[wl] = extra_child(wl)
 
     line = {
         "metric": "Gpairs/s similarity-join throughput at exact result set",
